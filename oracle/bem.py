@@ -1,0 +1,118 @@
+"""The 6N-unknown BEM system for one scatterer in vacuum (test infrastructure).
+
+Unknowns per node alpha: x_alpha = (Phi_alpha, Psi_alpha) in C^6 with
+Phi = E_0(s_alpha) and Psi = n x (curl E_0)(s_alpha), n the outward normal of
+the scatterer (eq. 2.12).  Applying the EFIE (2.5) in the host medium
+(outward normal of the host = -n, so the dyadic kernel and Psi change sign)
+and inside the scatterer with the boundary conditions (2.6)-(2.7),
+E_1 = T E_0 and n x curl E_1 = gamma Psi, gives two 3-vector rows per node:
+
+    (A x)_alpha[0:3] = 1/2 Phi_alpha + Op_{k0}(Phi, -Psi)_alpha
+    (A x)_alpha[3:6] = 1/2 T_alpha Phi_alpha - Op_{k1}(T Phi, -gamma Psi)_alpha
+    b_alpha          = (E_inc(s_alpha), 0)
+
+T = I + (eps_0 - eps_1)/eps_1 n n, gamma = mu_1/mu_0 (eq. 2.13), the host is
+vacuum (eps_0 = mu_0 = 1) and there is no incident field inside.  The paper
+prints the jump term as 1/2 I in every domain block; eq. 2.5 applies it to
+E_1 = T E_0, so the interior block uses 1/2 T.  Op_k is `direct.op_direct`.
+
+The preconditioner M = A_self keeps only the coincident-node part of the
+self-triangle integrals (Sec. 3.1, eq. 3.2 and the sentence after it):
+with (dV, dG) the correction block of a node with itself,
+
+    M_alpha = [[ 1/2 I + K(dV_0),          -dG_0 I      ],
+               [ 1/2 T - K(dV_1) T,  gamma dG_1 I ]]
+
+where K(V) a = n (V . a) - (n . V) a - V (n . a).
+"""
+
+import numpy as np
+
+from .corrections import self_blocks
+from .kernel import wavenumber
+from .native import point_sum_c
+from .direct import apply_corrections
+
+
+class BemProblem:
+    def __init__(self, nodes, k0: float, eps: complex, mu: complex = 1.0, mode="linear"):
+        self.nodes = nodes
+        self.k0 = complex(k0)
+        self.eps = complex(eps)
+        self.mu = complex(mu)
+        self.k1 = wavenumber(k0, eps, mu)
+        self.gamma = self.mu
+        n = nodes["points"].shape[0]
+        self.n = n
+        self.normals = nodes["normals"]
+        args = (nodes["points"], nodes["normals"], nodes["point_tri"], nodes["tri_vertices"])
+        self.corr0 = self_blocks(*args, self.k0, mode=mode)
+        self.corr1 = self_blocks(*args, self.k1, mode=mode)
+        self.matvecs = 0
+
+    def op(self, k, corr, a, b):
+        nd = self.nodes
+        y = point_sum_c(nd["points"], nd["normals"], nd["weights"], nd["point_tri"], k, a, b)
+        return y + apply_corrections(nd["normals"], nd["point_tri"], corr, a, b)
+
+    def T(self, phi):
+        """T Phi = Phi + (1 - eps)/eps n (n . Phi)."""
+        n = self.normals
+        c = (1.0 - self.eps) / self.eps
+        return phi + c * n * np.sum(n * phi, axis=-1, keepdims=True)
+
+    def apply(self, x):
+        """A x for x c128[n,6] (or [nrhs,n,6])."""
+        x = np.asarray(x, dtype=np.complex128)
+        phi = x[..., 0:3]
+        psi = x[..., 3:6]
+        tphi = self.T(phi)
+        r0 = 0.5 * phi + self.op(self.k0, self.corr0, phi, -psi)
+        r1 = 0.5 * tphi - self.op(self.k1, self.corr1, tphi, -self.gamma * psi)
+        self.matvecs += 1
+        return np.concatenate([r0, r1], axis=-1)
+
+    def rhs_planewave(self, d, p):
+        """b = (p exp(i k0 d . s), 0) for one direction d and polarisation p."""
+        s = self.nodes["points"]
+        e = np.exp(1j * self.k0 * (s @ np.asarray(d, dtype=np.float64)))
+        out = np.zeros((self.n, 6), dtype=np.complex128)
+        out[:, 0:3] = e[:, None] * np.asarray(p)[None, :]
+        return out
+
+    def precond_blocks(self):
+        """M_alpha as c128[n,6,6]."""
+        n = self.normals
+        N = self.n
+        I3 = np.eye(3)
+        nn = n[:, :, None] * n[:, None, :]
+        T = I3[None] + ((1.0 - self.eps) / self.eps) * nn
+
+        def Kmat(V):
+            # K(V) a = n (V . a) - (n . V) a - V (n . a)  ->  matrix n V^T - (n.V) I - V n^T
+            nV = np.sum(n * V, axis=1)
+            return n[:, :, None] * V[:, None, :] - nV[:, None, None] * I3[None] - V[:, :, None] * n[:, None, :]
+
+        V0, G0 = self._diag(self.corr0)
+        V1, G1 = self._diag(self.corr1)
+        M = np.zeros((N, 6, 6), dtype=np.complex128)
+        M[:, 0:3, 0:3] = 0.5 * I3[None] + Kmat(V0)
+        M[:, 0:3, 3:6] = -G0[:, None, None] * I3[None]
+        M[:, 3:6, 0:3] = 0.5 * T - Kmat(V1) @ T
+        M[:, 3:6, 3:6] = self.gamma * G1[:, None, None] * I3[None]
+        return M
+
+    def _diag(self, blocks):
+        """The block of every node with itself: (dV c128[n,3], dG c128[n])."""
+        nodes, dV, dG = blocks
+        own = nodes[self.nodes["point_tri"]] == np.arange(self.n)[:, None]
+        j = np.argmax(own, axis=1)
+        return dV[np.arange(self.n), j], dG[np.arange(self.n), j]
+
+    def block_preconditioner(self):
+        Minv = np.linalg.inv(self.precond_blocks())
+
+        def apply(v):
+            return np.einsum("nij,...nj->...ni", Minv, v)
+
+        return apply
