@@ -1,0 +1,221 @@
+/*
+ * fmbem: fast-multipole Nystrom operator and BEM solver for 3-D Helmholtz
+ * scattering on one gfx950 GPU.  C ABI.
+ *
+ * The operator follows the electric field integral equation of the paper
+ * (Sec. 2.1, eq. 2.5) discretised by the Nystrom rule (eq. 2.8) at the nodes
+ * of a planar triangle mesh.  For one wavenumber k the library computes, for
+ * complex 3-vector densities a and b given at the n nodes,
+ *
+ *   y_alpha = sum_{beta : t(beta) != t(alpha)} w_beta [ n_beta (grad'g . a_beta)
+ *               - (n_beta . grad'g) a_beta - grad'g (n_beta . a_beta) + g b_beta ]
+ *           + sum over the nodes beta of alpha's own triangle of the
+ *             analytically integrated self-triangle blocks (Appendix B),
+ *
+ * g = exp(i k R)/(4 pi R) (eq. 2.4), grad'g its gradient at the source node
+ * s_beta, R = |s_beta - s_alpha|, t(.) the triangle of a node.  The far part
+ * of the sum uses the fast multipole method of Sec. 2.2 (expansions of
+ * eqs. 2.14-2.17, collect / upward / downward / distribute steps of eqs.
+ * 2.18-2.23 on the octree of Appendix C); near pairs are summed directly.
+ *
+ * Conventions for every entry point:
+ *  - every call returns an int status: FMB_OK (0) or one of the codes below;
+ *    on error fmb_last_error() returns a thread-local message.  Nothing is
+ *    thrown across the ABI.
+ *  - "host" pointers are CPU memory read during the call only; "device"
+ *    pointers are GPU memory owned by the caller.  Complex arrays are
+ *    interleaved (re, im) pairs: c128 = two doubles, c64 = two floats.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Matvec work is
+ *    enqueued on it asynchronously; plan and solve calls synchronise it.
+ *  - a plan owns its device workspace: at most one matvec per plan may be in
+ *    flight at a time.  Input and output buffers must not alias.
+ */
+#ifndef FMBEM_H
+#define FMBEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FMB_OK = 0,
+    FMB_EINVAL = 1,      /* bad argument (sizes, non-finite input, bad normals, ...) */
+    FMB_ENOMEM = 2,      /* device allocation failed */
+    FMB_EDEVICE = 3,     /* a HIP runtime call failed */
+    FMB_ENOCONV = 4,     /* iterative solve hit its iteration limit */
+    FMB_EBREAKDOWN = 5,  /* solver breakdown it could not recover from */
+    FMB_ENONFINITE = 6,  /* NaN/Inf met in a solve */
+    FMB_ENOTIMPL = 7     /* entry point present, feature not implemented */
+};
+
+enum { FMB_FP64 = 0, FMB_FP32 = 1 };
+enum { FMB_CORR_NONE = 0, FMB_CORR_MEAN = 1, FMB_CORR_LINEAR = 2 };
+
+typedef struct fmb_plan_s *fmb_plan_t;
+typedef struct fmb_problem_s *fmb_problem_t;
+
+typedef struct {
+    int32_t depth;              /* octree depth below the root cube, 1..10 (0: pick one)     */
+    int32_t precision;          /* FMB_FP64 or FMB_FP32 (expansions, translations, near sum)  */
+    int32_t nrhs_max;           /* largest nrhs a matvec on this plan will pass (>= 1)       */
+    int32_t corr_mode;          /* FMB_CORR_*: how the self-triangle integrals are shared     */
+    const int32_t *point_tri;   /* host i32[n]: triangle of each node (NULL: own triangle)    */
+    const double *tri_vertices; /* host f64[ntri][3][3]: triangle corners (corr_mode > 0)     */
+    int64_t ntri;               /* number of triangles                                        */
+    int32_t leaf_target;        /* depth 0 only: aim for about this many nodes per leaf (0=32)*/
+    int32_t reserved[7];
+} fmb_plan_opts;
+
+typedef struct {
+    int32_t depth;
+    int32_t order;              /* p: expansions keep degrees n <= p-1 (eq. 2.17 truncation) */
+    int32_t precision;
+    int32_t nrhs_max;
+    int64_t n;
+    int64_t nbox[16];           /* boxes per level 0..depth                                   */
+    int64_t m2l_pairs[16];      /* far-field (S|R) pairs per level                             */
+    int64_t p2p_pairs;          /* near (target, source) pairs incl. excluded same-triangle  */
+    int64_t corr_blocks;        /* self-triangle blocks                                       */
+    int64_t device_bytes;       /* device memory the plan holds                               */
+} fmb_plan_info;
+
+/* Fill opts with defaults: depth 0, FP64, nrhs_max 1, LINEAR corrections. */
+int fmb_plan_opts_default(fmb_plan_opts *opts);
+
+/*
+ * fmm_plan: build the octree (Appendix C), the per-level translation
+ * operators S|S, S|R, R|R (eqs. 2.20-2.21) and the self-triangle correction
+ * blocks (Appendix B) for one wavenumber k = k_re + i k_im (k_im >= 0).
+ *   points   host f64[n][3]   node positions s_beta
+ *   normals  host f64[n][3]   unit normals (|n| within 1e-6 of 1), outward
+ *   weights  host f64[n]      Nystrom weights w_beta > 0 (eq. 2.8)
+ *   order    p >= 1: degrees 0..p-1 kept at every level (eq. 2.17 cut)
+ * Errors: FMB_EINVAL for n < 2, non-finite input, bad normal, w <= 0,
+ * k_im < 0, depth out of range, order out of range (1..24), duplicate
+ * nodes in one leaf, corr_mode > 0 without triangles or with a triangle not
+ * holding exactly 1 or 3 nodes.  The plan deep-copies its inputs.
+ */
+int fmm_plan(const double *points, const double *normals, const double *weights, int64_t n,
+             double k_re, double k_im, int32_t order, const fmb_plan_opts *opts, void *stream,
+             fmb_plan_t *out);
+
+/*
+ * fmm_matvec: y = Op_k(a, b) as defined at the top of this header.
+ *   a, b  device [nrhs][n][3] complex (c128 for an FP64 plan, c64 for FP32), user node order
+ *   y     device [nrhs][n][3] complex, written (not accumulated)
+ *   1 <= nrhs <= nrhs_max.  Asynchronous on `stream`.
+ */
+int fmm_matvec(fmb_plan_t plan, const void *a, const void *b, void *y, int32_t nrhs, void *stream);
+
+/*
+ * fmm_matvec_adjoint: (a_bar, b_bar) = Op_k^H y, the conjugate transpose.
+ * Declared for the adjoint/gradient work; returns FMB_ENOTIMPL.
+ */
+int fmm_matvec_adjoint(fmb_plan_t plan, const void *y, void *a_bar, void *b_bar, int32_t nrhs,
+                       void *stream);
+
+int fmm_plan_info(fmb_plan_t plan, fmb_plan_info *info);
+
+/*
+ * fmm_plan_export_tree: copy the octree to host memory for inspection.
+ *   codes  host u64[n]   Morton code of every node (user order)
+ *   perm   host i32[n]   perm[i] = user index of the i-th node in Morton order
+ * and for one level l (0..depth), sized by fmm_plan_info.nbox[l] = B:
+ *   keys   host u64[B]        box keys (code >> 3(21-l)), ascending
+ *   parent host i32[B]        parent box index at level l-1 (-1 at level 0)
+ *   start  host i32[B+1]      node range of each box in Morton order
+ *   nbr    host i32[B][27]    neighbour box indices (-1 where absent), slot
+ *                             (dz+1)*9 + (dy+1)*3 + (dx+1)
+ *   ff_ofs host i32[B+1], ff_idx host i32[ff_ofs[B]]: far-field list (l >= 2)
+ * Any pointer may be NULL to skip it; ff_idx needs ff_ofs from a first call.
+ */
+int fmm_plan_export_tree(fmb_plan_t plan, int32_t level, uint64_t *codes, int32_t *perm,
+                         uint64_t *keys, int32_t *parent, int32_t *start, int32_t *nbr,
+                         int32_t *ff_ofs, int32_t *ff_idx);
+
+int fmm_plan_destroy(fmb_plan_t plan);
+
+/*
+ * Stage timers.  fmm_plan_profile(plan, 1) makes every later matvec on the
+ * plan record HIP events around its stages on the matvec's stream;
+ * fmm_plan_profile_read synchronises on them and returns, per stage, the
+ * summed kernel time in milliseconds and the number of timed launches since
+ * the last read with reset = 1.  Stage order (FMB_NSTAGES = 9): gather, P2M,
+ * M2M (S|S), M2L (S|R, incl. the per-target sums), L2L (R|R), L2P, P2P,
+ * corrections, scatter.  ms and launches: host arrays of FMB_NSTAGES entries
+ * (either may be NULL).
+ */
+#define FMB_NSTAGES 9
+int fmm_plan_profile(fmb_plan_t plan, int32_t enable);
+int fmm_plan_profile_read(fmb_plan_t plan, double *ms, int64_t *launches, int32_t reset);
+
+/* ---------------- BEM system and solver (Secs. 2.2 and 3.1) ---------------- */
+
+typedef struct {
+    double tol;          /* stop when |b - A x| <= tol |b| (relative, 2-norm)               */
+    int32_t restart;     /* Krylov basis size m                                              */
+    int32_t maxit;       /* total iteration cap                                              */
+    int32_t precond;     /* 0 none, 1 block A_self (6x6 per node)                            */
+    int32_t x0_given;    /* 1: x holds the initial guess on entry                            */
+    int32_t mixed;       /* 1: FP32 inner solves refined by FP64 residuals (needs FP32 plans)*/
+    double inner_tol;    /* relative tolerance of each inner FP32 solve (mixed mode)         */
+    int32_t inner_maxit; /* iteration cap of each inner solve                                */
+    int32_t reserved[5];
+} fmb_gmres_opts;
+
+typedef struct {
+    int32_t iterations;      /* Krylov iterations (all inner iterations in mixed mode)       */
+    int32_t refinements;     /* outer FP64 refinement steps (mixed mode)                     */
+    int32_t matvecs64;       /* BEM applies with the FP64 plans                               */
+    int32_t matvecs32;       /* BEM applies with the FP32 plans                               */
+    double residual;         /* final true relative residual |b - A x| / |b| (FP64 operator) */
+    double history[256];     /* residual estimate per iteration (first 256)                  */
+} fmb_gmres_info;
+
+int fmb_gmres_opts_default(fmb_gmres_opts *opts);
+
+/*
+ * bem_problem_create: the 6N system of one scatterer in vacuum (eqs. 2.9-2.13),
+ * unknowns per node (Phi, Psi) = (E_0, n x curl E_0):
+ *   rows 0..2: 1/2 Phi + Op_{k0}(Phi, -Psi)
+ *   rows 3..5: 1/2 T Phi - Op_{k1}(T Phi, -gamma Psi),  T = I + (1 - eps)/eps n n,
+ * with p0 a plan at k0 and p1 a plan at k1 = k0 sqrt(eps mu) over the same
+ * nodes (same order), gamma = mu.  p0_32/p1_32 are optional FP32 plans of the
+ * same nodes for mixed-precision solves (NULL if unused).  The problem keeps
+ * references to the plans (the caller destroys them after the problem).
+ *   eps, mu  host c128 (2 doubles each)
+ */
+int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_t p1_32,
+                       const double *eps, const double *mu, void *stream, fmb_problem_t *out);
+
+/* bem_apply: r = A x, x and r device c128 [nrhs][n][6]. */
+int bem_apply(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, void *stream);
+
+/* bem_precond_apply: z = M^{-1} v with M = A_self (6x6 per node, eq. 3.2). c128 [nrhs][n][6]. */
+int bem_precond_apply(fmb_problem_t pb, const void *v, void *z, int32_t nrhs, void *stream);
+
+/* bem_rhs_planewave: rhs[q] = (p_q exp(i k0 d_q . s), 0); dirs, pols host f64[nrhs][3]. */
+int bem_rhs_planewave(fmb_problem_t pb, const double *dirs, const double *pols, void *rhs,
+                      int32_t nrhs, void *stream);
+
+/*
+ * gmres_solve: right-preconditioned flexible GMRES (Sec. 3.1, eq. 3.1) on
+ * A x = rhs for each of nrhs right-hand sides.  rhs, x device c128
+ * [nrhs][n][6].  Synchronous.  Returns FMB_ENOCONV (x holds the last
+ * iterate, info filled) when maxit is reached.  info may be NULL; with
+ * nrhs > 1 it describes the slowest right-hand side.
+ */
+int gmres_solve(fmb_problem_t pb, const void *rhs, void *x, int32_t nrhs, const fmb_gmres_opts *o,
+                fmb_gmres_info *info, void *stream);
+
+int bem_problem_destroy(fmb_problem_t pb);
+
+/* Thread-local message for the last non-zero status returned on this thread. */
+const char *fmb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMBEM_H */

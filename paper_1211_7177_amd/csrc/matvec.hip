@@ -1,0 +1,692 @@
+// One fast-multipole matvec y = Op_k(a, b) (Sec. 2.2, Steps 1-4).
+//
+// Each output channel c = x, y, z is a Helmholtz potential of sources that
+// carry a monopole and a dipole:
+//   y_c(s_alpha) = sum_beta [ sigma_{beta,c} g(s_beta, s_alpha) + q_{beta,c} . grad' g(s_beta, s_alpha) ],
+//   sigma_{beta,c} = w b_c,   q_{beta,c} = w (n_c a - a_c n - (n . a) e_c),
+// which is the kernel n (grad'g . a) - (n . grad'g) a - grad'g (n . a) + g b of
+// eq. 2.12 written per component.  Hence
+//   Step 1 (eqs. 2.18-2.19): M_nm,c = i k sum_beta [sigma_c R_n^-m + q_c . grad R_n^-m](s_beta - X),
+//   Step 2 (eq. 2.20): S|S to the parent, Step 3 (eq. 2.21): S|R over FF plus
+//   R|R from the parent, Step 4 (eq. 2.23): y_c = sum L_nm,c R_n^m(s - X) plus
+//   the near sum over the leaf and its neighbours.
+// Gradients of R_n^m use the recurrences that follow from the plane-wave form
+// of R (cos(theta) and sin(theta) e^{+-i phi} times Y_n^m shift n by one):
+//   d_z R_n^m        = k [ -A_n^m R_{n+1}^m     + B_n^m R_{n-1}^m ]
+//   (d_x + i d_y) R  = k [ -C_n^m R_{n+1}^{m+1} + D_n^m R_{n-1}^{m+1} ]
+//   (d_x - i d_y) R  = k [ -E_n^m R_{n+1}^{m-1} + F_n^m R_{n-1}^{m-1} ]
+#include "plan.h"
+
+namespace fmb {
+
+namespace {
+
+constexpr int TPB = 256;
+
+template <typename T>
+__device__ inline cx<T> tc(cx<double> z) { return mk((T)z.re, (T)z.im); }
+
+// ---------------------------------------------------------------- gather
+template <typename T>
+__global__ void k_gather_src(const cx<T> *__restrict__ a, const cx<T> *__restrict__ b, const int32_t *__restrict__ perm,
+                             const double *__restrict__ sw, const double *__restrict__ snrm, int64_t n, int nrhs,
+                             cx<T> *__restrict__ src) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = perm[i];
+    const T w = (T)sw[i];
+    const T nx = (T)snrm[3 * i], ny = (T)snrm[3 * i + 1], nz = (T)snrm[3 * i + 2];
+    for (int r = 0; r < nrhs; ++r) {
+        const cx<T> *A = a + ((int64_t)r * n + u) * 3;
+        const cx<T> *B = b + ((int64_t)r * n + u) * 3;
+        cx<T> *o = src + ((int64_t)r * n + i) * 7;
+        cx<T> wa0 = w * A[0], wa1 = w * A[1], wa2 = w * A[2];
+        o[0] = wa0;
+        o[1] = wa1;
+        o[2] = wa2;
+        o[3] = w * B[0];
+        o[4] = w * B[1];
+        o[5] = w * B[2];
+        o[6] = nx * wa0 + ny * wa1 + nz * wa2;
+    }
+}
+
+template <typename T>
+__global__ void k_scatter_out(const cx<T> *__restrict__ ys, const int32_t *__restrict__ perm, int64_t n, int nrhs,
+                              cx<T> *__restrict__ y) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = perm[i];
+    for (int r = 0; r < nrhs; ++r)
+        for (int c = 0; c < 3; ++c) y[((int64_t)r * n + u) * 3 + c] = ys[((int64_t)r * n + i) * 3 + c];
+}
+
+// ---------------------------------------------------------------- basis
+// R_n^m(d) for n <= N (all m) of one point into out[(N+1)^2]: thread-cooperative.
+// jb: j_0..j_N at k|d|.  Called by `nthr` threads with ids 0..nthr-1.
+template <typename T>
+__device__ inline void regular_column(const double d[3], const cx<T> *jb, int N, int m, cx<T> *out) {
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const T x = r > 0 ? (T)(d[2] / r) : T(1);
+    cx<T> w = r > 0 ? mk((T)(d[0] / r), (T)(d[1] / r)) : mk(T(0), T(0));
+    T qmm = T(0.28209479177387814347);   // 1/sqrt(4 pi)
+    cx<T> wm = mk(T(1), T(0));
+    for (int i = 1; i <= m; ++i) {
+        qmm *= sqrt(T(2 * i + 1) / T(2 * i));
+        wm = wm * w;
+    }
+    const T sgn = (m & 1) ? T(-1) : T(1);
+    T q2 = 0, q1 = qmm;
+    for (int n = m; n <= N; ++n) {
+        T q;
+        if (n == m) q = qmm;
+        else if (n == m + 1) q = sqrt(T(2 * m + 3)) * x * qmm;
+        else {
+            T a = sqrt(T(4 * n * n - 1) / T(n * n - m * m));
+            T b = sqrt(T((n - 1) * (n - 1) - m * m) / T(4 * (n - 1) * (n - 1) - 1));
+            q = a * (x * q1 - b * q2);
+        }
+        if (n > m) {
+            q2 = q1;
+            q1 = q;
+        }
+        cx<T> Y = (sgn * q) * wm;
+        out[n * n + n + m] = jb[n] * Y;
+        if (m > 0) out[n * n + n - m] = jb[n] * conj(Y);
+    }
+}
+
+template <typename T>
+__device__ inline cx<T> Rget(const cx<T> *R, int N, int n, int m) {
+    if (n < 0 || n > N || m > n || m < -n) return mk(T(0), T(0));
+    return R[n * n + n + m];
+}
+
+// gradient of R_n^mu from the table R (degrees <= n+1)
+template <typename T>
+__device__ inline void grad_regular(const cx<T> *R, int N, cx<T> k, int n, int mu, cx<T> g[3]) {
+    const int am = mu < 0 ? -mu : mu;
+    const T A = sqrt(T((n + 1 - am) * (n + 1 + am)) / T((2 * n + 1) * (2 * n + 3)));
+    const T B = n > 0 ? sqrt(T((n - am) * (n + am)) / T((2 * n - 1) * (2 * n + 1))) : T(0);
+    cx<T> dz = k * (-A * Rget(R, N, n + 1, mu) + B * Rget(R, N, n - 1, mu));
+    const T c1 = -sqrt(T((n + mu + 1) * (n + mu + 2)) / T((2 * n + 1) * (2 * n + 3)));
+    const T d1 = n > 0 && (n - mu) * (n - mu - 1) > 0 ? sqrt(T((n - mu) * (n - mu - 1)) / T((2 * n - 1) * (2 * n + 1))) : T(0);
+    const T su = mu >= 0 ? T(1) : T(-1);
+    cx<T> dp = k * (-(su * c1) * Rget(R, N, n + 1, mu + 1) + (su * d1) * Rget(R, N, n - 1, mu + 1));
+    const T e1 = sqrt(T((n - mu + 1) * (n - mu + 2)) / T((2 * n + 1) * (2 * n + 3)));
+    const T f1 = n > 0 && (n + mu) * (n + mu - 1) > 0 ? -sqrt(T((n + mu) * (n + mu - 1)) / T((2 * n - 1) * (2 * n + 1))) : T(0);
+    const T sd = mu > 0 ? T(1) : T(-1);
+    cx<T> dm = k * (-(sd * e1) * Rget(R, N, n + 1, mu - 1) + (sd * f1) * Rget(R, N, n - 1, mu - 1));
+    g[0] = T(0.5) * (dp + dm);
+    cx<T> df = dp - dm;                       // = 2 i d_y
+    g[1] = mk(T(0.5) * df.im, T(-0.5) * df.re);
+    g[2] = dz;
+}
+
+// ---------------------------------------------------------------- P2M
+constexpr int P2M_BATCH = 8;
+constexpr int P2M_SLOTS = 3;     // coefficients per thread: P2 <= 3 * 256
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, const double *__restrict__ center,
+                                             const double *__restrict__ spts, const double *__restrict__ snrm,
+                                             const cx<T> *__restrict__ src, int64_t n, int p, double k_re, double k_im,
+                                             const double *__restrict__ inv_alpha, int nrhs_max, int batch,
+                                             cx<T> *__restrict__ M) {
+    extern __shared__ unsigned char smem[];
+    const int N = p;                                  // degrees 0..p for the gradients
+    const int NN = (N + 1) * (N + 1);
+    cx<T> *Rb = reinterpret_cast<cx<T> *>(smem);                        // [BATCH][NN]
+    cx<T> *jb = Rb + batch * NN;                                        // [batch][N+1]
+    double *dd = reinterpret_cast<double *>(jb + batch * (N + 1));      // [batch][3]
+    const int box = blockIdx.x, r = blockIdx.y;
+    const int s0 = start[box], s1 = start[box + 1];
+    const double X[3] = {center[3 * box], center[3 * box + 1], center[3 * box + 2]};
+    const cx<T> k = mk((T)k_re, (T)k_im);
+    const int P2 = p * p;
+    cx<T> acc[P2M_SLOTS][3];
+    for (int u = 0; u < P2M_SLOTS; ++u)
+        for (int c = 0; c < 3; ++c) acc[u][c] = mk(T(0), T(0));
+    for (int b0 = s0; b0 < s1; b0 += batch) {
+        const int nb = min(batch, s1 - b0);
+        if (threadIdx.x < nb) {
+            const int i = b0 + threadIdx.x;
+            double d[3];
+            for (int q = 0; q < 3; ++q) d[q] = spts[3 * (int64_t)i + q] - X[q];
+            for (int q = 0; q < 3; ++q) dd[threadIdx.x * 3 + q] = d[q];
+            const double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            sph_bessel_j(mk((T)(k_re * rr), (T)(k_im * rr)), N, jb + threadIdx.x * (N + 1));
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < nb * (N + 1); t += blockDim.x) {
+            const int i = t / (N + 1), m = t % (N + 1);
+            const double d[3] = {dd[3 * i], dd[3 * i + 1], dd[3 * i + 2]};
+            regular_column<T>(d, jb + i * (N + 1), N, m, Rb + i * NN);
+        }
+        __syncthreads();
+        for (int u = 0; u < P2M_SLOTS; ++u) {
+            const int idx = threadIdx.x + u * blockDim.x;
+            if (idx >= P2) break;
+            int nn = 0;
+            while ((nn + 1) * (nn + 1) <= idx) ++nn;
+            const int mm = idx - nn * nn - nn;
+            for (int i = 0; i < nb; ++i) {
+                const int64_t pi = b0 + i;
+                const cx<T> *R = Rb + i * NN;
+                const cx<T> Rv = Rget(R, N, nn, -mm);            // R_n^{-m}
+                cx<T> g[3];
+                grad_regular(R, N, k, nn, -mm, g);
+                const cx<T> *sr = src + ((int64_t)r * n + pi) * 7;
+                const T nv[3] = {(T)snrm[3 * pi], (T)snrm[3 * pi + 1], (T)snrm[3 * pi + 2]};
+                const cx<T> aG = sr[0] * g[0] + sr[1] * g[1] + sr[2] * g[2];
+                const cx<T> nG = nv[0] * g[0] + nv[1] * g[1] + nv[2] * g[2];
+                for (int c = 0; c < 3; ++c)
+                    acc[u][c] += sr[3 + c] * Rv + nv[c] * aG - sr[c] * nG - sr[6] * g[c];
+            }
+        }
+        __syncthreads();
+    }
+    for (int u = 0; u < P2M_SLOTS; ++u) {
+        const int idx = threadIdx.x + u * blockDim.x;
+        if (idx >= P2) break;
+        int nn = 0;
+        while ((nn + 1) * (nn + 1) <= idx) ++nn;
+        const cx<T> sc = mk((T)(-k_im * inv_alpha[nn]), (T)(k_re * inv_alpha[nn]));   // i k / alpha_n
+        for (int c = 0; c < 3; ++c)
+            M[(((int64_t)box * nrhs_max + r) * 3 + c) * P2 + idx] = sc * acc[u][c];
+    }
+}
+
+// ---------------------------------------------------------------- L2P
+template <typename T>
+__global__ void __launch_bounds__(64) k_l2p(const int32_t *__restrict__ start, const double *__restrict__ center,
+                                            const double *__restrict__ spts, int64_t n, int p, double k_re, double k_im,
+                                            const double *__restrict__ inv_alpha, int nrhs_max,
+                                            const cx<T> *__restrict__ Lc, cx<T> *__restrict__ ys) {
+    extern __shared__ unsigned char smem[];
+    const int P2 = p * p;
+    cx<T> *Ls = reinterpret_cast<cx<T> *>(smem);        // [3][P2]
+    cx<T> *jb = Ls + 3 * P2;                             // [64][p]
+    const int box = blockIdx.x, r = blockIdx.y;
+    const int s0 = start[box], s1 = start[box + 1];
+    for (int t = threadIdx.x; t < 3 * P2; t += blockDim.x) {
+        int idx = t % P2;
+        int nn = 0;
+        while ((nn + 1) * (nn + 1) <= idx) ++nn;
+        Ls[t] = (T)inv_alpha[nn] * Lc[((int64_t)box * nrhs_max + r) * 3 * P2 + t];
+    }
+    __syncthreads();
+    const double X[3] = {center[3 * box], center[3 * box + 1], center[3 * box + 2]};
+    for (int i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+        double d[3];
+        for (int q = 0; q < 3; ++q) d[q] = spts[3 * (int64_t)i + q] - X[q];
+        const double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        cx<T> *J = jb + threadIdx.x * p;
+        sph_bessel_j(mk((T)(k_re * rr), (T)(k_im * rr)), p - 1, J);
+        const T x = rr > 0 ? (T)(d[2] / rr) : T(1);
+        const cx<T> w = rr > 0 ? mk((T)(d[0] / rr), (T)(d[1] / rr)) : mk(T(0), T(0));
+        cx<T> acc[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
+        T qmm = T(0.28209479177387814347);
+        cx<T> wm = mk(T(1), T(0));
+        for (int m = 0; m < p; ++m) {
+            if (m > 0) {
+                qmm *= sqrt(T(2 * m + 1) / T(2 * m));
+                wm = wm * w;
+            }
+            const T sgn = (m & 1) ? T(-1) : T(1);
+            T q2 = 0, q1 = qmm;
+            for (int nn = m; nn < p; ++nn) {
+                T q;
+                if (nn == m) q = qmm;
+                else if (nn == m + 1) q = sqrt(T(2 * m + 3)) * x * qmm;
+                else {
+                    T a = sqrt(T(4 * nn * nn - 1) / T(nn * nn - m * m));
+                    T b = sqrt(T((nn - 1) * (nn - 1) - m * m) / T(4 * (nn - 1) * (nn - 1) - 1));
+                    q = a * (x * q1 - b * q2);
+                }
+                if (nn > m) {
+                    q2 = q1;
+                    q1 = q;
+                }
+                const cx<T> Y = (sgn * q) * wm;
+                const cx<T> Rp = J[nn] * Y;
+                for (int c = 0; c < 3; ++c) acc[c] += Ls[c * P2 + nn * nn + nn + m] * Rp;
+                if (m > 0) {
+                    const cx<T> Rm = J[nn] * conj(Y);
+                    for (int c = 0; c < 3; ++c) acc[c] += Ls[c * P2 + nn * nn + nn - m] * Rm;
+                }
+            }
+        }
+        for (int c = 0; c < 3; ++c) ys[((int64_t)r * n + i) * 3 + c] = acc[c];
+    }
+}
+
+// ---------------------------------------------------------------- P2P
+// One block per leaf.  Targets on lanes; when a leaf holds fewer targets
+// than the block has threads, the sources are split into S slices handled by
+// the spare threads and the slices are summed in LDS at the end.
+constexpr int P2P_TILE = 256;
+
+template <typename T>
+struct SrcTile {
+    double pos[P2P_TILE][3];
+    T nrm[P2P_TILE][3];
+    int32_t tri[P2P_TILE];
+    cx<T> rec[P2P_TILE][7];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_p2p(const int32_t *__restrict__ start, const int32_t *__restrict__ nbr,
+                                             const double *__restrict__ spts, const double *__restrict__ snrm,
+                                             const int32_t *__restrict__ stri, const cx<T> *__restrict__ src, int64_t n,
+                                             double k_re, double k_im, cx<T> *__restrict__ ys) {
+    __shared__ SrcTile<T> tile;
+    __shared__ int32_t nb_start[28], nb_box[27];
+    __shared__ int n_nb;
+    __shared__ cx<T> red[TPB][3];
+    const int box = blockIdx.x, r = blockIdx.y;
+    const int t0 = start[box], t1 = start[box + 1];
+    const int nt = t1 - t0;
+    if (threadIdx.x == 0) {
+        int c = 0, tot = 0;
+        for (int s = 0; s < 27; ++s) {
+            int q = nbr[box * 27 + s];
+            if (q >= 0) {
+                nb_box[c] = q;
+                nb_start[c] = tot;
+                tot += start[q + 1] - start[q];
+                ++c;
+            }
+        }
+        nb_start[c] = tot;
+        n_nb = c;
+    }
+    __syncthreads();
+    const int ns_total = nb_start[n_nb];
+    const T kr = (T)k_re, ki = (T)k_im;
+    const T inv4pi = T(0.07957747154594766788);
+    for (int tc0 = 0; tc0 < nt; tc0 += TPB) {
+        const int ntc = min(TPB, nt - tc0);
+        const int S = TPB / ntc;                 // source slices
+        const int ti = threadIdx.x % ntc, sl = threadIdx.x / ntc;
+        const bool active = sl < S;
+        const int64_t ig = t0 + tc0 + ti;
+        double tp[3] = {0, 0, 0};
+        int32_t ttri = -1;
+        if (active) {
+            for (int q = 0; q < 3; ++q) tp[q] = spts[3 * ig + q];
+            ttri = stri[ig];
+        }
+        cx<T> acc[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
+        for (int base = 0; base < ns_total; base += P2P_TILE) {
+            const int cnt = min(P2P_TILE, ns_total - base);
+            __syncthreads();
+            for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
+                const int u = base + j;
+                int b = 0;
+                while (nb_start[b + 1] <= u) ++b;
+                const int64_t sidx = start[nb_box[b]] + (u - nb_start[b]);
+                for (int q = 0; q < 3; ++q) {
+                    tile.pos[j][q] = spts[3 * sidx + q];
+                    tile.nrm[j][q] = (T)snrm[3 * sidx + q];
+                }
+                tile.tri[j] = stri[sidx];
+                const cx<T> *sr = src + ((int64_t)r * n + sidx) * 7;
+                for (int q = 0; q < 7; ++q) tile.rec[j][q] = sr[q];
+            }
+            __syncthreads();
+            if (!active) continue;
+            for (int j = sl; j < cnt; j += S) {
+                if (tile.tri[j] == ttri) continue;
+                const T dx = (T)(tile.pos[j][0] - tp[0]), dy = (T)(tile.pos[j][1] - tp[1]),
+                        dz = (T)(tile.pos[j][2] - tp[2]);
+                const T R2 = dx * dx + dy * dy + dz * dz;
+                const T iR = T(1) / sqrt(R2);
+                const T R = R2 * iR;
+                T sn, cs;
+                sincos_t(kr * R, &sn, &cs);
+                const T ex = ki != T(0) ? exp(-ki * R) : T(1);
+                const cx<T> e = mk(ex * cs, ex * sn);
+                const cx<T> g = (inv4pi * iR) * e;
+                // f = (i k R - 1) e / (4 pi R^3)
+                const cx<T> ikR1 = mk(-ki * R - T(1), kr * R);
+                const cx<T> f = (inv4pi * iR * iR * iR) * (ikR1 * e);
+                const T nx = tile.nrm[j][0], ny = tile.nrm[j][1], nz = tile.nrm[j][2];
+                const T v = nx * dx + ny * dy + nz * dz;
+                const cx<T> *rc = tile.rec[j];
+                const cx<T> u = dx * rc[0] + dy * rc[1] + dz * rc[2];
+                const cx<T> tx = nx * u - v * rc[0] - dx * rc[6];
+                const cx<T> ty = ny * u - v * rc[1] - dy * rc[6];
+                const cx<T> tz = nz * u - v * rc[2] - dz * rc[6];
+                acc[0] += f * tx + g * rc[3];
+                acc[1] += f * ty + g * rc[4];
+                acc[2] += f * tz + g * rc[5];
+            }
+        }
+        __syncthreads();
+        for (int c = 0; c < 3; ++c) red[threadIdx.x][c] = acc[c];
+        __syncthreads();
+        if (threadIdx.x < ntc) {
+            cx<T> s[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
+            for (int q = 0; q < S; ++q)
+                for (int c = 0; c < 3; ++c) s[c] += red[q * ntc + threadIdx.x][c];
+            cx<T> *o = ys + ((int64_t)r * n + t0 + tc0 + threadIdx.x) * 3;
+            for (int c = 0; c < 3; ++c) o[c] += s[c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- translations
+// Batched complex GEMM grouped by operator: for every entry e of a tile,
+//   Y[dst(e)] (=|+=) T_op * X[src(e)]
+// with X, Y column blocks of 3*nrhs columns of P2 coefficients.
+struct Tile {
+    int32_t op, first, count;
+};
+constexpr int GEMM_EP = 16;       // largest number of entries per tile
+constexpr int GEMM_BK = 16;       // k-chunk
+constexpr int GEMM_CW = 48;       // columns per chunk
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_translate(const Tile *__restrict__ tiles, const int32_t *__restrict__ ent,
+                                                   const int32_t *__restrict__ src_map, const cx<T> *__restrict__ ops,
+                                                   const cx<T> *__restrict__ X, cx<T> *__restrict__ Y, int P2, int ncol,
+                                                   int64_t blk, int accumulate) {
+    // ncol = 3*nrhs columns per entry; blk = column-block stride per box (nrhs_max*3*P2)
+    __shared__ cx<T> As[64][GEMM_BK + 1];
+    __shared__ cx<T> Bs[GEMM_BK][GEMM_CW];
+    __shared__ int32_t s_src[GEMM_EP], s_dst[GEMM_EP];
+    const Tile tl = tiles[blockIdx.x];
+    const cx<T> *Top = ops + (size_t)tl.op * P2 * P2;
+    if (threadIdx.x < tl.count) {
+        int32_t e = ent[tl.first + threadIdx.x];
+        s_dst[threadIdx.x] = e;
+        s_src[threadIdx.x] = src_map ? src_map[e] : e;
+    }
+    __syncthreads();
+    const int Ctot = tl.count * ncol;        // columns in this tile
+    // thread layout: 64 rows x 4 column groups; columns processed in chunks of GEMM_CW
+    const int row = threadIdx.x & 63, cg = threadIdx.x >> 6;
+    for (int c0 = 0; c0 < Ctot; c0 += GEMM_CW) {
+        const int C = min(GEMM_CW, Ctot - c0);
+        const int CPG = (C + 3) / 4;         // columns per group (<= GEMM_CW/4)
+        for (int r0 = 0; r0 < P2; r0 += 64) {
+            cx<T> acc[GEMM_CW / 4];
+            for (int q = 0; q < GEMM_CW / 4; ++q) acc[q] = mk(T(0), T(0));
+            for (int k0 = 0; k0 < P2; k0 += GEMM_BK) {
+                __syncthreads();
+                for (int t = threadIdx.x; t < 64 * GEMM_BK; t += blockDim.x) {
+                    int rr = t / GEMM_BK, kk = t % GEMM_BK;
+                    As[rr][kk] = (r0 + rr < P2 && k0 + kk < P2) ? Top[(size_t)(r0 + rr) * P2 + k0 + kk] : mk(T(0), T(0));
+                }
+                for (int t = threadIdx.x; t < GEMM_BK * C; t += blockDim.x) {
+                    int kk = t % GEMM_BK, c = c0 + t / GEMM_BK;
+                    int e = c / ncol, cc = c % ncol;
+                    Bs[kk][c - c0] = (k0 + kk < P2) ? X[(int64_t)s_src[e] * blk + (int64_t)cc * P2 + k0 + kk]
+                                                    : mk(T(0), T(0));
+                }
+                __syncthreads();
+                const int kmax = min(GEMM_BK, P2 - k0);
+                for (int kk = 0; kk < kmax; ++kk) {
+                    const cx<T> a = As[row][kk];
+#pragma unroll
+                    for (int q = 0; q < GEMM_CW / 4; ++q) {
+                        const int c = cg * CPG + q;
+                        if (q < CPG && c < C) acc[q] += a * Bs[kk][c];
+                    }
+                }
+            }
+            if (r0 + row < P2) {
+#pragma unroll
+                for (int q = 0; q < GEMM_CW / 4; ++q) {
+                    const int c = c0 + cg * CPG + q;
+                    if (q >= CPG || c >= c0 + C) break;
+                    const int e = c / ncol, cc = c % ncol;
+                    cx<T> &o = Y[(int64_t)s_dst[e] * blk + (int64_t)cc * P2 + r0 + row];
+                    if (accumulate) o += acc[q];
+                    else o = acc[q];
+                }
+            }
+        }
+    }
+}
+
+// parent (level l) multipole = sum of its children's translated slots
+template <typename T>
+__global__ void k_sum_children(const int32_t *__restrict__ child_start, int64_t nbox, const cx<T> *__restrict__ Yc,
+                               cx<T> *__restrict__ Mp, int64_t blk, int ncolP2) {
+    const int64_t b = blockIdx.x;
+    const int c0 = child_start[b], c1 = child_start[b + 1];
+    for (int t = threadIdx.x; t < ncolP2; t += blockDim.x) {
+        cx<T> s = mk(T(0), T(0));
+        for (int c = c0; c < c1; ++c) s += Yc[(int64_t)c * blk + t];
+        Mp[b * blk + t] = s;
+    }
+}
+
+// target local (+)= sum over its far-field slots
+template <typename T>
+__global__ void k_sum_far(const int32_t *__restrict__ ff_ofs, const cx<T> *__restrict__ Yf, cx<T> *__restrict__ Lc,
+                          int64_t blk, int ncolP2, int accumulate) {
+    const int64_t b = blockIdx.x;
+    const int e0 = ff_ofs[b], e1 = ff_ofs[b + 1];
+    for (int t = threadIdx.x; t < ncolP2; t += blockDim.x) {
+        cx<T> s = mk(T(0), T(0));
+        for (int e = e0; e < e1; ++e) s += Yf[(int64_t)e * blk + t];
+        if (accumulate) Lc[b * blk + t] += s;
+        else Lc[b * blk + t] = s;
+    }
+}
+
+inline unsigned gridn(int64_t m, int tpb = TPB) { return (unsigned)((m + tpb - 1) / tpb); }
+
+template <typename T>
+void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipStream_t s) {
+    const int64_t n = P.n;
+    const int L = P.depth, p = P.order, P2 = P.P2;
+    const int64_t blk = (int64_t)P.nrhs_max * 3 * P2;
+    const int ncol = 3 * nrhs;
+    cx<T> *src = P.src.as<cx<T>>();
+    cx<T> *ys = P.ys.as<cx<T>>();
+    cx<T> *yb = P.ybuf.as<cx<T>>();
+    StageTimer &tm = P.timer;
+    hipEvent_t ev = nullptr;
+    tm.begin(ST_GATHER, s, ev);
+    k_gather_src<T><<<gridn(n), TPB, 0, s>>>(a, b, P.perm.as<int32_t>(), P.sw.as<double>(), P.snrm.as<double>(), n,
+                                             nrhs, src);
+    FMB_LAUNCH_CHECK();
+    tm.end(ST_GATHER, s, ev);
+    // Step 1: leaf multipoles
+    Level &LL = P.lv[L];
+    {
+        const int N = p;
+        const size_t per = (size_t)(N + 1) * (N + 2) * sizeof(cx<T>) + 3 * sizeof(double);
+        const int batch = (int)std::max<size_t>(1, std::min<size_t>(P2M_BATCH, 60000 / per));
+        const size_t sh = (size_t)batch * per;
+        tm.begin(ST_P2M, s, ev);
+        k_p2m<T><<<dim3((unsigned)LL.nbox, nrhs), TPB, sh, s>>>(
+            LL.start.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(), P.snrm.as<double>(), src, n, p, P.k_re,
+            P.k_im, P.inv_alpha.as<double>() + (size_t)L * p, P.nrhs_max, batch, LL.M.as<cx<T>>());
+        FMB_LAUNCH_CHECK();
+        tm.end(ST_P2M, s, ev);
+    }
+    // Step 2: upward pass (S|S), levels L-1 .. 2
+    for (int l = L - 1; l >= 2; --l) {
+        Level &V = P.lv[l], &C = P.lv[l + 1];
+        if (V.ntiles_m2m == 0) continue;
+        tm.begin(ST_M2M, s, ev);
+        k_translate<T><<<(unsigned)V.ntiles_m2m, TPB, 0, s>>>(V.tiles_m2m.as<Tile>(), C.by_octant.as<int32_t>(), nullptr,
+                                                               V.m2m.as<cx<T>>(), C.M.as<cx<T>>(), yb, P2, ncol, blk, 0);
+        k_sum_children<T><<<(unsigned)V.nbox, TPB, 0, s>>>(V.child_start.as<int32_t>(), V.nbox, yb, V.M.as<cx<T>>(), blk,
+                                                           ncol * P2);
+        FMB_LAUNCH_CHECK();
+        tm.end(ST_M2M, s, ev);
+    }
+    // Step 3: downward pass, levels 2 .. L
+    for (int l = 2; l <= L; ++l) {
+        Level &V = P.lv[l];
+        if (l >= 3 && V.ntiles_l2l > 0) {
+            Level &U = P.lv[l - 1];
+            tm.begin(ST_L2L, s, ev);
+            k_translate<T><<<(unsigned)V.ntiles_l2l, TPB, 0, s>>>(V.tiles_l2l.as<Tile>(), V.by_octant.as<int32_t>(),
+                                                                   V.parent.as<int32_t>(), V.l2l.as<cx<T>>(),
+                                                                   U.L.as<cx<T>>(), V.L.as<cx<T>>(), P2, ncol, blk, 0);
+            FMB_LAUNCH_CHECK();
+            tm.end(ST_L2L, s, ev);
+        }
+        tm.begin(ST_M2L, s, ev);
+        if (V.ntiles_m2l > 0) {
+            k_translate<T><<<(unsigned)V.ntiles_m2l, TPB, 0, s>>>(V.tiles_m2l.as<Tile>(), V.ff_by_op.as<int32_t>(),
+                                                                   V.ff_src.as<int32_t>(), V.m2l.as<cx<T>>(),
+                                                                   V.M.as<cx<T>>(), yb, P2, ncol, blk, 0);
+            FMB_LAUNCH_CHECK();
+        }
+        k_sum_far<T><<<(unsigned)V.nbox, TPB, 0, s>>>(V.ff_ofs.as<int32_t>(), yb, V.L.as<cx<T>>(), blk, ncol * P2,
+                                                      l >= 3 ? 1 : 0);
+        FMB_LAUNCH_CHECK();
+        tm.end(ST_M2L, s, ev);
+    }
+    // Step 4: local expansions at the targets, then the near sum
+    {
+        const size_t sh = (size_t)3 * P2 * sizeof(cx<T>) + (size_t)64 * p * sizeof(cx<T>);
+        tm.begin(ST_L2P, s, ev);
+        k_l2p<T><<<dim3((unsigned)LL.nbox, nrhs), 64, sh, s>>>(LL.start.as<int32_t>(), LL.center.as<double>(),
+                                                               P.spts.as<double>(), n, p, P.k_re, P.k_im,
+                                                               P.inv_alpha.as<double>() + (size_t)L * p, P.nrhs_max,
+                                                               LL.L.as<cx<T>>(), ys);
+        FMB_LAUNCH_CHECK();
+        tm.end(ST_L2P, s, ev);
+    }
+    tm.begin(ST_P2P, s, ev);
+    k_p2p<T><<<dim3((unsigned)LL.nbox, nrhs), TPB, 0, s>>>(LL.start.as<int32_t>(), LL.nbr.as<int32_t>(),
+                                                          P.spts.as<double>(), P.snrm.as<double>(), P.stri.as<int32_t>(),
+                                                          src, n, P.k_re, P.k_im, ys);
+    FMB_LAUNCH_CHECK();
+    tm.end(ST_P2P, s, ev);
+    tm.begin(ST_SCATTER, s, ev);
+    k_scatter_out<T><<<gridn(n), TPB, 0, s>>>(ys, P.perm.as<int32_t>(), n, nrhs, y);
+    FMB_LAUNCH_CHECK();
+    tm.end(ST_SCATTER, s, ev);
+    if (P.corr_mode != FMB_CORR_NONE) {
+        tm.begin(ST_CORR, s, ev);
+        apply_corrections(P, a, b, y, nrhs, s);
+        tm.end(ST_CORR, s, ev);
+    }
+}
+
+}  // namespace
+
+void build_tiles(Plan &P, hipStream_t s) {
+    const int L = P.depth;
+    auto upload = [&](std::vector<Tile> &v, DevBuf &buf, int64_t &cnt) {
+        cnt = (int64_t)v.size();
+        buf.alloc(std::max<size_t>(1, v.size()) * sizeof(Tile));
+        if (!v.empty())
+            FMB_CHECK_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+    };
+    const int ep = std::max(1, GEMM_EP / P.nrhs_max);
+    auto chunk = [ep](std::vector<Tile> &v, int op, int first, int count) {
+        for (int q = 0; q < count; q += ep) v.push_back(Tile{op, first + q, std::min(ep, count - q)});
+    };
+    for (int l = 2; l <= L; ++l) {
+        Level &V = P.lv[l];
+        std::vector<Tile> t;
+        for (int o = 0; o < N_M2L_OPS; ++o) chunk(t, o, V.op_start[o], V.op_start[o + 1] - V.op_start[o]);
+        upload(t, V.tiles_m2l, V.ntiles_m2l);
+        if (l < L) {
+            Level &C = P.lv[l + 1];
+            std::vector<Tile> u;
+            for (int o = 0; o < 8; ++o) chunk(u, o, C.oct_start[o], C.oct_start[o + 1] - C.oct_start[o]);
+            upload(u, V.tiles_m2m, V.ntiles_m2m);
+        }
+        if (l >= 3) {
+            std::vector<Tile> u;
+            for (int o = 0; o < 8; ++o) chunk(u, o, V.oct_start[o], V.oct_start[o + 1] - V.oct_start[o]);
+            upload(u, V.tiles_l2l, V.ntiles_l2l);
+        }
+    }
+    FMB_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+void alloc_workspace(Plan &P) {
+    const size_t esz = P.precision == FMB_FP64 ? sizeof(cx<double>) : sizeof(cx<float>);
+    const int64_t blk = (int64_t)P.nrhs_max * 3 * P.P2;
+    int64_t slots = 1;
+    for (int l = 2; l <= P.depth; ++l) {
+        Level &V = P.lv[l];
+        V.M.alloc((size_t)V.nbox * blk * esz);
+        V.L.alloc((size_t)V.nbox * blk * esz);
+        slots = std::max<int64_t>(slots, V.nff);
+        if (l < P.depth) slots = std::max<int64_t>(slots, P.lv[l + 1].nbox);
+    }
+    P.ybuf.alloc((size_t)slots * blk * esz);
+    P.src.alloc((size_t)P.nrhs_max * P.n * 7 * esz);
+    P.ys.alloc((size_t)P.nrhs_max * P.n * 3 * esz);
+}
+
+hipEvent_t StageTimer::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    FMB_CHECK_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void StageTimer::begin(int st, hipStream_t s, hipEvent_t &e0) {
+    (void)st;
+    if (!on) return;
+    e0 = get();
+    FMB_CHECK_HIP(hipEventRecord(e0, s));
+}
+
+void StageTimer::end(int st, hipStream_t s, hipEvent_t e0) {
+    if (!on) return;
+    hipEvent_t e1 = get();
+    FMB_CHECK_HIP(hipEventRecord(e1, s));
+    pending[st].push_back({e0, e1});
+    if (pending[st].size() > 4096) collect();
+}
+
+void StageTimer::collect() {
+    for (int st = 0; st < ST_COUNT; ++st) {
+        for (auto &pr : pending[st]) {
+            FMB_CHECK_HIP(hipEventSynchronize(pr.second));
+            float ms_ = 0.f;
+            FMB_CHECK_HIP(hipEventElapsedTime(&ms_, pr.first, pr.second));
+            ms[st] += ms_;
+            launches[st] += 1;
+            pool.push_back(pr.first);
+            pool.push_back(pr.second);
+        }
+        pending[st].clear();
+    }
+}
+
+void StageTimer::reset() {
+    collect();
+    for (int st = 0; st < ST_COUNT; ++st) {
+        ms[st] = 0;
+        launches[st] = 0;
+    }
+}
+
+StageTimer::~StageTimer() {
+    for (int st = 0; st < ST_COUNT; ++st)
+        for (auto &pr : pending[st]) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+void run_matvec(Plan &P, const void *a, const void *b, void *y, int nrhs, hipStream_t s) {
+    if (P.precision == FMB_FP64)
+        matvec_t<double>(P, (const cx<double> *)a, (const cx<double> *)b, (cx<double> *)y, nrhs, s);
+    else
+        matvec_t<float>(P, (const cx<float> *)a, (const cx<float> *)b, (cx<float> *)y, nrhs, s);
+}
+
+}  // namespace fmb

@@ -1,0 +1,112 @@
+// Plan object: the octree, translation operators, correction blocks and the
+// matvec workspace of one wavenumber.  Internal to the library.
+#pragma once
+
+#include <array>
+#include <memory>
+#include <vector>
+
+#include "common.h"
+
+namespace fmb {
+
+constexpr int MAX_DEPTH = 10;
+constexpr int MAX_ORDER = 24;
+constexpr int NBITS = 21;
+constexpr int N_M2L_OPS = 343;    // (dx,dy,dz) in [-3,3]^3, slot (dx+3)*49+(dy+3)*7+(dz+3); 316 used
+
+struct Level {
+    int64_t nbox = 0;
+    DevBuf keys;          // u64[nbox]
+    DevBuf start;         // i32[nbox+1] node range in Morton order
+    DevBuf parent;        // i32[nbox]
+    DevBuf center;        // f64[nbox][3]
+    DevBuf nbr;           // i32[nbox][27]
+    DevBuf child_start;   // i32[nbox+1] children (at level+1) ranges
+    DevBuf octant;        // i32[nbox] child position in its parent (0..7)
+    // far field (levels >= 2)
+    int64_t nff = 0;
+    DevBuf ff_ofs;        // i32[nbox+1]
+    DevBuf ff_src;        // i32[nff]
+    DevBuf ff_op;         // i32[nff] op slot 0..342
+    DevBuf ff_by_op;      // i32[nff] entry ids grouped by op
+    std::vector<int32_t> op_start;   // host, N_M2L_OPS+1
+    // boxes of this level grouped by octant (for the M2M / L2L GEMMs)
+    DevBuf by_octant;     // i32[nbox]
+    std::array<int32_t, 9> oct_start{};
+    // GEMM work tiles (op, first entry, count) for the translations into this level
+    DevBuf tiles_m2l, tiles_m2m, tiles_l2l;
+    int64_t ntiles_m2l = 0, ntiles_m2m = 0, ntiles_l2l = 0;
+    // operators (precision of the plan), complex [op][P2 (dst)][P2 (src)]
+    DevBuf m2l;           // [N_M2L_OPS] slots (unused slots left untouched)
+    DevBuf m2m;           // [8]: child (level+1) octant -> this level
+    DevBuf l2l;           // [8]: parent (level-1) -> child at this level with octant o
+    // expansions [nbox][nrhs_max][3][P2] complex
+    DevBuf M, L;
+};
+
+// stage timers (HIP events on the matvec stream), enabled per plan
+enum Stage { ST_GATHER = 0, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_L2P, ST_P2P, ST_CORR, ST_SCATTER, ST_COUNT };
+
+struct StageTimer {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[ST_COUNT];
+    std::vector<hipEvent_t> pool;
+    double ms[ST_COUNT] = {0};
+    int64_t launches[ST_COUNT] = {0};
+    hipEvent_t get();
+    void begin(int st, hipStream_t s, hipEvent_t &e0);
+    void end(int st, hipStream_t s, hipEvent_t e0);
+    void collect();
+    void reset();
+    ~StageTimer();
+};
+
+struct Plan {
+    int64_t n = 0;
+    int depth = 0, order = 0, P2 = 0, precision = FMB_FP64, nrhs_max = 1, corr_mode = 0;
+    double k_re = 0, k_im = 0;
+    double lo[3] = {0, 0, 0}, ext = 0;
+    int64_t ntri = 0, tri_m = 1;
+    int64_t p2p_pairs = 0;
+    int leaf_target = 32;
+    std::vector<Level> lv;
+    // per-node data in Morton order
+    DevBuf codes;     // u64[n] user order
+    DevBuf perm;      // i32[n] Morton position -> user index
+    DevBuf iperm;     // i32[n] user index -> Morton position
+    DevBuf spts;      // f64[n][3]
+    DevBuf snrm;      // f64[n][3]
+    DevBuf sw;        // f64[n]
+    DevBuf stri;      // i32[n]
+    DevBuf inv_alpha; // f64[depth+1][order] 1/alpha_n per level
+    // corrections (user order)
+    DevBuf point_tri; // i32[n]
+    DevBuf unrm;      // f64[n][3] normals, user order
+    DevBuf tri_nodes; // i32[ntri][tri_m]
+    DevBuf corr_v;    // c128[n][tri_m][3]
+    DevBuf corr_g;    // c128[n][tri_m]
+    // matvec workspace
+    DevBuf src;       // [nrhs_max][n][7] complex (w a, w b, w n.a) in Morton order
+    DevBuf ys;        // [nrhs_max][n][3] complex, Morton order
+    DevBuf ybuf;      // GEMM output slots, largest level
+    StageTimer timer;
+    size_t device_bytes() const;
+};
+
+// plan-building steps (plan.hip)
+void build_tree(Plan &P, const double *d_pts, hipStream_t s);
+void gather_nodes(Plan &P, const double *d_pts, const double *d_nrm, const double *d_w, const int32_t *d_tri,
+                  hipStream_t s);
+void build_operators(Plan &P, hipStream_t s);
+void build_corrections(Plan &P, const double *d_pts, const double *d_nrm, const double *d_tri,
+                       hipStream_t s);
+void apply_corrections(Plan &P, const void *a, const void *b, void *y, int nrhs, hipStream_t s);
+// matvec (matvec.hip)
+void run_matvec(Plan &P, const void *a, const void *b, void *y, int nrhs, hipStream_t s);
+
+}  // namespace fmb
+
+struct fmb_plan_s {
+    fmb::Plan p;
+};

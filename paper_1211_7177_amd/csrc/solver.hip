@@ -1,0 +1,729 @@
+// BEM system of one scatterer (eqs. 2.9-2.13), the block preconditioner
+// M = A_self (Sec. 3.1, eq. 3.2) and right-preconditioned flexible GMRES
+// (eq. 3.1), all device-resident in FP64.
+//
+// Rows of node alpha (unknowns Phi = E_0, Psi = n x curl E_0):
+//   r[0:3] = 1/2 Phi + Op_{k0}(Phi, -Psi)
+//   r[3:6] = 1/2 T Phi - Op_{k1}(T Phi, -gamma Psi),   T = I + (1 - eps)/eps n n.
+// M_alpha keeps the coincident-node self blocks (dV, dG) of both plans:
+//   M = [[1/2 I + K(dV0), -dG0 I], [1/2 T - K(dV1) T, gamma dG1 I]],
+//   K(V) a = n (V . a) - (n . V) a - V (n . a).
+//
+// fGMRES keeps the preconditioned directions z_j = M^{-1} v_j, orthogonalises
+// A z_j against the basis by classical Gram-Schmidt done twice, and updates a
+// QR factorisation of the Hessenberg matrix with complex Givens rotations
+//   c = |a| / sqrt(|a|^2 + |b|^2),  s = (a / |a|) conj(b) / sqrt(|a|^2 + |b|^2)
+// (a = h_jj, b = h_{j+1,j}); |g_{j+1}| estimates the residual.  Several
+// right-hand sides iterate in lockstep, each with its own Hessenberg matrix.
+//
+// Mixed mode (iterative refinement): r = b - A64 x with the FP64 plans, an
+// inner fGMRES solves A32 d = r with the FP32 plans (the Krylov vectors stay
+// FP64), x += d, until |r| <= tol |b|.
+#include <algorithm>
+#include <cstring>
+
+#include "plan.h"
+
+struct fmb_problem_s {
+    fmb_plan_t p0 = nullptr, p1 = nullptr, p032 = nullptr, p132 = nullptr;
+    int64_t n = 0;
+    fmb::cx<double> eps, mu, gamma;
+    double k0_re = 0, k0_im = 0;
+    int nrhs_max = 1;
+    fmb::DevBuf minv;          // c128[n][6][6]
+    fmb::DevBuf upts;          // f64[n][3] user order
+    // matvec staging [nrhs][n][3] for the two plans (FP64) and their FP32 copies
+    fmb::DevBuf a0, b0, a1, b1, y0, y1;
+    fmb::DevBuf a0s, b0s, a1s, b1s, y0s, y1s;
+};
+
+namespace fmb {
+
+namespace {
+
+constexpr int TPB = 256;
+inline unsigned gridn(int64_t m) { return (unsigned)((m + TPB - 1) / TPB); }
+
+__device__ inline void tmul(const double nv[3], double c, const cx<double> in[3], cx<double> out[3]) {
+    // out = T in = in + c n (n . in)
+    cx<double> d = nv[0] * in[0] + nv[1] * in[1] + nv[2] * in[2];
+    for (int i = 0; i < 3; ++i) out[i] = in[i] + (c * nv[i]) * d;
+}
+
+__global__ void k_bem_split(const cx<double> *__restrict__ x, const double *__restrict__ nrm, int64_t n, int nrhs,
+                            cx<double> tc, cx<double> gamma, cx<double> *__restrict__ a0, cx<double> *__restrict__ b0,
+                            cx<double> *__restrict__ a1, cx<double> *__restrict__ b1) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * nrhs) return;
+    const int64_t node = i % n;
+    const double nv[3] = {nrm[3 * node], nrm[3 * node + 1], nrm[3 * node + 2]};
+    const cx<double> *xi = x + i * 6;
+    cx<double> phi[3] = {xi[0], xi[1], xi[2]}, psi[3] = {xi[3], xi[4], xi[5]};
+    cx<double> d = nv[0] * phi[0] + nv[1] * phi[1] + nv[2] * phi[2];
+    for (int c = 0; c < 3; ++c) {
+        a0[i * 3 + c] = phi[c];
+        b0[i * 3 + c] = -psi[c];
+        a1[i * 3 + c] = phi[c] + (nv[c] * tc) * d;
+        b1[i * 3 + c] = -(gamma * psi[c]);
+    }
+}
+
+__global__ void k_bem_combine(const cx<double> *__restrict__ x, const double *__restrict__ nrm, int64_t n, int nrhs,
+                              cx<double> tc, const cx<double> *__restrict__ y0, const cx<double> *__restrict__ y1,
+                              cx<double> *__restrict__ r) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * nrhs) return;
+    const int64_t node = i % n;
+    const double nv[3] = {nrm[3 * node], nrm[3 * node + 1], nrm[3 * node + 2]};
+    const cx<double> *xi = x + i * 6;
+    cx<double> d = nv[0] * xi[0] + nv[1] * xi[1] + nv[2] * xi[2];
+    for (int c = 0; c < 3; ++c) {
+        cx<double> tphi = xi[c] + (nv[c] * tc) * d;
+        r[i * 6 + c] = 0.5 * xi[c] + y0[i * 3 + c];
+        r[i * 6 + 3 + c] = 0.5 * tphi - y1[i * 3 + c];
+    }
+}
+
+__global__ void k_to32(const cx<double> *__restrict__ in, cx<float> *__restrict__ out, int64_t m) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < m) out[i] = mk((float)in[i].re, (float)in[i].im);
+}
+
+__global__ void k_to64(const cx<float> *__restrict__ in, cx<double> *__restrict__ out, int64_t m) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < m) out[i] = mk((double)in[i].re, (double)in[i].im);
+}
+
+// M_alpha^{-1} from the coincident-node self blocks of both plans
+__global__ void k_precond_build(const double *__restrict__ nrm, const int32_t *__restrict__ point_tri,
+                                const int32_t *__restrict__ tri_nodes, int m, const cx<double> *__restrict__ cv0,
+                                const cx<double> *__restrict__ cg0, const cx<double> *__restrict__ cv1,
+                                const cx<double> *__restrict__ cg1, int64_t n, cx<double> tc, cx<double> gamma,
+                                cx<double> *__restrict__ minv, int32_t *__restrict__ bad) {
+    int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const int32_t t = point_tri[a];
+    int js = 0;
+    for (int j = 0; j < m; ++j)
+        if (tri_nodes[(int64_t)t * m + j] == (int32_t)a) js = j;
+    const double nv[3] = {nrm[3 * a], nrm[3 * a + 1], nrm[3 * a + 2]};
+    cx<double> V0[3], V1[3];
+    for (int i = 0; i < 3; ++i) {
+        V0[i] = cv0[(a * m + js) * 3 + i];
+        V1[i] = cv1[(a * m + js) * 3 + i];
+    }
+    const cx<double> G0 = cg0[a * m + js], G1 = cg1[a * m + js];
+    cx<double> A[6][12];
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 12; ++j) A[i][j] = mk(0.0, 0.0);
+    cx<double> nV0 = nv[0] * V0[0] + nv[1] * V0[1] + nv[2] * V0[2];
+    cx<double> nV1 = nv[0] * V1[0] + nv[1] * V1[1] + nv[2] * V1[2];
+    cx<double> K0[3][3], K1[3][3], T[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double d = i == j ? 1.0 : 0.0;
+            K0[i][j] = nv[i] * V0[j] - d * nV0 - V0[i] * nv[j];
+            K1[i][j] = nv[i] * V1[j] - d * nV1 - V1[i] * nv[j];
+            T[i][j] = mk(d, 0.0) + (nv[i] * nv[j]) * tc;
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double d = i == j ? 1.0 : 0.0;
+            A[i][j] = mk(0.5 * d, 0.0) + K0[i][j];
+            A[i][3 + j] = d * (-G0);
+            cx<double> kt = mk(0.0, 0.0);
+            for (int q = 0; q < 3; ++q) kt += K1[i][q] * T[q][j];
+            A[3 + i][j] = 0.5 * T[i][j] - kt;
+            A[3 + i][3 + j] = d * (gamma * G1);
+        }
+    for (int i = 0; i < 6; ++i) A[i][6 + i] = mk(1.0, 0.0);
+    // Gauss-Jordan with partial pivoting
+    for (int c = 0; c < 6; ++c) {
+        int piv = c;
+        double best = abs2(A[c][c]);
+        for (int r = c + 1; r < 6; ++r)
+            if (abs2(A[r][c]) > best) {
+                best = abs2(A[r][c]);
+                piv = r;
+            }
+        if (!(best > 0.0)) {
+            atomicOr(bad, 1);
+            return;
+        }
+        if (piv != c)
+            for (int j = 0; j < 12; ++j) {
+                cx<double> tmp = A[c][j];
+                A[c][j] = A[piv][j];
+                A[piv][j] = tmp;
+            }
+        cx<double> inv = cdiv(mk(1.0, 0.0), A[c][c]);
+        for (int j = 0; j < 12; ++j) A[c][j] = A[c][j] * inv;
+        for (int r = 0; r < 6; ++r) {
+            if (r == c) continue;
+            cx<double> f = A[r][c];
+            for (int j = 0; j < 12; ++j) A[r][j] -= f * A[c][j];
+        }
+    }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) minv[a * 36 + i * 6 + j] = A[i][6 + j];
+}
+
+__global__ void k_precond_apply(const cx<double> *__restrict__ minv, const cx<double> *__restrict__ v,
+                                cx<double> *__restrict__ z, int64_t n, int nrhs) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * nrhs) return;
+    const int64_t node = i % n;
+    const cx<double> *M = minv + node * 36;
+    const cx<double> *vi = v + i * 6;
+    cx<double> in[6];
+    for (int q = 0; q < 6; ++q) in[q] = vi[q];
+    for (int r = 0; r < 6; ++r) {
+        cx<double> s = mk(0.0, 0.0);
+        for (int q = 0; q < 6; ++q) s += M[r * 6 + q] * in[q];
+        z[i * 6 + r] = s;
+    }
+}
+
+__global__ void k_rhs_planewave(const double *__restrict__ spts, const int32_t *__restrict__ iperm,
+                                const double *__restrict__ dirs, const double *__restrict__ pols, int64_t n, int nrhs,
+                                double k_re, double k_im, cx<double> *__restrict__ rhs) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * nrhs) return;
+    const int64_t node = i % n, q = i / n;
+    const int64_t si = iperm[node];
+    const double ph = dirs[3 * q] * spts[3 * si] + dirs[3 * q + 1] * spts[3 * si + 1] + dirs[3 * q + 2] * spts[3 * si + 2];
+    // exp(i k ph) = exp(-k_im ph) (cos(k_re ph) + i sin(k_re ph))
+    double s, c;
+    sincos(k_re * ph, &s, &c);
+    const double e = exp(-k_im * ph);
+    for (int d = 0; d < 3; ++d) {
+        rhs[i * 6 + d] = mk(pols[3 * q + d] * e * c, pols[3 * q + d] * e * s);
+        rhs[i * 6 + 3 + d] = mk(0.0, 0.0);
+    }
+}
+
+// ---- Krylov kernels (vectors of length len per rhs, stride len) ----
+constexpr int DOT_CHUNKS = 64;
+
+// part[(i*nrhs + r)*DOT_CHUNKS + c] = sum_{k in chunk c} conj(V_i[r][k]) W[r][k]
+__global__ void k_dots(const cx<double> *__restrict__ V, int64_t vstride, int nv, const cx<double> *__restrict__ W,
+                       int64_t len, int nrhs, cx<double> *__restrict__ part) {
+    __shared__ cx<double> sm[TPB];
+    const int c = blockIdx.x % DOT_CHUNKS;
+    const int r = (blockIdx.x / DOT_CHUNKS) % nrhs;
+    const int i = blockIdx.x / (DOT_CHUNKS * nrhs);
+    const cx<double> *v = V + (int64_t)i * vstride + (int64_t)r * len;
+    const cx<double> *w = W + (int64_t)r * len;
+    const int64_t per = (len + DOT_CHUNKS - 1) / DOT_CHUNKS;
+    const int64_t k0 = c * per, k1 = min(len, k0 + per);
+    cx<double> s = mk(0.0, 0.0);
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) s += conj(v[k]) * w[k];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = TPB / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[((int64_t)i * nrhs + r) * DOT_CHUNKS + c] = sm[0];
+}
+
+__global__ void k_dots_reduce(const cx<double> *__restrict__ part, int cnt, cx<double> *__restrict__ out) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= cnt) return;
+    cx<double> s = mk(0.0, 0.0);
+    for (int c = 0; c < DOT_CHUNKS; ++c) s += part[(int64_t)e * DOT_CHUNKS + c];
+    out[e] = s;
+}
+
+// W[r] += sign * sum_i V_i[r] h[i][r]   (h laid out [i][nrhs]); masked by active[r]
+__global__ void k_combine(const cx<double> *__restrict__ V, int64_t vstride, int nv, const cx<double> *__restrict__ h,
+                          double sign, cx<double> *__restrict__ W, int64_t len, int nrhs,
+                          const int32_t *__restrict__ active) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= len * nrhs) return;
+    const int r = (int)(e / len);
+    if (active && !active[r]) return;
+    cx<double> s = mk(0.0, 0.0);
+    for (int i = 0; i < nv; ++i) s += V[(int64_t)i * vstride + e] * h[(int64_t)i * nrhs + r];
+    W[e] += sign * s;
+}
+
+__global__ void k_scale_into(const cx<double> *__restrict__ W, const double *__restrict__ inv, cx<double> *__restrict__ out,
+                             int64_t len, int nrhs, const int32_t *__restrict__ active) {
+    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= len * nrhs) return;
+    const int r = (int)(e / len);
+    out[e] = (active && !active[r]) ? mk(0.0, 0.0) : inv[r] * W[e];
+}
+
+__global__ void k_sub(const cx<double> *__restrict__ b, const cx<double> *__restrict__ ax, cx<double> *__restrict__ r,
+                      int64_t m) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < m) r[i] = b[i] - ax[i];
+}
+
+__global__ void k_axpy_masked(cx<double> *__restrict__ x, const cx<double> *__restrict__ d, int64_t len, int nrhs) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < len * nrhs) x[i] += d[i];
+}
+
+// One Arnoldi column per rhs: H[:, j] from h (j+1 entries, [i][nrhs]) and hn;
+// apply old rotations, form a new one, update g, write the residual estimate.
+__global__ void k_givens(cx<double> *__restrict__ H, int ldh, int j, const cx<double> *__restrict__ h,
+                         const double *__restrict__ hn, const double *__restrict__ nAz, double *__restrict__ cs,
+                         cx<double> *__restrict__ sn, cx<double> *__restrict__ g, double *__restrict__ res,
+                         int32_t *__restrict__ active, int32_t *__restrict__ brk, int nrhs, int m) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    if (!active[r]) return;
+    cx<double> *Hr = H + (int64_t)r * ldh * m;          // column-major [m][ldh]
+    cx<double> *col = Hr + (int64_t)j * ldh;
+    for (int i = 0; i <= j; ++i) col[i] = h[(int64_t)i * nrhs + r];
+    col[j + 1] = mk(hn[r], 0.0);
+    for (int i = 0; i < j; ++i) {
+        const double c = cs[r * m + i];
+        const cx<double> s = sn[r * m + i];
+        cx<double> t = c * col[i] + s * col[i + 1];
+        col[i + 1] = c * col[i + 1] - conj(s) * col[i];
+        col[i] = t;
+    }
+    const cx<double> a = col[j], b = col[j + 1];
+    const double aa = sqrt(abs2(a)), den = sqrt(abs2(a) + abs2(b));
+    double c;
+    cx<double> s;
+    if (aa == 0.0) {
+        c = 0.0;
+        s = mk(1.0, 0.0);
+    } else {
+        c = aa / den;
+        s = (1.0 / (aa * den)) * (a * conj(b));
+    }
+    cs[r * m + j] = c;
+    sn[r * m + j] = s;
+    col[j] = c * a + s * b;
+    col[j + 1] = mk(0.0, 0.0);
+    cx<double> gj = g[r * (m + 1) + j];
+    g[r * (m + 1) + j + 1] = -(conj(s) * gj);
+    g[r * (m + 1) + j] = c * gj;
+    res[r] = sqrt(abs2(g[r * (m + 1) + j + 1]));
+    brk[r] = (hn[r] <= 1e-14 * nAz[r]) ? 1 : 0;
+}
+
+// y = H^{-1} g (upper triangular, size jr[r]) per rhs, written as y[i][nrhs]
+__global__ void k_trisolve(const cx<double> *__restrict__ H, int ldh, const cx<double> *__restrict__ g,
+                           const int32_t *__restrict__ jr, cx<double> *__restrict__ y, int nrhs, int m) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    const cx<double> *Hr = H + (int64_t)r * ldh * m;
+    const int J = jr[r];
+    for (int i = 0; i < m; ++i) y[(int64_t)i * nrhs + r] = mk(0.0, 0.0);
+    for (int i = J - 1; i >= 0; --i) {
+        cx<double> s = g[r * (m + 1) + i];
+        for (int q = i + 1; q < J; ++q) s -= Hr[(int64_t)q * ldh + i] * y[(int64_t)q * nrhs + r];
+        y[(int64_t)i * nrhs + r] = cdiv(s, Hr[(int64_t)i * ldh + i]);
+    }
+}
+
+__global__ void k_add(cx<double> *__restrict__ h, const cx<double> *__restrict__ h2, int cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) h[i] += h2[i];
+}
+
+__global__ void k_sqrt_real(const cx<double> *__restrict__ in, double *__restrict__ out, double *__restrict__ inv, int m) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double v = sqrt(fmax(in[i].re, 0.0));
+    out[i] = v;
+    if (inv) inv[i] = v > 0 ? 1.0 / v : 0.0;
+}
+
+struct Krylov {
+    int64_t len = 0;
+    int nrhs = 0, m = 0;
+    DevBuf V, Z, W, H, cs, sn, g, h, h2, hn, hninv, nAz, res, part, act, brk, jr, y, tmp, r, ax;
+};
+
+void dots(Krylov &K, const cx<double> *V, int nv, const cx<double> *W, cx<double> *out, hipStream_t s) {
+    const int blocks = nv * K.nrhs * DOT_CHUNKS;
+    k_dots<<<blocks, TPB, 0, s>>>(V, K.len * K.nrhs, nv, W, K.len, K.nrhs, K.part.as<cx<double>>());
+    k_dots_reduce<<<gridn(nv * K.nrhs), TPB, 0, s>>>(K.part.as<cx<double>>(), nv * K.nrhs, out);
+    FMB_LAUNCH_CHECK();
+}
+
+void norms(Krylov &K, const cx<double> *W, double *out, double *inv, hipStream_t s) {
+    dots(K, W, 1, W, K.tmp.as<cx<double>>(), s);
+    k_sqrt_real<<<1, 1024, 0, s>>>(K.tmp.as<cx<double>>(), out, inv, K.nrhs);
+    FMB_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+// A x in FP64 (use32 = 0) or with the FP32 plans (use32 = 1)
+static void bem_apply_impl(fmb_problem_s &pb, const cx<double> *x, cx<double> *r, int nrhs, int use32, hipStream_t s) {
+    const int64_t n = pb.n, m3 = n * 3 * nrhs;
+    const cx<double> tc = cdiv(mk(1.0, 0.0) - pb.eps, pb.eps);
+    const double *nrm = pb.p0->p.unrm.as<double>();
+    cx<double> *a0 = pb.a0.as<cx<double>>(), *b0 = pb.b0.as<cx<double>>(), *a1 = pb.a1.as<cx<double>>(),
+               *b1 = pb.b1.as<cx<double>>(), *y0 = pb.y0.as<cx<double>>(), *y1 = pb.y1.as<cx<double>>();
+    k_bem_split<<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, tc, pb.gamma, a0, b0, a1, b1);
+    FMB_LAUNCH_CHECK();
+    if (!use32) {
+        run_matvec(pb.p0->p, a0, b0, y0, nrhs, s);
+        run_matvec(pb.p1->p, a1, b1, y1, nrhs, s);
+    } else {
+        cx<float> *A0 = pb.a0s.as<cx<float>>(), *B0 = pb.b0s.as<cx<float>>(), *A1 = pb.a1s.as<cx<float>>(),
+                  *B1 = pb.b1s.as<cx<float>>(), *Y0 = pb.y0s.as<cx<float>>(), *Y1 = pb.y1s.as<cx<float>>();
+        k_to32<<<gridn(m3), TPB, 0, s>>>(a0, A0, m3);
+        k_to32<<<gridn(m3), TPB, 0, s>>>(b0, B0, m3);
+        k_to32<<<gridn(m3), TPB, 0, s>>>(a1, A1, m3);
+        k_to32<<<gridn(m3), TPB, 0, s>>>(b1, B1, m3);
+        FMB_LAUNCH_CHECK();
+        run_matvec(pb.p032->p, A0, B0, Y0, nrhs, s);
+        run_matvec(pb.p132->p, A1, B1, Y1, nrhs, s);
+        k_to64<<<gridn(m3), TPB, 0, s>>>(Y0, y0, m3);
+        k_to64<<<gridn(m3), TPB, 0, s>>>(Y1, y1, m3);
+        FMB_LAUNCH_CHECK();
+    }
+    k_bem_combine<<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, tc, y0, y1, r);
+    FMB_LAUNCH_CHECK();
+}
+
+static void precond_impl(fmb_problem_s &pb, const cx<double> *v, cx<double> *z, int nrhs, hipStream_t s) {
+    k_precond_apply<<<gridn(pb.n * nrhs), TPB, 0, s>>>(pb.minv.as<cx<double>>(), v, z, pb.n, nrhs);
+    FMB_LAUNCH_CHECK();
+}
+
+// One right-preconditioned fGMRES solve of A x = b, x updated in place.
+// Returns the iteration count; relres receives |b - A x| / |b| per rhs
+// (computed with the operator the solve used).
+static int fgmres(fmb_problem_s &pb, Krylov &K, const cx<double> *b, cx<double> *x, bool x_nonzero, double tol,
+                  int maxit, int use32, int precond, std::vector<double> &relres, std::vector<double> *hist,
+                  int &matvecs, hipStream_t s) {
+    const int nrhs = K.nrhs, m = K.m;
+    const int64_t len = K.len, tot = len * nrhs;
+    cx<double> *V = K.V.as<cx<double>>(), *Z = K.Z.as<cx<double>>(), *W = K.W.as<cx<double>>();
+    cx<double> *R = K.r.as<cx<double>>(), *AX = K.ax.as<cx<double>>();
+    std::vector<double> bn(nrhs), beta(nrhs), res(nrhs);
+    std::vector<int32_t> act(nrhs), jr(nrhs), brk(nrhs);
+    norms(K, b, K.hn.as<double>(), nullptr, s);
+    FMB_CHECK_HIP(hipMemcpyAsync(bn.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (x_nonzero) {
+        bem_apply_impl(pb, x, AX, nrhs, use32, s);
+        ++matvecs;
+        k_sub<<<gridn(tot), TPB, 0, s>>>(b, AX, R, tot);
+        FMB_LAUNCH_CHECK();
+    } else {
+        FMB_CHECK_HIP(hipMemsetAsync(x, 0, tot * sizeof(cx<double>), s));
+        FMB_CHECK_HIP(hipMemcpyAsync(R, b, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+    }
+    int its = 0;
+    relres.assign(nrhs, 0.0);
+    while (true) {
+        norms(K, R, K.hn.as<double>(), K.hninv.as<double>(), s);
+        FMB_CHECK_HIP(hipMemcpyAsync(beta.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        FMB_CHECK_HIP(hipStreamSynchronize(s));
+        bool any = false;
+        for (int r = 0; r < nrhs; ++r) {
+            if (!std::isfinite(beta[r])) throw Status{FMB_ENONFINITE, "non-finite residual in fGMRES"};
+            relres[r] = bn[r] > 0 ? beta[r] / bn[r] : 0.0;
+            act[r] = (beta[r] > tol * bn[r]) ? 1 : 0;
+            any = any || act[r];
+        }
+        if (!any || its >= maxit) break;
+        FMB_CHECK_HIP(hipMemcpyAsync(K.act.p, act.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        k_scale_into<<<gridn(tot), TPB, 0, s>>>(R, K.hninv.as<double>(), V, len, nrhs, K.act.as<int32_t>());
+        FMB_LAUNCH_CHECK();
+        {
+            std::vector<cx<double>> g0((size_t)nrhs * (m + 1), mk(0.0, 0.0));
+            for (int r = 0; r < nrhs; ++r) g0[(size_t)r * (m + 1)] = mk(beta[r], 0.0);
+            FMB_CHECK_HIP(hipMemcpyAsync(K.g.p, g0.data(), g0.size() * sizeof(cx<double>), hipMemcpyHostToDevice, s));
+        }
+        for (int r = 0; r < nrhs; ++r) jr[r] = 0;
+        for (int j = 0; j < m && its < maxit; ++j) {
+            cx<double> *vj = V + (int64_t)j * tot, *zj = Z + (int64_t)j * tot;
+            if (precond) precond_impl(pb, vj, zj, nrhs, s);
+            else FMB_CHECK_HIP(hipMemcpyAsync(zj, vj, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+            bem_apply_impl(pb, zj, W, nrhs, use32, s);
+            ++matvecs;
+            norms(K, W, K.nAz.as<double>(), nullptr, s);
+            // classical Gram-Schmidt done twice
+            dots(K, V, j + 1, W, K.h.as<cx<double>>(), s);
+            k_combine<<<gridn(tot), TPB, 0, s>>>(V, tot, j + 1, K.h.as<cx<double>>(), -1.0, W, len, nrhs,
+                                                 K.act.as<int32_t>());
+            dots(K, V, j + 1, W, K.h2.as<cx<double>>(), s);
+            k_combine<<<gridn(tot), TPB, 0, s>>>(V, tot, j + 1, K.h2.as<cx<double>>(), -1.0, W, len, nrhs,
+                                                 K.act.as<int32_t>());
+            k_add<<<gridn((j + 1) * nrhs), TPB, 0, s>>>(K.h.as<cx<double>>(), K.h2.as<cx<double>>(), (j + 1) * nrhs);
+            FMB_LAUNCH_CHECK();
+            norms(K, W, K.hn.as<double>(), K.hninv.as<double>(), s);
+            k_scale_into<<<gridn(tot), TPB, 0, s>>>(W, K.hninv.as<double>(), V + (int64_t)(j + 1) * tot, len, nrhs,
+                                                    K.act.as<int32_t>());
+            k_givens<<<1, 1024, 0, s>>>(K.H.as<cx<double>>(), m + 1, j, K.h.as<cx<double>>(), K.hn.as<double>(),
+                                        K.nAz.as<double>(), K.cs.as<double>(), K.sn.as<cx<double>>(),
+                                        K.g.as<cx<double>>(), K.res.as<double>(), K.act.as<int32_t>(),
+                                        K.brk.as<int32_t>(), nrhs, m);
+            FMB_LAUNCH_CHECK();
+            FMB_CHECK_HIP(hipMemcpyAsync(res.data(), K.res.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+            FMB_CHECK_HIP(hipMemcpyAsync(brk.data(), K.brk.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            FMB_CHECK_HIP(hipStreamSynchronize(s));
+            ++its;
+            bool more = false;
+            double worst = 0.0;
+            for (int r = 0; r < nrhs; ++r) {
+                if (!act[r]) continue;
+                jr[r] = j + 1;
+                if (!std::isfinite(res[r])) throw Status{FMB_ENONFINITE, "non-finite Arnoldi step in fGMRES"};
+                worst = std::max(worst, bn[r] > 0 ? res[r] / bn[r] : 0.0);
+                if (res[r] <= tol * bn[r] || brk[r]) {
+                    act[r] = 0;
+                } else {
+                    more = true;
+                }
+            }
+            if (hist) hist->push_back(worst);
+            FMB_CHECK_HIP(hipMemcpyAsync(K.act.p, act.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            if (!more) break;
+        }
+        // x += Z y with y = H^{-1} g per rhs
+        FMB_CHECK_HIP(hipMemcpyAsync(K.jr.p, jr.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        k_trisolve<<<1, 1024, 0, s>>>(K.H.as<cx<double>>(), m + 1, K.g.as<cx<double>>(), K.jr.as<int32_t>(),
+                                      K.y.as<cx<double>>(), nrhs, m);
+        int jmax = 0;
+        for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jr[r]);
+        if (jmax > 0)
+            k_combine<<<gridn(tot), TPB, 0, s>>>(Z, tot, jmax, K.y.as<cx<double>>(), 1.0, x, len, nrhs, nullptr);
+        FMB_LAUNCH_CHECK();
+        // true residual
+        bem_apply_impl(pb, x, AX, nrhs, use32, s);
+        ++matvecs;
+        k_sub<<<gridn(tot), TPB, 0, s>>>(b, AX, R, tot);
+        FMB_LAUNCH_CHECK();
+    }
+    return its;
+}
+
+static void krylov_alloc(Krylov &K, int64_t len, int nrhs, int m) {
+    if (K.len == len && K.nrhs == nrhs && K.m == m) return;
+    K.len = len;
+    K.nrhs = nrhs;
+    K.m = m;
+    const size_t tot = (size_t)len * nrhs * sizeof(cx<double>);
+    K.V.alloc(tot * (m + 1));
+    K.Z.alloc(tot * m);
+    K.W.alloc(tot);
+    K.r.alloc(tot);
+    K.ax.alloc(tot);
+    K.H.alloc((size_t)nrhs * (m + 1) * m * sizeof(cx<double>));
+    K.cs.alloc((size_t)nrhs * m * sizeof(double));
+    K.sn.alloc((size_t)nrhs * m * sizeof(cx<double>));
+    K.g.alloc((size_t)nrhs * (m + 1) * sizeof(cx<double>));
+    K.h.alloc((size_t)(m + 1) * nrhs * sizeof(cx<double>));
+    K.h2.alloc((size_t)(m + 1) * nrhs * sizeof(cx<double>));
+    K.y.alloc((size_t)(m + 1) * nrhs * sizeof(cx<double>));
+    K.hn.alloc(nrhs * sizeof(double));
+    K.hninv.alloc(nrhs * sizeof(double));
+    K.nAz.alloc(nrhs * sizeof(double));
+    K.res.alloc(nrhs * sizeof(double));
+    K.act.alloc(nrhs * sizeof(int32_t));
+    K.brk.alloc(nrhs * sizeof(int32_t));
+    K.jr.alloc(nrhs * sizeof(int32_t));
+    K.tmp.alloc((size_t)(m + 1) * nrhs * sizeof(cx<double>));
+    K.part.alloc((size_t)(m + 1) * nrhs * DOT_CHUNKS * sizeof(cx<double>));
+}
+
+}  // namespace fmb
+
+using namespace fmb;
+
+extern "C" {
+
+int fmb_gmres_opts_default(fmb_gmres_opts *o) {
+    if (!o) return FMB_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-6;
+    o->restart = 100;
+    o->maxit = 1000;
+    o->precond = 1;
+    o->inner_tol = 1e-3;
+    o->inner_maxit = 300;
+    return FMB_OK;
+}
+
+int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_t p1_32, const double *eps,
+                       const double *mu, void *stream, fmb_problem_t *out) {
+    return guarded([&] {
+        FMB_REQUIRE(out != nullptr, "out is NULL");
+        *out = nullptr;
+        FMB_REQUIRE(p0 && p1, "plans p0 and p1 are required");
+        FMB_REQUIRE(eps && mu, "eps and mu are required");
+        const Plan &A = p0->p, &B = p1->p;
+        FMB_REQUIRE(A.n == B.n, "plans cover different node counts");
+        FMB_REQUIRE(A.precision == FMB_FP64 && B.precision == FMB_FP64, "p0 and p1 must be FP64 plans");
+        FMB_REQUIRE(A.corr_mode != FMB_CORR_NONE && B.corr_mode != FMB_CORR_NONE && A.tri_m == B.tri_m,
+                    "the BEM system needs self-triangle corrections in both plans");
+        FMB_REQUIRE((p0_32 == nullptr) == (p1_32 == nullptr), "give both FP32 plans or neither");
+        if (p0_32) {
+            FMB_REQUIRE(p0_32->p.n == A.n && p1_32->p.n == A.n, "FP32 plans cover different node counts");
+            FMB_REQUIRE(p0_32->p.precision == FMB_FP32 && p1_32->p.precision == FMB_FP32, "p0_32/p1_32 must be FP32");
+        }
+        cx<double> e = mk(eps[0], eps[1]), u = mk(mu[0], mu[1]);
+        FMB_REQUIRE(abs2(e) > 0.0, "eps must be non-zero");
+        hipStream_t s = (hipStream_t)stream;
+        auto *h = new fmb_problem_s;
+        std::unique_ptr<fmb_problem_s> guard(h);
+        h->p0 = p0;
+        h->p1 = p1;
+        h->p032 = p0_32;
+        h->p132 = p1_32;
+        h->n = A.n;
+        h->eps = e;
+        h->mu = u;
+        h->gamma = u;
+        h->k0_re = A.k_re;
+        h->k0_im = A.k_im;
+        int nr = std::min(A.nrhs_max, B.nrhs_max);
+        if (p0_32) nr = std::min(nr, std::min(p0_32->p.nrhs_max, p1_32->p.nrhs_max));
+        h->nrhs_max = nr;
+        const size_t m3 = (size_t)A.n * 3 * nr;
+        for (DevBuf *d : {&h->a0, &h->b0, &h->a1, &h->b1, &h->y0, &h->y1}) d->alloc(m3 * sizeof(cx<double>));
+        if (p0_32)
+            for (DevBuf *d : {&h->a0s, &h->b0s, &h->a1s, &h->b1s, &h->y0s, &h->y1s}) d->alloc(m3 * sizeof(cx<float>));
+        h->minv.alloc((size_t)A.n * 36 * sizeof(cx<double>));
+        DevBuf bad;
+        bad.alloc(sizeof(int32_t));
+        FMB_CHECK_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+        const cx<double> tc = cdiv(mk(1.0, 0.0) - e, e);
+        k_precond_build<<<gridn(A.n), TPB, 0, s>>>(A.unrm.as<double>(), A.point_tri.as<int32_t>(),
+                                                    A.tri_nodes.as<int32_t>(), (int)A.tri_m, A.corr_v.as<cx<double>>(),
+                                                    A.corr_g.as<cx<double>>(), B.corr_v.as<cx<double>>(),
+                                                    B.corr_g.as<cx<double>>(), A.n, tc, u, h->minv.as<cx<double>>(),
+                                                    bad.as<int32_t>());
+        FMB_LAUNCH_CHECK();
+        int32_t hb = 0;
+        FMB_CHECK_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        FMB_CHECK_HIP(hipStreamSynchronize(s));
+        FMB_REQUIRE(hb == 0, "a 6x6 self block of the preconditioner is singular");
+        *out = guard.release();
+    });
+}
+
+int bem_apply(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, void *stream) {
+    return guarded([&] {
+        FMB_REQUIRE(pb && x && r && x != r, "bad arguments");
+        FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
+        bem_apply_impl(*pb, (const cx<double> *)x, (cx<double> *)r, nrhs, 0, (hipStream_t)stream);
+    });
+}
+
+int bem_precond_apply(fmb_problem_t pb, const void *v, void *z, int32_t nrhs, void *stream) {
+    return guarded([&] {
+        FMB_REQUIRE(pb && v && z, "bad arguments");
+        FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
+        precond_impl(*pb, (const cx<double> *)v, (cx<double> *)z, nrhs, (hipStream_t)stream);
+    });
+}
+
+int bem_rhs_planewave(fmb_problem_t pb, const double *dirs, const double *pols, void *rhs, int32_t nrhs,
+                      void *stream) {
+    return guarded([&] {
+        FMB_REQUIRE(pb && dirs && pols && rhs, "bad arguments");
+        FMB_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+        hipStream_t s = (hipStream_t)stream;
+        DevBuf dd, dp;
+        dd.alloc(nrhs * 3 * sizeof(double));
+        dp.alloc(nrhs * 3 * sizeof(double));
+        FMB_CHECK_HIP(hipMemcpyAsync(dd.p, dirs, nrhs * 3 * sizeof(double), hipMemcpyHostToDevice, s));
+        FMB_CHECK_HIP(hipMemcpyAsync(dp.p, pols, nrhs * 3 * sizeof(double), hipMemcpyHostToDevice, s));
+        const Plan &A = pb->p0->p;
+        k_rhs_planewave<<<gridn(pb->n * nrhs), TPB, 0, s>>>(A.spts.as<double>(), A.iperm.as<int32_t>(), dd.as<double>(),
+                                                            dp.as<double>(), pb->n, nrhs, pb->k0_re, pb->k0_im,
+                                                            (cx<double> *)rhs);
+        FMB_LAUNCH_CHECK();
+        FMB_CHECK_HIP(hipStreamSynchronize(s));
+    });
+}
+
+int gmres_solve(fmb_problem_t pb, const void *rhs, void *x, int32_t nrhs, const fmb_gmres_opts *o,
+                fmb_gmres_info *info, void *stream) {
+    int conv_status = FMB_OK;
+    int code = guarded([&] {
+        FMB_REQUIRE(pb && rhs && x && rhs != x, "bad arguments");
+        FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
+        fmb_gmres_opts op;
+        fmb_gmres_opts_default(&op);
+        if (o) op = *o;
+        FMB_REQUIRE(op.tol > 0 && op.restart >= 1 && op.maxit >= 1, "bad solver options");
+        FMB_REQUIRE(!op.mixed || pb->p032, "mixed precision needs the FP32 plans");
+        hipStream_t s = (hipStream_t)stream;
+        Krylov K;
+        const int64_t len = pb->n * 6;
+        krylov_alloc(K, len, nrhs, op.restart);
+        const cx<double> *b = (const cx<double> *)rhs;
+        cx<double> *X = (cx<double> *)x;
+        std::vector<double> relres, hist;
+        int mv64 = 0, mv32 = 0, its = 0, refinements = 0;
+        double final_res = 0.0;
+        if (!op.mixed) {
+            its = fgmres(*pb, K, b, X, op.x0_given != 0, op.tol, op.maxit, 0, op.precond, relres, &hist, mv64, s);
+            for (double v : relres) final_res = std::max(final_res, v);
+        } else {
+            // iterative refinement: FP64 residuals, FP32-operator corrections
+            const int64_t tot = len * nrhs;
+            DevBuf rr, ax, dx;
+            rr.alloc(tot * sizeof(cx<double>));
+            ax.alloc(tot * sizeof(cx<double>));
+            dx.alloc(tot * sizeof(cx<double>));
+            if (op.x0_given) {
+                bem_apply_impl(*pb, X, ax.as<cx<double>>(), nrhs, 0, s);
+                ++mv64;
+                k_sub<<<gridn(tot), TPB, 0, s>>>(b, ax.as<cx<double>>(), rr.as<cx<double>>(), tot);
+            } else {
+                FMB_CHECK_HIP(hipMemsetAsync(X, 0, tot * sizeof(cx<double>), s));
+                FMB_CHECK_HIP(hipMemcpyAsync(rr.p, b, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+            }
+            std::vector<double> bn(nrhs), rn(nrhs);
+            norms(K, b, K.hn.as<double>(), nullptr, s);
+            FMB_CHECK_HIP(hipMemcpyAsync(bn.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+            while (true) {
+                norms(K, rr.as<cx<double>>(), K.hn.as<double>(), nullptr, s);
+                FMB_CHECK_HIP(hipMemcpyAsync(rn.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+                FMB_CHECK_HIP(hipStreamSynchronize(s));
+                final_res = 0.0;
+                for (int r = 0; r < nrhs; ++r) {
+                    if (!std::isfinite(rn[r])) throw Status{FMB_ENONFINITE, "non-finite residual in refinement"};
+                    final_res = std::max(final_res, bn[r] > 0 ? rn[r] / bn[r] : 0.0);
+                }
+                hist.push_back(final_res);
+                if (final_res <= op.tol || its >= op.maxit || refinements >= 50) break;
+                std::vector<double> inner;
+                its += fgmres(*pb, K, rr.as<cx<double>>(), dx.as<cx<double>>(), false, op.inner_tol,
+                              std::min(op.inner_maxit, op.maxit - its), 1, op.precond, inner, nullptr, mv32, s);
+                k_axpy_masked<<<gridn(tot), TPB, 0, s>>>(X, dx.as<cx<double>>(), len, nrhs);
+                bem_apply_impl(*pb, X, ax.as<cx<double>>(), nrhs, 0, s);
+                ++mv64;
+                k_sub<<<gridn(tot), TPB, 0, s>>>(b, ax.as<cx<double>>(), rr.as<cx<double>>(), tot);
+                FMB_LAUNCH_CHECK();
+                ++refinements;
+            }
+        }
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->iterations = its;
+            info->refinements = refinements;
+            info->matvecs64 = mv64;
+            info->matvecs32 = mv32;
+            info->residual = final_res;
+            for (size_t i = 0; i < hist.size() && i < 256; ++i) info->history[i] = hist[i];
+        }
+        if (!(final_res <= op.tol)) conv_status = FMB_ENOCONV;
+    });
+    if (code != FMB_OK) return code;
+    if (conv_status != FMB_OK) set_error("fGMRES reached maxit before the tolerance");
+    return conv_status;
+}
+
+int bem_problem_destroy(fmb_problem_t pb) {
+    return guarded([&] { delete pb; });
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+"""Binding of the BEM system and fGMRES entry points (marshalling only)."""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import Plan, check, _stream
+
+
+class BemProblem:
+    """One scatterer in vacuum: plans at k0 and k1 = k0 sqrt(eps mu) over the same nodes.
+
+    `bem_problem_create` wires the plans into the 6N system and builds the
+    A_self block preconditioner; solves run through `gmres_solve`.
+    """
+
+    def __init__(self, nodes, k0, eps, mu=1.0, order=16, depth=0, nrhs_max=1, order32=None,
+                 corr="linear", leaf_target=32):
+        lib = _abi.load()
+        self._lib = lib
+        self.k0 = complex(k0)
+        self.eps = complex(eps)
+        self.mu = complex(mu)
+        self.k1 = self.k0 * np.sqrt(self.eps * self.mu)
+        kw = dict(point_tri=nodes["point_tri"], tri_vertices=nodes["tri_vertices"], nrhs_max=nrhs_max,
+                  corr=corr, depth=depth, leaf_target=leaf_target)
+        pts, nrm, w = nodes["points"], nodes["normals"], nodes["weights"]
+        self.p0 = Plan(pts, nrm, w, self.k0, order, **kw)
+        kw["depth"] = self.p0.info()["depth"]
+        self.p1 = Plan(pts, nrm, w, self.k1, order, **kw)
+        self.p0_32 = self.p1_32 = None
+        if order32:
+            self.p0_32 = Plan(pts, nrm, w, self.k0, order32, precision="fp32", **kw)
+            self.p1_32 = Plan(pts, nrm, w, self.k1, order32, precision="fp32", **kw)
+        self.n = pts.shape[0]
+        self.nrhs_max = nrhs_max
+        eps_a = np.array([self.eps.real, self.eps.imag])
+        mu_a = np.array([self.mu.real, self.mu.imag])
+        h = ctypes.c_void_p()
+        check(lib.bem_problem_create(self.p0.h, self.p1.h, self.p0_32.h if self.p0_32 else None,
+                                     self.p1_32.h if self.p1_32 else None, eps_a.ctypes.data, mu_a.ctypes.data,
+                                     _stream(), ctypes.byref(h)))
+        self.h = h
+
+    def _v(self, t, name):
+        if t.dim() == 2:
+            t = t.unsqueeze(0)
+        return _abi._dev(t, torch.complex128, (self.n, 6), name), t.shape[0]
+
+    def apply(self, x):
+        """A x, x complex128 [nrhs, n, 6] (or [n, 6]) on the GPU."""
+        out = torch.empty_like(x)
+        px, nr = self._v(x, "x")
+        check(self._lib.bem_apply(self.h, px, ctypes.c_void_p(out.data_ptr()), nr, _stream()))
+        return out
+
+    def precond(self, v):
+        out = torch.empty_like(v)
+        pv, nr = self._v(v, "v")
+        check(self._lib.bem_precond_apply(self.h, pv, ctypes.c_void_p(out.data_ptr()), nr, _stream()))
+        return out
+
+    def rhs_planewave(self, dirs, pols):
+        d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+        p = np.ascontiguousarray(np.atleast_2d(pols), dtype=np.float64)
+        nr = d.shape[0]
+        out = torch.empty((nr, self.n, 6), dtype=torch.complex128, device="cuda")
+        check(self._lib.bem_rhs_planewave(self.h, d.ctypes.data, p.ctypes.data, ctypes.c_void_p(out.data_ptr()),
+                                          nr, _stream()))
+        return out
+
+    def solve(self, rhs, tol=1e-6, restart=100, maxit=1000, precond=True, mixed=False, inner_tol=1e-3,
+              inner_maxit=300, x0=None, raise_on_noconv=True):
+        opts = _abi.GmresOpts()
+        check(self._lib.fmb_gmres_opts_default(ctypes.byref(opts)))
+        opts.tol = tol
+        opts.restart = restart
+        opts.maxit = maxit
+        opts.precond = 1 if precond else 0
+        opts.mixed = 1 if mixed else 0
+        opts.inner_tol = inner_tol
+        opts.inner_maxit = inner_maxit
+        x = torch.zeros_like(rhs) if x0 is None else x0.clone()
+        opts.x0_given = 0 if x0 is None else 1
+        info = _abi.GmresInfo()
+        pr, nr = self._v(rhs, "rhs")
+        code = self._lib.gmres_solve(self.h, pr, ctypes.c_void_p(x.data_ptr()), nr, ctypes.byref(opts),
+                                     ctypes.byref(info), _stream())
+        res = {"iterations": info.iterations, "refinements": info.refinements, "matvecs64": info.matvecs64,
+               "matvecs32": info.matvecs32, "residual": info.residual, "code": code,
+               "history": list(info.history[:min(256, max(info.iterations, info.refinements + 1))])}
+        if code != _abi.FMB_OK and (code != _abi.FMB_ENOCONV or raise_on_noconv):
+            check(code)
+        return x, res
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.bem_problem_destroy(self.h)
+            self.h = None
+        for p in (self.p0, self.p1, self.p0_32, self.p1_32):
+            if p is not None:
+                p.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

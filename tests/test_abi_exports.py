@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every symbol include/fmbem.h declares (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fmbem.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:int|const char \*)\s*\**\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_symbols_exported():
+    from paper_1211_7177_amd import build as B
+    if not os.path.exists(B.LIB):
+        B.build()
+    lib = ctypes.CDLL(B.LIB)
+    names = _declared()
+    assert "fmm_plan" in names and "gmres_solve" in names and "fmm_matvec_adjoint" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_exposes_same_names():
+    from paper_1211_7177_amd import _abi
+    assert set(_declared()) <= set(_abi.EXPORTS)
+
+
+def test_host_validation_without_gpu():
+    """Argument errors are reported before any device work."""
+    import numpy as np
+    from paper_1211_7177_amd import _abi
+    lib = _abi.load()
+    h = ctypes.c_void_p()
+    pts = np.zeros((1, 3))
+    r = lib.fmm_plan(pts.ctypes.data, pts.ctypes.data, np.ones(1).ctypes.data, 1, 1.0, 0.0, 8, None, None,
+                     ctypes.byref(h))
+    assert r == _abi.FMB_EINVAL and b"n must be" in lib.fmb_last_error()
+    pts = np.random.default_rng(0).standard_normal((10, 3))
+    nrm = np.tile([0.0, 0.0, 1.0], (10, 1))
+    w = np.ones(10)
+    r = lib.fmm_plan(pts.ctypes.data, nrm.ctypes.data, w.ctypes.data, 10, 1.0, -0.5, 8, None, None, ctypes.byref(h))
+    assert r == _abi.FMB_EINVAL and b"Im k" in lib.fmb_last_error()
+    bad = nrm.copy()
+    bad[3] = [0.0, 0.0, 1.1]
+    r = lib.fmm_plan(pts.ctypes.data, bad.ctypes.data, w.ctypes.data, 10, 1.0, 0.0, 8, None, None, ctypes.byref(h))
+    assert r == _abi.FMB_EINVAL and b"unit" in lib.fmb_last_error()
+    pts2 = pts.copy()
+    pts2[2, 1] = np.nan
+    r = lib.fmm_plan(pts2.ctypes.data, nrm.ctypes.data, w.ctypes.data, 10, 1.0, 0.0, 8, None, None, ctypes.byref(h))
+    assert r == _abi.FMB_EINVAL and b"non-finite" in lib.fmb_last_error()
+    w2 = w.copy()
+    w2[5] = 0.0
+    r = lib.fmm_plan(pts.ctypes.data, nrm.ctypes.data, w2.ctypes.data, 10, 1.0, 0.0, 8, None, None, ctypes.byref(h))
+    assert r == _abi.FMB_EINVAL and b"weights" in lib.fmb_last_error()
+    r = lib.fmm_plan(pts.ctypes.data, nrm.ctypes.data, w.ctypes.data, 10, 1.0, 0.0, 99, None, None, ctypes.byref(h))
+    assert r == _abi.FMB_EINVAL and b"order" in lib.fmb_last_error()
+    assert lib.fmm_matvec_adjoint(None, None, None, None, 1, None) == _abi.FMB_ENOTIMPL

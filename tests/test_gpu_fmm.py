@@ -1,0 +1,163 @@
+"""GPU parity of the FMM operator against the oracle (needs an MI355X)."""
+
+import numpy as np
+import pytest
+
+from oracle.corrections import self_blocks
+from oracle.direct import apply_corrections
+from oracle.native import point_sum_c
+from oracle.tree import Octree
+from synthetic import complex_normal, icosphere, nystrom3, seed_for, torus
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def abi():
+    _need_gpu()
+    from paper_1211_7177_amd import _abi
+    _abi.load()
+    return _abi
+
+
+@pytest.fixture(scope="module")
+def sphere():
+    return nystrom3(icosphere(8))          # 1280 triangles, 3840 nodes
+
+
+@pytest.fixture(scope="module")
+def torus_c2():
+    return nystrom3(torus(1.0, 0.3, 200, 50))   # 20000 triangles, 60000 nodes
+
+
+def _plan(abi, q, k, order, depth, precision="fp64", corr="linear", nrhs_max=1):
+    return abi.Plan(q["points"], q["normals"], q["weights"], k, order, depth=depth, precision=precision,
+                    nrhs_max=nrhs_max, corr=corr, point_tri=q["point_tri"], tri_vertices=q["tri_vertices"])
+
+
+def _dens(n, cfg, nrhs=None, dtype=np.complex128):
+    shape = (n, 3) if nrhs is None else (nrhs, n, 3)
+    return complex_normal(shape, seed_for(cfg, "a"), dtype), complex_normal(shape, seed_for(cfg, "b"), dtype)
+
+
+def _gpu(x, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def _rel(y, ref):
+    return np.linalg.norm(y - ref) / np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("shape,depth", [("sphere", 3), ("torus", 5)])
+def test_tree_bit_exact(abi, sphere, torus_c2, shape, depth):
+    q = sphere if shape == "sphere" else torus_c2
+    print("tree", shape, depth, flush=True)
+    P = _plan(abi, q, 1.0, 4, depth, corr="none")
+    ref = Octree(q["points"], depth)
+    t = P.export_tree(depth)
+    assert np.array_equal(t["codes"], ref.codes)
+    assert np.array_equal(t["perm"], ref.perm.astype(np.int32))
+    for l in range(depth + 1):
+        t = P.export_tree(l)
+        assert np.array_equal(t["keys"], ref.keys[l])
+        assert np.array_equal(t["start"], ref.box_start[l].astype(np.int32))
+        assert np.array_equal(t["parent"], ref.parent[l].astype(np.int32))
+        for b in range(len(ref.keys[l])):
+            nb = np.sort(t["nbr"][b][t["nbr"][b] >= 0])
+            assert np.array_equal(nb, ref.nbr[l][b])
+            if l >= 2:
+                ff = np.sort(t["ff_idx"][t["ff_ofs"][b]:t["ff_ofs"][b + 1]])
+                assert np.array_equal(ff, ref.ff[l][b])
+    P.close()
+
+
+@pytest.mark.parametrize("k", [1.0, 1.5, 2 + 1.5j])
+def test_fp64_matvec_matches_direct_sum(abi, sphere, k):
+    q = sphere
+    n = q["points"].shape[0]
+    a, b = _dens(n, 1)
+    print("fp64 matvec sphere k=", k, flush=True)
+    P = _plan(abi, q, k, 16, 3, corr="none")
+    y = P.matvec(_gpu(a), _gpu(b)).cpu().numpy()
+    ref = point_sum_c(q["points"], q["normals"], q["weights"], q["point_tri"], k, a, b)
+    err = _rel(y, ref)
+    print("rel err", err)
+    assert err <= 1e-6
+    # high order: the far field converges further
+    P2 = _plan(abi, q, k, 22, 3, corr="none")
+    y2 = P2.matvec(_gpu(a), _gpu(b)).cpu().numpy()
+    assert _rel(y2, ref) <= 1e-8
+    P.close()
+    P2.close()
+
+
+def test_corrections_match_oracle(abi, sphere):
+    q = sphere
+    n = q["points"].shape[0]
+    a, b = _dens(n, 1)
+    for k in (1.0, 1.5 + 0.5j):
+        print("corrections k=", k, flush=True)
+        P0 = _plan(abi, q, k, 8, 3, corr="none")
+        P1 = _plan(abi, q, k, 8, 3, corr="linear")
+        y0 = P0.matvec(_gpu(a), _gpu(b)).cpu().numpy()
+        y1 = P1.matvec(_gpu(a), _gpu(b)).cpu().numpy()
+        blk = self_blocks(q["points"], q["normals"], q["point_tri"], q["tri_vertices"], k, mode="linear")
+        ref = apply_corrections(q["normals"], q["point_tri"], blk, a, b)
+        assert _rel(y1 - y0, ref) <= 1e-10
+        P0.close()
+        P1.close()
+
+
+def test_fp32_matvec_tolerance(abi, sphere):
+    q = sphere
+    n = q["points"].shape[0]
+    a, b = _dens(n, 1)
+    k = 1.5
+    P = _plan(abi, q, k, 10, 3, precision="fp32", corr="none")
+    y = P.matvec(_gpu(a, torch.complex64), _gpu(b, torch.complex64)).cpu().numpy()
+    ref = point_sum_c(q["points"], q["normals"], q["weights"], q["point_tri"], k, a, b)
+    err = _rel(y, ref)
+    print("fp32 rel err", err)
+    assert err <= 5e-5
+    P.close()
+
+
+def test_batched_rhs_and_determinism(abi, sphere):
+    q = sphere
+    n = q["points"].shape[0]
+    a, b = _dens(n, 1, nrhs=3)
+    P = _plan(abi, q, 1.2, 12, 3, nrhs_max=3)
+    yb = P.matvec(_gpu(a), _gpu(b)).cpu().numpy()
+    yb2 = P.matvec(_gpu(a), _gpu(b)).cpu().numpy()
+    assert np.array_equal(yb, yb2)                       # run-to-run bitwise identical
+    for r in range(3):
+        y1 = P.matvec(_gpu(a[r:r + 1]), _gpu(b[r:r + 1])).cpu().numpy()
+        assert np.array_equal(y1[0], yb[r])
+    P.close()
+
+
+@pytest.mark.parametrize("k", [4.0, complex(0.5161, 15.5034)])
+def test_torus_full_size_sampled_rows(abi, torus_c2, k):
+    """The 60k-node torus at depth 5: FP64 FMM + corrections against the oracle
+    on 512 seeded rows."""
+    q = torus_c2
+    n = q["points"].shape[0]
+    a, b = _dens(n, 2)
+    rows = np.sort(np.random.default_rng(seed_for(2, "rows")).choice(n, 512, replace=False))
+    print("torus k=", k, flush=True)
+    P = _plan(abi, q, k, 16, 5)
+    y = P.matvec(_gpu(a), _gpu(b)).cpu().numpy()[rows]
+    ref = point_sum_c(q["points"], q["normals"], q["weights"], q["point_tri"], k, a, b, rows=rows)
+    blk = self_blocks(q["points"], q["normals"], q["point_tri"], q["tri_vertices"], k, mode="linear")
+    ref = ref + apply_corrections(q["normals"], q["point_tri"], blk, a, b, rows=rows)
+    err = _rel(y, ref)
+    print("torus rel err", err, P.info())
+    assert err <= 1e-6
+    P.close()
