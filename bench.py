@@ -1,0 +1,221 @@
+"""Benchmark: GMRES solves/s (and FMM matvecs/s) at 1e-6 relative residual on
+the 60k-node silver-like torus (R = 1, r = 0.3, 200 x 50 x 2 triangles,
+eps = -15 + 1i, k0 R = 4, octree depth 5), FP32/mixed-precision against the
+plain FP64 solve, on one MI355X.
+
+One timed step is one right-preconditioned fGMRES solve of the 6N system for a
+seeded plane wave with the product path: FP32 FMM operators inside an FP64
+iterative refinement (gather, P2M, M2M, M2L, L2L, L2P, P2P, FP64 self-triangle
+corrections, BEM apply, block preconditioner, Arnoldi), to a true FP64
+residual <= 1e-6.  Plans (octree, operators, correction blocks) are built
+once before the timed region from host arrays.
+
+Prints one JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm_GBs": 8000.0, "fp64_TF": 78.6, "fp32_TF": 157.3}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--order64", type=int, default=16)
+    ap.add_argument("--order32", type=int, default=9)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--inner-tol", type=float, default=2e-3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=1500)
+    ap.add_argument("--skip-fp64-solve", action="store_true")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def m2l_flops(info, nrhs=1):
+    """Algorithmic flops of the dense S|R translations of one matvec: a complex
+    (p^2 x p^2) by (p^2 x 3 nrhs) product per far-field pair, 8 flops per
+    complex multiply-add."""
+    p2 = info["order"] ** 2
+    pairs = sum(info["m2l_pairs"])
+    return 8.0 * p2 * p2 * 3 * nrhs * pairs
+
+
+def p2p_flops(info, nrhs=1):
+    """About 110 flops per near (target, source) pair for one right-hand side."""
+    return 110.0 * info["p2p_pairs"] * nrhs
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1211_7177_amd.solver import BemProblem
+    from synthetic import config_mesh, nystrom3, plane_waves, seed_for, CONFIGS
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = CONFIGS[2]
+    mesh = config_mesh(2)
+    nodes = nystrom3(mesh)
+    n = nodes["points"].shape[0]
+    k0, eps, depth = cfg["k0"], cfg["eps"], cfg["depth"]
+    d, pol = plane_waves(1, seed_for(2, "dirs"), seed_for(2, "pols"))
+
+    t0 = time.perf_counter()
+    pb = BemProblem(nodes, k0, eps, order=args.order64, depth=depth, order32=args.order32)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    log("plans built in %.2f s" % plan_s)
+    info64 = pb.p0.info()
+    info32 = pb.p0_32.info()
+    rhs = pb.rhs_planewave(d, pol)
+
+    def step():
+        return pb.solve(rhs, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=100, maxit=2000)
+
+    for _ in range(args.warmup):
+        _, wi = step()
+        log("warmup solve", wi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        x, inf = step()
+        infos.append(inf)
+        log("timed solve", inf["iterations"], inf["refinements"], inf["residual"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt / args.steps
+    solves_per_s = args.steps / dt
+    last = infos[-1]
+
+    # plain FP64 solve (reference path) and matvec rates, outside the timed region
+    fp64 = None
+    if not args.skip_fp64_solve:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x64, inf64 = pb.solve(rhs, tol=args.tol, mixed=False, restart=100, maxit=2000)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        log("fp64 solve %.3f s" % t64, inf64["iterations"], inf64["residual"])
+        diff = (torch.linalg.vector_norm(x64 - x) / torch.linalg.vector_norm(x64)).item()
+        fp64 = {"solves_per_s": 1.0 / t64, "ms_per_solve": 1e3 * t64, "iterations": inf64["iterations"],
+                "bem_applies": inf64["matvecs64"], "residual": inf64["residual"],
+                "rel_diff_vs_mixed_solution": diff}
+
+    # FMM matvec rates and stage profile (HIP events on the stream the kernels run on)
+    rates = {}
+    prof = {}
+    for tag, plan, cdt in (("fp64", pb.p0, torch.complex128), ("fp32", pb.p0_32, torch.complex64)):
+        a = torch.randn(1, n, 3, dtype=cdt, device=dev)
+        b = torch.randn(1, n, 3, dtype=cdt, device=dev)
+        y = plan.matvec(a, b)
+        torch.cuda.synchronize()
+        reps = 10
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            plan.matvec(a, b, out=y)
+        torch.cuda.synchronize()
+        rates[tag] = reps / (time.perf_counter() - t1)
+        plan.profile(True)
+        plan.profile_read(reset=True)
+        for _ in range(reps):
+            plan.matvec(a, b, out=y)
+        prof[tag] = plan.profile_read(reset=True)
+        plan.profile(False)
+        log(tag, "matvec/s %.1f" % rates[tag], prof[tag])
+
+    # dominant kernel of the product path: the FP32 S|R translation stage
+    inf = info32
+    m2l_ms, m2l_launches = prof["fp32"]["m2l"]
+    per_matvec_ms = m2l_ms / 10.0
+    achieved_tf = m2l_flops(inf) / (per_matvec_ms * 1e-3) / 1e12
+    roofline = {"kernel": "k_translate (S|R, FP32, all levels) + per-target sums", "bound": "alu",
+                "achieved": achieved_tf, "peak": PEAK["fp32_TF"], "unit": "TFLOP/s",
+                "frac": achieved_tf / PEAK["fp32_TF"], "traffic": None,
+                "per_launch_flops": m2l_flops(inf) / max(1, m2l_launches // 10),
+                "avg_launch_ms": m2l_ms / max(1, m2l_launches)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(nodes, k0, eps, args.cpu_rows,
+                           fp64["bem_applies"] if fp64 else last["matvecs64"] + last["matvecs32"])
+
+    out = {
+        "metric": "FMM matvecs/s & GMRES solves/s at 1e-6 rel err, FP32/batched vs plain FP64",
+        "value": solves_per_s,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 FMM + f64 corrections/Arnoldi/residual",
+        "data": "synthetic",
+        "config": {"workload": "torus_R1_r0.3_20000tri_60000nodes_eps-15+1i_k0R4_depth5_planewave",
+                   "nodes": n, "unknowns": 6 * n, "depth": depth, "order_fp64": args.order64,
+                   "order_fp32": args.order32, "tol": args.tol},
+        "solve": {"iterations": last["iterations"], "refinements": last["refinements"],
+                  "bem_applies_fp32": last["matvecs32"], "bem_applies_fp64": last["matvecs64"],
+                  "residual": last["residual"]},
+        "fp64_solve": fp64,
+        "speedup_vs_fp64_solve": (solves_per_s / fp64["solves_per_s"]) if fp64 else None,
+        "fmm_matvecs_per_s": rates,
+        "unknowns_matvec_per_s": {k: 3 * n * v for k, v in rates.items()},
+        "stage_ms_per_matvec": {t: {s: v[0] / 10.0 for s, v in prof[t].items()} for t in prof},
+        "plan_s_4plans": plan_s,
+        "plan_info_fp64": {k: info64[k] for k in ("nbox", "m2l_pairs", "p2p_pairs", "device_bytes")},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(nodes, k0, eps, rows, applies_per_solve):
+    """The FP64 oracle's direct-sum BEM apply on a seeded sample of target rows
+    (both wavenumbers), scaled to a full apply and to one solve."""
+    from oracle.kernel import wavenumber
+    from oracle.native import point_sum_c
+    from synthetic import complex_normal, seed_for
+
+    n = nodes["points"].shape[0]
+    rng = np.random.default_rng(seed_for(2, "rows"))
+    sel = np.sort(rng.choice(n, rows, replace=False))
+    a = complex_normal((n, 3), seed_for(2, "a"))
+    b = complex_normal((n, 3), seed_for(2, "b"))
+    k1 = wavenumber(k0, eps)
+    t0 = time.perf_counter()
+    for k in (k0, k1):
+        point_sum_c(nodes["points"], nodes["normals"], nodes["weights"], nodes["point_tri"], k, a, b, rows=sel)
+    dt = time.perf_counter() - t0
+    apply_s = dt * n / rows
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    return {"value": 1.0 / (apply_s * applies_per_solve), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": "direct-sum BEM apply (both wavenumbers) on %d of %d target rows, %.2f s, scaled by n/rows "
+                      "to one apply (%.1f s) and by %d applies per FP64 fGMRES solve" %
+                      (rows, n, dt, apply_s, applies_per_solve),
+            "applies_per_s": 1.0 / apply_s}
+
+
+if __name__ == "__main__":
+    main()

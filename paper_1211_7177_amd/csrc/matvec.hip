@@ -377,77 +377,109 @@ __global__ void __launch_bounds__(TPB) k_p2p(const int32_t *__restrict__ start, 
 }
 
 // ---------------------------------------------------------------- translations
-// Batched complex GEMM grouped by operator: for every entry e of a tile,
-//   Y[dst(e)] (=|+=) T_op * X[src(e)]
-// with X, Y column blocks of 3*nrhs columns of P2 coefficients.
+// Batched GEMM grouped by operator: for every entry e of a tile,
+//   Y[dst(e)] = T_op * X[src(e)]
+// with X, Y column blocks of 3*nrhs columns of P2 complex coefficients.  The
+// complex product is done as a real one: a complex column is read as its
+// 2*P2 interleaved (re, im) reals and the operator is stored as the real
+// 2P2 x 2P2 matrix with 2x2 blocks [[re, -im], [im, re]].  Each 64x64 block
+// tile of the real product is computed by four waves of 16x16x4 MFMA
+// instructions with operands staged through LDS.
 struct Tile {
     int32_t op, first, count;
 };
-constexpr int GEMM_EP = 16;       // largest number of entries per tile
-constexpr int GEMM_BK = 16;       // k-chunk
-constexpr int GEMM_CW = 48;       // columns per chunk
+constexpr int TM = 64, TN = 64, TK = 16;
+
+template <typename T>
+struct Mfma;
+// Operand layout (both types): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16].
+// Result layout differs: register q of lane l holds D[row][l % 16] with
+//   f64 16x16x4: row = l / 16 + 4 q        f32 16x16x4: row = 4 (l / 16) + q
+// (both checked with an on-device probe).
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 mma(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int q) { return (lane >> 4) + 4 * q; }
+};
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 mma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int q) { return 4 * (lane >> 4) + q; }
+};
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_translate(const Tile *__restrict__ tiles, const int32_t *__restrict__ ent,
-                                                   const int32_t *__restrict__ src_map, const cx<T> *__restrict__ ops,
-                                                   const cx<T> *__restrict__ X, cx<T> *__restrict__ Y, int P2, int ncol,
-                                                   int64_t blk, int accumulate) {
-    // ncol = 3*nrhs columns per entry; blk = column-block stride per box (nrhs_max*3*P2)
-    __shared__ cx<T> As[64][GEMM_BK + 1];
-    __shared__ cx<T> Bs[GEMM_BK][GEMM_CW];
-    __shared__ int32_t s_src[GEMM_EP], s_dst[GEMM_EP];
+                                                   const int32_t *__restrict__ src_map, const T *__restrict__ ops,
+                                                   const T *__restrict__ X, T *__restrict__ Y, int KR, int ncol,
+                                                   int64_t blkR) {
+    typedef typename Mfma<T>::v4 v4;
+    __shared__ T As[TM][TK + 1];
+    __shared__ T Bs[TK][TN];
+    __shared__ int32_t s_src[TN], s_dst[TN];
     const Tile tl = tiles[blockIdx.x];
-    const cx<T> *Top = ops + (size_t)tl.op * P2 * P2;
-    if (threadIdx.x < tl.count) {
-        int32_t e = ent[tl.first + threadIdx.x];
-        s_dst[threadIdx.x] = e;
-        s_src[threadIdx.x] = src_map ? src_map[e] : e;
+    const int r0 = blockIdx.y * TM;
+    const T *Top = ops + (size_t)tl.op * KR * KR;
+    for (int q = threadIdx.x; q < tl.count && q < TN; q += blockDim.x) {
+        int32_t e = ent[tl.first + q];
+        s_dst[q] = e;
+        s_src[q] = src_map ? src_map[e] : e;
     }
-    __syncthreads();
-    const int Ctot = tl.count * ncol;        // columns in this tile
-    // thread layout: 64 rows x 4 column groups; columns processed in chunks of GEMM_CW
-    const int row = threadIdx.x & 63, cg = threadIdx.x >> 6;
-    for (int c0 = 0; c0 < Ctot; c0 += GEMM_CW) {
-        const int C = min(GEMM_CW, Ctot - c0);
-        const int CPG = (C + 3) / 4;         // columns per group (<= GEMM_CW/4)
-        for (int r0 = 0; r0 < P2; r0 += 64) {
-            cx<T> acc[GEMM_CW / 4];
-            for (int q = 0; q < GEMM_CW / 4; ++q) acc[q] = mk(T(0), T(0));
-            for (int k0 = 0; k0 < P2; k0 += GEMM_BK) {
-                __syncthreads();
-                for (int t = threadIdx.x; t < 64 * GEMM_BK; t += blockDim.x) {
-                    int rr = t / GEMM_BK, kk = t % GEMM_BK;
-                    As[rr][kk] = (r0 + rr < P2 && k0 + kk < P2) ? Top[(size_t)(r0 + rr) * P2 + k0 + kk] : mk(T(0), T(0));
-                }
-                for (int t = threadIdx.x; t < GEMM_BK * C; t += blockDim.x) {
-                    int kk = t % GEMM_BK, c = c0 + t / GEMM_BK;
-                    int e = c / ncol, cc = c % ncol;
-                    Bs[kk][c - c0] = (k0 + kk < P2) ? X[(int64_t)s_src[e] * blk + (int64_t)cc * P2 + k0 + kk]
-                                                    : mk(T(0), T(0));
-                }
-                __syncthreads();
-                const int kmax = min(GEMM_BK, P2 - k0);
-                for (int kk = 0; kk < kmax; ++kk) {
-                    const cx<T> a = As[row][kk];
-#pragma unroll
-                    for (int q = 0; q < GEMM_CW / 4; ++q) {
-                        const int c = cg * CPG + q;
-                        if (q < CPG && c < C) acc[q] += a * Bs[kk][c];
-                    }
-                }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr0 = (wave >> 1) * 32, wc0 = (wave & 1) * 32;
+    const int Ctot = tl.count * ncol;
+    for (int c0 = 0; c0 < Ctot; c0 += TN) {
+        const int C = min(TN, Ctot - c0);
+        v4 acc[2][2];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) acc[i][j] = v4{0, 0, 0, 0};
+        for (int k0 = 0; k0 < KR; k0 += TK) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < TM * TK; t += blockDim.x) {
+                const int rr = t / TK, kk = t % TK;
+                As[rr][kk] = (r0 + rr < KR && k0 + kk < KR) ? Top[(size_t)(r0 + rr) * KR + k0 + kk] : T(0);
             }
-            if (r0 + row < P2) {
-#pragma unroll
-                for (int q = 0; q < GEMM_CW / 4; ++q) {
-                    const int c = c0 + cg * CPG + q;
-                    if (q >= CPG || c >= c0 + C) break;
-                    const int e = c / ncol, cc = c % ncol;
-                    cx<T> &o = Y[(int64_t)s_dst[e] * blk + (int64_t)cc * P2 + r0 + row];
-                    if (accumulate) o += acc[q];
-                    else o = acc[q];
+            for (int t = threadIdx.x; t < TN * TK; t += blockDim.x) {
+                const int c = t / TK, kk = t % TK;
+                T v = T(0);
+                if (c < C && k0 + kk < KR) {
+                    const int cg = c0 + c;
+                    const int e = cg / ncol, cc = cg % ncol;
+                    v = X[(int64_t)s_src[e] * blkR + (int64_t)cc * KR + k0 + kk];
                 }
+                Bs[kk][c] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k4 = 0; k4 < TK; k4 += 4) {
+                T a[2], b[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) a[i] = As[wr0 + 16 * i + (lane & 15)][k4 + (lane >> 4)];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) b[j] = Bs[k4 + (lane >> 4)][wc0 + 16 * j + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
             }
         }
+        // lane holds column lane%16 and rows Mfma<T>::row(lane, q) of each 16x16 tile
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = wc0 + 16 * j + (lane & 15);
+                if (col >= C) continue;
+                const int cg = c0 + col;
+                const int e = cg / ncol, cc = cg % ncol;
+                T *yo = Y + (int64_t)s_dst[e] * blkR + (int64_t)cc * KR;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = r0 + wr0 + 16 * i + Mfma<T>::row(lane, q);
+                    if (row < KR) yo[row] = acc[i][j][q];
+                }
+            }
     }
 }
 
@@ -486,6 +518,9 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
     const int L = P.depth, p = P.order, P2 = P.P2;
     const int64_t blk = (int64_t)P.nrhs_max * 3 * P2;
     const int ncol = 3 * nrhs;
+    const int KR = 2 * P2;                          // real rows of the embedded operators
+    const int64_t blkR = 2 * blk;
+    const unsigned rowblocks = (unsigned)((KR + TM - 1) / TM);
     cx<T> *src = P.src.as<cx<T>>();
     cx<T> *ys = P.ys.as<cx<T>>();
     cx<T> *yb = P.ybuf.as<cx<T>>();
@@ -515,8 +550,9 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
         Level &V = P.lv[l], &C = P.lv[l + 1];
         if (V.ntiles_m2m == 0) continue;
         tm.begin(ST_M2M, s, ev);
-        k_translate<T><<<(unsigned)V.ntiles_m2m, TPB, 0, s>>>(V.tiles_m2m.as<Tile>(), C.by_octant.as<int32_t>(), nullptr,
-                                                               V.m2m.as<cx<T>>(), C.M.as<cx<T>>(), yb, P2, ncol, blk, 0);
+        k_translate<T><<<dim3((unsigned)V.ntiles_m2m, rowblocks), TPB, 0, s>>>(
+            V.tiles_m2m.as<Tile>(), C.by_octant.as<int32_t>(), nullptr, V.m2m.as<T>(), (const T *)C.M.p, (T *)yb, KR,
+            ncol, blkR);
         k_sum_children<T><<<(unsigned)V.nbox, TPB, 0, s>>>(V.child_start.as<int32_t>(), V.nbox, yb, V.M.as<cx<T>>(), blk,
                                                            ncol * P2);
         FMB_LAUNCH_CHECK();
@@ -528,17 +564,17 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
         if (l >= 3 && V.ntiles_l2l > 0) {
             Level &U = P.lv[l - 1];
             tm.begin(ST_L2L, s, ev);
-            k_translate<T><<<(unsigned)V.ntiles_l2l, TPB, 0, s>>>(V.tiles_l2l.as<Tile>(), V.by_octant.as<int32_t>(),
-                                                                   V.parent.as<int32_t>(), V.l2l.as<cx<T>>(),
-                                                                   U.L.as<cx<T>>(), V.L.as<cx<T>>(), P2, ncol, blk, 0);
+            k_translate<T><<<dim3((unsigned)V.ntiles_l2l, rowblocks), TPB, 0, s>>>(
+                V.tiles_l2l.as<Tile>(), V.by_octant.as<int32_t>(), V.parent.as<int32_t>(), V.l2l.as<T>(),
+                (const T *)U.L.p, (T *)V.L.p, KR, ncol, blkR);
             FMB_LAUNCH_CHECK();
             tm.end(ST_L2L, s, ev);
         }
         tm.begin(ST_M2L, s, ev);
         if (V.ntiles_m2l > 0) {
-            k_translate<T><<<(unsigned)V.ntiles_m2l, TPB, 0, s>>>(V.tiles_m2l.as<Tile>(), V.ff_by_op.as<int32_t>(),
-                                                                   V.ff_src.as<int32_t>(), V.m2l.as<cx<T>>(),
-                                                                   V.M.as<cx<T>>(), yb, P2, ncol, blk, 0);
+            k_translate<T><<<dim3((unsigned)V.ntiles_m2l, rowblocks), TPB, 0, s>>>(
+                V.tiles_m2l.as<Tile>(), V.ff_by_op.as<int32_t>(), V.ff_src.as<int32_t>(), V.m2l.as<T>(),
+                (const T *)V.M.p, (T *)yb, KR, ncol, blkR);
             FMB_LAUNCH_CHECK();
         }
         k_sum_far<T><<<(unsigned)V.nbox, TPB, 0, s>>>(V.ff_ofs.as<int32_t>(), yb, V.L.as<cx<T>>(), blk, ncol * P2,
@@ -584,7 +620,7 @@ void build_tiles(Plan &P, hipStream_t s) {
         if (!v.empty())
             FMB_CHECK_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
     };
-    const int ep = std::max(1, GEMM_EP / P.nrhs_max);
+    const int ep = std::max(1, TN / (3 * P.nrhs_max));
     auto chunk = [ep](std::vector<Tile> &v, int op, int first, int count) {
         for (int q = 0; q < count; q += ep) v.push_back(Tile{op, first + q, std::min(ep, count - q)});
     };

@@ -200,7 +200,9 @@ __global__ void k_build_op(OpDesc const *__restrict__ descs, int p, double k_re,
         }
     }
     __syncthreads();
-    TO *T = out + (size_t)d.out_slot * P2 * P2 * 2;
+    // real embedding: 2x2 block [[re, -im], [im, re]] at (2 dst, 2 src)
+    const int KR = 2 * P2;
+    TO *T = out + (size_t)d.out_slot * KR * KR;
     for (int e = threadIdx.x; e < P2 * P2; e += blockDim.x) {
         int dst = e / P2, src = e % P2;
         int n, m, n2, m2;
@@ -216,8 +218,10 @@ __global__ void k_build_op(OpDesc const *__restrict__ descs, int p, double k_re,
             acc += (4.0 * 3.14159265358979323846 * g[l]) * (ip * F[l * l + l + mu]);
         }
         acc = (sd[n2] * ss[n]) * acc;
-        T[2 * e] = (TO)acc.re;
-        T[2 * e + 1] = (TO)acc.im;
+        T[(size_t)(2 * dst) * KR + 2 * src] = (TO)acc.re;
+        T[(size_t)(2 * dst) * KR + 2 * src + 1] = (TO)(-acc.im);
+        T[(size_t)(2 * dst + 1) * KR + 2 * src] = (TO)acc.im;
+        T[(size_t)(2 * dst + 1) * KR + 2 * src + 1] = (TO)acc.re;
     }
 }
 
@@ -254,7 +258,7 @@ void build_operators(Plan &P, hipStream_t s) {
     }
     const size_t shmem = ((size_t)(Lm + 1) * (Lm + 1) + (Lm + 1)) * sizeof(cx<double>);
     auto launch = [&](std::vector<OpDesc> &ds, DevBuf &outbuf, int nslots) {
-        outbuf.alloc((size_t)nslots * P2 * P2 * 2 * esz);
+        outbuf.alloc((size_t)nslots * P2 * P2 * 4 * esz);
         if (ds.empty()) return;
         DevBuf dd;
         dd.alloc(ds.size() * sizeof(OpDesc));

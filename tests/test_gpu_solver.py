@@ -43,9 +43,10 @@ def test_bem_apply_precond_rhs_match_oracle(gpu, small):
     pb = gpu.BemProblem(q, 1.0, 2.25, order=20, depth=3)
     x = complex_normal((n, 6), seed_for(1, "a"))
     xg = torch.from_numpy(x).cuda()
-    y = pb.apply(xg).cpu().numpy()[0]
+    y = pb.apply(xg).cpu().numpy()
+    assert y.shape == x.shape
     assert _rel(y, ob.apply(x)) <= 1e-7
-    z = pb.precond(xg).cpu().numpy()[0]
+    z = pb.precond(xg).cpu().numpy()
     assert _rel(z, ob.block_preconditioner()(x)) <= 1e-11
     d = np.array([0.3, -0.4, np.sqrt(0.75)])
     p = np.cross(d, [1.0, 0.0, 0.0])
