@@ -148,6 +148,14 @@ __host__ __device__ inline cx<T> csin_(cx<T> z) {
 
 __device__ inline void sincos_t(double x, double *s, double *c) { sincos(x, s, c); }
 __device__ inline void sincos_t(float x, float *s, float *c) { sincosf(x, s, c); }
+// near-field kernel transcendentals: accurate FP64 library calls, hardware FP32 units
+// (v_sin/v_cos/v_exp/v_rsq; used where the arguments stay within a few radians)
+__device__ inline void fast_sincos(double x, double *s, double *c) { sincos(x, s, c); }
+__device__ inline void fast_sincos(float x, float *s, float *c) { *s = __sinf(x); *c = __cosf(x); }
+__device__ inline double fast_exp(double x) { return exp(x); }
+__device__ inline float fast_exp(float x) { return __expf(x); }
+__device__ inline double fast_rsqrt(double x) { return 1.0 / sqrt(x); }
+__device__ inline float fast_rsqrt(float x) { return rsqrtf(x); }
 
 // ---------------------------------------------------------------------------
 // spherical Bessel functions of complex argument (FP64 or FP32)

@@ -124,8 +124,12 @@ __device__ inline void grad_regular(const cx<T> *R, int N, cx<T> k, int n, int m
 }
 
 // ---------------------------------------------------------------- P2M
-constexpr int P2M_BATCH = 8;
-constexpr int P2M_SLOTS = 3;     // coefficients per thread: P2 <= 3 * 256
+// One block per leaf.  For a batch of the leaf's nodes the block first builds
+// the table R_n^m(s - X), n <= p, in LDS (one thread per (node, m) column),
+// then G = blockDim / p^2 thread groups each take every G-th node of the
+// batch and accumulate all three channels of one coefficient; the groups are
+// summed in LDS at the end (fixed order, so the result is deterministic).
+constexpr int P2M_SLOTS = 3;     // coefficients per thread when p^2 > blockDim
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, const double *__restrict__ center,
@@ -136,7 +140,7 @@ __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, 
     extern __shared__ unsigned char smem[];
     const int N = p;                                  // degrees 0..p for the gradients
     const int NN = (N + 1) * (N + 1);
-    cx<T> *Rb = reinterpret_cast<cx<T> *>(smem);                        // [BATCH][NN]
+    cx<T> *Rb = reinterpret_cast<cx<T> *>(smem);                        // [batch][NN]
     cx<T> *jb = Rb + batch * NN;                                        // [batch][N+1]
     double *dd = reinterpret_cast<double *>(jb + batch * (N + 1));      // [batch][3]
     const int box = blockIdx.x, r = blockIdx.y;
@@ -144,18 +148,20 @@ __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, 
     const double X[3] = {center[3 * box], center[3 * box + 1], center[3 * box + 2]};
     const cx<T> k = mk((T)k_re, (T)k_im);
     const int P2 = p * p;
+    const int G = P2 <= (int)blockDim.x ? (int)blockDim.x / P2 : 1;   // node groups
+    const int grp = P2 <= (int)blockDim.x ? (int)threadIdx.x / P2 : 0;
     cx<T> acc[P2M_SLOTS][3];
     for (int u = 0; u < P2M_SLOTS; ++u)
         for (int c = 0; c < 3; ++c) acc[u][c] = mk(T(0), T(0));
     for (int b0 = s0; b0 < s1; b0 += batch) {
         const int nb = min(batch, s1 - b0);
-        if (threadIdx.x < nb) {
-            const int i = b0 + threadIdx.x;
+        for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+            const int i = b0 + t;
             double d[3];
             for (int q = 0; q < 3; ++q) d[q] = spts[3 * (int64_t)i + q] - X[q];
-            for (int q = 0; q < 3; ++q) dd[threadIdx.x * 3 + q] = d[q];
+            for (int q = 0; q < 3; ++q) dd[t * 3 + q] = d[q];
             const double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            sph_bessel_j(mk((T)(k_re * rr), (T)(k_im * rr)), N, jb + threadIdx.x * (N + 1));
+            sph_bessel_j(mk((T)(k_re * rr), (T)(k_im * rr)), N, jb + t * (N + 1));
         }
         __syncthreads();
         for (int t = threadIdx.x; t < nb * (N + 1); t += blockDim.x) {
@@ -165,12 +171,12 @@ __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, 
         }
         __syncthreads();
         for (int u = 0; u < P2M_SLOTS; ++u) {
-            const int idx = threadIdx.x + u * blockDim.x;
-            if (idx >= P2) break;
+            const int idx = (G > 1) ? ((int)threadIdx.x % P2) : (int)threadIdx.x + u * (int)blockDim.x;
+            if (idx >= P2 || grp >= G || (G > 1 && u > 0)) break;
             int nn = 0;
             while ((nn + 1) * (nn + 1) <= idx) ++nn;
             const int mm = idx - nn * nn - nn;
-            for (int i = 0; i < nb; ++i) {
+            for (int i = grp; i < nb; i += G) {
                 const int64_t pi = b0 + i;
                 const cx<T> *R = Rb + i * NN;
                 const cx<T> Rv = Rget(R, N, nn, -mm);            // R_n^{-m}
@@ -185,6 +191,25 @@ __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, 
             }
         }
         __syncthreads();
+    }
+    if (G > 1) {
+        // sum the node groups in LDS (reuses the table area)
+        cx<T> *red = Rb;                                   // [G][P2][3]
+        if (grp < G)
+            for (int c = 0; c < 3; ++c) red[(grp * P2 + (threadIdx.x % P2)) * 3 + c] = acc[0][c];
+        __syncthreads();
+        if ((int)threadIdx.x < P2) {
+            const int idx = threadIdx.x;
+            int nn = 0;
+            while ((nn + 1) * (nn + 1) <= idx) ++nn;
+            const cx<T> sc = mk((T)(-k_im * inv_alpha[nn]), (T)(k_re * inv_alpha[nn]));   // i k / alpha_n
+            for (int c = 0; c < 3; ++c) {
+                cx<T> s = mk(T(0), T(0));
+                for (int g2 = 0; g2 < G; ++g2) s += red[(g2 * P2 + idx) * 3 + c];
+                M[(((int64_t)box * nrhs_max + r) * 3 + c) * P2 + idx] = sc * s;
+            }
+        }
+        return;
     }
     for (int u = 0; u < P2M_SLOTS; ++u) {
         const int idx = threadIdx.x + u * blockDim.x;
@@ -341,11 +366,11 @@ __global__ void __launch_bounds__(TPB) k_p2p(const int32_t *__restrict__ start, 
                 const T dx = (T)(tile.pos[j][0] - tp[0]), dy = (T)(tile.pos[j][1] - tp[1]),
                         dz = (T)(tile.pos[j][2] - tp[2]);
                 const T R2 = dx * dx + dy * dy + dz * dz;
-                const T iR = T(1) / sqrt(R2);
+                const T iR = fast_rsqrt(R2);
                 const T R = R2 * iR;
                 T sn, cs;
-                sincos_t(kr * R, &sn, &cs);
-                const T ex = ki != T(0) ? exp(-ki * R) : T(1);
+                fast_sincos(kr * R, &sn, &cs);
+                const T ex = ki != T(0) ? fast_exp(-ki * R) : T(1);
                 const cx<T> e = mk(ex * cs, ex * sn);
                 const cx<T> g = (inv4pi * iR) * e;
                 // f = (i k R - 1) e / (4 pi R^3)
@@ -389,6 +414,9 @@ struct Tile {
     int32_t op, first, count;
 };
 constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int OS_MAXCOLS = 288;                 // columns per operator-stationary job
+
+__device__ inline int xcd_tile(int i, int ntiles);
 
 template <typename T>
 struct Mfma;
@@ -410,7 +438,8 @@ struct Mfma<float> {
 };
 
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_translate(const Tile *__restrict__ tiles, const int32_t *__restrict__ ent,
+__global__ void __launch_bounds__(TPB) k_translate(const Tile *__restrict__ tiles, int ntiles,
+                                                   const int32_t *__restrict__ ent,
                                                    const int32_t *__restrict__ src_map, const T *__restrict__ ops,
                                                    const T *__restrict__ X, T *__restrict__ Y, int KR, int ncol,
                                                    int64_t blkR) {
@@ -418,7 +447,9 @@ __global__ void __launch_bounds__(TPB) k_translate(const Tile *__restrict__ tile
     __shared__ T As[TM][TK + 1];
     __shared__ T Bs[TK][TN];
     __shared__ int32_t s_src[TN], s_dst[TN];
-    const Tile tl = tiles[blockIdx.x];
+    const int tix = xcd_tile(blockIdx.x, ntiles);
+    if (tix >= ntiles) return;
+    const Tile tl = tiles[tix];
     const int r0 = blockIdx.y * TM;
     const T *Top = ops + (size_t)tl.op * KR * KR;
     for (int q = threadIdx.x; q < tl.count && q < TN; q += blockDim.x) {
@@ -483,6 +514,228 @@ __global__ void __launch_bounds__(TPB) k_translate(const Tile *__restrict__ tile
     }
 }
 
+// MI355X dispatches consecutive workgroups to its 8 XCDs in turn.  Tiles are
+// listed operator by operator; renumbering block i to tile (i % 8) * chunk + i / 8
+// gives each XCD a contiguous run of tiles, so the tiles that share an operator
+// share one L2.  The grid is padded to a multiple of 8; spare blocks exit.
+__device__ inline int xcd_tile(int i, int ntiles) {
+    const int chunk = (ntiles + 7) / 8;
+    return (i % 8) * chunk + i / 8;
+}
+
+// Variant for small operators (2 p^2 <= 16 RT): every block computes all rows
+// of its 64 columns, so each gathered column is read from memory once.  The
+// four waves split the columns (16 each); every wave holds RT 16x16 tiles.
+template <typename T, int RT>
+__global__ void __launch_bounds__(TPB) k_translate_fm(const Tile *__restrict__ tiles, int ntiles,
+                                                      const int32_t *__restrict__ ent,
+                                                      const int32_t *__restrict__ src_map, const T *__restrict__ ops,
+                                                      const T *__restrict__ X, T *__restrict__ Y, int KR, int ncol,
+                                                      int64_t blkR) {
+    typedef typename Mfma<T>::v4 v4;
+    __shared__ T As[RT * 16][TK + 1];
+    __shared__ T Bs[TK][TN];
+    __shared__ int32_t s_src[TN], s_dst[TN];
+    const int tix = xcd_tile(blockIdx.x, ntiles);
+    if (tix >= ntiles) return;
+    const Tile tl = tiles[tix];
+    const T *Top = ops + (size_t)tl.op * KR * KR;
+    for (int q = threadIdx.x; q < tl.count && q < TN; q += blockDim.x) {
+        int32_t e = ent[tl.first + q];
+        s_dst[q] = e;
+        s_src[q] = src_map ? src_map[e] : e;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wc0 = wave * 16;
+    const int Ctot = tl.count * ncol;
+    for (int c0 = 0; c0 < Ctot; c0 += TN) {
+        const int C = min(TN, Ctot - c0);
+        v4 acc[RT];
+#pragma unroll
+        for (int i = 0; i < RT; ++i) acc[i] = v4{0, 0, 0, 0};
+        for (int k0 = 0; k0 < KR; k0 += TK) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < RT * 16 * TK; t += blockDim.x) {
+                const int rr = t / TK, kk = t % TK;
+                As[rr][kk] = (rr < KR && k0 + kk < KR) ? Top[(size_t)rr * KR + k0 + kk] : T(0);
+            }
+            for (int t = threadIdx.x; t < TN * TK; t += blockDim.x) {
+                const int c = t / TK, kk = t % TK;
+                T v = T(0);
+                if (c < C && k0 + kk < KR) {
+                    const int cg = c0 + c;
+                    const int e = cg / ncol, cc = cg % ncol;
+                    v = X[(int64_t)s_src[e] * blkR + (int64_t)cc * KR + k0 + kk];
+                }
+                Bs[kk][c] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k4 = 0; k4 < TK; k4 += 4) {
+                const T b = Bs[k4 + (lane >> 4)][wc0 + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < RT; ++i) {
+                    const T a = As[16 * i + (lane & 15)][k4 + (lane >> 4)];
+                    acc[i] = Mfma<T>::mma(a, b, acc[i]);
+                }
+            }
+        }
+        const int col = wc0 + (lane & 15);
+        if (col < C) {
+            const int cg = c0 + col;
+            const int e = cg / ncol, cc = cg % ncol;
+            T *yo = Y + (int64_t)s_dst[e] * blkR + (int64_t)cc * KR;
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = 16 * i + Mfma<T>::row(lane, q);
+                    if (row < KR) yo[row] = acc[i][q];
+                }
+        }
+    }
+}
+
+// Operator-stationary variant for FP32 operators with 2 p^2 <= 164 (p <= 9):
+// a block owns one operator and a long run of that operator's columns.  Each
+// of its four waves loads the MFMA A-fragments of its RTW row tiles for the
+// whole K extent into registers once (a[i][kk] = T[16 i + l%16][4 kk + l/16]),
+// then the block streams the columns 16 at a time through double-buffered LDS.
+// Operator traffic drops from one read per 64 columns to one read per job.
+constexpr int OS_COLS = 16;
+
+template <int KS, int RTW>
+__global__ void __launch_bounds__(TPB) k_translate_os(const Tile *__restrict__ tiles, int ntiles,
+                                                      const int32_t *__restrict__ ent,
+                                                      const int32_t *__restrict__ src_map,
+                                                      const float *__restrict__ ops, const float *__restrict__ X,
+                                                      float *__restrict__ Y, int KR, int ncol, int64_t blkR) {
+    constexpr int KP = KS * 4;                     // K padded to whole MFMA k-steps
+    constexpr int LD = (KP * OS_COLS + TPB - 1) / TPB;
+    typedef typename Mfma<float>::v4 v4;
+    __shared__ float Bs[2][KP][OS_COLS];
+    __shared__ int64_t s_in[OS_MAXCOLS], s_out[OS_MAXCOLS];
+    const int tix = xcd_tile(blockIdx.x, ntiles);
+    if (tix >= ntiles) return;
+    const Tile tl = tiles[tix];
+    const int C = tl.count * ncol;                 // <= OS_MAXCOLS (plan-time tiling)
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        const int e = c / ncol, cc = c % ncol;
+        const int32_t en = ent[tl.first + e];
+        const int32_t sb = src_map ? src_map[en] : en;
+        s_in[c] = (int64_t)sb * blkR + (int64_t)cc * KR;
+        s_out[c] = (int64_t)en * blkR + (int64_t)cc * KR;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const float *Top = ops + (size_t)tl.op * KR * KR;
+    float a[RTW][KS];
+#pragma unroll
+    for (int i = 0; i < RTW; ++i) {
+        const int row = (wave * RTW + i) * 16 + (lane & 15);
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            const int k = 4 * kk + (lane >> 4);
+            a[i][kk] = (row < KR && k < KR) ? Top[(size_t)row * KR + k] : 0.f;
+        }
+    }
+    __syncthreads();
+    const int ntc = (C + OS_COLS - 1) / OS_COLS;
+    float pre[LD];
+    auto fetch = [&](int t) {
+#pragma unroll
+        for (int j = 0; j < LD; ++j) {
+            const int e = threadIdx.x + j * TPB;
+            const int c = e / KP, k = e % KP;
+            const int cg = t * OS_COLS + c;
+            pre[j] = (e < KP * OS_COLS && cg < C && k < KR) ? X[s_in[cg] + k] : 0.f;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < LD; ++j) {
+            const int e = threadIdx.x + j * TPB;
+            if (e < KP * OS_COLS) Bs[buf][e % KP][e / KP] = pre[j];
+        }
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int t = 0; t < ntc; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < ntc) fetch(t + 1);
+        v4 acc[RTW];
+#pragma unroll
+        for (int i = 0; i < RTW; ++i) acc[i] = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            const float b = Bs[buf][4 * kk + (lane >> 4)][lane & 15];
+#pragma unroll
+            for (int i = 0; i < RTW; ++i) acc[i] = Mfma<float>::mma(a[i][kk], b, acc[i]);
+        }
+        const int cg = t * OS_COLS + (lane & 15);
+        if (cg < C) {
+            float *yo = Y + s_out[cg];
+#pragma unroll
+            for (int i = 0; i < RTW; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = (wave * RTW + i) * 16 + Mfma<float>::row(lane, q);
+                    if (row < KR) yo[row] = acc[i][q];
+                }
+        }
+        if (t + 1 < ntc) stash(buf ^ 1);
+        __syncthreads();
+    }
+}
+
+// the operator-stationary kernel applies to FP32 operators of order 2 <= p <= 9
+// whose column blocks (3 nrhs columns per entry) fit one job
+inline bool use_os(int precision, int p, int nrhs_max) {
+    return precision == FMB_FP32 && p >= 2 && p <= 9 && 3 * nrhs_max <= OS_MAXCOLS;
+}
+
+template <typename T>
+void launch_translate(const Tile *tiles, int64_t ntiles, const int32_t *ent, const int32_t *src_map, const T *ops,
+                      const T *X, T *Y, int KR, int ncol, int64_t blkR, bool os, hipStream_t s) {
+    if (ntiles <= 0) return;
+    const int rt = (KR + 15) / 16;
+    const unsigned g = (unsigned)(((ntiles + 7) / 8) * 8);
+    if (os) {
+        const float *o = (const float *)ops;
+        const float *x = (const float *)X;
+        float *y = (float *)Y;
+        const int p = (int)lround(sqrt(KR / 2.0));
+        switch (p) {
+            case 2: k_translate_os<2, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
+            case 3: k_translate_os<5, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
+            case 4: k_translate_os<8, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
+            case 5: k_translate_os<13, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
+            case 6: k_translate_os<18, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
+            case 7: k_translate_os<25, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
+            case 8: k_translate_os<32, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
+            default: k_translate_os<41, 3><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
+        }
+        FMB_LAUNCH_CHECK();
+        return;
+    }
+#define FMB_FM(R)                                                                                                   \
+    case R:                                                                                                         \
+        k_translate_fm<T, R><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, ops, X, Y, KR, ncol, blkR);        \
+        break;
+    if (rt <= 16 && (sizeof(T) == 4 || rt <= 8)) {
+        switch (rt) {
+            FMB_FM(1) FMB_FM(2) FMB_FM(3) FMB_FM(4) FMB_FM(5) FMB_FM(6) FMB_FM(7) FMB_FM(8)
+            FMB_FM(9) FMB_FM(10) FMB_FM(11) FMB_FM(12) FMB_FM(13) FMB_FM(14) FMB_FM(15) FMB_FM(16)
+            default: break;
+        }
+    } else {
+        const unsigned rowblocks = (unsigned)((KR + TM - 1) / TM);
+        k_translate<T><<<dim3(g, rowblocks), TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, ops, X, Y, KR, ncol, blkR);
+    }
+#undef FMB_FM
+    FMB_LAUNCH_CHECK();
+}
+
 // parent (level l) multipole = sum of its children's translated slots
 template <typename T>
 __global__ void k_sum_children(const int32_t *__restrict__ child_start, int64_t nbox, const cx<T> *__restrict__ Yc,
@@ -520,7 +773,7 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
     const int ncol = 3 * nrhs;
     const int KR = 2 * P2;                          // real rows of the embedded operators
     const int64_t blkR = 2 * blk;
-    const unsigned rowblocks = (unsigned)((KR + TM - 1) / TM);
+    const bool os = use_os(P.precision, p, P.nrhs_max);
     cx<T> *src = P.src.as<cx<T>>();
     cx<T> *ys = P.ys.as<cx<T>>();
     cx<T> *yb = P.ybuf.as<cx<T>>();
@@ -536,8 +789,10 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
     {
         const int N = p;
         const size_t per = (size_t)(N + 1) * (N + 2) * sizeof(cx<T>) + 3 * sizeof(double);
-        const int batch = (int)std::max<size_t>(1, std::min<size_t>(P2M_BATCH, 60000 / per));
-        const size_t sh = (size_t)batch * per;
+        const int batch = (int)std::max<size_t>(1, std::min<size_t>(64, 60000 / per));
+        // the group reduction reuses the table: it needs G * P2 * 3 complex values
+        const int G = P2 <= TPB ? TPB / P2 : 1;
+        const size_t sh = std::max((size_t)batch * per, (size_t)G * P2 * 3 * sizeof(cx<T>));
         tm.begin(ST_P2M, s, ev);
         k_p2m<T><<<dim3((unsigned)LL.nbox, nrhs), TPB, sh, s>>>(
             LL.start.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(), P.snrm.as<double>(), src, n, p, P.k_re,
@@ -550,9 +805,8 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
         Level &V = P.lv[l], &C = P.lv[l + 1];
         if (V.ntiles_m2m == 0) continue;
         tm.begin(ST_M2M, s, ev);
-        k_translate<T><<<dim3((unsigned)V.ntiles_m2m, rowblocks), TPB, 0, s>>>(
-            V.tiles_m2m.as<Tile>(), C.by_octant.as<int32_t>(), nullptr, V.m2m.as<T>(), (const T *)C.M.p, (T *)yb, KR,
-            ncol, blkR);
+        launch_translate<T>(V.tiles_m2m.as<Tile>(), V.ntiles_m2m, C.by_octant.as<int32_t>(), nullptr, V.m2m.as<T>(),
+                            (const T *)C.M.p, (T *)yb, KR, ncol, blkR, os, s);
         k_sum_children<T><<<(unsigned)V.nbox, TPB, 0, s>>>(V.child_start.as<int32_t>(), V.nbox, yb, V.M.as<cx<T>>(), blk,
                                                            ncol * P2);
         FMB_LAUNCH_CHECK();
@@ -564,17 +818,15 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
         if (l >= 3 && V.ntiles_l2l > 0) {
             Level &U = P.lv[l - 1];
             tm.begin(ST_L2L, s, ev);
-            k_translate<T><<<dim3((unsigned)V.ntiles_l2l, rowblocks), TPB, 0, s>>>(
-                V.tiles_l2l.as<Tile>(), V.by_octant.as<int32_t>(), V.parent.as<int32_t>(), V.l2l.as<T>(),
-                (const T *)U.L.p, (T *)V.L.p, KR, ncol, blkR);
+            launch_translate<T>(V.tiles_l2l.as<Tile>(), V.ntiles_l2l, V.by_octant.as<int32_t>(), V.parent.as<int32_t>(),
+                                V.l2l.as<T>(), (const T *)U.L.p, (T *)V.L.p, KR, ncol, blkR, os, s);
             FMB_LAUNCH_CHECK();
             tm.end(ST_L2L, s, ev);
         }
         tm.begin(ST_M2L, s, ev);
         if (V.ntiles_m2l > 0) {
-            k_translate<T><<<dim3((unsigned)V.ntiles_m2l, rowblocks), TPB, 0, s>>>(
-                V.tiles_m2l.as<Tile>(), V.ff_by_op.as<int32_t>(), V.ff_src.as<int32_t>(), V.m2l.as<T>(),
-                (const T *)V.M.p, (T *)yb, KR, ncol, blkR);
+            launch_translate<T>(V.tiles_m2l.as<Tile>(), V.ntiles_m2l, V.ff_by_op.as<int32_t>(), V.ff_src.as<int32_t>(),
+                                V.m2l.as<T>(), (const T *)V.M.p, (T *)yb, KR, ncol, blkR, os, s);
             FMB_LAUNCH_CHECK();
         }
         k_sum_far<T><<<(unsigned)V.nbox, TPB, 0, s>>>(V.ff_ofs.as<int32_t>(), yb, V.L.as<cx<T>>(), blk, ncol * P2,
@@ -620,7 +872,9 @@ void build_tiles(Plan &P, hipStream_t s) {
         if (!v.empty())
             FMB_CHECK_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
     };
-    const int ep = std::max(1, TN / (3 * P.nrhs_max));
+    // entries per tile: operator-stationary jobs hold up to OS_MAXCOLS columns
+    const int ep = use_os(P.precision, P.order, P.nrhs_max) ? std::max(1, OS_MAXCOLS / (3 * P.nrhs_max))
+                                                : std::max(1, TN / (3 * P.nrhs_max));
     auto chunk = [ep](std::vector<Tile> &v, int op, int first, int count) {
         for (int q = 0; q < count; q += ep) v.push_back(Tile{op, first + q, std::min(ep, count - q)});
     };

@@ -696,7 +696,10 @@ int gmres_solve(fmb_problem_t pb, const void *rhs, void *x, int32_t nrhs, const 
                 hist.push_back(final_res);
                 if (final_res <= op.tol || its >= op.maxit || refinements >= 50) break;
                 std::vector<double> inner;
-                its += fgmres(*pb, K, rr.as<cx<double>>(), dx.as<cx<double>>(), false, op.inner_tol,
+                // the last refinements only need to close the gap to tol: loosen the inner tolerance to
+                // a fraction of tol/|r| when that is looser than the configured one
+                const double itol = std::min(0.5, std::max(op.inner_tol, 0.3 * op.tol / std::max(final_res, 1e-300)));
+                its += fgmres(*pb, K, rr.as<cx<double>>(), dx.as<cx<double>>(), false, itol,
                               std::min(op.inner_maxit, op.maxit - its), 1, op.precond, inner, nullptr, mv32, s);
                 k_axpy_masked<<<gridn(tot), TPB, 0, s>>>(X, dx.as<cx<double>>(), len, nrhs);
                 bem_apply_impl(*pb, X, ax.as<cx<double>>(), nrhs, 0, s);
