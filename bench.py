@@ -24,7 +24,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"hbm_GBs": 8000.0, "fp64_TF": 78.6, "fp32_TF": 157.3}
+PEAK = {"hbm_GBs": 8000.0, "fp64_TF": 78.6, "fp32_TF": 157.3, "bf16_TF": 2500.0}
 
 
 def parse():
@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1500)
     ap.add_argument("--skip-fp64-solve", action="store_true")
+    ap.add_argument("--translate32", choices=["fp32", "bf16x3"], default="fp32")
     return ap.parse_args()
 
 
@@ -80,7 +81,8 @@ def main():
     d, pol = plane_waves(1, seed_for(2, "dirs"), seed_for(2, "pols"))
 
     t0 = time.perf_counter()
-    pb = BemProblem(nodes, k0, eps, order=args.order64, depth=depth, order32=args.order32)
+    pb = BemProblem(nodes, k0, eps, order=args.order64, depth=depth, order32=args.order32,
+                    translate32=args.translate32)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     log("plans built in %.2f s" % plan_s)
@@ -148,11 +150,25 @@ def main():
     m2l_ms, m2l_launches = prof["fp32"]["m2l"]
     per_matvec_ms = m2l_ms / 10.0
     achieved_tf = m2l_flops(inf) / (per_matvec_ms * 1e-3) / 1e12
-    roofline = {"kernel": "k_translate (S|R, FP32, all levels) + per-target sums", "bound": "alu",
-                "achieved": achieved_tf, "peak": PEAK["fp32_TF"], "unit": "TFLOP/s",
-                "frac": achieved_tf / PEAK["fp32_TF"], "traffic": None,
+    if args.translate32 == "bf16x3":
+        kname, peak = "k_translate_bf3 (S|R, split-BF16 MFMA, FP32 accumulate)", PEAK["bf16_TF"]
+    else:
+        kname, peak = "k_translate_os (S|R, FP32 MFMA)", PEAK["fp32_TF"]
+    roofline = {"kernel": kname, "bound": "mfma",
+                "achieved": achieved_tf, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved_tf / peak, "traffic": None,
                 "per_launch_flops": m2l_flops(inf) / max(1, m2l_launches // 10),
                 "avg_launch_ms": m2l_ms / max(1, m2l_launches)}
+
+    # accuracy against the oracle: FP64 direct-sum residual of the GPU solutions on sampled rows
+    acc = None
+    if not args.no_cpu_baseline:
+        b_h = rhs[0].cpu().numpy()
+        acc = {"rows": args.cpu_rows,
+               "mixed": oracle_residual_rows(nodes, k0, eps, x[0].cpu().numpy(), b_h, args.cpu_rows)}
+        if fp64 is not None:
+            acc["fp64"] = oracle_residual_rows(nodes, k0, eps, x64[0].cpu().numpy(), b_h, args.cpu_rows)
+        log("oracle residual on sampled rows", acc)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -174,7 +190,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "torus_R1_r0.3_20000tri_60000nodes_eps-15+1i_k0R4_depth5_planewave",
                    "nodes": n, "unknowns": 6 * n, "depth": depth, "order_fp64": args.order64,
-                   "order_fp32": args.order32, "tol": args.tol},
+                   "order_fp32": args.order32, "translate_fp32": args.translate32, "tol": args.tol},
         "solve": {"iterations": last["iterations"], "refinements": last["refinements"],
                   "bem_applies_fp32": last["matvecs32"], "bem_applies_fp64": last["matvecs64"],
                   "residual": last["residual"]},
@@ -185,10 +201,48 @@ def main():
         "stage_ms_per_matvec": {t: {s: v[0] / 10.0 for s, v in prof[t].items()} for t in prof},
         "plan_s_4plans": plan_s,
         "plan_info_fp64": {k: info64[k] for k in ("nbox", "m2l_pairs", "p2p_pairs", "device_bytes")},
+        "oracle_residual_sampled_rows": acc,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def oracle_residual_rows(nodes, k0, eps, x, b, nrows):
+    """|b - A x| / |b| over seeded sample rows, A the oracle's direct-sum 6N system."""
+    from oracle.corrections import self_blocks
+    from oracle.direct import apply_corrections
+    from oracle.kernel import wavenumber
+    from oracle.native import point_sum_c
+    from synthetic import seed_for
+
+    n = nodes["points"].shape[0]
+    rows = np.sort(np.random.default_rng(seed_for(2, "rows")).choice(n, nrows, replace=False))
+    pts, nrm, w, pt = nodes["points"], nodes["normals"], nodes["weights"], nodes["point_tri"]
+    eps = complex(eps)
+    k1 = wavenumber(k0, eps)
+    phi, psi = x[:, :3], x[:, 3:]
+    tphi = phi + ((1 - eps) / eps) * nrm * np.sum(nrm * phi, axis=1, keepdims=True)
+    # self-triangle blocks only for the triangles of the sampled rows
+    tris = np.unique(pt[rows])
+    sub = np.concatenate([np.nonzero(pt == t)[0] for t in tris])
+    remap = {t: i for i, t in enumerate(tris)}
+    sub_nodes = {"points": pts[sub], "normals": nrm[sub], "point_tri": np.array([remap[t] for t in pt[sub]]),
+                 "tri_vertices": nodes["tri_vertices"][tris]}
+    where = {g: i for i, g in enumerate(sub)}
+    loc = np.array([where[r] for r in rows])
+
+    def op(k, a, bb):
+        y = point_sum_c(pts, nrm, w, pt, k, a, bb, rows=rows)
+        blk = self_blocks(sub_nodes["points"], sub_nodes["normals"], sub_nodes["point_tri"],
+                          sub_nodes["tri_vertices"], k)
+        yc = apply_corrections(sub_nodes["normals"], sub_nodes["point_tri"], blk, a[sub], bb[sub])
+        return y + yc[loc]
+
+    r0 = 0.5 * phi[rows] + op(k0, phi, -psi)
+    r1 = 0.5 * tphi[rows] - op(k1, tphi, -psi)
+    ax = np.concatenate([r0, r1], axis=1)
+    return float(np.linalg.norm(b[rows] - ax) / np.linalg.norm(b[rows]))
 
 
 def cpu_baseline(nodes, k0, eps, rows, applies_per_solve):

@@ -65,8 +65,17 @@ typedef struct {
     const double *tri_vertices; /* host f64[ntri][3][3]: triangle corners (corr_mode > 0)     */
     int64_t ntri;               /* number of triangles                                        */
     int32_t leaf_target;        /* depth 0 only: aim for about this many nodes per leaf (0=32)*/
-    int32_t reserved[7];
+    int32_t translate_mode;     /* FP32 plans: FMB_TRANSLATE_FP32 (default) or FMB_TRANSLATE_BF16X3 */
+    int32_t reserved[6];
 } fmb_plan_opts;
+
+/*
+ * Translation arithmetic of FP32 plans.  FMB_TRANSLATE_BF16X3 splits operator
+ * and coefficients into BF16 high and low parts and forms hi*hi + hi*lo +
+ * lo*hi on the BF16 matrix cores with FP32 accumulation (about 1e-5 relative
+ * per product); it applies to orders p <= 9 and falls back to FP32 otherwise.
+ */
+enum { FMB_TRANSLATE_DEFAULT = 0, FMB_TRANSLATE_FP32 = 1, FMB_TRANSLATE_BF16X3 = 2 };
 
 typedef struct {
     int32_t depth;
@@ -142,12 +151,13 @@ int fmm_plan_destroy(fmb_plan_t plan);
  * plan record HIP events around its stages on the matvec's stream;
  * fmm_plan_profile_read synchronises on them and returns, per stage, the
  * summed kernel time in milliseconds and the number of timed launches since
- * the last read with reset = 1.  Stage order (FMB_NSTAGES = 9): gather, P2M,
- * M2M (S|S), M2L (S|R, incl. the per-target sums), L2L (R|R), L2P, P2P,
- * corrections, scatter.  ms and launches: host arrays of FMB_NSTAGES entries
+ * the last read with reset = 1.  Stage order (FMB_NSTAGES = 10): gather, P2M,
+ * M2M (S|S translation kernel), M2L (S|R translation kernel), L2L (R|R), L2P,
+ * P2P, corrections, scatter, sums (the per-target sums of the S|S and S|R
+ * translation slots).  ms and launches: host arrays of FMB_NSTAGES entries
  * (either may be NULL).
  */
-#define FMB_NSTAGES 9
+#define FMB_NSTAGES 10
 int fmm_plan_profile(fmb_plan_t plan, int32_t enable);
 int fmm_plan_profile_read(fmb_plan_t plan, double *ms, int64_t *launches, int32_t reset);
 

@@ -29,7 +29,8 @@ class FmbError(RuntimeError):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("precision", ctypes.c_int32), ("nrhs_max", ctypes.c_int32),
                 ("corr_mode", ctypes.c_int32), ("point_tri", ctypes.c_void_p), ("tri_vertices", ctypes.c_void_p),
-                ("ntri", ctypes.c_int64), ("leaf_target", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("ntri", ctypes.c_int64), ("leaf_target", ctypes.c_int32), ("translate_mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -125,7 +126,7 @@ class Plan:
     """One wavenumber's FMM operator (`fmm_plan`)."""
 
     def __init__(self, points, normals, weights, k, order, depth=0, precision="fp64", nrhs_max=1,
-                 corr="linear", point_tri=None, tri_vertices=None, leaf_target=32):
+                 corr="linear", point_tri=None, tri_vertices=None, leaf_target=32, translate="fp32"):
         lib = load()
         self._lib = lib
         pts = _host(points, np.float64)
@@ -139,6 +140,7 @@ class Plan:
         opts.nrhs_max = int(nrhs_max)
         opts.corr_mode = CORR[corr] if isinstance(corr, str) else int(corr)
         opts.leaf_target = int(leaf_target)
+        opts.translate_mode = {"fp32": 1, "bf16x3": 2}[translate]
         keep = []
         if point_tri is not None:
             pt = _host(point_tri, np.int32)
@@ -211,7 +213,7 @@ class Plan:
         return {"codes": codes, "perm": perm, "keys": keys, "parent": parent, "start": start, "nbr": nbr,
                 "ff_ofs": ff_ofs, "ff_idx": ff_idx[:int(ff_ofs[-1])]}
 
-    STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "corr", "scatter")
+    STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "corr", "scatter", "sums")
 
     def profile(self, enable=True):
         check(self._lib.fmm_plan_profile(self.h, 1 if enable else 0))

@@ -17,12 +17,14 @@ size_t Plan::device_bytes() const {
     for (const Level &V : lv)
         b += V.keys.bytes + V.start.bytes + V.parent.bytes + V.center.bytes + V.nbr.bytes + V.child_start.bytes +
              V.octant.bytes + V.ff_ofs.bytes + V.ff_src.bytes + V.ff_op.bytes + V.ff_by_op.bytes + V.by_octant.bytes +
-             V.m2l.bytes + V.m2m.bytes + V.l2l.bytes + V.M.bytes + V.L.bytes + V.tiles_m2l.bytes + V.tiles_m2m.bytes +
+             V.m2l.bytes + V.m2m.bytes + V.l2l.bytes + V.m2l_hi.bytes + V.m2l_lo.bytes + V.m2m_hi.bytes +
+             V.m2m_lo.bytes + V.l2l_hi.bytes + V.l2l_lo.bytes + V.M.bytes + V.L.bytes + V.tiles_m2l.bytes + V.tiles_m2m.bytes +
              V.tiles_l2l.bytes;
     return b;
 }
 
 void build_tiles(Plan &P, hipStream_t s);
+void split_operators(Plan &P, hipStream_t s);
 void alloc_workspace(Plan &P);
 
 static void upload(DevBuf &d, const void *h, size_t bytes, hipStream_t s) {
@@ -114,6 +116,8 @@ int fmm_plan(const double *points, const double *normals, const double *weights,
         P.ntri = ntri;
         P.tri_m = m;
         P.leaf_target = o.leaf_target > 0 ? o.leaf_target : 32;
+        FMB_REQUIRE(o.translate_mode >= 0 && o.translate_mode <= 2, "translate_mode must be 0, 1 or 2");
+        P.translate_mode = o.translate_mode == FMB_TRANSLATE_BF16X3 ? FMB_TRANSLATE_BF16X3 : FMB_TRANSLATE_FP32;
         DevBuf d_pts, d_nrm, d_w, d_tv;
         upload(d_pts, points, n * 3 * sizeof(double), s);
         upload(d_nrm, normals, n * 3 * sizeof(double), s);
@@ -124,6 +128,7 @@ int fmm_plan(const double *points, const double *normals, const double *weights,
         gather_nodes(P, d_pts.as<double>(), d_nrm.as<double>(), d_w.as<double>(), P.point_tri.as<int32_t>(), s);
         build_operators(P, s);
         build_tiles(P, s);
+        split_operators(P, s);
         alloc_workspace(P);
         if (P.corr_mode != FMB_CORR_NONE) {
             upload(d_tv, o.tri_vertices, ntri * 9 * sizeof(double), s);
@@ -207,6 +212,8 @@ int fmm_plan_profile(fmb_plan_t plan, int32_t enable) {
         plan->p.timer.on = enable != 0;
     });
 }
+
+static_assert(ST_COUNT == FMB_NSTAGES, "stage list and FMB_NSTAGES differ");
 
 int fmm_plan_profile_read(fmb_plan_t plan, double *ms, int64_t *launches, int32_t reset) {
     return guarded([&] {

@@ -688,16 +688,186 @@ __global__ void __launch_bounds__(TPB) k_translate_os(const Tile *__restrict__ t
     }
 }
 
+inline bool use_bf3(const Plan &P) {
+    return P.precision == FMB_FP32 && P.translate_mode == FMB_TRANSLATE_BF16X3 && P.order >= 2 && P.order <= 9 &&
+           3 * P.nrhs_max <= OS_MAXCOLS;
+}
+
 // the operator-stationary kernel applies to FP32 operators of order 2 <= p <= 9
 // whose column blocks (3 nrhs columns per entry) fit one job
 inline bool use_os(int precision, int p, int nrhs_max) {
     return precision == FMB_FP32 && p >= 2 && p <= 9 && 3 * nrhs_max <= OS_MAXCOLS;
 }
 
+// Split-BF16 variant of the operator-stationary kernel (FP32 plans, p <= 9).
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi); a product is taken as
+// a_hi b_hi + a_hi b_lo + a_lo b_hi on the 16x16x32 BF16 MFMA with FP32
+// accumulation (the lo*lo term, ~2^-16 relative, is dropped).  Operators are
+// pre-split at plan time and stored fragment-major: lane l of row tile i and
+// k-step s holds T[16 i + l%16][32 s + 8 (l/16) + j], j = 0..7.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int KS, int RTW>
+__global__ void __launch_bounds__(TPB) k_translate_bf3(const Tile *__restrict__ tiles, int ntiles,
+                                                       const int32_t *__restrict__ ent,
+                                                       const int32_t *__restrict__ src_map,
+                                                       const bf16x8 *__restrict__ fhi,
+                                                       const bf16x8 *__restrict__ flo, const float *__restrict__ X,
+                                                       float *__restrict__ Y, int KR, int RT, int ncol,
+                                                       int64_t blkR) {
+    constexpr int KP = KS * 32;
+    constexpr int CS = KP + 4;                                   // LDS column stride (floats)
+    constexpr int LD = (KP * OS_COLS + TPB - 1) / TPB;
+    typedef typename Mfma<float>::v4 v4;
+    __shared__ __attribute__((aligned(16))) float Bs[2][OS_COLS][CS];
+    __shared__ int64_t s_in[OS_MAXCOLS], s_out[OS_MAXCOLS];
+    const int tix = xcd_tile(blockIdx.x, ntiles);
+    if (tix >= ntiles) return;
+    const Tile tl = tiles[tix];
+    const int C = tl.count * ncol;
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        const int e = c / ncol, cc = c % ncol;
+        const int32_t en = ent[tl.first + e];
+        const int32_t sb = src_map ? src_map[en] : en;
+        s_in[c] = (int64_t)sb * blkR + (int64_t)cc * KR;
+        s_out[c] = (int64_t)en * blkR + (int64_t)cc * KR;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bf16x8 ah[RTW][KS], al[RTW][KS];
+#pragma unroll
+    for (int i = 0; i < RTW; ++i) {
+        const int tile = wave * RTW + i;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if (tile < RT) {
+                const size_t f = (((size_t)tl.op * RT + tile) * KS + s) * 64 + lane;
+                ah[i][s] = fhi[f];
+                al[i][s] = flo[f];
+            } else {
+                for (int j = 0; j < 8; ++j) {
+                    ah[i][s][j] = (__bf16)0.f;
+                    al[i][s][j] = (__bf16)0.f;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int ntc = (C + OS_COLS - 1) / OS_COLS;
+    float pre[LD];
+    auto fetch = [&](int t) {
+#pragma unroll
+        for (int j = 0; j < LD; ++j) {
+            const int e = threadIdx.x + j * TPB;
+            const int c = e / KP, k = e % KP;
+            const int cg = t * OS_COLS + c;
+            pre[j] = (e < KP * OS_COLS && cg < C && k < KR) ? X[s_in[cg] + k] : 0.f;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < LD; ++j) {
+            const int e = threadIdx.x + j * TPB;
+            if (e < KP * OS_COLS) Bs[buf][e / KP][e % KP] = pre[j];
+        }
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int t = 0; t < ntc; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < ntc) fetch(t + 1);
+        v4 acc[RTW];
+#pragma unroll
+        for (int i = 0; i < RTW; ++i) acc[i] = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const float *bp = &Bs[buf][lane & 15][32 * s + 8 * (lane >> 4)];
+            const float4 v0 = *reinterpret_cast<const float4 *>(bp);
+            const float4 v1 = *reinterpret_cast<const float4 *>(bp + 4);
+            const float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+            bf16x8 bh, bl;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const __bf16 h = (__bf16)v[j];
+                bh[j] = h;
+                bl[j] = (__bf16)(v[j] - (float)h);
+            }
+#pragma unroll
+            for (int i = 0; i < RTW; ++i) {
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i][s], bh, acc[i], 0, 0, 0);
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i][s], bl, acc[i], 0, 0, 0);
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i][s], bh, acc[i], 0, 0, 0);
+            }
+        }
+        const int cg = t * OS_COLS + (lane & 15);
+        if (cg < C) {
+            float *yo = Y + s_out[cg];
+#pragma unroll
+            for (int i = 0; i < RTW; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = (wave * RTW + i) * 16 + 4 * (lane >> 4) + q;
+                    if (row < KR) yo[row] = acc[i][q];
+                }
+        }
+        if (t + 1 < ntc) stash(buf ^ 1);
+        __syncthreads();
+    }
+}
+
+// plan-time split of FP32 operators into fragment-major BF16 hi/lo parts
+__global__ void k_split_bf16(const float *__restrict__ T, int nops, int KR, int RT, int KS, bf16x8 *__restrict__ hi,
+                             bf16x8 *__restrict__ lo) {
+    const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)nops * RT * KS * 64;
+    if (f >= total) return;
+    const int lane = (int)(f % 64);
+    const int s = (int)((f / 64) % KS);
+    const int tile = (int)((f / (64 * KS)) % RT);
+    const int64_t op = f / ((int64_t)64 * KS * RT);
+    const int row = 16 * tile + (lane & 15);
+    bf16x8 h, l;
+    for (int j = 0; j < 8; ++j) {
+        const int k = 32 * s + 8 * (lane >> 4) + j;
+        const float x = (row < KR && k < KR) ? T[((size_t)op * KR + row) * KR + k] : 0.f;
+        const __bf16 xh = (__bf16)x;
+        h[j] = xh;
+        l[j] = (__bf16)(x - (float)xh);
+    }
+    hi[f] = h;
+    lo[f] = l;
+}
+
 template <typename T>
 void launch_translate(const Tile *tiles, int64_t ntiles, const int32_t *ent, const int32_t *src_map, const T *ops,
-                      const T *X, T *Y, int KR, int ncol, int64_t blkR, bool os, hipStream_t s) {
+                      const T *X, T *Y, int KR, int ncol, int64_t blkR, bool os, hipStream_t s,
+                      const void *fhi = nullptr, const void *flo = nullptr) {
     if (ntiles <= 0) return;
+    if (fhi) {
+        // split-BF16 translations (FP32 plans only, checked by use_bf3)
+        const int p = (int)lround(sqrt(KR / 2.0));
+        const int RT = (KR + 15) / 16;
+        // register tiles per instantiation below: KS k-steps of 32, 4 waves x RTW row tiles of 16
+        static const int ks_of[10] = {0, 0, 1, 1, 1, 2, 3, 4, 4, 6}, rtw_of[10] = {0, 0, 1, 1, 1, 1, 2, 2, 2, 3};
+        if (p < 2 || p > 9 || 2 * p * p != KR || (KR + 31) / 32 > ks_of[p] || RT > 4 * rtw_of[p])
+            throw std::runtime_error("split-BF16 translation: unsupported operator size");
+        const unsigned g = (unsigned)(((ntiles + 7) / 8) * 8);
+        const bf16x8 *h = (const bf16x8 *)fhi, *l = (const bf16x8 *)flo;
+        const float *x = (const float *)X;
+        float *y = (float *)Y;
+        switch (p) {
+            case 2: k_translate_bf3<1, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            case 3: k_translate_bf3<1, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            case 4: k_translate_bf3<1, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            case 5: k_translate_bf3<2, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            case 6: k_translate_bf3<3, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            case 7: k_translate_bf3<4, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            case 8: k_translate_bf3<4, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            default: k_translate_bf3<6, 3><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+        }
+        FMB_LAUNCH_CHECK();
+        return;
+    }
     const int rt = (KR + 15) / 16;
     const unsigned g = (unsigned)(((ntiles + 7) / 8) * 8);
     if (os) {
@@ -774,6 +944,7 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
     const int KR = 2 * P2;                          // real rows of the embedded operators
     const int64_t blkR = 2 * blk;
     const bool os = use_os(P.precision, p, P.nrhs_max);
+    const bool bf3 = use_bf3(P);
     cx<T> *src = P.src.as<cx<T>>();
     cx<T> *ys = P.ys.as<cx<T>>();
     cx<T> *yb = P.ybuf.as<cx<T>>();
@@ -806,11 +977,13 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
         if (V.ntiles_m2m == 0) continue;
         tm.begin(ST_M2M, s, ev);
         launch_translate<T>(V.tiles_m2m.as<Tile>(), V.ntiles_m2m, C.by_octant.as<int32_t>(), nullptr, V.m2m.as<T>(),
-                            (const T *)C.M.p, (T *)yb, KR, ncol, blkR, os, s);
+                            (const T *)C.M.p, (T *)yb, KR, ncol, blkR, os, s, bf3 ? V.m2m_hi.p : nullptr, V.m2m_lo.p);
+        tm.end(ST_M2M, s, ev);
+        tm.begin(ST_SUMS, s, ev);
         k_sum_children<T><<<(unsigned)V.nbox, TPB, 0, s>>>(V.child_start.as<int32_t>(), V.nbox, yb, V.M.as<cx<T>>(), blk,
                                                            ncol * P2);
         FMB_LAUNCH_CHECK();
-        tm.end(ST_M2M, s, ev);
+        tm.end(ST_SUMS, s, ev);
     }
     // Step 3: downward pass, levels 2 .. L
     for (int l = 2; l <= L; ++l) {
@@ -819,20 +992,24 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
             Level &U = P.lv[l - 1];
             tm.begin(ST_L2L, s, ev);
             launch_translate<T>(V.tiles_l2l.as<Tile>(), V.ntiles_l2l, V.by_octant.as<int32_t>(), V.parent.as<int32_t>(),
-                                V.l2l.as<T>(), (const T *)U.L.p, (T *)V.L.p, KR, ncol, blkR, os, s);
+                                V.l2l.as<T>(), (const T *)U.L.p, (T *)V.L.p, KR, ncol, blkR, os, s,
+                                bf3 ? V.l2l_hi.p : nullptr, V.l2l_lo.p);
             FMB_LAUNCH_CHECK();
             tm.end(ST_L2L, s, ev);
         }
-        tm.begin(ST_M2L, s, ev);
         if (V.ntiles_m2l > 0) {
+            tm.begin(ST_M2L, s, ev);
             launch_translate<T>(V.tiles_m2l.as<Tile>(), V.ntiles_m2l, V.ff_by_op.as<int32_t>(), V.ff_src.as<int32_t>(),
-                                V.m2l.as<T>(), (const T *)V.M.p, (T *)yb, KR, ncol, blkR, os, s);
+                                V.m2l.as<T>(), (const T *)V.M.p, (T *)yb, KR, ncol, blkR, os, s,
+                                bf3 ? V.m2l_hi.p : nullptr, V.m2l_lo.p);
             FMB_LAUNCH_CHECK();
+            tm.end(ST_M2L, s, ev);
         }
+        tm.begin(ST_SUMS, s, ev);
         k_sum_far<T><<<(unsigned)V.nbox, TPB, 0, s>>>(V.ff_ofs.as<int32_t>(), yb, V.L.as<cx<T>>(), blk, ncol * P2,
                                                       l >= 3 ? 1 : 0);
         FMB_LAUNCH_CHECK();
-        tm.end(ST_M2L, s, ev);
+        tm.end(ST_SUMS, s, ev);
     }
     // Step 4: local expansions at the targets, then the near sum
     {
@@ -872,28 +1049,59 @@ void build_tiles(Plan &P, hipStream_t s) {
         if (!v.empty())
             FMB_CHECK_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
     };
-    // entries per tile: operator-stationary jobs hold up to OS_MAXCOLS columns
-    const int ep = use_os(P.precision, P.order, P.nrhs_max) ? std::max(1, OS_MAXCOLS / (3 * P.nrhs_max))
-                                                : std::max(1, TN / (3 * P.nrhs_max));
-    auto chunk = [ep](std::vector<Tile> &v, int op, int first, int count) {
+    // entries per tile.  Operator-stationary jobs hold up to OS_MAXCOLS columns;
+    // a level with little work gets shorter jobs so that it still spreads over
+    // about 1024 blocks (its cost is then latency, not operator traffic).
+    const bool os = use_os(P.precision, P.order, P.nrhs_max);
+    const int ep_max = os ? std::max(1, OS_MAXCOLS / (3 * P.nrhs_max)) : std::max(1, TN / (3 * P.nrhs_max));
+    const int ep_min = os ? std::max(1, OS_COLS / (3 * P.nrhs_max)) : ep_max;
+    auto ep_for = [&](int64_t total) {
+        int64_t e = total / 1024;
+        return (int)std::max<int64_t>(ep_min, std::min<int64_t>(ep_max, e));
+    };
+    auto chunk = [](std::vector<Tile> &v, int ep, int op, int first, int count) {
         for (int q = 0; q < count; q += ep) v.push_back(Tile{op, first + q, std::min(ep, count - q)});
     };
     for (int l = 2; l <= L; ++l) {
         Level &V = P.lv[l];
         std::vector<Tile> t;
-        for (int o = 0; o < N_M2L_OPS; ++o) chunk(t, o, V.op_start[o], V.op_start[o + 1] - V.op_start[o]);
+        const int e2l = ep_for(V.nff);
+        for (int o = 0; o < N_M2L_OPS; ++o) chunk(t, e2l, o, V.op_start[o], V.op_start[o + 1] - V.op_start[o]);
         upload(t, V.tiles_m2l, V.ntiles_m2l);
         if (l < L) {
             Level &C = P.lv[l + 1];
             std::vector<Tile> u;
-            for (int o = 0; o < 8; ++o) chunk(u, o, C.oct_start[o], C.oct_start[o + 1] - C.oct_start[o]);
+            const int e = ep_for(C.nbox);
+            for (int o = 0; o < 8; ++o) chunk(u, e, o, C.oct_start[o], C.oct_start[o + 1] - C.oct_start[o]);
             upload(u, V.tiles_m2m, V.ntiles_m2m);
         }
         if (l >= 3) {
             std::vector<Tile> u;
-            for (int o = 0; o < 8; ++o) chunk(u, o, V.oct_start[o], V.oct_start[o + 1] - V.oct_start[o]);
+            const int e = ep_for(V.nbox);
+            for (int o = 0; o < 8; ++o) chunk(u, e, o, V.oct_start[o], V.oct_start[o + 1] - V.oct_start[o]);
             upload(u, V.tiles_l2l, V.ntiles_l2l);
         }
+    }
+    FMB_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+void split_operators(Plan &P, hipStream_t s) {
+    if (!use_bf3(P)) return;
+    const int KR = 2 * P.P2, RT = (KR + 15) / 16, KS = (KR + 31) / 32;
+    auto split = [&](const DevBuf &T, int nops, DevBuf &hi, DevBuf &lo) {
+        if (!T.p) return;
+        const int64_t total = (int64_t)nops * RT * KS * 64;
+        hi.alloc(total * sizeof(bf16x8));
+        lo.alloc(total * sizeof(bf16x8));
+        k_split_bf16<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(T.as<float>(), nops, KR, RT, KS, hi.as<bf16x8>(),
+                                                                      lo.as<bf16x8>());
+        FMB_LAUNCH_CHECK();
+    };
+    for (int l = 2; l <= P.depth; ++l) {
+        Level &V = P.lv[l];
+        split(V.m2l, N_M2L_OPS, V.m2l_hi, V.m2l_lo);
+        if (l < P.depth) split(V.m2m, 8, V.m2m_hi, V.m2m_lo);
+        if (l >= 3) split(V.l2l, 8, V.l2l_hi, V.l2l_lo);
     }
     FMB_CHECK_HIP(hipStreamSynchronize(s));
 }

@@ -41,12 +41,14 @@ struct Level {
     DevBuf m2l;           // [N_M2L_OPS] slots (unused slots left untouched)
     DevBuf m2m;           // [8]: child (level+1) octant -> this level
     DevBuf l2l;           // [8]: parent (level-1) -> child at this level with octant o
+    // split-BF16 fragment-major copies of the three operator sets (FP32 plans only)
+    DevBuf m2l_hi, m2l_lo, m2m_hi, m2m_lo, l2l_hi, l2l_lo;
     // expansions [nbox][nrhs_max][3][P2] complex
     DevBuf M, L;
 };
 
 // stage timers (HIP events on the matvec stream), enabled per plan
-enum Stage { ST_GATHER = 0, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_L2P, ST_P2P, ST_CORR, ST_SCATTER, ST_COUNT };
+enum Stage { ST_GATHER = 0, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_L2P, ST_P2P, ST_CORR, ST_SCATTER, ST_SUMS, ST_COUNT };
 
 struct StageTimer {
     bool on = false;
@@ -70,6 +72,7 @@ struct Plan {
     int64_t ntri = 0, tri_m = 1;
     int64_t p2p_pairs = 0;
     int leaf_target = 32;
+    int translate_mode = FMB_TRANSLATE_FP32;
     std::vector<Level> lv;
     // per-node data in Morton order
     DevBuf codes;     // u64[n] user order

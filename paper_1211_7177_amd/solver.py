@@ -17,7 +17,7 @@ class BemProblem:
     """
 
     def __init__(self, nodes, k0, eps, mu=1.0, order=16, depth=0, nrhs_max=1, order32=None,
-                 corr="linear", leaf_target=32):
+                 corr="linear", leaf_target=32, translate32="fp32"):
         lib = _abi.load()
         self._lib = lib
         self.k0 = complex(k0)
@@ -32,8 +32,8 @@ class BemProblem:
         self.p1 = Plan(pts, nrm, w, self.k1, order, **kw)
         self.p0_32 = self.p1_32 = None
         if order32:
-            self.p0_32 = Plan(pts, nrm, w, self.k0, order32, precision="fp32", **kw)
-            self.p1_32 = Plan(pts, nrm, w, self.k1, order32, precision="fp32", **kw)
+            self.p0_32 = Plan(pts, nrm, w, self.k0, order32, precision="fp32", translate=translate32, **kw)
+            self.p1_32 = Plan(pts, nrm, w, self.k1, order32, precision="fp32", translate=translate32, **kw)
         self.n = pts.shape[0]
         self.nrhs_max = nrhs_max
         eps_a = np.array([self.eps.real, self.eps.imag])

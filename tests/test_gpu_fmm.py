@@ -37,9 +37,10 @@ def torus_c2():
     return nystrom3(torus(1.0, 0.3, 200, 50))   # 20000 triangles, 60000 nodes
 
 
-def _plan(abi, q, k, order, depth, precision="fp64", corr="linear", nrhs_max=1):
+def _plan(abi, q, k, order, depth, precision="fp64", corr="linear", nrhs_max=1, translate="fp32"):
     return abi.Plan(q["points"], q["normals"], q["weights"], k, order, depth=depth, precision=precision,
-                    nrhs_max=nrhs_max, corr=corr, point_tri=q["point_tri"], tri_vertices=q["tri_vertices"])
+                    nrhs_max=nrhs_max, corr=corr, point_tri=q["point_tri"], tri_vertices=q["tri_vertices"],
+                    translate=translate)
 
 
 def _dens(n, cfg, nrhs=None, dtype=np.complex128):
@@ -134,14 +135,41 @@ def test_fp32_matvec_tolerance(abi, sphere, order, tol):
     P.close()
 
 
-def test_fp32_torus_bench_order(abi, torus_c2):
+@pytest.mark.parametrize("order", [4, 6, 8, 9])
+def test_bf16x3_matvec_tolerance(abi, sphere, order):
+    """Split-BF16 translations.  Bound: the FP64 plan's truncation error at the
+    same order plus 5e-5 for FP32 storage and the dropped lo*lo term (about
+    2^-16 of each product); and within 2e-5 of the FP32-translation result."""
+    q = sphere
+    n = q["points"].shape[0]
+    a, b = _dens(n, 1)
+    k = 1.5
+    print("bf16x3 order", order, flush=True)
+    P = _plan(abi, q, k, order, 3, precision="fp32", corr="none", translate="bf16x3")
+    F = _plan(abi, q, k, order, 3, precision="fp32", corr="none")
+    D = _plan(abi, q, k, order, 3, corr="none")
+    y = P.matvec(_gpu(a, torch.complex64), _gpu(b, torch.complex64)).cpu().numpy()
+    yf = F.matvec(_gpu(a, torch.complex64), _gpu(b, torch.complex64)).cpu().numpy()
+    yd = D.matvec(_gpu(a), _gpu(b)).cpu().numpy()
+    ref = point_sum_c(q["points"], q["normals"], q["weights"], q["point_tri"], k, a, b)
+    err, err64 = _rel(y, ref), _rel(yd, ref)
+    print("bf16x3 order", order, "rel err", err, "fp64", err64, "vs fp32", _rel(y, yf))
+    assert err <= err64 + 5e-5
+    assert _rel(y, yf) <= 2e-5
+    for X in (P, F, D):
+        X.close()
+
+
+@pytest.mark.parametrize("translate", ["fp32", "bf16x3"])
+def test_fp32_torus_bench_order(abi, torus_c2, translate):
     """The benchmark's FP32 operator (60k-node torus, depth 5, order 9) on 512 rows."""
     q = torus_c2
     n = q["points"].shape[0]
     a, b = _dens(n, 2)
     rows = np.sort(np.random.default_rng(seed_for(2, "rows")).choice(n, 512, replace=False))
     k = 4.0
-    P = _plan(abi, q, k, 9, 5, precision="fp32")
+    print("fp32 torus", translate, flush=True)
+    P = _plan(abi, q, k, 9, 5, precision="fp32", translate=translate)
     y = P.matvec(_gpu(a, torch.complex64), _gpu(b, torch.complex64)).cpu().numpy()[rows]
     ref = point_sum_c(q["points"], q["normals"], q["weights"], q["point_tri"], k, a, b, rows=rows)
     blk = self_blocks(q["points"], q["normals"], q["point_tri"], q["tri_vertices"], k, mode="linear")
