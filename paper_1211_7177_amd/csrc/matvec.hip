@@ -849,7 +849,7 @@ void launch_translate(const Tile *tiles, int64_t ntiles, const int32_t *ent, con
         const int RT = (KR + 15) / 16;
         // register tiles per instantiation below: KS k-steps of 32, 4 waves x RTW row tiles of 16
         static const int ks_of[10] = {0, 0, 1, 1, 1, 2, 3, 4, 4, 6}, rtw_of[10] = {0, 0, 1, 1, 1, 1, 2, 2, 2, 3};
-        if (p < 2 || p > 9 || 2 * p * p != KR || (KR + 31) / 32 > ks_of[p] || RT > 4 * rtw_of[p])
+        if (p < 2 || p > 9 || 2 * p * p != KR || (KR + 31) / 32 != ks_of[p] || RT > 4 * rtw_of[p])
             throw std::runtime_error("split-BF16 translation: unsupported operator size");
         const unsigned g = (unsigned)(((ntiles + 7) / 8) * 8);
         const bf16x8 *h = (const bf16x8 *)fhi, *l = (const bf16x8 *)flo;
@@ -907,30 +907,55 @@ void launch_translate(const Tile *tiles, int64_t ntiles, const int32_t *ent, con
 }
 
 // parent (level l) multipole = sum of its children's translated slots
+// Column sums of a row range [e0, e1) of slots (rows of blk complex values, the
+// first ncolP2 of which are used) by one block: G = TPB / ncolP2 row groups
+// take rows e0 + g, e0 + g + G, ... and their partial sums are added in group
+// order, so the result does not depend on timing.
 template <typename T>
-__global__ void k_sum_children(const int32_t *__restrict__ child_start, int64_t nbox, const cx<T> *__restrict__ Yc,
-                               cx<T> *__restrict__ Mp, int64_t blk, int ncolP2) {
-    const int64_t b = blockIdx.x;
-    const int c0 = child_start[b], c1 = child_start[b + 1];
-    for (int t = threadIdx.x; t < ncolP2; t += blockDim.x) {
-        cx<T> s = mk(T(0), T(0));
-        for (int c = c0; c < c1; ++c) s += Yc[(int64_t)c * blk + t];
-        Mp[b * blk + t] = s;
+__device__ inline void slot_sum(const cx<T> *__restrict__ Y, int e0, int e1, int64_t blk, int ncolP2,
+                                cx<T> *__restrict__ out, bool accumulate, cx<T> *sm) {
+    const int t = threadIdx.x;
+    if (ncolP2 * 2 > TPB) {
+        for (int c = t; c < ncolP2; c += TPB) {
+            cx<T> s = mk(T(0), T(0));
+            for (int e = e0; e < e1; ++e) s += Y[(int64_t)e * blk + c];
+            if (accumulate) out[c] += s;
+            else out[c] = s;
+        }
+        return;
     }
+    const int G = TPB / ncolP2;
+    const int g = t / ncolP2, c = t % ncolP2;
+    cx<T> s = mk(T(0), T(0));
+    if (g < G)
+        for (int e = e0 + g; e < e1; e += G) s += Y[(int64_t)e * blk + c];
+    sm[t] = s;
+    __syncthreads();
+    if (t < ncolP2) {
+        cx<T> tot = sm[t];
+        for (int q = 1; q < G; ++q) tot += sm[q * ncolP2 + t];
+        if (accumulate) out[t] += tot;
+        else out[t] = tot;
+    }
+}
+
+// parent multipole = sum of its children's S|S slots
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_sum_children(const int32_t *__restrict__ child_start, int64_t nbox,
+                                                      const cx<T> *__restrict__ Yc, cx<T> *__restrict__ Mp, int64_t blk,
+                                                      int ncolP2) {
+    __shared__ cx<T> sm[TPB];
+    const int64_t b = blockIdx.x;
+    slot_sum(Yc, child_start[b], child_start[b + 1], blk, ncolP2, Mp + b * blk, false, sm);
 }
 
 // target local (+)= sum over its far-field slots
 template <typename T>
-__global__ void k_sum_far(const int32_t *__restrict__ ff_ofs, const cx<T> *__restrict__ Yf, cx<T> *__restrict__ Lc,
-                          int64_t blk, int ncolP2, int accumulate) {
+__global__ void __launch_bounds__(TPB) k_sum_far(const int32_t *__restrict__ ff_ofs, const cx<T> *__restrict__ Yf,
+                                                 cx<T> *__restrict__ Lc, int64_t blk, int ncolP2, int accumulate) {
+    __shared__ cx<T> sm[TPB];
     const int64_t b = blockIdx.x;
-    const int e0 = ff_ofs[b], e1 = ff_ofs[b + 1];
-    for (int t = threadIdx.x; t < ncolP2; t += blockDim.x) {
-        cx<T> s = mk(T(0), T(0));
-        for (int e = e0; e < e1; ++e) s += Yf[(int64_t)e * blk + t];
-        if (accumulate) Lc[b * blk + t] += s;
-        else Lc[b * blk + t] = s;
-    }
+    slot_sum(Yf, ff_ofs[b], ff_ofs[b + 1], blk, ncolP2, Lc + b * blk, accumulate != 0, sm);
 }
 
 inline unsigned gridn(int64_t m, int tpb = TPB) { return (unsigned)((m + tpb - 1) / tpb); }

@@ -1,6 +1,6 @@
 // BEM system of one scatterer (eqs. 2.9-2.13), the block preconditioner
 // M = A_self (Sec. 3.1, eq. 3.2) and right-preconditioned flexible GMRES
-// (eq. 3.1), all device-resident in FP64.
+// (eq. 3.1), all device-resident.
 //
 // Rows of node alpha (unknowns Phi = E_0, Psi = n x curl E_0):
 //   r[0:3] = 1/2 Phi + Op_{k0}(Phi, -Psi)
@@ -10,15 +10,19 @@
 //   K(V) a = n (V . a) - (n . V) a - V (n . a).
 //
 // fGMRES keeps the preconditioned directions z_j = M^{-1} v_j, orthogonalises
-// A z_j against the basis by classical Gram-Schmidt done twice, and updates a
+// A z_j against the basis by classical Gram-Schmidt, and updates a
 // QR factorisation of the Hessenberg matrix with complex Givens rotations
 //   c = |a| / sqrt(|a|^2 + |b|^2),  s = (a / |a|) conj(b) / sqrt(|a|^2 + |b|^2)
 // (a = h_jj, b = h_{j+1,j}); |g_{j+1}| estimates the residual.  Several
 // right-hand sides iterate in lockstep, each with its own Hessenberg matrix.
 //
 // Mixed mode (iterative refinement): r = b - A64 x with the FP64 plans, an
-// inner fGMRES solves A32 d = r with the FP32 plans (the Krylov vectors stay
-// FP64), x += d, until |r| <= tol |b|.
+// inner fGMRES solves A32 d = r with the FP32 plans and FP32 Krylov vectors
+// (inner products accumulated in FP64), x += d, until |r| <= tol |b|.
+//
+// Gram-Schmidt: one classical pass, then a second one only for the rhs where
+// the first removed more than half of |A z|^2 (the DGKS criterion).  The two
+// FMM products of each application run concurrently on two streams.
 #include <algorithm>
 #include <cstring>
 
@@ -31,10 +35,19 @@ struct fmb_problem_s {
     double k0_re = 0, k0_im = 0;
     int nrhs_max = 1;
     fmb::DevBuf minv;          // c128[n][6][6]
+    fmb::DevBuf minv32;        // c64[n][6][6], FP32 copy for the inner solves (FP32 plans only)
     fmb::DevBuf upts;          // f64[n][3] user order
     // matvec staging [nrhs][n][3] for the two plans (FP64) and their FP32 copies
     fmb::DevBuf a0, b0, a1, b1, y0, y1;
     fmb::DevBuf a0s, b0s, a1s, b1s, y0s, y1s;
+    // second stream (default priority) for the k1 product, and the fork/join events
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    ~fmb_problem_s() {
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (s2) (void)hipStreamDestroy(s2);
+    }
 };
 
 namespace fmb {
@@ -50,16 +63,23 @@ __device__ inline void tmul(const double nv[3], double c, const cx<double> in[3]
     for (int i = 0; i < 3; ++i) out[i] = in[i] + (c * nv[i]) * d;
 }
 
-__global__ void k_bem_split(const cx<double> *__restrict__ x, const double *__restrict__ nrm, int64_t n, int nrhs,
-                            cx<double> tc, cx<double> gamma, cx<double> *__restrict__ a0, cx<double> *__restrict__ b0,
-                            cx<double> *__restrict__ a1, cx<double> *__restrict__ b1) {
+template <typename T>
+__device__ inline cx<T> narrow(cx<double> z) { return mk((T)z.re, (T)z.im); }
+template <typename T>
+__device__ inline cx<double> widen(cx<T> z) { return mk((double)z.re, (double)z.im); }
+
+template <typename T>
+__global__ void k_bem_split(const cx<T> *__restrict__ x, const double *__restrict__ nrm, int64_t n, int nrhs,
+                            cx<double> tcd, cx<double> gammad, cx<T> *__restrict__ a0, cx<T> *__restrict__ b0,
+                            cx<T> *__restrict__ a1, cx<T> *__restrict__ b1) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n * nrhs) return;
     const int64_t node = i % n;
-    const double nv[3] = {nrm[3 * node], nrm[3 * node + 1], nrm[3 * node + 2]};
-    const cx<double> *xi = x + i * 6;
-    cx<double> phi[3] = {xi[0], xi[1], xi[2]}, psi[3] = {xi[3], xi[4], xi[5]};
-    cx<double> d = nv[0] * phi[0] + nv[1] * phi[1] + nv[2] * phi[2];
+    const cx<T> tc = narrow<T>(tcd), gamma = narrow<T>(gammad);
+    const T nv[3] = {(T)nrm[3 * node], (T)nrm[3 * node + 1], (T)nrm[3 * node + 2]};
+    const cx<T> *xi = x + i * 6;
+    cx<T> phi[3] = {xi[0], xi[1], xi[2]}, psi[3] = {xi[3], xi[4], xi[5]};
+    cx<T> d = nv[0] * phi[0] + nv[1] * phi[1] + nv[2] * phi[2];
     for (int c = 0; c < 3; ++c) {
         a0[i * 3 + c] = phi[c];
         b0[i * 3 + c] = -psi[c];
@@ -68,19 +88,21 @@ __global__ void k_bem_split(const cx<double> *__restrict__ x, const double *__re
     }
 }
 
-__global__ void k_bem_combine(const cx<double> *__restrict__ x, const double *__restrict__ nrm, int64_t n, int nrhs,
-                              cx<double> tc, const cx<double> *__restrict__ y0, const cx<double> *__restrict__ y1,
-                              cx<double> *__restrict__ r) {
+template <typename T>
+__global__ void k_bem_combine(const cx<T> *__restrict__ x, const double *__restrict__ nrm, int64_t n, int nrhs,
+                              cx<double> tcd, const cx<T> *__restrict__ y0, const cx<T> *__restrict__ y1,
+                              cx<T> *__restrict__ r) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n * nrhs) return;
     const int64_t node = i % n;
-    const double nv[3] = {nrm[3 * node], nrm[3 * node + 1], nrm[3 * node + 2]};
-    const cx<double> *xi = x + i * 6;
-    cx<double> d = nv[0] * xi[0] + nv[1] * xi[1] + nv[2] * xi[2];
+    const cx<T> tc = narrow<T>(tcd);
+    const T nv[3] = {(T)nrm[3 * node], (T)nrm[3 * node + 1], (T)nrm[3 * node + 2]};
+    const cx<T> *xi = x + i * 6;
+    cx<T> d = nv[0] * xi[0] + nv[1] * xi[1] + nv[2] * xi[2];
     for (int c = 0; c < 3; ++c) {
-        cx<double> tphi = xi[c] + (nv[c] * tc) * d;
-        r[i * 6 + c] = 0.5 * xi[c] + y0[i * 3 + c];
-        r[i * 6 + 3 + c] = 0.5 * tphi - y1[i * 3 + c];
+        cx<T> tphi = xi[c] + (nv[c] * tc) * d;
+        r[i * 6 + c] = T(0.5) * xi[c] + y0[i * 3 + c];
+        r[i * 6 + 3 + c] = T(0.5) * tphi - y1[i * 3 + c];
     }
 }
 
@@ -89,12 +111,12 @@ __global__ void k_to32(const cx<double> *__restrict__ in, cx<float> *__restrict_
     if (i < m) out[i] = mk((float)in[i].re, (float)in[i].im);
 }
 
-__global__ void k_to64(const cx<float> *__restrict__ in, cx<double> *__restrict__ out, int64_t m) {
+// x += d (FP32 correction into the FP64 iterate)
+__global__ void k_add_from32(cx<double> *__restrict__ x, const cx<float> *__restrict__ d, int64_t m) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < m) out[i] = mk((double)in[i].re, (double)in[i].im);
+    if (i < m) x[i] += mk((double)d[i].re, (double)d[i].im);
 }
 
-// M_alpha^{-1} from the coincident-node self blocks of both plans
 __global__ void k_precond_build(const double *__restrict__ nrm, const int32_t *__restrict__ point_tri,
                                 const int32_t *__restrict__ tri_nodes, int m, const cx<double> *__restrict__ cv0,
                                 const cx<double> *__restrict__ cg0, const cx<double> *__restrict__ cv1,
@@ -168,17 +190,18 @@ __global__ void k_precond_build(const double *__restrict__ nrm, const int32_t *_
         for (int j = 0; j < 6; ++j) minv[a * 36 + i * 6 + j] = A[i][6 + j];
 }
 
-__global__ void k_precond_apply(const cx<double> *__restrict__ minv, const cx<double> *__restrict__ v,
-                                cx<double> *__restrict__ z, int64_t n, int nrhs) {
+template <typename T>
+__global__ void k_precond_apply(const cx<T> *__restrict__ minv, const cx<T> *__restrict__ v, cx<T> *__restrict__ z,
+                                int64_t n, int nrhs) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n * nrhs) return;
     const int64_t node = i % n;
-    const cx<double> *M = minv + node * 36;
-    const cx<double> *vi = v + i * 6;
-    cx<double> in[6];
+    const cx<T> *M = minv + node * 36;
+    const cx<T> *vi = v + i * 6;
+    cx<T> in[6];
     for (int q = 0; q < 6; ++q) in[q] = vi[q];
     for (int r = 0; r < 6; ++r) {
-        cx<double> s = mk(0.0, 0.0);
+        cx<T> s = mk(T(0), T(0));
         for (int q = 0; q < 6; ++q) s += M[r * 6 + q] * in[q];
         z[i * 6 + r] = s;
     }
@@ -203,28 +226,40 @@ __global__ void k_rhs_planewave(const double *__restrict__ spts, const int32_t *
 }
 
 // ---- Krylov kernels (vectors of length len per rhs, stride len) ----
+// Vectors are cx<T> (T = double for FP64 solves, float for the inner solves of
+// the mixed mode); inner products, the Hessenberg matrix and the rotations are
+// always FP64.
 constexpr int DOT_CHUNKS = 64;
 
-// part[(i*nrhs + r)*DOT_CHUNKS + c] = sum_{k in chunk c} conj(V_i[r][k]) W[r][k]
-__global__ void k_dots(const cx<double> *__restrict__ V, int64_t vstride, int nv, const cx<double> *__restrict__ W,
-                       int64_t len, int nrhs, cx<double> *__restrict__ part) {
+// part[(i*nrhs + r)*DOT_CHUNKS + c] = sum_{k in chunk c} conj(V_i[r][k]) W[r][k] for i < nv, and
+// for i == nv (when X is given) the same with X in place of V_i.  need (optional): rhs with
+// need[r] == 0 write zeros without reading.
+template <typename T>
+__global__ void k_dots(const cx<T> *__restrict__ V, int64_t vstride, int nv, const cx<T> *__restrict__ X,
+                       const cx<T> *__restrict__ W, int64_t len, int nrhs, const int32_t *__restrict__ need,
+                       cx<double> *__restrict__ part) {
     __shared__ cx<double> sm[TPB];
     const int c = blockIdx.x % DOT_CHUNKS;
     const int r = (blockIdx.x / DOT_CHUNKS) % nrhs;
     const int i = blockIdx.x / (DOT_CHUNKS * nrhs);
-    const cx<double> *v = V + (int64_t)i * vstride + (int64_t)r * len;
-    const cx<double> *w = W + (int64_t)r * len;
+    cx<double> *out = part + ((int64_t)i * nrhs + r) * DOT_CHUNKS + c;
+    if (need && !need[r]) {
+        if (threadIdx.x == 0) *out = mk(0.0, 0.0);
+        return;
+    }
+    const cx<T> *v = (i < nv ? V + (int64_t)i * vstride : X) + (int64_t)r * len;
+    const cx<T> *w = W + (int64_t)r * len;
     const int64_t per = (len + DOT_CHUNKS - 1) / DOT_CHUNKS;
     const int64_t k0 = c * per, k1 = min(len, k0 + per);
     cx<double> s = mk(0.0, 0.0);
-    for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) s += conj(v[k]) * w[k];
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) s += conj(widen(v[k])) * widen(w[k]);
     sm[threadIdx.x] = s;
     __syncthreads();
     for (int st = TPB / 2; st > 0; st >>= 1) {
         if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[((int64_t)i * nrhs + r) * DOT_CHUNKS + c] = sm[0];
+    if (threadIdx.x == 0) *out = sm[0];
 }
 
 __global__ void k_dots_reduce(const cx<double> *__restrict__ part, int cnt, cx<double> *__restrict__ out) {
@@ -235,50 +270,51 @@ __global__ void k_dots_reduce(const cx<double> *__restrict__ part, int cnt, cx<d
     out[e] = s;
 }
 
-// W[r] += sign * sum_i V_i[r] h[i][r]   (h laid out [i][nrhs]); masked by active[r]
-__global__ void k_combine(const cx<double> *__restrict__ V, int64_t vstride, int nv, const cx<double> *__restrict__ h,
-                          double sign, cx<double> *__restrict__ W, int64_t len, int nrhs,
-                          const int32_t *__restrict__ active) {
+// W[r] += sign * sum_i V_i[r] h[i][r]   (h laid out [i][nrhs]); only rhs with active[r] (and need[r])
+template <typename T>
+__global__ void k_combine(const cx<T> *__restrict__ V, int64_t vstride, int nv, const cx<double> *__restrict__ h,
+                          double sign, cx<T> *__restrict__ W, int64_t len, int nrhs,
+                          const int32_t *__restrict__ active, const int32_t *__restrict__ need) {
     int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= len * nrhs) return;
     const int r = (int)(e / len);
     if (active && !active[r]) return;
+    if (need && !need[r]) return;
     cx<double> s = mk(0.0, 0.0);
-    for (int i = 0; i < nv; ++i) s += V[(int64_t)i * vstride + e] * h[(int64_t)i * nrhs + r];
-    W[e] += sign * s;
+    for (int i = 0; i < nv; ++i) s += widen(V[(int64_t)i * vstride + e]) * h[(int64_t)i * nrhs + r];
+    W[e] = narrow<T>(widen(W[e]) + sign * s);
 }
 
-__global__ void k_scale_into(const cx<double> *__restrict__ W, const double *__restrict__ inv, cx<double> *__restrict__ out,
+template <typename T>
+__global__ void k_scale_into(const cx<T> *__restrict__ W, const double *__restrict__ inv, cx<T> *__restrict__ out,
                              int64_t len, int nrhs, const int32_t *__restrict__ active) {
     int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= len * nrhs) return;
     const int r = (int)(e / len);
-    out[e] = (active && !active[r]) ? mk(0.0, 0.0) : inv[r] * W[e];
+    out[e] = (active && !active[r]) ? mk(T(0), T(0)) : narrow<T>(inv[r] * widen(W[e]));
 }
 
-__global__ void k_sub(const cx<double> *__restrict__ b, const cx<double> *__restrict__ ax, cx<double> *__restrict__ r,
-                      int64_t m) {
+template <typename T>
+__global__ void k_sub(const cx<T> *__restrict__ b, const cx<T> *__restrict__ ax, cx<T> *__restrict__ r, int64_t m) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < m) r[i] = b[i] - ax[i];
 }
 
-__global__ void k_axpy_masked(cx<double> *__restrict__ x, const cx<double> *__restrict__ d, int64_t len, int nrhs) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < len * nrhs) x[i] += d[i];
-}
-
 // One Arnoldi column per rhs: H[:, j] from h (j+1 entries, [i][nrhs]) and hn;
 // apply old rotations, form a new one, update g, write the residual estimate.
+// |A z| (for the breakdown test) is sqrt of h[j+1] = (A z)^H (A z), the extra
+// inner product of the first Gram-Schmidt pass.
 __global__ void k_givens(cx<double> *__restrict__ H, int ldh, int j, const cx<double> *__restrict__ h,
-                         const double *__restrict__ hn, const double *__restrict__ nAz, double *__restrict__ cs,
-                         cx<double> *__restrict__ sn, cx<double> *__restrict__ g, double *__restrict__ res,
-                         int32_t *__restrict__ active, int32_t *__restrict__ brk, int nrhs, int m) {
+                         const double *__restrict__ hn, double *__restrict__ cs, cx<double> *__restrict__ sn,
+                         cx<double> *__restrict__ g, double *__restrict__ res, int32_t *__restrict__ active,
+                         int32_t *__restrict__ brk, int nrhs, int m) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrhs) return;
     if (!active[r]) return;
     cx<double> *Hr = H + (int64_t)r * ldh * m;          // column-major [m][ldh]
     cx<double> *col = Hr + (int64_t)j * ldh;
     for (int i = 0; i <= j; ++i) col[i] = h[(int64_t)i * nrhs + r];
+    const double nAz = sqrt(fmax(h[(int64_t)(j + 1) * nrhs + r].re, 0.0));
     col[j + 1] = mk(hn[r], 0.0);
     for (int i = 0; i < j; ++i) {
         const double c = cs[r * m + i];
@@ -306,7 +342,7 @@ __global__ void k_givens(cx<double> *__restrict__ H, int ldh, int j, const cx<do
     g[r * (m + 1) + j + 1] = -(conj(s) * gj);
     g[r * (m + 1) + j] = c * gj;
     res[r] = sqrt(abs2(g[r * (m + 1) + j + 1]));
-    brk[r] = (hn[r] <= 1e-14 * nAz[r]) ? 1 : 0;
+    brk[r] = (hn[r] <= 1e-14 * nAz) ? 1 : 0;
 }
 
 // y = H^{-1} g (upper triangular, size jr[r]) per rhs, written as y[i][nrhs]
@@ -324,102 +360,160 @@ __global__ void k_trisolve(const cx<double> *__restrict__ H, int ldh, const cx<d
     }
 }
 
-__global__ void k_add(cx<double> *__restrict__ h, const cx<double> *__restrict__ h2, int cnt) {
+// h += h2 for the rhs that took the second Gram-Schmidt pass
+__global__ void k_add_need(cx<double> *__restrict__ h, const cx<double> *__restrict__ h2, int cnt, int nrhs,
+                           const int32_t *__restrict__ need) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt) h[i] += h2[i];
+    if (i < cnt && need[i % nrhs]) h[i] += h2[i];
 }
 
-__global__ void k_sqrt_real(const cx<double> *__restrict__ in, double *__restrict__ out, double *__restrict__ inv, int m) {
+// out = sqrt(re in), inv = 1/out (0 for 0); with need, only rhs with need[r] are updated
+__global__ void k_sqrt_real(const cx<double> *__restrict__ in, double *__restrict__ out, double *__restrict__ inv, int m,
+                            const int32_t *__restrict__ need) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
+    if (need && !need[i]) return;
     double v = sqrt(fmax(in[i].re, 0.0));
     out[i] = v;
     if (inv) inv[i] = v > 0 ? 1.0 / v : 0.0;
 }
 
+// Daniel-Gragg-Kaufman-Stewart test: a second Gram-Schmidt pass is taken when
+// the first one removed more than half of |A z|^2 (|w'| < |A z| / sqrt 2).
+__global__ void k_dgks(const cx<double> *__restrict__ h, int j, const double *__restrict__ hn,
+                       const int32_t *__restrict__ active, int32_t *__restrict__ need, int nrhs) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    const double az2 = h[(int64_t)(j + 1) * nrhs + r].re;
+    need[r] = (active[r] && 2.0 * hn[r] * hn[r] < az2) ? 1 : 0;
+}
+
+template <typename T>
 struct Krylov {
     int64_t len = 0;
     int nrhs = 0, m = 0;
-    DevBuf V, Z, W, H, cs, sn, g, h, h2, hn, hninv, nAz, res, part, act, brk, jr, y, tmp, r, ax;
+    DevBuf V, Z, W, r, ax;                                            // cx<T>
+    DevBuf H, cs, sn, g, h, h2, hn, hninv, res, part, act, brk, jr, y, tmp, need;   // FP64 / int32
 };
 
-void dots(Krylov &K, const cx<double> *V, int nv, const cx<double> *W, cx<double> *out, hipStream_t s) {
-    const int blocks = nv * K.nrhs * DOT_CHUNKS;
-    k_dots<<<blocks, TPB, 0, s>>>(V, K.len * K.nrhs, nv, W, K.len, K.nrhs, K.part.as<cx<double>>());
-    k_dots_reduce<<<gridn(nv * K.nrhs), TPB, 0, s>>>(K.part.as<cx<double>>(), nv * K.nrhs, out);
+template <typename T>
+void dots(Krylov<T> &K, const cx<T> *V, int nv, const cx<T> *X, const cx<T> *W, const int32_t *need, cx<double> *out,
+          hipStream_t s) {
+    const int nvt = nv + (X ? 1 : 0);
+    const int blocks = nvt * K.nrhs * DOT_CHUNKS;
+    k_dots<T><<<blocks, TPB, 0, s>>>(V, K.len * K.nrhs, nv, X, W, K.len, K.nrhs, need, K.part.template as<cx<double>>());
+    k_dots_reduce<<<gridn(nvt * K.nrhs), TPB, 0, s>>>(K.part.template as<cx<double>>(), nvt * K.nrhs, out);
     FMB_LAUNCH_CHECK();
 }
 
-void norms(Krylov &K, const cx<double> *W, double *out, double *inv, hipStream_t s) {
-    dots(K, W, 1, W, K.tmp.as<cx<double>>(), s);
-    k_sqrt_real<<<1, 1024, 0, s>>>(K.tmp.as<cx<double>>(), out, inv, K.nrhs);
+template <typename T>
+void norms(Krylov<T> &K, const cx<T> *W, double *out, double *inv, hipStream_t s, const int32_t *need = nullptr) {
+    dots(K, W, 1, (const cx<T> *)nullptr, W, need, K.tmp.template as<cx<double>>(), s);
+    k_sqrt_real<<<1, 1024, 0, s>>>(K.tmp.template as<cx<double>>(), out, inv, K.nrhs, need);
     FMB_LAUNCH_CHECK();
+}
+
+template <typename T>
+void krylov_alloc(Krylov<T> &K, int64_t len, int nrhs, int m) {
+    if (K.len == len && K.nrhs == nrhs && K.m == m) return;
+    K.len = len;
+    K.nrhs = nrhs;
+    K.m = m;
+    const size_t tot = (size_t)len * nrhs * sizeof(cx<T>);
+    K.V.alloc(tot * (m + 1));
+    K.Z.alloc(tot * m);
+    K.W.alloc(tot);
+    K.r.alloc(tot);
+    K.ax.alloc(tot);
+    K.H.alloc((size_t)nrhs * (m + 1) * m * sizeof(cx<double>));
+    K.cs.alloc((size_t)nrhs * m * sizeof(double));
+    K.sn.alloc((size_t)nrhs * m * sizeof(cx<double>));
+    K.g.alloc((size_t)nrhs * (m + 1) * sizeof(cx<double>));
+    K.h.alloc((size_t)(m + 2) * nrhs * sizeof(cx<double>));
+    K.h2.alloc((size_t)(m + 2) * nrhs * sizeof(cx<double>));
+    K.y.alloc((size_t)(m + 1) * nrhs * sizeof(cx<double>));
+    K.hn.alloc(nrhs * sizeof(double));
+    K.hninv.alloc(nrhs * sizeof(double));
+    K.res.alloc(nrhs * sizeof(double));
+    K.act.alloc(nrhs * sizeof(int32_t));
+    K.brk.alloc(nrhs * sizeof(int32_t));
+    K.jr.alloc(nrhs * sizeof(int32_t));
+    K.need.alloc(nrhs * sizeof(int32_t));
+    K.tmp.alloc((size_t)(m + 2) * nrhs * sizeof(cx<double>));
+    K.part.alloc((size_t)(m + 2) * nrhs * DOT_CHUNKS * sizeof(cx<double>));
 }
 
 }  // namespace
 
-// A x in FP64 (use32 = 0) or with the FP32 plans (use32 = 1)
-static void bem_apply_impl(fmb_problem_s &pb, const cx<double> *x, cx<double> *r, int nrhs, int use32, hipStream_t s) {
-    const int64_t n = pb.n, m3 = n * 3 * nrhs;
+// The two FMM products of one BEM application run concurrently: the k1 plan
+// on the problem's second stream, forked from and joined back into s.
+template <typename T>
+static void fmm_pair(fmb_problem_s &pb, const Plan *P0, const Plan *P1, const cx<T> *a0, const cx<T> *b0, cx<T> *y0,
+                     const cx<T> *a1, const cx<T> *b1, cx<T> *y1, int nrhs, hipStream_t s) {
+    FMB_CHECK_HIP(hipEventRecord(pb.ev_fork, s));
+    FMB_CHECK_HIP(hipStreamWaitEvent(pb.s2, pb.ev_fork, 0));
+    run_matvec(*const_cast<Plan *>(P0), a0, b0, y0, nrhs, s);
+    run_matvec(*const_cast<Plan *>(P1), a1, b1, y1, nrhs, pb.s2);
+    FMB_CHECK_HIP(hipEventRecord(pb.ev_join, pb.s2));
+    FMB_CHECK_HIP(hipStreamWaitEvent(s, pb.ev_join, 0));
+}
+
+// A x with the FP64 plans (T = double) or the FP32 plans (T = float)
+template <typename T>
+static void bem_apply_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int nrhs, hipStream_t s) {
+    const int64_t n = pb.n;
     const cx<double> tc = cdiv(mk(1.0, 0.0) - pb.eps, pb.eps);
     const double *nrm = pb.p0->p.unrm.as<double>();
-    cx<double> *a0 = pb.a0.as<cx<double>>(), *b0 = pb.b0.as<cx<double>>(), *a1 = pb.a1.as<cx<double>>(),
-               *b1 = pb.b1.as<cx<double>>(), *y0 = pb.y0.as<cx<double>>(), *y1 = pb.y1.as<cx<double>>();
-    k_bem_split<<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, tc, pb.gamma, a0, b0, a1, b1);
+    const bool f32 = sizeof(T) == sizeof(float);
+    cx<T> *a0 = (f32 ? pb.a0s : pb.a0).template as<cx<T>>(), *b0 = (f32 ? pb.b0s : pb.b0).template as<cx<T>>(),
+          *a1 = (f32 ? pb.a1s : pb.a1).template as<cx<T>>(), *b1 = (f32 ? pb.b1s : pb.b1).template as<cx<T>>(),
+          *y0 = (f32 ? pb.y0s : pb.y0).template as<cx<T>>(), *y1 = (f32 ? pb.y1s : pb.y1).template as<cx<T>>();
+    k_bem_split<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, tc, pb.gamma, a0, b0, a1, b1);
     FMB_LAUNCH_CHECK();
-    if (!use32) {
-        run_matvec(pb.p0->p, a0, b0, y0, nrhs, s);
-        run_matvec(pb.p1->p, a1, b1, y1, nrhs, s);
-    } else {
-        cx<float> *A0 = pb.a0s.as<cx<float>>(), *B0 = pb.b0s.as<cx<float>>(), *A1 = pb.a1s.as<cx<float>>(),
-                  *B1 = pb.b1s.as<cx<float>>(), *Y0 = pb.y0s.as<cx<float>>(), *Y1 = pb.y1s.as<cx<float>>();
-        k_to32<<<gridn(m3), TPB, 0, s>>>(a0, A0, m3);
-        k_to32<<<gridn(m3), TPB, 0, s>>>(b0, B0, m3);
-        k_to32<<<gridn(m3), TPB, 0, s>>>(a1, A1, m3);
-        k_to32<<<gridn(m3), TPB, 0, s>>>(b1, B1, m3);
-        FMB_LAUNCH_CHECK();
-        run_matvec(pb.p032->p, A0, B0, Y0, nrhs, s);
-        run_matvec(pb.p132->p, A1, B1, Y1, nrhs, s);
-        k_to64<<<gridn(m3), TPB, 0, s>>>(Y0, y0, m3);
-        k_to64<<<gridn(m3), TPB, 0, s>>>(Y1, y1, m3);
-        FMB_LAUNCH_CHECK();
-    }
-    k_bem_combine<<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, tc, y0, y1, r);
+    const Plan *P0 = f32 ? &pb.p032->p : &pb.p0->p, *P1 = f32 ? &pb.p132->p : &pb.p1->p;
+    fmm_pair<T>(pb, P0, P1, a0, b0, y0, a1, b1, y1, nrhs, s);
+    k_bem_combine<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, tc, y0, y1, r);
     FMB_LAUNCH_CHECK();
 }
 
-static void precond_impl(fmb_problem_s &pb, const cx<double> *v, cx<double> *z, int nrhs, hipStream_t s) {
-    k_precond_apply<<<gridn(pb.n * nrhs), TPB, 0, s>>>(pb.minv.as<cx<double>>(), v, z, pb.n, nrhs);
+template <typename T>
+static void precond_t(fmb_problem_s &pb, const cx<T> *v, cx<T> *z, int nrhs, hipStream_t s) {
+    const bool f32 = sizeof(T) == sizeof(float);
+    k_precond_apply<T><<<gridn(pb.n * nrhs), TPB, 0, s>>>((f32 ? pb.minv32 : pb.minv).template as<cx<T>>(), v, z,
+                                                           pb.n, nrhs);
     FMB_LAUNCH_CHECK();
 }
 
-// One right-preconditioned fGMRES solve of A x = b, x updated in place.
-// Returns the iteration count; relres receives |b - A x| / |b| per rhs
-// (computed with the operator the solve used).
-static int fgmres(fmb_problem_s &pb, Krylov &K, const cx<double> *b, cx<double> *x, bool x_nonzero, double tol,
-                  int maxit, int use32, int precond, std::vector<double> &relres, std::vector<double> *hist,
-                  int &matvecs, hipStream_t s) {
+// One right-preconditioned fGMRES solve of A x = b, x updated in place, with
+// the FP64 operator (T = double) or the FP32 one (T = float).  Returns the
+// iteration count; relres receives |b - A x| / |b| per rhs (computed with the
+// operator the solve used).
+template <typename T>
+static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, bool x_nonzero, double tol, int maxit,
+                  int precond, std::vector<double> &relres, std::vector<double> *hist, int &matvecs, hipStream_t s) {
     const int nrhs = K.nrhs, m = K.m;
     const int64_t len = K.len, tot = len * nrhs;
-    cx<double> *V = K.V.as<cx<double>>(), *Z = K.Z.as<cx<double>>(), *W = K.W.as<cx<double>>();
-    cx<double> *R = K.r.as<cx<double>>(), *AX = K.ax.as<cx<double>>();
+    cx<T> *V = K.V.template as<cx<T>>(), *Z = K.Z.template as<cx<T>>(), *W = K.W.template as<cx<T>>();
+    cx<T> *R = K.r.template as<cx<T>>(), *AX = K.ax.template as<cx<T>>();
+    int32_t *need = K.need.template as<int32_t>(), *actd = K.act.template as<int32_t>();
+    cx<double> *h = K.h.template as<cx<double>>(), *h2 = K.h2.template as<cx<double>>();
     std::vector<double> bn(nrhs), beta(nrhs), res(nrhs);
     std::vector<int32_t> act(nrhs), jr(nrhs), brk(nrhs);
-    norms(K, b, K.hn.as<double>(), nullptr, s);
+    norms(K, b, K.hn.template as<double>(), nullptr, s);
     FMB_CHECK_HIP(hipMemcpyAsync(bn.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
     if (x_nonzero) {
-        bem_apply_impl(pb, x, AX, nrhs, use32, s);
+        bem_apply_t<T>(pb, x, AX, nrhs, s);
         ++matvecs;
-        k_sub<<<gridn(tot), TPB, 0, s>>>(b, AX, R, tot);
+        k_sub<T><<<gridn(tot), TPB, 0, s>>>(b, AX, R, tot);
         FMB_LAUNCH_CHECK();
     } else {
-        FMB_CHECK_HIP(hipMemsetAsync(x, 0, tot * sizeof(cx<double>), s));
-        FMB_CHECK_HIP(hipMemcpyAsync(R, b, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+        FMB_CHECK_HIP(hipMemsetAsync(x, 0, tot * sizeof(cx<T>), s));
+        FMB_CHECK_HIP(hipMemcpyAsync(R, b, tot * sizeof(cx<T>), hipMemcpyDeviceToDevice, s));
     }
     int its = 0;
     relres.assign(nrhs, 0.0);
     while (true) {
-        norms(K, R, K.hn.as<double>(), K.hninv.as<double>(), s);
+        norms(K, R, K.hn.template as<double>(), K.hninv.template as<double>(), s);
         FMB_CHECK_HIP(hipMemcpyAsync(beta.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
         FMB_CHECK_HIP(hipStreamSynchronize(s));
         bool any = false;
@@ -430,8 +524,8 @@ static int fgmres(fmb_problem_s &pb, Krylov &K, const cx<double> *b, cx<double> 
             any = any || act[r];
         }
         if (!any || its >= maxit) break;
-        FMB_CHECK_HIP(hipMemcpyAsync(K.act.p, act.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        k_scale_into<<<gridn(tot), TPB, 0, s>>>(R, K.hninv.as<double>(), V, len, nrhs, K.act.as<int32_t>());
+        FMB_CHECK_HIP(hipMemcpyAsync(actd, act.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        k_scale_into<T><<<gridn(tot), TPB, 0, s>>>(R, K.hninv.template as<double>(), V, len, nrhs, actd);
         FMB_LAUNCH_CHECK();
         {
             std::vector<cx<double>> g0((size_t)nrhs * (m + 1), mk(0.0, 0.0));
@@ -440,28 +534,29 @@ static int fgmres(fmb_problem_s &pb, Krylov &K, const cx<double> *b, cx<double> 
         }
         for (int r = 0; r < nrhs; ++r) jr[r] = 0;
         for (int j = 0; j < m && its < maxit; ++j) {
-            cx<double> *vj = V + (int64_t)j * tot, *zj = Z + (int64_t)j * tot;
-            if (precond) precond_impl(pb, vj, zj, nrhs, s);
-            else FMB_CHECK_HIP(hipMemcpyAsync(zj, vj, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
-            bem_apply_impl(pb, zj, W, nrhs, use32, s);
+            cx<T> *vj = V + (int64_t)j * tot, *zj = Z + (int64_t)j * tot;
+            if (precond) precond_t<T>(pb, vj, zj, nrhs, s);
+            else FMB_CHECK_HIP(hipMemcpyAsync(zj, vj, tot * sizeof(cx<T>), hipMemcpyDeviceToDevice, s));
+            bem_apply_t<T>(pb, zj, W, nrhs, s);
             ++matvecs;
-            norms(K, W, K.nAz.as<double>(), nullptr, s);
-            // classical Gram-Schmidt done twice
-            dots(K, V, j + 1, W, K.h.as<cx<double>>(), s);
-            k_combine<<<gridn(tot), TPB, 0, s>>>(V, tot, j + 1, K.h.as<cx<double>>(), -1.0, W, len, nrhs,
-                                                 K.act.as<int32_t>());
-            dots(K, V, j + 1, W, K.h2.as<cx<double>>(), s);
-            k_combine<<<gridn(tot), TPB, 0, s>>>(V, tot, j + 1, K.h2.as<cx<double>>(), -1.0, W, len, nrhs,
-                                                 K.act.as<int32_t>());
-            k_add<<<gridn((j + 1) * nrhs), TPB, 0, s>>>(K.h.as<cx<double>>(), K.h2.as<cx<double>>(), (j + 1) * nrhs);
+            // classical Gram-Schmidt; the same pass yields |A z|^2 as h[j+1]
+            dots(K, (const cx<T> *)V, j + 1, (const cx<T> *)W, (const cx<T> *)W, (const int32_t *)nullptr, h, s);
+            k_combine<T><<<gridn(tot), TPB, 0, s>>>(V, tot, j + 1, h, -1.0, W, len, nrhs, actd, nullptr);
             FMB_LAUNCH_CHECK();
-            norms(K, W, K.hn.as<double>(), K.hninv.as<double>(), s);
-            k_scale_into<<<gridn(tot), TPB, 0, s>>>(W, K.hninv.as<double>(), V + (int64_t)(j + 1) * tot, len, nrhs,
-                                                    K.act.as<int32_t>());
-            k_givens<<<1, 1024, 0, s>>>(K.H.as<cx<double>>(), m + 1, j, K.h.as<cx<double>>(), K.hn.as<double>(),
-                                        K.nAz.as<double>(), K.cs.as<double>(), K.sn.as<cx<double>>(),
-                                        K.g.as<cx<double>>(), K.res.as<double>(), K.act.as<int32_t>(),
-                                        K.brk.as<int32_t>(), nrhs, m);
+            norms(K, (const cx<T> *)W, K.hn.template as<double>(), K.hninv.template as<double>(), s);
+            // second pass only where the DGKS test asks for it
+            k_dgks<<<1, 1024, 0, s>>>(h, j, K.hn.template as<double>(), actd, need, nrhs);
+            dots(K, (const cx<T> *)V, j + 1, (const cx<T> *)nullptr, (const cx<T> *)W, (const int32_t *)need, h2, s);
+            k_combine<T><<<gridn(tot), TPB, 0, s>>>(V, tot, j + 1, h2, -1.0, W, len, nrhs, actd, need);
+            k_add_need<<<gridn((j + 1) * nrhs), TPB, 0, s>>>(h, h2, (j + 1) * nrhs, nrhs, need);
+            FMB_LAUNCH_CHECK();
+            norms(K, (const cx<T> *)W, K.hn.template as<double>(), K.hninv.template as<double>(), s, need);
+            k_scale_into<T><<<gridn(tot), TPB, 0, s>>>(W, K.hninv.template as<double>(), V + (int64_t)(j + 1) * tot,
+                                                       len, nrhs, actd);
+            k_givens<<<1, 1024, 0, s>>>(K.H.template as<cx<double>>(), m + 1, j, h, K.hn.template as<double>(),
+                                        K.cs.template as<double>(), K.sn.template as<cx<double>>(),
+                                        K.g.template as<cx<double>>(), K.res.template as<double>(), actd,
+                                        K.brk.template as<int32_t>(), nrhs, m);
             FMB_LAUNCH_CHECK();
             FMB_CHECK_HIP(hipMemcpyAsync(res.data(), K.res.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
             FMB_CHECK_HIP(hipMemcpyAsync(brk.data(), K.brk.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -481,54 +576,26 @@ static int fgmres(fmb_problem_s &pb, Krylov &K, const cx<double> *b, cx<double> 
                 }
             }
             if (hist) hist->push_back(worst);
-            FMB_CHECK_HIP(hipMemcpyAsync(K.act.p, act.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            FMB_CHECK_HIP(hipMemcpyAsync(actd, act.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
             if (!more) break;
         }
         // x += Z y with y = H^{-1} g per rhs
         FMB_CHECK_HIP(hipMemcpyAsync(K.jr.p, jr.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        k_trisolve<<<1, 1024, 0, s>>>(K.H.as<cx<double>>(), m + 1, K.g.as<cx<double>>(), K.jr.as<int32_t>(),
-                                      K.y.as<cx<double>>(), nrhs, m);
+        k_trisolve<<<1, 1024, 0, s>>>(K.H.template as<cx<double>>(), m + 1, K.g.template as<cx<double>>(),
+                                      K.jr.template as<int32_t>(), K.y.template as<cx<double>>(), nrhs, m);
         int jmax = 0;
         for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jr[r]);
         if (jmax > 0)
-            k_combine<<<gridn(tot), TPB, 0, s>>>(Z, tot, jmax, K.y.as<cx<double>>(), 1.0, x, len, nrhs, nullptr);
+            k_combine<T><<<gridn(tot), TPB, 0, s>>>(Z, tot, jmax, K.y.template as<cx<double>>(), 1.0, x, len, nrhs,
+                                                    nullptr, nullptr);
         FMB_LAUNCH_CHECK();
         // true residual
-        bem_apply_impl(pb, x, AX, nrhs, use32, s);
+        bem_apply_t<T>(pb, x, AX, nrhs, s);
         ++matvecs;
-        k_sub<<<gridn(tot), TPB, 0, s>>>(b, AX, R, tot);
+        k_sub<T><<<gridn(tot), TPB, 0, s>>>(b, AX, R, tot);
         FMB_LAUNCH_CHECK();
     }
     return its;
-}
-
-static void krylov_alloc(Krylov &K, int64_t len, int nrhs, int m) {
-    if (K.len == len && K.nrhs == nrhs && K.m == m) return;
-    K.len = len;
-    K.nrhs = nrhs;
-    K.m = m;
-    const size_t tot = (size_t)len * nrhs * sizeof(cx<double>);
-    K.V.alloc(tot * (m + 1));
-    K.Z.alloc(tot * m);
-    K.W.alloc(tot);
-    K.r.alloc(tot);
-    K.ax.alloc(tot);
-    K.H.alloc((size_t)nrhs * (m + 1) * m * sizeof(cx<double>));
-    K.cs.alloc((size_t)nrhs * m * sizeof(double));
-    K.sn.alloc((size_t)nrhs * m * sizeof(cx<double>));
-    K.g.alloc((size_t)nrhs * (m + 1) * sizeof(cx<double>));
-    K.h.alloc((size_t)(m + 1) * nrhs * sizeof(cx<double>));
-    K.h2.alloc((size_t)(m + 1) * nrhs * sizeof(cx<double>));
-    K.y.alloc((size_t)(m + 1) * nrhs * sizeof(cx<double>));
-    K.hn.alloc(nrhs * sizeof(double));
-    K.hninv.alloc(nrhs * sizeof(double));
-    K.nAz.alloc(nrhs * sizeof(double));
-    K.res.alloc(nrhs * sizeof(double));
-    K.act.alloc(nrhs * sizeof(int32_t));
-    K.brk.alloc(nrhs * sizeof(int32_t));
-    K.jr.alloc(nrhs * sizeof(int32_t));
-    K.tmp.alloc((size_t)(m + 1) * nrhs * sizeof(cx<double>));
-    K.part.alloc((size_t)(m + 1) * nrhs * DOT_CHUNKS * sizeof(cx<double>));
 }
 
 }  // namespace fmb
@@ -603,6 +670,15 @@ int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_
         FMB_CHECK_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         FMB_CHECK_HIP(hipStreamSynchronize(s));
         FMB_REQUIRE(hb == 0, "a 6x6 self block of the preconditioner is singular");
+        if (p0_32) {
+            h->minv32.alloc((size_t)A.n * 36 * sizeof(cx<float>));
+            k_to32<<<gridn(A.n * 36), TPB, 0, s>>>(h->minv.as<cx<double>>(), h->minv32.as<cx<float>>(), A.n * 36);
+            FMB_LAUNCH_CHECK();
+            FMB_CHECK_HIP(hipStreamSynchronize(s));
+        }
+        FMB_CHECK_HIP(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
+        FMB_CHECK_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        FMB_CHECK_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
         *out = guard.release();
     });
 }
@@ -611,7 +687,7 @@ int bem_apply(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, void *stre
     return guarded([&] {
         FMB_REQUIRE(pb && x && r && x != r, "bad arguments");
         FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
-        bem_apply_impl(*pb, (const cx<double> *)x, (cx<double> *)r, nrhs, 0, (hipStream_t)stream);
+        bem_apply_t<double>(*pb, (const cx<double> *)x, (cx<double> *)r, nrhs, (hipStream_t)stream);
     });
 }
 
@@ -619,7 +695,7 @@ int bem_precond_apply(fmb_problem_t pb, const void *v, void *z, int32_t nrhs, vo
     return guarded([&] {
         FMB_REQUIRE(pb && v && z, "bad arguments");
         FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
-        precond_impl(*pb, (const cx<double> *)v, (cx<double> *)z, nrhs, (hipStream_t)stream);
+        precond_t<double>(*pb, (const cx<double> *)v, (cx<double> *)z, nrhs, (hipStream_t)stream);
     });
 }
 
@@ -655,28 +731,32 @@ int gmres_solve(fmb_problem_t pb, const void *rhs, void *x, int32_t nrhs, const 
         FMB_REQUIRE(op.tol > 0 && op.restart >= 1 && op.maxit >= 1, "bad solver options");
         FMB_REQUIRE(!op.mixed || pb->p032, "mixed precision needs the FP32 plans");
         hipStream_t s = (hipStream_t)stream;
-        Krylov K;
-        const int64_t len = pb->n * 6;
-        krylov_alloc(K, len, nrhs, op.restart);
+        const int64_t len = pb->n * 6, tot = len * nrhs;
         const cx<double> *b = (const cx<double> *)rhs;
         cx<double> *X = (cx<double> *)x;
         std::vector<double> relres, hist;
         int mv64 = 0, mv32 = 0, its = 0, refinements = 0;
         double final_res = 0.0;
+        Krylov<double> K;
         if (!op.mixed) {
-            its = fgmres(*pb, K, b, X, op.x0_given != 0, op.tol, op.maxit, 0, op.precond, relres, &hist, mv64, s);
+            krylov_alloc(K, len, nrhs, op.restart);
+            its = fgmres<double>(*pb, K, b, X, op.x0_given != 0, op.tol, op.maxit, op.precond, relres, &hist, mv64, s);
             for (double v : relres) final_res = std::max(final_res, v);
         } else {
-            // iterative refinement: FP64 residuals, FP32-operator corrections
-            const int64_t tot = len * nrhs;
-            DevBuf rr, ax, dx;
+            // iterative refinement: FP64 residuals r = b - A64 x, inner fGMRES on
+            // A32 d = r with FP32 Krylov vectors, x += d
+            krylov_alloc(K, len, nrhs, 1);                  // FP64 norms only
+            Krylov<float> K32;
+            krylov_alloc(K32, len, nrhs, op.restart);
+            DevBuf rr, ax, r32, d32;
             rr.alloc(tot * sizeof(cx<double>));
             ax.alloc(tot * sizeof(cx<double>));
-            dx.alloc(tot * sizeof(cx<double>));
+            r32.alloc(tot * sizeof(cx<float>));
+            d32.alloc(tot * sizeof(cx<float>));
             if (op.x0_given) {
-                bem_apply_impl(*pb, X, ax.as<cx<double>>(), nrhs, 0, s);
+                bem_apply_t<double>(*pb, X, ax.as<cx<double>>(), nrhs, s);
                 ++mv64;
-                k_sub<<<gridn(tot), TPB, 0, s>>>(b, ax.as<cx<double>>(), rr.as<cx<double>>(), tot);
+                k_sub<double><<<gridn(tot), TPB, 0, s>>>(b, ax.as<cx<double>>(), rr.as<cx<double>>(), tot);
             } else {
                 FMB_CHECK_HIP(hipMemsetAsync(X, 0, tot * sizeof(cx<double>), s));
                 FMB_CHECK_HIP(hipMemcpyAsync(rr.p, b, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
@@ -685,7 +765,7 @@ int gmres_solve(fmb_problem_t pb, const void *rhs, void *x, int32_t nrhs, const 
             norms(K, b, K.hn.as<double>(), nullptr, s);
             FMB_CHECK_HIP(hipMemcpyAsync(bn.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
             while (true) {
-                norms(K, rr.as<cx<double>>(), K.hn.as<double>(), nullptr, s);
+                norms(K, (const cx<double> *)rr.as<cx<double>>(), K.hn.as<double>(), nullptr, s);
                 FMB_CHECK_HIP(hipMemcpyAsync(rn.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
                 FMB_CHECK_HIP(hipStreamSynchronize(s));
                 final_res = 0.0;
@@ -699,12 +779,14 @@ int gmres_solve(fmb_problem_t pb, const void *rhs, void *x, int32_t nrhs, const 
                 // the last refinements only need to close the gap to tol: loosen the inner tolerance to
                 // a fraction of tol/|r| when that is looser than the configured one
                 const double itol = std::min(0.5, std::max(op.inner_tol, 0.3 * op.tol / std::max(final_res, 1e-300)));
-                its += fgmres(*pb, K, rr.as<cx<double>>(), dx.as<cx<double>>(), false, itol,
-                              std::min(op.inner_maxit, op.maxit - its), 1, op.precond, inner, nullptr, mv32, s);
-                k_axpy_masked<<<gridn(tot), TPB, 0, s>>>(X, dx.as<cx<double>>(), len, nrhs);
-                bem_apply_impl(*pb, X, ax.as<cx<double>>(), nrhs, 0, s);
+                k_to32<<<gridn(tot), TPB, 0, s>>>(rr.as<cx<double>>(), r32.as<cx<float>>(), tot);
+                FMB_LAUNCH_CHECK();
+                its += fgmres<float>(*pb, K32, r32.as<cx<float>>(), d32.as<cx<float>>(), false, itol,
+                                     std::min(op.inner_maxit, op.maxit - its), op.precond, inner, nullptr, mv32, s);
+                k_add_from32<<<gridn(tot), TPB, 0, s>>>(X, d32.as<cx<float>>(), tot);
+                bem_apply_t<double>(*pb, X, ax.as<cx<double>>(), nrhs, s);
                 ++mv64;
-                k_sub<<<gridn(tot), TPB, 0, s>>>(b, ax.as<cx<double>>(), rr.as<cx<double>>(), tot);
+                k_sub<double><<<gridn(tot), TPB, 0, s>>>(b, ax.as<cx<double>>(), rr.as<cx<double>>(), tot);
                 FMB_LAUNCH_CHECK();
                 ++refinements;
             }
