@@ -514,6 +514,125 @@ __global__ void __launch_bounds__(TPB) k_translate(const Tile *__restrict__ tile
     }
 }
 
+// Large operators (KR > 128 rows in FP64, > 256 in FP32): block tile of
+// BG_M = 128 rows x BG_N = 128 columns, four waves in a 2 x 2 arrangement, each
+// holding 4 x 4 MFMA tiles (64 x 64).  K advances BG_K = 16 at a time; the next
+// stage's A and B elements are fetched into registers while the MFMAs run on
+// the current LDS buffer, then stored into the other buffer (one barrier per
+// stage).  A is kept row-major in LDS (pitch BG_K + 1), B k-major (pitch
+// BG_N + 1), so fragment reads and the transposing stores avoid bank conflicts.
+constexpr int BG_M = 128, BG_N = 128, BG_K = 16;
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_translate_big(const Tile *__restrict__ tiles, int ntiles,
+                                                       const int32_t *__restrict__ ent,
+                                                       const int32_t *__restrict__ src_map,
+                                                       const T *__restrict__ ops, const T *__restrict__ X,
+                                                       T *__restrict__ Y, int KR, int ncol, int64_t blkR) {
+    typedef typename Mfma<T>::v4 v4;
+    constexpr int AP = BG_K + 1, BP = BG_N + 1;
+    constexpr int LA = BG_M * BG_K / TPB, LB = BG_K * BG_N / TPB;   // elements per thread and stage
+    __shared__ T As[2][BG_M * AP];
+    __shared__ T Bs[2][BG_K * BP];
+    __shared__ int64_t s_in[BG_N], s_out[BG_N];
+    const int tix = xcd_tile(blockIdx.x, ntiles);
+    if (tix >= ntiles) return;
+    const Tile tl = tiles[tix];
+    const int r0 = blockIdx.y * BG_M;
+    const T *Top = ops + (size_t)tl.op * KR * KR;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr0 = (wave >> 1) * 64, wc0 = (wave & 1) * 64;
+    const int Ctot = tl.count * ncol;
+    const int nk = (KR + BG_K - 1) / BG_K;
+    T pa[LA], pb[LB];
+    for (int c0 = 0; c0 < Ctot; c0 += BG_N) {
+        const int C = min(BG_N, Ctot - c0);
+        __syncthreads();                                  // s_in/s_out and LDS buffers of the previous chunk
+        for (int c = threadIdx.x; c < BG_N; c += blockDim.x) {
+            if (c < C) {
+                const int cg = c0 + c;
+                const int e = cg / ncol, cc = cg % ncol;
+                const int32_t en = ent[tl.first + e];
+                const int32_t sb = src_map ? src_map[en] : en;
+                s_in[c] = (int64_t)sb * blkR + (int64_t)cc * KR;
+                s_out[c] = (int64_t)en * blkR + (int64_t)cc * KR;
+            } else {
+                s_in[c] = -1;
+                s_out[c] = -1;
+            }
+        }
+        __syncthreads();
+        auto fetch = [&](int ks) {
+            const int k0 = ks * BG_K;
+#pragma unroll
+            for (int j = 0; j < LA; ++j) {
+                const int idx = threadIdx.x + j * TPB;
+                const int r = idx / BG_K, kk = idx % BG_K;
+                pa[j] = (r0 + r < KR && k0 + kk < KR) ? Top[(size_t)(r0 + r) * KR + k0 + kk] : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < LB; ++j) {
+                const int idx = threadIdx.x + j * TPB;
+                const int c = idx / BG_K, kk = idx % BG_K;
+                const int64_t o = s_in[c];
+                pb[j] = (o >= 0 && k0 + kk < KR) ? X[o + k0 + kk] : T(0);
+            }
+        };
+        auto stash = [&](int buf) {
+#pragma unroll
+            for (int j = 0; j < LA; ++j) {
+                const int idx = threadIdx.x + j * TPB;
+                As[buf][(idx / BG_K) * AP + idx % BG_K] = pa[j];
+            }
+#pragma unroll
+            for (int j = 0; j < LB; ++j) {
+                const int idx = threadIdx.x + j * TPB;
+                Bs[buf][(idx % BG_K) * BP + idx / BG_K] = pb[j];
+            }
+        };
+        v4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = v4{0, 0, 0, 0};
+        fetch(0);
+        stash(0);
+        __syncthreads();
+        for (int ks = 0; ks < nk; ++ks) {
+            const int buf = ks & 1;
+            if (ks + 1 < nk) fetch(ks + 1);
+            const T *A = As[buf], *B = Bs[buf];
+#pragma unroll
+            for (int k4 = 0; k4 < BG_K; k4 += 4) {
+                T a[4], b[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = A[(wr0 + 16 * i + (lane & 15)) * AP + k4 + (lane >> 4)];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) b[j] = B[(k4 + (lane >> 4)) * BP + wc0 + 16 * j + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
+            }
+            if (ks + 1 < nk) stash(buf ^ 1);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = wc0 + 16 * j + (lane & 15);
+            if (col >= C) continue;
+            T *yo = Y + s_out[col];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = r0 + wr0 + 16 * i + Mfma<T>::row(lane, q);
+                    if (row < KR) yo[row] = acc[i][j][q];
+                }
+        }
+    }
+}
+
 // MI355X dispatches consecutive workgroups to its 8 XCDs in turn.  Tiles are
 // listed operator by operator; renumbering block i to tile (i % 8) * chunk + i / 8
 // gives each XCD a contiguous run of tiles, so the tiles that share an operator
@@ -686,6 +805,12 @@ __global__ void __launch_bounds__(TPB) k_translate_os(const Tile *__restrict__ t
         if (t + 1 < ntc) stash(buf ^ 1);
         __syncthreads();
     }
+}
+
+// operators with more than 128 (FP64) or 256 (FP32) real rows take k_translate_big
+inline bool use_big(int precision, int KR) {
+    const int rt = (KR + 15) / 16;
+    return !(rt <= 16 && (precision == FMB_FP32 || rt <= 8));
 }
 
 inline bool use_bf3(const Plan &P) {
@@ -892,15 +1017,16 @@ void launch_translate(const Tile *tiles, int64_t ntiles, const int32_t *ent, con
     case R:                                                                                                         \
         k_translate_fm<T, R><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, ops, X, Y, KR, ncol, blkR);        \
         break;
-    if (rt <= 16 && (sizeof(T) == 4 || rt <= 8)) {
+    if (!use_big(sizeof(T) == 4 ? FMB_FP32 : FMB_FP64, KR)) {
         switch (rt) {
             FMB_FM(1) FMB_FM(2) FMB_FM(3) FMB_FM(4) FMB_FM(5) FMB_FM(6) FMB_FM(7) FMB_FM(8)
             FMB_FM(9) FMB_FM(10) FMB_FM(11) FMB_FM(12) FMB_FM(13) FMB_FM(14) FMB_FM(15) FMB_FM(16)
             default: break;
         }
     } else {
-        const unsigned rowblocks = (unsigned)((KR + TM - 1) / TM);
-        k_translate<T><<<dim3(g, rowblocks), TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, ops, X, Y, KR, ncol, blkR);
+        const unsigned rowblocks = (unsigned)((KR + BG_M - 1) / BG_M);
+        k_translate_big<T><<<dim3(g, rowblocks), TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, ops, X, Y, KR, ncol,
+                                                             blkR);
     }
 #undef FMB_FM
     FMB_LAUNCH_CHECK();
@@ -1078,7 +1204,8 @@ void build_tiles(Plan &P, hipStream_t s) {
     // a level with little work gets shorter jobs so that it still spreads over
     // about 1024 blocks (its cost is then latency, not operator traffic).
     const bool os = use_os(P.precision, P.order, P.nrhs_max);
-    const int ep_max = os ? std::max(1, OS_MAXCOLS / (3 * P.nrhs_max)) : std::max(1, TN / (3 * P.nrhs_max));
+    const int cols = os ? OS_MAXCOLS : (use_big(P.precision, 2 * P.P2) ? BG_N : TN);
+    const int ep_max = std::max(1, cols / (3 * P.nrhs_max));
     const int ep_min = os ? std::max(1, OS_COLS / (3 * P.nrhs_max)) : ep_max;
     auto ep_for = [&](int64_t total) {
         int64_t e = total / 1024;
