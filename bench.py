@@ -33,13 +33,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--order64", type=int, default=16)
-    ap.add_argument("--order32", type=int, default=9)
+    ap.add_argument("--order32", type=int, default=5)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--inner-tol", type=float, default=2e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1500)
     ap.add_argument("--skip-fp64-solve", action="store_true")
-    ap.add_argument("--translate32", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--translate32", choices=["fp32", "bf16x3"], default="bf16x3")
     return ap.parse_args()
 
 
@@ -50,15 +50,19 @@ def log(*a):
 def m2l_flops(info, nrhs=1):
     """Algorithmic flops of the dense S|R translations of one matvec: a complex
     (p^2 x p^2) by (p^2 x 3 nrhs) product per far-field pair, 8 flops per
-    complex multiply-add."""
+    complex multiply-add, i.e. 24 p^4 per pair and right-hand side."""
     p2 = info["order"] ** 2
     pairs = sum(info["m2l_pairs"])
     return 8.0 * p2 * p2 * 3 * nrhs * pairs
 
 
-def p2p_flops(info, nrhs=1):
-    """About 110 flops per near (target, source) pair for one right-hand side."""
-    return 110.0 * info["p2p_pairs"] * nrhs
+P2P_FLOPS_PER_PAIR = 150.0   # ~45 geometry (r, 1/R, g, grad g) + ~105 per rhs; plus rsqrt, sincos, exp
+
+
+def p2p_pairs(info, n):
+    """Near (target, source) pairs the method must evaluate: the plan's count
+    less the 3 same-triangle pairs of every target (computed as masked)."""
+    return info["p2p_pairs"] - 3 * n
 
 
 def main():
@@ -108,6 +112,22 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
     solves_per_s = args.steps / dt
     last = infos[-1]
+    # one more identical solve with HIP events (on the streams the kernels run
+    # on) around the near-field and S|R translation launches of both FP32 plans;
+    # the roofline below uses their per-launch averages.  Kept out of the timed
+    # region because the events cost the solve a few per cent.
+    for p in (pb.p0_32, pb.p1_32):
+        p.profile(True, stages=("p2p", "m2l"))
+        p.profile_read(reset=True)
+    step()
+    torch.cuda.synchronize()
+    timed = {}
+    for p in (pb.p0_32, pb.p1_32):
+        for st, (ms, cnt) in p.profile_read(reset=True).items():
+            a0, c0 = timed.get(st, (0.0, 0))
+            timed[st] = (a0 + ms, c0 + cnt)
+        p.profile(False)
+    log("profiled solve: stage totals (ms, launches)", {k: v for k, v in timed.items() if v[1]})
 
     # plain FP64 solve (reference path) and matvec rates, outside the timed region
     fp64 = None
@@ -145,20 +165,31 @@ def main():
         plan.profile(False)
         log(tag, "matvec/s %.1f" % rates[tag], prof[tag])
 
-    # dominant kernel of the product path: the FP32 S|R translation stage
+    # roofline of the dominant FP32 kernel in the timed solves (both FP32 plans):
+    # the near-field kernel (VALU) or the S|R translations (matrix cores)
     inf = info32
-    m2l_ms, m2l_launches = prof["fp32"]["m2l"]
-    per_matvec_ms = m2l_ms / 10.0
-    achieved_tf = m2l_flops(inf) / (per_matvec_ms * 1e-3) / 1e12
+    mv32 = timed["p2p"][1]                      # one P2P launch per FP32 matvec
+    p2p_ms, m2l_ms = timed["p2p"][0], timed["m2l"][0]
+    p2p_fl = P2P_FLOPS_PER_PAIR * p2p_pairs(inf, n)
+    p2p_tf = p2p_fl / (p2p_ms / mv32 * 1e-3) / 1e12
+    m2l_tf = m2l_flops(inf) * mv32 / (m2l_ms * 1e-3) / 1e12
     if args.translate32 == "bf16x3":
-        kname, peak = "k_translate_bf3 (S|R, split-BF16 MFMA, FP32 accumulate)", PEAK["bf16_TF"]
+        m2l_name, m2l_peak = "k_translate_bf3 (S|R, split-BF16 MFMA, FP32 accumulate)", PEAK["bf16_TF"]
     else:
-        kname, peak = "k_translate_os (S|R, FP32 MFMA)", PEAK["fp32_TF"]
-    roofline = {"kernel": kname, "bound": "mfma",
-                "achieved": achieved_tf, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved_tf / peak, "traffic": None,
-                "per_launch_flops": m2l_flops(inf) / max(1, m2l_launches // 10),
-                "avg_launch_ms": m2l_ms / max(1, m2l_launches)}
+        m2l_name, m2l_peak = "k_translate_os (S|R, FP32 MFMA)", PEAK["fp32_TF"]
+    stages_rf = {
+        "p2p": {"kernel": "k_p2p32 (near field, FP32 VALU)", "bound": "alu", "achieved": p2p_tf,
+                "peak": PEAK["fp32_TF"], "unit": "TFLOP/s", "frac": p2p_tf / PEAK["fp32_TF"], "traffic": None,
+                "per_launch_flops": p2p_fl, "avg_launch_ms": p2p_ms / mv32, "launches": mv32,
+                "gpairs_per_s": p2p_pairs(inf, n) / (p2p_ms / mv32 * 1e-3) / 1e9},
+        "m2l": {"kernel": m2l_name, "bound": "mfma", "achieved": m2l_tf, "peak": m2l_peak, "unit": "TFLOP/s",
+                "frac": m2l_tf / m2l_peak, "traffic": None,
+                "per_launch_flops": m2l_flops(inf) * mv32 / max(1, timed["m2l"][1]),
+                "avg_launch_ms": m2l_ms / max(1, timed["m2l"][1]), "launches": timed["m2l"][1]},
+    }
+    dominant = "p2p" if p2p_ms >= m2l_ms else "m2l"
+    roofline = dict(stages_rf[dominant])
+    log("roofline", stages_rf)
 
     # accuracy against the oracle: FP64 direct-sum residual of the GPU solutions on sampled rows
     acc = None
@@ -186,7 +217,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 FMM + f64 corrections/Arnoldi/residual",
+        "dtype": "f32",
+        "precision": "FP32 FMM (split-BF16 MFMA translations with FP32 accumulation when translate_fp32 is "
+                     "bf16x3) and FP32 inner Krylov vectors; FP64 self-triangle corrections, inner products, "
+                     "Hessenberg/Givens, residuals and the refinement iterate",
         "data": "synthetic",
         "config": {"workload": "torus_R1_r0.3_20000tri_60000nodes_eps-15+1i_k0R4_depth5_planewave",
                    "nodes": n, "unknowns": 6 * n, "depth": depth, "order_fp64": args.order64,
@@ -203,6 +237,8 @@ def main():
         "plan_info_fp64": {k: info64[k] for k in ("nbox", "m2l_pairs", "p2p_pairs", "device_bytes")},
         "oracle_residual_sampled_rows": acc,
         "roofline": roofline,
+        "roofline_stages": stages_rf,
+        "profiled_solve_kernel_ms": {s: v[0] for s, v in timed.items() if v[1]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -147,8 +147,10 @@ int fmm_plan_export_tree(fmb_plan_t plan, int32_t level, uint64_t *codes, int32_
 int fmm_plan_destroy(fmb_plan_t plan);
 
 /*
- * Stage timers.  fmm_plan_profile(plan, 1) makes every later matvec on the
- * plan record HIP events around its stages on the matvec's stream;
+ * Stage timers.  fmm_plan_profile(plan, mask) makes every later matvec on the
+ * plan record HIP events around the stages whose bit (1 << stage) is set in
+ * mask, on the matvec's stream; mask = 0 turns timing off and FMB_PROFILE_ALL
+ * (or 1, kept for callers that pass a boolean) times every stage;
  * fmm_plan_profile_read synchronises on them and returns, per stage, the
  * summed kernel time in milliseconds and the number of timed launches since
  * the last read with reset = 1.  Stage order (FMB_NSTAGES = 10): gather, P2M,
@@ -158,7 +160,8 @@ int fmm_plan_destroy(fmb_plan_t plan);
  * (either may be NULL).
  */
 #define FMB_NSTAGES 10
-int fmm_plan_profile(fmb_plan_t plan, int32_t enable);
+#define FMB_PROFILE_ALL 0x3ff
+int fmm_plan_profile(fmb_plan_t plan, int32_t mask);
 int fmm_plan_profile_read(fmb_plan_t plan, double *ms, int64_t *launches, int32_t reset);
 
 /* ---------------- BEM system and solver (Secs. 2.2 and 3.1) ---------------- */

@@ -215,8 +215,16 @@ class Plan:
 
     STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "corr", "scatter", "sums")
 
-    def profile(self, enable=True):
-        check(self._lib.fmm_plan_profile(self.h, 1 if enable else 0))
+    def profile(self, enable=True, stages=None):
+        """Time stages with HIP events on later matvecs: all of them, or only
+        the names in stages (a subset of STAGES); enable=False stops timing."""
+        if not enable:
+            mask = 0
+        elif stages is None:
+            mask = (1 << len(self.STAGES)) - 1
+        else:
+            mask = sum(1 << self.STAGES.index(s) for s in stages)
+        check(self._lib.fmm_plan_profile(self.h, mask))
 
     def profile_read(self, reset=True):
         ms = np.zeros(len(self.STAGES))

@@ -12,7 +12,7 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 
 size_t Plan::device_bytes() const {
     size_t b = codes.bytes + perm.bytes + iperm.bytes + spts.bytes + snrm.bytes + sw.bytes + stri.bytes +
-               inv_alpha.bytes + point_tri.bytes + unrm.bytes + tri_nodes.bytes + corr_v.bytes + corr_g.bytes +
+               inv_alpha.bytes + btab.bytes + bgix.bytes + point_tri.bytes + unrm.bytes + tri_nodes.bytes + corr_v.bytes + corr_g.bytes +
                src.bytes + ys.bytes + ybuf.bytes;
     for (const Level &V : lv)
         b += V.keys.bytes + V.start.bytes + V.parent.bytes + V.center.bytes + V.nbr.bytes + V.child_start.bytes +
@@ -206,10 +206,10 @@ int fmm_plan_export_tree(fmb_plan_t plan, int32_t level, uint64_t *codes, int32_
     });
 }
 
-int fmm_plan_profile(fmb_plan_t plan, int32_t enable) {
+int fmm_plan_profile(fmb_plan_t plan, int32_t mask) {
     return guarded([&] {
         FMB_REQUIRE(plan != nullptr, "plan is NULL");
-        plan->p.timer.on = enable != 0;
+        plan->p.timer.mask = (mask == 1) ? FMB_PROFILE_ALL : (uint32_t)mask & FMB_PROFILE_ALL;
     });
 }
 

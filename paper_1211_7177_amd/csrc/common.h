@@ -165,20 +165,31 @@ __device__ inline float fast_rsqrt(float x) { return rsqrtf(x); }
 // satisfies r_n = z / (2n + 1 - z r_{n+1}); started far above N with r = 0 it
 // is stable for every z, including z -> 0 where r_n -> z/(2n+1).  Then
 // j_0 = sin z / z (series for small |z|) and j_n = j_{n-1} r_n.
+// z / den for the ratio recurrence (|den| >= 1 there, no scaling needed):
+// FP32 uses the hardware reciprocal.
+__device__ inline cx<double> cdiv_ratio(cx<double> a, cx<double> b) { return cdiv(a, b); }
+__device__ inline cx<float> cdiv_ratio(cx<float> a, cx<float> b) {
+    const float inv = __builtin_amdgcn_rcpf(b.re * b.re + b.im * b.im);
+    return mk((a.re * b.re + a.im * b.im) * inv, (a.im * b.re - a.re * b.im) * inv);
+}
+
 template <typename T>
-__host__ __device__ inline void sph_bessel_j(cx<T> z, int N, cx<T> *out) {
+__device__ inline void sph_bessel_j(cx<T> z, int N, cx<T> *out) {
     const T az = (T)sqrt(abs2(z));
     if (az < T(1e-30)) {
         out[0] = mk(T(1), T(0));
         for (int n = 1; n <= N; ++n) out[n] = mk(T(0), T(0));
         return;
     }
-    int start = N + 16 + (int)az;
+    // FP32 needs fewer extra terms: the neglected tail scales like the product
+    // of |z / (2n + 1)|^2 over the skipped degrees
+    const int extra = sizeof(T) == sizeof(float) ? 8 + (int)(T(1.2) * az) : 16 + (int)az;
+    const int start = N + extra;
     cx<T> r = mk(T(0), T(0));
     // walk down from `start`, store ratios for n <= N in out[] temporarily
     for (int n = start; n >= 1; --n) {
         cx<T> den = mk(T(2 * n + 1), T(0)) - z * r;
-        r = cdiv(z, den);
+        r = cdiv_ratio(z, den);
         if (n <= N) out[n] = r;
     }
     cx<T> j0;

@@ -62,30 +62,50 @@ __global__ void k_scatter_out(const cx<T> *__restrict__ ys, const int32_t *__res
 }
 
 // ---------------------------------------------------------------- basis
-// R_n^m(d) for n <= N (all m) of one point into out[(N+1)^2]: thread-cooperative.
-// jb: j_0..j_N at k|d|.  Called by `nthr` threads with ids 0..nthr-1.
+// Recurrence constants of the normalised associated Legendre functions and of
+// the gradient of R_n^m, tabulated on the host at plan time (BasisTab layout
+// below) so that the per-node loops carry no square roots or divisions.
+//   Q_m^m = qmm[m],  Q_{m+1}^m = q1[m] x Q_m^m,
+//   Q_n^m = la[n][m] (x Q_{n-1}^m - lb[n][m] Q_{n-2}^m)            (n >= m + 2)
 template <typename T>
-__device__ inline void regular_column(const double d[3], const cx<T> *jb, int N, int m, cx<T> *out) {
-    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    const T x = r > 0 ? (T)(d[2] / r) : T(1);
-    cx<T> w = r > 0 ? mk((T)(d[0] / r), (T)(d[1] / r)) : mk(T(0), T(0));
-    T qmm = T(0.28209479177387814347);   // 1/sqrt(4 pi)
+struct BasisTab {
+    const T *la, *lb, *qmm, *q1;     // [(N+1)^2] (row n, column m), [(N+1)^2], [N+1], [N+1]
+    const T *gco;                    // [P2][6] gradient coefficients of coefficient idx (mu = -m)
+    const int32_t *gix;              // [P2][7] R-table indices of the six gradient terms and of R_n^{-m}
+    int N;
+};
+
+template <typename T>
+__device__ inline BasisTab<T> basis_tab(const T *tab, const int32_t *gix, int N, int P2) {
+    BasisTab<T> b;
+    const int NN = (N + 1) * (N + 1);
+    b.la = tab;
+    b.lb = tab + NN;
+    b.qmm = tab + 2 * NN;
+    b.q1 = tab + 2 * NN + (N + 1);
+    b.gco = tab + 2 * NN + 2 * (N + 1);
+    b.gix = gix;
+    b.N = N;
+    (void)P2;
+    return b;
+}
+
+// R_n^m(d) for n <= N, one order m, of one point into out[(N+1)^2]; jb holds
+// j_0..j_N at k|d|.
+// x = cos th, w = sin th e^{i ph} of the point's direction from the centre.
+template <typename T>
+__device__ inline void regular_column(T x, cx<T> w, const cx<T> *jb, const BasisTab<T> &bt, int m, cx<T> *out) {
+    const int N = bt.N;
+    const T qmm = bt.qmm[m];
     cx<T> wm = mk(T(1), T(0));
-    for (int i = 1; i <= m; ++i) {
-        qmm *= sqrt(T(2 * i + 1) / T(2 * i));
-        wm = wm * w;
-    }
+    for (int i = 1; i <= m; ++i) wm = wm * w;
     const T sgn = (m & 1) ? T(-1) : T(1);
     T q2 = 0, q1 = qmm;
     for (int n = m; n <= N; ++n) {
         T q;
         if (n == m) q = qmm;
-        else if (n == m + 1) q = sqrt(T(2 * m + 3)) * x * qmm;
-        else {
-            T a = sqrt(T(4 * n * n - 1) / T(n * n - m * m));
-            T b = sqrt(T((n - 1) * (n - 1) - m * m) / T(4 * (n - 1) * (n - 1) - 1));
-            q = a * (x * q1 - b * q2);
-        }
+        else if (n == m + 1) q = bt.q1[m] * x * qmm;
+        else q = bt.la[n * (N + 1) + m] * (x * q1 - bt.lb[n * (N + 1) + m] * q2);
         if (n > m) {
             q2 = q1;
             q1 = q;
@@ -96,102 +116,100 @@ __device__ inline void regular_column(const double d[3], const cx<T> *jb, int N,
     }
 }
 
-template <typename T>
-__device__ inline cx<T> Rget(const cx<T> *R, int N, int n, int m) {
-    if (n < 0 || n > N || m > n || m < -n) return mk(T(0), T(0));
-    return R[n * n + n + m];
-}
-
-// gradient of R_n^mu from the table R (degrees <= n+1)
-template <typename T>
-__device__ inline void grad_regular(const cx<T> *R, int N, cx<T> k, int n, int mu, cx<T> g[3]) {
-    const int am = mu < 0 ? -mu : mu;
-    const T A = sqrt(T((n + 1 - am) * (n + 1 + am)) / T((2 * n + 1) * (2 * n + 3)));
-    const T B = n > 0 ? sqrt(T((n - am) * (n + am)) / T((2 * n - 1) * (2 * n + 1))) : T(0);
-    cx<T> dz = k * (-A * Rget(R, N, n + 1, mu) + B * Rget(R, N, n - 1, mu));
-    const T c1 = -sqrt(T((n + mu + 1) * (n + mu + 2)) / T((2 * n + 1) * (2 * n + 3)));
-    const T d1 = n > 0 && (n - mu) * (n - mu - 1) > 0 ? sqrt(T((n - mu) * (n - mu - 1)) / T((2 * n - 1) * (2 * n + 1))) : T(0);
-    const T su = mu >= 0 ? T(1) : T(-1);
-    cx<T> dp = k * (-(su * c1) * Rget(R, N, n + 1, mu + 1) + (su * d1) * Rget(R, N, n - 1, mu + 1));
-    const T e1 = sqrt(T((n - mu + 1) * (n - mu + 2)) / T((2 * n + 1) * (2 * n + 3)));
-    const T f1 = n > 0 && (n + mu) * (n + mu - 1) > 0 ? -sqrt(T((n + mu) * (n + mu - 1)) / T((2 * n - 1) * (2 * n + 1))) : T(0);
-    const T sd = mu > 0 ? T(1) : T(-1);
-    cx<T> dm = k * (-(sd * e1) * Rget(R, N, n + 1, mu - 1) + (sd * f1) * Rget(R, N, n - 1, mu - 1));
-    g[0] = T(0.5) * (dp + dm);
-    cx<T> df = dp - dm;                       // = 2 i d_y
-    g[1] = mk(T(0.5) * df.im, T(-0.5) * df.re);
-    g[2] = dz;
-}
-
 // ---------------------------------------------------------------- P2M
 // One block per leaf.  For a batch of the leaf's nodes the block first builds
-// the table R_n^m(s - X), n <= p, in LDS (one thread per (node, m) column),
-// then G = blockDim / p^2 thread groups each take every G-th node of the
-// batch and accumulate all three channels of one coefficient; the groups are
-// summed in LDS at the end (fixed order, so the result is deterministic).
+// the table R_n^m(s - X), n <= p, in LDS (one thread per (node, m) column;
+// entry (p+1)^2 of each node's table is a zero that stands for the terms the
+// gradient recurrence lacks), then G = blockDim / p^2 thread groups each take
+// every G-th node of the batch and accumulate all three channels of one
+// coefficient; the groups are summed in LDS at the end (fixed order, so the
+// result is deterministic).  The gradient of R_n^{-m} is
+//   d_z = k (c0 R[i0] + c1 R[i1]),  d_+ = k (c2 R[i2] + c3 R[i3]),  d_- = k (c4 R[i4] + c5 R[i5]),
+//   grad = ((d_+ + d_-) / 2, (d_+ - d_-) / 2i, d_z),
+// with coefficients and indices from the plan's table; k multiplies the whole
+// gradient part once per coefficient after the node loop.
 constexpr int P2M_SLOTS = 3;     // coefficients per thread when p^2 > blockDim
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, const double *__restrict__ center,
                                              const double *__restrict__ spts, const double *__restrict__ snrm,
                                              const cx<T> *__restrict__ src, int64_t n, int p, double k_re, double k_im,
-                                             const double *__restrict__ inv_alpha, int nrhs_max, int batch,
+                                             const double *__restrict__ inv_alpha, const T *__restrict__ tab,
+                                             const int32_t *__restrict__ gix, int nrhs_max, int batch,
                                              cx<T> *__restrict__ M) {
     extern __shared__ unsigned char smem[];
     const int N = p;                                  // degrees 0..p for the gradients
     const int NN = (N + 1) * (N + 1);
-    cx<T> *Rb = reinterpret_cast<cx<T> *>(smem);                        // [batch][NN]
-    cx<T> *jb = Rb + batch * NN;                                        // [batch][N+1]
-    double *dd = reinterpret_cast<double *>(jb + batch * (N + 1));      // [batch][3]
+    const int NT = NN + 1;                            // per-node table incl. the zero entry
+    const int P2 = p * p;
+    const BasisTab<T> bt = basis_tab(tab, gix, N, P2);
+    cx<T> *Rb = reinterpret_cast<cx<T> *>(smem);                        // [batch][NT]
+    cx<T> *jb = Rb + batch * NT;                                        // [batch][N+1]
+    cx<T> *sv = jb + batch * (N + 1);                                   // [batch][7] node densities
+    T *dd = reinterpret_cast<T *>(sv + batch * 7);                      // [batch][3] cos th, sin th e^{i ph}
+    T *nvs = dd + batch * 3;                                            // [batch][3] normals
     const int box = blockIdx.x, r = blockIdx.y;
     const int s0 = start[box], s1 = start[box + 1];
     const double X[3] = {center[3 * box], center[3 * box + 1], center[3 * box + 2]};
     const cx<T> k = mk((T)k_re, (T)k_im);
-    const int P2 = p * p;
     const int G = P2 <= (int)blockDim.x ? (int)blockDim.x / P2 : 1;   // node groups
     const int grp = P2 <= (int)blockDim.x ? (int)threadIdx.x / P2 : 0;
-    cx<T> acc[P2M_SLOTS][3];
+    cx<T> accb[P2M_SLOTS][3], accg[P2M_SLOTS][3];
     for (int u = 0; u < P2M_SLOTS; ++u)
-        for (int c = 0; c < 3; ++c) acc[u][c] = mk(T(0), T(0));
+        for (int c = 0; c < 3; ++c) accb[u][c] = accg[u][c] = mk(T(0), T(0));
     for (int b0 = s0; b0 < s1; b0 += batch) {
         const int nb = min(batch, s1 - b0);
         for (int t = threadIdx.x; t < nb; t += blockDim.x) {
             const int i = b0 + t;
             double d[3];
             for (int q = 0; q < 3; ++q) d[q] = spts[3 * (int64_t)i + q] - X[q];
-            for (int q = 0; q < 3; ++q) dd[t * 3 + q] = d[q];
             const double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            const double ir = rr > 0 ? 1.0 / rr : 0.0;
+            dd[t * 3] = rr > 0 ? (T)(d[2] * ir) : T(1);
+            dd[t * 3 + 1] = (T)(d[0] * ir);
+            dd[t * 3 + 2] = (T)(d[1] * ir);
             sph_bessel_j(mk((T)(k_re * rr), (T)(k_im * rr)), N, jb + t * (N + 1));
+            Rb[t * NT + NN] = mk(T(0), T(0));
+            const cx<T> *sr = src + ((int64_t)r * n + i) * 7;
+            for (int q = 0; q < 7; ++q) sv[t * 7 + q] = sr[q];
+            for (int q = 0; q < 3; ++q) nvs[t * 3 + q] = (T)snrm[3 * (int64_t)i + q];
         }
         __syncthreads();
         for (int t = threadIdx.x; t < nb * (N + 1); t += blockDim.x) {
             const int i = t / (N + 1), m = t % (N + 1);
-            const double d[3] = {dd[3 * i], dd[3 * i + 1], dd[3 * i + 2]};
-            regular_column<T>(d, jb + i * (N + 1), N, m, Rb + i * NN);
+            regular_column<T>(dd[3 * i], mk(dd[3 * i + 1], dd[3 * i + 2]), jb + i * (N + 1), bt, m, Rb + i * NT);
         }
         __syncthreads();
         for (int u = 0; u < P2M_SLOTS; ++u) {
             const int idx = (G > 1) ? ((int)threadIdx.x % P2) : (int)threadIdx.x + u * (int)blockDim.x;
             if (idx >= P2 || grp >= G || (G > 1 && u > 0)) break;
-            int nn = 0;
-            while ((nn + 1) * (nn + 1) <= idx) ++nn;
-            const int mm = idx - nn * nn - nn;
+            int ix[7];
+            T co[6];
+            for (int q = 0; q < 7; ++q) ix[q] = bt.gix[idx * 7 + q];
+            for (int q = 0; q < 6; ++q) co[q] = bt.gco[idx * 6 + q];
             for (int i = grp; i < nb; i += G) {
-                const int64_t pi = b0 + i;
-                const cx<T> *R = Rb + i * NN;
-                const cx<T> Rv = Rget(R, N, nn, -mm);            // R_n^{-m}
-                cx<T> g[3];
-                grad_regular(R, N, k, nn, -mm, g);
-                const cx<T> *sr = src + ((int64_t)r * n + pi) * 7;
-                const T nv[3] = {(T)snrm[3 * pi], (T)snrm[3 * pi + 1], (T)snrm[3 * pi + 2]};
+                const cx<T> *R = Rb + i * NT;
+                const cx<T> Rv = R[ix[6]];                                  // R_n^{-m}
+                const cx<T> dz = co[0] * R[ix[0]] + co[1] * R[ix[1]];
+                const cx<T> dp = co[2] * R[ix[2]] + co[3] * R[ix[3]];
+                const cx<T> dm = co[4] * R[ix[4]] + co[5] * R[ix[5]];
+                const cx<T> df = dp - dm;
+                const cx<T> g[3] = {T(0.5) * (dp + dm), mk(T(0.5) * df.im, T(-0.5) * df.re), dz};   // grad / k
+                const cx<T> *sr = sv + i * 7;
+                const T nv[3] = {nvs[3 * i], nvs[3 * i + 1], nvs[3 * i + 2]};
                 const cx<T> aG = sr[0] * g[0] + sr[1] * g[1] + sr[2] * g[2];
                 const cx<T> nG = nv[0] * g[0] + nv[1] * g[1] + nv[2] * g[2];
-                for (int c = 0; c < 3; ++c)
-                    acc[u][c] += sr[3 + c] * Rv + nv[c] * aG - sr[c] * nG - sr[6] * g[c];
+                for (int c = 0; c < 3; ++c) {
+                    accb[u][c] += sr[3 + c] * Rv;
+                    accg[u][c] += nv[c] * aG - sr[c] * nG - sr[6] * g[c];
+                }
             }
         }
         __syncthreads();
     }
+    cx<T> acc[P2M_SLOTS][3];
+    for (int u = 0; u < P2M_SLOTS; ++u)
+        for (int c = 0; c < 3; ++c) acc[u][c] = accb[u][c] + k * accg[u][c];
     if (G > 1) {
         // sum the node groups in LDS (reuses the table area)
         cx<T> *red = Rb;                                   // [G][P2][3]
@@ -226,10 +244,11 @@ __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, 
 template <typename T>
 __global__ void __launch_bounds__(64) k_l2p(const int32_t *__restrict__ start, const double *__restrict__ center,
                                             const double *__restrict__ spts, int64_t n, int p, double k_re, double k_im,
-                                            const double *__restrict__ inv_alpha, int nrhs_max,
-                                            const cx<T> *__restrict__ Lc, cx<T> *__restrict__ ys) {
+                                            const double *__restrict__ inv_alpha, const T *__restrict__ tab,
+                                            int nrhs_max, const cx<T> *__restrict__ Lc, cx<T> *__restrict__ ys) {
     extern __shared__ unsigned char smem[];
     const int P2 = p * p;
+    const BasisTab<T> bt = basis_tab(tab, (const int32_t *)nullptr, p, P2);
     cx<T> *Ls = reinterpret_cast<cx<T> *>(smem);        // [3][P2]
     cx<T> *jb = Ls + 3 * P2;                             // [64][p]
     const int box = blockIdx.x, r = blockIdx.y;
@@ -246,29 +265,23 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *__restrict__ start, c
         double d[3];
         for (int q = 0; q < 3; ++q) d[q] = spts[3 * (int64_t)i + q] - X[q];
         const double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const double ir = rr > 0 ? 1.0 / rr : 0.0;
         cx<T> *J = jb + threadIdx.x * p;
         sph_bessel_j(mk((T)(k_re * rr), (T)(k_im * rr)), p - 1, J);
-        const T x = rr > 0 ? (T)(d[2] / rr) : T(1);
-        const cx<T> w = rr > 0 ? mk((T)(d[0] / rr), (T)(d[1] / rr)) : mk(T(0), T(0));
+        const T x = rr > 0 ? (T)(d[2] * ir) : T(1);
+        const cx<T> w = mk((T)(d[0] * ir), (T)(d[1] * ir));
         cx<T> acc[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
-        T qmm = T(0.28209479177387814347);
         cx<T> wm = mk(T(1), T(0));
         for (int m = 0; m < p; ++m) {
-            if (m > 0) {
-                qmm *= sqrt(T(2 * m + 1) / T(2 * m));
-                wm = wm * w;
-            }
+            if (m > 0) wm = wm * w;
+            const T qmm = bt.qmm[m];
             const T sgn = (m & 1) ? T(-1) : T(1);
             T q2 = 0, q1 = qmm;
             for (int nn = m; nn < p; ++nn) {
                 T q;
                 if (nn == m) q = qmm;
-                else if (nn == m + 1) q = sqrt(T(2 * m + 3)) * x * qmm;
-                else {
-                    T a = sqrt(T(4 * nn * nn - 1) / T(nn * nn - m * m));
-                    T b = sqrt(T((nn - 1) * (nn - 1) - m * m) / T(4 * (nn - 1) * (nn - 1) - 1));
-                    q = a * (x * q1 - b * q2);
-                }
+                else if (nn == m + 1) q = bt.q1[m] * x * qmm;
+                else q = bt.la[nn * (bt.N + 1) + m] * (x * q1 - bt.lb[nn * (bt.N + 1) + m] * q2);
                 if (nn > m) {
                     q2 = q1;
                     q1 = q;
@@ -396,6 +409,134 @@ __global__ void __launch_bounds__(TPB) k_p2p(const int32_t *__restrict__ start, 
             for (int q = 0; q < S; ++q)
                 for (int c = 0; c < 3; ++c) s[c] += red[q * ntc + threadIdx.x][c];
             cx<T> *o = ys + ((int64_t)r * n + t0 + tc0 + threadIdx.x) * 3;
+            for (int c = 0; c < 3; ++c) o[c] += s[c];
+        }
+    }
+}
+
+// FP32 near field.  Source records are packed into six 16-byte LDS words per
+// source: position relative to the target leaf's centre (FP32; the leaf and its
+// neighbours span a few leaf widths, so the difference keeps FP32 relative
+// accuracy) with the triangle id, the normal, and the seven density values.
+// The transcendentals go straight to the hardware units with the scale folded
+// into the constants: v_sin/v_cos take revolutions (kR / 2 pi), v_exp takes a
+// base-2 exponent (-Im k R log2 e); the LOSSY = false instance (real k) skips
+// the decay factor.  Same-triangle pairs are masked, not branched around, so
+// the source loop unrolls.
+struct __attribute__((aligned(16))) SrcRec32 {
+    float x, y, z;
+    int32_t tri;
+    float nx, ny, nz, pad;
+    cx<float> rec[8];                      // a[3], b[3], n.a, unused
+};
+
+template <bool LOSSY>
+__global__ void __launch_bounds__(TPB) k_p2p32(const int32_t *__restrict__ start, const int32_t *__restrict__ nbr,
+                                               const double *__restrict__ center, const double *__restrict__ spts,
+                                               const double *__restrict__ snrm, const int32_t *__restrict__ stri,
+                                               const cx<float> *__restrict__ src, int64_t n, double k_re,
+                                               double k_im, cx<float> *__restrict__ ys) {
+    __shared__ SrcRec32 tile[P2P_TILE];
+    __shared__ int32_t nb_start[28], nb_box[27];
+    __shared__ int n_nb;
+    __shared__ cx<float> red[TPB][3];
+    const int box = blockIdx.x, r = blockIdx.y;
+    const int t0 = start[box], t1 = start[box + 1];
+    const int nt = t1 - t0;
+    const double c0x = center[3 * box], c0y = center[3 * box + 1], c0z = center[3 * box + 2];
+    if (threadIdx.x == 0) {
+        int c = 0, tot = 0;
+        for (int s = 0; s < 27; ++s) {
+            int q = nbr[box * 27 + s];
+            if (q >= 0) {
+                nb_box[c] = q;
+                nb_start[c] = tot;
+                tot += start[q + 1] - start[q];
+                ++c;
+            }
+        }
+        nb_start[c] = tot;
+        n_nb = c;
+    }
+    __syncthreads();
+    const int ns_total = nb_start[n_nb];
+    const float krev = (float)(k_re * 0.15915494309189533577);        // k_re / (2 pi)
+    const float kexp = (float)(-k_im * 1.44269504088896340736);       // -k_im log2(e)
+    const float kr = (float)k_re, ki = (float)k_im;
+    const float inv4pi = 0.07957747154594766788f;
+    for (int tc0 = 0; tc0 < nt; tc0 += TPB) {
+        const int ntc = min(TPB, nt - tc0);
+        const int S = TPB / ntc;
+        const int ti = threadIdx.x % ntc, sl = threadIdx.x / ntc;
+        const bool active = sl < S;
+        const int64_t ig = t0 + tc0 + ti;
+        float tx = 0.f, ty = 0.f, tz = 0.f;
+        int32_t ttri = -1;
+        if (active) {
+            tx = (float)(spts[3 * ig] - c0x);
+            ty = (float)(spts[3 * ig + 1] - c0y);
+            tz = (float)(spts[3 * ig + 2] - c0z);
+            ttri = stri[ig];
+        }
+        cx<float> acc[3] = {mk(0.f, 0.f), mk(0.f, 0.f), mk(0.f, 0.f)};
+        for (int base = 0; base < ns_total; base += P2P_TILE) {
+            const int cnt = min(P2P_TILE, ns_total - base);
+            __syncthreads();
+            for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
+                const int u = base + j;
+                int b = 0;
+                while (nb_start[b + 1] <= u) ++b;
+                const int64_t sidx = start[nb_box[b]] + (u - nb_start[b]);
+                SrcRec32 q;
+                q.x = (float)(spts[3 * sidx] - c0x);
+                q.y = (float)(spts[3 * sidx + 1] - c0y);
+                q.z = (float)(spts[3 * sidx + 2] - c0z);
+                q.tri = stri[sidx];
+                q.nx = (float)snrm[3 * sidx];
+                q.ny = (float)snrm[3 * sidx + 1];
+                q.nz = (float)snrm[3 * sidx + 2];
+                q.pad = 0.f;
+                const cx<float> *sr = src + ((int64_t)r * n + sidx) * 7;
+                for (int w = 0; w < 7; ++w) q.rec[w] = sr[w];
+                q.rec[7] = mk(0.f, 0.f);
+                tile[j] = q;
+            }
+            __syncthreads();
+            if (!active) continue;
+#pragma unroll 2
+            for (int j = sl; j < cnt; j += S) {
+                const SrcRec32 &q = tile[j];
+                const bool self = q.tri == ttri;
+                const float dx = q.x - tx, dy = q.y - ty, dz = q.z - tz;
+                const float R2 = self ? 1.f : dx * dx + dy * dy + dz * dz;
+                const float iR = __builtin_amdgcn_rsqf(R2);
+                const float R = R2 * iR;
+                const float sn = __builtin_amdgcn_sinf(krev * R), cs = __builtin_amdgcn_cosf(krev * R);
+                const float ex = LOSSY ? __builtin_amdgcn_exp2f(kexp * R) : 1.f;   // real k: no decay
+                const float sc = self ? 0.f : inv4pi * iR * ex;            // e^{-Im k R} / (4 pi R)
+                const cx<float> g = mk(sc * cs, sc * sn);                   // e^{ikR} / (4 pi R)
+                const float iR2 = iR * iR;
+                // f = (i k R - 1) g / R^2
+                const cx<float> f = mk(iR2 * ((-ki * R - 1.f) * g.re - kr * R * g.im),
+                                       iR2 * ((-ki * R - 1.f) * g.im + kr * R * g.re));
+                const float v = q.nx * dx + q.ny * dy + q.nz * dz;
+                const cx<float> u = dx * q.rec[0] + dy * q.rec[1] + dz * q.rec[2];
+                const cx<float> wx = q.nx * u - v * q.rec[0] - dx * q.rec[6];
+                const cx<float> wy = q.ny * u - v * q.rec[1] - dy * q.rec[6];
+                const cx<float> wz = q.nz * u - v * q.rec[2] - dz * q.rec[6];
+                acc[0] += f * wx + g * q.rec[3];
+                acc[1] += f * wy + g * q.rec[4];
+                acc[2] += f * wz + g * q.rec[5];
+            }
+        }
+        __syncthreads();
+        for (int c = 0; c < 3; ++c) red[threadIdx.x][c] = acc[c];
+        __syncthreads();
+        if (threadIdx.x < ntc) {
+            cx<float> s[3] = {mk(0.f, 0.f), mk(0.f, 0.f), mk(0.f, 0.f)};
+            for (int q = 0; q < S; ++q)
+                for (int c = 0; c < 3; ++c) s[c] += red[q * ntc + threadIdx.x][c];
+            cx<float> *o = ys + ((int64_t)r * n + t0 + tc0 + threadIdx.x) * 3;
             for (int c = 0; c < 3; ++c) o[c] += s[c];
         }
     }
@@ -1110,7 +1251,7 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
     Level &LL = P.lv[L];
     {
         const int N = p;
-        const size_t per = (size_t)(N + 1) * (N + 2) * sizeof(cx<T>) + 3 * sizeof(double);
+        const size_t per = ((size_t)(N + 1) * (N + 2) + 1 + 7) * sizeof(cx<T>) + 6 * sizeof(T);
         const int batch = (int)std::max<size_t>(1, std::min<size_t>(64, 60000 / per));
         // the group reduction reuses the table: it needs G * P2 * 3 complex values
         const int G = P2 <= TPB ? TPB / P2 : 1;
@@ -1118,7 +1259,8 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
         tm.begin(ST_P2M, s, ev);
         k_p2m<T><<<dim3((unsigned)LL.nbox, nrhs), TPB, sh, s>>>(
             LL.start.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(), P.snrm.as<double>(), src, n, p, P.k_re,
-            P.k_im, P.inv_alpha.as<double>() + (size_t)L * p, P.nrhs_max, batch, LL.M.as<cx<T>>());
+            P.k_im, P.inv_alpha.as<double>() + (size_t)L * p, P.btab.as<T>(), P.bgix.as<int32_t>(), P.nrhs_max,
+            batch, LL.M.as<cx<T>>());
         FMB_LAUNCH_CHECK();
         tm.end(ST_P2M, s, ev);
     }
@@ -1168,12 +1310,19 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
         tm.begin(ST_L2P, s, ev);
         k_l2p<T><<<dim3((unsigned)LL.nbox, nrhs), 64, sh, s>>>(LL.start.as<int32_t>(), LL.center.as<double>(),
                                                                P.spts.as<double>(), n, p, P.k_re, P.k_im,
-                                                               P.inv_alpha.as<double>() + (size_t)L * p, P.nrhs_max,
+                                                               P.inv_alpha.as<double>() + (size_t)L * p,
+                                                               P.btab.as<T>(), P.nrhs_max,
                                                                LL.L.as<cx<T>>(), ys);
         FMB_LAUNCH_CHECK();
         tm.end(ST_L2P, s, ev);
     }
     tm.begin(ST_P2P, s, ev);
+    if (sizeof(T) == sizeof(float)) {
+        auto kern = P.k_im != 0.0 ? k_p2p32<true> : k_p2p32<false>;
+        kern<<<dim3((unsigned)LL.nbox, nrhs), TPB, 0, s>>>(
+            LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(),
+            P.snrm.as<double>(), P.stri.as<int32_t>(), (const cx<float> *)src, n, P.k_re, P.k_im, (cx<float> *)ys);
+    } else
     k_p2p<T><<<dim3((unsigned)LL.nbox, nrhs), TPB, 0, s>>>(LL.start.as<int32_t>(), LL.nbr.as<int32_t>(),
                                                           P.spts.as<double>(), P.snrm.as<double>(), P.stri.as<int32_t>(),
                                                           src, n, P.k_re, P.k_im, ys);
@@ -1286,14 +1435,13 @@ hipEvent_t StageTimer::get() {
 }
 
 void StageTimer::begin(int st, hipStream_t s, hipEvent_t &e0) {
-    (void)st;
-    if (!on) return;
+    if (!(mask >> st & 1u)) return;
     e0 = get();
     FMB_CHECK_HIP(hipEventRecord(e0, s));
 }
 
 void StageTimer::end(int st, hipStream_t s, hipEvent_t e0) {
-    if (!on) return;
+    if (!(mask >> st & 1u)) return;
     hipEvent_t e1 = get();
     FMB_CHECK_HIP(hipEventRecord(e1, s));
     pending[st].push_back({e0, e1});

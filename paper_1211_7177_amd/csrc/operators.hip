@@ -227,6 +227,75 @@ __global__ void k_build_op(OpDesc const *__restrict__ descs, int p, double k_re,
 
 }  // namespace
 
+// Recurrence constants for the basis kernels (P2M, L2P), N = order:
+//   la[n][m] = sqrt((4n^2 - 1) / (n^2 - m^2)), lb[n][m] = sqrt(((n-1)^2 - m^2) / (4(n-1)^2 - 1))  (n >= m + 2),
+//   qmm[m] = Q_m^m / (sin th)^m = (4 pi)^{-1/2} prod_{i <= m} sqrt((2i + 1) / 2i),  q1[m] = sqrt(2m + 3),
+// then, per coefficient idx = n^2 + n + m (n < order) with mu = -m, the six
+// coefficients and R-table indices of the gradient recurrences
+//   d_z R_n^mu = k (-A R_{n+1}^mu + B R_{n-1}^mu)
+//   d_+ R_n^mu = k s_u (-c R_{n+1}^{mu+1} + d R_{n-1}^{mu+1})    (s_u = sign of mu, +1 at 0)
+//   d_- R_n^mu = k s_d (-e R_{n+1}^{mu-1} + f R_{n-1}^{mu-1})    (s_d = +1 for mu > 0, else -1)
+// and the index of R_n^mu itself; terms outside 0 <= n <= N, |mu| <= n point
+// at the zero entry (N+1)^2.
+void build_basis_tables(Plan &P, hipStream_t s) {
+    const int N = P.order, NN = (N + 1) * (N + 1), P2 = P.order * P.order;
+    std::vector<double> t((size_t)2 * NN + 2 * (N + 1) + (size_t)6 * P2, 0.0);
+    double *la = t.data(), *lb = la + NN, *qmm = lb + NN, *q1 = qmm + (N + 1), *gco = q1 + (N + 1);
+    for (int m = 0; m <= N; ++m)
+        for (int n = m + 2; n <= N; ++n) {
+            la[n * (N + 1) + m] = std::sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
+            lb[n * (N + 1) + m] = std::sqrt(((double)(n - 1) * (n - 1) - (double)m * m) / (4.0 * (n - 1) * (n - 1) - 1.0));
+        }
+    qmm[0] = 0.28209479177387814347;
+    for (int m = 1; m <= N; ++m) qmm[m] = qmm[m - 1] * std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+    for (int m = 0; m <= N; ++m) q1[m] = std::sqrt(2.0 * m + 3.0);
+    std::vector<int32_t> gix((size_t)7 * P2);
+    auto at = [&](int n, int mu) { return (n < 0 || n > N || mu > n || mu < -n) ? NN : n * n + n + mu; };
+    for (int idx = 0; idx < P2; ++idx) {
+        int n = 0;
+        while ((n + 1) * (n + 1) <= idx) ++n;
+        const int mu = -(idx - n * n - n);
+        const int am = mu < 0 ? -mu : mu;
+        const double A = std::sqrt((double)(n + 1 - am) * (n + 1 + am) / ((2.0 * n + 1) * (2.0 * n + 3)));
+        const double B = n > 0 ? std::sqrt((double)(n - am) * (n + am) / ((2.0 * n - 1) * (2.0 * n + 1))) : 0.0;
+        const double c = -std::sqrt((double)(n + mu + 1) * (n + mu + 2) / ((2.0 * n + 1) * (2.0 * n + 3)));
+        const double d = (n > 0 && (n - mu) * (n - mu - 1) > 0)
+                             ? std::sqrt((double)(n - mu) * (n - mu - 1) / ((2.0 * n - 1) * (2.0 * n + 1)))
+                             : 0.0;
+        const double e = std::sqrt((double)(n - mu + 1) * (n - mu + 2) / ((2.0 * n + 1) * (2.0 * n + 3)));
+        const double f = (n > 0 && (n + mu) * (n + mu - 1) > 0)
+                             ? -std::sqrt((double)(n + mu) * (n + mu - 1) / ((2.0 * n - 1) * (2.0 * n + 1)))
+                             : 0.0;
+        const double su = mu >= 0 ? 1.0 : -1.0, sd = mu > 0 ? 1.0 : -1.0;
+        double *g = gco + (size_t)6 * idx;
+        g[0] = -A;
+        g[1] = B;
+        g[2] = -su * c;
+        g[3] = su * d;
+        g[4] = -sd * e;
+        g[5] = sd * f;
+        int32_t *ix = gix.data() + (size_t)7 * idx;
+        ix[0] = at(n + 1, mu);
+        ix[1] = at(n - 1, mu);
+        ix[2] = at(n + 1, mu + 1);
+        ix[3] = at(n - 1, mu + 1);
+        ix[4] = at(n + 1, mu - 1);
+        ix[5] = at(n - 1, mu - 1);
+        ix[6] = at(n, mu);
+    }
+    if (P.precision == FMB_FP64) {
+        P.btab.alloc(t.size() * sizeof(double));
+        FMB_CHECK_HIP(hipMemcpyAsync(P.btab.p, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    } else {
+        std::vector<float> tf(t.begin(), t.end());
+        P.btab.alloc(tf.size() * sizeof(float));
+        FMB_CHECK_HIP(hipMemcpyAsync(P.btab.p, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    }
+    P.bgix.alloc(gix.size() * sizeof(int32_t));
+    FMB_CHECK_HIP(hipMemcpyAsync(P.bgix.p, gix.data(), gix.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    FMB_CHECK_HIP(hipStreamSynchronize(s));
+}
+
 void build_operators(Plan &P, hipStream_t s) {
     const int p = P.order, P2 = p * p, L = P.depth;
     const int Lm = 2 * p - 2;
@@ -256,6 +325,7 @@ void build_operators(Plan &P, hipStream_t s) {
         FMB_CHECK_HIP(hipMemcpyAsync(P.inv_alpha.p, hi.data(), hi.size() * sizeof(double), hipMemcpyHostToDevice, s));
         FMB_CHECK_HIP(hipStreamSynchronize(s));
     }
+    build_basis_tables(P, s);
     const size_t shmem = ((size_t)(Lm + 1) * (Lm + 1) + (Lm + 1)) * sizeof(cx<double>);
     auto launch = [&](std::vector<OpDesc> &ds, DevBuf &outbuf, int nslots) {
         outbuf.alloc((size_t)nslots * P2 * P2 * 4 * esz);

@@ -51,7 +51,7 @@ struct Level {
 enum Stage { ST_GATHER = 0, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_L2P, ST_P2P, ST_CORR, ST_SCATTER, ST_SUMS, ST_COUNT };
 
 struct StageTimer {
-    bool on = false;
+    uint32_t mask = 0;                   // stages (bit 1 << stage) that record events
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[ST_COUNT];
     std::vector<hipEvent_t> pool;
     double ms[ST_COUNT] = {0};
@@ -83,6 +83,8 @@ struct Plan {
     DevBuf sw;        // f64[n]
     DevBuf stri;      // i32[n]
     DevBuf inv_alpha; // f64[depth+1][order] 1/alpha_n per level
+    DevBuf btab;      // basis recurrence constants in the plan's precision (BasisTab layout, N = order)
+    DevBuf bgix;      // i32[order^2][7] R-table indices of the gradient terms
     // corrections (user order)
     DevBuf point_tri; // i32[n]
     DevBuf unrm;      // f64[n][3] normals, user order
