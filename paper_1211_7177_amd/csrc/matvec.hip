@@ -954,9 +954,12 @@ inline bool use_big(int precision, int KR) {
     return !(rt <= 16 && (precision == FMB_FP32 || rt <= 8));
 }
 
+// columns per split-BF16 job (the instantiations in launch_translate)
+inline int bf3_job_cols(int p) { return p <= 5 ? 96 : (p <= 8 ? 64 : 32); }
+
 inline bool use_bf3(const Plan &P) {
     return P.precision == FMB_FP32 && P.translate_mode == FMB_TRANSLATE_BF16X3 && P.order >= 2 && P.order <= 9 &&
-           3 * P.nrhs_max <= OS_MAXCOLS;
+           3 * P.nrhs_max <= bf3_job_cols(P.order);
 }
 
 // the operator-stationary kernel applies to FP32 operators of order 2 <= p <= 9
@@ -973,7 +976,10 @@ inline bool use_os(int precision, int p, int nrhs_max) {
 // k-step s holds T[16 i + l%16][32 s + 8 (l/16) + j], j = 0..7.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-template <int KS, int RTW>
+// A job holds at most JC columns (bf3_job_cols); all of them are staged into
+// LDS with one batch of loads before any MFMA runs, so a job waits for memory
+// once instead of once per 16-column chunk.
+template <int KS, int RTW, int JC>
 __global__ void __launch_bounds__(TPB) k_translate_bf3(const Tile *__restrict__ tiles, int ntiles,
                                                        const int32_t *__restrict__ ent,
                                                        const int32_t *__restrict__ src_map,
@@ -983,14 +989,16 @@ __global__ void __launch_bounds__(TPB) k_translate_bf3(const Tile *__restrict__ 
                                                        int64_t blkR) {
     constexpr int KP = KS * 32;
     constexpr int CS = KP + 4;                                   // LDS column stride (floats)
-    constexpr int LD = (KP * OS_COLS + TPB - 1) / TPB;
+    constexpr int LD = (KP * JC + TPB - 1) / TPB;
     typedef typename Mfma<float>::v4 v4;
-    __shared__ __attribute__((aligned(16))) float Bs[2][OS_COLS][CS];
-    __shared__ int64_t s_in[OS_MAXCOLS], s_out[OS_MAXCOLS];
+    constexpr int RP = 64 * RTW + 1;                             // output tile pitch (rows of 4 waves)
+    __shared__ __attribute__((aligned(16))) float Bs[JC][CS];
+    __shared__ float Os[16][RP];
+    __shared__ int64_t s_in[JC], s_out[JC];
     const int tix = xcd_tile(blockIdx.x, ntiles);
     if (tix >= ntiles) return;
     const Tile tl = tiles[tix];
-    const int C = tl.count * ncol;
+    const int C = tl.count * ncol;                               // <= JC (plan-time tiling)
     for (int c = threadIdx.x; c < C; c += blockDim.x) {
         const int e = c / ncol, cc = c % ncol;
         const int32_t en = ent[tl.first + e];
@@ -1018,36 +1026,29 @@ __global__ void __launch_bounds__(TPB) k_translate_bf3(const Tile *__restrict__ 
         }
     }
     __syncthreads();
-    const int ntc = (C + OS_COLS - 1) / OS_COLS;
-    float pre[LD];
-    auto fetch = [&](int t) {
+    {
+        float pre[LD];
 #pragma unroll
         for (int j = 0; j < LD; ++j) {
             const int e = threadIdx.x + j * TPB;
             const int c = e / KP, k = e % KP;
-            const int cg = t * OS_COLS + c;
-            pre[j] = (e < KP * OS_COLS && cg < C && k < KR) ? X[s_in[cg] + k] : 0.f;
+            pre[j] = (e < KP * JC && c < C && k < KR) ? X[s_in[c] + k] : 0.f;
         }
-    };
-    auto stash = [&](int buf) {
 #pragma unroll
         for (int j = 0; j < LD; ++j) {
             const int e = threadIdx.x + j * TPB;
-            if (e < KP * OS_COLS) Bs[buf][e / KP][e % KP] = pre[j];
+            if (e < KP * JC) Bs[e / KP][e % KP] = pre[j];
         }
-    };
-    fetch(0);
-    stash(0);
+    }
     __syncthreads();
+    const int ntc = (C + 15) / 16;
     for (int t = 0; t < ntc; ++t) {
-        const int buf = t & 1;
-        if (t + 1 < ntc) fetch(t + 1);
         v4 acc[RTW];
 #pragma unroll
         for (int i = 0; i < RTW; ++i) acc[i] = v4{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            const float *bp = &Bs[buf][lane & 15][32 * s + 8 * (lane >> 4)];
+            const float *bp = &Bs[16 * t + (lane & 15)][32 * s + 8 * (lane >> 4)];
             const float4 v0 = *reinterpret_cast<const float4 *>(bp);
             const float4 v1 = *reinterpret_cast<const float4 *>(bp + 4);
             const float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
@@ -1065,18 +1066,18 @@ __global__ void __launch_bounds__(TPB) k_translate_bf3(const Tile *__restrict__ 
                 acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i][s], bh, acc[i], 0, 0, 0);
             }
         }
-        const int cg = t * OS_COLS + (lane & 15);
-        if (cg < C) {
-            float *yo = Y + s_out[cg];
+        // the 16 x KR output tile goes through LDS so that every column is
+        // written as one contiguous run of KR floats
 #pragma unroll
-            for (int i = 0; i < RTW; ++i)
+        for (int i = 0; i < RTW; ++i)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int row = (wave * RTW + i) * 16 + 4 * (lane >> 4) + q;
-                    if (row < KR) yo[row] = acc[i][q];
-                }
+            for (int q = 0; q < 4; ++q) Os[lane & 15][(wave * RTW + i) * 16 + 4 * (lane >> 4) + q] = acc[i][q];
+        __syncthreads();
+        const int cn = min(16, C - 16 * t);
+        for (int e = threadIdx.x; e < cn * KR; e += TPB) {
+            const int c = e / KR, row = e % KR;
+            Y[s_out[16 * t + c] + row] = Os[c][row];
         }
-        if (t + 1 < ntc) stash(buf ^ 1);
         __syncthreads();
     }
 }
@@ -1122,14 +1123,14 @@ void launch_translate(const Tile *tiles, int64_t ntiles, const int32_t *ent, con
         const float *x = (const float *)X;
         float *y = (float *)Y;
         switch (p) {
-            case 2: k_translate_bf3<1, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            case 3: k_translate_bf3<1, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            case 4: k_translate_bf3<1, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            case 5: k_translate_bf3<2, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            case 6: k_translate_bf3<3, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            case 7: k_translate_bf3<4, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            case 8: k_translate_bf3<4, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            default: k_translate_bf3<6, 3><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            case 2: k_translate_bf3<1, 1, 96><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            case 3: k_translate_bf3<1, 1, 96><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            case 4: k_translate_bf3<1, 1, 96><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            case 5: k_translate_bf3<2, 1, 96><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            case 6: k_translate_bf3<3, 2, 64><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            case 7: k_translate_bf3<4, 2, 64><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            case 8: k_translate_bf3<4, 2, 64><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+            default: k_translate_bf3<6, 3, 32><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
         }
         FMB_LAUNCH_CHECK();
         return;
@@ -1341,6 +1342,9 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
 
 }  // namespace
 
+// target job count per launch: about 12 resident blocks on each of the 256 CUs
+constexpr int64_t EP_BLOCKS = 3072;
+
 void build_tiles(Plan &P, hipStream_t s) {
     const int L = P.depth;
     auto upload = [&](std::vector<Tile> &v, DevBuf &buf, int64_t &cnt) {
@@ -1350,14 +1354,16 @@ void build_tiles(Plan &P, hipStream_t s) {
             FMB_CHECK_HIP(hipMemcpyAsync(buf.p, v.data(), v.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
     };
     // entries per tile.  Operator-stationary jobs hold up to OS_MAXCOLS columns;
-    // a level with little work gets shorter jobs so that it still spreads over
-    // about 1024 blocks (its cost is then latency, not operator traffic).
+    // shorter jobs are used until a level spreads over about EP_BLOCKS blocks:
+    // a job walks its columns one 16-column chunk after another, so the level's
+    // time is set by the longest chain of gathered loads, not by operator traffic.
     const bool os = use_os(P.precision, P.order, P.nrhs_max);
-    const int cols = os ? OS_MAXCOLS : (use_big(P.precision, 2 * P.P2) ? BG_N : TN);
+    const int cols = use_bf3(P) ? bf3_job_cols(P.order)
+                                : (os ? OS_MAXCOLS : (use_big(P.precision, 2 * P.P2) ? BG_N : TN));
     const int ep_max = std::max(1, cols / (3 * P.nrhs_max));
     const int ep_min = os ? std::max(1, OS_COLS / (3 * P.nrhs_max)) : ep_max;
     auto ep_for = [&](int64_t total) {
-        int64_t e = total / 1024;
+        int64_t e = total / EP_BLOCKS;
         return (int)std::max<int64_t>(ep_min, std::min<int64_t>(ep_max, e));
     };
     auto chunk = [](std::vector<Tile> &v, int ep, int op, int first, int count) {

@@ -229,16 +229,35 @@ __global__ void k_rhs_planewave(const double *__restrict__ spts, const int32_t *
 // Vectors are cx<T> (T = double for FP64 solves, float for the inner solves of
 // the mixed mode); inner products, the Hessenberg matrix and the rotations are
 // always FP64.
-constexpr int DOT_CHUNKS = 64;
+constexpr int DOT_CHUNKS = 64;            // blocks per (vector, rhs) in the inner-product kernel
 
-// part[(i*nrhs + r)*DOT_CHUNKS + c] = sum_{k in chunk c} conj(V_i[r][k]) W[r][k] for i < nv, and
-// for i == nv (when X is given) the same with X in place of V_i.  need (optional): rhs with
-// need[r] == 0 write zeros without reading.
+inline int nchunks_c(int64_t len) { return (int)((len + TPB - 1) / TPB); }   // update-kernel blocks per rhs
+__device__ inline int nchunks_c_dev(int64_t len) { return (int)((len + TPB - 1) / TPB); }
+
+__device__ inline cx<double> shfl_xor_cx(cx<double> v, int m) {
+    return mk(__shfl_xor(v.re, m), __shfl_xor(v.im, m));
+}
+
+// sum of v over the block (TPB threads), fixed reduction order; result valid in thread 0
+__device__ inline cx<double> block_sum(cx<double> v, cx<double> *sm) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) v += shfl_xor_cx(v, o);
+    if (lane == 0) sm[wave] = v;
+    __syncthreads();
+    cx<double> s = sm[0];
+    for (int w = 1; w < TPB / 64; ++w) s += sm[w];
+    return s;
+}
+
+// part[(i*nrhs + r)*DOT_CHUNKS + c] = sum over chunk c of conj(V_i[r]) W[r] for
+// i < nv, and for i == nv (when X is given) the same with X in place of V_i.
+// need (optional): rhs with need[r] == 0 write zeros without reading.
 template <typename T>
-__global__ void k_dots(const cx<T> *__restrict__ V, int64_t vstride, int nv, const cx<T> *__restrict__ X,
-                       const cx<T> *__restrict__ W, int64_t len, int nrhs, const int32_t *__restrict__ need,
-                       cx<double> *__restrict__ part) {
-    __shared__ cx<double> sm[TPB];
+__global__ void __launch_bounds__(TPB) k_dots(const cx<T> *__restrict__ V, int64_t vstride, int nv,
+                                              const cx<T> *__restrict__ X, const cx<T> *__restrict__ W, int64_t len,
+                                              int nrhs, const int32_t *__restrict__ need,
+                                              cx<double> *__restrict__ part) {
+    __shared__ cx<double> sm[TPB / 64];
     const int c = blockIdx.x % DOT_CHUNKS;
     const int r = (blockIdx.x / DOT_CHUNKS) % nrhs;
     const int i = blockIdx.x / (DOT_CHUNKS * nrhs);
@@ -252,37 +271,96 @@ __global__ void k_dots(const cx<T> *__restrict__ V, int64_t vstride, int nv, con
     const int64_t per = (len + DOT_CHUNKS - 1) / DOT_CHUNKS;
     const int64_t k0 = c * per, k1 = min(len, k0 + per);
     cx<double> s = mk(0.0, 0.0);
-    for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) s += conj(widen(v[k])) * widen(w[k]);
-    sm[threadIdx.x] = s;
-    __syncthreads();
-    for (int st = TPB / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) sm[threadIdx.x] += sm[threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = sm[0];
+#pragma unroll 4
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += TPB) s += conj(widen(v[k])) * widen(w[k]);
+    s = block_sum(s, sm);
+    if (threadIdx.x == 0) *out = s;
 }
 
+// out[e] = sum_c part[e*DOT_CHUNKS + c], one wave per e (fixed order)
 __global__ void k_dots_reduce(const cx<double> *__restrict__ part, int cnt, cx<double> *__restrict__ out) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = blockIdx.x;
     if (e >= cnt) return;
-    cx<double> s = mk(0.0, 0.0);
-    for (int c = 0; c < DOT_CHUNKS; ++c) s += part[(int64_t)e * DOT_CHUNKS + c];
-    out[e] = s;
+    cx<double> s = part[(int64_t)e * DOT_CHUNKS + threadIdx.x];
+    for (int o = 32; o > 0; o >>= 1) s += shfl_xor_cx(s, o);
+    if (threadIdx.x == 0) out[e] = s;
 }
 
-// W[r] += sign * sum_i V_i[r] h[i][r]   (h laid out [i][nrhs]); only rhs with active[r] (and need[r])
+// W[r] += sign * sum_i V_i[r] h[i][r]   (h laid out [i][nrhs]) for the rhs with
+// active[r] (and need[r]); with npart, also each block's |W_new|^2 into
+// npart[r*nchunks_c(len) + block].  One element per thread; blocks do not
+// straddle rhs; h of the block's rhs in LDS.
 template <typename T>
-__global__ void k_combine(const cx<T> *__restrict__ V, int64_t vstride, int nv, const cx<double> *__restrict__ h,
-                          double sign, cx<T> *__restrict__ W, int64_t len, int nrhs,
-                          const int32_t *__restrict__ active, const int32_t *__restrict__ need) {
-    int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (e >= len * nrhs) return;
-    const int r = (int)(e / len);
-    if (active && !active[r]) return;
-    if (need && !need[r]) return;
-    cx<double> s = mk(0.0, 0.0);
-    for (int i = 0; i < nv; ++i) s += widen(V[(int64_t)i * vstride + e]) * h[(int64_t)i * nrhs + r];
-    W[e] = narrow<T>(widen(W[e]) + sign * s);
+__global__ void __launch_bounds__(TPB) k_combine(const cx<T> *__restrict__ V, int64_t vstride, int nv,
+                                                 const cx<double> *__restrict__ h, double sign,
+                                                 cx<T> *__restrict__ W, int64_t len, int nrhs,
+                                                 const int32_t *__restrict__ active,
+                                                 const int32_t *__restrict__ need, double *__restrict__ npart) {
+    extern __shared__ cx<double> sh[];                 // [nv]
+    __shared__ cx<double> sm[TPB / 64];
+    const int nb = nchunks_c_dev(len);
+    const int c = blockIdx.x % nb, r = blockIdx.x / nb;
+    if ((active && !active[r]) || (need && !need[r])) {
+        if (npart && threadIdx.x == 0) npart[(int64_t)r * nb + c] = 0.0;
+        return;
+    }
+    for (int i = threadIdx.x; i < nv; i += TPB) sh[i] = sign * h[(int64_t)i * nrhs + r];
+    __syncthreads();
+    const int64_t k = (int64_t)c * TPB + threadIdx.x;
+    double n2 = 0.0;
+    if (k < len) {
+        const int64_t e = (int64_t)r * len + k;
+        cx<double> acc = widen(W[e]);
+#pragma unroll 8
+        for (int i = 0; i < nv; ++i) acc += widen(V[(int64_t)i * vstride + e]) * sh[i];
+        const cx<T> o = narrow<T>(acc);
+        W[e] = o;
+        n2 = abs2(widen(o));
+    }
+    if (npart) {
+        const cx<double> t = block_sum(mk(n2, 0.0), sm);
+        if (threadIdx.x == 0) npart[(int64_t)r * nb + c] = t.re;
+    }
+}
+
+// After the first Gram-Schmidt pass: hn = |W'| from the chunk partials, and the
+// Daniel-Gragg-Kaufman-Stewart test for a second pass, taken when the first
+// one removed more than half of |A z|^2 = h[j+1] (|W'|^2 < |A z|^2 / 2).
+// One wave per rhs.
+__global__ void k_post1(const double *__restrict__ npart, int nch, const cx<double> *__restrict__ h, int j,
+                        const int32_t *__restrict__ active, int32_t *__restrict__ need, double *__restrict__ hn,
+                        double *__restrict__ hninv, int nrhs) {
+    const int r = blockIdx.x;
+    double s = 0.0;
+    for (int c = threadIdx.x; c < nch; c += 64) s += npart[(int64_t)r * nch + c];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (threadIdx.x == 0) {
+        const double v = sqrt(s);
+        hn[r] = v;
+        hninv[r] = v > 0 ? 1.0 / v : 0.0;
+        need[r] = (active[r] && 2.0 * s < h[(int64_t)(j + 1) * nrhs + r].re) ? 1 : 0;
+    }
+}
+
+// After the second pass (rhs with need[r]): h += h2 and, the basis being
+// orthonormal, |W''|^2 = |W'|^2 - |h2|^2.  One wave per rhs.
+__global__ void k_post2(cx<double> *__restrict__ h, const cx<double> *__restrict__ h2, int nv,
+                        const int32_t *__restrict__ need, double *__restrict__ hn, double *__restrict__ hninv,
+                        int nrhs) {
+    const int r = blockIdx.x;
+    if (!need[r]) return;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nv; i += 64) {
+        const cx<double> d = h2[(int64_t)i * nrhs + r];
+        h[(int64_t)i * nrhs + r] += d;
+        s += abs2(d);
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (threadIdx.x == 0) {
+        const double v = sqrt(fmax(hn[r] * hn[r] - s, 0.0));
+        hn[r] = v;
+        hninv[r] = v > 0 ? 1.0 / v : 0.0;
+    }
 }
 
 template <typename T>
@@ -300,49 +378,61 @@ __global__ void k_sub(const cx<T> *__restrict__ b, const cx<T> *__restrict__ ax,
     if (i < m) r[i] = b[i] - ax[i];
 }
 
-// One Arnoldi column per rhs: H[:, j] from h (j+1 entries, [i][nrhs]) and hn;
-// apply old rotations, form a new one, update g, write the residual estimate.
-// |A z| (for the breakdown test) is sqrt of h[j+1] = (A z)^H (A z), the extra
-// inner product of the first Gram-Schmidt pass.
+// One Arnoldi column per rhs (one block each): H[:, j] from h (j+1 entries,
+// [i][nrhs]) and hn; apply the old rotations, form a new one, update g, write
+// the residual estimate.  |A z| (for the breakdown test) is sqrt of h[j+1] =
+// (A z)^H (A z), the extra inner product of the first Gram-Schmidt pass.  The
+// column and the rotations are staged in LDS; one thread applies them in order.
 __global__ void k_givens(cx<double> *__restrict__ H, int ldh, int j, const cx<double> *__restrict__ h,
                          const double *__restrict__ hn, double *__restrict__ cs, cx<double> *__restrict__ sn,
                          cx<double> *__restrict__ g, double *__restrict__ res, int32_t *__restrict__ active,
                          int32_t *__restrict__ brk, int nrhs, int m) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
+    extern __shared__ unsigned char gsm[];
+    cx<double> *col = reinterpret_cast<cx<double> *>(gsm);          // [j+2]
+    cx<double> *ssn = col + (j + 2);                                 // [j]
+    double *scs = reinterpret_cast<double *>(ssn + j);               // [j]
+    const int r = blockIdx.x;
     if (!active[r]) return;
-    cx<double> *Hr = H + (int64_t)r * ldh * m;          // column-major [m][ldh]
-    cx<double> *col = Hr + (int64_t)j * ldh;
-    for (int i = 0; i <= j; ++i) col[i] = h[(int64_t)i * nrhs + r];
-    const double nAz = sqrt(fmax(h[(int64_t)(j + 1) * nrhs + r].re, 0.0));
-    col[j + 1] = mk(hn[r], 0.0);
-    for (int i = 0; i < j; ++i) {
-        const double c = cs[r * m + i];
-        const cx<double> s = sn[r * m + i];
-        cx<double> t = c * col[i] + s * col[i + 1];
-        col[i + 1] = c * col[i + 1] - conj(s) * col[i];
-        col[i] = t;
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = h[(int64_t)i * nrhs + r];
+    for (int i = threadIdx.x; i < j; i += blockDim.x) {
+        scs[i] = cs[r * m + i];
+        ssn[i] = sn[r * m + i];
     }
-    const cx<double> a = col[j], b = col[j + 1];
-    const double aa = sqrt(abs2(a)), den = sqrt(abs2(a) + abs2(b));
-    double c;
-    cx<double> s;
-    if (aa == 0.0) {
-        c = 0.0;
-        s = mk(1.0, 0.0);
-    } else {
-        c = aa / den;
-        s = (1.0 / (aa * den)) * (a * conj(b));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double nAz = sqrt(fmax(h[(int64_t)(j + 1) * nrhs + r].re, 0.0));
+        col[j + 1] = mk(hn[r], 0.0);
+        for (int i = 0; i < j; ++i) {
+            const double c = scs[i];
+            const cx<double> s = ssn[i];
+            cx<double> t = c * col[i] + s * col[i + 1];
+            col[i + 1] = c * col[i + 1] - conj(s) * col[i];
+            col[i] = t;
+        }
+        const cx<double> a = col[j], b = col[j + 1];
+        const double aa = sqrt(abs2(a)), den = sqrt(abs2(a) + abs2(b));
+        double c;
+        cx<double> s;
+        if (aa == 0.0) {
+            c = 0.0;
+            s = mk(1.0, 0.0);
+        } else {
+            c = aa / den;
+            s = (1.0 / (aa * den)) * (a * conj(b));
+        }
+        cs[r * m + j] = c;
+        sn[r * m + j] = s;
+        col[j] = c * a + s * b;
+        col[j + 1] = mk(0.0, 0.0);
+        cx<double> gj = g[r * (m + 1) + j];
+        g[r * (m + 1) + j + 1] = -(conj(s) * gj);
+        g[r * (m + 1) + j] = c * gj;
+        res[r] = sqrt(abs2(g[r * (m + 1) + j + 1]));
+        brk[r] = (hn[r] <= 1e-14 * nAz) ? 1 : 0;
     }
-    cs[r * m + j] = c;
-    sn[r * m + j] = s;
-    col[j] = c * a + s * b;
-    col[j + 1] = mk(0.0, 0.0);
-    cx<double> gj = g[r * (m + 1) + j];
-    g[r * (m + 1) + j + 1] = -(conj(s) * gj);
-    g[r * (m + 1) + j] = c * gj;
-    res[r] = sqrt(abs2(g[r * (m + 1) + j + 1]));
-    brk[r] = (hn[r] <= 1e-14 * nAz) ? 1 : 0;
+    __syncthreads();
+    cx<double> *Hc = H + (int64_t)r * ldh * m + (int64_t)j * ldh;   // column-major [m][ldh]
+    for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) Hc[i] = col[i];
 }
 
 // y = H^{-1} g (upper triangular, size jr[r]) per rhs, written as y[i][nrhs]
@@ -360,56 +450,48 @@ __global__ void k_trisolve(const cx<double> *__restrict__ H, int ldh, const cx<d
     }
 }
 
-// h += h2 for the rhs that took the second Gram-Schmidt pass
-__global__ void k_add_need(cx<double> *__restrict__ h, const cx<double> *__restrict__ h2, int cnt, int nrhs,
-                           const int32_t *__restrict__ need) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt && need[i % nrhs]) h[i] += h2[i];
-}
-
-// out = sqrt(re in), inv = 1/out (0 for 0); with need, only rhs with need[r] are updated
-__global__ void k_sqrt_real(const cx<double> *__restrict__ in, double *__restrict__ out, double *__restrict__ inv, int m,
-                            const int32_t *__restrict__ need) {
+// out = sqrt(re in), inv = 1/out (0 for 0)
+__global__ void k_sqrt_real(const cx<double> *__restrict__ in, double *__restrict__ out, double *__restrict__ inv,
+                            int m) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
-    if (need && !need[i]) return;
     double v = sqrt(fmax(in[i].re, 0.0));
     out[i] = v;
     if (inv) inv[i] = v > 0 ? 1.0 / v : 0.0;
 }
 
-// Daniel-Gragg-Kaufman-Stewart test: a second Gram-Schmidt pass is taken when
-// the first one removed more than half of |A z|^2 (|w'| < |A z| / sqrt 2).
-__global__ void k_dgks(const cx<double> *__restrict__ h, int j, const double *__restrict__ hn,
-                       const int32_t *__restrict__ active, int32_t *__restrict__ need, int nrhs) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
-    const double az2 = h[(int64_t)(j + 1) * nrhs + r].re;
-    need[r] = (active[r] && 2.0 * hn[r] * hn[r] < az2) ? 1 : 0;
-}
-
 template <typename T>
 struct Krylov {
     int64_t len = 0;
-    int nrhs = 0, m = 0;
+    int nrhs = 0, m = 0, nchc = 0;
     DevBuf V, Z, W, r, ax;                                            // cx<T>
-    DevBuf H, cs, sn, g, h, h2, hn, hninv, res, part, act, brk, jr, y, tmp, need;   // FP64 / int32
+    DevBuf H, cs, sn, g, h, h2, hn, hninv, res, part, npart, act, brk, jr, y, tmp, need;   // FP64 / int32
 };
 
+// out[i][r] = V_i[r]^H W[r] for i < nv, plus X[r]^H W[r] as entry nv when X is given
 template <typename T>
 void dots(Krylov<T> &K, const cx<T> *V, int nv, const cx<T> *X, const cx<T> *W, const int32_t *need, cx<double> *out,
           hipStream_t s) {
     const int nvt = nv + (X ? 1 : 0);
-    const int blocks = nvt * K.nrhs * DOT_CHUNKS;
-    k_dots<T><<<blocks, TPB, 0, s>>>(V, K.len * K.nrhs, nv, X, W, K.len, K.nrhs, need, K.part.template as<cx<double>>());
-    k_dots_reduce<<<gridn(nvt * K.nrhs), TPB, 0, s>>>(K.part.template as<cx<double>>(), nvt * K.nrhs, out);
+    k_dots<T><<<(unsigned)(nvt * K.nrhs * DOT_CHUNKS), TPB, 0, s>>>(V, K.len * K.nrhs, nv, X, W, K.len, K.nrhs,
+                                                                    need, K.part.template as<cx<double>>());
+    k_dots_reduce<<<nvt * K.nrhs, 64, 0, s>>>(K.part.template as<cx<double>>(), nvt * K.nrhs, out);
     FMB_LAUNCH_CHECK();
 }
 
 template <typename T>
-void norms(Krylov<T> &K, const cx<T> *W, double *out, double *inv, hipStream_t s, const int32_t *need = nullptr) {
-    dots(K, W, 1, (const cx<T> *)nullptr, W, need, K.tmp.template as<cx<double>>(), s);
-    k_sqrt_real<<<1, 1024, 0, s>>>(K.tmp.template as<cx<double>>(), out, inv, K.nrhs, need);
+void norms(Krylov<T> &K, const cx<T> *W, double *out, double *inv, hipStream_t s) {
+    dots(K, W, 1, (const cx<T> *)nullptr, W, (const int32_t *)nullptr, K.tmp.template as<cx<double>>(), s);
+    k_sqrt_real<<<1, 1024, 0, s>>>(K.tmp.template as<cx<double>>(), out, inv, K.nrhs);
+    FMB_LAUNCH_CHECK();
+}
+
+// W -= V h (sign -1) or W += V h (sign +1) over nv vectors
+template <typename T>
+void combine(Krylov<T> &K, const cx<T> *V, int nv, const cx<double> *h, double sign, cx<T> *W, const int32_t *active,
+             const int32_t *need, double *npart, hipStream_t s) {
+    k_combine<T><<<(unsigned)(K.nchc * K.nrhs), TPB, (size_t)std::max(nv, 1) * sizeof(cx<double>), s>>>(
+        V, K.len * K.nrhs, nv, h, sign, W, K.len, K.nrhs, active, need, npart);
     FMB_LAUNCH_CHECK();
 }
 
@@ -419,6 +501,7 @@ void krylov_alloc(Krylov<T> &K, int64_t len, int nrhs, int m) {
     K.len = len;
     K.nrhs = nrhs;
     K.m = m;
+    K.nchc = nchunks_c(len);
     const size_t tot = (size_t)len * nrhs * sizeof(cx<T>);
     K.V.alloc(tot * (m + 1));
     K.Z.alloc(tot * m);
@@ -441,6 +524,7 @@ void krylov_alloc(Krylov<T> &K, int64_t len, int nrhs, int m) {
     K.need.alloc(nrhs * sizeof(int32_t));
     K.tmp.alloc((size_t)(m + 2) * nrhs * sizeof(cx<double>));
     K.part.alloc((size_t)(m + 2) * nrhs * DOT_CHUNKS * sizeof(cx<double>));
+    K.npart.alloc((size_t)nrhs * K.nchc * sizeof(double));
 }
 
 }  // namespace
@@ -539,24 +623,23 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
             else FMB_CHECK_HIP(hipMemcpyAsync(zj, vj, tot * sizeof(cx<T>), hipMemcpyDeviceToDevice, s));
             bem_apply_t<T>(pb, zj, W, nrhs, s);
             ++matvecs;
-            // classical Gram-Schmidt; the same pass yields |A z|^2 as h[j+1]
+            // classical Gram-Schmidt; the same pass yields |A z|^2 as h[j+1], the
+            // update yields |W'|^2
+            double *npart = K.npart.template as<double>(), *hn = K.hn.template as<double>(),
+                   *hninv = K.hninv.template as<double>();
             dots(K, (const cx<T> *)V, j + 1, (const cx<T> *)W, (const cx<T> *)W, (const int32_t *)nullptr, h, s);
-            k_combine<T><<<gridn(tot), TPB, 0, s>>>(V, tot, j + 1, h, -1.0, W, len, nrhs, actd, nullptr);
+            combine(K, (const cx<T> *)V, j + 1, h, -1.0, W, actd, (const int32_t *)nullptr, npart, s);
+            k_post1<<<nrhs, 64, 0, s>>>(npart, K.nchc, h, j, actd, need, hn, hninv, nrhs);
             FMB_LAUNCH_CHECK();
-            norms(K, (const cx<T> *)W, K.hn.template as<double>(), K.hninv.template as<double>(), s);
             // second pass only where the DGKS test asks for it
-            k_dgks<<<1, 1024, 0, s>>>(h, j, K.hn.template as<double>(), actd, need, nrhs);
             dots(K, (const cx<T> *)V, j + 1, (const cx<T> *)nullptr, (const cx<T> *)W, (const int32_t *)need, h2, s);
-            k_combine<T><<<gridn(tot), TPB, 0, s>>>(V, tot, j + 1, h2, -1.0, W, len, nrhs, actd, need);
-            k_add_need<<<gridn((j + 1) * nrhs), TPB, 0, s>>>(h, h2, (j + 1) * nrhs, nrhs, need);
-            FMB_LAUNCH_CHECK();
-            norms(K, (const cx<T> *)W, K.hn.template as<double>(), K.hninv.template as<double>(), s, need);
-            k_scale_into<T><<<gridn(tot), TPB, 0, s>>>(W, K.hninv.template as<double>(), V + (int64_t)(j + 1) * tot,
-                                                       len, nrhs, actd);
-            k_givens<<<1, 1024, 0, s>>>(K.H.template as<cx<double>>(), m + 1, j, h, K.hn.template as<double>(),
-                                        K.cs.template as<double>(), K.sn.template as<cx<double>>(),
-                                        K.g.template as<cx<double>>(), K.res.template as<double>(), actd,
-                                        K.brk.template as<int32_t>(), nrhs, m);
+            combine(K, (const cx<T> *)V, j + 1, h2, -1.0, W, actd, (const int32_t *)need, (double *)nullptr, s);
+            k_post2<<<nrhs, 64, 0, s>>>(h, h2, j + 1, need, hn, hninv, nrhs);
+            k_scale_into<T><<<gridn(tot), TPB, 0, s>>>(W, hninv, V + (int64_t)(j + 1) * tot, len, nrhs, actd);
+            k_givens<<<nrhs, 64, (size_t)(2 * j + 2) * sizeof(cx<double>) + (size_t)j * sizeof(double), s>>>(
+                K.H.template as<cx<double>>(), m + 1, j, h, hn, K.cs.template as<double>(),
+                K.sn.template as<cx<double>>(), K.g.template as<cx<double>>(), K.res.template as<double>(), actd,
+                K.brk.template as<int32_t>(), nrhs, m);
             FMB_LAUNCH_CHECK();
             FMB_CHECK_HIP(hipMemcpyAsync(res.data(), K.res.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
             FMB_CHECK_HIP(hipMemcpyAsync(brk.data(), K.brk.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -586,8 +669,8 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
         int jmax = 0;
         for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jr[r]);
         if (jmax > 0)
-            k_combine<T><<<gridn(tot), TPB, 0, s>>>(Z, tot, jmax, K.y.template as<cx<double>>(), 1.0, x, len, nrhs,
-                                                    nullptr, nullptr);
+            combine(K, (const cx<T> *)Z, jmax, (const cx<double> *)K.y.template as<cx<double>>(), 1.0, x,
+                    (const int32_t *)nullptr, (const int32_t *)nullptr, (double *)nullptr, s);
         FMB_LAUNCH_CHECK();
         // true residual
         bem_apply_t<T>(pb, x, AX, nrhs, s);
