@@ -14,6 +14,7 @@ Prints one JSON line.
 """
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -40,6 +41,10 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=1500)
     ap.add_argument("--skip-fp64-solve", action="store_true")
     ap.add_argument("--translate32", choices=["fp32", "bf16x3"], default="bf16x3")
+    ap.add_argument("--serial", action="store_true",
+                    help="run the k0 and k1 FMM products of each application one after the other (one stream)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -47,13 +52,27 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def m2l_flops(info, nrhs=1):
-    """Algorithmic flops of the dense S|R translations of one matvec: a complex
-    (p^2 x p^2) by (p^2 x 3 nrhs) product per far-field pair, 8 flops per
-    complex multiply-add, i.e. 24 p^4 per pair and right-hand side."""
+def translations(info):
+    """Dense p^2 x p^2 translations of one matvec: one per far-field (S|R) pair,
+    one per box at levels >= 3 for S|S (child to parent) and again for R|R
+    (parent to child)."""
+    return sum(info["m2l_pairs"]) + 2 * sum(info["nbox"][3:])
+
+
+def translate_flops(info, nrhs=1):
+    """Algorithmic flops of one matvec's translations: a complex (p^2 x p^2) by
+    (p^2 x 3 nrhs) product each, 8 flops per complex multiply-add, i.e.
+    24 p^4 per translation and right-hand side."""
     p2 = info["order"] ** 2
-    pairs = sum(info["m2l_pairs"])
-    return 8.0 * p2 * p2 * 3 * nrhs * pairs
+    return 8.0 * p2 * p2 * 3 * nrhs * translations(info)
+
+
+def translate_bytes(info, csize, nrhs=1):
+    """Algorithmic HBM bytes of one matvec's translations: each reads its
+    source block (3 nrhs columns of p^2 coefficients) and writes its output
+    block once; the operators (per offset and level) are read once per job and
+    counted separately."""
+    return 2.0 * 3 * nrhs * info["order"] ** 2 * csize * translations(info)
 
 
 P2P_FLOPS_PER_PAIR = 150.0   # ~45 geometry (r, 1/R, g, grad g) + ~105 per rhs; plus rsqrt, sincos, exp
@@ -63,6 +82,31 @@ def p2p_pairs(info, n):
     """Near (target, source) pairs the method must evaluate: the plan's count
     less the 3 same-triangle pairs of every target (computed as masked)."""
     return info["p2p_pairs"] - 3 * n
+
+
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "translate_bf3_torus60k_p5_hbm_traffic.md")
+KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1211_7177_amd", "csrc", "matvec.hip")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when there is none or the translation source
+    has changed since the counters were taken."""
+    try:
+        meta = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line and line.startswith("    "):
+                    k, v = line.strip().split(":", 1)
+                    meta[k.strip()] = v.strip()
+        with open(KERNEL_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if meta.get("kernel") != kernel or meta.get("source_sha256") != sha:
+            return None
+        return float(meta["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -94,8 +138,9 @@ def main():
     info32 = pb.p0_32.info()
     rhs = pb.rhs_planewave(d, pol)
 
-    def step():
-        return pb.solve(rhs, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=100, maxit=2000)
+    def step(serial=args.serial):
+        return pb.solve(rhs, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=100, maxit=2000,
+                        serial=serial)
 
     for _ in range(args.warmup):
         _, wi = step()
@@ -112,14 +157,20 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
     solves_per_s = args.steps / dt
     last = infos[-1]
-    # one more identical solve with HIP events (on the streams the kernels run
-    # on) around the near-field and S|R translation launches of both FP32 plans;
-    # the roofline below uses their per-launch averages.  Kept out of the timed
-    # region because the events cost the solve a few per cent.
+    # one more solve of the same system with HIP events around the near-field
+    # and translation launches of both FP32 plans; the roofline below uses their
+    # per-launch averages.  It runs the two products of each application one
+    # after the other, so that an event pair brackets its kernel alone, and it
+    # is kept out of the timed region.  Two plane-wave right-hand-side kernels
+    # (k_rhs_planewave) bracket it so that a kernel trace can be cut to it.
     for p in (pb.p0_32, pb.p1_32):
-        p.profile(True, stages=("p2p", "m2l"))
+        p.profile(True, stages=("p2p", "m2m", "m2l", "l2l"))
         p.profile_read(reset=True)
-    step()
+    pb.rhs_planewave(d, pol)
+    torch.cuda.synchronize()
+    step(serial=True)
+    torch.cuda.synchronize()
+    pb.rhs_planewave(d, pol)
     torch.cuda.synchronize()
     timed = {}
     for p in (pb.p0_32, pb.p1_32):
@@ -165,30 +216,48 @@ def main():
         plan.profile(False)
         log(tag, "matvec/s %.1f" % rates[tag], prof[tag])
 
-    # roofline of the dominant FP32 kernel in the timed solves (both FP32 plans):
-    # the near-field kernel (VALU) or the S|R translations (matrix cores)
+    # roofline of the dominant FP32 kernel of the solve (both FP32 plans): the
+    # translation kernel (every S|S, S|R and R|R launch) or the near field
     inf = info32
-    mv32 = timed["p2p"][1]                      # one P2P launch per FP32 matvec
-    p2p_ms, m2l_ms = timed["p2p"][0], timed["m2l"][0]
+    mv32 = timed["p2p"][1]                      # one near-field launch per FP32 matvec
+    p2p_ms = timed["p2p"][0]
+    tr_ms = sum(timed[s][0] for s in ("m2m", "m2l", "l2l"))
+    tr_launches = sum(timed[s][1] for s in ("m2m", "m2l", "l2l"))
     p2p_fl = P2P_FLOPS_PER_PAIR * p2p_pairs(inf, n)
     p2p_tf = p2p_fl / (p2p_ms / mv32 * 1e-3) / 1e12
-    m2l_tf = m2l_flops(inf) * mv32 / (m2l_ms * 1e-3) / 1e12
+    tr_fl = translate_flops(inf) * mv32
+    tr_by = translate_bytes(inf, 8) * mv32
+    tr_tf = tr_fl / (tr_ms * 1e-3) / 1e12
+    tr_gbs = tr_by / (tr_ms * 1e-3) / 1e9
     if args.translate32 == "bf16x3":
-        m2l_name, m2l_peak = "k_translate_bf3 (S|R, split-BF16 MFMA, FP32 accumulate)", PEAK["bf16_TF"]
+        tr_name, tr_peak = "k_translate_bf3 (S|S, S|R, R|R; split-BF16 MFMA, FP32 accumulate)", PEAK["bf16_TF"]
     else:
-        m2l_name, m2l_peak = "k_translate_os (S|R, FP32 MFMA)", PEAK["fp32_TF"]
+        tr_name, tr_peak = "k_translate_os (S|S, S|R, R|R; FP32 MFMA)", PEAK["fp32_TF"]
+    # below the ridge point (peak flops / HBM bandwidth) the translations are bound by memory
+    tr_hbm = tr_fl / tr_by < tr_peak * 1e12 / (PEAK["hbm_GBs"] * 1e9)
     stages_rf = {
         "p2p": {"kernel": "k_p2p32 (near field, FP32 VALU)", "bound": "alu", "achieved": p2p_tf,
                 "peak": PEAK["fp32_TF"], "unit": "TFLOP/s", "frac": p2p_tf / PEAK["fp32_TF"], "traffic": None,
                 "per_launch_flops": p2p_fl, "avg_launch_ms": p2p_ms / mv32, "launches": mv32,
                 "gpairs_per_s": p2p_pairs(inf, n) / (p2p_ms / mv32 * 1e-3) / 1e9},
-        "m2l": {"kernel": m2l_name, "bound": "mfma", "achieved": m2l_tf, "peak": m2l_peak, "unit": "TFLOP/s",
-                "frac": m2l_tf / m2l_peak, "traffic": None,
-                "per_launch_flops": m2l_flops(inf) * mv32 / max(1, timed["m2l"][1]),
-                "avg_launch_ms": m2l_ms / max(1, timed["m2l"][1]), "launches": timed["m2l"][1]},
+        "translate": {"kernel": tr_name, "bound": "hbm" if tr_hbm else "mfma",
+                      "achieved": tr_gbs if tr_hbm else tr_tf,
+                      "peak": PEAK["hbm_GBs"] if tr_hbm else tr_peak,
+                      "unit": "GB/s" if tr_hbm else "TFLOP/s",
+                      "frac": tr_gbs / PEAK["hbm_GBs"] if tr_hbm else tr_tf / tr_peak, "traffic": None,
+                      "per_launch_bytes": tr_by / max(1, tr_launches), "per_launch_flops": tr_fl / max(1, tr_launches),
+                      "avg_launch_ms": tr_ms / max(1, tr_launches), "launches": tr_launches,
+                      "mfma_view": {"achieved_TFLOPs": tr_tf, "peak_TFLOPs": tr_peak, "frac": tr_tf / tr_peak}},
     }
-    dominant = "p2p" if p2p_ms >= m2l_ms else "m2l"
+    stages_rf["translate"]["traffic"] = measured_traffic(tr_name.split()[0])
+    dominant = "p2p" if p2p_ms >= tr_ms else "translate"
     roofline = dict(stages_rf[dominant])
+    if args.copy_calibration:
+        buf = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).uniform_()
+        torch.cuda.synchronize()
+        buf2 = buf.clone()
+        torch.cuda.synchronize()
+        log("copy calibration: 256 MiB device-to-device copy done", buf2.numel())
     log("roofline", stages_rf)
 
     # accuracy against the oracle: FP64 direct-sum residual of the GPU solutions on sampled rows

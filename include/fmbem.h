@@ -175,7 +175,10 @@ typedef struct {
     int32_t mixed;       /* 1: FP32 inner solves refined by FP64 residuals (needs FP32 plans)*/
     double inner_tol;    /* relative tolerance of each inner FP32 solve (mixed mode)         */
     int32_t inner_maxit; /* iteration cap of each inner solve                                */
-    int32_t reserved[5];
+    int32_t serial;      /* 1: the k0 and k1 FMM products of each application run one after  */
+                         /*    the other on the caller's stream (0, the default: concurrently */
+                         /*    on the caller's stream and the problem's second stream)        */
+    int32_t reserved[4];
 } fmb_gmres_opts;
 
 typedef struct {

@@ -43,7 +43,8 @@ class PlanInfo(ctypes.Structure):
 class GmresOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("x0_given", ctypes.c_int32), ("mixed", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int32), ("serial", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class GmresInfo(ctypes.Structure):

@@ -43,6 +43,7 @@ struct fmb_problem_s {
     // second stream (default priority) for the k1 product, and the fork/join events
     hipStream_t s2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool serial = false;       // both products on the caller's stream (set per solve)
     ~fmb_problem_s() {
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
@@ -534,6 +535,11 @@ void krylov_alloc(Krylov<T> &K, int64_t len, int nrhs, int m) {
 template <typename T>
 static void fmm_pair(fmb_problem_s &pb, const Plan *P0, const Plan *P1, const cx<T> *a0, const cx<T> *b0, cx<T> *y0,
                      const cx<T> *a1, const cx<T> *b1, cx<T> *y1, int nrhs, hipStream_t s) {
+    if (pb.serial) {
+        run_matvec(*const_cast<Plan *>(P0), a0, b0, y0, nrhs, s);
+        run_matvec(*const_cast<Plan *>(P1), a1, b1, y1, nrhs, s);
+        return;
+    }
     FMB_CHECK_HIP(hipEventRecord(pb.ev_fork, s));
     FMB_CHECK_HIP(hipStreamWaitEvent(pb.s2, pb.ev_fork, 0));
     run_matvec(*const_cast<Plan *>(P0), a0, b0, y0, nrhs, s);
@@ -814,6 +820,11 @@ int gmres_solve(fmb_problem_t pb, const void *rhs, void *x, int32_t nrhs, const 
         FMB_REQUIRE(op.tol > 0 && op.restart >= 1 && op.maxit >= 1, "bad solver options");
         FMB_REQUIRE(!op.mixed || pb->p032, "mixed precision needs the FP32 plans");
         hipStream_t s = (hipStream_t)stream;
+        pb->serial = op.serial != 0;
+        struct SerialReset {
+            fmb_problem_s *p;
+            ~SerialReset() { p->serial = false; }
+        } serial_reset{pb};
         const int64_t len = pb->n * 6, tot = len * nrhs;
         const cx<double> *b = (const cx<double> *)rhs;
         cx<double> *X = (cx<double> *)x;

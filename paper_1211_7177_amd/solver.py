@@ -72,7 +72,7 @@ class BemProblem:
         return out
 
     def solve(self, rhs, tol=1e-6, restart=100, maxit=1000, precond=True, mixed=False, inner_tol=1e-3,
-              inner_maxit=300, x0=None, raise_on_noconv=True):
+              inner_maxit=300, x0=None, raise_on_noconv=True, serial=False):
         opts = _abi.GmresOpts()
         check(self._lib.fmb_gmres_opts_default(ctypes.byref(opts)))
         opts.tol = tol
@@ -82,6 +82,7 @@ class BemProblem:
         opts.mixed = 1 if mixed else 0
         opts.inner_tol = inner_tol
         opts.inner_maxit = inner_maxit
+        opts.serial = 1 if serial else 0
         x = torch.zeros_like(rhs) if x0 is None else x0.clone()
         opts.x0_given = 0 if x0 is None else 1
         info = _abi.GmresInfo()
