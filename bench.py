@@ -38,7 +38,9 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--inner-tol", type=float, default=2e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=1500)
+    ap.add_argument("--cpu-rows", type=int, default=1500, help="seeded rows of the oracle residual check")
+    ap.add_argument("--cpu-sample-rows", type=int, default=0,
+                    help="target rows of the timed oracle apply (0: all rows, one full BEM application)")
     ap.add_argument("--skip-fp64-solve", action="store_true")
     ap.add_argument("--translate32", choices=["fp32", "bf16x3"], default="bf16x3")
     ap.add_argument("--serial", action="store_true",
@@ -52,27 +54,25 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def translations(info):
-    """Dense p^2 x p^2 translations of one matvec: one per far-field (S|R) pair,
-    one per box at levels >= 3 for S|S (child to parent) and again for R|R
-    (parent to child)."""
-    return sum(info["m2l_pairs"]) + 2 * sum(info["nbox"][3:])
+def sr_pairs(info):
+    """Far-field (S|R) box pairs of one matvec, all levels."""
+    return sum(info["m2l_pairs"])
 
 
-def translate_flops(info, nrhs=1):
-    """Algorithmic flops of one matvec's translations: a complex (p^2 x p^2) by
-    (p^2 x 3 nrhs) product each, 8 flops per complex multiply-add, i.e.
-    24 p^4 per translation and right-hand side."""
+def sr_flops(info, nrhs=1):
+    """Algorithmic flops of one matvec's S|R translations: a complex (p^2 x p^2)
+    by (p^2 x 3 nrhs) product per pair, 8 flops per complex multiply-add, i.e.
+    24 p^4 per pair and right-hand side."""
     p2 = info["order"] ** 2
-    return 8.0 * p2 * p2 * 3 * nrhs * translations(info)
+    return 8.0 * p2 * p2 * 3 * nrhs * sr_pairs(info)
 
 
-def translate_bytes(info, csize, nrhs=1):
-    """Algorithmic HBM bytes of one matvec's translations: each reads its
-    source block (3 nrhs columns of p^2 coefficients) and writes its output
-    block once; the operators (per offset and level) are read once per job and
-    counted separately."""
-    return 2.0 * 3 * nrhs * info["order"] ** 2 * csize * translations(info)
+def sr_bytes(info, csize, nrhs=1):
+    """Algorithmic HBM bytes of one matvec's S|R translations: each pair reads
+    its source block (3 nrhs columns of p^2 coefficients) and writes its slot
+    once; the operators (per offset and level) are read once per job and are
+    not counted."""
+    return 2.0 * 3 * nrhs * info["order"] ** 2 * csize * sr_pairs(info)
 
 
 P2P_FLOPS_PER_PAIR = 150.0   # ~45 geometry (r, 1/R, g, grad g) + ~105 per rhs; plus rsqrt, sincos, exp
@@ -84,18 +84,20 @@ def p2p_pairs(info, n):
     return info["p2p_pairs"] - 3 * n
 
 
-TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                            "translate_bf3_torus60k_p5_hbm_traffic.md")
-KERNEL_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1211_7177_amd", "csrc", "matvec.hip")
+TRAFFIC_FILES = {
+    "k_translate_bf3 S|R": os.path.join(ROOT, "profiles", "translate_bf3_sr_torus60k_p5_hbm_traffic.md"),
+    "k_p2p32": os.path.join(ROOT, "profiles", "p2p32_torus60k_hbm_traffic.md"),
+}
+KERNEL_SRC = os.path.join(ROOT, "paper_1211_7177_amd", "csrc", "matvec.hip")
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
-    WRITE_SIZE summary, or None when there is none or the translation source
-    has changed since the counters were taken."""
+    """HBM bytes per launch of `kernel` from its committed FETCH_SIZE /
+    WRITE_SIZE summary, or None when there is none or the kernel source has
+    changed since the counters were taken."""
     try:
         meta = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[kernel]) as f:
             for line in f:
                 if ":" in line and line.startswith("    "):
                     k, v = line.strip().split(":", 1)
@@ -164,7 +166,7 @@ def main():
     # is kept out of the timed region.  Two plane-wave right-hand-side kernels
     # (k_rhs_planewave) bracket it so that a kernel trace can be cut to it.
     for p in (pb.p0_32, pb.p1_32):
-        p.profile(True, stages=("p2p", "m2m", "m2l", "l2l"))
+        p.profile(True, stages=("p2p", "m2l"))
         p.profile_read(reset=True)
     pb.rhs_planewave(d, pol)
     torch.cuda.synchronize()
@@ -217,22 +219,21 @@ def main():
         log(tag, "matvec/s %.1f" % rates[tag], prof[tag])
 
     # roofline of the dominant FP32 kernel of the solve (both FP32 plans): the
-    # translation kernel (every S|S, S|R and R|R launch) or the near field
+    # S|R translation kernel (its launches of all levels) or the near field
     inf = info32
     mv32 = timed["p2p"][1]                      # one near-field launch per FP32 matvec
     p2p_ms = timed["p2p"][0]
-    tr_ms = sum(timed[s][0] for s in ("m2m", "m2l", "l2l"))
-    tr_launches = sum(timed[s][1] for s in ("m2m", "m2l", "l2l"))
+    tr_ms, tr_launches = timed["m2l"]
     p2p_fl = P2P_FLOPS_PER_PAIR * p2p_pairs(inf, n)
     p2p_tf = p2p_fl / (p2p_ms / mv32 * 1e-3) / 1e12
-    tr_fl = translate_flops(inf) * mv32
-    tr_by = translate_bytes(inf, 8) * mv32
+    tr_fl = sr_flops(inf) * mv32
+    tr_by = sr_bytes(inf, 8) * mv32
     tr_tf = tr_fl / (tr_ms * 1e-3) / 1e12
     tr_gbs = tr_by / (tr_ms * 1e-3) / 1e9
     if args.translate32 == "bf16x3":
-        tr_name, tr_peak = "k_translate_bf3 (S|S, S|R, R|R; split-BF16 MFMA, FP32 accumulate)", PEAK["bf16_TF"]
+        tr_name, tr_peak = "k_translate_bf3 S|R (role 1; split-BF16 MFMA, FP32 accumulate)", PEAK["bf16_TF"]
     else:
-        tr_name, tr_peak = "k_translate_os (S|S, S|R, R|R; FP32 MFMA)", PEAK["fp32_TF"]
+        tr_name, tr_peak = "k_translate_os S|R (FP32 MFMA)", PEAK["fp32_TF"]
     # below the ridge point (peak flops / HBM bandwidth) the translations are bound by memory
     tr_hbm = tr_fl / tr_by < tr_peak * 1e12 / (PEAK["hbm_GBs"] * 1e9)
     stages_rf = {
@@ -249,7 +250,9 @@ def main():
                       "avg_launch_ms": tr_ms / max(1, tr_launches), "launches": tr_launches,
                       "mfma_view": {"achieved_TFLOPs": tr_tf, "peak_TFLOPs": tr_peak, "frac": tr_tf / tr_peak}},
     }
-    stages_rf["translate"]["traffic"] = measured_traffic(tr_name.split()[0])
+    stages_rf["translate"]["traffic"] = measured_traffic("k_translate_bf3 S|R") if args.translate32 == "bf16x3" \
+        else None
+    stages_rf["p2p"]["traffic"] = measured_traffic("k_p2p32")
     dominant = "p2p" if p2p_ms >= tr_ms else "translate"
     roofline = dict(stages_rf[dominant])
     if args.copy_calibration:
@@ -272,7 +275,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(nodes, k0, eps, args.cpu_rows,
+        cpu = cpu_baseline(nodes, k0, eps, args.cpu_sample_rows or n,
                            fp64["bem_applies"] if fp64 else last["matvecs64"] + last["matvecs32"])
 
     out = {
@@ -359,7 +362,7 @@ def cpu_baseline(nodes, k0, eps, rows, applies_per_solve):
 
     n = nodes["points"].shape[0]
     rng = np.random.default_rng(seed_for(2, "rows"))
-    sel = np.sort(rng.choice(n, rows, replace=False))
+    sel = np.arange(n) if rows >= n else np.sort(rng.choice(n, rows, replace=False))
     a = complex_normal((n, 3), seed_for(2, "a"))
     b = complex_normal((n, 3), seed_for(2, "b"))
     k1 = wavenumber(k0, eps)
@@ -367,12 +370,12 @@ def cpu_baseline(nodes, k0, eps, rows, applies_per_solve):
     for k in (k0, k1):
         point_sum_c(nodes["points"], nodes["normals"], nodes["weights"], nodes["point_tri"], k, a, b, rows=sel)
     dt = time.perf_counter() - t0
-    apply_s = dt * n / rows
+    apply_s = dt * n / len(sel)
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     return {"value": 1.0 / (apply_s * applies_per_solve), "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": "direct-sum BEM apply (both wavenumbers) on %d of %d target rows, %.2f s, scaled by n/rows "
-                      "to one apply (%.1f s) and by %d applies per FP64 fGMRES solve" %
-                      (rows, n, dt, apply_s, applies_per_solve),
+            "sample": "direct-sum BEM apply (both wavenumbers, FP64 oracle) on %d of %d target rows, %.2f s, "
+                      "scaled by n/rows to one apply (%.1f s) and by the %d applies of one FP64 fGMRES solve" %
+                      (len(sel), n, dt, apply_s, applies_per_solve),
             "applies_per_s": 1.0 / apply_s}
 
 

@@ -152,8 +152,9 @@ int fmm_plan_destroy(fmb_plan_t plan);
  * mask, on the matvec's stream; mask = 0 turns timing off and FMB_PROFILE_ALL
  * (or 1, kept for callers that pass a boolean) times every stage;
  * fmm_plan_profile_read synchronises on them and returns, per stage, the
- * summed kernel time in milliseconds and the number of timed launches since
- * the last read with reset = 1.  Stage order (FMB_NSTAGES = 10): gather, P2M,
+ * summed time in milliseconds and the number of kernel launches timed since
+ * the last read with reset = 1 (the S|R launches of all levels run back to
+ * back and share one pair of events).  Stage order (FMB_NSTAGES = 10): gather, P2M,
  * M2M (S|S translation kernel), M2L (S|R translation kernel), L2L (R|R), L2P,
  * P2P, corrections, scatter, sums (the per-target sums of the S|S and S|R
  * translation slots).  ms and launches: host arrays of FMB_NSTAGES entries

@@ -61,6 +61,15 @@ __global__ void k_scatter_out(const cx<T> *__restrict__ ys, const int32_t *__res
         for (int c = 0; c < 3; ++c) y[((int64_t)r * n + u) * 3 + c] = ys[((int64_t)r * n + i) * 3 + c];
 }
 
+// MI355X dispatches consecutive workgroups to its 8 XCDs in turn.  Tiles are
+// listed operator by operator; renumbering block i to tile (i % 8) * chunk + i / 8
+// gives each XCD a contiguous run of tiles, so the tiles that share an operator
+// share one L2.  The grid is padded to a multiple of 8; spare blocks exit.
+__device__ inline int xcd_tile(int i, int ntiles) {
+    const int chunk = (ntiles + 7) / 8;
+    return (i % 8) * chunk + i / 8;
+}
+
 // ---------------------------------------------------------------- basis
 // Recurrence constants of the normalised associated Legendre functions and of
 // the gradient of R_n^m, tabulated on the host at plan time (BasisTab layout
@@ -414,15 +423,19 @@ __global__ void __launch_bounds__(TPB) k_p2p(const int32_t *__restrict__ start, 
     }
 }
 
-// FP32 near field.  Source records are packed into six 16-byte LDS words per
-// source: position relative to the target leaf's centre (FP32; the leaf and its
-// neighbours span a few leaf widths, so the difference keeps FP32 relative
-// accuracy) with the triangle id, the normal, and the seven density values.
-// The transcendentals go straight to the hardware units with the scale folded
-// into the constants: v_sin/v_cos take revolutions (kR / 2 pi), v_exp takes a
-// base-2 exponent (-Im k R log2 e); the LOSSY = false instance (real k) skips
-// the decay factor.  Same-triangle pairs are masked, not branched around, so
-// the source loop unrolls.
+// FP32 near field, one block per leaf in Morton order.  Consecutive blocks go
+// to different XCDs; giving each XCD contiguous runs of leaves cuts the L2-miss
+// traffic (52 -> 12 MB per launch on the 60k-node torus) but unbalances the
+// load and is slower, and the kernel is bound by its arithmetic.  Source
+// records are packed into six 16-byte LDS words per source: position relative
+// to the target leaf's centre (FP32; the leaf and its neighbours span a few
+// leaf widths, so the difference keeps FP32 relative accuracy) with the
+// triangle id, the normal, and the seven density values.  The transcendentals
+// go straight to the hardware units with the scale folded into the constants:
+// v_sin/v_cos take revolutions (kR / 2 pi), v_exp takes a base-2 exponent
+// (-Im k R log2 e); the LOSSY = false instance (real k) skips the decay
+// factor.  Same-triangle pairs are masked, not branched around, so the source
+// loop unrolls.
 struct __attribute__((aligned(16))) SrcRec32 {
     float x, y, z;
     int32_t tri;
@@ -431,7 +444,8 @@ struct __attribute__((aligned(16))) SrcRec32 {
 };
 
 template <bool LOSSY>
-__global__ void __launch_bounds__(TPB) k_p2p32(const int32_t *__restrict__ start, const int32_t *__restrict__ nbr,
+__global__ void __launch_bounds__(TPB) k_p2p32(int nleaf, const int32_t *__restrict__ start,
+                                               const int32_t *__restrict__ nbr,
                                                const double *__restrict__ center, const double *__restrict__ spts,
                                                const double *__restrict__ snrm, const int32_t *__restrict__ stri,
                                                const cx<float> *__restrict__ src, int64_t n, double k_re,
@@ -441,6 +455,7 @@ __global__ void __launch_bounds__(TPB) k_p2p32(const int32_t *__restrict__ start
     __shared__ int n_nb;
     __shared__ cx<float> red[TPB][3];
     const int box = blockIdx.x, r = blockIdx.y;
+    if (box >= nleaf) return;
     const int t0 = start[box], t1 = start[box + 1];
     const int nt = t1 - t0;
     const double c0x = center[3 * box], c0y = center[3 * box + 1], c0z = center[3 * box + 2];
@@ -557,7 +572,6 @@ struct Tile {
 constexpr int TM = 64, TN = 64, TK = 16;
 constexpr int OS_MAXCOLS = 288;                 // columns per operator-stationary job
 
-__device__ inline int xcd_tile(int i, int ntiles);
 
 template <typename T>
 struct Mfma;
@@ -774,14 +788,6 @@ __global__ void __launch_bounds__(TPB) k_translate_big(const Tile *__restrict__ 
     }
 }
 
-// MI355X dispatches consecutive workgroups to its 8 XCDs in turn.  Tiles are
-// listed operator by operator; renumbering block i to tile (i % 8) * chunk + i / 8
-// gives each XCD a contiguous run of tiles, so the tiles that share an operator
-// share one L2.  The grid is padded to a multiple of 8; spare blocks exit.
-__device__ inline int xcd_tile(int i, int ntiles) {
-    const int chunk = (ntiles + 7) / 8;
-    return (i % 8) * chunk + i / 8;
-}
 
 // Variant for small operators (2 p^2 <= 16 RT): every block computes all rows
 // of its 64 columns, so each gathered column is read from memory once.  The
@@ -979,7 +985,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // A job holds at most JC columns (bf3_job_cols); all of them are staged into
 // LDS with one batch of loads before any MFMA runs, so a job waits for memory
 // once instead of once per 16-column chunk.
-template <int KS, int RTW, int JC>
+// ROLE only names the launch in kernel traces: 0 S|S (M2M), 1 S|R (M2L), 2 R|R (L2L).
+template <int KS, int RTW, int JC, int ROLE>
 __global__ void __launch_bounds__(TPB) k_translate_bf3(const Tile *__restrict__ tiles, int ntiles,
                                                        const int32_t *__restrict__ ent,
                                                        const int32_t *__restrict__ src_map,
@@ -1105,9 +1112,27 @@ __global__ void k_split_bf16(const float *__restrict__ T, int nops, int KR, int 
     lo[f] = l;
 }
 
+template <int ROLE>
+void launch_bf3(int p, unsigned g, const Tile *tiles, int64_t ntiles, const int32_t *ent, const int32_t *src_map,
+                const bf16x8 *h, const bf16x8 *l, const float *x, float *y, int KR, int RT, int ncol, int64_t blkR,
+                hipStream_t s) {
+    const int nt = (int)ntiles;
+    switch (p) {
+        case 2:
+        case 3:
+        case 4: k_translate_bf3<1, 1, 96, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+        case 5: k_translate_bf3<2, 1, 96, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+        case 6: k_translate_bf3<3, 2, 64, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+        case 7:
+        case 8: k_translate_bf3<4, 2, 64, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+        default: k_translate_bf3<6, 3, 32, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+    }
+}
+
+// role: 0 S|S, 1 S|R, 2 R|R (names the split-BF16 launches in kernel traces)
 template <typename T>
 void launch_translate(const Tile *tiles, int64_t ntiles, const int32_t *ent, const int32_t *src_map, const T *ops,
-                      const T *X, T *Y, int KR, int ncol, int64_t blkR, bool os, hipStream_t s,
+                      const T *X, T *Y, int KR, int ncol, int64_t blkR, bool os, hipStream_t s, int role,
                       const void *fhi = nullptr, const void *flo = nullptr) {
     if (ntiles <= 0) return;
     if (fhi) {
@@ -1122,15 +1147,10 @@ void launch_translate(const Tile *tiles, int64_t ntiles, const int32_t *ent, con
         const bf16x8 *h = (const bf16x8 *)fhi, *l = (const bf16x8 *)flo;
         const float *x = (const float *)X;
         float *y = (float *)Y;
-        switch (p) {
-            case 2: k_translate_bf3<1, 1, 96><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            case 3: k_translate_bf3<1, 1, 96><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            case 4: k_translate_bf3<1, 1, 96><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            case 5: k_translate_bf3<2, 1, 96><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            case 6: k_translate_bf3<3, 2, 64><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            case 7: k_translate_bf3<4, 2, 64><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            case 8: k_translate_bf3<4, 2, 64><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-            default: k_translate_bf3<6, 3, 32><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+        switch (role) {
+            case 0: launch_bf3<0>(p, g, tiles, ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, s); break;
+            case 1: launch_bf3<1>(p, g, tiles, ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, s); break;
+            default: launch_bf3<2>(p, g, tiles, ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, s); break;
         }
         FMB_LAUNCH_CHECK();
         return;
@@ -1271,7 +1291,8 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
         if (V.ntiles_m2m == 0) continue;
         tm.begin(ST_M2M, s, ev);
         launch_translate<T>(V.tiles_m2m.as<Tile>(), V.ntiles_m2m, C.by_octant.as<int32_t>(), nullptr, V.m2m.as<T>(),
-                            (const T *)C.M.p, (T *)yb, KR, ncol, blkR, os, s, bf3 ? V.m2m_hi.p : nullptr, V.m2m_lo.p);
+                            (const T *)C.M.p, (T *)yb, KR, ncol, blkR, os, s, 0, bf3 ? V.m2m_hi.p : nullptr,
+                            V.m2m_lo.p);
         tm.end(ST_M2M, s, ev);
         tm.begin(ST_SUMS, s, ev);
         k_sum_children<T><<<(unsigned)V.nbox, TPB, 0, s>>>(V.child_start.as<int32_t>(), V.nbox, yb, V.M.as<cx<T>>(), blk,
@@ -1279,29 +1300,36 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
         FMB_LAUNCH_CHECK();
         tm.end(ST_SUMS, s, ev);
     }
-    // Step 3: downward pass, levels 2 .. L
+    // Step 3a: S|R of every level, one run of launches; each level's slots have
+    // their own region of the slot buffer (slot_base)
+    {
+        int nk = 0;
+        tm.begin(ST_M2L, s, ev);
+        for (int l = 2; l <= L; ++l) {
+            Level &V = P.lv[l];
+            if (V.ntiles_m2l == 0) continue;
+            launch_translate<T>(V.tiles_m2l.as<Tile>(), V.ntiles_m2l, V.ff_by_op.as<int32_t>(), V.ff_src.as<int32_t>(),
+                                V.m2l.as<T>(), (const T *)V.M.p, (T *)(yb + V.slot_base * blk), KR, ncol, blkR, os, s,
+                                1, bf3 ? V.m2l_hi.p : nullptr, V.m2l_lo.p);
+            ++nk;
+        }
+        tm.end(ST_M2L, s, ev, nk);
+    }
+    // Step 3b: downward pass, levels 2 .. L: R|R from the parent, then the level's S|R slot sums
     for (int l = 2; l <= L; ++l) {
         Level &V = P.lv[l];
         if (l >= 3 && V.ntiles_l2l > 0) {
             Level &U = P.lv[l - 1];
             tm.begin(ST_L2L, s, ev);
             launch_translate<T>(V.tiles_l2l.as<Tile>(), V.ntiles_l2l, V.by_octant.as<int32_t>(), V.parent.as<int32_t>(),
-                                V.l2l.as<T>(), (const T *)U.L.p, (T *)V.L.p, KR, ncol, blkR, os, s,
+                                V.l2l.as<T>(), (const T *)U.L.p, (T *)V.L.p, KR, ncol, blkR, os, s, 2,
                                 bf3 ? V.l2l_hi.p : nullptr, V.l2l_lo.p);
             FMB_LAUNCH_CHECK();
             tm.end(ST_L2L, s, ev);
         }
-        if (V.ntiles_m2l > 0) {
-            tm.begin(ST_M2L, s, ev);
-            launch_translate<T>(V.tiles_m2l.as<Tile>(), V.ntiles_m2l, V.ff_by_op.as<int32_t>(), V.ff_src.as<int32_t>(),
-                                V.m2l.as<T>(), (const T *)V.M.p, (T *)yb, KR, ncol, blkR, os, s,
-                                bf3 ? V.m2l_hi.p : nullptr, V.m2l_lo.p);
-            FMB_LAUNCH_CHECK();
-            tm.end(ST_M2L, s, ev);
-        }
         tm.begin(ST_SUMS, s, ev);
-        k_sum_far<T><<<(unsigned)V.nbox, TPB, 0, s>>>(V.ff_ofs.as<int32_t>(), yb, V.L.as<cx<T>>(), blk, ncol * P2,
-                                                      l >= 3 ? 1 : 0);
+        k_sum_far<T><<<(unsigned)V.nbox, TPB, 0, s>>>(V.ff_ofs.as<int32_t>(), yb + V.slot_base * blk, V.L.as<cx<T>>(),
+                                                      blk, ncol * P2, l >= 3 ? 1 : 0);
         FMB_LAUNCH_CHECK();
         tm.end(ST_SUMS, s, ev);
     }
@@ -1321,7 +1349,7 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
     if (sizeof(T) == sizeof(float)) {
         auto kern = P.k_im != 0.0 ? k_p2p32<true> : k_p2p32<false>;
         kern<<<dim3((unsigned)LL.nbox, nrhs), TPB, 0, s>>>(
-            LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(),
+            (int)LL.nbox, LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(),
             P.snrm.as<double>(), P.stri.as<int32_t>(), (const cx<float> *)src, n, P.k_re, P.k_im, (cx<float> *)ys);
     } else
     k_p2p<T><<<dim3((unsigned)LL.nbox, nrhs), TPB, 0, s>>>(LL.start.as<int32_t>(), LL.nbr.as<int32_t>(),
@@ -1416,14 +1444,18 @@ void split_operators(Plan &P, hipStream_t s) {
 void alloc_workspace(Plan &P) {
     const size_t esz = P.precision == FMB_FP64 ? sizeof(cx<double>) : sizeof(cx<float>);
     const int64_t blk = (int64_t)P.nrhs_max * 3 * P.P2;
-    int64_t slots = 1;
+    // S|R slots of all levels side by side (they are written in one run of
+    // launches); the S|S slots of the upward pass reuse the front of the buffer
+    int64_t slots = 1, sr = 0;
     for (int l = 2; l <= P.depth; ++l) {
         Level &V = P.lv[l];
         V.M.alloc((size_t)V.nbox * blk * esz);
         V.L.alloc((size_t)V.nbox * blk * esz);
-        slots = std::max<int64_t>(slots, V.nff);
+        V.slot_base = sr;
+        sr += V.nff;
         if (l < P.depth) slots = std::max<int64_t>(slots, P.lv[l + 1].nbox);
     }
+    slots = std::max(slots, sr);
     P.ybuf.alloc((size_t)slots * blk * esz);
     P.src.alloc((size_t)P.nrhs_max * P.n * 7 * esz);
     P.ys.alloc((size_t)P.nrhs_max * P.n * 3 * esz);
@@ -1446,26 +1478,29 @@ void StageTimer::begin(int st, hipStream_t s, hipEvent_t &e0) {
     FMB_CHECK_HIP(hipEventRecord(e0, s));
 }
 
-void StageTimer::end(int st, hipStream_t s, hipEvent_t e0) {
+void StageTimer::end(int st, hipStream_t s, hipEvent_t e0, int nk) {
     if (!(mask >> st & 1u)) return;
     hipEvent_t e1 = get();
     FMB_CHECK_HIP(hipEventRecord(e1, s));
     pending[st].push_back({e0, e1});
+    pending_nk[st].push_back(nk);
     if (pending[st].size() > 4096) collect();
 }
 
 void StageTimer::collect() {
     for (int st = 0; st < ST_COUNT; ++st) {
-        for (auto &pr : pending[st]) {
+        for (size_t i = 0; i < pending[st].size(); ++i) {
+            auto &pr = pending[st][i];
             FMB_CHECK_HIP(hipEventSynchronize(pr.second));
             float ms_ = 0.f;
             FMB_CHECK_HIP(hipEventElapsedTime(&ms_, pr.first, pr.second));
             ms[st] += ms_;
-            launches[st] += 1;
+            launches[st] += pending_nk[st][i];
             pool.push_back(pr.first);
             pool.push_back(pr.second);
         }
         pending[st].clear();
+        pending_nk[st].clear();
     }
 }
 

@@ -26,6 +26,7 @@ struct Level {
     DevBuf octant;        // i32[nbox] child position in its parent (0..7)
     // far field (levels >= 2)
     int64_t nff = 0;
+    int64_t slot_base = 0;   // first S|R slot of this level in the slot buffer
     DevBuf ff_ofs;        // i32[nbox+1]
     DevBuf ff_src;        // i32[nff]
     DevBuf ff_op;         // i32[nff] op slot 0..342
@@ -53,12 +54,13 @@ enum Stage { ST_GATHER = 0, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_L2P, ST_P2P, ST_C
 struct StageTimer {
     uint32_t mask = 0;                   // stages (bit 1 << stage) that record events
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[ST_COUNT];
+    std::vector<int> pending_nk[ST_COUNT];   // kernel launches inside each bracket
     std::vector<hipEvent_t> pool;
     double ms[ST_COUNT] = {0};
     int64_t launches[ST_COUNT] = {0};
     hipEvent_t get();
     void begin(int st, hipStream_t s, hipEvent_t &e0);
-    void end(int st, hipStream_t s, hipEvent_t e0);
+    void end(int st, hipStream_t s, hipEvent_t e0, int nk = 1);
     void collect();
     void reset();
     ~StageTimer();
