@@ -43,6 +43,8 @@ def parse():
                     help="target rows of the timed oracle apply (0: all rows, one full BEM application)")
     ap.add_argument("--skip-fp64-solve", action="store_true")
     ap.add_argument("--translate32", choices=["fp32", "bf16x3"], default="bf16x3")
+    ap.add_argument("--batch", type=int, default=8,
+                    help="also time one lockstep solve of this many plane waves (0: skip)")
     ap.add_argument("--serial", action="store_true",
                     help="run the k0 and k1 FMM products of each application one after the other (one stream)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -182,6 +184,26 @@ def main():
         p.profile(False)
     log("profiled solve: stage totals (ms, launches)", {k: v for k, v in timed.items() if v[1]})
 
+    # batched right-hand sides (outside the timed region): one lockstep solve of
+    # args.batch seeded plane waves through plans built for that many columns
+    batched = None
+    if args.batch > 1:
+        pbb = BemProblem(nodes, k0, eps, order=args.order64, depth=depth, order32=args.order32,
+                         translate32=args.translate32, nrhs_max=args.batch)
+        db, pob = plane_waves(args.batch, seed_for(2, "dirs"), seed_for(2, "pols"))
+        rb = pbb.rhs_planewave(db, pob)
+        pbb.solve(rb, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=100, maxit=2000)
+        torch.cuda.synchronize()
+        tb0 = time.perf_counter()
+        _, ib = pbb.solve(rb, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=100, maxit=2000)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - tb0
+        batched = {"nrhs": args.batch, "rhs_solves_per_s": args.batch / tb, "ms_per_batch": 1e3 * tb,
+                   "iterations": ib["iterations"], "refinements": ib["refinements"], "residual": ib["residual"],
+                   "speedup_per_rhs_vs_single": (args.batch / tb) / solves_per_s}
+        log("batched", batched)
+        pbb.close()
+
     # plain FP64 solve (reference path) and matvec rates, outside the timed region
     fp64 = None
     if not args.skip_fp64_solve:
@@ -300,6 +322,7 @@ def main():
         "solve": {"iterations": last["iterations"], "refinements": last["refinements"],
                   "bem_applies_fp32": last["matvecs32"], "bem_applies_fp64": last["matvecs64"],
                   "residual": last["residual"]},
+        "batched": batched,
         "fp64_solve": fp64,
         "speedup_vs_fp64_solve": (solves_per_s / fp64["solves_per_s"]) if fp64 else None,
         "fmm_matvecs_per_s": rates,

@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, 
                                              const double *__restrict__ spts, const double *__restrict__ snrm,
                                              const cx<T> *__restrict__ src, int64_t n, int p, double k_re, double k_im,
                                              const double *__restrict__ inv_alpha, const T *__restrict__ tab,
-                                             const int32_t *__restrict__ gix, int nrhs_max, int batch,
+                                             const int32_t *__restrict__ gix, int nrhs, int nrhs_max, int batch,
                                              cx<T> *__restrict__ M) {
     extern __shared__ unsigned char smem[];
     const int N = p;                                  // degrees 0..p for the gradients
@@ -152,121 +152,134 @@ __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, 
     const int NT = NN + 1;                            // per-node table incl. the zero entry
     const int P2 = p * p;
     const BasisTab<T> bt = basis_tab(tab, gix, N, P2);
-    cx<T> *Rb = reinterpret_cast<cx<T> *>(smem);                        // [batch][NT]
+    const int G = P2 <= (int)blockDim.x ? (int)blockDim.x / P2 : 1;   // node groups
+    const int grp = P2 <= (int)blockDim.x ? (int)threadIdx.x / P2 : 0;
+    cx<T> *red = reinterpret_cast<cx<T> *>(smem);                       // [G][P2][3] (G > 1)
+    cx<T> *Rb = red + (G > 1 ? G * P2 * 3 : 0);                         // [batch][NT]
     cx<T> *jb = Rb + batch * NT;                                        // [batch][N+1]
     cx<T> *sv = jb + batch * (N + 1);                                   // [batch][7] node densities
     T *dd = reinterpret_cast<T *>(sv + batch * 7);                      // [batch][3] cos th, sin th e^{i ph}
     T *nvs = dd + batch * 3;                                            // [batch][3] normals
-    const int box = blockIdx.x, r = blockIdx.y;
+    const int box = blockIdx.x;
     const int s0 = start[box], s1 = start[box + 1];
     const double X[3] = {center[3 * box], center[3 * box + 1], center[3 * box + 2]};
     const cx<T> k = mk((T)k_re, (T)k_im);
-    const int G = P2 <= (int)blockDim.x ? (int)blockDim.x / P2 : 1;   // node groups
-    const int grp = P2 <= (int)blockDim.x ? (int)threadIdx.x / P2 : 0;
-    cx<T> accb[P2M_SLOTS][3], accg[P2M_SLOTS][3];
-    for (int u = 0; u < P2M_SLOTS; ++u)
-        for (int c = 0; c < 3; ++c) accb[u][c] = accg[u][c] = mk(T(0), T(0));
-    for (int b0 = s0; b0 < s1; b0 += batch) {
-        const int nb = min(batch, s1 - b0);
-        for (int t = threadIdx.x; t < nb; t += blockDim.x) {
-            const int i = b0 + t;
-            double d[3];
-            for (int q = 0; q < 3; ++q) d[q] = spts[3 * (int64_t)i + q] - X[q];
-            const double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            const double ir = rr > 0 ? 1.0 / rr : 0.0;
-            dd[t * 3] = rr > 0 ? (T)(d[2] * ir) : T(1);
-            dd[t * 3 + 1] = (T)(d[0] * ir);
-            dd[t * 3 + 2] = (T)(d[1] * ir);
-            sph_bessel_j(mk((T)(k_re * rr), (T)(k_im * rr)), N, jb + t * (N + 1));
-            Rb[t * NT + NN] = mk(T(0), T(0));
-            const cx<T> *sr = src + ((int64_t)r * n + i) * 7;
-            for (int q = 0; q < 7; ++q) sv[t * 7 + q] = sr[q];
-            for (int q = 0; q < 3; ++q) nvs[t * 3 + q] = (T)snrm[3 * (int64_t)i + q];
-        }
-        __syncthreads();
-        for (int t = threadIdx.x; t < nb * (N + 1); t += blockDim.x) {
-            const int i = t / (N + 1), m = t % (N + 1);
-            regular_column<T>(dd[3 * i], mk(dd[3 * i + 1], dd[3 * i + 2]), jb + i * (N + 1), bt, m, Rb + i * NT);
-        }
-        __syncthreads();
-        for (int u = 0; u < P2M_SLOTS; ++u) {
-            const int idx = (G > 1) ? ((int)threadIdx.x % P2) : (int)threadIdx.x + u * (int)blockDim.x;
-            if (idx >= P2 || grp >= G || (G > 1 && u > 0)) break;
-            int ix[7];
-            T co[6];
-            for (int q = 0; q < 7; ++q) ix[q] = bt.gix[idx * 7 + q];
-            for (int q = 0; q < 6; ++q) co[q] = bt.gco[idx * 6 + q];
-            for (int i = grp; i < nb; i += G) {
-                const cx<T> *R = Rb + i * NT;
-                const cx<T> Rv = R[ix[6]];                                  // R_n^{-m}
-                const cx<T> dz = co[0] * R[ix[0]] + co[1] * R[ix[1]];
-                const cx<T> dp = co[2] * R[ix[2]] + co[3] * R[ix[3]];
-                const cx<T> dm = co[4] * R[ix[4]] + co[5] * R[ix[5]];
-                const cx<T> df = dp - dm;
-                const cx<T> g[3] = {T(0.5) * (dp + dm), mk(T(0.5) * df.im, T(-0.5) * df.re), dz};   // grad / k
-                const cx<T> *sr = sv + i * 7;
-                const T nv[3] = {nvs[3 * i], nvs[3 * i + 1], nvs[3 * i + 2]};
-                const cx<T> aG = sr[0] * g[0] + sr[1] * g[1] + sr[2] * g[2];
-                const cx<T> nG = nv[0] * g[0] + nv[1] * g[1] + nv[2] * g[2];
-                for (int c = 0; c < 3; ++c) {
-                    accb[u][c] += sr[3 + c] * Rv;
-                    accg[u][c] += nv[c] * aG - sr[c] * nG - sr[6] * g[c];
+    // a leaf that fits one batch builds its tables once for all right-hand sides
+    const bool one = s1 - s0 <= batch;
+    for (int r = 0; r < nrhs; ++r) {
+        cx<T> accb[P2M_SLOTS][3], accg[P2M_SLOTS][3];
+        for (int u = 0; u < P2M_SLOTS; ++u)
+            for (int c = 0; c < 3; ++c) accb[u][c] = accg[u][c] = mk(T(0), T(0));
+        for (int b0 = s0; b0 < s1; b0 += batch) {
+            const int nb = min(batch, s1 - b0);
+            __syncthreads();
+            if (!one || r == 0) {
+                for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+                    const int i = b0 + t;
+                    double d[3];
+                    for (int q = 0; q < 3; ++q) d[q] = spts[3 * (int64_t)i + q] - X[q];
+                    const double rr = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                    const double ir = rr > 0 ? 1.0 / rr : 0.0;
+                    dd[t * 3] = rr > 0 ? (T)(d[2] * ir) : T(1);
+                    dd[t * 3 + 1] = (T)(d[0] * ir);
+                    dd[t * 3 + 2] = (T)(d[1] * ir);
+                    sph_bessel_j(mk((T)(k_re * rr), (T)(k_im * rr)), N, jb + t * (N + 1));
+                    Rb[t * NT + NN] = mk(T(0), T(0));
+                    for (int q = 0; q < 3; ++q) nvs[t * 3 + q] = (T)snrm[3 * (int64_t)i + q];
+                }
+                __syncthreads();
+                for (int t = threadIdx.x; t < nb * (N + 1); t += blockDim.x) {
+                    const int i = t / (N + 1), m = t % (N + 1);
+                    regular_column<T>(dd[3 * i], mk(dd[3 * i + 1], dd[3 * i + 2]), jb + i * (N + 1), bt, m,
+                                      Rb + i * NT);
+                }
+            }
+            for (int t = threadIdx.x; t < nb * 7; t += blockDim.x)
+                sv[t] = src[((int64_t)r * n + b0) * 7 + t];
+            __syncthreads();
+            for (int u = 0; u < P2M_SLOTS; ++u) {
+                const int idx = (G > 1) ? ((int)threadIdx.x % P2) : (int)threadIdx.x + u * (int)blockDim.x;
+                if (idx >= P2 || grp >= G || (G > 1 && u > 0)) break;
+                int ix[7];
+                T co[6];
+                for (int q = 0; q < 7; ++q) ix[q] = bt.gix[idx * 7 + q];
+                for (int q = 0; q < 6; ++q) co[q] = bt.gco[idx * 6 + q];
+                for (int i = grp; i < nb; i += G) {
+                    const cx<T> *R = Rb + i * NT;
+                    const cx<T> Rv = R[ix[6]];                                  // R_n^{-m}
+                    const cx<T> dz = co[0] * R[ix[0]] + co[1] * R[ix[1]];
+                    const cx<T> dp = co[2] * R[ix[2]] + co[3] * R[ix[3]];
+                    const cx<T> dm = co[4] * R[ix[4]] + co[5] * R[ix[5]];
+                    const cx<T> df = dp - dm;
+                    const cx<T> g[3] = {T(0.5) * (dp + dm), mk(T(0.5) * df.im, T(-0.5) * df.re), dz};   // grad / k
+                    const cx<T> *sr = sv + i * 7;
+                    const T nv[3] = {nvs[3 * i], nvs[3 * i + 1], nvs[3 * i + 2]};
+                    const cx<T> aG = sr[0] * g[0] + sr[1] * g[1] + sr[2] * g[2];
+                    const cx<T> nG = nv[0] * g[0] + nv[1] * g[1] + nv[2] * g[2];
+                    for (int c = 0; c < 3; ++c) {
+                        accb[u][c] += sr[3 + c] * Rv;
+                        accg[u][c] += nv[c] * aG - sr[c] * nG - sr[6] * g[c];
+                    }
                 }
             }
         }
-        __syncthreads();
-    }
-    cx<T> acc[P2M_SLOTS][3];
-    for (int u = 0; u < P2M_SLOTS; ++u)
-        for (int c = 0; c < 3; ++c) acc[u][c] = accb[u][c] + k * accg[u][c];
-    if (G > 1) {
-        // sum the node groups in LDS (reuses the table area)
-        cx<T> *red = Rb;                                   // [G][P2][3]
-        if (grp < G)
-            for (int c = 0; c < 3; ++c) red[(grp * P2 + (threadIdx.x % P2)) * 3 + c] = acc[0][c];
-        __syncthreads();
-        if ((int)threadIdx.x < P2) {
-            const int idx = threadIdx.x;
-            int nn = 0;
-            while ((nn + 1) * (nn + 1) <= idx) ++nn;
-            const cx<T> sc = mk((T)(-k_im * inv_alpha[nn]), (T)(k_re * inv_alpha[nn]));   // i k / alpha_n
-            for (int c = 0; c < 3; ++c) {
-                cx<T> s = mk(T(0), T(0));
-                for (int g2 = 0; g2 < G; ++g2) s += red[(g2 * P2 + idx) * 3 + c];
-                M[(((int64_t)box * nrhs_max + r) * 3 + c) * P2 + idx] = sc * s;
+        cx<T> acc[P2M_SLOTS][3];
+        for (int u = 0; u < P2M_SLOTS; ++u)
+            for (int c = 0; c < 3; ++c) acc[u][c] = accb[u][c] + k * accg[u][c];
+        cx<T> *Mo = M + ((int64_t)box * nrhs_max + r) * 3 * P2;
+        if (G > 1) {
+            // sum the node groups in LDS
+            __syncthreads();
+            if (grp < G)
+                for (int c = 0; c < 3; ++c) red[(grp * P2 + (threadIdx.x % P2)) * 3 + c] = acc[0][c];
+            __syncthreads();
+            if ((int)threadIdx.x < P2) {
+                const int idx = threadIdx.x;
+                int nn = 0;
+                while ((nn + 1) * (nn + 1) <= idx) ++nn;
+                const cx<T> sc = mk((T)(-k_im * inv_alpha[nn]), (T)(k_re * inv_alpha[nn]));   // i k / alpha_n
+                for (int c = 0; c < 3; ++c) {
+                    cx<T> s = mk(T(0), T(0));
+                    for (int g2 = 0; g2 < G; ++g2) s += red[(g2 * P2 + idx) * 3 + c];
+                    Mo[c * P2 + idx] = sc * s;
+                }
+            }
+        } else {
+            for (int u = 0; u < P2M_SLOTS; ++u) {
+                const int idx = threadIdx.x + u * blockDim.x;
+                if (idx >= P2) break;
+                int nn = 0;
+                while ((nn + 1) * (nn + 1) <= idx) ++nn;
+                const cx<T> sc = mk((T)(-k_im * inv_alpha[nn]), (T)(k_re * inv_alpha[nn]));   // i k / alpha_n
+                for (int c = 0; c < 3; ++c) Mo[c * P2 + idx] = sc * acc[u][c];
             }
         }
-        return;
-    }
-    for (int u = 0; u < P2M_SLOTS; ++u) {
-        const int idx = threadIdx.x + u * blockDim.x;
-        if (idx >= P2) break;
-        int nn = 0;
-        while ((nn + 1) * (nn + 1) <= idx) ++nn;
-        const cx<T> sc = mk((T)(-k_im * inv_alpha[nn]), (T)(k_re * inv_alpha[nn]));   // i k / alpha_n
-        for (int c = 0; c < 3; ++c)
-            M[(((int64_t)box * nrhs_max + r) * 3 + c) * P2 + idx] = sc * acc[u][c];
     }
 }
 
 // ---------------------------------------------------------------- L2P
-template <typename T>
+// RC right-hand sides per block (blockIdx.y = chunk of RC): each node's basis
+// values are evaluated once and contracted with the RC local expansions.
+template <typename T, int RC>
 __global__ void __launch_bounds__(64) k_l2p(const int32_t *__restrict__ start, const double *__restrict__ center,
                                             const double *__restrict__ spts, int64_t n, int p, double k_re, double k_im,
                                             const double *__restrict__ inv_alpha, const T *__restrict__ tab,
-                                            int nrhs_max, const cx<T> *__restrict__ Lc, cx<T> *__restrict__ ys) {
+                                            int nrhs, int nrhs_max, const cx<T> *__restrict__ Lc,
+                                            cx<T> *__restrict__ ys) {
     extern __shared__ unsigned char smem[];
     const int P2 = p * p;
     const BasisTab<T> bt = basis_tab(tab, (const int32_t *)nullptr, p, P2);
-    cx<T> *Ls = reinterpret_cast<cx<T> *>(smem);        // [3][P2]
-    cx<T> *jb = Ls + 3 * P2;                             // [64][p]
-    const int box = blockIdx.x, r = blockIdx.y;
+    cx<T> *Ls = reinterpret_cast<cx<T> *>(smem);        // [RC][3][P2]
+    cx<T> *jb = Ls + RC * 3 * P2;                        // [64][p]
+    const int box = blockIdx.x, r0 = blockIdx.y * RC;
+    const int rcn = min(RC, nrhs - r0);
     const int s0 = start[box], s1 = start[box + 1];
-    for (int t = threadIdx.x; t < 3 * P2; t += blockDim.x) {
-        int idx = t % P2;
+    for (int t = threadIdx.x; t < RC * 3 * P2; t += blockDim.x) {
+        const int rr = t / (3 * P2), e = t % (3 * P2);
+        const int idx = e % P2;
         int nn = 0;
         while ((nn + 1) * (nn + 1) <= idx) ++nn;
-        Ls[t] = (T)inv_alpha[nn] * Lc[((int64_t)box * nrhs_max + r) * 3 * P2 + t];
+        Ls[t] = rr < rcn ? (T)inv_alpha[nn] * Lc[((int64_t)box * nrhs_max + r0 + rr) * 3 * P2 + e] : mk(T(0), T(0));
     }
     __syncthreads();
     const double X[3] = {center[3 * box], center[3 * box + 1], center[3 * box + 2]};
@@ -279,7 +292,10 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *__restrict__ start, c
         sph_bessel_j(mk((T)(k_re * rr), (T)(k_im * rr)), p - 1, J);
         const T x = rr > 0 ? (T)(d[2] * ir) : T(1);
         const cx<T> w = mk((T)(d[0] * ir), (T)(d[1] * ir));
-        cx<T> acc[3] = {mk(T(0), T(0)), mk(T(0), T(0)), mk(T(0), T(0))};
+        cx<T> acc[RC][3];
+#pragma unroll
+        for (int q = 0; q < RC; ++q)
+            for (int c = 0; c < 3; ++c) acc[q][c] = mk(T(0), T(0));
         cx<T> wm = mk(T(1), T(0));
         for (int m = 0; m < p; ++m) {
             if (m > 0) wm = wm * w;
@@ -297,14 +313,20 @@ __global__ void __launch_bounds__(64) k_l2p(const int32_t *__restrict__ start, c
                 }
                 const cx<T> Y = (sgn * q) * wm;
                 const cx<T> Rp = J[nn] * Y;
-                for (int c = 0; c < 3; ++c) acc[c] += Ls[c * P2 + nn * nn + nn + m] * Rp;
-                if (m > 0) {
-                    const cx<T> Rm = J[nn] * conj(Y);
-                    for (int c = 0; c < 3; ++c) acc[c] += Ls[c * P2 + nn * nn + nn - m] * Rm;
+                const cx<T> Rm = J[nn] * conj(Y);
+#pragma unroll
+                for (int rq = 0; rq < RC; ++rq) {
+                    const cx<T> *L = Ls + rq * 3 * P2;
+                    for (int c = 0; c < 3; ++c) acc[rq][c] += L[c * P2 + nn * nn + nn + m] * Rp;
+                    if (m > 0)
+                        for (int c = 0; c < 3; ++c) acc[rq][c] += L[c * P2 + nn * nn + nn - m] * Rm;
                 }
             }
         }
-        for (int c = 0; c < 3; ++c) ys[((int64_t)r * n + i) * 3 + c] = acc[c];
+#pragma unroll
+        for (int rq = 0; rq < RC; ++rq)
+            if (rq < rcn)
+                for (int c = 0; c < 3; ++c) ys[((int64_t)(r0 + rq) * n + i) * 3 + c] = acc[rq][c];
     }
 }
 
@@ -436,26 +458,37 @@ __global__ void __launch_bounds__(TPB) k_p2p(const int32_t *__restrict__ start, 
 // (-Im k R log2 e); the LOSSY = false instance (real k) skips the decay
 // factor.  Same-triangle pairs are masked, not branched around, so the source
 // loop unrolls.
-struct __attribute__((aligned(16))) SrcRec32 {
+struct __attribute__((aligned(16))) SrcHdr32 {
     float x, y, z;
     int32_t tri;
     float nx, ny, nz, pad;
-    cx<float> rec[8];                      // a[3], b[3], n.a, unused
 };
 
-template <bool LOSSY>
-__global__ void __launch_bounds__(TPB) k_p2p32(int nleaf, const int32_t *__restrict__ start,
+// RC right-hand sides per block (blockIdx.y = chunk of RC): the pair geometry,
+// the transcendentals and g, f are computed once per pair and applied to all
+// RC density sets.  The source tile shrinks as RC grows to keep LDS near 32 KB.
+template <int RC>
+struct P2PTile {
+    static constexpr int TS = RC == 1 ? 256 : (RC == 2 ? 128 : 64);
+};
+
+template <bool LOSSY, int RC>
+__global__ void __launch_bounds__(TPB) k_p2p32(int nleaf, int nrhs, const int32_t *__restrict__ start,
                                                const int32_t *__restrict__ nbr,
                                                const double *__restrict__ center, const double *__restrict__ spts,
                                                const double *__restrict__ snrm, const int32_t *__restrict__ stri,
                                                const cx<float> *__restrict__ src, int64_t n, double k_re,
                                                double k_im, cx<float> *__restrict__ ys) {
-    __shared__ SrcRec32 tile[P2P_TILE];
+    constexpr int TS = P2PTile<RC>::TS;
+    __shared__ SrcHdr32 hdr[TS];
+    __shared__ __attribute__((aligned(16))) cx<float> rec[TS][RC][8];   // a[3], b[3], n.a, unused
+    __shared__ int32_t sid[TS];
     __shared__ int32_t nb_start[28], nb_box[27];
     __shared__ int n_nb;
     __shared__ cx<float> red[TPB][3];
-    const int box = blockIdx.x, r = blockIdx.y;
+    const int box = blockIdx.x, r0 = blockIdx.y * RC;
     if (box >= nleaf) return;
+    const int rcn = min(RC, nrhs - r0);
     const int t0 = start[box], t1 = start[box + 1];
     const int nt = t1 - t0;
     const double c0x = center[3 * box], c0y = center[3 * box + 1], c0z = center[3 * box + 2];
@@ -493,16 +526,19 @@ __global__ void __launch_bounds__(TPB) k_p2p32(int nleaf, const int32_t *__restr
             tz = (float)(spts[3 * ig + 2] - c0z);
             ttri = stri[ig];
         }
-        cx<float> acc[3] = {mk(0.f, 0.f), mk(0.f, 0.f), mk(0.f, 0.f)};
-        for (int base = 0; base < ns_total; base += P2P_TILE) {
-            const int cnt = min(P2P_TILE, ns_total - base);
+        cx<float> acc[RC][3];
+#pragma unroll
+        for (int rr = 0; rr < RC; ++rr)
+            for (int c = 0; c < 3; ++c) acc[rr][c] = mk(0.f, 0.f);
+        for (int base = 0; base < ns_total; base += TS) {
+            const int cnt = min(TS, ns_total - base);
             __syncthreads();
             for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
                 const int u = base + j;
                 int b = 0;
                 while (nb_start[b + 1] <= u) ++b;
                 const int64_t sidx = start[nb_box[b]] + (u - nb_start[b]);
-                SrcRec32 q;
+                SrcHdr32 q;
                 q.x = (float)(spts[3 * sidx] - c0x);
                 q.y = (float)(spts[3 * sidx + 1] - c0y);
                 q.z = (float)(spts[3 * sidx + 2] - c0z);
@@ -511,16 +547,19 @@ __global__ void __launch_bounds__(TPB) k_p2p32(int nleaf, const int32_t *__restr
                 q.ny = (float)snrm[3 * sidx + 1];
                 q.nz = (float)snrm[3 * sidx + 2];
                 q.pad = 0.f;
-                const cx<float> *sr = src + ((int64_t)r * n + sidx) * 7;
-                for (int w = 0; w < 7; ++w) q.rec[w] = sr[w];
-                q.rec[7] = mk(0.f, 0.f);
-                tile[j] = q;
+                hdr[j] = q;
+                sid[j] = (int32_t)sidx;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < cnt * RC * 8; e += blockDim.x) {
+                const int w = e % 8, rr = (e / 8) % RC, j = e / (8 * RC);
+                rec[j][rr][w] = (w < 7 && rr < rcn) ? src[((int64_t)(r0 + rr) * n + sid[j]) * 7 + w] : mk(0.f, 0.f);
             }
             __syncthreads();
             if (!active) continue;
 #pragma unroll 2
             for (int j = sl; j < cnt; j += S) {
-                const SrcRec32 &q = tile[j];
+                const SrcHdr32 &q = hdr[j];
                 const bool self = q.tri == ttri;
                 const float dx = q.x - tx, dy = q.y - ty, dz = q.z - tz;
                 const float R2 = self ? 1.f : dx * dx + dy * dy + dz * dz;
@@ -535,24 +574,32 @@ __global__ void __launch_bounds__(TPB) k_p2p32(int nleaf, const int32_t *__restr
                 const cx<float> f = mk(iR2 * ((-ki * R - 1.f) * g.re - kr * R * g.im),
                                        iR2 * ((-ki * R - 1.f) * g.im + kr * R * g.re));
                 const float v = q.nx * dx + q.ny * dy + q.nz * dz;
-                const cx<float> u = dx * q.rec[0] + dy * q.rec[1] + dz * q.rec[2];
-                const cx<float> wx = q.nx * u - v * q.rec[0] - dx * q.rec[6];
-                const cx<float> wy = q.ny * u - v * q.rec[1] - dy * q.rec[6];
-                const cx<float> wz = q.nz * u - v * q.rec[2] - dz * q.rec[6];
-                acc[0] += f * wx + g * q.rec[3];
-                acc[1] += f * wy + g * q.rec[4];
-                acc[2] += f * wz + g * q.rec[5];
+#pragma unroll
+                for (int rr = 0; rr < RC; ++rr) {
+                    const cx<float> *qr = rec[j][rr];
+                    const cx<float> u = dx * qr[0] + dy * qr[1] + dz * qr[2];
+                    const cx<float> wx = q.nx * u - v * qr[0] - dx * qr[6];
+                    const cx<float> wy = q.ny * u - v * qr[1] - dy * qr[6];
+                    const cx<float> wz = q.nz * u - v * qr[2] - dz * qr[6];
+                    acc[rr][0] += f * wx + g * qr[3];
+                    acc[rr][1] += f * wy + g * qr[4];
+                    acc[rr][2] += f * wz + g * qr[5];
+                }
             }
         }
-        __syncthreads();
-        for (int c = 0; c < 3; ++c) red[threadIdx.x][c] = acc[c];
-        __syncthreads();
-        if (threadIdx.x < ntc) {
-            cx<float> s[3] = {mk(0.f, 0.f), mk(0.f, 0.f), mk(0.f, 0.f)};
-            for (int q = 0; q < S; ++q)
-                for (int c = 0; c < 3; ++c) s[c] += red[q * ntc + threadIdx.x][c];
-            cx<float> *o = ys + ((int64_t)r * n + t0 + tc0 + threadIdx.x) * 3;
-            for (int c = 0; c < 3; ++c) o[c] += s[c];
+        // sum the source slices, one right-hand side at a time
+#pragma unroll
+        for (int rr = 0; rr < RC; ++rr) {
+            __syncthreads();
+            for (int c = 0; c < 3; ++c) red[threadIdx.x][c] = acc[rr][c];
+            __syncthreads();
+            if (threadIdx.x < ntc && rr < rcn) {
+                cx<float> s[3] = {mk(0.f, 0.f), mk(0.f, 0.f), mk(0.f, 0.f)};
+                for (int q = 0; q < S; ++q)
+                    for (int c = 0; c < 3; ++c) s[c] += red[q * ntc + threadIdx.x][c];
+                cx<float> *o = ys + ((int64_t)(r0 + rr) * n + t0 + tc0 + threadIdx.x) * 3;
+                for (int c = 0; c < 3; ++c) o[c] += s[c];
+            }
         }
     }
 }
@@ -670,13 +717,16 @@ __global__ void __launch_bounds__(TPB) k_translate(const Tile *__restrict__ tile
 }
 
 // Large operators (KR > 128 rows in FP64, > 256 in FP32): block tile of
-// BG_M = 128 rows x BG_N = 128 columns, four waves in a 2 x 2 arrangement, each
-// holding 4 x 4 MFMA tiles (64 x 64).  K advances BG_K = 16 at a time; the next
+// BG_M = 128 rows x big_n<T>() columns (64 in FP64, 128 in FP32), four waves in a
+// 2 x 2 arrangement, each holding 4 x (big_n / 32) MFMA tiles.  K advances BG_K = 16 at a time; the next
 // stage's A and B elements are fetched into registers while the MFMAs run on
 // the current LDS buffer, then stored into the other buffer (one barrier per
 // stage).  A is kept row-major in LDS (pitch BG_K + 1), B k-major (pitch
 // BG_N + 1), so fragment reads and the transposing stores avoid bank conflicts.
-constexpr int BG_M = 128, BG_N = 128, BG_K = 16;
+constexpr int BG_M = 128, BG_K = 16;
+// block columns: 64 in FP64 (keeps two waves per SIMD), 128 in FP32
+template <typename T>
+constexpr int big_n() { return sizeof(T) == 8 ? 64 : 128; }
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_translate_big(const Tile *__restrict__ tiles, int ntiles,
@@ -685,6 +735,7 @@ __global__ void __launch_bounds__(TPB) k_translate_big(const Tile *__restrict__ 
                                                        const T *__restrict__ ops, const T *__restrict__ X,
                                                        T *__restrict__ Y, int KR, int ncol, int64_t blkR) {
     typedef typename Mfma<T>::v4 v4;
+    constexpr int BG_N = big_n<T>(), NJ = BG_N / 32;          // 16-column MFMA tiles per wave
     constexpr int AP = BG_K + 1, BP = BG_N + 1;
     constexpr int LA = BG_M * BG_K / TPB, LB = BG_K * BG_N / TPB;   // elements per thread and stage
     __shared__ T As[2][BG_M * AP];
@@ -696,7 +747,7 @@ __global__ void __launch_bounds__(TPB) k_translate_big(const Tile *__restrict__ 
     const int r0 = blockIdx.y * BG_M;
     const T *Top = ops + (size_t)tl.op * KR * KR;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr0 = (wave >> 1) * 64, wc0 = (wave & 1) * 64;
+    const int wr0 = (wave >> 1) * 64, wc0 = (wave & 1) * (BG_N / 2);
     const int Ctot = tl.count * ncol;
     const int nk = (KR + BG_K - 1) / BG_K;
     T pa[LA], pb[LB];
@@ -745,11 +796,11 @@ __global__ void __launch_bounds__(TPB) k_translate_big(const Tile *__restrict__ 
                 Bs[buf][(idx % BG_K) * BP + idx / BG_K] = pb[j];
             }
         };
-        v4 acc[4][4];
+        v4 acc[4][NJ];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = v4{0, 0, 0, 0};
+            for (int j = 0; j < NJ; ++j) acc[i][j] = v4{0, 0, 0, 0};
         fetch(0);
         stash(0);
         __syncthreads();
@@ -759,21 +810,21 @@ __global__ void __launch_bounds__(TPB) k_translate_big(const Tile *__restrict__ 
             const T *A = As[buf], *B = Bs[buf];
 #pragma unroll
             for (int k4 = 0; k4 < BG_K; k4 += 4) {
-                T a[4], b[4];
+                T a[4], b[NJ];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) a[i] = A[(wr0 + 16 * i + (lane & 15)) * AP + k4 + (lane >> 4)];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) b[j] = B[(k4 + (lane >> 4)) * BP + wc0 + 16 * j + (lane & 15)];
+                for (int j = 0; j < NJ; ++j) b[j] = B[(k4 + (lane >> 4)) * BP + wc0 + 16 * j + (lane & 15)];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
+                    for (int j = 0; j < NJ; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
             }
             if (ks + 1 < nk) stash(buf ^ 1);
             __syncthreads();
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NJ; ++j) {
             const int col = wc0 + 16 * j + (lane & 15);
             if (col >= C) continue;
             T *yo = Y + s_out[col];
@@ -1196,34 +1247,32 @@ void launch_translate(const Tile *tiles, int64_t ntiles, const int32_t *ent, con
 
 // parent (level l) multipole = sum of its children's translated slots
 // Column sums of a row range [e0, e1) of slots (rows of blk complex values, the
-// first ncolP2 of which are used) by one block: G = TPB / ncolP2 row groups
-// take rows e0 + g, e0 + g + G, ... and their partial sums are added in group
-// order, so the result does not depend on timing.
+// first ncolP2 of which are used) by one block: columns go in chunks of
+// CW = min(ncolP2, 128); within a chunk G = TPB / CW row groups take rows
+// e0 + g, e0 + g + G, ... and their partial sums are added in group order, so
+// the result does not depend on timing.
 template <typename T>
 __device__ inline void slot_sum(const cx<T> *__restrict__ Y, int e0, int e1, int64_t blk, int ncolP2,
                                 cx<T> *__restrict__ out, bool accumulate, cx<T> *sm) {
     const int t = threadIdx.x;
-    if (ncolP2 * 2 > TPB) {
-        for (int c = t; c < ncolP2; c += TPB) {
-            cx<T> s = mk(T(0), T(0));
-            for (int e = e0; e < e1; ++e) s += Y[(int64_t)e * blk + c];
-            if (accumulate) out[c] += s;
-            else out[c] = s;
+    const int CW = min(ncolP2, 128), G = TPB / CW;
+    const int g = t / CW, c = t % CW;
+    for (int c0 = 0; c0 < ncolP2; c0 += CW) {
+        const int cw = min(CW, ncolP2 - c0);
+        cx<T> s = mk(T(0), T(0));
+        if (g < G && c < cw) {
+#pragma unroll 4
+            for (int e = e0 + g; e < e1; e += G) s += Y[(int64_t)e * blk + c0 + c];
         }
-        return;
-    }
-    const int G = TPB / ncolP2;
-    const int g = t / ncolP2, c = t % ncolP2;
-    cx<T> s = mk(T(0), T(0));
-    if (g < G)
-        for (int e = e0 + g; e < e1; e += G) s += Y[(int64_t)e * blk + c];
-    sm[t] = s;
-    __syncthreads();
-    if (t < ncolP2) {
-        cx<T> tot = sm[t];
-        for (int q = 1; q < G; ++q) tot += sm[q * ncolP2 + t];
-        if (accumulate) out[t] += tot;
-        else out[t] = tot;
+        sm[t] = s;
+        __syncthreads();
+        if (t < cw) {
+            cx<T> tot = sm[t];
+            for (int q = 1; q < G; ++q) tot += sm[q * CW + t];
+            if (accumulate) out[c0 + t] += tot;
+            else out[c0 + t] = tot;
+        }
+        __syncthreads();
     }
 }
 
@@ -1273,14 +1322,15 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
     {
         const int N = p;
         const size_t per = ((size_t)(N + 1) * (N + 2) + 1 + 7) * sizeof(cx<T>) + 6 * sizeof(T);
-        const int batch = (int)std::max<size_t>(1, std::min<size_t>(64, 60000 / per));
-        // the group reduction reuses the table: it needs G * P2 * 3 complex values
+        // LDS: the group-reduction area (G * P2 * 3 complex when G > 1), then per node of a batch
         const int G = P2 <= TPB ? TPB / P2 : 1;
-        const size_t sh = std::max((size_t)batch * per, (size_t)G * P2 * 3 * sizeof(cx<T>));
+        const size_t redb = G > 1 ? (size_t)G * P2 * 3 * sizeof(cx<T>) : 0;
+        const int batch = (int)std::max<size_t>(1, std::min<size_t>(64, (60000 - redb) / per));
+        const size_t sh = redb + (size_t)batch * per;
         tm.begin(ST_P2M, s, ev);
-        k_p2m<T><<<dim3((unsigned)LL.nbox, nrhs), TPB, sh, s>>>(
+        k_p2m<T><<<(unsigned)LL.nbox, TPB, sh, s>>>(
             LL.start.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(), P.snrm.as<double>(), src, n, p, P.k_re,
-            P.k_im, P.inv_alpha.as<double>() + (size_t)L * p, P.btab.as<T>(), P.bgix.as<int32_t>(), P.nrhs_max,
+            P.k_im, P.inv_alpha.as<double>() + (size_t)L * p, P.btab.as<T>(), P.bgix.as<int32_t>(), nrhs, P.nrhs_max,
             batch, LL.M.as<cx<T>>());
         FMB_LAUNCH_CHECK();
         tm.end(ST_P2M, s, ev);
@@ -1335,21 +1385,32 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
     }
     // Step 4: local expansions at the targets, then the near sum
     {
-        const size_t sh = (size_t)3 * P2 * sizeof(cx<T>) + (size_t)64 * p * sizeof(cx<T>);
+        // chunk of right-hand sides per block while their local expansions fit ~24 KB of LDS
+        const size_t lrhs = (size_t)3 * P2 * sizeof(cx<T>);
+        const int rc = (nrhs >= 8 && 8 * lrhs <= 24576) ? 8 : ((nrhs >= 4 && 4 * lrhs <= 24576) ? 4 : 1);
+        const size_t sh = (size_t)rc * lrhs + (size_t)64 * p * sizeof(cx<T>);
+        const dim3 grid((unsigned)LL.nbox, (unsigned)((nrhs + rc - 1) / rc));
+        auto kern = rc == 8 ? k_l2p<T, 8> : (rc == 4 ? k_l2p<T, 4> : k_l2p<T, 1>);
         tm.begin(ST_L2P, s, ev);
-        k_l2p<T><<<dim3((unsigned)LL.nbox, nrhs), 64, sh, s>>>(LL.start.as<int32_t>(), LL.center.as<double>(),
-                                                               P.spts.as<double>(), n, p, P.k_re, P.k_im,
-                                                               P.inv_alpha.as<double>() + (size_t)L * p,
-                                                               P.btab.as<T>(), P.nrhs_max,
-                                                               LL.L.as<cx<T>>(), ys);
+        kern<<<grid, 64, sh, s>>>(LL.start.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(), n, p, P.k_re,
+                                  P.k_im, P.inv_alpha.as<double>() + (size_t)L * p, P.btab.as<T>(), nrhs, P.nrhs_max,
+                                  LL.L.as<cx<T>>(), ys);
         FMB_LAUNCH_CHECK();
         tm.end(ST_L2P, s, ev);
     }
     tm.begin(ST_P2P, s, ev);
     if (sizeof(T) == sizeof(float)) {
-        auto kern = P.k_im != 0.0 ? k_p2p32<true> : k_p2p32<false>;
-        kern<<<dim3((unsigned)LL.nbox, nrhs), TPB, 0, s>>>(
-            (int)LL.nbox, LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(),
+        const bool lossy = P.k_im != 0.0;
+        const int rc = nrhs >= 8 ? 8 : (nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1));
+        decltype(&k_p2p32<true, 1>) kern;
+        switch (rc) {
+            case 8: kern = lossy ? k_p2p32<true, 8> : k_p2p32<false, 8>; break;
+            case 4: kern = lossy ? k_p2p32<true, 4> : k_p2p32<false, 4>; break;
+            case 2: kern = lossy ? k_p2p32<true, 2> : k_p2p32<false, 2>; break;
+            default: kern = lossy ? k_p2p32<true, 1> : k_p2p32<false, 1>; break;
+        }
+        kern<<<dim3((unsigned)LL.nbox, (unsigned)((nrhs + rc - 1) / rc)), TPB, 0, s>>>(
+            (int)LL.nbox, nrhs, LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(),
             P.snrm.as<double>(), P.stri.as<int32_t>(), (const cx<float> *)src, n, P.k_re, P.k_im, (cx<float> *)ys);
     } else
     k_p2p<T><<<dim3((unsigned)LL.nbox, nrhs), TPB, 0, s>>>(LL.start.as<int32_t>(), LL.nbr.as<int32_t>(),
@@ -1387,7 +1448,10 @@ void build_tiles(Plan &P, hipStream_t s) {
     // time is set by the longest chain of gathered loads, not by operator traffic.
     const bool os = use_os(P.precision, P.order, P.nrhs_max);
     const int cols = use_bf3(P) ? bf3_job_cols(P.order)
-                                : (os ? OS_MAXCOLS : (use_big(P.precision, 2 * P.P2) ? BG_N : TN));
+                                : (os ? OS_MAXCOLS
+                                      : (use_big(P.precision, 2 * P.P2)
+                                             ? (P.precision == FMB_FP64 ? big_n<double>() : big_n<float>())
+                                             : TN));
     const int ep_max = std::max(1, cols / (3 * P.nrhs_max));
     const int ep_min = os ? std::max(1, OS_COLS / (3 * P.nrhs_max)) : ep_max;
     auto ep_for = [&](int64_t total) {

@@ -194,6 +194,27 @@ def test_batched_rhs_and_determinism(abi, sphere):
     P.close()
 
 
+@pytest.mark.parametrize("translate,nrhs", [("fp32", 5), ("bf16x3", 8)])
+def test_fp32_batched_rhs_match_single(abi, sphere, translate, nrhs):
+    """FP32 plans with several right-hand sides (the near field shares the pair
+    geometry across a chunk of them; 5 = a chunk of 4 and a ragged chunk of 1):
+    each column equals its single-RHS product to FP32 rounding, and both match
+    the direct sum."""
+    q = sphere
+    n = q["points"].shape[0]
+    a, b = _dens(n, 1, nrhs=nrhs)
+    k = 1.0 + 0.5j
+    print("fp32 batched", translate, nrhs, flush=True)
+    P = _plan(abi, q, k, 8, 3, precision="fp32", corr="none", nrhs_max=nrhs, translate=translate)
+    yb = P.matvec(_gpu(a, torch.complex64), _gpu(b, torch.complex64)).cpu().numpy()
+    for r in range(nrhs):
+        y1 = P.matvec(_gpu(a[r:r + 1], torch.complex64), _gpu(b[r:r + 1], torch.complex64)).cpu().numpy()[0]
+        assert _rel(yb[r], y1) <= 1e-6
+    ref = point_sum_c(q["points"], q["normals"], q["weights"], q["point_tri"], k, a[nrhs - 1], b[nrhs - 1])
+    assert _rel(yb[nrhs - 1], ref) <= 2.5e-4
+    P.close()
+
+
 @pytest.mark.parametrize("k", [4.0, complex(0.5161, 15.5034)])
 def test_torus_full_size_sampled_rows(abi, torus_c2, k):
     """The 60k-node torus at depth 5: FP64 FMM + corrections against the oracle
