@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--order64", type=int, default=16)
     ap.add_argument("--order32", type=int, default=5)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--inner-tol", type=float, default=2e-3)
+    ap.add_argument("--inner-tol", type=float, default=5e-3)
+    ap.add_argument("--restart", type=int, default=150, help="Krylov basis size (inner solves and the FP64 solve)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1500, help="seeded rows of the oracle residual check")
     ap.add_argument("--cpu-sample-rows", type=int, default=0,
@@ -143,7 +144,7 @@ def main():
     rhs = pb.rhs_planewave(d, pol)
 
     def step(serial=args.serial):
-        return pb.solve(rhs, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=100, maxit=2000,
+        return pb.solve(rhs, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=args.restart, maxit=2000,
                         serial=serial)
 
     for _ in range(args.warmup):
@@ -192,10 +193,11 @@ def main():
                          translate32=args.translate32, nrhs_max=args.batch)
         db, pob = plane_waves(args.batch, seed_for(2, "dirs"), seed_for(2, "pols"))
         rb = pbb.rhs_planewave(db, pob)
-        pbb.solve(rb, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=100, maxit=2000)
+        pbb.solve(rb, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=args.restart, maxit=2000)
         torch.cuda.synchronize()
         tb0 = time.perf_counter()
-        _, ib = pbb.solve(rb, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=100, maxit=2000)
+        _, ib = pbb.solve(rb, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=args.restart,
+                          maxit=2000)
         torch.cuda.synchronize()
         tb = time.perf_counter() - tb0
         batched = {"nrhs": args.batch, "rhs_solves_per_s": args.batch / tb, "ms_per_batch": 1e3 * tb,
@@ -209,7 +211,7 @@ def main():
     if not args.skip_fp64_solve:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        x64, inf64 = pb.solve(rhs, tol=args.tol, mixed=False, restart=100, maxit=2000)
+        x64, inf64 = pb.solve(rhs, tol=args.tol, mixed=False, restart=args.restart, maxit=2000)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t1
         log("fp64 solve %.3f s" % t64, inf64["iterations"], inf64["residual"])
@@ -318,7 +320,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "torus_R1_r0.3_20000tri_60000nodes_eps-15+1i_k0R4_depth5_planewave",
                    "nodes": n, "unknowns": 6 * n, "depth": depth, "order_fp64": args.order64,
-                   "order_fp32": args.order32, "translate_fp32": args.translate32, "tol": args.tol},
+                   "order_fp32": args.order32, "translate_fp32": args.translate32, "tol": args.tol,
+                   "restart": args.restart, "inner_tol": args.inner_tol},
         "solve": {"iterations": last["iterations"], "refinements": last["refinements"],
                   "bem_applies_fp32": last["matvecs32"], "bem_applies_fp64": last["matvecs64"],
                   "residual": last["residual"]},

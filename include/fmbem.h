@@ -156,8 +156,9 @@ int fmm_plan_destroy(fmb_plan_t plan);
  * the last read with reset = 1 (the S|R launches of all levels run back to
  * back and share one pair of events).  Stage order (FMB_NSTAGES = 10): gather, P2M,
  * M2M (S|S translation kernel), M2L (S|R translation kernel), L2L (R|R), L2P,
- * P2P, corrections, scatter, sums (the per-target sums of the S|S and S|R
- * translation slots).  ms and launches: host arrays of FMB_NSTAGES entries
+ * P2P, corrections (with the return to user order, plans with corrections),
+ * scatter (the return to user order, plans without corrections), sums (the
+ * per-target sums of the S|S and S|R translation slots).  ms and launches: host arrays of FMB_NSTAGES entries
  * (either may be NULL).
  */
 #define FMB_NSTAGES 10

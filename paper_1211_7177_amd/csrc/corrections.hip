@@ -216,18 +216,27 @@ __global__ void k_corr_build(const double *__restrict__ pts, const double *__res
 
 }  // namespace
 
-// y[alpha] += sum_j [ n_b (dV.a_b) - (n_b.dV) a_b - dV (n_b.a_b) + dG b_b ],  b = tri_nodes[t(alpha)][j]
+// The matvec's last step: y[alpha] = ys[iperm[alpha]] (the FMM result, Morton
+// order, gathered back to user order) plus the self-triangle terms of alpha,
+//   sum_j [ n_b (dV.a_b) - (n_b.dV) a_b - dV (n_b.a_b) + dG b_b ],  b = tri_nodes[t(alpha)][j],
+// in one pass over the nodes.
 template <typename T>
-__global__ void k_corr_apply(const cx<T> *__restrict__ a, const cx<T> *__restrict__ b, cx<T> *__restrict__ y,
-                             const double *__restrict__ unrm, const int32_t *__restrict__ point_tri,
-                             const int32_t *__restrict__ tri_nodes, const cx<double> *__restrict__ cv,
-                             const cx<double> *__restrict__ cg, int64_t n, int m, int nrhs) {
+__global__ void k_scatter_corr(const cx<T> *__restrict__ ys, const int32_t *__restrict__ iperm,
+                               const cx<T> *__restrict__ a, const cx<T> *__restrict__ b, cx<T> *__restrict__ y,
+                               const double *__restrict__ unrm, const int32_t *__restrict__ point_tri,
+                               const int32_t *__restrict__ tri_nodes, const cx<double> *__restrict__ cv,
+                               const cx<double> *__restrict__ cg, int64_t n, int m, int nrhs) {
     int64_t al = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (al >= n) return;
     const int32_t t = point_tri[al];
+    const int64_t im = iperm[al];
     for (int r = 0; r < nrhs; ++r) {
         const int64_t off = (int64_t)r * n;
-        cx<double> acc[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+        cx<double> acc[3];
+        for (int i = 0; i < 3; ++i) {
+            const cx<T> v = ys[(off + im) * 3 + i];
+            acc[i] = mk((double)v.re, (double)v.im);
+        }
         for (int j = 0; j < m; ++j) {
             const int32_t be = tri_nodes[(int64_t)t * m + j];
             const double nb[3] = {unrm[3 * (int64_t)be], unrm[3 * (int64_t)be + 1], unrm[3 * (int64_t)be + 2]};
@@ -244,26 +253,25 @@ __global__ void k_corr_apply(const cx<T> *__restrict__ a, const cx<T> *__restric
             cx<double> na = nb[0] * A[0] + nb[1] * A[1] + nb[2] * A[2];
             for (int i = 0; i < 3; ++i) acc[i] += nb[i] * Va - nV * A[i] - dV[i] * na + dG * B[i];
         }
-        for (int i = 0; i < 3; ++i) {
-            cx<T> &o = y[(off + al) * 3 + i];
-            o.re = (T)((double)o.re + acc[i].re);
-            o.im = (T)((double)o.im + acc[i].im);
-        }
+        for (int i = 0; i < 3; ++i) y[(off + al) * 3 + i] = mk((T)acc[i].re, (T)acc[i].im);
     }
 }
 
-void apply_corrections(Plan &P, const void *a, const void *b, void *y, int nrhs, hipStream_t s) {
+void scatter_with_corrections(Plan &P, const void *ys, const void *a, const void *b, void *y, int nrhs,
+                              hipStream_t s) {
     const unsigned g = (unsigned)((P.n + 255) / 256);
     if (P.precision == FMB_FP64)
-        k_corr_apply<double><<<g, 256, 0, s>>>((const cx<double> *)a, (const cx<double> *)b, (cx<double> *)y,
-                                                P.unrm.as<double>(), P.point_tri.as<int32_t>(),
-                                                P.tri_nodes.as<int32_t>(), P.corr_v.as<cx<double>>(),
-                                                P.corr_g.as<cx<double>>(), P.n, (int)P.tri_m, nrhs);
+        k_scatter_corr<double><<<g, 256, 0, s>>>((const cx<double> *)ys, P.iperm.as<int32_t>(),
+                                                  (const cx<double> *)a, (const cx<double> *)b, (cx<double> *)y,
+                                                  P.unrm.as<double>(), P.point_tri.as<int32_t>(),
+                                                  P.tri_nodes.as<int32_t>(), P.corr_v.as<cx<double>>(),
+                                                  P.corr_g.as<cx<double>>(), P.n, (int)P.tri_m, nrhs);
     else
-        k_corr_apply<float><<<g, 256, 0, s>>>((const cx<float> *)a, (const cx<float> *)b, (cx<float> *)y,
-                                               P.unrm.as<double>(), P.point_tri.as<int32_t>(),
-                                               P.tri_nodes.as<int32_t>(), P.corr_v.as<cx<double>>(),
-                                               P.corr_g.as<cx<double>>(), P.n, (int)P.tri_m, nrhs);
+        k_scatter_corr<float><<<g, 256, 0, s>>>((const cx<float> *)ys, P.iperm.as<int32_t>(), (const cx<float> *)a,
+                                                 (const cx<float> *)b, (cx<float> *)y, P.unrm.as<double>(),
+                                                 P.point_tri.as<int32_t>(), P.tri_nodes.as<int32_t>(),
+                                                 P.corr_v.as<cx<double>>(), P.corr_g.as<cx<double>>(), P.n,
+                                                 (int)P.tri_m, nrhs);
     FMB_LAUNCH_CHECK();
 }
 

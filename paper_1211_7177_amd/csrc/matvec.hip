@@ -639,83 +639,6 @@ struct Mfma<float> {
     __device__ static int row(int lane, int q) { return 4 * (lane >> 4) + q; }
 };
 
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_translate(const Tile *__restrict__ tiles, int ntiles,
-                                                   const int32_t *__restrict__ ent,
-                                                   const int32_t *__restrict__ src_map, const T *__restrict__ ops,
-                                                   const T *__restrict__ X, T *__restrict__ Y, int KR, int ncol,
-                                                   int64_t blkR) {
-    typedef typename Mfma<T>::v4 v4;
-    __shared__ T As[TM][TK + 1];
-    __shared__ T Bs[TK][TN];
-    __shared__ int32_t s_src[TN], s_dst[TN];
-    const int tix = xcd_tile(blockIdx.x, ntiles);
-    if (tix >= ntiles) return;
-    const Tile tl = tiles[tix];
-    const int r0 = blockIdx.y * TM;
-    const T *Top = ops + (size_t)tl.op * KR * KR;
-    for (int q = threadIdx.x; q < tl.count && q < TN; q += blockDim.x) {
-        int32_t e = ent[tl.first + q];
-        s_dst[q] = e;
-        s_src[q] = src_map ? src_map[e] : e;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr0 = (wave >> 1) * 32, wc0 = (wave & 1) * 32;
-    const int Ctot = tl.count * ncol;
-    for (int c0 = 0; c0 < Ctot; c0 += TN) {
-        const int C = min(TN, Ctot - c0);
-        v4 acc[2][2];
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j) acc[i][j] = v4{0, 0, 0, 0};
-        for (int k0 = 0; k0 < KR; k0 += TK) {
-            __syncthreads();
-            for (int t = threadIdx.x; t < TM * TK; t += blockDim.x) {
-                const int rr = t / TK, kk = t % TK;
-                As[rr][kk] = (r0 + rr < KR && k0 + kk < KR) ? Top[(size_t)(r0 + rr) * KR + k0 + kk] : T(0);
-            }
-            for (int t = threadIdx.x; t < TN * TK; t += blockDim.x) {
-                const int c = t / TK, kk = t % TK;
-                T v = T(0);
-                if (c < C && k0 + kk < KR) {
-                    const int cg = c0 + c;
-                    const int e = cg / ncol, cc = cg % ncol;
-                    v = X[(int64_t)s_src[e] * blkR + (int64_t)cc * KR + k0 + kk];
-                }
-                Bs[kk][c] = v;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k4 = 0; k4 < TK; k4 += 4) {
-                T a[2], b[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) a[i] = As[wr0 + 16 * i + (lane & 15)][k4 + (lane >> 4)];
-#pragma unroll
-                for (int j = 0; j < 2; ++j) b[j] = Bs[k4 + (lane >> 4)][wc0 + 16 * j + (lane & 15)];
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
-            }
-        }
-        // lane holds column lane%16 and rows Mfma<T>::row(lane, q) of each 16x16 tile
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int col = wc0 + 16 * j + (lane & 15);
-                if (col >= C) continue;
-                const int cg = c0 + col;
-                const int e = cg / ncol, cc = cg % ncol;
-                T *yo = Y + (int64_t)s_dst[e] * blkR + (int64_t)cc * KR;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int row = r0 + wr0 + 16 * i + Mfma<T>::row(lane, q);
-                    if (row < KR) yo[row] = acc[i][j][q];
-                }
-            }
-    }
-}
-
 // Large operators (KR > 128 rows in FP64, > 256 in FP32): block tile of
 // BG_M = 128 rows x big_n<T>() columns (64 in FP64, 128 in FP32), four waves in a
 // 2 x 2 arrangement, each holding 4 x (big_n / 32) MFMA tiles.  K advances BG_K = 16 at a time; the next
@@ -728,7 +651,7 @@ constexpr int BG_M = 128, BG_K = 16;
 template <typename T>
 constexpr int big_n() { return sizeof(T) == 8 ? 64 : 128; }
 
-template <typename T>
+template <typename T, bool ACCUM>
 __global__ void __launch_bounds__(TPB) k_translate_big(const Tile *__restrict__ tiles, int ntiles,
                                                        const int32_t *__restrict__ ent,
                                                        const int32_t *__restrict__ src_map,
@@ -823,18 +746,35 @@ __global__ void __launch_bounds__(TPB) k_translate_big(const Tile *__restrict__ 
             if (ks + 1 < nk) stash(buf ^ 1);
             __syncthreads();
         }
+        // ACCUM is a template parameter: the overwrite instance carries no loads of Y
+        if (ACCUM) {
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int col = wc0 + 16 * j + (lane & 15);
-            if (col >= C) continue;
-            T *yo = Y + s_out[col];
+            for (int j = 0; j < NJ; ++j) {
+                const int col = wc0 + 16 * j + (lane & 15);
+                if (col >= C) continue;
+                T *yo = Y + s_out[col];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int row = r0 + wr0 + 16 * i + Mfma<T>::row(lane, q);
-                    if (row < KR) yo[row] = acc[i][j][q];
-                }
+                    for (int q = 0; q < 4; ++q) {
+                        const int row = r0 + wr0 + 16 * i + Mfma<T>::row(lane, q);
+                        if (row < KR) yo[row] += acc[i][j][q];
+                    }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int col = wc0 + 16 * j + (lane & 15);
+                if (col >= C) continue;
+                T *yo = Y + s_out[col];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int row = r0 + wr0 + 16 * i + Mfma<T>::row(lane, q);
+                        if (row < KR) yo[row] = acc[i][j][q];
+                    }
+            }
         }
     }
 }
@@ -848,7 +788,7 @@ __global__ void __launch_bounds__(TPB) k_translate_fm(const Tile *__restrict__ t
                                                       const int32_t *__restrict__ ent,
                                                       const int32_t *__restrict__ src_map, const T *__restrict__ ops,
                                                       const T *__restrict__ X, T *__restrict__ Y, int KR, int ncol,
-                                                      int64_t blkR) {
+                                                      int64_t blkR, int accum) {
     typedef typename Mfma<T>::v4 v4;
     __shared__ T As[RT * 16][TK + 1];
     __shared__ T Bs[TK][TN];
@@ -907,7 +847,7 @@ __global__ void __launch_bounds__(TPB) k_translate_fm(const Tile *__restrict__ t
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int row = 16 * i + Mfma<T>::row(lane, q);
-                    if (row < KR) yo[row] = acc[i][q];
+                    if (row < KR) yo[row] = accum ? yo[row] + acc[i][q] : acc[i][q];
                 }
         }
     }
@@ -926,7 +866,7 @@ __global__ void __launch_bounds__(TPB) k_translate_os(const Tile *__restrict__ t
                                                       const int32_t *__restrict__ ent,
                                                       const int32_t *__restrict__ src_map,
                                                       const float *__restrict__ ops, const float *__restrict__ X,
-                                                      float *__restrict__ Y, int KR, int ncol, int64_t blkR) {
+                                                      float *__restrict__ Y, int KR, int ncol, int64_t blkR, int accum) {
     constexpr int KP = KS * 4;                     // K padded to whole MFMA k-steps
     constexpr int LD = (KP * OS_COLS + TPB - 1) / TPB;
     typedef typename Mfma<float>::v4 v4;
@@ -997,7 +937,7 @@ __global__ void __launch_bounds__(TPB) k_translate_os(const Tile *__restrict__ t
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int row = (wave * RTW + i) * 16 + Mfma<float>::row(lane, q);
-                    if (row < KR) yo[row] = acc[i][q];
+                    if (row < KR) yo[row] = accum ? yo[row] + acc[i][q] : acc[i][q];
                 }
         }
         if (t + 1 < ntc) stash(buf ^ 1);
@@ -1044,7 +984,7 @@ __global__ void __launch_bounds__(TPB) k_translate_bf3(const Tile *__restrict__ 
                                                        const bf16x8 *__restrict__ fhi,
                                                        const bf16x8 *__restrict__ flo, const float *__restrict__ X,
                                                        float *__restrict__ Y, int KR, int RT, int ncol,
-                                                       int64_t blkR) {
+                                                       int64_t blkR, int accum) {
     constexpr int KP = KS * 32;
     constexpr int CS = KP + 4;                                   // LDS column stride (floats)
     constexpr int LD = (KP * JC + TPB - 1) / TPB;
@@ -1134,7 +1074,8 @@ __global__ void __launch_bounds__(TPB) k_translate_bf3(const Tile *__restrict__ 
         const int cn = min(16, C - 16 * t);
         for (int e = threadIdx.x; e < cn * KR; e += TPB) {
             const int c = e / KR, row = e % KR;
-            Y[s_out[16 * t + c] + row] = Os[c][row];
+            float *yo = Y + s_out[16 * t + c] + row;
+            *yo = accum ? *yo + Os[c][row] : Os[c][row];
         }
         __syncthreads();
     }
@@ -1166,24 +1107,25 @@ __global__ void k_split_bf16(const float *__restrict__ T, int nops, int KR, int 
 template <int ROLE>
 void launch_bf3(int p, unsigned g, const Tile *tiles, int64_t ntiles, const int32_t *ent, const int32_t *src_map,
                 const bf16x8 *h, const bf16x8 *l, const float *x, float *y, int KR, int RT, int ncol, int64_t blkR,
-                hipStream_t s) {
+                int accum, hipStream_t s) {
     const int nt = (int)ntiles;
     switch (p) {
         case 2:
         case 3:
-        case 4: k_translate_bf3<1, 1, 96, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-        case 5: k_translate_bf3<2, 1, 96, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-        case 6: k_translate_bf3<3, 2, 64, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+        case 4: k_translate_bf3<1, 1, 96, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, accum); break;
+        case 5: k_translate_bf3<2, 1, 96, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, accum); break;
+        case 6: k_translate_bf3<3, 2, 64, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, accum); break;
         case 7:
-        case 8: k_translate_bf3<4, 2, 64, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
-        default: k_translate_bf3<6, 3, 32, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR); break;
+        case 8: k_translate_bf3<4, 2, 64, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, accum); break;
+        default: k_translate_bf3<6, 3, 32, ROLE><<<g, TPB, 0, s>>>(tiles, nt, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, accum); break;
     }
 }
 
-// role: 0 S|S, 1 S|R, 2 R|R (names the split-BF16 launches in kernel traces)
+// role: 0 S|S, 1 S|R, 2 R|R (names the split-BF16 launches in kernel traces);
+// accum: add the products into Y instead of overwriting it
 template <typename T>
 void launch_translate(const Tile *tiles, int64_t ntiles, const int32_t *ent, const int32_t *src_map, const T *ops,
-                      const T *X, T *Y, int KR, int ncol, int64_t blkR, bool os, hipStream_t s, int role,
+                      const T *X, T *Y, int KR, int ncol, int64_t blkR, bool os, hipStream_t s, int role, int accum,
                       const void *fhi = nullptr, const void *flo = nullptr) {
     if (ntiles <= 0) return;
     if (fhi) {
@@ -1199,9 +1141,9 @@ void launch_translate(const Tile *tiles, int64_t ntiles, const int32_t *ent, con
         const float *x = (const float *)X;
         float *y = (float *)Y;
         switch (role) {
-            case 0: launch_bf3<0>(p, g, tiles, ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, s); break;
-            case 1: launch_bf3<1>(p, g, tiles, ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, s); break;
-            default: launch_bf3<2>(p, g, tiles, ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, s); break;
+            case 0: launch_bf3<0>(p, g, tiles, ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, accum, s); break;
+            case 1: launch_bf3<1>(p, g, tiles, ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, accum, s); break;
+            default: launch_bf3<2>(p, g, tiles, ntiles, ent, src_map, h, l, x, y, KR, RT, ncol, blkR, accum, s); break;
         }
         FMB_LAUNCH_CHECK();
         return;
@@ -1214,21 +1156,21 @@ void launch_translate(const Tile *tiles, int64_t ntiles, const int32_t *ent, con
         float *y = (float *)Y;
         const int p = (int)lround(sqrt(KR / 2.0));
         switch (p) {
-            case 2: k_translate_os<2, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
-            case 3: k_translate_os<5, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
-            case 4: k_translate_os<8, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
-            case 5: k_translate_os<13, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
-            case 6: k_translate_os<18, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
-            case 7: k_translate_os<25, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
-            case 8: k_translate_os<32, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
-            default: k_translate_os<41, 3><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR); break;
+            case 2: k_translate_os<2, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR, accum); break;
+            case 3: k_translate_os<5, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR, accum); break;
+            case 4: k_translate_os<8, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR, accum); break;
+            case 5: k_translate_os<13, 1><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR, accum); break;
+            case 6: k_translate_os<18, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR, accum); break;
+            case 7: k_translate_os<25, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR, accum); break;
+            case 8: k_translate_os<32, 2><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR, accum); break;
+            default: k_translate_os<41, 3><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, o, x, y, KR, ncol, blkR, accum); break;
         }
         FMB_LAUNCH_CHECK();
         return;
     }
 #define FMB_FM(R)                                                                                                   \
     case R:                                                                                                         \
-        k_translate_fm<T, R><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, ops, X, Y, KR, ncol, blkR);        \
+        k_translate_fm<T, R><<<g, TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, ops, X, Y, KR, ncol, blkR, accum); \
         break;
     if (!use_big(sizeof(T) == 4 ? FMB_FP32 : FMB_FP64, KR)) {
         switch (rt) {
@@ -1238,8 +1180,12 @@ void launch_translate(const Tile *tiles, int64_t ntiles, const int32_t *ent, con
         }
     } else {
         const unsigned rowblocks = (unsigned)((KR + BG_M - 1) / BG_M);
-        k_translate_big<T><<<dim3(g, rowblocks), TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, ops, X, Y, KR, ncol,
-                                                             blkR);
+        if (accum)
+            k_translate_big<T, true><<<dim3(g, rowblocks), TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, ops, X, Y, KR,
+                                                                        ncol, blkR);
+        else
+            k_translate_big<T, false><<<dim3(g, rowblocks), TPB, 0, s>>>(tiles, (int)ntiles, ent, src_map, ops, X, Y,
+                                                                         KR, ncol, blkR);
     }
 #undef FMB_FM
     FMB_LAUNCH_CHECK();
@@ -1286,13 +1232,27 @@ __global__ void __launch_bounds__(TPB) k_sum_children(const int32_t *__restrict_
     slot_sum(Yc, child_start[b], child_start[b + 1], blk, ncolP2, Mp + b * blk, false, sm);
 }
 
-// target local (+)= sum over its far-field slots
+// The S|R slot sums of every level in one launch: block b belongs to the level
+// l with box0[l] <= b < box0[l + 1]; that level's box b - box0[l] sums its
+// slots into its local expansion (overwriting it).
+struct FarSumLevels {
+    int nlev;
+    int64_t box0[MAX_DEPTH + 2];
+    const int32_t *ff_ofs[MAX_DEPTH + 1];
+    int64_t slot_base[MAX_DEPTH + 1];
+    void *L[MAX_DEPTH + 1];
+};
+
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_sum_far(const int32_t *__restrict__ ff_ofs, const cx<T> *__restrict__ Yf,
-                                                 cx<T> *__restrict__ Lc, int64_t blk, int ncolP2, int accumulate) {
+__global__ void __launch_bounds__(TPB) k_sum_far_all(FarSumLevels lv, const cx<T> *__restrict__ Yf, int64_t blk,
+                                                     int ncolP2) {
     __shared__ cx<T> sm[TPB];
-    const int64_t b = blockIdx.x;
-    slot_sum(Yf, ff_ofs[b], ff_ofs[b + 1], blk, ncolP2, Lc + b * blk, accumulate != 0, sm);
+    const int64_t gb = blockIdx.x;
+    int l = 0;
+    while (l + 1 < lv.nlev && lv.box0[l + 1] <= gb) ++l;
+    const int64_t b = gb - lv.box0[l];
+    const int32_t *ofs = lv.ff_ofs[l];
+    slot_sum(Yf + lv.slot_base[l] * blk, ofs[b], ofs[b + 1], blk, ncolP2, (cx<T> *)lv.L[l] + b * blk, false, sm);
 }
 
 inline unsigned gridn(int64_t m, int tpb = TPB) { return (unsigned)((m + tpb - 1) / tpb); }
@@ -1341,7 +1301,7 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
         if (V.ntiles_m2m == 0) continue;
         tm.begin(ST_M2M, s, ev);
         launch_translate<T>(V.tiles_m2m.as<Tile>(), V.ntiles_m2m, C.by_octant.as<int32_t>(), nullptr, V.m2m.as<T>(),
-                            (const T *)C.M.p, (T *)yb, KR, ncol, blkR, os, s, 0, bf3 ? V.m2m_hi.p : nullptr,
+                            (const T *)C.M.p, (T *)yb, KR, ncol, blkR, os, s, 0, 0, bf3 ? V.m2m_hi.p : nullptr,
                             V.m2m_lo.p);
         tm.end(ST_M2M, s, ev);
         tm.begin(ST_SUMS, s, ev);
@@ -1360,28 +1320,40 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
             if (V.ntiles_m2l == 0) continue;
             launch_translate<T>(V.tiles_m2l.as<Tile>(), V.ntiles_m2l, V.ff_by_op.as<int32_t>(), V.ff_src.as<int32_t>(),
                                 V.m2l.as<T>(), (const T *)V.M.p, (T *)(yb + V.slot_base * blk), KR, ncol, blkR, os, s,
-                                1, bf3 ? V.m2l_hi.p : nullptr, V.m2l_lo.p);
+                                1, 0, bf3 ? V.m2l_hi.p : nullptr, V.m2l_lo.p);
             ++nk;
         }
         tm.end(ST_M2L, s, ev, nk);
     }
-    // Step 3b: downward pass, levels 2 .. L: R|R from the parent, then the level's S|R slot sums
-    for (int l = 2; l <= L; ++l) {
-        Level &V = P.lv[l];
-        if (l >= 3 && V.ntiles_l2l > 0) {
-            Level &U = P.lv[l - 1];
-            tm.begin(ST_L2L, s, ev);
-            launch_translate<T>(V.tiles_l2l.as<Tile>(), V.ntiles_l2l, V.by_octant.as<int32_t>(), V.parent.as<int32_t>(),
-                                V.l2l.as<T>(), (const T *)U.L.p, (T *)V.L.p, KR, ncol, blkR, os, s, 2,
-                                bf3 ? V.l2l_hi.p : nullptr, V.l2l_lo.p);
-            FMB_LAUNCH_CHECK();
-            tm.end(ST_L2L, s, ev);
+    // Step 3b: the S|R slot sums of every level (one launch, overwriting L),
+    // then R|R from the parent added into each level in turn
+    {
+        FarSumLevels fs{};
+        fs.nlev = L - 1;
+        int64_t tot = 0;
+        for (int l = 2; l <= L; ++l) {
+            Level &V = P.lv[l];
+            fs.box0[l - 2] = tot;
+            fs.ff_ofs[l - 2] = V.ff_ofs.as<int32_t>();
+            fs.slot_base[l - 2] = V.slot_base;
+            fs.L[l - 2] = V.L.p;
+            tot += V.nbox;
         }
+        fs.box0[L - 1] = tot;
         tm.begin(ST_SUMS, s, ev);
-        k_sum_far<T><<<(unsigned)V.nbox, TPB, 0, s>>>(V.ff_ofs.as<int32_t>(), yb + V.slot_base * blk, V.L.as<cx<T>>(),
-                                                      blk, ncol * P2, l >= 3 ? 1 : 0);
+        k_sum_far_all<T><<<(unsigned)tot, TPB, 0, s>>>(fs, yb, blk, ncol * P2);
         FMB_LAUNCH_CHECK();
         tm.end(ST_SUMS, s, ev);
+    }
+    for (int l = 3; l <= L; ++l) {
+        Level &V = P.lv[l];
+        if (V.ntiles_l2l == 0) continue;
+        Level &U = P.lv[l - 1];
+        tm.begin(ST_L2L, s, ev);
+        launch_translate<T>(V.tiles_l2l.as<Tile>(), V.ntiles_l2l, V.by_octant.as<int32_t>(), V.parent.as<int32_t>(),
+                            V.l2l.as<T>(), (const T *)U.L.p, (T *)V.L.p, KR, ncol, blkR, os, s, 2, 1,
+                            bf3 ? V.l2l_hi.p : nullptr, V.l2l_lo.p);
+        tm.end(ST_L2L, s, ev);
     }
     // Step 4: local expansions at the targets, then the near sum
     {
@@ -1418,14 +1390,16 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
                                                           src, n, P.k_re, P.k_im, ys);
     FMB_LAUNCH_CHECK();
     tm.end(ST_P2P, s, ev);
-    tm.begin(ST_SCATTER, s, ev);
-    k_scatter_out<T><<<gridn(n), TPB, 0, s>>>(ys, P.perm.as<int32_t>(), n, nrhs, y);
-    FMB_LAUNCH_CHECK();
-    tm.end(ST_SCATTER, s, ev);
     if (P.corr_mode != FMB_CORR_NONE) {
+        // back to user order with the self-triangle terms added in the same pass
         tm.begin(ST_CORR, s, ev);
-        apply_corrections(P, a, b, y, nrhs, s);
+        scatter_with_corrections(P, ys, a, b, y, nrhs, s);
         tm.end(ST_CORR, s, ev);
+    } else {
+        tm.begin(ST_SCATTER, s, ev);
+        k_scatter_out<T><<<gridn(n), TPB, 0, s>>>(ys, P.perm.as<int32_t>(), n, nrhs, y);
+        FMB_LAUNCH_CHECK();
+        tm.end(ST_SCATTER, s, ev);
     }
 }
 

@@ -108,7 +108,8 @@ void gather_nodes(Plan &P, const double *d_pts, const double *d_nrm, const doubl
 void build_operators(Plan &P, hipStream_t s);
 void build_corrections(Plan &P, const double *d_pts, const double *d_nrm, const double *d_tri,
                        hipStream_t s);
-void apply_corrections(Plan &P, const void *a, const void *b, void *y, int nrhs, hipStream_t s);
+void scatter_with_corrections(Plan &P, const void *ys, const void *a, const void *b, void *y, int nrhs,
+                              hipStream_t s);
 // matvec (matvec.hip)
 void run_matvec(Plan &P, const void *a, const void *b, void *y, int nrhs, hipStream_t s);
 

@@ -208,6 +208,37 @@ __global__ void k_precond_apply(const cx<T> *__restrict__ minv, const cx<T> *__r
     }
 }
 
+// z = M^{-1} v per node (the block preconditioner) and, in the same pass, the
+// split of z into the densities of the two plans (as k_bem_split)
+template <typename T>
+__global__ void k_precond_split(const cx<T> *__restrict__ minv, const cx<T> *__restrict__ v, cx<T> *__restrict__ z,
+                                const double *__restrict__ nrm, int64_t n, int nrhs, cx<double> tcd,
+                                cx<double> gammad, cx<T> *__restrict__ a0, cx<T> *__restrict__ b0,
+                                cx<T> *__restrict__ a1, cx<T> *__restrict__ b1) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * nrhs) return;
+    const int64_t node = i % n;
+    const cx<T> *M = minv + node * 36;
+    const cx<T> *vi = v + i * 6;
+    cx<T> in[6], x[6];
+    for (int q = 0; q < 6; ++q) in[q] = vi[q];
+    for (int r = 0; r < 6; ++r) {
+        cx<T> s = mk(T(0), T(0));
+        for (int q = 0; q < 6; ++q) s += M[r * 6 + q] * in[q];
+        x[r] = s;
+        z[i * 6 + r] = s;
+    }
+    const cx<T> tc = narrow<T>(tcd), gamma = narrow<T>(gammad);
+    const T nv[3] = {(T)nrm[3 * node], (T)nrm[3 * node + 1], (T)nrm[3 * node + 2]};
+    const cx<T> d = nv[0] * x[0] + nv[1] * x[1] + nv[2] * x[2];
+    for (int c = 0; c < 3; ++c) {
+        a0[i * 3 + c] = x[c];
+        b0[i * 3 + c] = -x[3 + c];
+        a1[i * 3 + c] = x[c] + (nv[c] * tc) * d;
+        b1[i * 3 + c] = -(gamma * x[3 + c]);
+    }
+}
+
 __global__ void k_rhs_planewave(const double *__restrict__ spts, const int32_t *__restrict__ iperm,
                                 const double *__restrict__ dirs, const double *__restrict__ pols, int64_t n, int nrhs,
                                 double k_re, double k_im, cx<double> *__restrict__ rhs) {
@@ -548,9 +579,12 @@ static void fmm_pair(fmb_problem_s &pb, const Plan *P0, const Plan *P1, const cx
     FMB_CHECK_HIP(hipStreamWaitEvent(s, pb.ev_join, 0));
 }
 
-// A x with the FP64 plans (T = double) or the FP32 plans (T = float)
+// A x with the FP64 plans (T = double) or the FP32 plans (T = float).  With
+// pre = v, x is first set to M^{-1} v (the preconditioned direction), fused
+// with the split.
 template <typename T>
-static void bem_apply_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int nrhs, hipStream_t s) {
+static void bem_apply_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int nrhs, hipStream_t s,
+                        const cx<T> *pre = nullptr) {
     const int64_t n = pb.n;
     const cx<double> tc = cdiv(mk(1.0, 0.0) - pb.eps, pb.eps);
     const double *nrm = pb.p0->p.unrm.as<double>();
@@ -558,7 +592,14 @@ static void bem_apply_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int nrhs, h
     cx<T> *a0 = (f32 ? pb.a0s : pb.a0).template as<cx<T>>(), *b0 = (f32 ? pb.b0s : pb.b0).template as<cx<T>>(),
           *a1 = (f32 ? pb.a1s : pb.a1).template as<cx<T>>(), *b1 = (f32 ? pb.b1s : pb.b1).template as<cx<T>>(),
           *y0 = (f32 ? pb.y0s : pb.y0).template as<cx<T>>(), *y1 = (f32 ? pb.y1s : pb.y1).template as<cx<T>>();
-    k_bem_split<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, tc, pb.gamma, a0, b0, a1, b1);
+    if (pre) {
+        const bool f32m = sizeof(T) == sizeof(float);
+        k_precond_split<T><<<gridn(n * nrhs), TPB, 0, s>>>((f32m ? pb.minv32 : pb.minv).template as<cx<T>>(), pre,
+                                                            const_cast<cx<T> *>(x), nrm, n, nrhs, tc, pb.gamma, a0,
+                                                            b0, a1, b1);
+    } else {
+        k_bem_split<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, tc, pb.gamma, a0, b0, a1, b1);
+    }
     FMB_LAUNCH_CHECK();
     const Plan *P0 = f32 ? &pb.p032->p : &pb.p0->p, *P1 = f32 ? &pb.p132->p : &pb.p1->p;
     fmm_pair<T>(pb, P0, P1, a0, b0, y0, a1, b1, y1, nrhs, s);
@@ -625,9 +666,12 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
         for (int r = 0; r < nrhs; ++r) jr[r] = 0;
         for (int j = 0; j < m && its < maxit; ++j) {
             cx<T> *vj = V + (int64_t)j * tot, *zj = Z + (int64_t)j * tot;
-            if (precond) precond_t<T>(pb, vj, zj, nrhs, s);
-            else FMB_CHECK_HIP(hipMemcpyAsync(zj, vj, tot * sizeof(cx<T>), hipMemcpyDeviceToDevice, s));
-            bem_apply_t<T>(pb, zj, W, nrhs, s);
+            if (precond) {
+                bem_apply_t<T>(pb, zj, W, nrhs, s, vj);      // z_j = M^{-1} v_j fused with the split
+            } else {
+                FMB_CHECK_HIP(hipMemcpyAsync(zj, vj, tot * sizeof(cx<T>), hipMemcpyDeviceToDevice, s));
+                bem_apply_t<T>(pb, zj, W, nrhs, s);
+            }
             ++matvecs;
             // classical Gram-Schmidt; the same pass yields |A z|^2 as h[j+1], the
             // update yields |W'|^2
