@@ -208,6 +208,15 @@ int fmb_gmres_opts_default(fmb_gmres_opts *opts);
 int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_t p1_32,
                        const double *eps, const double *mu, void *stream, fmb_problem_t *out);
 
+/*
+ * bem_problem_use_graphs: enable (1, the default) or disable (0) the replay of
+ * the two FMM products of each application from a captured HIP graph.  The
+ * graph is captured on first use per precision and rhs count, on a stream the
+ * problem owns, ordered after and before the caller's stream by events; plans
+ * with stage timers on always run eagerly.  Results are identical either way.
+ */
+int bem_problem_use_graphs(fmb_problem_t pb, int32_t enable);
+
 /* bem_apply: r = A x, x and r device c128 [nrhs][n][6]. */
 int bem_apply(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, void *stream);
 

@@ -43,11 +43,26 @@ struct fmb_problem_s {
     // second stream (default priority) for the k1 product, and the fork/join events
     hipStream_t s2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    bool serial = false;       // both products on the caller's stream (set per solve)
+    bool serial = false;       // both products on one stream (set per solve)
+    // The two FMM products of an application, captured once per precision and
+    // rhs count as a HIP graph and replayed on the problem's own stream s1
+    // (the caller's stream may be the legacy default stream, which cannot be
+    // captured); ev_in / ev_out order s1 after and before the caller's stream.
+    bool graphs = true;
+    hipStream_t s1 = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    struct PairGraph {
+        hipGraphExec_t exec = nullptr;
+        int nrhs = 0;
+        bool serial = false;
+    } g64, g32;
     ~fmb_problem_s() {
-        if (ev_fork) (void)hipEventDestroy(ev_fork);
-        if (ev_join) (void)hipEventDestroy(ev_join);
+        for (PairGraph *g : {&g64, &g32})
+            if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        for (hipEvent_t e : {ev_fork, ev_join, ev_in, ev_out})
+            if (e) (void)hipEventDestroy(e);
         if (s2) (void)hipStreamDestroy(s2);
+        if (s1) (void)hipStreamDestroy(s1);
     }
 };
 
@@ -415,10 +430,14 @@ __global__ void k_sub(const cx<T> *__restrict__ b, const cx<T> *__restrict__ ax,
 // the residual estimate.  |A z| (for the breakdown test) is sqrt of h[j+1] =
 // (A z)^H (A z), the extra inner product of the first Gram-Schmidt pass.  The
 // column and the rotations are staged in LDS; one thread applies them in order.
+// The residual estimate and the breakdown flag go straight to host-mapped
+// memory (hres, hbrk), and a rhs whose estimate reached tol |b| (bnd) or that
+// broke down is retired here (active = 0); the host applies the same rule to
+// the same values.
 __global__ void k_givens(cx<double> *__restrict__ H, int ldh, int j, const cx<double> *__restrict__ h,
                          const double *__restrict__ hn, double *__restrict__ cs, cx<double> *__restrict__ sn,
-                         cx<double> *__restrict__ g, double *__restrict__ res, int32_t *__restrict__ active,
-                         int32_t *__restrict__ brk, int nrhs, int m) {
+                         cx<double> *__restrict__ g, int32_t *__restrict__ active, const double *__restrict__ bnd,
+                         double tol, double *__restrict__ hres, int32_t *__restrict__ hbrk, int nrhs, int m) {
     extern __shared__ unsigned char gsm[];
     cx<double> *col = reinterpret_cast<cx<double> *>(gsm);          // [j+2]
     cx<double> *ssn = col + (j + 2);                                 // [j]
@@ -459,8 +478,11 @@ __global__ void k_givens(cx<double> *__restrict__ H, int ldh, int j, const cx<do
         cx<double> gj = g[r * (m + 1) + j];
         g[r * (m + 1) + j + 1] = -(conj(s) * gj);
         g[r * (m + 1) + j] = c * gj;
-        res[r] = sqrt(abs2(g[r * (m + 1) + j + 1]));
-        brk[r] = (hn[r] <= 1e-14 * nAz) ? 1 : 0;
+        const double res = sqrt(abs2(g[r * (m + 1) + j + 1]));
+        const int32_t brk = (hn[r] <= 1e-14 * nAz) ? 1 : 0;
+        hres[r] = res;
+        hbrk[r] = brk;
+        if (res <= tol * bnd[r] || brk) active[r] = 0;
     }
     __syncthreads();
     cx<double> *Hc = H + (int64_t)r * ldh * m + (int64_t)j * ldh;   // column-major [m][ldh]
@@ -492,12 +514,32 @@ __global__ void k_sqrt_real(const cx<double> *__restrict__ in, double *__restric
     if (inv) inv[i] = v > 0 ? 1.0 / v : 0.0;
 }
 
+// host memory the device writes directly (allocated pinned and mapped)
+struct HostMapped {
+    void *h = nullptr, *d = nullptr;
+    HostMapped() = default;
+    HostMapped(const HostMapped &) = delete;
+    HostMapped &operator=(const HostMapped &) = delete;
+    void alloc(size_t bytes) {
+        release();
+        FMB_CHECK_HIP(hipHostMalloc(&h, bytes, hipHostMallocMapped));
+        FMB_CHECK_HIP(hipHostGetDevicePointer(&d, h, 0));
+    }
+    void release() {
+        if (h) (void)hipHostFree(h);
+        h = d = nullptr;
+    }
+    ~HostMapped() { release(); }
+};
+
 template <typename T>
 struct Krylov {
     int64_t len = 0;
     int nrhs = 0, m = 0, nchc = 0;
+    HostMapped step;   // per Arnoldi step: double res[nrhs], int32 brk[nrhs]
+    DevBuf bnd;        // |b| per rhs (device copy of the values the host holds)
     DevBuf V, Z, W, r, ax;                                            // cx<T>
-    DevBuf H, cs, sn, g, h, h2, hn, hninv, res, part, npart, act, brk, jr, y, tmp, need;   // FP64 / int32
+    DevBuf H, cs, sn, g, h, h2, hn, hninv, part, npart, act, jr, y, tmp, need;   // FP64 / int32
 };
 
 // out[i][r] = V_i[r]^H W[r] for i < nv, plus X[r]^H W[r] as entry nv when X is given
@@ -549,14 +591,14 @@ void krylov_alloc(Krylov<T> &K, int64_t len, int nrhs, int m) {
     K.y.alloc((size_t)(m + 1) * nrhs * sizeof(cx<double>));
     K.hn.alloc(nrhs * sizeof(double));
     K.hninv.alloc(nrhs * sizeof(double));
-    K.res.alloc(nrhs * sizeof(double));
     K.act.alloc(nrhs * sizeof(int32_t));
-    K.brk.alloc(nrhs * sizeof(int32_t));
     K.jr.alloc(nrhs * sizeof(int32_t));
     K.need.alloc(nrhs * sizeof(int32_t));
     K.tmp.alloc((size_t)(m + 2) * nrhs * sizeof(cx<double>));
     K.part.alloc((size_t)(m + 2) * nrhs * DOT_CHUNKS * sizeof(cx<double>));
     K.npart.alloc((size_t)nrhs * K.nchc * sizeof(double));
+    K.bnd.alloc(nrhs * sizeof(double));
+    K.step.alloc((size_t)nrhs * (sizeof(double) + sizeof(int32_t)));
 }
 
 }  // namespace
@@ -564,8 +606,8 @@ void krylov_alloc(Krylov<T> &K, int64_t len, int nrhs, int m) {
 // The two FMM products of one BEM application run concurrently: the k1 plan
 // on the problem's second stream, forked from and joined back into s.
 template <typename T>
-static void fmm_pair(fmb_problem_s &pb, const Plan *P0, const Plan *P1, const cx<T> *a0, const cx<T> *b0, cx<T> *y0,
-                     const cx<T> *a1, const cx<T> *b1, cx<T> *y1, int nrhs, hipStream_t s) {
+static void fmm_pair_eager(fmb_problem_s &pb, const Plan *P0, const Plan *P1, const cx<T> *a0, const cx<T> *b0,
+                           cx<T> *y0, const cx<T> *a1, const cx<T> *b1, cx<T> *y1, int nrhs, hipStream_t s) {
     if (pb.serial) {
         run_matvec(*const_cast<Plan *>(P0), a0, b0, y0, nrhs, s);
         run_matvec(*const_cast<Plan *>(P1), a1, b1, y1, nrhs, s);
@@ -577,6 +619,42 @@ static void fmm_pair(fmb_problem_s &pb, const Plan *P0, const Plan *P1, const cx
     run_matvec(*const_cast<Plan *>(P1), a1, b1, y1, nrhs, pb.s2);
     FMB_CHECK_HIP(hipEventRecord(pb.ev_join, pb.s2));
     FMB_CHECK_HIP(hipStreamWaitEvent(s, pb.ev_join, 0));
+}
+
+// The two products, replayed from a captured graph (one launch instead of
+// some fifty) unless graphs are off or a plan's stage timers are on.
+template <typename T>
+static void fmm_pair(fmb_problem_s &pb, const Plan *P0, const Plan *P1, const cx<T> *a0, const cx<T> *b0, cx<T> *y0,
+                     const cx<T> *a1, const cx<T> *b1, cx<T> *y1, int nrhs, hipStream_t s) {
+    if (!pb.graphs || P0->timer.mask || P1->timer.mask) {
+        fmm_pair_eager<T>(pb, P0, P1, a0, b0, y0, a1, b1, y1, nrhs, s);
+        return;
+    }
+    fmb_problem_s::PairGraph &G = sizeof(T) == sizeof(float) ? pb.g32 : pb.g64;
+    FMB_CHECK_HIP(hipEventRecord(pb.ev_in, s));
+    FMB_CHECK_HIP(hipStreamWaitEvent(pb.s1, pb.ev_in, 0));
+    if (!G.exec || G.nrhs != nrhs || G.serial != pb.serial) {
+        if (G.exec) FMB_CHECK_HIP(hipGraphExecDestroy(G.exec));
+        G.exec = nullptr;
+        FMB_CHECK_HIP(hipStreamBeginCapture(pb.s1, hipStreamCaptureModeThreadLocal));
+        hipGraph_t graph = nullptr;
+        try {
+            fmm_pair_eager<T>(pb, P0, P1, a0, b0, y0, a1, b1, y1, nrhs, pb.s1);
+        } catch (...) {
+            (void)hipStreamEndCapture(pb.s1, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        FMB_CHECK_HIP(hipStreamEndCapture(pb.s1, &graph));
+        const hipError_t e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        FMB_CHECK_HIP(e);
+        G.nrhs = nrhs;
+        G.serial = pb.serial;
+    }
+    FMB_CHECK_HIP(hipGraphLaunch(G.exec, pb.s1));
+    FMB_CHECK_HIP(hipEventRecord(pb.ev_out, pb.s1));
+    FMB_CHECK_HIP(hipStreamWaitEvent(s, pb.ev_out, 0));
 }
 
 // A x with the FP64 plans (T = double) or the FP32 plans (T = float).  With
@@ -628,10 +706,14 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
     cx<T> *R = K.r.template as<cx<T>>(), *AX = K.ax.template as<cx<T>>();
     int32_t *need = K.need.template as<int32_t>(), *actd = K.act.template as<int32_t>();
     cx<double> *h = K.h.template as<cx<double>>(), *h2 = K.h2.template as<cx<double>>();
-    std::vector<double> bn(nrhs), beta(nrhs), res(nrhs);
-    std::vector<int32_t> act(nrhs), jr(nrhs), brk(nrhs);
-    norms(K, b, K.hn.template as<double>(), nullptr, s);
-    FMB_CHECK_HIP(hipMemcpyAsync(bn.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> bn(nrhs), beta(nrhs);
+    std::vector<int32_t> act(nrhs), jr(nrhs);
+    norms(K, b, K.bnd.template as<double>(), nullptr, s);
+    FMB_CHECK_HIP(hipMemcpyAsync(bn.data(), K.bnd.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    double *hres = static_cast<double *>(K.step.h);
+    int32_t *hbrk = reinterpret_cast<int32_t *>(hres + nrhs);
+    double *dres = static_cast<double *>(K.step.d);
+    int32_t *dbrk = reinterpret_cast<int32_t *>(dres + nrhs);
     if (x_nonzero) {
         bem_apply_t<T>(pb, x, AX, nrhs, s);
         ++matvecs;
@@ -688,11 +770,9 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
             k_scale_into<T><<<gridn(tot), TPB, 0, s>>>(W, hninv, V + (int64_t)(j + 1) * tot, len, nrhs, actd);
             k_givens<<<nrhs, 64, (size_t)(2 * j + 2) * sizeof(cx<double>) + (size_t)j * sizeof(double), s>>>(
                 K.H.template as<cx<double>>(), m + 1, j, h, hn, K.cs.template as<double>(),
-                K.sn.template as<cx<double>>(), K.g.template as<cx<double>>(), K.res.template as<double>(), actd,
-                K.brk.template as<int32_t>(), nrhs, m);
+                K.sn.template as<cx<double>>(), K.g.template as<cx<double>>(), actd, K.bnd.template as<double>(), tol,
+                dres, dbrk, nrhs, m);
             FMB_LAUNCH_CHECK();
-            FMB_CHECK_HIP(hipMemcpyAsync(res.data(), K.res.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-            FMB_CHECK_HIP(hipMemcpyAsync(brk.data(), K.brk.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             FMB_CHECK_HIP(hipStreamSynchronize(s));
             ++its;
             bool more = false;
@@ -700,16 +780,16 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
             for (int r = 0; r < nrhs; ++r) {
                 if (!act[r]) continue;
                 jr[r] = j + 1;
-                if (!std::isfinite(res[r])) throw Status{FMB_ENONFINITE, "non-finite Arnoldi step in fGMRES"};
-                worst = std::max(worst, bn[r] > 0 ? res[r] / bn[r] : 0.0);
-                if (res[r] <= tol * bn[r] || brk[r]) {
-                    act[r] = 0;
+                const double rs = hres[r];
+                if (!std::isfinite(rs)) throw Status{FMB_ENONFINITE, "non-finite Arnoldi step in fGMRES"};
+                worst = std::max(worst, bn[r] > 0 ? rs / bn[r] : 0.0);
+                if (rs <= tol * bn[r] || hbrk[r]) {
+                    act[r] = 0;                       // retired on the device by the same rule
                 } else {
                     more = true;
                 }
             }
             if (hist) hist->push_back(worst);
-            FMB_CHECK_HIP(hipMemcpyAsync(actd, act.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
             if (!more) break;
         }
         // x += Z y with y = H^{-1} g per rhs
@@ -810,9 +890,17 @@ int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_
             FMB_CHECK_HIP(hipStreamSynchronize(s));
         }
         FMB_CHECK_HIP(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
-        FMB_CHECK_HIP(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
-        FMB_CHECK_HIP(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+        FMB_CHECK_HIP(hipStreamCreateWithFlags(&h->s1, hipStreamNonBlocking));
+        for (hipEvent_t *e : {&h->ev_fork, &h->ev_join, &h->ev_in, &h->ev_out})
+            FMB_CHECK_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
         *out = guard.release();
+    });
+}
+
+int bem_problem_use_graphs(fmb_problem_t pb, int32_t enable) {
+    return guarded([&] {
+        FMB_REQUIRE(pb != nullptr, "problem is NULL");
+        pb->graphs = enable != 0;
     });
 }
 

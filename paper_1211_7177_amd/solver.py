@@ -49,6 +49,11 @@ class BemProblem:
             t = t.unsqueeze(0)
         return _abi._dev(t, torch.complex128, (self.n, 6), name), t.shape[0]
 
+    def use_graphs(self, enable=True):
+        """Replay the two FMM products of each application from a captured HIP
+        graph (the default) or launch them one by one."""
+        check(self._lib.bem_problem_use_graphs(self.h, 1 if enable else 0))
+
     def apply(self, x):
         """A x, x complex128 [nrhs, n, 6] (or [n, 6]) on the GPU."""
         out = torch.empty_like(x)

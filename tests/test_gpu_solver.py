@@ -123,3 +123,33 @@ def test_sphere_c1_solve_vs_oracle_and_mie(gpu, c1):
     xm = mie.surface_unknowns(q, 1.0, 1.0, 2.25)
     assert _rel(x[:, :3], xm[:, :3]) < 0.05
     pb.close()
+
+
+def test_graph_replays_equal_eager(gpu, small):
+    """The captured FMM pair replayed several times, with eager work and host
+    synchronisations between the replays, gives exactly the eager result; and
+    a mixed solve with graphs equals the one without."""
+    q, ob = small
+    n = q["points"].shape[0]
+    pb = gpu.BemProblem(q, 1.0, 2.25, order=14, depth=3, order32=8, nrhs_max=2)
+    xs = [torch.from_numpy(complex_normal((2, n, 6), seed_for(1, "a") + i)).cuda() for i in range(3)]
+    pb.use_graphs(False)
+    eager = [pb.apply(x) for x in xs]
+    torch.cuda.synchronize()
+    pb.use_graphs(True)
+    for rep in range(3):
+        for x, ref in zip(xs, eager):
+            y = pb.apply(x)
+            z = (x * 2.0).sum()                       # eager work between replays
+            torch.cuda.synchronize()
+            assert torch.equal(y, ref), "replay %d differs" % rep
+        assert torch.isfinite(z)
+    y1 = pb.apply(xs[0][:1].contiguous())             # other rhs count: a second graph
+    pb.use_graphs(False)
+    assert torch.equal(y1, pb.apply(xs[0][:1].contiguous()))
+    b = pb.rhs_planewave([0, 0, 1.0], [1.0, 0, 0])
+    xe, ie = pb.solve(b, tol=1e-8, mixed=True)
+    pb.use_graphs(True)
+    xg, ig = pb.solve(b, tol=1e-8, mixed=True)
+    assert torch.equal(xe, xg) and ie["iterations"] == ig["iterations"]
+    pb.close()
