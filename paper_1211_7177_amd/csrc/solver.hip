@@ -536,8 +536,16 @@ template <typename T>
 struct Krylov {
     int64_t len = 0;
     int nrhs = 0, m = 0, nchc = 0;
-    HostMapped step;   // per Arnoldi step: double res[nrhs], int32 brk[nrhs]
+    HostMapped step;   // two slots (step parity) of: double res[nrhs], int32 brk[nrhs]
     DevBuf bnd;        // |b| per rhs (device copy of the values the host holds)
+    hipEvent_t ev[2] = {nullptr, nullptr};   // recorded after the Givens step, per slot
+    Krylov() = default;
+    Krylov(const Krylov &) = delete;
+    Krylov &operator=(const Krylov &) = delete;
+    ~Krylov() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
     DevBuf V, Z, W, r, ax;                                            // cx<T>
     DevBuf H, cs, sn, g, h, h2, hn, hninv, part, npart, act, jr, y, tmp, need;   // FP64 / int32
 };
@@ -598,7 +606,9 @@ void krylov_alloc(Krylov<T> &K, int64_t len, int nrhs, int m) {
     K.part.alloc((size_t)(m + 2) * nrhs * DOT_CHUNKS * sizeof(cx<double>));
     K.npart.alloc((size_t)nrhs * K.nchc * sizeof(double));
     K.bnd.alloc(nrhs * sizeof(double));
-    K.step.alloc((size_t)nrhs * (sizeof(double) + sizeof(int32_t)));
+    K.step.alloc((size_t)2 * nrhs * (sizeof(double) + sizeof(int32_t)));
+    for (hipEvent_t &e : K.ev)
+        if (!e) FMB_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
 }  // namespace
@@ -710,10 +720,11 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
     std::vector<int32_t> act(nrhs), jr(nrhs);
     norms(K, b, K.bnd.template as<double>(), nullptr, s);
     FMB_CHECK_HIP(hipMemcpyAsync(bn.data(), K.bnd.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    // step results, slot j & 1: res at [slot * nrhs], brk after the 2 nrhs doubles
     double *hres = static_cast<double *>(K.step.h);
-    int32_t *hbrk = reinterpret_cast<int32_t *>(hres + nrhs);
+    int32_t *hbrk = reinterpret_cast<int32_t *>(hres + 2 * nrhs);
     double *dres = static_cast<double *>(K.step.d);
-    int32_t *dbrk = reinterpret_cast<int32_t *>(dres + nrhs);
+    int32_t *dbrk = reinterpret_cast<int32_t *>(dres + 2 * nrhs);
     if (x_nonzero) {
         bem_apply_t<T>(pb, x, AX, nrhs, s);
         ++matvecs;
@@ -746,7 +757,11 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
             FMB_CHECK_HIP(hipMemcpyAsync(K.g.p, g0.data(), g0.size() * sizeof(cx<double>), hipMemcpyHostToDevice, s));
         }
         for (int r = 0; r < nrhs; ++r) jr[r] = 0;
-        for (int j = 0; j < m && its < maxit; ++j) {
+        // One Arnoldi step: apply, orthogonalise, rotate.  The device retires
+        // converged rhs itself, so step j + 1 is enqueued before the host reads
+        // step j's result: the GPU does not wait on the host between steps.
+        // After the last step of a solve one masked step may have run.
+        auto enqueue = [&](int j) {
             cx<T> *vj = V + (int64_t)j * tot, *zj = Z + (int64_t)j * tot;
             if (precond) {
                 bem_apply_t<T>(pb, zj, W, nrhs, s, vj);      // z_j = M^{-1} v_j fused with the split
@@ -768,22 +783,36 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
             combine(K, (const cx<T> *)V, j + 1, h2, -1.0, W, actd, (const int32_t *)need, (double *)nullptr, s);
             k_post2<<<nrhs, 64, 0, s>>>(h, h2, j + 1, need, hn, hninv, nrhs);
             k_scale_into<T><<<gridn(tot), TPB, 0, s>>>(W, hninv, V + (int64_t)(j + 1) * tot, len, nrhs, actd);
+            const int sl = j & 1;
             k_givens<<<nrhs, 64, (size_t)(2 * j + 2) * sizeof(cx<double>) + (size_t)j * sizeof(double), s>>>(
                 K.H.template as<cx<double>>(), m + 1, j, h, hn, K.cs.template as<double>(),
                 K.sn.template as<cx<double>>(), K.g.template as<cx<double>>(), actd, K.bnd.template as<double>(), tol,
-                dres, dbrk, nrhs, m);
+                dres + sl * nrhs, dbrk + sl * nrhs, nrhs, m);
             FMB_LAUNCH_CHECK();
-            FMB_CHECK_HIP(hipStreamSynchronize(s));
+            FMB_CHECK_HIP(hipEventRecord(K.ev[sl], s));
+        };
+        int queued = -1;
+        for (int j = 0; j < m && its < maxit; ++j) {
+            if (queued < j) {
+                enqueue(j);
+                queued = j;
+            }
+            if (j + 1 < m && its + 1 < maxit) {
+                enqueue(j + 1);
+                queued = j + 1;
+            }
+            const int sl = j & 1;
+            FMB_CHECK_HIP(hipEventSynchronize(K.ev[sl]));
             ++its;
             bool more = false;
             double worst = 0.0;
             for (int r = 0; r < nrhs; ++r) {
                 if (!act[r]) continue;
                 jr[r] = j + 1;
-                const double rs = hres[r];
+                const double rs = hres[sl * nrhs + r];
                 if (!std::isfinite(rs)) throw Status{FMB_ENONFINITE, "non-finite Arnoldi step in fGMRES"};
                 worst = std::max(worst, bn[r] > 0 ? rs / bn[r] : 0.0);
-                if (rs <= tol * bn[r] || hbrk[r]) {
+                if (rs <= tol * bn[r] || hbrk[sl * nrhs + r]) {
                     act[r] = 0;                       // retired on the device by the same rule
                 } else {
                     more = true;
