@@ -237,6 +237,22 @@ int bem_rhs_planewave(fmb_problem_t pb, const double *dirs, const double *pols, 
 int gmres_solve(fmb_problem_t pb, const void *rhs, void *x, int32_t nrhs, const fmb_gmres_opts *o,
                 fmb_gmres_info *info, void *stream);
 
+/*
+ * gmres_solve_group: the solves of `count` independent problems (meshes of
+ * any sizes, each with its own plans, wavenumbers and permittivity) run
+ * together on the current device: problem i solves A_i x[i] = rhs[i] for
+ * nrhs[i] right-hand sides exactly as gmres_solve would (same options o for
+ * all, results bit-identical to separate calls), each on its own host thread
+ * and its own stream, so that the GPU overlaps the problems' launches.  The
+ * batched multi-mesh workload of the fGMRES loop (Sec. 3.1) thus runs as one
+ * call.  Problems and their plans must be distinct.  rhs[i], x[i]: device
+ * c128 [nrhs[i]][n_i][6].  info: NULL or `count` entries.  The work starts
+ * after the work queued on `stream` so far; synchronous.  Returns the first
+ * failing problem's error, else FMB_ENOCONV if any problem reached maxit.
+ */
+int gmres_solve_group(const fmb_problem_t *pbs, int32_t count, const void *const *rhs, void *const *x,
+                      const int32_t *nrhs, const fmb_gmres_opts *o, fmb_gmres_info *info, void *stream);
+
 int bem_problem_destroy(fmb_problem_t pb);
 
 /* Thread-local message for the last non-zero status returned on this thread. */

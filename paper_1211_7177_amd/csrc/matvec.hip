@@ -1257,8 +1257,11 @@ __global__ void __launch_bounds__(TPB) k_sum_far_all(FarSumLevels lv, const cx<T
 
 inline unsigned gridn(int64_t m, int tpb = TPB) { return (unsigned)((m + tpb - 1) / tpb); }
 
+// One product is a fixed sequence of steps (a launch or a short run of
+// launches); matvec_step issues step number `step` and returns false past the
+// last one, so that two products on two streams can be issued alternately.
 template <typename T>
-void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipStream_t s) {
+bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipStream_t s, int step) {
     const int64_t n = P.n;
     const int L = P.depth, p = P.order, P2 = P.P2;
     const int64_t blk = (int64_t)P.nrhs_max * 3 * P2;
@@ -1272,14 +1275,18 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
     cx<T> *yb = P.ybuf.as<cx<T>>();
     StageTimer &tm = P.timer;
     hipEvent_t ev = nullptr;
-    tm.begin(ST_GATHER, s, ev);
-    k_gather_src<T><<<gridn(n), TPB, 0, s>>>(a, b, P.perm.as<int32_t>(), P.sw.as<double>(), P.snrm.as<double>(), n,
-                                             nrhs, src);
-    FMB_LAUNCH_CHECK();
-    tm.end(ST_GATHER, s, ev);
+    int k = 0;
+    if (step == k++) {
+        tm.begin(ST_GATHER, s, ev);
+        k_gather_src<T><<<gridn(n), TPB, 0, s>>>(a, b, P.perm.as<int32_t>(), P.sw.as<double>(), P.snrm.as<double>(), n,
+                                                 nrhs, src);
+        FMB_LAUNCH_CHECK();
+        tm.end(ST_GATHER, s, ev);
+        return true;
+    }
     // Step 1: leaf multipoles
     Level &LL = P.lv[L];
-    {
+    if (step == k++) {
         const int N = p;
         const size_t per = ((size_t)(N + 1) * (N + 2) + 1 + 7) * sizeof(cx<T>) + 6 * sizeof(T);
         // LDS: the group-reduction area (G * P2 * 3 complex when G > 1), then per node of a batch
@@ -1294,11 +1301,13 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
             batch, LL.M.as<cx<T>>());
         FMB_LAUNCH_CHECK();
         tm.end(ST_P2M, s, ev);
+        return true;
     }
     // Step 2: upward pass (S|S), levels L-1 .. 2
     for (int l = L - 1; l >= 2; --l) {
         Level &V = P.lv[l], &C = P.lv[l + 1];
-        if (V.ntiles_m2m == 0) continue;
+        if (step != k++) continue;
+        if (V.ntiles_m2m == 0) return true;
         tm.begin(ST_M2M, s, ev);
         launch_translate<T>(V.tiles_m2m.as<Tile>(), V.ntiles_m2m, C.by_octant.as<int32_t>(), nullptr, V.m2m.as<T>(),
                             (const T *)C.M.p, (T *)yb, KR, ncol, blkR, os, s, 0, 0, bf3 ? V.m2m_hi.p : nullptr,
@@ -1309,10 +1318,11 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
                                                            ncol * P2);
         FMB_LAUNCH_CHECK();
         tm.end(ST_SUMS, s, ev);
+        return true;
     }
     // Step 3a: S|R of every level, one run of launches; each level's slots have
     // their own region of the slot buffer (slot_base)
-    {
+    if (step == k++) {
         int nk = 0;
         tm.begin(ST_M2L, s, ev);
         for (int l = 2; l <= L; ++l) {
@@ -1324,10 +1334,11 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
             ++nk;
         }
         tm.end(ST_M2L, s, ev, nk);
+        return true;
     }
     // Step 3b: the S|R slot sums of every level (one launch, overwriting L),
     // then R|R from the parent added into each level in turn
-    {
+    if (step == k++) {
         FarSumLevels fs{};
         fs.nlev = L - 1;
         int64_t tot = 0;
@@ -1344,19 +1355,22 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
         k_sum_far_all<T><<<(unsigned)tot, TPB, 0, s>>>(fs, yb, blk, ncol * P2);
         FMB_LAUNCH_CHECK();
         tm.end(ST_SUMS, s, ev);
+        return true;
     }
     for (int l = 3; l <= L; ++l) {
         Level &V = P.lv[l];
-        if (V.ntiles_l2l == 0) continue;
+        if (step != k++) continue;
+        if (V.ntiles_l2l == 0) return true;
         Level &U = P.lv[l - 1];
         tm.begin(ST_L2L, s, ev);
         launch_translate<T>(V.tiles_l2l.as<Tile>(), V.ntiles_l2l, V.by_octant.as<int32_t>(), V.parent.as<int32_t>(),
                             V.l2l.as<T>(), (const T *)U.L.p, (T *)V.L.p, KR, ncol, blkR, os, s, 2, 1,
                             bf3 ? V.l2l_hi.p : nullptr, V.l2l_lo.p);
         tm.end(ST_L2L, s, ev);
+        return true;
     }
     // Step 4: local expansions at the targets, then the near sum
-    {
+    if (step == k++) {
         // chunk of right-hand sides per block while their local expansions fit ~24 KB of LDS
         const size_t lrhs = (size_t)3 * P2 * sizeof(cx<T>);
         const int rc = (nrhs >= 8 && 8 * lrhs <= 24576) ? 8 : ((nrhs >= 4 && 4 * lrhs <= 24576) ? 4 : 1);
@@ -1369,27 +1383,34 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
                                   LL.L.as<cx<T>>(), ys);
         FMB_LAUNCH_CHECK();
         tm.end(ST_L2P, s, ev);
+        return true;
     }
-    tm.begin(ST_P2P, s, ev);
-    if (sizeof(T) == sizeof(float)) {
-        const bool lossy = P.k_im != 0.0;
-        const int rc = nrhs >= 8 ? 8 : (nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1));
-        decltype(&k_p2p32<true, 1>) kern;
-        switch (rc) {
-            case 8: kern = lossy ? k_p2p32<true, 8> : k_p2p32<false, 8>; break;
-            case 4: kern = lossy ? k_p2p32<true, 4> : k_p2p32<false, 4>; break;
-            case 2: kern = lossy ? k_p2p32<true, 2> : k_p2p32<false, 2>; break;
-            default: kern = lossy ? k_p2p32<true, 1> : k_p2p32<false, 1>; break;
+    if (step == k++) {
+        tm.begin(ST_P2P, s, ev);
+        if (sizeof(T) == sizeof(float)) {
+            const bool lossy = P.k_im != 0.0;
+            const int rc = nrhs >= 8 ? 8 : (nrhs >= 4 ? 4 : (nrhs >= 2 ? 2 : 1));
+            decltype(&k_p2p32<true, 1>) kern;
+            switch (rc) {
+                case 8: kern = lossy ? k_p2p32<true, 8> : k_p2p32<false, 8>; break;
+                case 4: kern = lossy ? k_p2p32<true, 4> : k_p2p32<false, 4>; break;
+                case 2: kern = lossy ? k_p2p32<true, 2> : k_p2p32<false, 2>; break;
+                default: kern = lossy ? k_p2p32<true, 1> : k_p2p32<false, 1>; break;
+            }
+            kern<<<dim3((unsigned)LL.nbox, (unsigned)((nrhs + rc - 1) / rc)), TPB, 0, s>>>(
+                (int)LL.nbox, nrhs, LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), LL.center.as<double>(),
+                P.spts.as<double>(), P.snrm.as<double>(), P.stri.as<int32_t>(), (const cx<float> *)src, n, P.k_re,
+                P.k_im, (cx<float> *)ys);
+        } else {
+            k_p2p<T><<<dim3((unsigned)LL.nbox, nrhs), TPB, 0, s>>>(
+                LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), P.spts.as<double>(), P.snrm.as<double>(),
+                P.stri.as<int32_t>(), src, n, P.k_re, P.k_im, ys);
         }
-        kern<<<dim3((unsigned)LL.nbox, (unsigned)((nrhs + rc - 1) / rc)), TPB, 0, s>>>(
-            (int)LL.nbox, nrhs, LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(),
-            P.snrm.as<double>(), P.stri.as<int32_t>(), (const cx<float> *)src, n, P.k_re, P.k_im, (cx<float> *)ys);
-    } else
-    k_p2p<T><<<dim3((unsigned)LL.nbox, nrhs), TPB, 0, s>>>(LL.start.as<int32_t>(), LL.nbr.as<int32_t>(),
-                                                          P.spts.as<double>(), P.snrm.as<double>(), P.stri.as<int32_t>(),
-                                                          src, n, P.k_re, P.k_im, ys);
-    FMB_LAUNCH_CHECK();
-    tm.end(ST_P2P, s, ev);
+        FMB_LAUNCH_CHECK();
+        tm.end(ST_P2P, s, ev);
+        return true;
+    }
+    if (step != k++) return false;
     if (P.corr_mode != FMB_CORR_NONE) {
         // back to user order with the self-triangle terms added in the same pass
         tm.begin(ST_CORR, s, ev);
@@ -1401,6 +1422,7 @@ void matvec_t(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hipSt
         FMB_LAUNCH_CHECK();
         tm.end(ST_SCATTER, s, ev);
     }
+    return true;
 }
 
 }  // namespace
@@ -1559,11 +1581,24 @@ StageTimer::~StageTimer() {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
-void run_matvec(Plan &P, const void *a, const void *b, void *y, int nrhs, hipStream_t s) {
+static bool run_step(Plan &P, const void *a, const void *b, void *y, int nrhs, hipStream_t s, int step) {
     if (P.precision == FMB_FP64)
-        matvec_t<double>(P, (const cx<double> *)a, (const cx<double> *)b, (cx<double> *)y, nrhs, s);
-    else
-        matvec_t<float>(P, (const cx<float> *)a, (const cx<float> *)b, (cx<float> *)y, nrhs, s);
+        return matvec_step<double>(P, (const cx<double> *)a, (const cx<double> *)b, (cx<double> *)y, nrhs, s, step);
+    return matvec_step<float>(P, (const cx<float> *)a, (const cx<float> *)b, (cx<float> *)y, nrhs, s, step);
+}
+
+void run_matvec(Plan &P, const void *a, const void *b, void *y, int nrhs, hipStream_t s) {
+    for (int st = 0; run_step(P, a, b, y, nrhs, s, st); ++st) {
+    }
+}
+
+void run_matvec_pair(Plan &P0, const void *a0, const void *b0, void *y0, hipStream_t s0, Plan &P1, const void *a1,
+                     const void *b1, void *y1, hipStream_t s1, int nrhs) {
+    bool more0 = true, more1 = true;
+    for (int st = 0; more0 || more1; ++st) {
+        if (more0) more0 = run_step(P0, a0, b0, y0, nrhs, s0, st);
+        if (more1) more1 = run_step(P1, a1, b1, y1, nrhs, s1, st);
+    }
 }
 
 }  // namespace fmb

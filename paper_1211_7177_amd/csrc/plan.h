@@ -112,6 +112,9 @@ void scatter_with_corrections(Plan &P, const void *ys, const void *a, const void
                               hipStream_t s);
 // matvec (matvec.hip)
 void run_matvec(Plan &P, const void *a, const void *b, void *y, int nrhs, hipStream_t s);
+// two products, P0 on s0 and P1 on s1, their launches issued alternately
+void run_matvec_pair(Plan &P0, const void *a0, const void *b0, void *y0, hipStream_t s0, Plan &P1, const void *a1,
+                     const void *b1, void *y1, hipStream_t s1, int nrhs);
 
 }  // namespace fmb
 

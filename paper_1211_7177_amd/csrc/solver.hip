@@ -25,6 +25,9 @@
 // FMM products of each application run concurrently on two streams.
 #include <algorithm>
 #include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
 
 #include "plan.h"
 
@@ -625,8 +628,7 @@ static void fmm_pair_eager(fmb_problem_s &pb, const Plan *P0, const Plan *P1, co
     }
     FMB_CHECK_HIP(hipEventRecord(pb.ev_fork, s));
     FMB_CHECK_HIP(hipStreamWaitEvent(pb.s2, pb.ev_fork, 0));
-    run_matvec(*const_cast<Plan *>(P0), a0, b0, y0, nrhs, s);
-    run_matvec(*const_cast<Plan *>(P1), a1, b1, y1, nrhs, pb.s2);
+    run_matvec_pair(*const_cast<Plan *>(P0), a0, b0, y0, s, *const_cast<Plan *>(P1), a1, b1, y1, pb.s2, nrhs);
     FMB_CHECK_HIP(hipEventRecord(pb.ev_join, pb.s2));
     FMB_CHECK_HIP(hipStreamWaitEvent(s, pb.ev_join, 0));
 }
@@ -840,6 +842,101 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
     return its;
 }
 
+static fmb_gmres_opts solve_opts(const fmb_gmres_opts *o) {
+    fmb_gmres_opts op;
+    fmb_gmres_opts_default(&op);
+    if (o) op = *o;
+    return op;
+}
+
+static void check_solve_args(fmb_problem_s *pb, const void *rhs, const void *x, int nrhs, const fmb_gmres_opts &op) {
+    FMB_REQUIRE(pb && rhs && x && rhs != x, "bad arguments");
+    FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
+    FMB_REQUIRE(op.tol > 0 && op.restart >= 1 && op.maxit >= 1, "bad solver options");
+    FMB_REQUIRE(!op.mixed || pb->p032, "mixed precision needs the FP32 plans");
+}
+
+// One complete solve on stream s; returns whether the tolerance was reached.
+static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs, const fmb_gmres_opts &op,
+                      fmb_gmres_info *info, hipStream_t s) {
+    check_solve_args(pb, rhs, x, nrhs, op);
+    pb->serial = op.serial != 0;
+    struct SerialReset {
+        fmb_problem_s *p;
+        ~SerialReset() { p->serial = false; }
+    } serial_reset{pb};
+    const int64_t len = pb->n * 6, tot = len * nrhs;
+    const cx<double> *b = (const cx<double> *)rhs;
+    cx<double> *X = (cx<double> *)x;
+    std::vector<double> relres, hist;
+    int mv64 = 0, mv32 = 0, its = 0, refinements = 0;
+    double final_res = 0.0;
+    Krylov<double> K;
+    if (!op.mixed) {
+        krylov_alloc(K, len, nrhs, op.restart);
+        its = fgmres<double>(*pb, K, b, X, op.x0_given != 0, op.tol, op.maxit, op.precond, relres, &hist, mv64, s);
+        for (double v : relres) final_res = std::max(final_res, v);
+    } else {
+        // iterative refinement: FP64 residuals r = b - A64 x, inner fGMRES on
+        // A32 d = r with FP32 Krylov vectors, x += d
+        krylov_alloc(K, len, nrhs, 1);                  // FP64 norms only
+        Krylov<float> K32;
+        krylov_alloc(K32, len, nrhs, op.restart);
+        DevBuf rr, ax, r32, d32;
+        rr.alloc(tot * sizeof(cx<double>));
+        ax.alloc(tot * sizeof(cx<double>));
+        r32.alloc(tot * sizeof(cx<float>));
+        d32.alloc(tot * sizeof(cx<float>));
+        if (op.x0_given) {
+            bem_apply_t<double>(*pb, X, ax.as<cx<double>>(), nrhs, s);
+            ++mv64;
+            k_sub<double><<<gridn(tot), TPB, 0, s>>>(b, ax.as<cx<double>>(), rr.as<cx<double>>(), tot);
+        } else {
+            FMB_CHECK_HIP(hipMemsetAsync(X, 0, tot * sizeof(cx<double>), s));
+            FMB_CHECK_HIP(hipMemcpyAsync(rr.p, b, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
+        }
+        std::vector<double> bn(nrhs), rn(nrhs);
+        norms(K, b, K.hn.as<double>(), nullptr, s);
+        FMB_CHECK_HIP(hipMemcpyAsync(bn.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        while (true) {
+            norms(K, (const cx<double> *)rr.as<cx<double>>(), K.hn.as<double>(), nullptr, s);
+            FMB_CHECK_HIP(hipMemcpyAsync(rn.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+            FMB_CHECK_HIP(hipStreamSynchronize(s));
+            final_res = 0.0;
+            for (int r = 0; r < nrhs; ++r) {
+                if (!std::isfinite(rn[r])) throw Status{FMB_ENONFINITE, "non-finite residual in refinement"};
+                final_res = std::max(final_res, bn[r] > 0 ? rn[r] / bn[r] : 0.0);
+            }
+            hist.push_back(final_res);
+            if (final_res <= op.tol || its >= op.maxit || refinements >= 50) break;
+            std::vector<double> inner;
+            // the last refinements only need to close the gap to tol: loosen the inner tolerance to
+            // a fraction of tol/|r| when that is looser than the configured one
+            const double itol = std::min(0.5, std::max(op.inner_tol, 0.3 * op.tol / std::max(final_res, 1e-300)));
+            k_to32<<<gridn(tot), TPB, 0, s>>>(rr.as<cx<double>>(), r32.as<cx<float>>(), tot);
+            FMB_LAUNCH_CHECK();
+            its += fgmres<float>(*pb, K32, r32.as<cx<float>>(), d32.as<cx<float>>(), false, itol,
+                                 std::min(op.inner_maxit, op.maxit - its), op.precond, inner, nullptr, mv32, s);
+            k_add_from32<<<gridn(tot), TPB, 0, s>>>(X, d32.as<cx<float>>(), tot);
+            bem_apply_t<double>(*pb, X, ax.as<cx<double>>(), nrhs, s);
+            ++mv64;
+            k_sub<double><<<gridn(tot), TPB, 0, s>>>(b, ax.as<cx<double>>(), rr.as<cx<double>>(), tot);
+            FMB_LAUNCH_CHECK();
+            ++refinements;
+        }
+    }
+    if (info) {
+        std::memset(info, 0, sizeof(*info));
+        info->iterations = its;
+        info->refinements = refinements;
+        info->matvecs64 = mv64;
+        info->matvecs32 = mv32;
+        info->residual = final_res;
+        for (size_t i = 0; i < hist.size() && i < 256; ++i) info->history[i] = hist[i];
+    }
+    return final_res <= op.tol;
+}
+
 }  // namespace fmb
 
 using namespace fmb;
@@ -971,95 +1068,83 @@ int bem_rhs_planewave(fmb_problem_t pb, const double *dirs, const double *pols, 
 
 int gmres_solve(fmb_problem_t pb, const void *rhs, void *x, int32_t nrhs, const fmb_gmres_opts *o,
                 fmb_gmres_info *info, void *stream) {
-    int conv_status = FMB_OK;
-    int code = guarded([&] {
-        FMB_REQUIRE(pb && rhs && x && rhs != x, "bad arguments");
-        FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
-        fmb_gmres_opts op;
-        fmb_gmres_opts_default(&op);
-        if (o) op = *o;
-        FMB_REQUIRE(op.tol > 0 && op.restart >= 1 && op.maxit >= 1, "bad solver options");
-        FMB_REQUIRE(!op.mixed || pb->p032, "mixed precision needs the FP32 plans");
-        hipStream_t s = (hipStream_t)stream;
-        pb->serial = op.serial != 0;
-        struct SerialReset {
-            fmb_problem_s *p;
-            ~SerialReset() { p->serial = false; }
-        } serial_reset{pb};
-        const int64_t len = pb->n * 6, tot = len * nrhs;
-        const cx<double> *b = (const cx<double> *)rhs;
-        cx<double> *X = (cx<double> *)x;
-        std::vector<double> relres, hist;
-        int mv64 = 0, mv32 = 0, its = 0, refinements = 0;
-        double final_res = 0.0;
-        Krylov<double> K;
-        if (!op.mixed) {
-            krylov_alloc(K, len, nrhs, op.restart);
-            its = fgmres<double>(*pb, K, b, X, op.x0_given != 0, op.tol, op.maxit, op.precond, relres, &hist, mv64, s);
-            for (double v : relres) final_res = std::max(final_res, v);
-        } else {
-            // iterative refinement: FP64 residuals r = b - A64 x, inner fGMRES on
-            // A32 d = r with FP32 Krylov vectors, x += d
-            krylov_alloc(K, len, nrhs, 1);                  // FP64 norms only
-            Krylov<float> K32;
-            krylov_alloc(K32, len, nrhs, op.restart);
-            DevBuf rr, ax, r32, d32;
-            rr.alloc(tot * sizeof(cx<double>));
-            ax.alloc(tot * sizeof(cx<double>));
-            r32.alloc(tot * sizeof(cx<float>));
-            d32.alloc(tot * sizeof(cx<float>));
-            if (op.x0_given) {
-                bem_apply_t<double>(*pb, X, ax.as<cx<double>>(), nrhs, s);
-                ++mv64;
-                k_sub<double><<<gridn(tot), TPB, 0, s>>>(b, ax.as<cx<double>>(), rr.as<cx<double>>(), tot);
-            } else {
-                FMB_CHECK_HIP(hipMemsetAsync(X, 0, tot * sizeof(cx<double>), s));
-                FMB_CHECK_HIP(hipMemcpyAsync(rr.p, b, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
-            }
-            std::vector<double> bn(nrhs), rn(nrhs);
-            norms(K, b, K.hn.as<double>(), nullptr, s);
-            FMB_CHECK_HIP(hipMemcpyAsync(bn.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-            while (true) {
-                norms(K, (const cx<double> *)rr.as<cx<double>>(), K.hn.as<double>(), nullptr, s);
-                FMB_CHECK_HIP(hipMemcpyAsync(rn.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
-                FMB_CHECK_HIP(hipStreamSynchronize(s));
-                final_res = 0.0;
-                for (int r = 0; r < nrhs; ++r) {
-                    if (!std::isfinite(rn[r])) throw Status{FMB_ENONFINITE, "non-finite residual in refinement"};
-                    final_res = std::max(final_res, bn[r] > 0 ? rn[r] / bn[r] : 0.0);
-                }
-                hist.push_back(final_res);
-                if (final_res <= op.tol || its >= op.maxit || refinements >= 50) break;
-                std::vector<double> inner;
-                // the last refinements only need to close the gap to tol: loosen the inner tolerance to
-                // a fraction of tol/|r| when that is looser than the configured one
-                const double itol = std::min(0.5, std::max(op.inner_tol, 0.3 * op.tol / std::max(final_res, 1e-300)));
-                k_to32<<<gridn(tot), TPB, 0, s>>>(rr.as<cx<double>>(), r32.as<cx<float>>(), tot);
-                FMB_LAUNCH_CHECK();
-                its += fgmres<float>(*pb, K32, r32.as<cx<float>>(), d32.as<cx<float>>(), false, itol,
-                                     std::min(op.inner_maxit, op.maxit - its), op.precond, inner, nullptr, mv32, s);
-                k_add_from32<<<gridn(tot), TPB, 0, s>>>(X, d32.as<cx<float>>(), tot);
-                bem_apply_t<double>(*pb, X, ax.as<cx<double>>(), nrhs, s);
-                ++mv64;
-                k_sub<double><<<gridn(tot), TPB, 0, s>>>(b, ax.as<cx<double>>(), rr.as<cx<double>>(), tot);
-                FMB_LAUNCH_CHECK();
-                ++refinements;
-            }
-        }
-        if (info) {
-            std::memset(info, 0, sizeof(*info));
-            info->iterations = its;
-            info->refinements = refinements;
-            info->matvecs64 = mv64;
-            info->matvecs32 = mv32;
-            info->residual = final_res;
-            for (size_t i = 0; i < hist.size() && i < 256; ++i) info->history[i] = hist[i];
-        }
-        if (!(final_res <= op.tol)) conv_status = FMB_ENOCONV;
+    bool converged = true;
+    const int code = guarded([&] {
+        const fmb_gmres_opts op = solve_opts(o);
+        converged = solve_one(pb, rhs, x, nrhs, op, info, (hipStream_t)stream);
     });
     if (code != FMB_OK) return code;
-    if (conv_status != FMB_OK) set_error("fGMRES reached maxit before the tolerance");
-    return conv_status;
+    if (!converged) {
+        set_error("fGMRES reached maxit before the tolerance");
+        return FMB_ENOCONV;
+    }
+    return FMB_OK;
+}
+
+int gmres_solve_group(const fmb_problem_t *pbs, int32_t count, const void *const *rhs, void *const *x,
+                      const int32_t *nrhs, const fmb_gmres_opts *o, fmb_gmres_info *info, void *stream) {
+    std::vector<int> codes;
+    std::vector<std::string> msgs;
+    std::vector<char> conv;
+    const int code = guarded([&] {
+        FMB_REQUIRE(pbs && rhs && x && nrhs && count >= 1, "bad arguments");
+        const fmb_gmres_opts op = solve_opts(o);
+        for (int i = 0; i < count; ++i) {
+            check_solve_args(pbs[i], rhs[i], x[i], nrhs[i], op);
+            for (int q = 0; q < i; ++q) {
+                FMB_REQUIRE(pbs[q] != pbs[i], "a problem appears twice in the group");
+                const fmb_problem_s &A = *pbs[q], &B = *pbs[i];
+                for (const fmb_plan_s *pa : {A.p0, A.p1, A.p032, A.p132})
+                    for (const fmb_plan_s *pb2 : {B.p0, B.p1, B.p032, B.p132})
+                        FMB_REQUIRE(!pa || pa != pb2, "two problems of the group share a plan");
+            }
+        }
+        int dev = 0;
+        FMB_CHECK_HIP(hipGetDevice(&dev));
+        hipStream_t cs = (hipStream_t)stream;
+        hipEvent_t start = nullptr;
+        FMB_CHECK_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+        struct EvFree {
+            hipEvent_t e;
+            ~EvFree() { (void)hipEventDestroy(e); }
+        } start_free{start};
+        FMB_CHECK_HIP(hipEventRecord(start, cs));
+        codes.assign(count, FMB_OK);
+        msgs.assign(count, std::string());
+        conv.assign(count, 1);
+        // one host thread and one stream per problem: the problems' launches
+        // overlap on the GPU while each solve keeps its own host decisions
+        std::vector<std::thread> th;
+        th.reserve(count);
+        for (int i = 0; i < count; ++i) {
+            th.emplace_back([&, i] {
+                hipStream_t si = nullptr;
+                codes[i] = guarded([&] {
+                    FMB_CHECK_HIP(hipSetDevice(dev));
+                    FMB_CHECK_HIP(hipStreamCreateWithFlags(&si, hipStreamNonBlocking));
+                    FMB_CHECK_HIP(hipStreamWaitEvent(si, start, 0));
+                    conv[i] = solve_one(pbs[i], rhs[i], x[i], nrhs[i], op, info ? info + i : nullptr, si) ? 1 : 0;
+                    FMB_CHECK_HIP(hipStreamSynchronize(si));
+                });
+                if (codes[i] != FMB_OK) {
+                    msgs[i] = fmb_last_error();
+                    if (si) (void)hipStreamSynchronize(si);
+                }
+                if (si) (void)hipStreamDestroy(si);
+            });
+        }
+        for (auto &t : th) t.join();
+        for (int i = 0; i < count; ++i)
+            if (codes[i] != FMB_OK)
+                throw Status{codes[i], "problem " + std::to_string(i) + " of the group: " + msgs[i]};
+    });
+    if (code != FMB_OK) return code;
+    for (int i = 0; i < count; ++i)
+        if (!conv[i]) {
+            set_error("fGMRES reached maxit before the tolerance (problem " + std::to_string(i) + " of the group)");
+            return FMB_ENOCONV;
+        }
+    return FMB_OK;
 }
 
 int bem_problem_destroy(fmb_problem_t pb) {

@@ -9,6 +9,54 @@ from . import _abi
 from ._abi import Plan, check, _stream
 
 
+def _opts(lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, serial):
+    opts = _abi.GmresOpts()
+    check(lib.fmb_gmres_opts_default(ctypes.byref(opts)))
+    opts.tol = tol
+    opts.restart = restart
+    opts.maxit = maxit
+    opts.precond = 1 if precond else 0
+    opts.mixed = 1 if mixed else 0
+    opts.inner_tol = inner_tol
+    opts.inner_maxit = inner_maxit
+    opts.serial = 1 if serial else 0
+    return opts
+
+
+def _info_dict(info, code):
+    return {"iterations": info.iterations, "refinements": info.refinements, "matvecs64": info.matvecs64,
+            "matvecs32": info.matvecs32, "residual": info.residual, "code": code,
+            "history": list(info.history[:min(256, max(info.iterations, info.refinements + 1))])}
+
+
+def solve_group(problems, rhs_list, tol=1e-6, restart=100, maxit=1000, precond=True, mixed=False, inner_tol=1e-3,
+                inner_maxit=300, raise_on_noconv=True, serial=False):
+    """Solve several independent problems (meshes of any sizes) in one
+    `gmres_solve_group` call; rhs_list[i] is complex128 [nrhs_i, n_i, 6] on the
+    GPU.  Returns the solutions and one info dict per problem."""
+    if len(problems) != len(rhs_list) or not problems:
+        raise ValueError("one right-hand side tensor per problem")
+    lib = _abi.load()
+    opts = _opts(lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, serial)
+    opts.x0_given = 0
+    cnt = len(problems)
+    xs, ptr_r, nrs = [], [], []
+    for pb, rhs in zip(problems, rhs_list):
+        pr, nr = pb._v(rhs, "rhs")
+        ptr_r.append(pr.value)
+        nrs.append(nr)
+        xs.append(torch.zeros_like(rhs if rhs.dim() == 3 else rhs.unsqueeze(0)))
+    hs = (ctypes.c_void_p * cnt)(*[pb.h.value for pb in problems])
+    rp = (ctypes.c_void_p * cnt)(*ptr_r)
+    xp = (ctypes.c_void_p * cnt)(*[x.data_ptr() for x in xs])
+    nv = (ctypes.c_int32 * cnt)(*nrs)
+    infos = (_abi.GmresInfo * cnt)()
+    code = lib.gmres_solve_group(hs, cnt, rp, xp, nv, ctypes.byref(opts), infos, _stream())
+    if code != _abi.FMB_OK and (code != _abi.FMB_ENOCONV or raise_on_noconv):
+        check(code)
+    return xs, [_info_dict(infos[i], code) for i in range(cnt)]
+
+
 class BemProblem:
     """One scatterer in vacuum: plans at k0 and k1 = k0 sqrt(eps mu) over the same nodes.
 
@@ -78,25 +126,14 @@ class BemProblem:
 
     def solve(self, rhs, tol=1e-6, restart=100, maxit=1000, precond=True, mixed=False, inner_tol=1e-3,
               inner_maxit=300, x0=None, raise_on_noconv=True, serial=False):
-        opts = _abi.GmresOpts()
-        check(self._lib.fmb_gmres_opts_default(ctypes.byref(opts)))
-        opts.tol = tol
-        opts.restart = restart
-        opts.maxit = maxit
-        opts.precond = 1 if precond else 0
-        opts.mixed = 1 if mixed else 0
-        opts.inner_tol = inner_tol
-        opts.inner_maxit = inner_maxit
-        opts.serial = 1 if serial else 0
+        opts = _opts(self._lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, serial)
         x = torch.zeros_like(rhs) if x0 is None else x0.clone()
         opts.x0_given = 0 if x0 is None else 1
         info = _abi.GmresInfo()
         pr, nr = self._v(rhs, "rhs")
         code = self._lib.gmres_solve(self.h, pr, ctypes.c_void_p(x.data_ptr()), nr, ctypes.byref(opts),
                                      ctypes.byref(info), _stream())
-        res = {"iterations": info.iterations, "refinements": info.refinements, "matvecs64": info.matvecs64,
-               "matvecs32": info.matvecs32, "residual": info.residual, "code": code,
-               "history": list(info.history[:min(256, max(info.iterations, info.refinements + 1))])}
+        res = _info_dict(info, code)
         if code != _abi.FMB_OK and (code != _abi.FMB_ENOCONV or raise_on_noconv):
             check(code)
         return x, res

@@ -153,3 +153,38 @@ def test_graph_replays_equal_eager(gpu, small):
     xg, ig = pb.solve(b, tol=1e-8, mixed=True)
     assert torch.equal(xe, xg) and ie["iterations"] == ig["iterations"]
     pb.close()
+
+
+def test_group_solve_uneven_meshes_equals_separate_solves(gpu):
+    """Three meshes of uneven size, wavenumber and permittivity (an ellipsoid,
+    a lossy torus, a sphere) with 2, 1 and 3 plane waves, solved by one
+    gmres_solve_group call: each answer is bit-identical to that problem's own
+    gmres_solve, and solves the oracle's system."""
+    from synthetic import geodesic_ellipsoid, torus
+    meshes = [(nystrom3(geodesic_ellipsoid((1.5, 1.0, 0.75), 4)), 1.2, 2.25, 2),
+              (nystrom3(torus(1.0, 0.3, 24, 8)), 1.0, -15 + 1j, 1),
+              (nystrom3(icosphere(6)), 1.5, 2.25, 3)]
+    pbs, rhs = [], []
+    rng = np.random.default_rng(7)
+    for q, k0, eps, nr in meshes:
+        print("group member: %d nodes, k0 %.2f, eps %s, %d rhs" % (q["points"].shape[0], k0, eps, nr), flush=True)
+        pb = gpu.BemProblem(q, k0, eps, order=14, depth=3, order32=8, nrhs_max=nr)
+        d = rng.standard_normal((nr, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        p = np.cross(d, [0.3, 0.5, 0.8])
+        p /= np.linalg.norm(p, axis=1, keepdims=True)
+        pbs.append(pb)
+        rhs.append(pb.rhs_planewave(d, p))
+    xs, infos = gpu.solve_group(pbs, rhs, tol=1e-8, mixed=True, inner_tol=1e-3)
+    for i, (pb, b) in enumerate(zip(pbs, rhs)):
+        x1, i1 = pb.solve(b, tol=1e-8, mixed=True, inner_tol=1e-3)
+        print("member", i, infos[i]["iterations"], i1["iterations"], infos[i]["residual"], flush=True)
+        assert infos[i]["residual"] <= 1e-8
+        assert infos[i]["iterations"] == i1["iterations"]
+        assert torch.equal(xs[i], x1), "group member %d differs from its own solve" % i
+    for (q, k0, eps, nr), x, b in zip(meshes, xs, rhs):
+        ob = OracleBem(q, k0, eps)
+        xn, bn = x.cpu().numpy()[0], b.cpu().numpy()[0]
+        assert np.linalg.norm(bn - ob.apply(xn)) / np.linalg.norm(bn) <= 1e-5
+    for pb in pbs:
+        pb.close()
