@@ -48,6 +48,8 @@ def parse():
                     help="also time one lockstep solve of this many plane waves (0: skip)")
     ap.add_argument("--serial", action="store_true",
                     help="run the k0 and k1 FMM products of each application one after the other (one stream)")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay the two FMM products from a captured HIP graph (default: eager launches)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
@@ -139,6 +141,8 @@ def main():
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     log("plans built in %.2f s" % plan_s)
+    if args.graphs:
+        pb.use_graphs(True)
     info64 = pb.p0.info()
     info32 = pb.p0_32.info()
     rhs = pb.rhs_planewave(d, pol)

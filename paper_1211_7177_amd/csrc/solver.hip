@@ -47,11 +47,14 @@ struct fmb_problem_s {
     hipStream_t s2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool serial = false;       // both products on one stream (set per solve)
-    // The two FMM products of an application, captured once per precision and
-    // rhs count as a HIP graph and replayed on the problem's own stream s1
-    // (the caller's stream may be the legacy default stream, which cannot be
-    // captured); ev_in / ev_out order s1 after and before the caller's stream.
-    bool graphs = true;
+    // Optionally (off by default) the two FMM products of an application,
+    // captured once per precision and rhs count as a HIP graph and replayed on
+    // the problem's own stream s1 (the caller's stream may be the legacy
+    // default stream, which cannot be captured); ev_in / ev_out order s1 after
+    // and before the caller's stream.  Eager launches, issued alternately to
+    // the two streams, measured faster: the graph's second branch started
+    // well after its first.
+    bool graphs = false;
     hipStream_t s1 = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     struct PairGraph {
