@@ -48,6 +48,8 @@ def parse():
                     help="also time one lockstep solve of this many plane waves (0: skip)")
     ap.add_argument("--serial", action="store_true",
                     help="run the k0 and k1 FMM products of each application one after the other (one stream)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the FP32 order and translation kernel by timing whole solves first (autotune.tune_solve)")
     ap.add_argument("--graphs", action="store_true",
                     help="replay the two FMM products from a captured HIP graph (default: eager launches)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -135,6 +137,16 @@ def main():
     k0, eps, depth = cfg["k0"], cfg["eps"], cfg["depth"]
     d, pol = plane_waves(1, seed_for(2, "dirs"), seed_for(2, "pols"))
 
+    tuned = None
+    if args.autotune:
+        from paper_1211_7177_amd.autotune import tune_solve
+        best, table = tune_solve(nodes, k0, eps, d, pol, tol=args.tol, orders32=(4, 5, 6),
+                                 translates=("bf16x3", "fp32"), inner_tols=(args.inner_tol,), order64=args.order64,
+                                 depth=depth, restart=args.restart)
+        tuned = {"chosen": best, "table": table}
+        log("autotune", best)
+        if best is not None:
+            args.order32, args.translate32 = best["order32"], best["translate"]
     t0 = time.perf_counter()
     pb = BemProblem(nodes, k0, eps, order=args.order64, depth=depth, order32=args.order32,
                     translate32=args.translate32)
@@ -330,6 +342,7 @@ def main():
                   "bem_applies_fp32": last["matvecs32"], "bem_applies_fp64": last["matvecs64"],
                   "residual": last["residual"]},
         "batched": batched,
+        "autotune": tuned,
         "fp64_solve": fp64,
         "speedup_vs_fp64_solve": (solves_per_s / fp64["solves_per_s"]) if fp64 else None,
         "fmm_matvecs_per_s": rates,
