@@ -119,8 +119,18 @@ int fmm_plan(const double *points, const double *normals, const double *weights,
 int fmm_matvec(fmb_plan_t plan, const void *a, const void *b, void *y, int32_t nrhs, void *stream);
 
 /*
- * fmm_matvec_adjoint: (a_bar, b_bar) = Op_k^H y, the conjugate transpose.
- * Declared for the adjoint/gradient work; returns FMB_ENOTIMPL.
+ * fmm_matvec_adjoint: (a_bar, b_bar) = Op_k^H y, the conjugate transpose of
+ * the operator fmm_matvec applies (eq. 2.12 with the point rule of eq. 2.8,
+ * plus the self-triangle terms of App. B), so that
+ *   sum conj(y) . Op_k(a, b) = sum conj(a_bar) . a + sum conj(b_bar) . b.
+ * Per node beta, with F_c = sum_alpha g(s_beta, s_alpha) conj(y_alpha,c) and H_ic = d_i F_c,
+ *   a_bar = conj(w (H n - H^T n - n tr H) + ...),  b_bar = conj(w F + ...)
+ * (the dots being the transposed self-triangle blocks).  It runs the same
+ * fast multipole method with monopole sources and value-and-gradient
+ * evaluation.  y, a_bar, b_bar: device [nrhs][n][3] complex of the plan's
+ * precision, user node order; none may alias.  Asynchronous on `stream`.
+ * The first call allocates a workspace of nrhs_max * n * 12 complex.
+ * FMB_EINVAL for FP64 plans of order above 23.
  */
 int fmm_matvec_adjoint(fmb_plan_t plan, const void *y, void *a_bar, void *b_bar, int32_t nrhs,
                        void *stream);

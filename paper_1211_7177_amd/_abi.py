@@ -183,11 +183,16 @@ class Plan:
         return out[0] if squeeze else out
 
     def matvec_adjoint(self, y):
+        """(a_bar, b_bar) = Op_k^H y; y complex [nrhs, n, 3] or [n, 3] on the GPU."""
+        squeeze = y.dim() == 2
+        if squeeze:
+            y = y.unsqueeze(0)
+        py = _dev(y, self.cdtype, (self.n, 3), "y")
         a = torch.empty_like(y)
         b = torch.empty_like(y)
-        check(self._lib.fmm_matvec_adjoint(self.h, ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(a.data_ptr()),
-                                           ctypes.c_void_p(b.data_ptr()), 1, _stream()))
-        return a, b
+        check(self._lib.fmm_matvec_adjoint(self.h, py, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                           y.shape[0], _stream()))
+        return (a[0], b[0]) if squeeze else (a, b)
 
     def info(self):
         inf = PlanInfo()

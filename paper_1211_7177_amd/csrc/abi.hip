@@ -150,14 +150,13 @@ int fmm_matvec(fmb_plan_t plan, const void *a, const void *b, void *y, int32_t n
 }
 
 int fmm_matvec_adjoint(fmb_plan_t plan, const void *y, void *a_bar, void *b_bar, int32_t nrhs, void *stream) {
-    (void)plan;
-    (void)y;
-    (void)a_bar;
-    (void)b_bar;
-    (void)nrhs;
-    (void)stream;
-    set_error("fmm_matvec_adjoint is not implemented");
-    return FMB_ENOTIMPL;
+    return guarded([&] {
+        FMB_REQUIRE(plan != nullptr, "plan is NULL");
+        FMB_REQUIRE(y && a_bar && b_bar, "y, a_bar and b_bar are required");
+        FMB_REQUIRE(a_bar != y && b_bar != y && a_bar != b_bar, "a_bar, b_bar and y must not alias");
+        FMB_REQUIRE(nrhs >= 1 && nrhs <= plan->p.nrhs_max, "nrhs must be in [1, nrhs_max]");
+        run_matvec_adjoint(plan->p, y, a_bar, b_bar, nrhs, (hipStream_t)stream);
+    });
 }
 
 int fmm_plan_info(fmb_plan_t plan, fmb_plan_info *info) {

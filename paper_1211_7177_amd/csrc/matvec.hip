@@ -15,6 +15,7 @@
 //   d_z R_n^m        = k [ -A_n^m R_{n+1}^m     + B_n^m R_{n-1}^m ]
 //   (d_x + i d_y) R  = k [ -C_n^m R_{n+1}^{m+1} + D_n^m R_{n-1}^{m+1} ]
 //   (d_x - i d_y) R  = k [ -E_n^m R_{n+1}^{m-1} + F_n^m R_{n-1}^{m-1} ]
+#include "basis.h"
 #include "plan.h"
 
 namespace fmb {
@@ -68,61 +69,6 @@ __global__ void k_scatter_out(const cx<T> *__restrict__ ys, const int32_t *__res
 __device__ inline int xcd_tile(int i, int ntiles) {
     const int chunk = (ntiles + 7) / 8;
     return (i % 8) * chunk + i / 8;
-}
-
-// ---------------------------------------------------------------- basis
-// Recurrence constants of the normalised associated Legendre functions and of
-// the gradient of R_n^m, tabulated on the host at plan time (BasisTab layout
-// below) so that the per-node loops carry no square roots or divisions.
-//   Q_m^m = qmm[m],  Q_{m+1}^m = q1[m] x Q_m^m,
-//   Q_n^m = la[n][m] (x Q_{n-1}^m - lb[n][m] Q_{n-2}^m)            (n >= m + 2)
-template <typename T>
-struct BasisTab {
-    const T *la, *lb, *qmm, *q1;     // [(N+1)^2] (row n, column m), [(N+1)^2], [N+1], [N+1]
-    const T *gco;                    // [P2][6] gradient coefficients of coefficient idx (mu = -m)
-    const int32_t *gix;              // [P2][7] R-table indices of the six gradient terms and of R_n^{-m}
-    int N;
-};
-
-template <typename T>
-__device__ inline BasisTab<T> basis_tab(const T *tab, const int32_t *gix, int N, int P2) {
-    BasisTab<T> b;
-    const int NN = (N + 1) * (N + 1);
-    b.la = tab;
-    b.lb = tab + NN;
-    b.qmm = tab + 2 * NN;
-    b.q1 = tab + 2 * NN + (N + 1);
-    b.gco = tab + 2 * NN + 2 * (N + 1);
-    b.gix = gix;
-    b.N = N;
-    (void)P2;
-    return b;
-}
-
-// R_n^m(d) for n <= N, one order m, of one point into out[(N+1)^2]; jb holds
-// j_0..j_N at k|d|.
-// x = cos th, w = sin th e^{i ph} of the point's direction from the centre.
-template <typename T>
-__device__ inline void regular_column(T x, cx<T> w, const cx<T> *jb, const BasisTab<T> &bt, int m, cx<T> *out) {
-    const int N = bt.N;
-    const T qmm = bt.qmm[m];
-    cx<T> wm = mk(T(1), T(0));
-    for (int i = 1; i <= m; ++i) wm = wm * w;
-    const T sgn = (m & 1) ? T(-1) : T(1);
-    T q2 = 0, q1 = qmm;
-    for (int n = m; n <= N; ++n) {
-        T q;
-        if (n == m) q = qmm;
-        else if (n == m + 1) q = bt.q1[m] * x * qmm;
-        else q = bt.la[n * (N + 1) + m] * (x * q1 - bt.lb[n * (N + 1) + m] * q2);
-        if (n > m) {
-            q2 = q1;
-            q1 = q;
-        }
-        cx<T> Y = (sgn * q) * wm;
-        out[n * n + n + m] = jb[n] * Y;
-        if (m > 0) out[n * n + n - m] = jb[n] * conj(Y);
-    }
 }
 
 // ---------------------------------------------------------------- P2M
@@ -1581,6 +1527,44 @@ StageTimer::~StageTimer() {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
 }
 
+// The adjoint product shares the forward steps from P2M through the last
+// R|R level (its sources are monopole charges in the forward record layout);
+// gather, L2P, P2P and the return to user order are its own.
+static bool adjoint_step(Plan &P, const void *y, void *abar, void *bbar, int nrhs, hipStream_t s, int step) {
+    const int nmid = 3 + 2 * std::max(P.depth - 2, 0);
+    StageTimer &tm = P.timer;
+    hipEvent_t ev = nullptr;
+    if (step == 0) {
+        tm.begin(ST_GATHER, s, ev);
+        adjoint_gather(P, y, nrhs, s);
+        tm.end(ST_GATHER, s, ev);
+        return true;
+    }
+    if (step <= nmid) {
+        if (P.precision == FMB_FP64) return matvec_step<double>(P, nullptr, nullptr, nullptr, nrhs, s, step);
+        return matvec_step<float>(P, nullptr, nullptr, nullptr, nrhs, s, step);
+    }
+    if (step == nmid + 1) {
+        tm.begin(ST_L2P, s, ev);
+        adjoint_l2p(P, nrhs, s);
+        tm.end(ST_L2P, s, ev);
+        return true;
+    }
+    if (step == nmid + 2) {
+        tm.begin(ST_P2P, s, ev);
+        adjoint_p2p(P, nrhs, s);
+        tm.end(ST_P2P, s, ev);
+        return true;
+    }
+    if (step == nmid + 3) {
+        tm.begin(ST_CORR, s, ev);
+        adjoint_finish(P, y, abar, bbar, nrhs, s);
+        tm.end(ST_CORR, s, ev);
+        return true;
+    }
+    return false;
+}
+
 static bool run_step(Plan &P, const void *a, const void *b, void *y, int nrhs, hipStream_t s, int step) {
     if (P.precision == FMB_FP64)
         return matvec_step<double>(P, (const cx<double> *)a, (const cx<double> *)b, (cx<double> *)y, nrhs, s, step);
@@ -1589,6 +1573,12 @@ static bool run_step(Plan &P, const void *a, const void *b, void *y, int nrhs, h
 
 void run_matvec(Plan &P, const void *a, const void *b, void *y, int nrhs, hipStream_t s) {
     for (int st = 0; run_step(P, a, b, y, nrhs, s, st); ++st) {
+    }
+}
+
+void run_matvec_adjoint(Plan &P, const void *y, void *abar, void *bbar, int nrhs, hipStream_t s) {
+    adjoint_prepare(P);
+    for (int st = 0; adjoint_step(P, y, abar, bbar, nrhs, s, st); ++st) {
     }
 }
 

@@ -97,6 +97,7 @@ struct Plan {
     DevBuf src;       // [nrhs_max][n][7] complex (w a, w b, w n.a) in Morton order
     DevBuf ys;        // [nrhs_max][n][3] complex, Morton order
     DevBuf ybuf;      // GEMM output slots, largest level
+    DevBuf aws;       // adjoint: [nrhs_max][n][12] potentials and gradients per channel, Morton order (on first use)
     StageTimer timer;
     size_t device_bytes() const;
 };
@@ -112,6 +113,13 @@ void scatter_with_corrections(Plan &P, const void *ys, const void *a, const void
                               hipStream_t s);
 // matvec (matvec.hip)
 void run_matvec(Plan &P, const void *a, const void *b, void *y, int nrhs, hipStream_t s);
+// the adjoint product (a_bar, b_bar) = Op^H y (adjoint.hip for its own steps)
+void adjoint_prepare(Plan &P);
+void adjoint_gather(Plan &P, const void *y, int nrhs, hipStream_t s);
+void adjoint_l2p(Plan &P, int nrhs, hipStream_t s);
+void adjoint_p2p(Plan &P, int nrhs, hipStream_t s);
+void adjoint_finish(Plan &P, const void *y, void *abar, void *bbar, int nrhs, hipStream_t s);
+void run_matvec_adjoint(Plan &P, const void *y, void *abar, void *bbar, int nrhs, hipStream_t s);
 // two products, P0 on s0 and P1 on s1, their launches issued alternately
 void run_matvec_pair(Plan &P0, const void *a0, const void *b0, void *y0, hipStream_t s0, Plan &P1, const void *a1,
                      const void *b1, void *y1, hipStream_t s1, int nrhs);

@@ -59,4 +59,6 @@ def test_host_validation_without_gpu():
     assert r == _abi.FMB_EINVAL and b"weights" in lib.fmb_last_error()
     r = lib.fmm_plan(pts.ctypes.data, nrm.ctypes.data, w.ctypes.data, 10, 1.0, 0.0, 99, None, None, ctypes.byref(h))
     assert r == _abi.FMB_EINVAL and b"order" in lib.fmb_last_error()
-    assert lib.fmm_matvec_adjoint(None, None, None, None, 1, None) == _abi.FMB_ENOTIMPL
+    assert lib.fmm_matvec_adjoint(None, None, None, None, 1, None) == _abi.FMB_EINVAL
+    assert b"plan" in lib.fmb_last_error()
+    assert lib.gmres_solve_group(None, 1, None, None, None, None, None, None) == _abi.FMB_EINVAL
