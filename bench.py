@@ -238,6 +238,7 @@ def main():
 
     # FMM matvec rates and stage profile (HIP events on the stream the kernels run on)
     rates = {}
+    adj_rates = {}
     prof = {}
     for tag, plan, cdt in (("fp64", pb.p0, torch.complex128), ("fp32", pb.p0_32, torch.complex64)):
         a = torch.randn(1, n, 3, dtype=cdt, device=dev)
@@ -250,13 +251,20 @@ def main():
             plan.matvec(a, b, out=y)
         torch.cuda.synchronize()
         rates[tag] = reps / (time.perf_counter() - t1)
+        plan.matvec_adjoint(y)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            plan.matvec_adjoint(y)
+        torch.cuda.synchronize()
+        adj_rates[tag] = reps / (time.perf_counter() - t1)
         plan.profile(True)
         plan.profile_read(reset=True)
         for _ in range(reps):
             plan.matvec(a, b, out=y)
         prof[tag] = plan.profile_read(reset=True)
         plan.profile(False)
-        log(tag, "matvec/s %.1f" % rates[tag], prof[tag])
+        log(tag, "matvec/s %.1f adjoint/s %.1f" % (rates[tag], adj_rates[tag]), prof[tag])
 
     # roofline of the dominant FP32 kernel of the solve (both FP32 plans): the
     # S|R translation kernel (its launches of all levels) or the near field
@@ -346,6 +354,7 @@ def main():
         "fp64_solve": fp64,
         "speedup_vs_fp64_solve": (solves_per_s / fp64["solves_per_s"]) if fp64 else None,
         "fmm_matvecs_per_s": rates,
+        "fmm_adjoint_matvecs_per_s": adj_rates,
         "unknowns_matvec_per_s": {k: 3 * n * v for k, v in rates.items()},
         "stage_ms_per_matvec": {t: {s: v[0] / 10.0 for s, v in prof[t].items()} for t in prof},
         "plan_s_4plans": plan_s,

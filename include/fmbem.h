@@ -190,7 +190,9 @@ typedef struct {
     int32_t serial;      /* 1: the k0 and k1 FMM products of each application run one after  */
                          /*    the other on the caller's stream (0, the default: concurrently */
                          /*    on the caller's stream and the problem's second stream)        */
-    int32_t reserved[4];
+    int32_t adjoint;     /* 1: solve the adjoint system A^H x = rhs, right-preconditioned by */
+                         /*    M^{-H} (info->residual is then |rhs - A^H x| / |rhs|)          */
+    int32_t reserved[3];
 } fmb_gmres_opts;
 
 typedef struct {
@@ -231,6 +233,15 @@ int bem_problem_use_graphs(fmb_problem_t pb, int32_t enable);
 
 /* bem_apply: r = A x, x and r device c128 [nrhs][n][6]. */
 int bem_apply(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, void *stream);
+
+/*
+ * bem_apply_adjoint: r = A^H x, the conjugate transpose of bem_apply's
+ * operator, x and r device c128 [nrhs][n][6].  With (a_j, b_j) = Op_kj^H x_j
+ * (fmm_matvec_adjoint) for x_0 = x[0:3], x_1 = x[3:6]:
+ *   r[0:3] = 1/2 x_0 + a_0 + T^H (1/2 x_1 - a_1),   r[3:6] = conj(gamma) b_1 - b_0.
+ * The first call allocates the plans' adjoint workspaces.
+ */
+int bem_apply_adjoint(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, void *stream);
 
 /* bem_precond_apply: z = M^{-1} v with M = A_self (6x6 per node, eq. 3.2). c128 [nrhs][n][6]. */
 int bem_precond_apply(fmb_problem_t pb, const void *v, void *z, int32_t nrhs, void *stream);

@@ -32,6 +32,7 @@ from .corrections import self_blocks
 from .kernel import wavenumber
 from .native import point_sum_c
 from .direct import apply_corrections
+from .adjoint import apply_corrections_adjoint, point_sum_adjoint
 
 
 class BemProblem:
@@ -72,6 +73,32 @@ class BemProblem:
         self.matvecs += 1
         return np.concatenate([r0, r1], axis=-1)
 
+    def op_adjoint(self, k, corr, y):
+        """(a_bar, b_bar) = Op_k^H y (point sum and self-triangle terms)."""
+        nd = self.nodes
+        a, b = point_sum_adjoint(nd["points"], nd["normals"], nd["weights"], nd["point_tri"], k, y)
+        ca, cb = apply_corrections_adjoint(nd["normals"], nd["point_tri"], corr, y)
+        return a + ca, b + cb
+
+    def apply_adjoint(self, v):
+        """A^H v for v c128[n,6].  Each row of A is a sum of terms; transposing
+        them one by one, with T symmetric (T^H = conj(T)) and (a_j, b_j) = Op_kj^H v_j:
+            (A^H v)[0:3] = 1/2 v0 + a0 + 1/2 T^H v1 - T^H a1
+            (A^H v)[3:6] = -b0 + conj(gamma) b1."""
+        v = np.asarray(v, dtype=np.complex128)
+        v0, v1 = v[..., 0:3], v[..., 3:6]
+        a0, b0 = self.op_adjoint(self.k0, self.corr0, v0)
+        a1, b1 = self.op_adjoint(self.k1, self.corr1, v1)
+        n = self.normals
+        ch = np.conj((1.0 - self.eps) / self.eps)
+
+        def TH(u):
+            return u + ch * n * np.sum(n * u, axis=-1, keepdims=True)
+
+        r0 = 0.5 * v0 + a0 + TH(0.5 * v1 - a1)
+        r1 = -b0 + np.conj(self.gamma) * b1
+        return np.concatenate([r0, r1], axis=-1)
+
     def rhs_planewave(self, d, p):
         """b = (p exp(i k0 d . s), 0) for one direction d and polarisation p."""
         s = self.nodes["points"]
@@ -109,8 +136,11 @@ class BemProblem:
         j = np.argmax(own, axis=1)
         return dV[np.arange(self.n), j], dG[np.arange(self.n), j]
 
-    def block_preconditioner(self):
+    def block_preconditioner(self, adjoint=False):
+        """v -> M^{-1} v, or M^{-H} v (the adjoint system's preconditioner)."""
         Minv = np.linalg.inv(self.precond_blocks())
+        if adjoint:
+            Minv = np.conj(np.transpose(Minv, (0, 2, 1)))
 
         def apply(v):
             return np.einsum("nij,...nj->...ni", Minv, v)

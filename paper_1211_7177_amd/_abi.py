@@ -44,7 +44,7 @@ class GmresOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("x0_given", ctypes.c_int32), ("mixed", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int32), ("serial", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("adjoint", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class GmresInfo(ctypes.Structure):
@@ -54,7 +54,7 @@ class GmresInfo(ctypes.Structure):
 
 EXPORTS = [
     "fmb_plan_opts_default", "fmm_plan", "fmm_matvec", "fmm_matvec_adjoint", "fmm_plan_info",
-    "fmm_plan_export_tree", "fmm_plan_destroy", "fmm_plan_profile", "fmm_plan_profile_read", "fmb_gmres_opts_default", "bem_problem_create", "bem_problem_use_graphs", "bem_apply",
+    "fmm_plan_export_tree", "fmm_plan_destroy", "fmm_plan_profile", "fmm_plan_profile_read", "fmb_gmres_opts_default", "bem_problem_create", "bem_problem_use_graphs", "bem_apply", "bem_apply_adjoint",
     "bem_precond_apply", "bem_rhs_planewave", "gmres_solve", "gmres_solve_group", "bem_problem_destroy", "fmb_last_error",
 ]
 
@@ -85,6 +85,7 @@ def load():
         "fmb_gmres_opts_default": [vp],
         "bem_problem_create": [vp, vp, vp, vp, vp, vp, vp, vp],
         "bem_problem_use_graphs": [vp, i32],
+        "bem_apply_adjoint": [vp, vp, vp, i32, vp],
         "bem_apply": [vp, vp, vp, i32, vp],
         "bem_precond_apply": [vp, vp, vp, i32, vp],
         "bem_rhs_planewave": [vp, vp, vp, vp, i32, vp],

@@ -47,6 +47,7 @@ struct fmb_problem_s {
     hipStream_t s2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool serial = false;       // both products on one stream (set per solve)
+    bool adjoint = false;      // solves and applications use A^H and M^{-H} (set per solve)
     // Optionally (off by default) the two FMM products of an application,
     // captured once per precision and rhs count as a HIP graph and replayed on
     // the problem's own stream s1 (the caller's stream may be the legacy
@@ -259,6 +260,66 @@ __global__ void k_precond_split(const cx<T> *__restrict__ minv, const cx<T> *__r
         b1[i * 3 + c] = -(gamma * x[3 + c]);
     }
 }
+
+// ---- the adjoint system A^H ----
+// With x = (Phi, Psi) the rows of A are r0 = 1/2 Phi + Op0(Phi, -Psi) and
+// r1 = 1/2 T Phi - Op1(T Phi, -gamma Psi), T = I + tc n n^T.  Hence, for v =
+// (v0, v1) and (a_j, b_j) = Op_j^H v_j,
+//   (A^H v)[0:3] = 1/2 v0 + a0 + 1/2 T^H v1 - T^H a1,
+//   (A^H v)[3:6] = -b0 + conj(gamma) b1,          T^H u = u + conj(tc) n (n . u).
+template <typename T>
+__global__ void k_adj_split(const cx<T> *__restrict__ x, int64_t n, int nrhs, cx<T> *__restrict__ y0,
+                            cx<T> *__restrict__ y1) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * nrhs) return;
+    for (int c = 0; c < 3; ++c) {
+        y0[i * 3 + c] = x[i * 6 + c];
+        y1[i * 3 + c] = x[i * 6 + 3 + c];
+    }
+}
+
+// z = M^{-H} v per node (conjugate transpose of the 6x6 block inverse), split as k_adj_split
+template <typename T>
+__global__ void k_adj_precond_split(const cx<T> *__restrict__ minv, const cx<T> *__restrict__ v,
+                                    cx<T> *__restrict__ z, int64_t n, int nrhs, cx<T> *__restrict__ y0,
+                                    cx<T> *__restrict__ y1) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * nrhs) return;
+    const int64_t node = i % n;
+    const cx<T> *M = minv + node * 36;
+    const cx<T> *vi = v + i * 6;
+    cx<T> in[6];
+    for (int q = 0; q < 6; ++q) in[q] = vi[q];
+    for (int r = 0; r < 6; ++r) {
+        cx<T> acc = mk(T(0), T(0));
+        for (int q = 0; q < 6; ++q) acc += conj(M[q * 6 + r]) * in[q];
+        z[i * 6 + r] = acc;
+        if (r < 3) y0[i * 3 + r] = acc;
+        else y1[i * 3 + r - 3] = acc;
+    }
+}
+
+template <typename T>
+__global__ void k_adj_combine(const cx<T> *__restrict__ x, const double *__restrict__ nrm, int64_t n, int nrhs,
+                              cx<double> tcd, cx<double> gammad, const cx<T> *__restrict__ a0,
+                              const cx<T> *__restrict__ b0, const cx<T> *__restrict__ a1,
+                              const cx<T> *__restrict__ b1, cx<T> *__restrict__ r) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * nrhs) return;
+    const int64_t node = i % n;
+    const cx<T> tch = narrow<T>(conj(tcd)), gc = narrow<T>(conj(gammad));
+    const T nv[3] = {(T)nrm[3 * node], (T)nrm[3 * node + 1], (T)nrm[3 * node + 2]};
+    const cx<T> *xi = x + i * 6;
+    cx<T> u[3];                                        // 1/2 v1 - a1, then T^H of it
+    for (int c = 0; c < 3; ++c) u[c] = T(0.5) * xi[3 + c] - a1[i * 3 + c];
+    const cx<T> d = nv[0] * u[0] + nv[1] * u[1] + nv[2] * u[2];
+    for (int c = 0; c < 3; ++c) {
+        r[i * 6 + c] = T(0.5) * xi[c] + a0[i * 3 + c] + u[c] + (nv[c] * tch) * d;
+        r[i * 6 + 3 + c] = gc * b1[i * 3 + c] - b0[i * 3 + c];
+    }
+}
+
+
 
 __global__ void k_rhs_planewave(const double *__restrict__ spts, const int32_t *__restrict__ iperm,
                                 const double *__restrict__ dirs, const double *__restrict__ pols, int64_t n, int nrhs,
@@ -672,12 +733,59 @@ static void fmm_pair(fmb_problem_s &pb, const Plan *P0, const Plan *P1, const cx
     FMB_CHECK_HIP(hipStreamWaitEvent(s, pb.ev_out, 0));
 }
 
+// The two adjoint products of an application: P0 on s and P1 on the
+// problem's second stream (or both on s when the problem runs serially).
+static void adjoint_pair(fmb_problem_s &pb, Plan &P0, Plan &P1, const void *y0, void *a0, void *b0, const void *y1,
+                         void *a1, void *b1, int nrhs, hipStream_t s) {
+    if (pb.serial) {
+        run_matvec_adjoint(P0, y0, a0, b0, nrhs, s);
+        run_matvec_adjoint(P1, y1, a1, b1, nrhs, s);
+        return;
+    }
+    adjoint_prepare(P0);
+    adjoint_prepare(P1);
+    FMB_CHECK_HIP(hipEventRecord(pb.ev_fork, s));
+    FMB_CHECK_HIP(hipStreamWaitEvent(pb.s2, pb.ev_fork, 0));
+    run_matvec_adjoint(P0, y0, a0, b0, nrhs, s);
+    run_matvec_adjoint(P1, y1, a1, b1, nrhs, pb.s2);
+    FMB_CHECK_HIP(hipEventRecord(pb.ev_join, pb.s2));
+    FMB_CHECK_HIP(hipStreamWaitEvent(s, pb.ev_join, 0));
+}
+
+// A^H x; with pre = v, x is first set to M^{-H} v, fused with the split.
+template <typename T>
+static void bem_apply_adjoint_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int nrhs, hipStream_t s,
+                                const cx<T> *pre) {
+    const int64_t n = pb.n;
+    const cx<double> tc = cdiv(mk(1.0, 0.0) - pb.eps, pb.eps);
+    const double *nrm = pb.p0->p.unrm.as<double>();
+    const bool f32 = sizeof(T) == sizeof(float);
+    cx<T> *a0 = (f32 ? pb.a0s : pb.a0).template as<cx<T>>(), *b0 = (f32 ? pb.b0s : pb.b0).template as<cx<T>>(),
+          *a1 = (f32 ? pb.a1s : pb.a1).template as<cx<T>>(), *b1 = (f32 ? pb.b1s : pb.b1).template as<cx<T>>(),
+          *y0 = (f32 ? pb.y0s : pb.y0).template as<cx<T>>(), *y1 = (f32 ? pb.y1s : pb.y1).template as<cx<T>>();
+    if (pre) {
+        k_adj_precond_split<T><<<gridn(n * nrhs), TPB, 0, s>>>((f32 ? pb.minv32 : pb.minv).template as<cx<T>>(),
+                                                                pre, const_cast<cx<T> *>(x), n, nrhs, y0, y1);
+    } else {
+        k_adj_split<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, n, nrhs, y0, y1);
+    }
+    FMB_LAUNCH_CHECK();
+    Plan &P0 = f32 ? pb.p032->p : pb.p0->p, &P1 = f32 ? pb.p132->p : pb.p1->p;
+    adjoint_pair(pb, P0, P1, y0, a0, b0, y1, a1, b1, nrhs, s);
+    k_adj_combine<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, tc, pb.gamma, a0, b0, a1, b1, r);
+    FMB_LAUNCH_CHECK();
+}
+
 // A x with the FP64 plans (T = double) or the FP32 plans (T = float).  With
 // pre = v, x is first set to M^{-1} v (the preconditioned direction), fused
-// with the split.
+// with the split.  A problem in adjoint mode applies A^H and M^{-H} instead.
 template <typename T>
 static void bem_apply_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int nrhs, hipStream_t s,
                         const cx<T> *pre = nullptr) {
+    if (pb.adjoint) {
+        bem_apply_adjoint_t<T>(pb, x, r, nrhs, s, pre);
+        return;
+    }
     const int64_t n = pb.n;
     const cx<double> tc = cdiv(mk(1.0, 0.0) - pb.eps, pb.eps);
     const double *nrm = pb.p0->p.unrm.as<double>();
@@ -864,10 +972,14 @@ static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs,
                       fmb_gmres_info *info, hipStream_t s) {
     check_solve_args(pb, rhs, x, nrhs, op);
     pb->serial = op.serial != 0;
-    struct SerialReset {
+    pb->adjoint = op.adjoint != 0;
+    struct ModeReset {
         fmb_problem_s *p;
-        ~SerialReset() { p->serial = false; }
-    } serial_reset{pb};
+        ~ModeReset() {
+            p->serial = false;
+            p->adjoint = false;
+        }
+    } mode_reset{pb};
     const int64_t len = pb->n * 6, tot = len * nrhs;
     const cx<double> *b = (const cx<double> *)rhs;
     cx<double> *X = (cx<double> *)x;
@@ -1038,6 +1150,14 @@ int bem_apply(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, void *stre
         FMB_REQUIRE(pb && x && r && x != r, "bad arguments");
         FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
         bem_apply_t<double>(*pb, (const cx<double> *)x, (cx<double> *)r, nrhs, (hipStream_t)stream);
+    });
+}
+
+int bem_apply_adjoint(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, void *stream) {
+    return guarded([&] {
+        FMB_REQUIRE(pb && x && r && x != r, "bad arguments");
+        FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
+        bem_apply_adjoint_t<double>(*pb, (const cx<double> *)x, (cx<double> *)r, nrhs, (hipStream_t)stream, nullptr);
     });
 }
 

@@ -9,7 +9,7 @@ from . import _abi
 from ._abi import Plan, check, _stream
 
 
-def _opts(lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, serial):
+def _opts(lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, serial, adjoint=False):
     opts = _abi.GmresOpts()
     check(lib.fmb_gmres_opts_default(ctypes.byref(opts)))
     opts.tol = tol
@@ -20,6 +20,7 @@ def _opts(lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, seri
     opts.inner_tol = inner_tol
     opts.inner_maxit = inner_maxit
     opts.serial = 1 if serial else 0
+    opts.adjoint = 1 if adjoint else 0
     return opts
 
 
@@ -109,6 +110,13 @@ class BemProblem:
         check(self._lib.bem_apply(self.h, px, ctypes.c_void_p(out.data_ptr()), nr, _stream()))
         return out
 
+    def apply_adjoint(self, v):
+        """A^H v, v complex128 [nrhs, n, 6] (or [n, 6]) on the GPU."""
+        out = torch.empty_like(v)
+        pv, nr = self._v(v, "v")
+        check(self._lib.bem_apply_adjoint(self.h, pv, ctypes.c_void_p(out.data_ptr()), nr, _stream()))
+        return out
+
     def precond(self, v):
         out = torch.empty_like(v)
         pv, nr = self._v(v, "v")
@@ -125,8 +133,9 @@ class BemProblem:
         return out
 
     def solve(self, rhs, tol=1e-6, restart=100, maxit=1000, precond=True, mixed=False, inner_tol=1e-3,
-              inner_maxit=300, x0=None, raise_on_noconv=True, serial=False):
-        opts = _opts(self._lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, serial)
+              inner_maxit=300, x0=None, raise_on_noconv=True, serial=False, adjoint=False):
+        """Solve A x = rhs (or A^H x = rhs with adjoint=True) with fGMRES."""
+        opts = _opts(self._lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, serial, adjoint)
         x = torch.zeros_like(rhs) if x0 is None else x0.clone()
         opts.x0_given = 0 if x0 is None else 1
         info = _abi.GmresInfo()

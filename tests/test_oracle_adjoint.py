@@ -65,3 +65,19 @@ def test_correction_adjoint_identity(sphere_nodes, mode):
     ab, bb = apply_corrections_adjoint(q["normals"], q["point_tri"], blk, y)
     lhs = _dot(y, C)
     assert abs(lhs - (_dot(ab, a) + _dot(bb, b))) <= 1e-12 * abs(lhs)
+
+
+def test_bem_apply_adjoint_identity(sphere_nodes):
+    """sum conj(v) . A x = sum conj(A^H v) . x for the 6N system (lossy interior),
+    and M^{-H} is the conjugate transpose of M^{-1} in the same sense."""
+    from oracle.bem import BemProblem
+    q = sphere_nodes[2]
+    n = q["points"].shape[0]
+    ob = BemProblem(q, 1.0, -15 + 1j)
+    x = complex_normal((n, 6), 81)
+    v = complex_normal((n, 6), 82)
+    lhs = _dot(v, ob.apply(x))
+    rhs = _dot(ob.apply_adjoint(v), x)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    P, PH = ob.block_preconditioner(), ob.block_preconditioner(adjoint=True)
+    assert abs(_dot(v, P(x)) - _dot(PH(v), x)) <= 1e-12 * abs(_dot(v, P(x)))
