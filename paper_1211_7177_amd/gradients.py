@@ -1,0 +1,91 @@
+"""Scattering cross section and its gradient in the permittivity by the adjoint method.
+
+C_sca = (Z0 / |E0|^2) oint Re(E_sca x H_sca^*) . n dA (eq. 4.2) taken over the
+scatterer's own surface, where the unknowns give the scattered fields
+directly: E_sca = Phi - E_inc and n x H_sca = (Psi - Psi_inc) / (i omega mu0),
+with Psi = n x curl E (eq. 2.12).  In the units of this library
+(eps0 = mu0 = 1, omega = k0, Z0 = 1) and with (E x H^*) . n = -E . (n x H^*),
+
+    C_sca = -(1/|E0|^2) sum_beta w_beta Re[ E_sca,beta . conj((Psi_beta - Psi_inc,beta) / (i k0)) ].
+
+For dC/d eps: A(eps) x = b gives dx = -A^{-1} (dA/deps) x deps, so with
+g = grad_x C (torch's convention: dC = Re <g, dx>) and the adjoint solution
+lambda = A^{-H} g,
+
+    dC = -Re[ <lambda, (dA/deps) x> deps ].
+
+Only the interior rows depend on eps: through T = I + (1 - eps)/eps n n^T
+(dT/deps = -n n^T / eps^2) and through k1 = k0 sqrt(eps mu) (dk1/deps = k1 / (2 eps)),
+whose operator derivative is taken as the central difference of two products
+at k1 +- delta (plans of the same octree and order).
+"""
+
+import numpy as np
+import torch
+
+from ._abi import Plan
+from .solver import BemProblem
+
+
+def _incident(nodes, k0, d, pol, dtype=torch.complex128):
+    """E_inc and Psi_inc = n x curl E_inc at the nodes (user order), GPU tensors [n, 3]."""
+    s = torch.from_numpy(np.ascontiguousarray(nodes["points"])).cuda()
+    nrm = torch.from_numpy(np.ascontiguousarray(nodes["normals"])).cuda()
+    d = torch.tensor(np.asarray(d, dtype=np.float64), device="cuda")
+    p = torch.tensor(np.asarray(pol, dtype=np.complex128), device="cuda")
+    ph = torch.exp(1j * complex(k0) * (s @ d))
+    E = ph[:, None] * p[None, :]
+    curl = (1j * complex(k0)) * torch.linalg.cross(d.to(torch.complex128).expand_as(E), E)
+    return E.to(dtype), torch.linalg.cross(nrm.to(torch.complex128), curl).to(dtype)
+
+
+def scattering_cross_section(nodes, k0, x, d, pol):
+    """C_sca of the solution x [n, 6] (or [1, n, 6]) for the incident wave p exp(i k0 d . s),
+    as a differentiable torch scalar."""
+    if x.dim() == 3:
+        x = x[0]
+    E, Pi = _incident(nodes, k0, d, pol)
+    w = torch.from_numpy(np.ascontiguousarray(nodes["weights"])).cuda()
+    e0 = float(np.sum(np.abs(np.asarray(pol)) ** 2))
+    esca = x[:, 0:3] - E
+    nh = (x[:, 3:6] - Pi) / (1j * complex(k0))
+    return -torch.sum(w * torch.real(torch.sum(esca * torch.conj(nh), dim=1))) / e0
+
+
+def cross_section_and_eps_gradient(nodes, k0, eps, d, pol, order=16, depth=0, tol=1e-10, restart=150,
+                                   dk_rel=1e-5, mu=1.0):
+    """(C_sca, dC/dRe eps, dC/dIm eps) for one scatterer and one plane wave, by one
+    forward solve, one adjoint solve and three FMM products of the interior plan."""
+    eps = complex(eps)
+    pb = BemProblem(nodes, k0, eps, mu=mu, order=order, depth=depth)
+    dep = pb.p0.info()["depth"]
+    rhs = pb.rhs_planewave(d, pol)
+    kw = dict(tol=tol, restart=restart, maxit=4000)
+    xd, _ = pb.solve(rhs, **kw)
+    xg = xd.clone().requires_grad_(True)
+    C = scattering_cross_section(nodes, k0, xg, d, pol)
+    g = torch.autograd.grad(C, xg)[0]                              # dC = Re <g, dx>
+    lam, _ = pb.solve(g.contiguous(), adjoint=True, **kw)
+    # (dA/deps) x: interior rows only
+    nrm = torch.from_numpy(np.ascontiguousarray(nodes["normals"])).cuda().to(torch.complex128)
+    phi, psi = xd[0, :, 0:3], xd[0, :, 3:6]
+    nphi = torch.sum(nrm * phi, dim=1, keepdim=True)
+    dT_phi = (-1.0 / eps ** 2) * nrm * nphi
+    T_phi = phi + ((1.0 - eps) / eps) * nrm * nphi
+    k1 = pb.k1
+    delta = dk_rel * abs(k1)
+    pts, nn, ww = nodes["points"], nodes["normals"], nodes["weights"]
+    pk = dict(depth=dep, point_tri=nodes["point_tri"], tri_vertices=nodes["tri_vertices"])
+    Pp = Plan(pts, nn, ww, k1 + delta, order, **pk)
+    Pm = Plan(pts, nn, ww, k1 - delta, order, **pk)
+    gamma = pb.mu
+    b_int = (-gamma) * psi
+    dOp = (Pp.matvec(T_phi.contiguous(), b_int.contiguous())
+           - Pm.matvec(T_phi.contiguous(), b_int.contiguous())) / (2.0 * delta)
+    zero = torch.zeros_like(phi)
+    term = 0.5 * dT_phi - pb.p1.matvec(dT_phi.contiguous(), zero) - (k1 / (2.0 * eps)) * dOp
+    u = torch.sum(torch.conj(lam[0, :, 3:6]) * term).item()
+    Pp.close()
+    Pm.close()
+    pb.close()
+    return C.item(), -u.real, u.imag

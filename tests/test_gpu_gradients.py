@@ -1,0 +1,70 @@
+"""The scattering cross section functional and its permittivity gradient by the
+adjoint method (needs an MI355X)."""
+
+import numpy as np
+import pytest
+
+from oracle import mie
+from oracle.bem import BemProblem as OracleBem
+from oracle.gmres import gmres_solve as oracle_gmres
+from synthetic import icosphere, nystrom3
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+D, POL = [0.0, 0.0, 1.0], [1.0, 0.0, 0.0]
+
+
+@pytest.fixture(scope="module")
+def grad():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1211_7177_amd import gradients
+    return gradients
+
+
+def test_cross_section_on_exact_fields_matches_mie(grad):
+    """eq. 4.2 on the sphere's own surface, fed the exact (Mie) surface fields,
+    gives Mie's C_sca (lossless and lossy interiors) to the quadrature error."""
+    q = nystrom3(icosphere(8))
+    for eps in (2.25, 2.25 + 0.5j):
+        xm = torch.from_numpy(mie.surface_unknowns(q, 1.0, 1.0, eps)).cuda()
+        C = grad.scattering_cross_section(q, 1.0, xm, D, POL).item()
+        ref = mie.efficiencies(1.0, np.sqrt(eps))[1] * np.pi
+        print(eps, C, ref)
+        assert abs(C - ref) <= 5e-3 * ref
+
+
+def _oracle_C(q, eps):
+    ob = OracleBem(q, 1.0, eps)
+    b = ob.rhs_planewave(D, POL)
+    x, _ = oracle_gmres(ob.apply, b, ob.block_preconditioner(), tol=1e-12, restart=200)
+    s, n, w = q["points"], q["normals"], q["weights"]
+    e = np.exp(1j * (s @ np.asarray(D)))
+    E = e[:, None] * np.asarray(POL)
+    Pi = np.cross(n, 1j * np.cross(D, POL)[None] * e[:, None])
+    return -np.sum(w * np.real(np.sum((x[:, 0:3] - E) * np.conj((x[:, 3:6] - Pi) / 1j), axis=1)))
+
+
+def test_eps_gradient_matches_differences(grad):
+    """dC/deps from one forward and one adjoint solve against central
+    differences of C: of the GPU solves (both directions of complex eps) and of
+    the oracle's dense-free direct solves (real direction)."""
+    from paper_1211_7177_amd.solver import BemProblem
+    q = nystrom3(icosphere(4))
+    eps = 2.25 + 0.5j
+    C, gr, gi = grad.cross_section_and_eps_gradient(q, 1.0, eps, D, POL, order=18, depth=3, tol=1e-12)
+    h = 1e-5
+    vals = []
+    for de in (h, -h, 1j * h, -1j * h):
+        pb = BemProblem(q, 1.0, eps + de, order=18, depth=3)
+        x, _ = pb.solve(pb.rhs_planewave(D, POL), tol=1e-12, restart=150, maxit=4000)
+        vals.append(grad.scattering_cross_section(q, 1.0, x, D, POL).item())
+        pb.close()
+    fr, fi = (vals[0] - vals[1]) / (2 * h), (vals[2] - vals[3]) / (2 * h)
+    print("adjoint", gr, gi, "gpu differences", fr, fi)
+    assert abs(gr - fr) <= 1e-6 * abs(fr) and abs(gi - fi) <= 1e-6 * max(abs(fi), abs(fr))
+    hr = 1e-5
+    fo = (_oracle_C(q, eps + hr) - _oracle_C(q, eps - hr)) / (2 * hr)
+    print("oracle differences", fo, "C gpu", C, "C oracle", _oracle_C(q, eps))
+    assert abs(gr - fo) <= 1e-5 * abs(fo)
