@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--translate32", choices=["fp32", "bf16x3"], default="bf16x3")
     ap.add_argument("--batch", type=int, default=8,
                     help="also time one lockstep solve of this many plane waves (0: skip)")
+    ap.add_argument("--inner-reorth", action="store_true",
+                    help="second (DGKS-triggered) Gram-Schmidt pass in the inner FP32 solves too")
     ap.add_argument("--serial", action="store_true",
                     help="run the k0 and k1 FMM products of each application one after the other (one stream)")
     ap.add_argument("--autotune", action="store_true",
@@ -161,7 +163,7 @@ def main():
 
     def step(serial=args.serial):
         return pb.solve(rhs, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=args.restart, maxit=2000,
-                        serial=serial)
+                        serial=serial, inner_reorth=args.inner_reorth)
 
     for _ in range(args.warmup):
         _, wi = step()
@@ -209,11 +211,12 @@ def main():
                          translate32=args.translate32, nrhs_max=args.batch)
         db, pob = plane_waves(args.batch, seed_for(2, "dirs"), seed_for(2, "pols"))
         rb = pbb.rhs_planewave(db, pob)
-        pbb.solve(rb, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=args.restart, maxit=2000)
+        pbb.solve(rb, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=args.restart, maxit=2000,
+                  inner_reorth=args.inner_reorth)
         torch.cuda.synchronize()
         tb0 = time.perf_counter()
         _, ib = pbb.solve(rb, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=args.restart,
-                          maxit=2000)
+                          maxit=2000, inner_reorth=args.inner_reorth)
         torch.cuda.synchronize()
         tb = time.perf_counter() - tb0
         batched = {"nrhs": args.batch, "rhs_solves_per_s": args.batch / tb, "ms_per_batch": 1e3 * tb,
@@ -345,7 +348,8 @@ def main():
         "config": {"workload": "torus_R1_r0.3_20000tri_60000nodes_eps-15+1i_k0R4_depth5_planewave",
                    "nodes": n, "unknowns": 6 * n, "depth": depth, "order_fp64": args.order64,
                    "order_fp32": args.order32, "translate_fp32": args.translate32, "tol": args.tol,
-                   "restart": args.restart, "inner_tol": args.inner_tol},
+                   "restart": args.restart, "inner_tol": args.inner_tol,
+                   "inner_gram_schmidt": "two passes (DGKS)" if args.inner_reorth else "one classical pass"},
         "solve": {"iterations": last["iterations"], "refinements": last["refinements"],
                   "bem_applies_fp32": last["matvecs32"], "bem_applies_fp64": last["matvecs64"],
                   "residual": last["residual"]},

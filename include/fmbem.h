@@ -192,7 +192,10 @@ typedef struct {
                          /*    on the caller's stream and the problem's second stream)        */
     int32_t adjoint;     /* 1: solve the adjoint system A^H x = rhs, right-preconditioned by */
                          /*    M^{-H} (info->residual is then |rhs - A^H x| / |rhs|)          */
-    int32_t reserved[3];
+    int32_t inner_reorth;/* mixed mode: 1 = the DGKS-triggered second Gram-Schmidt pass in   */
+                         /*    the inner FP32 solves too; 0 (default) = one classical pass    */
+                         /*    there (FP64 solves always use the DGKS test)                   */
+    int32_t reserved[2];
 } fmb_gmres_opts;
 
 typedef struct {

@@ -44,7 +44,7 @@ class GmresOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("x0_given", ctypes.c_int32), ("mixed", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("inner_maxit", ctypes.c_int32), ("serial", ctypes.c_int32),
-                ("adjoint", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("adjoint", ctypes.c_int32), ("inner_reorth", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class GmresInfo(ctypes.Structure):

@@ -9,7 +9,8 @@ from . import _abi
 from ._abi import Plan, check, _stream
 
 
-def _opts(lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, serial, adjoint=False):
+def _opts(lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, serial, adjoint=False,
+          inner_reorth=False):
     opts = _abi.GmresOpts()
     check(lib.fmb_gmres_opts_default(ctypes.byref(opts)))
     opts.tol = tol
@@ -21,6 +22,7 @@ def _opts(lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, seri
     opts.inner_maxit = inner_maxit
     opts.serial = 1 if serial else 0
     opts.adjoint = 1 if adjoint else 0
+    opts.inner_reorth = 1 if inner_reorth else 0
     return opts
 
 
@@ -133,9 +135,10 @@ class BemProblem:
         return out
 
     def solve(self, rhs, tol=1e-6, restart=100, maxit=1000, precond=True, mixed=False, inner_tol=1e-3,
-              inner_maxit=300, x0=None, raise_on_noconv=True, serial=False, adjoint=False):
+              inner_maxit=300, x0=None, raise_on_noconv=True, serial=False, adjoint=False, inner_reorth=False):
         """Solve A x = rhs (or A^H x = rhs with adjoint=True) with fGMRES."""
-        opts = _opts(self._lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, serial, adjoint)
+        opts = _opts(self._lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, serial, adjoint,
+                     inner_reorth)
         x = torch.zeros_like(rhs) if x0 is None else x0.clone()
         opts.x0_given = 0 if x0 is None else 1
         info = _abi.GmresInfo()

@@ -75,12 +75,15 @@ def test_fp64_solve_matches_oracle_solve(gpu, small):
     pb.close()
 
 
-def test_mixed_precision_refinement_reaches_fp64_tolerance(gpu, small):
+@pytest.mark.parametrize("inner_reorth", [False, True])
+def test_mixed_precision_refinement_reaches_fp64_tolerance(gpu, small, inner_reorth):
+    """Both Gram-Schmidt policies of the inner FP32 solves (one pass, or the
+    DGKS-triggered second pass) reach the FP64 tolerance."""
     q, ob = small
-    print("mixed solve small sphere", flush=True)
+    print("mixed solve small sphere, inner reorth", inner_reorth, flush=True)
     pb = gpu.BemProblem(q, 1.0, 2.25, order=20, depth=3, order32=10)
     b = pb.rhs_planewave([0, 0, 1.0], [1.0, 0, 0])
-    x, info = pb.solve(b, tol=1e-8, mixed=True, inner_tol=1e-3)
+    x, info = pb.solve(b, tol=1e-8, mixed=True, inner_tol=1e-3, inner_reorth=inner_reorth)
     print(info)
     assert info["residual"] <= 1e-8 and info["refinements"] >= 2
     # the answer solves the oracle's system to the same backward error scale
