@@ -146,3 +146,76 @@ class BemProblem:
             return np.einsum("nij,...nj->...ni", Minv, v)
 
         return apply
+
+
+class IbcProblem:
+    """The impedance-boundary-condition system of eq. 2.25 (test infrastructure).
+
+    With n x E = Z n x (n x H) (eq. 2.24) and n x curl E = i omega mu0 n x H,
+    the tangential Psi of the dielectric system is -c n x (n x Phi) with
+    c = i omega mu0 / Z = i k0 / Z (vacuum units).  Substituting into the host
+    rows leaves three unknowns per node, Phi = E_0:
+
+        (A Phi)_alpha = 1/2 Phi_alpha + Op_{k0}(Phi, c n x (n x Phi))_alpha = E_inc(s_alpha),
+
+    n x (n x Phi) = n (n . Phi) - Phi.  The preconditioner keeps the coincident-node
+    block 1/2 I + K(dV) + c dG (n n^T - I).
+    """
+
+    def __init__(self, nodes, k0: float, Z: complex, mode="linear"):
+        self.nodes = nodes
+        self.k0 = complex(k0)
+        self.Z = complex(Z)
+        self.c = 1j * self.k0 / self.Z
+        self.n = nodes["points"].shape[0]
+        self.normals = nodes["normals"]
+        args = (nodes["points"], nodes["normals"], nodes["point_tri"], nodes["tri_vertices"])
+        self.corr0 = self_blocks(*args, self.k0, mode=mode)
+
+    def nnx(self, v):
+        """n x (n x v) = n (n . v) - v."""
+        n = self.normals
+        return n * np.sum(n * v, axis=-1, keepdims=True) - v
+
+    def apply(self, phi):
+        nd = self.nodes
+        phi = np.asarray(phi, dtype=np.complex128)
+        b = self.c * self.nnx(phi)
+        y = point_sum_c(nd["points"], nd["normals"], nd["weights"], nd["point_tri"], self.k0, phi, b)
+        return 0.5 * phi + y + apply_corrections(nd["normals"], nd["point_tri"], self.corr0, phi, b)
+
+    def apply_adjoint(self, v):
+        """A^H v = 1/2 v + a + conj(c) n x (n x b), (a, b) = Op_{k0}^H v (n x (n x .) is real symmetric)."""
+        nd = self.nodes
+        v = np.asarray(v, dtype=np.complex128)
+        a, b = point_sum_adjoint(nd["points"], nd["normals"], nd["weights"], nd["point_tri"], self.k0, v)
+        ca, cb = apply_corrections_adjoint(nd["normals"], nd["point_tri"], self.corr0, v)
+        return 0.5 * v + a + ca + np.conj(self.c) * self.nnx(b + cb)
+
+    def rhs_planewave(self, d, p):
+        s = self.nodes["points"]
+        e = np.exp(1j * self.k0 * (s @ np.asarray(d, dtype=np.float64)))
+        return e[:, None] * np.asarray(p)[None, :]
+
+    def precond_blocks(self):
+        n = self.normals
+        I3 = np.eye(3)
+        nn = n[:, :, None] * n[:, None, :]
+        nodes, dV, dG = self.corr0
+        own = nodes[self.nodes["point_tri"]] == np.arange(self.n)[:, None]
+        j = np.argmax(own, axis=1)
+        V = dV[np.arange(self.n), j]
+        G = dG[np.arange(self.n), j]
+        nV = np.sum(n * V, axis=1)
+        K = n[:, :, None] * V[:, None, :] - nV[:, None, None] * I3[None] - V[:, :, None] * n[:, None, :]
+        return 0.5 * I3[None] + K + (self.c * G)[:, None, None] * (nn - I3[None])
+
+    def block_preconditioner(self, adjoint=False):
+        Minv = np.linalg.inv(self.precond_blocks())
+        if adjoint:
+            Minv = np.conj(np.transpose(Minv, (0, 2, 1)))
+
+        def apply(v):
+            return np.einsum("nij,...nj->...ni", Minv, v)
+
+        return apply

@@ -93,15 +93,46 @@ def _vsh(n, k, r, theta, phi, kind):
     return Mo, Me, No, Ne
 
 
-def fields(points, k: float, a: float, eps: complex, region="outside", nmax=None):
+def impedance_coefficients(x: float, Z: complex, nmax=None):
+    """a_n, b_n of a sphere whose surface obeys n x E = Z n x (n x H) (eq. 2.24,
+    Z relative to the vacuum impedance).  They are the dielectric coefficients
+    above in the limit of a large lossy index m = 1/Z, where
+    psi_n'(mx)/psi_n(mx) -> -i:
+        a_n = (psi_n'(x) + i Z psi_n(x)) / (xi_n'(x) + i Z xi_n(x)),
+        b_n = (psi_n(x) - i Z psi_n'(x)) / (xi_n(x) - i Z xi_n'(x))."""
+    if nmax is None:
+        nmax = int(np.ceil(x + 4.0 * x ** (1.0 / 3.0) + 2.0))
+    n = np.arange(1, nmax + 1)
+    jx, djx = _jn(n, x), _jn(n, x, True)
+    hx, dhx = _hn(n, x), _hn(n, x, True)
+    psi, dpsi = x * jx, jx + x * djx
+    xi, dxi = x * hx, hx + x * dhx
+    Z = complex(Z)
+    a = (dpsi + 1j * Z * psi) / (dxi + 1j * Z * xi)
+    b = (psi - 1j * Z * dpsi) / (xi - 1j * Z * dxi)
+    return n, a, b
+
+
+def impedance_fields(points, k: float, a: float, Z: complex, nmax=None):
+    """(E, curl E) of the total host field around the impedance sphere."""
+    n, an, bn = impedance_coefficients(k * a, Z, nmax)
+    return fields(points, k, a, None, "outside", coeffs=(n, an, bn))
+
+
+def fields(points, k: float, a: float, eps: complex, region="outside", nmax=None, coeffs=None):
     """(E, curl E) at points for E_inc = x^ exp(i k z).  region 'outside'
-    gives the total host field E_inc + E_sca, 'inside' the interior field."""
+    gives the total host field E_inc + E_sca, 'inside' the interior field.
+    coeffs = (n, a_n, b_n) replaces the dielectric scattering coefficients."""
     p = np.asarray(points, dtype=np.float64)
     r = np.linalg.norm(p, axis=1)
     theta = np.arccos(np.clip(p[:, 2] / r, -1.0, 1.0))
     phi = np.arctan2(p[:, 1], p[:, 0])
-    m = np.sqrt(complex(eps))
-    n, an, bn, cn, dn = coefficients(k * a, m, nmax)
+    if coeffs is not None:
+        n, an, bn = coeffs
+        m = None
+    else:
+        m = np.sqrt(complex(eps))
+        n, an, bn, cn, dn = coefficients(k * a, m, nmax)
     En = (1j ** n) * (2 * n + 1) / (n * (n + 1))
     if region == "outside":
         Mo1, Me1, No1, Ne1 = _vsh(n, k, r, theta, phi, 1)
