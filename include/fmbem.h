@@ -224,6 +224,20 @@ int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_
                        const double *eps, const double *mu, void *stream, fmb_problem_t *out);
 
 /*
+ * bem_problem_create_ibc: the impedance-boundary-condition system of eq. 2.25
+ * for a good conductor: with n x E = Z n x (n x H) (eq. 2.24) the unknowns
+ * are Phi = E_0 alone (three per node), and
+ *   (A Phi) = 1/2 Phi + Op_{k0}(Phi, c n x (n x Phi)),   c = i k0 / Z,
+ * right-preconditioned by the 3x3 self blocks 1/2 I + K(dV) + c dG (n n^T - I).
+ * p0: FP64 plan at k0 with self-triangle corrections; p0_32: optional FP32
+ * plan of the same nodes and wavenumber (mixed solves); Z: host c128 surface
+ * impedance relative to vacuum (Z = sqrt(mu/eps) of the conductor).  On such
+ * a problem bem_apply, bem_apply_adjoint, bem_precond_apply,
+ * bem_rhs_planewave and gmres_solve(_group) take [nrhs][n][3] vectors.
+ */
+int bem_problem_create_ibc(fmb_plan_t p0, fmb_plan_t p0_32, const double *Z, void *stream, fmb_problem_t *out);
+
+/*
  * bem_problem_use_graphs: enable (1) or disable (0, the default) the replay of
  * the two FMM products of each application from a captured HIP graph.  The
  * graph is captured on first use per precision and rhs count, on a stream the

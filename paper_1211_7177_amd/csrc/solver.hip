@@ -41,7 +41,12 @@ struct fmb_problem_s {
     fmb::cx<double> eps, mu, gamma;
     double k0_re = 0, k0_im = 0;
     int nrhs_max = 1;
-    fmb::DevBuf minv;          // c128[n][6][6]
+    // impedance boundary condition problems (eq. 2.25): one plan, three unknowns
+    // per node, Psi replaced by -c n x (n x Phi) with c = i k0 / Z
+    bool ibc = false;
+    int nu = 6;                // unknowns per node: 6 (Phi, Psi) or 3 (Phi, ibc)
+    fmb::cx<double> cibc;
+    fmb::DevBuf minv;          // c128[n][6][6] (c128[n][3][3] for ibc)
     fmb::DevBuf minv32;        // c64[n][6][6], FP32 copy for the inner solves (FP32 plans only)
     fmb::DevBuf upts;          // f64[n][3] user order
     // matvec staging [nrhs][n][3] for the two plans (FP64) and their FP32 copies
@@ -327,7 +332,7 @@ __global__ void k_adj_combine(const cx<T> *__restrict__ x, const double *__restr
 
 __global__ void k_rhs_planewave(const double *__restrict__ spts, const int32_t *__restrict__ iperm,
                                 const double *__restrict__ dirs, const double *__restrict__ pols, int64_t n, int nrhs,
-                                double k_re, double k_im, cx<double> *__restrict__ rhs) {
+                                double k_re, double k_im, int nu, cx<double> *__restrict__ rhs) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n * nrhs) return;
     const int64_t node = i % n, q = i / n;
@@ -337,10 +342,133 @@ __global__ void k_rhs_planewave(const double *__restrict__ spts, const int32_t *
     double s, c;
     sincos(k_re * ph, &s, &c);
     const double e = exp(-k_im * ph);
-    for (int d = 0; d < 3; ++d) {
-        rhs[i * 6 + d] = mk(pols[3 * q + d] * e * c, pols[3 * q + d] * e * s);
-        rhs[i * 6 + 3 + d] = mk(0.0, 0.0);
+    for (int d = 0; d < 3; ++d) rhs[i * nu + d] = mk(pols[3 * q + d] * e * c, pols[3 * q + d] * e * s);
+    for (int d = 3; d < nu; ++d) rhs[i * nu + d] = mk(0.0, 0.0);
+}
+
+// ---- impedance boundary condition (eq. 2.25), three unknowns per node ----
+//   A Phi = 1/2 Phi + Op0(Phi, c n x (n x Phi)),  n x (n x v) = n (n . v) - v,
+//   A^H v = 1/2 v + a + conj(c) n x (n x b),  (a, b) = Op0^H v.
+template <typename T>
+__device__ inline void nnx(const T nv[3], const cx<T> in[3], cx<T> out[3]) {
+    const cx<T> d = nv[0] * in[0] + nv[1] * in[1] + nv[2] * in[2];
+    for (int q = 0; q < 3; ++q) out[q] = nv[q] * d - in[q];
+}
+
+// b = c n x (n x x); with minv, x is first set to M^{-1} v (3x3 blocks)
+template <typename T>
+__global__ void k_ibc_split(const cx<T> *__restrict__ minv, const cx<T> *__restrict__ v, cx<T> *__restrict__ x,
+                            const double *__restrict__ nrm, int64_t n, int nrhs, cx<double> cd,
+                            cx<T> *__restrict__ b) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * nrhs) return;
+    const int64_t node = i % n;
+    const T nv[3] = {(T)nrm[3 * node], (T)nrm[3 * node + 1], (T)nrm[3 * node + 2]};
+    cx<T> xi[3];
+    if (minv) {
+        const cx<T> *M = minv + node * 9;
+        for (int r = 0; r < 3; ++r) {
+            cx<T> acc = mk(T(0), T(0));
+            for (int q = 0; q < 3; ++q) acc += M[r * 3 + q] * v[i * 3 + q];
+            xi[r] = acc;
+        }
+        for (int r = 0; r < 3; ++r) x[i * 3 + r] = xi[r];
+    } else {
+        for (int r = 0; r < 3; ++r) xi[r] = x[i * 3 + r];
     }
+    cx<T> t[3];
+    nnx(nv, xi, t);
+    const cx<T> c = narrow<T>(cd);
+    for (int q = 0; q < 3; ++q) b[i * 3 + q] = c * t[q];
+}
+
+template <typename T>
+__global__ void k_ibc_combine(const cx<T> *__restrict__ x, const cx<T> *__restrict__ y0, int64_t m,
+                              cx<T> *__restrict__ r) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < m) r[i] = T(0.5) * x[i] + y0[i];
+}
+
+// z = M^{-H} v (3x3 blocks)
+template <typename T>
+__global__ void k_ibc_adj_precond(const cx<T> *__restrict__ minv, const cx<T> *__restrict__ v, cx<T> *__restrict__ z,
+                                  int64_t n, int nrhs) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * nrhs) return;
+    const cx<T> *M = minv + (i % n) * 9;
+    for (int r = 0; r < 3; ++r) {
+        cx<T> acc = mk(T(0), T(0));
+        for (int q = 0; q < 3; ++q) acc += conj(M[q * 3 + r]) * v[i * 3 + q];
+        z[i * 3 + r] = acc;
+    }
+}
+
+template <typename T>
+__global__ void k_ibc_adj_combine(const cx<T> *__restrict__ x, const double *__restrict__ nrm, int64_t n, int nrhs,
+                                  cx<double> cd, const cx<T> *__restrict__ a0, const cx<T> *__restrict__ b0,
+                                  cx<T> *__restrict__ r) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * nrhs) return;
+    const int64_t node = i % n;
+    const T nv[3] = {(T)nrm[3 * node], (T)nrm[3 * node + 1], (T)nrm[3 * node + 2]};
+    cx<T> bb[3], t[3];
+    for (int q = 0; q < 3; ++q) bb[q] = b0[i * 3 + q];
+    nnx(nv, bb, t);
+    const cx<T> ch = narrow<T>(conj(cd));
+    for (int q = 0; q < 3; ++q) r[i * 3 + q] = T(0.5) * x[i * 3 + q] + a0[i * 3 + q] + ch * t[q];
+}
+
+// 3x3 preconditioner blocks 1/2 I + K(dV) + c dG (n n^T - I), inverted by Gauss-Jordan in FP64
+__global__ void k_ibc_precond_build(const double *__restrict__ nrm, const int32_t *__restrict__ point_tri,
+                                    const int32_t *__restrict__ tri_nodes, int m, const cx<double> *__restrict__ cv,
+                                    const cx<double> *__restrict__ cg, int64_t n, cx<double> c,
+                                    cx<double> *__restrict__ minv, int32_t *__restrict__ bad) {
+    int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    const int32_t t = point_tri[a];
+    int js = 0;
+    for (int j = 0; j < m; ++j)
+        if (tri_nodes[(int64_t)t * m + j] == (int32_t)a) js = j;
+    const double nv[3] = {nrm[3 * a], nrm[3 * a + 1], nrm[3 * a + 2]};
+    cx<double> V[3];
+    for (int i = 0; i < 3; ++i) V[i] = cv[(a * m + js) * 3 + i];
+    const cx<double> cG = c * cg[a * m + js];
+    const cx<double> nV = nv[0] * V[0] + nv[1] * V[1] + nv[2] * V[2];
+    cx<double> A[3][6];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double d = i == j ? 1.0 : 0.0;
+            A[i][j] = mk(0.5 * d, 0.0) + nv[i] * V[j] - d * nV - V[i] * nv[j] + (nv[i] * nv[j] - d) * cG;
+            A[i][3 + j] = mk(d, 0.0);
+        }
+    for (int col = 0; col < 3; ++col) {
+        int piv = col;
+        double best = abs2(A[col][col]);
+        for (int r = col + 1; r < 3; ++r)
+            if (abs2(A[r][col]) > best) {
+                best = abs2(A[r][col]);
+                piv = r;
+            }
+        if (!(best > 0.0)) {
+            atomicOr(bad, 1);
+            return;
+        }
+        if (piv != col)
+            for (int j = 0; j < 6; ++j) {
+                const cx<double> tmp = A[col][j];
+                A[col][j] = A[piv][j];
+                A[piv][j] = tmp;
+            }
+        const cx<double> inv = cdiv(mk(1.0, 0.0), A[col][col]);
+        for (int j = 0; j < 6; ++j) A[col][j] = A[col][j] * inv;
+        for (int r = 0; r < 3; ++r) {
+            if (r == col) continue;
+            const cx<double> f = A[r][col];
+            for (int j = 0; j < 6; ++j) A[r][j] -= f * A[col][j];
+        }
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) minv[a * 9 + i * 3 + j] = A[i][3 + j];
 }
 
 // ---- Krylov kernels (vectors of length len per rhs, stride len) ----
@@ -756,10 +884,45 @@ static void adjoint_pair(fmb_problem_s &pb, Plan &P0, Plan &P1, const void *y0, 
     FMB_CHECK_HIP(hipStreamWaitEvent(s, pb.ev_join, 0));
 }
 
+// The impedance-boundary-condition system: A x (or A^H x in adjoint mode)
+// with the k0 plan alone; with pre = v, x is first set to M^{-1} v (M^{-H} v).
+template <typename T>
+static void ibc_apply_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int nrhs, hipStream_t s, const cx<T> *pre) {
+    const int64_t n = pb.n;
+    const double *nrm = pb.p0->p.unrm.as<double>();
+    const bool f32 = sizeof(T) == sizeof(float);
+    cx<T> *a0 = (f32 ? pb.a0s : pb.a0).template as<cx<T>>(), *b0 = (f32 ? pb.b0s : pb.b0).template as<cx<T>>(),
+          *y0 = (f32 ? pb.y0s : pb.y0).template as<cx<T>>();
+    const cx<T> *minv = (f32 ? pb.minv32 : pb.minv).template as<cx<T>>();
+    Plan &P0 = f32 ? pb.p032->p : pb.p0->p;
+    cx<T> *xw = const_cast<cx<T> *>(x);
+    if (!pb.adjoint) {
+        k_ibc_split<T><<<gridn(n * nrhs), TPB, 0, s>>>(pre ? minv : nullptr, pre, xw, nrm, n, nrhs, pb.cibc, b0);
+        FMB_LAUNCH_CHECK();
+        run_matvec(P0, x, b0, y0, nrhs, s);
+        k_ibc_combine<T><<<gridn(n * nrhs * 3), TPB, 0, s>>>(x, y0, n * nrhs * 3, r);
+    } else {
+        if (pre) {
+            k_ibc_adj_precond<T><<<gridn(n * nrhs), TPB, 0, s>>>(minv, pre, xw, n, nrhs);
+            FMB_LAUNCH_CHECK();
+        }
+        run_matvec_adjoint(P0, x, a0, b0, nrhs, s);
+        k_ibc_adj_combine<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, pb.cibc, a0, b0, r);
+    }
+    FMB_LAUNCH_CHECK();
+}
+
 // A^H x; with pre = v, x is first set to M^{-H} v, fused with the split.
 template <typename T>
 static void bem_apply_adjoint_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int nrhs, hipStream_t s,
                                 const cx<T> *pre) {
+    if (pb.ibc) {
+        const bool was = pb.adjoint;
+        pb.adjoint = true;
+        ibc_apply_t<T>(pb, x, r, nrhs, s, pre);
+        pb.adjoint = was;
+        return;
+    }
     const int64_t n = pb.n;
     const cx<double> tc = cdiv(mk(1.0, 0.0) - pb.eps, pb.eps);
     const double *nrm = pb.p0->p.unrm.as<double>();
@@ -786,6 +949,10 @@ static void bem_apply_adjoint_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int
 template <typename T>
 static void bem_apply_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int nrhs, hipStream_t s,
                         const cx<T> *pre = nullptr) {
+    if (pb.ibc) {
+        ibc_apply_t<T>(pb, x, r, nrhs, s, pre);
+        return;
+    }
     if (pb.adjoint) {
         bem_apply_adjoint_t<T>(pb, x, r, nrhs, s, pre);
         return;
@@ -815,6 +982,14 @@ static void bem_apply_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int nrhs, h
 template <typename T>
 static void precond_t(fmb_problem_s &pb, const cx<T> *v, cx<T> *z, int nrhs, hipStream_t s) {
     const bool f32 = sizeof(T) == sizeof(float);
+    if (pb.ibc) {
+        // z = M^{-1} v through the split kernel (its b output lands in the staging buffer)
+        k_ibc_split<T><<<gridn(pb.n * nrhs), TPB, 0, s>>>((f32 ? pb.minv32 : pb.minv).template as<cx<T>>(), v, z,
+                                                           pb.p0->p.unrm.as<double>(), pb.n, nrhs, pb.cibc,
+                                                           (f32 ? pb.b0s : pb.b0).template as<cx<T>>());
+        FMB_LAUNCH_CHECK();
+        return;
+    }
     k_precond_apply<T><<<gridn(pb.n * nrhs), TPB, 0, s>>>((f32 ? pb.minv32 : pb.minv).template as<cx<T>>(), v, z,
                                                            pb.n, nrhs);
     FMB_LAUNCH_CHECK();
@@ -988,7 +1163,7 @@ static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs,
             p->adjoint = false;
         }
     } mode_reset{pb};
-    const int64_t len = pb->n * 6, tot = len * nrhs;
+    const int64_t len = pb->n * pb->nu, tot = len * nrhs;
     const cx<double> *b = (const cx<double> *)rhs;
     cx<double> *X = (cx<double> *)x;
     std::vector<double> relres, hist;
@@ -1147,6 +1322,68 @@ int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_
     });
 }
 
+int bem_problem_create_ibc(fmb_plan_t p0, fmb_plan_t p0_32, const double *Z, void *stream, fmb_problem_t *out) {
+    return guarded([&] {
+        FMB_REQUIRE(out != nullptr, "out is NULL");
+        *out = nullptr;
+        FMB_REQUIRE(p0 != nullptr && Z != nullptr, "the k0 plan and Z are required");
+        const Plan &A = p0->p;
+        FMB_REQUIRE(A.precision == FMB_FP64, "p0 must be an FP64 plan");
+        FMB_REQUIRE(A.corr_mode != FMB_CORR_NONE, "the IBC system needs self-triangle corrections");
+        if (p0_32) {
+            FMB_REQUIRE(p0_32->p.n == A.n && p0_32->p.precision == FMB_FP32, "p0_32 must be an FP32 plan of the nodes");
+            FMB_REQUIRE(p0_32->p.k_re == A.k_re && p0_32->p.k_im == A.k_im, "p0_32 must have the wavenumber of p0");
+        }
+        const cx<double> z = mk(Z[0], Z[1]);
+        FMB_REQUIRE(std::isfinite(z.re) && std::isfinite(z.im) && abs2(z) > 0.0, "Z must be finite and non-zero");
+        hipStream_t s = (hipStream_t)stream;
+        auto *h = new fmb_problem_s;
+        std::unique_ptr<fmb_problem_s> guard(h);
+        h->p0 = p0;
+        h->p032 = p0_32;
+        h->ibc = true;
+        h->nu = 3;
+        h->n = A.n;
+        h->eps = mk(1.0, 0.0);
+        h->mu = mk(1.0, 0.0);
+        h->gamma = h->mu;
+        h->k0_re = A.k_re;
+        h->k0_im = A.k_im;
+        h->cibc = cdiv(mk(-A.k_im, A.k_re), z);              // i k0 / Z
+        int nr = A.nrhs_max;
+        if (p0_32) nr = std::min(nr, p0_32->p.nrhs_max);
+        h->nrhs_max = nr;
+        const size_t m3 = (size_t)A.n * 3 * nr;
+        for (DevBuf *d : {&h->a0, &h->b0, &h->y0}) d->alloc(m3 * sizeof(cx<double>));
+        if (p0_32)
+            for (DevBuf *d : {&h->a0s, &h->b0s, &h->y0s}) d->alloc(m3 * sizeof(cx<float>));
+        h->minv.alloc((size_t)A.n * 9 * sizeof(cx<double>));
+        DevBuf bad;
+        bad.alloc(sizeof(int32_t));
+        FMB_CHECK_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+        k_ibc_precond_build<<<gridn(A.n), TPB, 0, s>>>(A.unrm.as<double>(), A.point_tri.as<int32_t>(),
+                                                        A.tri_nodes.as<int32_t>(), (int)A.tri_m,
+                                                        A.corr_v.as<cx<double>>(), A.corr_g.as<cx<double>>(), A.n,
+                                                        h->cibc, h->minv.as<cx<double>>(), bad.as<int32_t>());
+        FMB_LAUNCH_CHECK();
+        int32_t hb = 0;
+        FMB_CHECK_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        FMB_CHECK_HIP(hipStreamSynchronize(s));
+        FMB_REQUIRE(hb == 0, "a 3x3 self block of the preconditioner is singular");
+        if (p0_32) {
+            h->minv32.alloc((size_t)A.n * 9 * sizeof(cx<float>));
+            k_to32<<<gridn(A.n * 9), TPB, 0, s>>>(h->minv.as<cx<double>>(), h->minv32.as<cx<float>>(), A.n * 9);
+            FMB_LAUNCH_CHECK();
+            FMB_CHECK_HIP(hipStreamSynchronize(s));
+        }
+        FMB_CHECK_HIP(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
+        FMB_CHECK_HIP(hipStreamCreateWithFlags(&h->s1, hipStreamNonBlocking));
+        for (hipEvent_t *e : {&h->ev_fork, &h->ev_join, &h->ev_in, &h->ev_out})
+            FMB_CHECK_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+        *out = guard.release();
+    });
+}
+
 int bem_problem_use_graphs(fmb_problem_t pb, int32_t enable) {
     return guarded([&] {
         FMB_REQUIRE(pb != nullptr, "problem is NULL");
@@ -1191,7 +1428,7 @@ int bem_rhs_planewave(fmb_problem_t pb, const double *dirs, const double *pols, 
         FMB_CHECK_HIP(hipMemcpyAsync(dp.p, pols, nrhs * 3 * sizeof(double), hipMemcpyHostToDevice, s));
         const Plan &A = pb->p0->p;
         k_rhs_planewave<<<gridn(pb->n * nrhs), TPB, 0, s>>>(A.spts.as<double>(), A.iperm.as<int32_t>(), dd.as<double>(),
-                                                            dp.as<double>(), pb->n, nrhs, pb->k0_re, pb->k0_im,
+                                                            dp.as<double>(), pb->n, nrhs, pb->k0_re, pb->k0_im, pb->nu,
                                                             (cx<double> *)rhs);
         FMB_LAUNCH_CHECK();
         FMB_CHECK_HIP(hipStreamSynchronize(s));

@@ -95,10 +95,12 @@ class BemProblem:
                                      _stream(), ctypes.byref(h)))
         self.h = h
 
+    nu = 6                      # unknowns per node
+
     def _v(self, t, name):
         if t.dim() == 2:
             t = t.unsqueeze(0)
-        return _abi._dev(t, torch.complex128, (self.n, 6), name), t.shape[0]
+        return _abi._dev(t, torch.complex128, (self.n, self.nu), name), t.shape[0]
 
     def use_graphs(self, enable=True):
         """Replay the two FMM products of each application from a captured HIP
@@ -129,7 +131,7 @@ class BemProblem:
         d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
         p = np.ascontiguousarray(np.atleast_2d(pols), dtype=np.float64)
         nr = d.shape[0]
-        out = torch.empty((nr, self.n, 6), dtype=torch.complex128, device="cuda")
+        out = torch.empty((nr, self.n, self.nu), dtype=torch.complex128, device="cuda")
         check(self._lib.bem_rhs_planewave(self.h, d.ctypes.data, p.ctypes.data, ctypes.c_void_p(out.data_ptr()),
                                           nr, _stream()))
         return out
@@ -163,3 +165,36 @@ class BemProblem:
             self.close()
         except Exception:
             pass
+
+
+class IbcProblem(BemProblem):
+    """A good conductor under the impedance boundary condition (eqs. 2.24-2.25):
+    three unknowns per node (Phi = E_0), one plan at k0, surface impedance Z
+    relative to vacuum.  Vectors are complex128 [nrhs, n, 3]; `apply`,
+    `apply_adjoint`, `precond`, `rhs_planewave` and `solve` work as for
+    BemProblem."""
+
+    nu = 3
+
+    def __init__(self, nodes, k0, Z, order=16, depth=0, nrhs_max=1, order32=None, corr="linear", leaf_target=32,
+                 translate32="fp32"):
+        lib = _abi.load()
+        self._lib = lib
+        self.k0 = complex(k0)
+        self.Z = complex(Z)
+        kw = dict(point_tri=nodes["point_tri"], tri_vertices=nodes["tri_vertices"], nrhs_max=nrhs_max,
+                  corr=corr, depth=depth, leaf_target=leaf_target)
+        pts, nrm, w = nodes["points"], nodes["normals"], nodes["weights"]
+        self.p0 = Plan(pts, nrm, w, self.k0, order, **kw)
+        kw["depth"] = self.p0.info()["depth"]
+        self.p1 = self.p1_32 = None
+        self.p0_32 = None
+        if order32:
+            self.p0_32 = Plan(pts, nrm, w, self.k0, order32, precision="fp32", translate=translate32, **kw)
+        self.n = pts.shape[0]
+        self.nrhs_max = nrhs_max
+        z = np.array([self.Z.real, self.Z.imag])
+        h = ctypes.c_void_p()
+        check(lib.bem_problem_create_ibc(self.p0.h, self.p0_32.h if self.p0_32 else None, z.ctypes.data, _stream(),
+                                         ctypes.byref(h)))
+        self.h = h
