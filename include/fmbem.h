@@ -293,6 +293,25 @@ int gmres_solve(fmb_problem_t pb, const void *rhs, void *x, int32_t nrhs, const 
 int gmres_solve_group(const fmb_problem_t *pbs, int32_t count, const void *const *rhs, void *const *x,
                       const int32_t *nrhs, const fmb_gmres_opts *o, fmb_gmres_info *info, void *stream);
 
+/*
+ * bem_field: fields away from the surface from a solution x (device c128
+ * [nrhs][n][nu], nu = 6, or 3 for an impedance problem).  Eq. 2.5 at points off
+ * the boundary carries the jump term 1 instead of 1/2, so with the rows of
+ * bem_apply:
+ *   region 0, far 0: the scattered field at host points, E_sca(r) = -Op_k0(Phi, -Psi)(r)
+ *                    (b = c n x (n x Phi) in place of -Psi for an impedance problem);
+ *   region 1, far 0: the field inside the scatterer, E_1(r) = Op_k1(T Phi, -gamma Psi)(r)
+ *                    (dielectric problems);
+ *   region 0, far 1: the far-field amplitude F(rhat), E_sca ~ e^{i k0 r} / r F(rhat), for unit
+ *                    directions rhat.
+ * points: host f64[nt][3] target points (off the surface: a target that
+ * coincides with a node skips that node) or unit directions; E: device c128
+ * [nrhs][nt][3].  Direct FP64 sums over all nodes (cost nt * n per right-hand
+ * side); synchronous.
+ */
+int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt, int32_t region,
+              int32_t far, void *E, void *stream);
+
 int bem_problem_destroy(fmb_problem_t pb);
 
 /* Thread-local message for the last non-zero status returned on this thread. */

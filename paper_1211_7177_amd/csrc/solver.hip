@@ -471,6 +471,111 @@ __global__ void k_ibc_precond_build(const double *__restrict__ nrm, const int32_
         for (int j = 0; j < 3; ++j) minv[a * 9 + i * 3 + j] = A[i][3 + j];
 }
 
+// ---- fields off the surface ----
+// Eq. 2.5 at points off the boundary has the jump term 1 instead of 1/2, so in
+// the row convention of the system the scattered field at host points is
+// E_sca(r) = -Op_k0(a, b)(r) with a = Phi, b = -Psi (b = c n x (n x Phi) for the
+// impedance condition), and the field inside the scatterer is
+// E_1(r) = Op_k1(T Phi, -gamma Psi)(r), where
+//   Op(a, b)(r) = sum_beta w_beta [ n (G . a) - (n . G) a - G (n . a) + g b ],
+//   g = e^{ikR} / (4 pi R), G = grad' g = (ikR - 1) g (s_beta - r) / R^2.
+// Far away E_sca ~ e^{ikr} / r F(rhat) with
+//   F(rhat) = -(1/4pi) sum_beta w_beta e^{-ik rhat . s_beta} [ -ik (n (rhat . a) - (n . rhat) a - rhat (n . a)) + b ].
+// Both are direct FP64 sums over all nodes: one thread per target point or
+// direction, the nodes streamed through LDS in tiles.
+constexpr int FE_TILE = 128;
+
+struct FieldSrc {
+    double pos[FE_TILE][3];
+    double nrm[FE_TILE][3];
+    double w[FE_TILE];
+    cx<double> a[FE_TILE][3], b[FE_TILE][3];
+};
+
+// region: 0 host (scattered field), 1 interior; far: targets are unit directions
+template <bool FAR>
+__global__ void __launch_bounds__(FE_TILE) k_field(const double *__restrict__ tgt, int64_t nt,
+                                                   const double *__restrict__ spts, const double *__restrict__ snrm,
+                                                   const double *__restrict__ sw, const int32_t *__restrict__ perm,
+                                                   const cx<double> *__restrict__ x, int64_t n, int nu, int region,
+                                                   int ibc, double k_re, double k_im, cx<double> tc,
+                                                   cx<double> gamma, cx<double> cibc, cx<double> *__restrict__ out) {
+    __shared__ FieldSrc S;
+    const int r = blockIdx.y;
+    const int64_t t = blockIdx.x * (int64_t)FE_TILE + threadIdx.x;
+    const bool active = t < nt;
+    double p[3] = {0, 0, 0};
+    if (active)
+        for (int q = 0; q < 3; ++q) p[q] = tgt[3 * t + q];
+    cx<double> acc[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+    const cx<double> k = mk(k_re, k_im);
+    const double inv4pi = 0.07957747154594766788;
+    for (int64_t base = 0; base < n; base += FE_TILE) {
+        const int cnt = (int)min((int64_t)FE_TILE, n - base);
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) {
+            const int j = threadIdx.x;
+            const int64_t i = base + j;
+            const cx<double> *xi = x + ((int64_t)r * n + perm[i]) * nu;
+            double nv[3];
+            for (int q = 0; q < 3; ++q) {
+                S.pos[j][q] = spts[3 * i + q];
+                nv[q] = snrm[3 * i + q];
+                S.nrm[j][q] = nv[q];
+            }
+            S.w[j] = sw[i];
+            const cx<double> d = nv[0] * xi[0] + nv[1] * xi[1] + nv[2] * xi[2];
+            for (int q = 0; q < 3; ++q) {
+                if (ibc) {
+                    S.a[j][q] = xi[q];
+                    S.b[j][q] = cibc * (nv[q] * d - xi[q]);
+                } else if (region == 0) {
+                    S.a[j][q] = xi[q];
+                    S.b[j][q] = -xi[3 + q];
+                } else {
+                    S.a[j][q] = xi[q] + (nv[q] * tc) * d;
+                    S.b[j][q] = -(gamma * xi[3 + q]);
+                }
+            }
+        }
+        __syncthreads();
+        if (!active) continue;
+        for (int j = 0; j < cnt; ++j) {
+            const double *nb = S.nrm[j];
+            const cx<double> *a = S.a[j], *b = S.b[j];
+            const cx<double> na = nb[0] * a[0] + nb[1] * a[1] + nb[2] * a[2];
+            if (FAR) {
+                // e^{-ik rhat . s} w / (4 pi) times [ -ik (n (rhat . a) - (n . rhat) a - rhat (n . a)) + b ]
+                const double ph = p[0] * S.pos[j][0] + p[1] * S.pos[j][1] + p[2] * S.pos[j][2];
+                double sn, cs;
+                sincos(-k_re * ph, &sn, &cs);
+                const cx<double> e = (S.w[j] * inv4pi * exp(k_im * ph)) * mk(cs, sn);
+                const cx<double> ra = p[0] * a[0] + p[1] * a[1] + p[2] * a[2];
+                const double nr = nb[0] * p[0] + nb[1] * p[1] + nb[2] * p[2];
+                const cx<double> mik = mk(k_im, -k_re);           // -i k
+                for (int q = 0; q < 3; ++q)
+                    acc[q] += e * (mik * (nb[q] * ra - nr * a[q] - p[q] * na) + b[q]);
+            } else {
+                const double dx = S.pos[j][0] - p[0], dy = S.pos[j][1] - p[1], dz = S.pos[j][2] - p[2];
+                const double R2 = dx * dx + dy * dy + dz * dz;
+                if (R2 <= 0.0) continue;
+                const double R = sqrt(R2), iR = 1.0 / R;
+                double sn, cs;
+                sincos(k_re * R, &sn, &cs);
+                const cx<double> g = (S.w[j] * inv4pi * iR * exp(-k_im * R)) * mk(cs, sn);
+                const cx<double> f = (iR * iR) * (mk(-k_im * R - 1.0, k_re * R) * g);
+                const double dv[3] = {dx, dy, dz};
+                const cx<double> Ga = dx * a[0] + dy * a[1] + dz * a[2];
+                const double nG = nb[0] * dx + nb[1] * dy + nb[2] * dz;
+                for (int q = 0; q < 3; ++q) acc[q] += f * (nb[q] * Ga - nG * a[q] - dv[q] * na) + g * b[q];
+            }
+        }
+    }
+    if (!active) return;
+    const double sg = FAR ? -1.0 : (region == 0 ? -1.0 : 1.0);
+    for (int q = 0; q < 3; ++q) out[((int64_t)r * nt + t) * 3 + q] = sg * acc[q];
+}
+
 // ---- Krylov kernels (vectors of length len per rhs, stride len) ----
 // Vectors are cx<T> (T = double for FP64 solves, float for the inner solves of
 // the mixed mode); inner products, the Hessenberg matrix and the rotations are
@@ -1381,6 +1486,38 @@ int bem_problem_create_ibc(fmb_plan_t p0, fmb_plan_t p0_32, const double *Z, voi
         for (hipEvent_t *e : {&h->ev_fork, &h->ev_join, &h->ev_in, &h->ev_out})
             FMB_CHECK_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
         *out = guard.release();
+    });
+}
+
+int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt, int32_t region,
+              int32_t far, void *E, void *stream) {
+    return guarded([&] {
+        FMB_REQUIRE(pb && x && points && E, "bad arguments");
+        FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
+        FMB_REQUIRE(nt >= 1, "no target points");
+        FMB_REQUIRE(region == 0 || (region == 1 && !pb->ibc), "region must be 0 (host) or 1 (interior, dielectric)");
+        FMB_REQUIRE(!far || region == 0, "the far field is of the host region");
+        hipStream_t s = (hipStream_t)stream;
+        for (int64_t i = 0; i < 3 * nt; ++i) FMB_REQUIRE(std::isfinite(points[i]), "non-finite target point");
+        if (far)
+            for (int64_t i = 0; i < nt; ++i) {
+                const double r2 = points[3 * i] * points[3 * i] + points[3 * i + 1] * points[3 * i + 1] +
+                                  points[3 * i + 2] * points[3 * i + 2];
+                FMB_REQUIRE(std::fabs(r2 - 1.0) <= 1e-9, "far-field directions must be unit vectors");
+            }
+        const Plan &A = pb->p0->p;
+        const Plan &K = region == 1 ? pb->p1->p : A;
+        DevBuf dt;
+        dt.alloc((size_t)nt * 3 * sizeof(double));
+        FMB_CHECK_HIP(hipMemcpyAsync(dt.p, points, (size_t)nt * 3 * sizeof(double), hipMemcpyHostToDevice, s));
+        const cx<double> tc = cdiv(mk(1.0, 0.0) - pb->eps, pb->eps);
+        const dim3 grid((unsigned)((nt + FE_TILE - 1) / FE_TILE), (unsigned)nrhs);
+        auto kern = far ? k_field<true> : k_field<false>;
+        kern<<<grid, FE_TILE, 0, s>>>(dt.as<double>(), nt, A.spts.as<double>(), A.snrm.as<double>(), A.sw.as<double>(),
+                                      A.perm.as<int32_t>(), (const cx<double> *)x, pb->n, pb->nu, region,
+                                      pb->ibc ? 1 : 0, K.k_re, K.k_im, tc, pb->gamma, pb->cibc, (cx<double> *)E);
+        FMB_LAUNCH_CHECK();
+        FMB_CHECK_HIP(hipStreamSynchronize(s));
     });
 }
 
