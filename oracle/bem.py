@@ -219,3 +219,126 @@ class IbcProblem:
             return np.einsum("nij,...nj->...ni", Minv, v)
 
         return apply
+
+
+def subset_nodes(nodes, mask):
+    """The nodes of one scatterer (mask over all nodes) as a node set of its own:
+    points, normals, weights, triangles renumbered in order of first appearance."""
+    idx = np.nonzero(mask)[0]
+    tri = nodes["point_tri"][idx]
+    uniq, inv = np.unique(tri, return_inverse=True)
+    return {"points": nodes["points"][idx], "normals": nodes["normals"][idx], "weights": nodes["weights"][idx],
+            "point_tri": inv.astype(np.int32), "tri_vertices": nodes["tri_vertices"][uniq]}
+
+
+class MultiBemProblem:
+    """J scatterers in vacuum (Sec. 2.1, Fig. 1): node alpha belongs to scatterer
+    region[alpha] = j with permittivity eps[j] and permeability mu[j].  The host
+    rows use all nodes, the interior rows of scatterer j only its own nodes:
+
+        (A x)_alpha[0:3] = 1/2 Phi_alpha + Op_{k0}(Phi, -Psi)_alpha                       (all nodes)
+        (A x)_alpha[3:6] = 1/2 T_j Phi_alpha - Op_{kj}(T_j Phi, -gamma_j Psi)|_{j}(alpha)  (scatterer j)
+
+    with k_j = k0 sqrt(eps_j mu_j), T_j = I + (1 - eps_j)/eps_j n n, gamma_j = mu_j.
+    J = 1 is BemProblem.  The preconditioner keeps each node's 6x6 self block."""
+
+    def __init__(self, nodes, region, k0, eps, mu=None, mode="linear"):
+        self.nodes = nodes
+        self.region = np.asarray(region)
+        self.J = int(self.region.max()) + 1
+        self.k0 = complex(k0)
+        self.eps = [complex(e) for e in eps]
+        self.mu = [complex(m) for m in (mu if mu is not None else [1.0] * self.J)]
+        self.k = [wavenumber(k0, e, m) for e, m in zip(self.eps, self.mu)]
+        self.n = nodes["points"].shape[0]
+        self.normals = nodes["normals"]
+        args = (nodes["points"], nodes["normals"], nodes["point_tri"], nodes["tri_vertices"])
+        self.corr0 = self_blocks(*args, self.k0, mode=mode)
+        self.sub = [subset_nodes(nodes, self.region == j) for j in range(self.J)]
+        self.idx = [np.nonzero(self.region == j)[0] for j in range(self.J)]
+        self.corr = [self_blocks(s["points"], s["normals"], s["point_tri"], s["tri_vertices"], kj, mode=mode)
+                     for s, kj in zip(self.sub, self.k)]
+
+    def _op(self, nodes, k, corr, a, b):
+        y = point_sum_c(nodes["points"], nodes["normals"], nodes["weights"], nodes["point_tri"], k, a, b)
+        return y + apply_corrections(nodes["normals"], nodes["point_tri"], corr, a, b)
+
+    def _T(self, j, phi, conj=False):
+        n = self.normals[self.idx[j]]
+        c = (1.0 - self.eps[j]) / self.eps[j]
+        if conj:
+            c = np.conj(c)
+        return phi + c * n * np.sum(n * phi, axis=-1, keepdims=True)
+
+    def apply(self, x):
+        x = np.asarray(x, dtype=np.complex128)
+        phi, psi = x[:, 0:3], x[:, 3:6]
+        r = np.zeros_like(x)
+        r[:, 0:3] = 0.5 * phi + self._op(self.nodes, self.k0, self.corr0, phi, -psi)
+        for j in range(self.J):
+            i = self.idx[j]
+            tphi = self._T(j, phi[i])
+            r[i, 3:6] = 0.5 * tphi - self._op(self.sub[j], self.k[j], self.corr[j], tphi, -self.mu[j] * psi[i])
+        return r
+
+    def apply_adjoint(self, v):
+        """Each scatterer's interior rows transpose as in BemProblem.apply_adjoint."""
+        v = np.asarray(v, dtype=np.complex128)
+        nd = self.nodes
+        a0, b0 = point_sum_adjoint(nd["points"], nd["normals"], nd["weights"], nd["point_tri"], self.k0, v[:, 0:3])
+        ca, cb = apply_corrections_adjoint(nd["normals"], nd["point_tri"], self.corr0, v[:, 0:3])
+        r = np.zeros_like(v)
+        r[:, 0:3] = 0.5 * v[:, 0:3] + a0 + ca
+        r[:, 3:6] = -(b0 + cb)
+        for j in range(self.J):
+            i = self.idx[j]
+            s = self.sub[j]
+            a1, b1 = point_sum_adjoint(s["points"], s["normals"], s["weights"], s["point_tri"], self.k[j], v[i, 3:6])
+            c1, d1 = apply_corrections_adjoint(s["normals"], s["point_tri"], self.corr[j], v[i, 3:6])
+            r[i, 0:3] += self._T(j, 0.5 * v[i, 3:6] - a1 - c1, conj=True)
+            r[i, 3:6] += np.conj(self.mu[j]) * (b1 + d1)
+        return r
+
+    def rhs_planewave(self, d, p):
+        s = self.nodes["points"]
+        e = np.exp(1j * self.k0 * (s @ np.asarray(d, dtype=np.float64)))
+        out = np.zeros((self.n, 6), dtype=np.complex128)
+        out[:, 0:3] = e[:, None] * np.asarray(p)[None, :]
+        return out
+
+    def precond_blocks(self):
+        I3 = np.eye(3)
+        M = np.zeros((self.n, 6, 6), dtype=np.complex128)
+
+        def diag(blocks, nodes, n_nodes):
+            nd_, dV, dG = blocks
+            own = nd_[nodes["point_tri"]] == np.arange(n_nodes)[:, None]
+            jj = np.argmax(own, axis=1)
+            return dV[np.arange(n_nodes), jj], dG[np.arange(n_nodes), jj]
+
+        def Kmat(n, V):
+            nV = np.sum(n * V, axis=1)
+            return n[:, :, None] * V[:, None, :] - nV[:, None, None] * I3[None] - V[:, :, None] * n[:, None, :]
+
+        V0, G0 = diag(self.corr0, self.nodes, self.n)
+        n = self.normals
+        M[:, 0:3, 0:3] = 0.5 * I3[None] + Kmat(n, V0)
+        M[:, 0:3, 3:6] = -G0[:, None, None] * I3[None]
+        for j in range(self.J):
+            i = self.idx[j]
+            nj = n[i]
+            V1, G1 = diag(self.corr[j], self.sub[j], len(i))
+            T = I3[None] + ((1.0 - self.eps[j]) / self.eps[j]) * nj[:, :, None] * nj[:, None, :]
+            M[i, 3:6, 0:3] = 0.5 * T - Kmat(nj, V1) @ T
+            M[i, 3:6, 3:6] = self.mu[j] * G1[:, None, None] * I3[None]
+        return M
+
+    def block_preconditioner(self, adjoint=False):
+        Minv = np.linalg.inv(self.precond_blocks())
+        if adjoint:
+            Minv = np.conj(np.transpose(Minv, (0, 2, 1)))
+
+        def apply(v):
+            return np.einsum("nij,...nj->...ni", Minv, v)
+
+        return apply

@@ -13,6 +13,7 @@ from .meshes import (  # noqa: F401
     torus,
     split_ring,
     nystrom3,
+    union,
 )
 from .draws import (  # noqa: F401
     seed_for,

@@ -270,3 +270,16 @@ def nystrom3(mesh: Mesh):
         "point_tri": point_tri,
         "tri_vertices": tv,
     }
+
+
+def union(meshes, offsets):
+    """Several closed meshes as one triangle set, mesh i translated by offsets[i].
+    Returns (mesh, tri_region) with tri_region[t] = index of the mesh holding triangle t."""
+    verts, tris, reg = [], [], []
+    base = 0
+    for i, (m, off) in enumerate(zip(meshes, offsets)):
+        verts.append(m.vertices + np.asarray(off, dtype=np.float64)[None, :])
+        tris.append(m.triangles + base)
+        reg.append(np.full(len(m.triangles), i, dtype=np.int32))
+        base += len(m.vertices)
+    return Mesh(np.concatenate(verts), np.concatenate(tris).astype(np.int32)), np.concatenate(reg)
