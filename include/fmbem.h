@@ -224,6 +224,24 @@ int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_
                        const double *eps, const double *mu, void *stream, fmb_problem_t *out);
 
 /*
+ * bem_problem_create_multi: J scatterers in vacuum (Sec. 2.1, Fig. 1).  Node
+ * alpha belongs to scatterer region[alpha] (host i32[n], values 0..J-1), with
+ * permittivity eps[j] and permeability mu[j] (host c128[J] each).  The host
+ * rows use p0, a plan at k0 over all n nodes; the interior rows of scatterer j
+ * use pj[j], a plan at k_j = k0 sqrt(eps_j mu_j) over that scatterer's nodes
+ * in their global order (the nodes with region j, ascending):
+ *   rows 0..2: 1/2 Phi + Op_{k0}(Phi, -Psi)                          (all nodes)
+ *   rows 3..5: 1/2 T_j Phi - Op_{kj}(T_j Phi, -gamma_j Psi)          (scatterer j's plan)
+ * p0_32 and pj_32 (J FP32 plans) are optional, together.  J <= 8.  J = 1 with
+ * region all 0 is bem_problem_create.  All other entry points accept the
+ * problem (the interior field of bem_field needs J = 1); the products of the
+ * scatterers' plans run one after the other beside the host product.
+ */
+int bem_problem_create_multi(fmb_plan_t p0, const fmb_plan_t *pj, int32_t J, const int32_t *region,
+                             const double *eps, const double *mu, fmb_plan_t p0_32, const fmb_plan_t *pj_32,
+                             void *stream, fmb_problem_t *out);
+
+/*
  * bem_problem_create_ibc: the impedance-boundary-condition system of eq. 2.25
  * for a good conductor: with n x E = Z n x (n x H) (eq. 2.24) the unknowns
  * are Phi = E_0 alone (three per node), and

@@ -121,7 +121,8 @@ def impedance_fields(points, k: float, a: float, Z: complex, nmax=None):
 
 def fields(points, k: float, a: float, eps: complex, region="outside", nmax=None, coeffs=None):
     """(E, curl E) at points for E_inc = x^ exp(i k z).  region 'outside'
-    gives the total host field E_inc + E_sca, 'inside' the interior field.
+    gives the total host field E_inc + E_sca, 'scattered' E_sca alone, 'inside'
+    the interior field.
     coeffs = (n, a_n, b_n) replaces the dielectric scattering coefficients."""
     p = np.asarray(points, dtype=np.float64)
     r = np.linalg.norm(p, axis=1)
@@ -134,7 +135,11 @@ def fields(points, k: float, a: float, eps: complex, region="outside", nmax=None
         m = np.sqrt(complex(eps))
         n, an, bn, cn, dn = coefficients(k * a, m, nmax)
     En = (1j ** n) * (2 * n + 1) / (n * (n + 1))
-    if region == "outside":
+    if region == "scattered":
+        Mo3, Me3, No3, Ne3 = _vsh(n, k, r, theta, phi, 3)
+        E = np.einsum("n,npd->pd", En * 1j * an, Ne3) - np.einsum("n,npd->pd", En * bn, Mo3)
+        C = k * (np.einsum("n,npd->pd", En * 1j * an, Me3) - np.einsum("n,npd->pd", En * bn, No3))
+    elif region == "outside":
         Mo1, Me1, No1, Ne1 = _vsh(n, k, r, theta, phi, 1)
         Mo3, Me3, No3, Ne3 = _vsh(n, k, r, theta, phi, 3)
         E = np.einsum("n,npd->pd", En, Mo1 - 1j * Ne1) + np.einsum("n,npd->pd", En * 1j * an, Ne3) \

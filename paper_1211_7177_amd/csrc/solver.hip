@@ -46,6 +46,15 @@ struct fmb_problem_s {
     bool ibc = false;
     int nu = 6;                // unknowns per node: 6 (Phi, Psi) or 3 (Phi, ibc)
     fmb::cx<double> cibc;
+    // several scatterers: plan pj[j] (and pj32[j]) holds scatterer j's nodes at
+    // k_j; reg/loc map every node to its scatterer and its position there; the
+    // interior staging block of scatterer j starts at element off[j] (per-rhs
+    // stride nj[j] * 3).  One scatterer: J = 1, pj[0] = p1, no maps.
+    int J = 1;
+    fmb_plan_t pj[8] = {}, pj32[8] = {};
+    fmb::DevBuf reg, loc;
+    int64_t off[8] = {}, nj[8] = {};
+    fmb::cx<double> tcj[8] = {}, gamj[8] = {};
     fmb::DevBuf minv;          // c128[n][6][6] (c128[n][3][3] for ibc)
     fmb::DevBuf minv32;        // c64[n][6][6], FP32 copy for the inner solves (FP32 plans only)
     fmb::DevBuf upts;          // f64[n][3] user order
@@ -100,14 +109,52 @@ __device__ inline cx<T> narrow(cx<double> z) { return mk((T)z.re, (T)z.im); }
 template <typename T>
 __device__ inline cx<double> widen(cx<T> z) { return mk((double)z.re, (double)z.im); }
 
+// Several scatterers: node alpha belongs to scatterer reg[alpha] = j, whose plan
+// holds it at position loc[alpha]; the host plan holds every node.  Scatterer
+// j's interior densities occupy the block [nrhs][n_j][3] starting at element
+// off[j] of the interior staging arrays (the blocks of all scatterers fill
+// n * 3 * nrhs_max elements, as the one scatterer does).  reg = loc = nullptr
+// is the one-scatterer case.
+constexpr int MAXJ = 8;
+struct Regions {
+    const int32_t *reg;
+    const int32_t *loc;
+    int64_t off[MAXJ];
+    int64_t nj[MAXJ];
+    cx<double> tc[MAXJ], gamma[MAXJ];
+};
+
+// element index of (rhs, node) in the interior staging arrays; j receives the scatterer
+__device__ inline int64_t interior_at(const Regions &R, int64_t i, int64_t n, int &j) {
+    const int64_t node = i % n, r = i / n;
+    j = R.reg ? R.reg[node] : 0;
+    const int64_t l = R.loc ? R.loc[node] : node;
+    return R.off[j] + (r * R.nj[j] + l) * 3;
+}
+
+Regions regions_of(const fmb_problem_s &pb) {
+    Regions R{};
+    R.reg = pb.J > 1 ? pb.reg.as<int32_t>() : nullptr;
+    R.loc = pb.J > 1 ? pb.loc.as<int32_t>() : nullptr;
+    for (int j = 0; j < pb.J; ++j) {
+        R.off[j] = pb.off[j];
+        R.nj[j] = pb.nj[j];
+        R.tc[j] = pb.tcj[j];
+        R.gamma[j] = pb.gamj[j];
+    }
+    return R;
+}
+
 template <typename T>
 __global__ void k_bem_split(const cx<T> *__restrict__ x, const double *__restrict__ nrm, int64_t n, int nrhs,
-                            cx<double> tcd, cx<double> gammad, cx<T> *__restrict__ a0, cx<T> *__restrict__ b0,
+                            const Regions R, cx<T> *__restrict__ a0, cx<T> *__restrict__ b0,
                             cx<T> *__restrict__ a1, cx<T> *__restrict__ b1) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n * nrhs) return;
     const int64_t node = i % n;
-    const cx<T> tc = narrow<T>(tcd), gamma = narrow<T>(gammad);
+    int j;
+    const int64_t ii = interior_at(R, i, n, j);
+    const cx<T> tc = narrow<T>(R.tc[j]), gamma = narrow<T>(R.gamma[j]);
     const T nv[3] = {(T)nrm[3 * node], (T)nrm[3 * node + 1], (T)nrm[3 * node + 2]};
     const cx<T> *xi = x + i * 6;
     cx<T> phi[3] = {xi[0], xi[1], xi[2]}, psi[3] = {xi[3], xi[4], xi[5]};
@@ -115,26 +162,28 @@ __global__ void k_bem_split(const cx<T> *__restrict__ x, const double *__restric
     for (int c = 0; c < 3; ++c) {
         a0[i * 3 + c] = phi[c];
         b0[i * 3 + c] = -psi[c];
-        a1[i * 3 + c] = phi[c] + (nv[c] * tc) * d;
-        b1[i * 3 + c] = -(gamma * psi[c]);
+        a1[ii + c] = phi[c] + (nv[c] * tc) * d;
+        b1[ii + c] = -(gamma * psi[c]);
     }
 }
 
 template <typename T>
 __global__ void k_bem_combine(const cx<T> *__restrict__ x, const double *__restrict__ nrm, int64_t n, int nrhs,
-                              cx<double> tcd, const cx<T> *__restrict__ y0, const cx<T> *__restrict__ y1,
+                              const Regions R, const cx<T> *__restrict__ y0, const cx<T> *__restrict__ y1,
                               cx<T> *__restrict__ r) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n * nrhs) return;
     const int64_t node = i % n;
-    const cx<T> tc = narrow<T>(tcd);
+    int j;
+    const int64_t ii = interior_at(R, i, n, j);
+    const cx<T> tc = narrow<T>(R.tc[j]);
     const T nv[3] = {(T)nrm[3 * node], (T)nrm[3 * node + 1], (T)nrm[3 * node + 2]};
     const cx<T> *xi = x + i * 6;
     cx<T> d = nv[0] * xi[0] + nv[1] * xi[1] + nv[2] * xi[2];
     for (int c = 0; c < 3; ++c) {
         cx<T> tphi = xi[c] + (nv[c] * tc) * d;
         r[i * 6 + c] = T(0.5) * xi[c] + y0[i * 3 + c];
-        r[i * 6 + 3 + c] = T(0.5) * tphi - y1[i * 3 + c];
+        r[i * 6 + 3 + c] = T(0.5) * tphi - y1[ii + c];
     }
 }
 
@@ -149,10 +198,17 @@ __global__ void k_add_from32(cx<double> *__restrict__ x, const cx<float> *__rest
     if (i < m) x[i] += mk((double)d[i].re, (double)d[i].im);
 }
 
+// the interior plans' self-triangle blocks, per scatterer
+struct RegionCorr {
+    const cx<double> *cv[MAXJ];
+    const cx<double> *cg[MAXJ];
+    const int32_t *tri_nodes[MAXJ];
+    const int32_t *point_tri[MAXJ];
+};
+
 __global__ void k_precond_build(const double *__restrict__ nrm, const int32_t *__restrict__ point_tri,
                                 const int32_t *__restrict__ tri_nodes, int m, const cx<double> *__restrict__ cv0,
-                                const cx<double> *__restrict__ cg0, const cx<double> *__restrict__ cv1,
-                                const cx<double> *__restrict__ cg1, int64_t n, cx<double> tc, cx<double> gamma,
+                                const cx<double> *__restrict__ cg0, const RegionCorr C, const Regions R, int64_t n,
                                 cx<double> *__restrict__ minv, int32_t *__restrict__ bad) {
     int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (a >= n) return;
@@ -160,13 +216,21 @@ __global__ void k_precond_build(const double *__restrict__ nrm, const int32_t *_
     int js = 0;
     for (int j = 0; j < m; ++j)
         if (tri_nodes[(int64_t)t * m + j] == (int32_t)a) js = j;
+    // the node in its scatterer's plan
+    const int rj = R.reg ? R.reg[a] : 0;
+    const int64_t l = R.loc ? R.loc[a] : a;
+    const int32_t tl = C.point_tri[rj][l];
+    int jl = 0;
+    for (int j = 0; j < m; ++j)
+        if (C.tri_nodes[rj][(int64_t)tl * m + j] == (int32_t)l) jl = j;
+    const cx<double> tc = R.tc[rj], gamma = R.gamma[rj];
     const double nv[3] = {nrm[3 * a], nrm[3 * a + 1], nrm[3 * a + 2]};
     cx<double> V0[3], V1[3];
     for (int i = 0; i < 3; ++i) {
         V0[i] = cv0[(a * m + js) * 3 + i];
-        V1[i] = cv1[(a * m + js) * 3 + i];
+        V1[i] = C.cv[rj][(l * m + jl) * 3 + i];
     }
-    const cx<double> G0 = cg0[a * m + js], G1 = cg1[a * m + js];
+    const cx<double> G0 = cg0[a * m + js], G1 = C.cg[rj][l * m + jl];
     cx<double> A[6][12];
     for (int i = 0; i < 6; ++i)
         for (int j = 0; j < 12; ++j) A[i][j] = mk(0.0, 0.0);
@@ -243,9 +307,9 @@ __global__ void k_precond_apply(const cx<T> *__restrict__ minv, const cx<T> *__r
 // split of z into the densities of the two plans (as k_bem_split)
 template <typename T>
 __global__ void k_precond_split(const cx<T> *__restrict__ minv, const cx<T> *__restrict__ v, cx<T> *__restrict__ z,
-                                const double *__restrict__ nrm, int64_t n, int nrhs, cx<double> tcd,
-                                cx<double> gammad, cx<T> *__restrict__ a0, cx<T> *__restrict__ b0,
-                                cx<T> *__restrict__ a1, cx<T> *__restrict__ b1) {
+                                const double *__restrict__ nrm, int64_t n, int nrhs, const Regions R,
+                                cx<T> *__restrict__ a0, cx<T> *__restrict__ b0, cx<T> *__restrict__ a1,
+                                cx<T> *__restrict__ b1) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n * nrhs) return;
     const int64_t node = i % n;
@@ -259,14 +323,16 @@ __global__ void k_precond_split(const cx<T> *__restrict__ minv, const cx<T> *__r
         x[r] = s;
         z[i * 6 + r] = s;
     }
-    const cx<T> tc = narrow<T>(tcd), gamma = narrow<T>(gammad);
+    int j;
+    const int64_t ii = interior_at(R, i, n, j);
+    const cx<T> tc = narrow<T>(R.tc[j]), gamma = narrow<T>(R.gamma[j]);
     const T nv[3] = {(T)nrm[3 * node], (T)nrm[3 * node + 1], (T)nrm[3 * node + 2]};
     const cx<T> d = nv[0] * x[0] + nv[1] * x[1] + nv[2] * x[2];
     for (int c = 0; c < 3; ++c) {
         a0[i * 3 + c] = x[c];
         b0[i * 3 + c] = -x[3 + c];
-        a1[i * 3 + c] = x[c] + (nv[c] * tc) * d;
-        b1[i * 3 + c] = -(gamma * x[3 + c]);
+        a1[ii + c] = x[c] + (nv[c] * tc) * d;
+        b1[ii + c] = -(gamma * x[3 + c]);
     }
 }
 
@@ -277,24 +343,28 @@ __global__ void k_precond_split(const cx<T> *__restrict__ minv, const cx<T> *__r
 //   (A^H v)[0:3] = 1/2 v0 + a0 + 1/2 T^H v1 - T^H a1,
 //   (A^H v)[3:6] = -b0 + conj(gamma) b1,          T^H u = u + conj(tc) n (n . u).
 template <typename T>
-__global__ void k_adj_split(const cx<T> *__restrict__ x, int64_t n, int nrhs, cx<T> *__restrict__ y0,
-                            cx<T> *__restrict__ y1) {
+__global__ void k_adj_split(const cx<T> *__restrict__ x, int64_t n, int nrhs, const Regions R,
+                            cx<T> *__restrict__ y0, cx<T> *__restrict__ y1) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n * nrhs) return;
+    int j;
+    const int64_t ii = interior_at(R, i, n, j);
     for (int c = 0; c < 3; ++c) {
         y0[i * 3 + c] = x[i * 6 + c];
-        y1[i * 3 + c] = x[i * 6 + 3 + c];
+        y1[ii + c] = x[i * 6 + 3 + c];
     }
 }
 
 // z = M^{-H} v per node (conjugate transpose of the 6x6 block inverse), split as k_adj_split
 template <typename T>
 __global__ void k_adj_precond_split(const cx<T> *__restrict__ minv, const cx<T> *__restrict__ v,
-                                    cx<T> *__restrict__ z, int64_t n, int nrhs, cx<T> *__restrict__ y0,
-                                    cx<T> *__restrict__ y1) {
+                                    cx<T> *__restrict__ z, int64_t n, int nrhs, const Regions R,
+                                    cx<T> *__restrict__ y0, cx<T> *__restrict__ y1) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n * nrhs) return;
     const int64_t node = i % n;
+    int j;
+    const int64_t ii = interior_at(R, i, n, j);
     const cx<T> *M = minv + node * 36;
     const cx<T> *vi = v + i * 6;
     cx<T> in[6];
@@ -304,27 +374,28 @@ __global__ void k_adj_precond_split(const cx<T> *__restrict__ minv, const cx<T> 
         for (int q = 0; q < 6; ++q) acc += conj(M[q * 6 + r]) * in[q];
         z[i * 6 + r] = acc;
         if (r < 3) y0[i * 3 + r] = acc;
-        else y1[i * 3 + r - 3] = acc;
+        else y1[ii + r - 3] = acc;
     }
 }
 
 template <typename T>
 __global__ void k_adj_combine(const cx<T> *__restrict__ x, const double *__restrict__ nrm, int64_t n, int nrhs,
-                              cx<double> tcd, cx<double> gammad, const cx<T> *__restrict__ a0,
-                              const cx<T> *__restrict__ b0, const cx<T> *__restrict__ a1,
-                              const cx<T> *__restrict__ b1, cx<T> *__restrict__ r) {
+                              const Regions R, const cx<T> *__restrict__ a0, const cx<T> *__restrict__ b0,
+                              const cx<T> *__restrict__ a1, const cx<T> *__restrict__ b1, cx<T> *__restrict__ r) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n * nrhs) return;
     const int64_t node = i % n;
-    const cx<T> tch = narrow<T>(conj(tcd)), gc = narrow<T>(conj(gammad));
+    int j;
+    const int64_t ii = interior_at(R, i, n, j);
+    const cx<T> tch = narrow<T>(conj(R.tc[j])), gc = narrow<T>(conj(R.gamma[j]));
     const T nv[3] = {(T)nrm[3 * node], (T)nrm[3 * node + 1], (T)nrm[3 * node + 2]};
     const cx<T> *xi = x + i * 6;
     cx<T> u[3];                                        // 1/2 v1 - a1, then T^H of it
-    for (int c = 0; c < 3; ++c) u[c] = T(0.5) * xi[3 + c] - a1[i * 3 + c];
+    for (int c = 0; c < 3; ++c) u[c] = T(0.5) * xi[3 + c] - a1[ii + c];
     const cx<T> d = nv[0] * u[0] + nv[1] * u[1] + nv[2] * u[2];
     for (int c = 0; c < 3; ++c) {
         r[i * 6 + c] = T(0.5) * xi[c] + a0[i * 3 + c] + u[c] + (nv[c] * tch) * d;
-        r[i * 6 + 3 + c] = gc * b1[i * 3 + c] - b0[i * 3 + c];
+        r[i * 6 + 3 + c] = gc * b1[ii + c] - b0[i * 3 + c];
     }
 }
 
@@ -989,6 +1060,40 @@ static void adjoint_pair(fmb_problem_s &pb, Plan &P0, Plan &P1, const void *y0, 
     FMB_CHECK_HIP(hipStreamWaitEvent(s, pb.ev_join, 0));
 }
 
+// The products of a several-scatterer application: the host plan on s, the
+// scatterers' plans one after the other on the problem's second stream (all on
+// s when the problem runs serially).  Forward: (in0, in0b) -> out0 with the host
+// plan and (in1, in1b) -> out1 blockwise; adjoint: in0 -> (out0a, out0b) and
+// in1 -> (out1a, out1b).  Block j of the interior arrays starts at off[j].
+template <typename T>
+static void multi_products(fmb_problem_s &pb, bool adj, const cx<T> *u0, cx<T> *v0, cx<T> *w0, const cx<T> *u1,
+                           cx<T> *v1, cx<T> *w1, int nrhs, hipStream_t s) {
+    const bool f32 = sizeof(T) == sizeof(float);
+    Plan &P0 = f32 ? pb.p032->p : pb.p0->p;
+    hipStream_t s2 = pb.serial ? s : pb.s2;
+    if (adj) {
+        adjoint_prepare(P0);
+        for (int j = 0; j < pb.J; ++j) adjoint_prepare(f32 ? pb.pj32[j]->p : pb.pj[j]->p);
+    }
+    if (!pb.serial) {
+        FMB_CHECK_HIP(hipEventRecord(pb.ev_fork, s));
+        FMB_CHECK_HIP(hipStreamWaitEvent(s2, pb.ev_fork, 0));
+    }
+    // forward: (u, v) -> w;  adjoint: u -> (v, w)
+    if (adj) run_matvec_adjoint(P0, u0, v0, w0, nrhs, s);
+    else run_matvec(P0, u0, v0, w0, nrhs, s);
+    for (int j = 0; j < pb.J; ++j) {
+        Plan &Pj = f32 ? pb.pj32[j]->p : pb.pj[j]->p;
+        const int64_t o = pb.off[j];
+        if (adj) run_matvec_adjoint(Pj, u1 + o, v1 + o, w1 + o, nrhs, s2);
+        else run_matvec(Pj, u1 + o, v1 + o, w1 + o, nrhs, s2);
+    }
+    if (!pb.serial) {
+        FMB_CHECK_HIP(hipEventRecord(pb.ev_join, s2));
+        FMB_CHECK_HIP(hipStreamWaitEvent(s, pb.ev_join, 0));
+    }
+}
+
 // The impedance-boundary-condition system: A x (or A^H x in adjoint mode)
 // with the k0 plan alone; with pre = v, x is first set to M^{-1} v (M^{-H} v).
 template <typename T>
@@ -1029,7 +1134,7 @@ static void bem_apply_adjoint_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int
         return;
     }
     const int64_t n = pb.n;
-    const cx<double> tc = cdiv(mk(1.0, 0.0) - pb.eps, pb.eps);
+    const Regions R = regions_of(pb);
     const double *nrm = pb.p0->p.unrm.as<double>();
     const bool f32 = sizeof(T) == sizeof(float);
     cx<T> *a0 = (f32 ? pb.a0s : pb.a0).template as<cx<T>>(), *b0 = (f32 ? pb.b0s : pb.b0).template as<cx<T>>(),
@@ -1037,14 +1142,18 @@ static void bem_apply_adjoint_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int
           *y0 = (f32 ? pb.y0s : pb.y0).template as<cx<T>>(), *y1 = (f32 ? pb.y1s : pb.y1).template as<cx<T>>();
     if (pre) {
         k_adj_precond_split<T><<<gridn(n * nrhs), TPB, 0, s>>>((f32 ? pb.minv32 : pb.minv).template as<cx<T>>(),
-                                                                pre, const_cast<cx<T> *>(x), n, nrhs, y0, y1);
+                                                                pre, const_cast<cx<T> *>(x), n, nrhs, R, y0, y1);
     } else {
-        k_adj_split<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, n, nrhs, y0, y1);
+        k_adj_split<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, n, nrhs, R, y0, y1);
     }
     FMB_LAUNCH_CHECK();
-    Plan &P0 = f32 ? pb.p032->p : pb.p0->p, &P1 = f32 ? pb.p132->p : pb.p1->p;
-    adjoint_pair(pb, P0, P1, y0, a0, b0, y1, a1, b1, nrhs, s);
-    k_adj_combine<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, tc, pb.gamma, a0, b0, a1, b1, r);
+    if (pb.J == 1) {
+        Plan &P0 = f32 ? pb.p032->p : pb.p0->p, &P1 = f32 ? pb.p132->p : pb.p1->p;
+        adjoint_pair(pb, P0, P1, y0, a0, b0, y1, a1, b1, nrhs, s);
+    } else {
+        multi_products<T>(pb, true, y0, a0, b0, y1, a1, b1, nrhs, s);
+    }
+    k_adj_combine<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, R, a0, b0, a1, b1, r);
     FMB_LAUNCH_CHECK();
 }
 
@@ -1063,24 +1172,26 @@ static void bem_apply_t(fmb_problem_s &pb, const cx<T> *x, cx<T> *r, int nrhs, h
         return;
     }
     const int64_t n = pb.n;
-    const cx<double> tc = cdiv(mk(1.0, 0.0) - pb.eps, pb.eps);
+    const Regions R = regions_of(pb);
     const double *nrm = pb.p0->p.unrm.as<double>();
     const bool f32 = sizeof(T) == sizeof(float);
     cx<T> *a0 = (f32 ? pb.a0s : pb.a0).template as<cx<T>>(), *b0 = (f32 ? pb.b0s : pb.b0).template as<cx<T>>(),
           *a1 = (f32 ? pb.a1s : pb.a1).template as<cx<T>>(), *b1 = (f32 ? pb.b1s : pb.b1).template as<cx<T>>(),
           *y0 = (f32 ? pb.y0s : pb.y0).template as<cx<T>>(), *y1 = (f32 ? pb.y1s : pb.y1).template as<cx<T>>();
     if (pre) {
-        const bool f32m = sizeof(T) == sizeof(float);
-        k_precond_split<T><<<gridn(n * nrhs), TPB, 0, s>>>((f32m ? pb.minv32 : pb.minv).template as<cx<T>>(), pre,
-                                                            const_cast<cx<T> *>(x), nrm, n, nrhs, tc, pb.gamma, a0,
-                                                            b0, a1, b1);
+        k_precond_split<T><<<gridn(n * nrhs), TPB, 0, s>>>((f32 ? pb.minv32 : pb.minv).template as<cx<T>>(), pre,
+                                                            const_cast<cx<T> *>(x), nrm, n, nrhs, R, a0, b0, a1, b1);
     } else {
-        k_bem_split<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, tc, pb.gamma, a0, b0, a1, b1);
+        k_bem_split<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, R, a0, b0, a1, b1);
     }
     FMB_LAUNCH_CHECK();
-    const Plan *P0 = f32 ? &pb.p032->p : &pb.p0->p, *P1 = f32 ? &pb.p132->p : &pb.p1->p;
-    fmm_pair<T>(pb, P0, P1, a0, b0, y0, a1, b1, y1, nrhs, s);
-    k_bem_combine<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, tc, y0, y1, r);
+    if (pb.J == 1) {
+        const Plan *P0 = f32 ? &pb.p032->p : &pb.p0->p, *P1 = f32 ? &pb.p132->p : &pb.p1->p;
+        fmm_pair<T>(pb, P0, P1, a0, b0, y0, a1, b1, y1, nrhs, s);
+    } else {
+        multi_products<T>(pb, false, a0, b0, y0, a1, b1, y1, nrhs, s);
+    }
+    k_bem_combine<T><<<gridn(n * nrhs), TPB, 0, s>>>(x, nrm, n, nrhs, R, y0, y1, r);
     FMB_LAUNCH_CHECK();
 }
 
@@ -1359,6 +1470,70 @@ int fmb_gmres_opts_default(fmb_gmres_opts *o) {
     return FMB_OK;
 }
 
+namespace fmb {
+
+// Shared set-up of a dielectric problem with J scatterers: staging buffers,
+// the 6x6 preconditioner blocks and the streams.  h->p0, pj, pj32, J, reg,
+// loc, off, nj, tcj, gamj are filled in by the caller.
+static void setup_dielectric(fmb_problem_s *h, hipStream_t s) {
+    const Plan &A = h->p0->p;
+    int nr = A.nrhs_max;
+    for (int j = 0; j < h->J; ++j) {
+        nr = std::min(nr, h->pj[j]->p.nrhs_max);
+        if (h->p032) nr = std::min(nr, h->pj32[j]->p.nrhs_max);
+    }
+    if (h->p032) nr = std::min(nr, h->p032->p.nrhs_max);
+    h->nrhs_max = nr;
+    int64_t o = 0;
+    for (int j = 0; j < h->J; ++j) {
+        h->off[j] = o;
+        o += (int64_t)nr * 3 * h->nj[j];
+    }
+    const size_t m3 = (size_t)A.n * 3 * nr;
+    for (DevBuf *d : {&h->a0, &h->b0, &h->a1, &h->b1, &h->y0, &h->y1}) d->alloc(m3 * sizeof(cx<double>));
+    if (h->p032)
+        for (DevBuf *d : {&h->a0s, &h->b0s, &h->a1s, &h->b1s, &h->y0s, &h->y1s}) d->alloc(m3 * sizeof(cx<float>));
+    h->minv.alloc((size_t)A.n * 36 * sizeof(cx<double>));
+    RegionCorr C{};
+    for (int j = 0; j < h->J; ++j) {
+        const Plan &B = h->pj[j]->p;
+        C.cv[j] = B.corr_v.as<cx<double>>();
+        C.cg[j] = B.corr_g.as<cx<double>>();
+        C.tri_nodes[j] = B.tri_nodes.as<int32_t>();
+        C.point_tri[j] = B.point_tri.as<int32_t>();
+    }
+    DevBuf bad;
+    bad.alloc(sizeof(int32_t));
+    FMB_CHECK_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+    k_precond_build<<<gridn(A.n), TPB, 0, s>>>(A.unrm.as<double>(), A.point_tri.as<int32_t>(),
+                                                A.tri_nodes.as<int32_t>(), (int)A.tri_m, A.corr_v.as<cx<double>>(),
+                                                A.corr_g.as<cx<double>>(), C, regions_of(*h), A.n,
+                                                h->minv.as<cx<double>>(), bad.as<int32_t>());
+    FMB_LAUNCH_CHECK();
+    int32_t hb = 0;
+    FMB_CHECK_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    FMB_CHECK_HIP(hipStreamSynchronize(s));
+    FMB_REQUIRE(hb == 0, "a 6x6 self block of the preconditioner is singular");
+    if (h->p032) {
+        h->minv32.alloc((size_t)A.n * 36 * sizeof(cx<float>));
+        k_to32<<<gridn(A.n * 36), TPB, 0, s>>>(h->minv.as<cx<double>>(), h->minv32.as<cx<float>>(), A.n * 36);
+        FMB_LAUNCH_CHECK();
+        FMB_CHECK_HIP(hipStreamSynchronize(s));
+    }
+    FMB_CHECK_HIP(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
+    FMB_CHECK_HIP(hipStreamCreateWithFlags(&h->s1, hipStreamNonBlocking));
+    for (hipEvent_t *e : {&h->ev_fork, &h->ev_join, &h->ev_in, &h->ev_out})
+        FMB_CHECK_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+}
+
+static void check_plans(const Plan &A, const Plan &B, const char *what) {
+    FMB_REQUIRE(B.precision == A.precision, what);
+    FMB_REQUIRE(B.corr_mode != FMB_CORR_NONE && B.tri_m == A.tri_m,
+                "the BEM system needs self-triangle corrections in every plan");
+}
+
+}  // namespace fmb
+
 int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_t p1_32, const double *eps,
                        const double *mu, void *stream, fmb_problem_t *out) {
     return guarded([&] {
@@ -1369,8 +1544,8 @@ int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_
         const Plan &A = p0->p, &B = p1->p;
         FMB_REQUIRE(A.n == B.n, "plans cover different node counts");
         FMB_REQUIRE(A.precision == FMB_FP64 && B.precision == FMB_FP64, "p0 and p1 must be FP64 plans");
-        FMB_REQUIRE(A.corr_mode != FMB_CORR_NONE && B.corr_mode != FMB_CORR_NONE && A.tri_m == B.tri_m,
-                    "the BEM system needs self-triangle corrections in both plans");
+        FMB_REQUIRE(A.corr_mode != FMB_CORR_NONE, "the BEM system needs self-triangle corrections in both plans");
+        check_plans(A, B, "p0 and p1 must be FP64 plans");
         FMB_REQUIRE((p0_32 == nullptr) == (p1_32 == nullptr), "give both FP32 plans or neither");
         if (p0_32) {
             FMB_REQUIRE(p0_32->p.n == A.n && p1_32->p.n == A.n, "FP32 plans cover different node counts");
@@ -1378,7 +1553,6 @@ int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_
         }
         cx<double> e = mk(eps[0], eps[1]), u = mk(mu[0], mu[1]);
         FMB_REQUIRE(abs2(e) > 0.0, "eps must be non-zero");
-        hipStream_t s = (hipStream_t)stream;
         auto *h = new fmb_problem_s;
         std::unique_ptr<fmb_problem_s> guard(h);
         h->p0 = p0;
@@ -1391,38 +1565,73 @@ int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_
         h->gamma = u;
         h->k0_re = A.k_re;
         h->k0_im = A.k_im;
-        int nr = std::min(A.nrhs_max, B.nrhs_max);
-        if (p0_32) nr = std::min(nr, std::min(p0_32->p.nrhs_max, p1_32->p.nrhs_max));
-        h->nrhs_max = nr;
-        const size_t m3 = (size_t)A.n * 3 * nr;
-        for (DevBuf *d : {&h->a0, &h->b0, &h->a1, &h->b1, &h->y0, &h->y1}) d->alloc(m3 * sizeof(cx<double>));
-        if (p0_32)
-            for (DevBuf *d : {&h->a0s, &h->b0s, &h->a1s, &h->b1s, &h->y0s, &h->y1s}) d->alloc(m3 * sizeof(cx<float>));
-        h->minv.alloc((size_t)A.n * 36 * sizeof(cx<double>));
-        DevBuf bad;
-        bad.alloc(sizeof(int32_t));
-        FMB_CHECK_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
-        const cx<double> tc = cdiv(mk(1.0, 0.0) - e, e);
-        k_precond_build<<<gridn(A.n), TPB, 0, s>>>(A.unrm.as<double>(), A.point_tri.as<int32_t>(),
-                                                    A.tri_nodes.as<int32_t>(), (int)A.tri_m, A.corr_v.as<cx<double>>(),
-                                                    A.corr_g.as<cx<double>>(), B.corr_v.as<cx<double>>(),
-                                                    B.corr_g.as<cx<double>>(), A.n, tc, u, h->minv.as<cx<double>>(),
-                                                    bad.as<int32_t>());
-        FMB_LAUNCH_CHECK();
-        int32_t hb = 0;
-        FMB_CHECK_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        FMB_CHECK_HIP(hipStreamSynchronize(s));
-        FMB_REQUIRE(hb == 0, "a 6x6 self block of the preconditioner is singular");
-        if (p0_32) {
-            h->minv32.alloc((size_t)A.n * 36 * sizeof(cx<float>));
-            k_to32<<<gridn(A.n * 36), TPB, 0, s>>>(h->minv.as<cx<double>>(), h->minv32.as<cx<float>>(), A.n * 36);
-            FMB_LAUNCH_CHECK();
-            FMB_CHECK_HIP(hipStreamSynchronize(s));
+        h->J = 1;
+        h->pj[0] = p1;
+        h->pj32[0] = p1_32;
+        h->nj[0] = A.n;
+        h->tcj[0] = cdiv(mk(1.0, 0.0) - e, e);
+        h->gamj[0] = u;
+        setup_dielectric(h, (hipStream_t)stream);
+        *out = guard.release();
+    });
+}
+
+int bem_problem_create_multi(fmb_plan_t p0, const fmb_plan_t *pj, int32_t J, const int32_t *region,
+                             const double *eps, const double *mu, fmb_plan_t p0_32, const fmb_plan_t *pj_32,
+                             void *stream, fmb_problem_t *out) {
+    return guarded([&] {
+        FMB_REQUIRE(out != nullptr, "out is NULL");
+        *out = nullptr;
+        FMB_REQUIRE(p0 && pj && region && eps && mu, "p0, pj, region, eps and mu are required");
+        FMB_REQUIRE(J >= 1 && J <= MAXJ, "J must be in [1, 8]");
+        const Plan &A = p0->p;
+        FMB_REQUIRE(A.precision == FMB_FP64 && A.corr_mode != FMB_CORR_NONE,
+                    "p0 must be an FP64 plan with self-triangle corrections");
+        FMB_REQUIRE((p0_32 == nullptr) == (pj_32 == nullptr), "give the FP32 host plan and FP32 scatterer plans together");
+        std::vector<int32_t> loc(A.n);
+        std::vector<int64_t> cnt(J, 0);
+        for (int64_t a = 0; a < A.n; ++a) {
+            FMB_REQUIRE(region[a] >= 0 && region[a] < J, "region out of range");
+            loc[a] = (int32_t)cnt[region[a]]++;
         }
-        FMB_CHECK_HIP(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
-        FMB_CHECK_HIP(hipStreamCreateWithFlags(&h->s1, hipStreamNonBlocking));
-        for (hipEvent_t *e : {&h->ev_fork, &h->ev_join, &h->ev_in, &h->ev_out})
-            FMB_CHECK_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+        auto *h = new fmb_problem_s;
+        std::unique_ptr<fmb_problem_s> guard(h);
+        for (int j = 0; j < J; ++j) {
+            FMB_REQUIRE(pj[j] != nullptr, "a scatterer plan is NULL");
+            FMB_REQUIRE(pj[j]->p.n == cnt[j], "scatterer plan j must hold exactly the nodes with region j");
+            check_plans(A, pj[j]->p, "scatterer plans must be FP64");
+            if (p0_32) {
+                FMB_REQUIRE(pj_32[j] && pj_32[j]->p.n == cnt[j] && pj_32[j]->p.precision == FMB_FP32,
+                            "FP32 scatterer plan j must hold the nodes with region j");
+            }
+            const cx<double> e = mk(eps[2 * j], eps[2 * j + 1]), u = mk(mu[2 * j], mu[2 * j + 1]);
+            FMB_REQUIRE(abs2(e) > 0.0, "eps must be non-zero");
+            h->pj[j] = pj[j];
+            h->pj32[j] = p0_32 ? pj_32[j] : nullptr;
+            h->nj[j] = cnt[j];
+            h->tcj[j] = cdiv(mk(1.0, 0.0) - e, e);
+            h->gamj[j] = u;
+        }
+        if (p0_32) FMB_REQUIRE(p0_32->p.n == A.n && p0_32->p.precision == FMB_FP32, "p0_32 must be an FP32 host plan");
+        h->p0 = p0;
+        h->p1 = pj[0];
+        h->p032 = p0_32;
+        h->p132 = p0_32 ? pj_32[0] : nullptr;
+        h->n = A.n;
+        h->eps = mk(eps[0], eps[1]);
+        h->mu = mk(mu[0], mu[1]);
+        h->gamma = h->mu;
+        h->k0_re = A.k_re;
+        h->k0_im = A.k_im;
+        h->J = J;
+        hipStream_t s = (hipStream_t)stream;
+        if (J > 1) {
+            h->reg.alloc((size_t)A.n * sizeof(int32_t));
+            h->loc.alloc((size_t)A.n * sizeof(int32_t));
+            FMB_CHECK_HIP(hipMemcpyAsync(h->reg.p, region, (size_t)A.n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            FMB_CHECK_HIP(hipMemcpyAsync(h->loc.p, loc.data(), (size_t)A.n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        }
+        setup_dielectric(h, s);
         *out = guard.release();
     });
 }
@@ -1495,7 +1704,8 @@ int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *point
         FMB_REQUIRE(pb && x && points && E, "bad arguments");
         FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
         FMB_REQUIRE(nt >= 1, "no target points");
-        FMB_REQUIRE(region == 0 || (region == 1 && !pb->ibc), "region must be 0 (host) or 1 (interior, dielectric)");
+        FMB_REQUIRE(region == 0 || (region == 1 && !pb->ibc && pb->J == 1),
+                    "region must be 0 (host) or 1 (interior of a one-scatterer dielectric problem)");
         FMB_REQUIRE(!far || region == 0, "the far field is of the host region");
         hipStream_t s = (hipStream_t)stream;
         for (int64_t i = 0; i < 3 * nt; ++i) FMB_REQUIRE(std::isfinite(points[i]), "non-finite target point");
@@ -1600,9 +1810,12 @@ int gmres_solve_group(const fmb_problem_t *pbs, int32_t count, const void *const
             for (int q = 0; q < i; ++q) {
                 FMB_REQUIRE(pbs[q] != pbs[i], "a problem appears twice in the group");
                 const fmb_problem_s &A = *pbs[q], &B = *pbs[i];
-                for (const fmb_plan_s *pa : {A.p0, A.p1, A.p032, A.p132})
-                    for (const fmb_plan_s *pb2 : {B.p0, B.p1, B.p032, B.p132})
-                        FMB_REQUIRE(!pa || pa != pb2, "two problems of the group share a plan");
+                std::vector<const fmb_plan_s *> pa = {A.p0, A.p032}, pbv = {B.p0, B.p032};
+                for (int j = 0; j < A.J; ++j) pa.insert(pa.end(), {A.pj[j], A.pj32[j]});
+                for (int j = 0; j < B.J; ++j) pbv.insert(pbv.end(), {B.pj[j], B.pj32[j]});
+                for (const fmb_plan_s *x1 : pa)
+                    for (const fmb_plan_s *x2 : pbv)
+                        FMB_REQUIRE(!x1 || x1 != x2, "two problems of the group share a plan");
             }
         }
         int dev = 0;

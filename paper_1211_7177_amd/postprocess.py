@@ -1,0 +1,94 @@
+"""Cross sections and far-field multipole coefficients from a solved problem.
+
+With the far-field amplitude F of `bem_field` (E_sca ~ e^{ik0 r} / r F(rhat)),
+for an incident wave p exp(i k0 d . r):
+
+* C_sca = oint |F|^2 dOmega / |p|^2 (eq. 4.2 taken on a sphere in the far zone),
+* C_ext = (4 pi / k0) Im(conj(p) . F(d)) / |p|^2 (the optical theorem),
+* C_abs = C_ext - C_sca (eq. 4.2's C_ext = C_abs + C_sca).
+
+The expansion of eq. 4.4, E_sca = sum_n (a_n N_n + b_n M_n), is read off the
+far field for an x-polarised wave along +z (the convention of the Mie
+coefficients): far away r e^{-ikr} N_e1n -> (-i)^n n_n / k and
+r e^{-ikr} M_o1n -> (-i)^{n+1} m_n / k with the angular functions
+n_n = cos(phi) tau_n theta^ - sin(phi) pi_n phi^ and
+m_n = cos(phi) pi_n theta^ - sin(phi) tau_n phi^, which are orthogonal over the
+sphere with squared norm 2 pi n^2 (n+1)^2 / (2n+1).  Writing E_sca = sum_n E_n
+(i a_n N_e1n - b_n M_o1n), E_n = i^n (2n+1) / (n (n+1)), the projections of
+eq. 4.5 give a_n and b_n (the weighted form of the eq. 4.5 coefficients).
+"""
+
+import numpy as np
+
+
+def sphere_quadrature(nt=32, nph=64):
+    """Gauss-Legendre in cos(theta) times the uniform rule in phi: directions f64[m,3], weights f64[m]."""
+    x, w = np.polynomial.legendre.leggauss(nt)
+    ph = np.linspace(0.0, 2.0 * np.pi, nph, endpoint=False)
+    ct, pp = np.meshgrid(x, ph, indexing="ij")
+    st = np.sqrt(1.0 - ct ** 2)
+    dirs = np.stack([st * np.cos(pp), st * np.sin(pp), ct], -1).reshape(-1, 3)
+    wts = (w[:, None] * np.full(nph, 2.0 * np.pi / nph)[None, :]).reshape(-1)
+    return dirs, wts
+
+
+def _far(problem, x, dirs):
+    return problem.field(x, dirs, far=True).cpu().numpy()
+
+
+def scattering_from_far(F, wts, pol):
+    """C_sca from far-field samples F c128[m,3] with quadrature weights wts."""
+    e0 = float(np.sum(np.abs(np.asarray(pol)) ** 2))
+    return float(np.sum(wts * np.sum(np.abs(F) ** 2, axis=1))) / e0
+
+
+def extinction_from_forward(F_fwd, pol, k0):
+    """C_ext by the optical theorem from the far field F c128[3] in the incident direction."""
+    p = np.asarray(pol, dtype=np.complex128)
+    e0 = float(np.sum(np.abs(p) ** 2))
+    return float(4.0 * np.pi / np.real(k0) * np.imag(np.sum(np.conj(p) * F_fwd))) / e0
+
+
+def cross_sections(problem, x, d, pol, k0, nt=32, nph=64):
+    """(C_ext, C_sca, C_abs) of the solution x [1, n, nu] for the wave pol exp(i k0 d . r)."""
+    d = np.asarray(d, dtype=np.float64)
+    d = d / np.linalg.norm(d)
+    dirs, wts = sphere_quadrature(nt, nph)
+    F = _far(problem, x, np.vstack([dirs, d[None, :]]))[0]
+    csca = scattering_from_far(F[:-1], wts, pol)
+    cext = extinction_from_forward(F[-1], pol, k0)
+    return cext, csca, cext - csca
+
+
+def _pi_tau(nmax, mu):
+    pi = np.zeros((nmax + 1,) + mu.shape)
+    tau = np.zeros((nmax + 1,) + mu.shape)
+    pi[1] = 1.0
+    tau[1] = mu
+    for n in range(2, nmax + 1):
+        pi[n] = (2 * n - 1) / (n - 1) * mu * pi[n - 1] - n / (n - 1) * pi[n - 2]
+        tau[n] = n * mu * pi[n] - (n + 1) * pi[n - 1]
+    return pi[1:], tau[1:]
+
+
+def multipole_coefficients(F, dirs, wts, k0, nmax):
+    """a_n, b_n (n = 1..nmax) of an x-polarised incidence along +z from far-field
+    samples F c128[m,3] at directions dirs with quadrature weights wts."""
+    ct = np.clip(dirs[:, 2], -1.0, 1.0)
+    st = np.sqrt(np.maximum(1.0 - ct ** 2, 0.0))
+    ph = np.arctan2(dirs[:, 1], dirs[:, 0])
+    et = np.stack([ct * np.cos(ph), ct * np.sin(ph), -st], -1)
+    ep = np.stack([-np.sin(ph), np.cos(ph), np.zeros_like(ph)], -1)
+    Ft = np.sum(F * et, axis=1)
+    Fp = np.sum(F * ep, axis=1)
+    pi, tau = _pi_tau(nmax, ct)
+    n = np.arange(1, nmax + 1)
+    En = (1j ** n) * (2 * n + 1) / (n * (n + 1))
+    norm = 2.0 * np.pi * n ** 2 * (n + 1) ** 2 / (2 * n + 1)
+    cp, sp = np.cos(ph), np.sin(ph)
+    pn = np.sum(wts * (cp * tau * Ft - sp * pi * Fp), axis=1) / norm          # <n_n, F> / |n_n|^2
+    pm = np.sum(wts * (cp * pi * Ft - sp * tau * Fp), axis=1) / norm          # <m_n, F> / |m_n|^2
+    k = np.real(k0)
+    a = pn * k / (En * 1j * (-1j) ** n)
+    b = -pm * k / (En * (-1j) ** (n + 1))
+    return a, b

@@ -212,3 +212,73 @@ class IbcProblem(BemProblem):
         check(lib.bem_problem_create_ibc(self.p0.h, self.p0_32.h if self.p0_32 else None, z.ctypes.data, _stream(),
                                          ctypes.byref(h)))
         self.h = h
+
+
+def _nodes_of(nodes, mask):
+    """The nodes with mask set, in their global order, as a node set of its own
+    (triangles renumbered in order)."""
+    idx = np.nonzero(mask)[0]
+    tri = nodes["point_tri"][idx]
+    uniq, inv = np.unique(tri, return_inverse=True)
+    return {"points": np.ascontiguousarray(nodes["points"][idx]), "normals": np.ascontiguousarray(nodes["normals"][idx]),
+            "weights": np.ascontiguousarray(nodes["weights"][idx]), "point_tri": inv.astype(np.int32),
+            "tri_vertices": np.ascontiguousarray(nodes["tri_vertices"][uniq])}
+
+
+class MultiBemProblem(BemProblem):
+    """J dielectric scatterers in vacuum: region[alpha] in 0..J-1 names the
+    scatterer of node alpha; eps, mu list the scatterers' constants.  The host
+    plan covers every node, plan j the nodes of scatterer j (built here from
+    the node subset).  Vectors are complex128 [nrhs, n, 6]."""
+
+    def __init__(self, nodes, region, k0, eps, mu=None, order=16, depth=0, depths=None, nrhs_max=1, order32=None,
+                 corr="linear", leaf_target=32, translate32="fp32"):
+        lib = _abi.load()
+        self._lib = lib
+        region = np.ascontiguousarray(region, dtype=np.int32)
+        J = int(region.max()) + 1
+        self.k0 = complex(k0)
+        self.eps = [complex(e) for e in eps]
+        self.mu = [complex(m) for m in (mu if mu is not None else [1.0] * J)]
+        self.kj = [self.k0 * np.sqrt(e * m) for e, m in zip(self.eps, self.mu)]
+        kw = dict(nrhs_max=nrhs_max, corr=corr, leaf_target=leaf_target)
+        self.p0 = Plan(nodes["points"], nodes["normals"], nodes["weights"], self.k0, order, depth=depth,
+                       point_tri=nodes["point_tri"], tri_vertices=nodes["tri_vertices"], **kw)
+        self.p0_32 = None
+        if order32:
+            self.p0_32 = Plan(nodes["points"], nodes["normals"], nodes["weights"], self.k0, order32,
+                              depth=self.p0.info()["depth"], precision="fp32", translate=translate32,
+                              point_tri=nodes["point_tri"], tri_vertices=nodes["tri_vertices"], **kw)
+        self.pj, self.pj_32 = [], []
+        for j in range(J):
+            sub = _nodes_of(nodes, region == j)
+            dj = depths[j] if depths is not None else 0
+            P = Plan(sub["points"], sub["normals"], sub["weights"], self.kj[j], order, depth=dj,
+                     point_tri=sub["point_tri"], tri_vertices=sub["tri_vertices"], **kw)
+            self.pj.append(P)
+            if order32:
+                self.pj_32.append(Plan(sub["points"], sub["normals"], sub["weights"], self.kj[j], order32,
+                                       depth=P.info()["depth"], precision="fp32", translate=translate32,
+                                       point_tri=sub["point_tri"], tri_vertices=sub["tri_vertices"], **kw))
+        self.p1 = self.pj[0]
+        self.p1_32 = self.pj_32[0] if self.pj_32 else None
+        self.n = nodes["points"].shape[0]
+        self.nrhs_max = nrhs_max
+        hs = (ctypes.c_void_p * J)(*[P.h.value for P in self.pj])
+        hs32 = (ctypes.c_void_p * J)(*[P.h.value for P in self.pj_32]) if self.pj_32 else None
+        e = np.array([[z.real, z.imag] for z in self.eps]).ravel()
+        m = np.array([[z.real, z.imag] for z in self.mu]).ravel()
+        h = ctypes.c_void_p()
+        check(lib.bem_problem_create_multi(self.p0.h, hs, J, region.ctypes.data, e.ctypes.data, m.ctypes.data,
+                                           self.p0_32.h if self.p0_32 else None, hs32, _stream(), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.bem_problem_destroy(self.h)
+            self.h = None
+        for p in [self.p0, self.p0_32] + list(self.pj) + list(self.pj_32):
+            if p is not None:
+                p.close()
+        self.pj, self.pj_32 = [], []
+        self.p0 = self.p0_32 = self.p1 = self.p1_32 = None

@@ -97,3 +97,30 @@ def test_impedance_sphere_far_field(gpu):
     print("impedance sphere C_sca %.5f mie %.5f" % (C, cref))
     assert abs(C - cref) <= 0.08 * cref
     pb.close()
+
+
+def test_cross_sections_and_multipoles_of_solved_sphere(gpu):
+    """Lossy sphere (k0 a = 1, eps = 2.25 + 0.5i, 1280 triangles): C_ext (optical
+    theorem), C_sca (far field) and C_abs, and the far-field multipole
+    coefficients a_1, b_1, a_2 of eq. 4.4, against Mie."""
+    from paper_1211_7177_amd import postprocess as pp
+    eps = 2.25 + 0.5j
+    q = nystrom3(icosphere(8))
+    pb = gpu.BemProblem(q, 1.0, eps, order=20, depth=3, order32=10)
+    b = pb.rhs_planewave([0, 0, 1.0], [1.0, 0, 0])
+    x, info = pb.solve(b, tol=1e-8, mixed=True, inner_tol=1e-3)
+    cext, csca, cabs = pp.cross_sections(pb, x, [0, 0, 1.0], [1.0, 0, 0], 1.0)
+    qext, qsca = mie.efficiencies(1.0, np.sqrt(eps))
+    print("C_ext %.4f (%.4f)  C_sca %.4f (%.4f)  C_abs %.4f (%.4f)" % (
+        cext, qext * np.pi, csca, qsca * np.pi, cabs, (qext - qsca) * np.pi))
+    assert abs(cext - qext * np.pi) <= 0.02 * qext * np.pi
+    assert abs(csca - qsca * np.pi) <= 0.02 * qsca * np.pi
+    assert abs(cabs - (qext - qsca) * np.pi) <= 0.03 * (qext - qsca) * np.pi
+    dirs, wts = pp.sphere_quadrature(24, 48)
+    F = pb.field(x, dirs, far=True).cpu().numpy()[0]
+    a, bb = pp.multipole_coefficients(F, dirs, wts, 1.0, 3)
+    _, am, bm, _, _ = mie.coefficients(1.0, np.sqrt(eps), 3)
+    print("a", a, am, "b", bb, bm)
+    assert abs(a[0] - am[0]) <= 0.03 * abs(am[0]) and abs(bb[0] - bm[0]) <= 0.03 * abs(bm[0])
+    assert abs(a[1] - am[1]) <= 0.05 * abs(am[1])
+    pb.close()

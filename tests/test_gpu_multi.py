@@ -1,0 +1,76 @@
+"""GPU parity of the several-scatterer system against the oracle (needs an MI355X)."""
+
+import numpy as np
+import pytest
+
+from oracle.bem import MultiBemProblem as OracleMulti
+from oracle.gmres import gmres_solve as oracle_gmres
+from synthetic import complex_normal, icosphere, nystrom3, torus, union
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1211_7177_amd import solver
+    return solver
+
+
+@pytest.fixture(scope="module")
+def three():
+    """A sphere, a smaller sphere and a torus side by side (uneven node counts),
+    with a lossless, a lossy dielectric and a metal-like permittivity."""
+    m, treg = union([icosphere(4), icosphere(3, 0.6), torus(0.8, 0.25, 24, 8)],
+                    [[0.0, 0.0, 0.0], [2.2, 0.0, 0.0], [0.0, 2.4, 0.3]])
+    q = nystrom3(m)
+    reg = treg[q["point_tri"]]
+    eps = [2.25, 4.0 + 0.5j, -6.0 + 1.0j]
+    return q, reg, eps, OracleMulti(q, reg, 1.0, eps)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_multi_apply_and_adjoint_match_oracle(gpu, three):
+    q, reg, eps, ob = three
+    n = q["points"].shape[0]
+    print("multi apply: %d nodes, regions %s" % (n, np.bincount(reg)), flush=True)
+    pb = gpu.MultiBemProblem(q, reg, 1.0, eps, order=20, depth=4)
+    x = complex_normal((n, 6), 161)
+    xg = torch.from_numpy(x).cuda()
+    assert _rel(pb.apply(xg).cpu().numpy(), ob.apply(x)) <= 1e-7
+    assert _rel(pb.apply_adjoint(xg).cpu().numpy(), ob.apply_adjoint(x)) <= 1e-7
+    assert _rel(pb.precond(xg).cpu().numpy(), ob.block_preconditioner()(x)) <= 1e-11
+    pb.close()
+
+
+def test_multi_solves_match_oracle(gpu, three):
+    q, reg, eps, ob = three
+    print("multi solves", flush=True)
+    b = ob.rhs_planewave([0.0, 0.6, 0.8], [1.0, 0.0, 0.0])
+    xo, io = oracle_gmres(ob.apply, b, ob.block_preconditioner(), tol=1e-10, restart=200)
+    pb = gpu.MultiBemProblem(q, reg, 1.0, eps, order=22, depth=4, order32=10)
+    bg = torch.from_numpy(b).cuda().unsqueeze(0)
+    x, info = pb.solve(bg, tol=1e-10, restart=200, maxit=800)
+    print("its gpu", info["iterations"], "oracle", io["iterations"], "err", _rel(x.cpu().numpy()[0], xo))
+    assert info["residual"] <= 1e-10 and _rel(x.cpu().numpy()[0], xo) <= 1e-6
+    xm, im = pb.solve(bg, tol=1e-8, mixed=True, inner_tol=1e-3)
+    assert im["residual"] <= 1e-8 and _rel(xm.cpu().numpy()[0], xo) <= 1e-6
+    xs, _ = pb.solve(bg, tol=1e-8, mixed=True, inner_tol=1e-3, serial=True)
+    assert torch.equal(xs, xm)                          # the products' order on the streams does not change a bit
+    pb.close()
+
+
+def test_one_region_multi_equals_single(gpu):
+    q = nystrom3(icosphere(4))
+    n = q["points"].shape[0]
+    pm = gpu.MultiBemProblem(q, np.zeros(n, np.int32), 1.0, [2.25], order=14, depth=3, depths=[3])
+    ps = gpu.BemProblem(q, 1.0, 2.25, order=14, depth=3)
+    x = torch.from_numpy(complex_normal((n, 6), 162)).cuda()
+    assert torch.equal(pm.apply(x), ps.apply(x))
+    pm.close()
+    ps.close()

@@ -1,0 +1,52 @@
+"""Pins of the cross-section and multipole post-processing against Mie (CPU only)."""
+
+import numpy as np
+
+from oracle import mie
+from paper_1211_7177_amd import postprocess as pp
+
+
+def _mie_far(eps, dirs, r=2e4):
+    """r e^{-ikr} E_sca(r rhat) of the Mie sphere (k a = 1) at large r (the
+    oracle's numerical vector spherical harmonics, scattered part only)."""
+    E, _ = mie.fields(r * dirs, 1.0, 1.0, eps, "scattered")
+    return E * r * np.exp(-1j * r)
+
+
+def test_projection_recovers_known_coefficients():
+    """A far field built from chosen a_n, b_n with the far-zone forms of N_e1n and
+    M_o1n is projected back to the same coefficients."""
+    rng = np.random.default_rng(3)
+    nmax = 5
+    a = rng.standard_normal(nmax) + 1j * rng.standard_normal(nmax)
+    b = rng.standard_normal(nmax) + 1j * rng.standard_normal(nmax)
+    dirs, wts = pp.sphere_quadrature(24, 48)
+    ct = dirs[:, 2]
+    st = np.sqrt(1 - ct ** 2)
+    ph = np.arctan2(dirs[:, 1], dirs[:, 0])
+    et = np.stack([ct * np.cos(ph), ct * np.sin(ph), -st], -1)
+    ep = np.stack([-np.sin(ph), np.cos(ph), 0 * ph], -1)
+    pi, tau = pp._pi_tau(nmax, ct)
+    F = np.zeros((len(ct), 3), complex)
+    k = 1.7
+    for i, n in enumerate(range(1, nmax + 1)):
+        En = 1j ** n * (2 * n + 1) / (n * (n + 1))
+        nn = np.cos(ph)[:, None] * tau[i][:, None] * et - np.sin(ph)[:, None] * pi[i][:, None] * ep
+        mm = np.cos(ph)[:, None] * pi[i][:, None] * et - np.sin(ph)[:, None] * tau[i][:, None] * ep
+        F += En * (1j * a[i] * (-1j) ** n * nn - b[i] * (-1j) ** (n + 1) * mm) / k
+    ra, rb = pp.multipole_coefficients(F, dirs, wts, k, nmax)
+    assert np.abs(ra - a).max() <= 1e-12 and np.abs(rb - b).max() <= 1e-12
+
+
+def test_mie_far_field_gives_mie_coefficients_and_cross_sections():
+    for eps in (2.25, 2.25 + 0.5j):
+        dirs, wts = pp.sphere_quadrature(24, 48)
+        F = _mie_far(eps, dirs)
+        n, a, b, _, _ = mie.coefficients(1.0, np.sqrt(eps), 4)
+        ra, rb = pp.multipole_coefficients(F, dirs, wts, 1.0, 4)
+        assert np.abs(ra - a).max() <= 1e-3 * np.abs(a).max() and np.abs(rb - b).max() <= 1e-3 * np.abs(a).max()
+        qext, qsca = mie.efficiencies(1.0, np.sqrt(eps))
+        csca = pp.scattering_from_far(F, wts, [1.0, 0, 0])
+        cext = pp.extinction_from_forward(_mie_far(eps, np.array([[0.0, 0.0, 1.0]]))[0], [1.0, 0, 0], 1.0)
+        assert abs(csca - qsca * np.pi) <= 1e-3 * qsca * np.pi
+        assert abs(cext - qext * np.pi) <= 1e-3 * qext * np.pi
