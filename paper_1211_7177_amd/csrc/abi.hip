@@ -124,7 +124,7 @@ int fmm_plan(const double *points, const double *normals, const double *weights,
         upload(d_w, weights, n * sizeof(double), s);
         upload(P.point_tri, tri.data(), n * sizeof(int32_t), s);
         upload(P.unrm, normals, n * 3 * sizeof(double), s);
-        build_tree(P, d_pts.as<double>(), s);
+        build_tree(P, d_pts.as<double>(), s, ntri > 0 ? tri.data() : nullptr);
         gather_nodes(P, d_pts.as<double>(), d_nrm.as<double>(), d_w.as<double>(), P.point_tri.as<int32_t>(), s);
         build_operators(P, s);
         build_tiles(P, s);

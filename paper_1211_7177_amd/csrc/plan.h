@@ -103,7 +103,10 @@ struct Plan {
 };
 
 // plan-building steps (plan.hip)
-void build_tree(Plan &P, const double *d_pts, hipStream_t s);
+// host_tri (optional, host i32[n]): triangle of each node; depths at which two
+// nodes of one triangle fall in non-neighbouring leaves are refused (an
+// automatic depth steps down instead)
+void build_tree(Plan &P, const double *d_pts, hipStream_t s, const int32_t *host_tri = nullptr);
 void gather_nodes(Plan &P, const double *d_pts, const double *d_nrm, const double *d_w, const int32_t *d_tri,
                   hipStream_t s);
 void build_operators(Plan &P, hipStream_t s);

@@ -10,6 +10,8 @@
 //   neighbours = same-level boxes with integer coordinates within 1 per axis,
 //   FF(l,q) = Children(Neighbor(Parent(l,q))) \ Neighbor(l,q)   (Appendix C).
 #include <algorithm>
+#include <cstdlib>
+#include <vector>
 
 #include "plan.h"
 
@@ -408,7 +410,37 @@ int64_t device_exclusive_scan(int32_t *d, int64_t m, hipStream_t s) {
 
 }  // namespace
 
-void build_tree(Plan &P, const double *d_pts, hipStream_t s) {
+// Number of node pairs that share a triangle but lie in leaves of level d that
+// are not neighbours (box coordinates differing by more than one on an axis).
+// The near field excludes same-triangle pairs; a pair that the octree hands to
+// the far field instead would be counted, so such depths are refused.  code:
+// Morton codes in user order; tri: the triangle of each node.
+static int64_t split_triangle_pairs(const std::vector<uint64_t> &code, const int32_t *tri, int64_t n, int64_t ntri,
+                                    int d) {
+    std::vector<int64_t> start(ntri + 1, 0), idx(n);
+    for (int64_t i = 0; i < n; ++i) ++start[tri[i] + 1];
+    for (int64_t t = 0; t < ntri; ++t) start[t + 1] += start[t];
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    for (int64_t i = 0; i < n; ++i) idx[fill[tri[i]]++] = i;
+    auto coord = [&](uint64_t c, int axis) {
+        const uint64_t key = c >> (3 * (NBITS - d));
+        int64_t v = 0;
+        for (int b = 0; b < d; ++b) v |= (int64_t)((key >> (3 * b + axis)) & 1u) << b;
+        return v;
+    };
+    int64_t bad = 0;
+    for (int64_t t = 0; t < ntri; ++t)
+        for (int64_t x = start[t]; x < start[t + 1]; ++x)
+            for (int64_t y = x + 1; y < start[t + 1]; ++y)
+                for (int axis = 0; axis < 3; ++axis)
+                    if (std::llabs(coord(code[idx[x]], axis) - coord(code[idx[y]], axis)) > 1) {
+                        ++bad;
+                        break;
+                    }
+    return bad;
+}
+
+void build_tree(Plan &P, const double *d_pts, hipStream_t s, const int32_t *host_tri) {
     const int64_t n = P.n;
     // bounding cube
     const int nbp = (int)std::min<int64_t>(1024, grid_for(n));
@@ -475,7 +507,8 @@ void build_tree(Plan &P, const double *d_pts, hipStream_t s) {
         FMB_CHECK_HIP(hipStreamSynchronize(s));
         return last;
     };
-    if (P.depth == 0) {
+    const bool auto_depth = P.depth == 0;
+    if (auto_depth) {
         // deepest level whose mean leaf population still reaches the target
         int d = 2;
         for (; d < MAX_DEPTH; ++d) {
@@ -483,6 +516,20 @@ void build_tree(Plan &P, const double *d_pts, hipStream_t s) {
             if ((double)n / (double)nl < (double)P.leaf_target) break;
         }
         P.depth = d;
+    }
+    if (host_tri && P.ntri > 0 && n > P.ntri) {
+        std::vector<uint64_t> hc(n);
+        FMB_CHECK_HIP(hipMemcpyAsync(hc.data(), P.codes.p, n * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        FMB_CHECK_HIP(hipStreamSynchronize(s));
+        int64_t bad = split_triangle_pairs(hc, host_tri, n, P.ntri, P.depth);
+        while (auto_depth && bad > 0 && P.depth > 2) {
+            --P.depth;
+            bad = split_triangle_pairs(hc, host_tri, n, P.ntri, P.depth);
+        }
+        FMB_REQUIRE(bad == 0, "the octree is too deep for this mesh: " + std::to_string(bad) +
+                                  " node pairs of one triangle fall in leaves that are not neighbours at depth " +
+                                  std::to_string(P.depth) + " (their interaction would leave the near field); " +
+                                  "use a smaller depth");
     }
     const int L = P.depth;
     P.lv.clear();

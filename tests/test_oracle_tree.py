@@ -79,3 +79,32 @@ def test_tree_invariants_and_exact_cover(shape):
                 assert d.max() >= 2
                 pd = np.abs(T.coords[l - 1][T.parent[l][j]] - T.coords[l - 1][T.parent[l][i]])
                 assert pd.max() <= 1
+
+
+def _split_triangle_pairs(q, depth):
+    """Node pairs of one triangle whose leaves are not neighbours in the reference octree."""
+    from oracle.tree import Octree
+    T = Octree(q["points"], depth)
+    inv = np.empty_like(T.perm)
+    inv[T.perm] = np.arange(len(T.perm))
+    leaf = T.point_box[depth][inv]
+    tri = q["point_tri"]
+    order = np.argsort(tri, kind="stable")
+    bad = 0
+    for t in range(int(tri.max()) + 1):
+        nodes = order[np.searchsorted(tri[order], t):np.searchsorted(tri[order], t, side="right")]
+        for i, a in enumerate(nodes):
+            near = set(T.nbr[depth][leaf[a]].tolist())
+            bad += sum(1 for b in nodes[i + 1:] if leaf[b] not in near)
+    return bad
+
+
+def test_deep_trees_split_triangles():
+    """Why the library refuses some depths: at the configurations' depths every
+    triangle's nodes share the near field, one level or two deeper they do not
+    (the torus at depth 7, the 1280-triangle sphere at depth 5)."""
+    from synthetic import icosphere, nystrom3, torus
+    qt = nystrom3(torus(1.0, 0.3, 200, 50))
+    qs = nystrom3(icosphere(8))
+    assert _split_triangle_pairs(qt, 5) == 0 and _split_triangle_pairs(qt, 7) > 0
+    assert _split_triangle_pairs(qs, 3) == 0 and _split_triangle_pairs(qs, 5) > 0
