@@ -321,11 +321,15 @@ int gmres_solve_group(const fmb_problem_t *pbs, int32_t count, const void *const
  *   region 1, far 0: the field inside the scatterer, E_1(r) = Op_k1(T Phi, -gamma Psi)(r)
  *                    (dielectric problems);
  *   region 0, far 1: the far-field amplitude F(rhat), E_sca ~ e^{i k0 r} / r F(rhat), for unit
- *                    directions rhat.
+ *                    directions rhat;
+ *   region 0, far 2: curl E_sca at host points (the scattered magnetic field is
+ *                    curl E_sca / (i k0) in units with eps0 = mu0 = 1), the curl in r of the
+ *                    same sum: -sum w [ Hess(g) (a x n) + k0^2 g (a x n) + grad g x b ].
  * points: host f64[nt][3] target points (off the surface: a target that
  * coincides with a node skips that node) or unit directions; E: device c128
  * [nrhs][nt][3].  Direct FP64 sums over all nodes (cost nt * n per right-hand
- * side); synchronous.
+ * side); synchronous.  far outside 0..2, or far != 0 with region 1, is
+ * FMB_EINVAL.
  */
 int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt, int32_t region,
               int32_t far, void *E, void *stream);

@@ -162,6 +162,24 @@ def efficiencies(x: float, m: complex, nmax=None):
     return qext, qsca
 
 
+def radiation_pressure(x: float, m: complex, nmax=None, coeffs=None):
+    """Q_pr = Q_ext - g Q_sca, with the asymmetry term (B&H eq. 4.74)
+    g Q_sca = 4/x^2 [ sum_n n(n+2)/(n+1) Re(a_n a_{n+1}^* + b_n b_{n+1}^*)
+                      + sum_n (2n+1)/(n(n+1)) Re(a_n b_n^*) ].
+    The time-averaged force on the sphere in a plane wave of irradiance I is
+    Q_pr pi a^2 I / c along the propagation direction."""
+    if coeffs is None:
+        n, a, b, _, _ = coefficients(x, m, nmax)
+    else:
+        n, a, b = coeffs
+    qsca = 2.0 / x ** 2 * np.sum((2 * n + 1) * (abs(a) ** 2 + abs(b) ** 2))
+    qext = 2.0 / x ** 2 * np.sum((2 * n + 1) * np.real(a + b))
+    nn = n[:-1]
+    gq = 4.0 / x ** 2 * (np.sum(nn * (nn + 2) / (nn + 1) * np.real(a[:-1] * np.conj(a[1:]) + b[:-1] * np.conj(b[1:])))
+                         + np.sum((2 * n + 1) / (n * (n + 1)) * np.real(a * np.conj(b))))
+    return qext - gq
+
+
 def surface_unknowns(nodes, k: float, a: float, eps: complex, nmax=None):
     """Mie (Phi, Psi) at the radially projected nodes a s/|s|, with Psi formed with
     the mesh's face normal: Psi = n x curl E_0.  Returns c128[n,6]."""

@@ -563,8 +563,13 @@ struct FieldSrc {
     cx<double> a[FE_TILE][3], b[FE_TILE][3];
 };
 
-// region: 0 host (scattered field), 1 interior; far: targets are unit directions
-template <bool FAR>
+// region: 0 host (scattered field), 1 interior; KIND 0: the field at points,
+// 1: the far-field amplitude at unit directions, 2: curl of the scattered field
+// at host points, -sum w [ Hess(g) c + k^2 g c + grad_r g x b ] with c = a x n
+// (the summand's curl: its first term is grad_r g x c, the (n . a) grad_r g term
+// is a gradient), grad_r g = g' u, Hess(g) = (g'' - g'/R) u u^T + (g'/R) I,
+// u = (r - s)/R, g' = (ik - 1/R) g, g'' = ((ik - 1/R)^2 + 1/R^2) g.
+template <int KIND>
 __global__ void __launch_bounds__(FE_TILE) k_field(const double *__restrict__ tgt, int64_t nt,
                                                    const double *__restrict__ spts, const double *__restrict__ snrm,
                                                    const double *__restrict__ sw, const int32_t *__restrict__ perm,
@@ -615,7 +620,27 @@ __global__ void __launch_bounds__(FE_TILE) k_field(const double *__restrict__ tg
             const double *nb = S.nrm[j];
             const cx<double> *a = S.a[j], *b = S.b[j];
             const cx<double> na = nb[0] * a[0] + nb[1] * a[1] + nb[2] * a[2];
-            if (FAR) {
+            if (KIND == 2) {
+                const double ux0 = p[0] - S.pos[j][0], uy0 = p[1] - S.pos[j][1], uz0 = p[2] - S.pos[j][2];
+                const double R2 = ux0 * ux0 + uy0 * uy0 + uz0 * uz0;
+                if (R2 <= 0.0) continue;
+                const double R = sqrt(R2), iR = 1.0 / R;
+                const double u[3] = {ux0 * iR, uy0 * iR, uz0 * iR};
+                double sn, cs;
+                sincos(k_re * R, &sn, &cs);
+                const cx<double> g = (S.w[j] * inv4pi * iR * exp(-k_im * R)) * mk(cs, sn);
+                const cx<double> ikr = mk(-k_im - iR, k_re);                  // i k - 1/R
+                const cx<double> g1 = ikr * g;
+                const cx<double> g2 = (ikr * ikr + mk(iR * iR, 0.0)) * g;
+                const cx<double> c[3] = {a[1] * nb[2] - a[2] * nb[1], a[2] * nb[0] - a[0] * nb[2],
+                                         a[0] * nb[1] - a[1] * nb[0]};
+                const cx<double> uc = u[0] * c[0] + u[1] * c[1] + u[2] * c[2];
+                const cx<double> hu = (g2 - iR * g1) * uc, hc = iR * g1, kk = k * k * g;
+                const cx<double> gr[3] = {u[0] * g1, u[1] * g1, u[2] * g1};
+                const cx<double> gxb[3] = {gr[1] * b[2] - gr[2] * b[1], gr[2] * b[0] - gr[0] * b[2],
+                                           gr[0] * b[1] - gr[1] * b[0]};
+                for (int q2 = 0; q2 < 3; ++q2) acc[q2] += u[q2] * hu + (hc + kk) * c[q2] + gxb[q2];
+            } else if (KIND == 1) {
                 // e^{-ik rhat . s} w / (4 pi) times [ -ik (n (rhat . a) - (n . rhat) a - rhat (n . a)) + b ]
                 const double ph = p[0] * S.pos[j][0] + p[1] * S.pos[j][1] + p[2] * S.pos[j][2];
                 double sn, cs;
@@ -643,7 +668,7 @@ __global__ void __launch_bounds__(FE_TILE) k_field(const double *__restrict__ tg
         }
     }
     if (!active) return;
-    const double sg = FAR ? -1.0 : (region == 0 ? -1.0 : 1.0);
+    const double sg = KIND != 0 ? -1.0 : (region == 0 ? -1.0 : 1.0);
     for (int q = 0; q < 3; ++q) out[((int64_t)r * nt + t) * 3 + q] = sg * acc[q];
 }
 
@@ -1706,10 +1731,11 @@ int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *point
         FMB_REQUIRE(nt >= 1, "no target points");
         FMB_REQUIRE(region == 0 || (region == 1 && !pb->ibc && pb->J == 1),
                     "region must be 0 (host) or 1 (interior of a one-scatterer dielectric problem)");
-        FMB_REQUIRE(!far || region == 0, "the far field is of the host region");
+        FMB_REQUIRE(far >= 0 && far <= 2, "kind must be 0 (field), 1 (far field) or 2 (curl)");
+        FMB_REQUIRE(far == 0 || region == 0, "the far field and the curl are of the host region");
         hipStream_t s = (hipStream_t)stream;
         for (int64_t i = 0; i < 3 * nt; ++i) FMB_REQUIRE(std::isfinite(points[i]), "non-finite target point");
-        if (far)
+        if (far == 1)
             for (int64_t i = 0; i < nt; ++i) {
                 const double r2 = points[3 * i] * points[3 * i] + points[3 * i + 1] * points[3 * i + 1] +
                                   points[3 * i + 2] * points[3 * i + 2];
@@ -1722,7 +1748,7 @@ int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *point
         FMB_CHECK_HIP(hipMemcpyAsync(dt.p, points, (size_t)nt * 3 * sizeof(double), hipMemcpyHostToDevice, s));
         const cx<double> tc = cdiv(mk(1.0, 0.0) - pb->eps, pb->eps);
         const dim3 grid((unsigned)((nt + FE_TILE - 1) / FE_TILE), (unsigned)nrhs);
-        auto kern = far ? k_field<true> : k_field<false>;
+        auto kern = far == 1 ? k_field<1> : (far == 2 ? k_field<2> : k_field<0>);
         kern<<<grid, FE_TILE, 0, s>>>(dt.as<double>(), nt, A.spts.as<double>(), A.snrm.as<double>(), A.sw.as<double>(),
                                       A.perm.as<int32_t>(), (const cx<double> *)x, pb->n, pb->nu, region,
                                       pb->ibc ? 1 : 0, K.k_re, K.k_im, tc, pb->gamma, pb->cibc, (cx<double> *)E);

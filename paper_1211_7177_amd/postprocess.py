@@ -7,6 +7,11 @@ for an incident wave p exp(i k0 d . r):
 * C_ext = (4 pi / k0) Im(conj(p) . F(d)) / |p|^2 (the optical theorem),
 * C_abs = C_ext - C_sca (eq. 4.2's C_ext = C_abs + C_sca).
 
+The time-averaged optical force on the scatterers follows from the total host
+fields on a closed sphere around them: F = oint <T> . n dA with the Maxwell
+stress tensor <T> = 1/2 Re[ E E^* + H H^* - 1/2 (|E|^2 + |H|^2) I ] (eps0 = mu0 = 1)
+and H = curl E / (i k0), where E_sca and curl E_sca come from `bem_field`.
+
 The expansion of eq. 4.4, E_sca = sum_n (a_n N_n + b_n M_n), is read off the
 far field for an x-polarised wave along +z (the convention of the Mie
 coefficients): far away r e^{-ikr} N_e1n -> (-i)^n n_n / k and
@@ -58,6 +63,40 @@ def cross_sections(problem, x, d, pol, k0, nt=32, nph=64):
     csca = scattering_from_far(F[:-1], wts, pol)
     cext = extinction_from_forward(F[-1], pol, k0)
     return cext, csca, cext - csca
+
+
+def stress_tensor_force(E, curlE, k0, normals, weights):
+    """oint <T> . n dA from total fields E, curl E c128[m,3] on a closed surface in
+    the host medium with outward normals f64[m,3] and area weights f64[m]."""
+    H = np.asarray(curlE) / (1j * k0)
+    E = np.asarray(E)
+    nrm = np.asarray(normals, dtype=np.float64)
+    sE = np.einsum("md,md->m", np.conj(E), nrm)
+    sH = np.einsum("md,md->m", np.conj(H), nrm)
+    u = 0.5 * (np.einsum("md,md->m", E, np.conj(E)).real + np.einsum("md,md->m", H, np.conj(H)).real)
+    t = 0.5 * np.real(E * sE[:, None] + H * sH[:, None] - u[:, None] * nrm)
+    return np.einsum("m,md->d", np.asarray(weights, dtype=np.float64), t)
+
+
+def optical_force(problem, x, d, pol, k0, radius, center=(0.0, 0.0, 0.0), nt=32, nph=64):
+    """Time-averaged force f64[nrhs, 3] on the scatterers of the solutions x
+    [nrhs, n, nu] for the plane waves pol exp(i k0 d . r) (d, pol: [3] or
+    [nrhs, 3]), integrated over the sphere of the given radius and center,
+    which must enclose every scatterer and stay off the surface."""
+    dirs, wts = sphere_quadrature(nt, nph)
+    pts = np.asarray(center, dtype=np.float64)[None, :] + radius * dirs
+    Es = problem.field(x, pts).cpu().numpy()
+    Cs = problem.field(x, pts, curl=True).cpu().numpy()
+    nr = Es.shape[0]
+    D = np.broadcast_to(np.atleast_2d(np.asarray(d, dtype=np.float64)), (nr, 3))
+    P = np.broadcast_to(np.atleast_2d(np.asarray(pol, dtype=np.complex128)), (nr, 3))
+    out = np.zeros((nr, 3))
+    for r in range(nr):
+        dr = D[r] / np.linalg.norm(D[r])
+        Ei = np.exp(1j * k0 * (pts @ dr))[:, None] * P[r][None, :]
+        Ci = 1j * k0 * np.cross(np.broadcast_to(dr, Ei.shape), Ei)
+        out[r] = stress_tensor_force(Ei + Es[r], Ci + Cs[r], k0, dirs, wts * radius ** 2)
+    return out
 
 
 def _pi_tau(nmax, mu):
