@@ -79,10 +79,13 @@ def stress_tensor_force(E, curlE, k0, normals, weights):
 
 
 def optical_force(problem, x, d, pol, k0, radius, center=(0.0, 0.0, 0.0), nt=32, nph=64):
-    """Time-averaged force f64[nrhs, 3] on the scatterers of the solutions x
-    [nrhs, n, nu] for the plane waves pol exp(i k0 d . r) (d, pol: [3] or
-    [nrhs, 3]), integrated over the sphere of the given radius and center,
-    which must enclose every scatterer and stay off the surface."""
+    """Time-averaged force f64[nrhs, 3] on the scatterers inside the sphere of
+    the given radius and center, for the solutions x [nrhs, n, nu] of the plane
+    waves pol exp(i k0 d . r) (d, pol: [3] or [nrhs, 3]).  The sphere lies in
+    the host medium: it encloses the scatterers whose force is wanted, and no
+    surface crosses it (around one scatterer of several, it gives the force on
+    that one).  The fields are the discrete representation's, whose accuracy
+    falls within about a mesh edge of a surface; keep the sphere farther off."""
     dirs, wts = sphere_quadrature(nt, nph)
     pts = np.asarray(center, dtype=np.float64)[None, :] + radius * dirs
     Es = problem.field(x, pts).cpu().numpy()

@@ -74,3 +74,47 @@ def test_one_region_multi_equals_single(gpu):
     assert torch.equal(pm.apply(x), ps.apply(x))
     pm.close()
     ps.close()
+
+
+def test_gold_dimer_force_on_one_sphere(gpu):
+    """Two gold spheres (radius 100 nm, surface gap 250 nm, along x; 960 nodes
+    each; length unit 100 nm) at 500 nm, eps from the Drude model of Sec. 3.2,
+    under a wave along +z polarised along x, with the force on each sphere from
+    a stress-tensor sphere around it alone (the workload of the force comparison
+    in the paper's appendix D).  The GPU solve and forces against the oracle's;
+    mirror symmetry of the two forces; and the sum of the two forces against the
+    force from one sphere around both (0.26% apart in the oracle too: the discrete
+    field is not exactly divergence-free, so the stress tensor is not exactly
+    conserved between the surfaces)."""
+    from oracle import fields as of
+    from oracle import materials as om
+    from paper_1211_7177_amd import materials, postprocess as pp
+    eps = complex(materials.gold_drude(500e-9))
+    k0 = float(materials.wavenumber(500e-9, 100e-9))
+    m, treg = union([icosphere(4), icosphere(4)], [[-2.25, 0.0, 0.0], [2.25, 0.0, 0.0]])
+    q = nystrom3(m)
+    reg = treg[q["point_tri"]]
+    ob = OracleMulti(q, reg, k0, [complex(om.eps_gold(om.omega(500e-9)))] * 2)
+    b = ob.rhs_planewave([0, 0, 1.0], [1.0, 0, 0])
+    xo, io = oracle_gmres(ob.apply, b, ob.block_preconditioner(), tol=1e-10, restart=200)
+    pb = gpu.MultiBemProblem(q, reg, k0, [eps, eps], order=20)
+    x, info = pb.solve(pb.rhs_planewave([0, 0, 1.0], [1.0, 0, 0]), tol=1e-10, restart=200)
+    print("dimer its gpu", info["iterations"], "oracle", io["iterations"], flush=True)
+    assert _rel(x.cpu().numpy()[0], xo) <= 1e-6
+    kw = dict(nt=24, nph=48)
+    Fl = pp.optical_force(pb, x, [0, 0, 1.0], [1.0, 0, 0], k0, 1.6, center=[-2.25, 0, 0], **kw)[0]
+    Fr = pp.optical_force(pb, x, [0, 0, 1.0], [1.0, 0, 0], k0, 1.6, center=[2.25, 0, 0], **kw)[0]
+    Fb = pp.optical_force(pb, x, [0, 0, 1.0], [1.0, 0, 0], k0, 3.8, **kw)[0]
+    dirs, wts = pp.sphere_quadrature(24, 48)
+    pts = np.array([-2.25, 0, 0])[None] + 1.6 * dirs
+    Ei = np.exp(1j * k0 * pts[:, 2])[:, None] * np.array([1.0, 0, 0])[None, :]
+    Ci = 1j * k0 * np.cross(np.broadcast_to([0, 0, 1.0], Ei.shape), Ei)
+    Fo = of.stress_force(Ei + of.scattered_field(q, k0, xo, pts), Ci + of.scattered_curl(q, k0, xo, pts),
+                         k0, dirs, 1.6 ** 2 * wts)
+    print("F_left", Fl, "oracle", Fo, "F_right", Fr, "F_both", Fb, flush=True)
+    assert np.linalg.norm(Fl - Fo) <= 1e-6 * np.linalg.norm(Fo)
+    scale = np.linalg.norm(Fl)
+    assert abs(Fl[0] + Fr[0]) <= 1e-6 * scale and abs(Fl[2] - Fr[2]) <= 1e-6 * scale
+    assert abs(Fl[1]) <= 1e-8 * scale and abs(Fr[1]) <= 1e-8 * scale
+    assert np.linalg.norm(Fl + Fr - Fb) <= 0.01 * np.linalg.norm(Fb)
+    pb.close()
