@@ -18,6 +18,18 @@ Only the interior rows depend on eps: through T = I + (1 - eps)/eps n n^T
 (dT/deps = -n n^T / eps^2) and through k1 = k0 sqrt(eps mu) (dk1/deps = k1 / (2 eps)),
 whose operator derivative is taken as the central difference of two products
 at k1 +- delta (plans of the same octree and order).
+
+For a shape family nodes(theta) (theta in R^m: vertex displacements, along the
+vertex normals or any other field, applied to the mesh, with points, normals,
+weights and self-triangle blocks all following from the moved triangles) both
+the system and the functional move: A(theta) x = b(theta), C = f(x, theta).  Then
+
+    dC/dtheta_i = df/dtheta_i |_x + Re < lambda, d(b - A x)/dtheta_i |_x >,
+
+again with lambda = A^{-H} g, so one forward and one adjoint solve serve every
+parameter; each parameter adds the central difference of b - A x and of f at
+theta +- h e_i (two problem builds and two products on the octree depth of the
+unperturbed shape, with x held fixed).
 """
 
 import numpy as np
@@ -89,3 +101,36 @@ def cross_section_and_eps_gradient(nodes, k0, eps, d, pol, order=16, depth=0, to
     Pm.close()
     pb.close()
     return C.item(), -u.real, u.imag
+
+
+def cross_section_and_shape_gradient(nodes_at, nparams, k0, eps, d, pol, order=16, depth=0, tol=1e-10, restart=150,
+                                     h=1e-3, mu=1.0):
+    """(C_sca, dC/dtheta f64[nparams]) at theta = 0 for the shape family
+    nodes_at(theta) (a callable returning the Nystrom nodes of the moved mesh,
+    node order unchanged), by one forward and one adjoint solve and, per
+    parameter, two rebuilt problems and products."""
+    eps = complex(eps)
+    q0 = nodes_at(np.zeros(nparams))
+    pb = BemProblem(q0, k0, eps, mu=mu, order=order, depth=depth)
+    dep = pb.p0.info()["depth"]
+    kw = dict(tol=tol, restart=restart, maxit=4000)
+    xd, _ = pb.solve(pb.rhs_planewave(d, pol), **kw)
+    xg = xd.clone().requires_grad_(True)
+    C = scattering_cross_section(q0, k0, xg, d, pol)
+    g = torch.autograd.grad(C, xg)[0]
+    lam, _ = pb.solve(g.contiguous(), adjoint=True, **kw)
+    pb.close()
+    grad = np.zeros(nparams)
+    for i in range(nparams):
+        res, fun = [], []
+        for sgn in (1.0, -1.0):
+            th = np.zeros(nparams)
+            th[i] = sgn * h
+            q = nodes_at(th)
+            p = BemProblem(q, k0, eps, mu=mu, order=order, depth=dep)
+            res.append(p.rhs_planewave(d, pol) - p.apply(xd))
+            fun.append(scattering_cross_section(q, k0, xd, d, pol).item())
+            p.close()
+        dr = (res[0] - res[1]) / (2.0 * h)
+        grad[i] = (fun[0] - fun[1]) / (2.0 * h) + torch.sum(torch.conj(lam) * dr).real.item()
+    return C.item(), grad
