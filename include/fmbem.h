@@ -334,6 +334,24 @@ int gmres_solve_group(const fmb_problem_t *pbs, int32_t count, const void *const
 int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt, int32_t region,
               int32_t far, void *E, void *stream);
 
+/*
+ * bem_field_fmm: the field of bem_field's kind 0 (region 0: E_sca at host
+ * points; region 1: the interior field) by the fast multipole method instead of
+ * direct sums, for many targets.  A temporary FP64 plan of the given order is
+ * built over the nodes followed by the nt targets (the targets carry zero
+ * density, so only the nodes radiate); one product of it gives the sum at every
+ * target.  Cost O((n + nt) log) per call plus the plan build, against n * nt for
+ * bem_field; the result agrees with bem_field to the FMM tolerance of the order
+ * (p = 16: about 1e-7 relative when the top-level boxes of the cube around
+ * nodes and targets are a few wavelengths or less).
+ * points: host f64[nt][3], off the surface and distinct from every node and
+ * from each other (a coincident point is FMB_EINVAL); E: device c128
+ * [nrhs][nt][3].  Allocates device memory for the plan and three
+ * [nrhs][n + nt][3] work arrays; synchronous.
+ */
+int bem_field_fmm(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt, int32_t region,
+                  int32_t order, void *E, void *stream);
+
 int bem_problem_destroy(fmb_problem_t pb);
 
 /* Thread-local message for the last non-zero status returned on this thread. */

@@ -672,6 +672,55 @@ __global__ void __launch_bounds__(FE_TILE) k_field(const double *__restrict__ tg
     for (int q = 0; q < 3; ++q) out[((int64_t)r * nt + t) * 3 + q] = sg * acc[q];
 }
 
+// Densities of the field sum laid out for a plan over the nodes (user order)
+// followed by nt target points, zero at the targets: a = Phi, b = -Psi (host
+// region), a = T Phi, b = -gamma Psi (interior), a = Phi, b = c n x (n x Phi)
+// (impedance).  Threads run over the sorted node index and the targets.
+__global__ void __launch_bounds__(TPB) k_field_dens(const double *__restrict__ snrm, const int32_t *__restrict__ perm,
+                                                    const cx<double> *__restrict__ x, int64_t n, int64_t nt, int nu,
+                                                    int region, int ibc, cx<double> tc, cx<double> gamma,
+                                                    cx<double> cibc, cx<double> *__restrict__ a,
+                                                    cx<double> *__restrict__ b) {
+    const int r = blockIdx.y;
+    const int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    const int64_t m = n + nt;
+    if (i >= m) return;
+    cx<double> *ar = a + (int64_t)r * m * 3, *br = b + (int64_t)r * m * 3;
+    if (i >= n) {
+        for (int q = 0; q < 3; ++q) ar[3 * i + q] = br[3 * i + q] = mk(0.0, 0.0);
+        return;
+    }
+    const int64_t u = perm[i];
+    const cx<double> *xi = x + ((int64_t)r * n + u) * nu;
+    const double nv[3] = {snrm[3 * i], snrm[3 * i + 1], snrm[3 * i + 2]};
+    const cx<double> d = nv[0] * xi[0] + nv[1] * xi[1] + nv[2] * xi[2];
+    for (int q = 0; q < 3; ++q) {
+        cx<double> av, bv;
+        if (ibc) {
+            av = xi[q];
+            bv = cibc * (nv[q] * d - xi[q]);
+        } else if (region == 0) {
+            av = xi[q];
+            bv = -xi[3 + q];
+        } else {
+            av = xi[q] + (nv[q] * tc) * d;
+            bv = -(gamma * xi[3 + q]);
+        }
+        ar[3 * u + q] = av;
+        br[3 * u + q] = bv;
+    }
+}
+
+// E[r][t] = sg * y[r][n + t]
+__global__ void __launch_bounds__(TPB) k_field_take(const cx<double> *__restrict__ y, int64_t n, int64_t nt, double sg,
+                                                    cx<double> *__restrict__ E) {
+    const int r = blockIdx.y;
+    const int64_t t = blockIdx.x * (int64_t)TPB + threadIdx.x;
+    if (t >= nt) return;
+    const cx<double> *yr = y + ((int64_t)r * (n + nt) + n + t) * 3;
+    for (int q = 0; q < 3; ++q) E[((int64_t)r * nt + t) * 3 + q] = sg * yr[q];
+}
+
 // ---- Krylov kernels (vectors of length len per rhs, stride len) ----
 // Vectors are cx<T> (T = double for FP64 solves, float for the inner solves of
 // the mixed mode); inner products, the Hessenberg matrix and the rotations are
@@ -1752,6 +1801,71 @@ int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *point
         kern<<<grid, FE_TILE, 0, s>>>(dt.as<double>(), nt, A.spts.as<double>(), A.snrm.as<double>(), A.sw.as<double>(),
                                       A.perm.as<int32_t>(), (const cx<double> *)x, pb->n, pb->nu, region,
                                       pb->ibc ? 1 : 0, K.k_re, K.k_im, tc, pb->gamma, pb->cibc, (cx<double> *)E);
+        FMB_LAUNCH_CHECK();
+        FMB_CHECK_HIP(hipStreamSynchronize(s));
+    });
+}
+
+int bem_field_fmm(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt, int32_t region,
+                  int32_t order, void *E, void *stream) {
+    return guarded([&] {
+        FMB_REQUIRE(pb && x && points && E, "bad arguments");
+        FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
+        FMB_REQUIRE(nt >= 1, "no target points");
+        FMB_REQUIRE(region == 0 || (region == 1 && !pb->ibc && pb->J == 1),
+                    "region must be 0 (host) or 1 (interior of a one-scatterer dielectric problem)");
+        FMB_REQUIRE(order >= 1 && order <= MAX_ORDER, "order must be in [1, 24]");
+        for (int64_t i = 0; i < 3 * nt; ++i) FMB_REQUIRE(std::isfinite(points[i]), "non-finite target point");
+        hipStream_t s = (hipStream_t)stream;
+        const Plan &A = pb->p0->p;
+        const Plan &K = region == 1 ? pb->p1->p : A;
+        const int64_t n = pb->n, m = n + nt;
+        std::vector<double> sp(3 * n), sn(3 * n), sw(n);
+        std::vector<int32_t> perm(n);
+        FMB_CHECK_HIP(hipMemcpyAsync(sp.data(), A.spts.p, sp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        FMB_CHECK_HIP(hipMemcpyAsync(sn.data(), A.snrm.p, sn.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        FMB_CHECK_HIP(hipMemcpyAsync(sw.data(), A.sw.p, sw.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        FMB_CHECK_HIP(hipMemcpyAsync(perm.data(), A.perm.p, perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        FMB_CHECK_HIP(hipStreamSynchronize(s));
+        // nodes in user order, then the targets (unit normal, unit weight, zero density)
+        std::vector<double> up(3 * m), un(3 * m), uw(m);
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t u = perm[i];
+            for (int q = 0; q < 3; ++q) {
+                up[3 * u + q] = sp[3 * i + q];
+                un[3 * u + q] = sn[3 * i + q];
+            }
+            uw[u] = sw[i];
+        }
+        for (int64_t t = 0; t < nt; ++t) {
+            for (int q = 0; q < 3; ++q) up[3 * (n + t) + q] = points[3 * t + q];
+            un[3 * (n + t)] = un[3 * (n + t) + 1] = 0.0;
+            un[3 * (n + t) + 2] = 1.0;
+            uw[n + t] = 1.0;
+        }
+        fmb_plan_opts o;
+        fmb_plan_opts_default(&o);
+        o.precision = FMB_FP64;
+        o.nrhs_max = nrhs;
+        o.corr_mode = FMB_CORR_NONE;
+        fmb_plan_t fp = nullptr;
+        int rc = fmm_plan(up.data(), un.data(), uw.data(), m, K.k_re, K.k_im, order, &o, stream, &fp);
+        if (rc != FMB_OK) throw Status{rc, std::string("field plan over nodes and targets: ") + fmb_last_error()};
+        std::unique_ptr<fmb_plan_s, int (*)(fmb_plan_t)> own(fp, fmm_plan_destroy);
+        DevBuf da, db, dy;
+        const size_t bytes = (size_t)nrhs * m * 3 * sizeof(cx<double>);
+        da.alloc(bytes);
+        db.alloc(bytes);
+        dy.alloc(bytes);
+        const cx<double> tc = cdiv(mk(1.0, 0.0) - pb->eps, pb->eps);
+        k_field_dens<<<dim3((unsigned)((m + TPB - 1) / TPB), (unsigned)nrhs), TPB, 0, s>>>(
+            A.snrm.as<double>(), A.perm.as<int32_t>(), (const cx<double> *)x, n, nt, pb->nu, region,
+            pb->ibc ? 1 : 0, tc, pb->gamma, pb->cibc, da.as<cx<double>>(), db.as<cx<double>>());
+        FMB_LAUNCH_CHECK();
+        rc = fmm_matvec(fp, da.p, db.p, dy.p, nrhs, stream);
+        if (rc != FMB_OK) throw Status{rc, std::string("field product: ") + fmb_last_error()};
+        k_field_take<<<dim3((unsigned)((nt + TPB - 1) / TPB), (unsigned)nrhs), TPB, 0, s>>>(
+            dy.as<cx<double>>(), n, nt, region == 0 ? -1.0 : 1.0, (cx<double> *)E);
         FMB_LAUNCH_CHECK();
         FMB_CHECK_HIP(hipStreamSynchronize(s));
     });

@@ -121,17 +121,27 @@ class BemProblem:
         check(self._lib.bem_apply_adjoint(self.h, pv, ctypes.c_void_p(out.data_ptr()), nr, _stream()))
         return out
 
-    def field(self, x, points, region="host", far=False, curl=False):
+    def field(self, x, points, region="host", far=False, curl=False, method="direct", order=16):
         """Fields from the solution x [nrhs, n, nu]: the scattered field at host
         points (region "host"), the interior field ("interior"), with far=True
         the far-field amplitude F at unit directions, or with curl=True the curl
         of the scattered field at host points.  points: host array [nt, 3].
+        method "fmm" evaluates the first two by a fast multipole product of the
+        given order over nodes and targets (for many targets).
         Returns complex128 [nrhs, nt, 3] on the GPU."""
         px, nr = self._v(x, "x")
         pts = np.ascontiguousarray(np.atleast_2d(points), dtype=np.float64)
         nt = pts.shape[0]
         out = torch.empty((nr, nt, 3), dtype=torch.complex128, device="cuda")
         reg = {"host": 0, "interior": 1}[region]
+        if method == "fmm":
+            if far or curl:
+                raise ValueError("the FMM evaluation serves the near field and the interior field")
+            check(self._lib.bem_field_fmm(self.h, px, nr, pts.ctypes.data, nt, reg, int(order),
+                                          ctypes.c_void_p(out.data_ptr()), _stream()))
+            return out
+        if method != "direct":
+            raise ValueError("method must be 'direct' or 'fmm'")
         if far and curl:
             raise ValueError("far and curl are exclusive")
         kind = 1 if far else (2 if curl else 0)

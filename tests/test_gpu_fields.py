@@ -179,3 +179,60 @@ def test_optical_force_on_impedance_sphere(gpu):
     assert abs(F[2] - ref) <= 0.05 * ref
     assert np.linalg.norm(F[:2]) <= 0.01 * ref
     pb.close()
+
+
+def test_fmm_field_evaluation_matches_direct_sums(gpu):
+    """bem_field_fmm against the direct sums of bem_field and the oracle: a lossy
+    sphere (3840 nodes, two right-hand sides) on an xoz-plane grid outside
+    (scattered field) and inside (interior field), p = 16 and 22; then the
+    60k-node torus (k0 = 4) on a 20 000-point plane grid, with both timed."""
+    import time
+    q = nystrom3(icosphere(8))
+    n = q["points"].shape[0]
+    eps = 2.25 + 0.5j
+    pb = gpu.BemProblem(q, 1.2, eps, order=12, depth=3, nrhs_max=2)
+    x = complex_normal((2, n, 6), 171)
+    xg = torch.from_numpy(x).cuda()
+    g = np.linspace(-3.0, 3.0, 61)
+    X, Z = np.meshgrid(g + 0.013, g - 0.007, indexing="ij")
+    P = np.stack([X.ravel(), 0.21 + 0.0 * X.ravel(), Z.ravel()], 1)
+    rad = np.linalg.norm(P, axis=1)
+    host, inner = P[rad > 1.1], P[rad < 0.9]
+    for order, tol in ((16, 1e-6), (22, 5e-8)):                # the FP64 product's bounds (7e-7 and 1.3e-8 measured at 16, 22)
+        for pts, reg in ((host, "host"), (inner, "interior")):
+            Ed = pb.field(xg, pts, region=reg).cpu().numpy()
+            Ef = pb.field(xg, pts, region=reg, method="fmm", order=order).cpu().numpy()
+            e = max(_rel(Ef[r], Ed[r]) for r in range(2))
+            print("sphere %s p=%d: %d targets, fmm vs direct %.2e" % (reg, order, len(pts), e), flush=True)
+            assert e <= tol
+    sub = host[::17]
+    Ef = pb.field(xg, sub, method="fmm", order=22).cpu().numpy()
+    for r in range(2):
+        assert _rel(Ef[r], fields.scattered_field(q, 1.2, x[r], sub)) <= 5e-8
+    pb.close()
+
+    from synthetic import config_mesh
+    qt = nystrom3(config_mesh(2))
+    nn = qt["points"].shape[0]
+    pt = gpu.BemProblem(qt, 4.0, -15.0 + 1.0j, order=16, depth=5)
+    xt = torch.from_numpy(complex_normal((1, nn, 6), 172)).cuda()
+    X, Z = np.meshgrid(np.linspace(-1.6, 1.6, 200), np.linspace(-0.8, 0.8, 100), indexing="ij")
+    P = np.stack([X.ravel(), 0.0 * X.ravel() + 0.011, Z.ravel()], 1)
+    d = np.hypot(np.hypot(P[:, 0], P[:, 1]) - 1.0, P[:, 2]) - 0.3
+    P = P[d > 0.03]
+    times = {}
+    for method in ("direct", "fmm", "direct", "fmm"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E = pt.field(xt, P, method=method, order=16)
+        torch.cuda.synchronize()
+        times[method] = time.perf_counter() - t0
+        if method == "direct":
+            Ed = E.cpu().numpy()
+        else:
+            Ef = E.cpu().numpy()
+    e = _rel(Ef[0], Ed[0])
+    print("torus %d nodes, %d targets: direct %.1f ms, fmm %.1f ms, rel %.2e" % (
+        nn, len(P), 1e3 * times["direct"], 1e3 * times["fmm"], e), flush=True)
+    assert e <= 1e-6
+    pt.close()
