@@ -335,6 +335,19 @@ int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *point
               int32_t far, void *E, void *stream);
 
 /*
+ * bem_far_field_adjoint: the conjugate transpose of the far-field map of
+ * bem_field (region 0, far 1), x -> F: given samples G at nd unit directions it
+ * returns xbar = L^H G, so that sum conj(G) . (L x) = sum conj(xbar) . x for
+ * every x.  This is the backward pass of a functional of the far field (e.g.
+ * C_sca = oint |F|^2 dOmega) with respect to the unknowns.  G: device c128
+ * [nrhs][nd][3]; dirs: host f64[nd][3] unit vectors; xbar: device c128
+ * [nrhs][n][nu] (every entry written).  Direct FP64 sums (cost n * nd);
+ * synchronous.
+ */
+int bem_far_field_adjoint(fmb_problem_t pb, const void *G, int32_t nrhs, const double *dirs, int64_t nd, void *xbar,
+                          void *stream);
+
+/*
  * bem_field_fmm: the field of bem_field's kind 0 (region 0: E_sca at host
  * points; region 1: the interior field) by the fast multipole method instead of
  * direct sums, for many targets.  A temporary FP64 plan of the given order is

@@ -55,7 +55,7 @@ class GmresInfo(ctypes.Structure):
 EXPORTS = [
     "fmb_plan_opts_default", "fmm_plan", "fmm_matvec", "fmm_matvec_adjoint", "fmm_plan_info",
     "fmm_plan_export_tree", "fmm_plan_destroy", "fmm_plan_profile", "fmm_plan_profile_read", "fmb_gmres_opts_default", "bem_problem_create", "bem_problem_create_multi", "bem_problem_create_ibc", "bem_problem_use_graphs", "bem_apply", "bem_apply_adjoint",
-    "bem_precond_apply", "bem_rhs_planewave", "bem_field", "bem_field_fmm", "gmres_solve", "gmres_solve_group", "bem_problem_destroy", "fmb_last_error",
+    "bem_precond_apply", "bem_rhs_planewave", "bem_field", "bem_field_fmm", "bem_far_field_adjoint", "gmres_solve", "gmres_solve_group", "bem_problem_destroy", "fmb_last_error",
 ]
 
 _lib = None
@@ -95,6 +95,7 @@ def load():
         "gmres_solve_group": [vp, i32, vp, vp, vp, vp, vp, vp],
         "bem_field": [vp, vp, i32, vp, ctypes.c_int64, i32, i32, vp, vp],
         "bem_field_fmm": [vp, vp, i32, vp, ctypes.c_int64, i32, i32, vp, vp],
+        "bem_far_field_adjoint": [vp, vp, i32, vp, ctypes.c_int64, vp, vp],
         "bem_problem_destroy": [vp],
     }
     for name, args in sig.items():

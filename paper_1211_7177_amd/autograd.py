@@ -7,7 +7,9 @@ grad_x = A^H grad_y, so:
 * `fmm_matvec(plan, a, b)`: backward is `fmm_matvec_adjoint`;
 * `bem_apply(problem, x)`: backward is `bem_apply_adjoint`;
 * `bem_solve(problem, rhs, ...)`: x = A^{-1} rhs, backward solves the adjoint
-  system A^H g = grad_x with the same fGMRES (right-preconditioned by M^{-H}).
+  system A^H g = grad_x with the same fGMRES (right-preconditioned by M^{-H});
+* `far_field(problem, x, dirs)`: F = L x at unit directions, backward is
+  `bem_far_field_adjoint`.
 """
 
 import torch
@@ -50,6 +52,18 @@ class _BemSolve(torch.autograd.Function):
         return g, None, None
 
 
+class _FarField(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, problem, dirs):
+        ctx.problem = problem
+        ctx.dirs = dirs
+        return problem.field(x.contiguous(), dirs, far=True)
+
+    @staticmethod
+    def backward(ctx, gF):
+        return ctx.problem.far_field_adjoint(gF.contiguous(), ctx.dirs), None, None
+
+
 def fmm_matvec(plan, a, b):
     """y = Op_k(a, b), differentiable in a and b."""
     return _FmmMatvec.apply(a, b, plan)
@@ -64,3 +78,9 @@ def bem_solve(problem, rhs, **solve_kw):
     """x = A^{-1} rhs by fGMRES, differentiable in rhs (the backward pass is an
     adjoint solve with the same options)."""
     return _BemSolve.apply(rhs, problem, dict(solve_kw))
+
+
+def far_field(problem, x, dirs):
+    """Far-field amplitudes F [nrhs, nd, 3] at unit directions dirs [nd, 3],
+    differentiable in x."""
+    return _FarField.apply(x, problem, dirs)

@@ -672,6 +672,83 @@ __global__ void __launch_bounds__(FE_TILE) k_field(const double *__restrict__ tg
     for (int q = 0; q < 3; ++q) out[((int64_t)r * nt + t) * 3 + q] = sg * acc[q];
 }
 
+// Conjugate transpose of the far-field map x -> F of k_field<1>.  With
+// F(rhat) = sum_beta c [ M a_beta + b_beta ], c = -w e^{-ik rhat . s} / (4 pi) and
+// M = -ik (n rhat^T - (n . rhat) I - rhat n^T), the adjoint of samples G(rhat) is
+//   a_bar = sum_rhat conj(c) i conj(k) [ rhat (n . G) - (n . rhat) G - n (rhat . G) ],
+//   b_bar = sum_rhat conj(c) G,
+// then Phi_bar = a_bar, Psi_bar = -b_bar (dielectric), or for an impedance
+// problem (b = c_Z (n n^T - I) Phi) Phi_bar = a_bar + conj(c_Z) (n (n . b_bar) - b_bar).
+// One thread per node (sorted index), directions staged through LDS.
+struct FarAdjTile {
+    double dir[FE_TILE][3];
+    cx<double> g[FE_TILE][3];
+};
+
+__global__ void __launch_bounds__(FE_TILE) k_far_adjoint(const double *__restrict__ dirs, int64_t nd,
+                                                         const cx<double> *__restrict__ G,
+                                                         const double *__restrict__ spts,
+                                                         const double *__restrict__ snrm,
+                                                         const double *__restrict__ sw,
+                                                         const int32_t *__restrict__ perm, int64_t n, int nu, int ibc,
+                                                         double k_re, double k_im, cx<double> cibc,
+                                                         cx<double> *__restrict__ xbar) {
+    __shared__ FarAdjTile S;
+    const int r = blockIdx.y;
+    const int64_t i = blockIdx.x * (int64_t)FE_TILE + threadIdx.x;
+    const bool active = i < n;
+    double s[3] = {0, 0, 0}, nv[3] = {0, 0, 0};
+    if (active)
+        for (int q = 0; q < 3; ++q) {
+            s[q] = spts[3 * i + q];
+            nv[q] = snrm[3 * i + q];
+        }
+    cx<double> aa[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+    cx<double> bb[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
+    for (int64_t base = 0; base < nd; base += FE_TILE) {
+        const int cnt = (int)min((int64_t)FE_TILE, nd - base);
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) {
+            const int64_t d = base + threadIdx.x;
+            for (int q = 0; q < 3; ++q) {
+                S.dir[threadIdx.x][q] = dirs[3 * d + q];
+                S.g[threadIdx.x][q] = G[((int64_t)r * nd + d) * 3 + q];
+            }
+        }
+        __syncthreads();
+        if (!active) continue;
+        for (int j = 0; j < cnt; ++j) {
+            const double *u = S.dir[j];
+            const cx<double> *g = S.g[j];
+            const double ph = u[0] * s[0] + u[1] * s[1] + u[2] * s[2];
+            double sn, cs;
+            sincos(k_re * ph, &sn, &cs);
+            const cx<double> ec = exp(k_im * ph) * mk(cs, sn);        // conj(e^{-ik rhat . s})
+            const cx<double> nG = nv[0] * g[0] + nv[1] * g[1] + nv[2] * g[2];
+            const cx<double> uG = u[0] * g[0] + u[1] * g[1] + u[2] * g[2];
+            const double nu_ = nv[0] * u[0] + nv[1] * u[1] + nv[2] * u[2];
+            for (int q = 0; q < 3; ++q) {
+                aa[q] += ec * (u[q] * nG - nu_ * g[q] - nv[q] * uG);
+                bb[q] += ec * g[q];
+            }
+        }
+    }
+    if (!active) return;
+    const double fac = -sw[i] * 0.07957747154594766788;           // -w / (4 pi)
+    const cx<double> ick = mk(k_im, k_re);                          // i conj(k)
+    cx<double> *o = xbar + ((int64_t)r * n + perm[i]) * nu;
+    if (ibc) {
+        const cx<double> nb = nv[0] * bb[0] + nv[1] * bb[1] + nv[2] * bb[2];
+        const cx<double> cz = mk(cibc.re, -cibc.im);
+        for (int q = 0; q < 3; ++q) o[q] = fac * (ick * aa[q] + cz * (nv[q] * nb - bb[q]));
+    } else {
+        for (int q = 0; q < 3; ++q) {
+            o[q] = fac * (ick * aa[q]);
+            o[3 + q] = -(fac * bb[q]);
+        }
+    }
+}
+
 // Densities of the field sum laid out for a plan over the nodes (user order)
 // followed by nt target points, zero at the targets: a = Phi, b = -Psi (host
 // region), a = T Phi, b = -gamma Psi (interior), a = Phi, b = c n x (n x Phi)
@@ -1801,6 +1878,31 @@ int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *point
         kern<<<grid, FE_TILE, 0, s>>>(dt.as<double>(), nt, A.spts.as<double>(), A.snrm.as<double>(), A.sw.as<double>(),
                                       A.perm.as<int32_t>(), (const cx<double> *)x, pb->n, pb->nu, region,
                                       pb->ibc ? 1 : 0, K.k_re, K.k_im, tc, pb->gamma, pb->cibc, (cx<double> *)E);
+        FMB_LAUNCH_CHECK();
+        FMB_CHECK_HIP(hipStreamSynchronize(s));
+    });
+}
+
+int bem_far_field_adjoint(fmb_problem_t pb, const void *G, int32_t nrhs, const double *dirs, int64_t nd, void *xbar,
+                          void *stream) {
+    return guarded([&] {
+        FMB_REQUIRE(pb && G && dirs && xbar, "bad arguments");
+        FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
+        FMB_REQUIRE(nd >= 1, "no directions");
+        for (int64_t i = 0; i < nd; ++i) {
+            const double r2 = dirs[3 * i] * dirs[3 * i] + dirs[3 * i + 1] * dirs[3 * i + 1] + dirs[3 * i + 2] * dirs[3 * i + 2];
+            FMB_REQUIRE(std::isfinite(r2) && std::fabs(r2 - 1.0) <= 1e-9, "directions must be unit vectors");
+        }
+        hipStream_t s = (hipStream_t)stream;
+        const Plan &A = pb->p0->p;
+        DevBuf dd;
+        dd.alloc((size_t)nd * 3 * sizeof(double));
+        FMB_CHECK_HIP(hipMemcpyAsync(dd.p, dirs, (size_t)nd * 3 * sizeof(double), hipMemcpyHostToDevice, s));
+        const dim3 grid((unsigned)((pb->n + FE_TILE - 1) / FE_TILE), (unsigned)nrhs);
+        k_far_adjoint<<<grid, FE_TILE, 0, s>>>(dd.as<double>(), nd, (const cx<double> *)G, A.spts.as<double>(),
+                                               A.snrm.as<double>(), A.sw.as<double>(), A.perm.as<int32_t>(), pb->n,
+                                               pb->nu, pb->ibc ? 1 : 0, A.k_re, A.k_im, pb->cibc,
+                                               (cx<double> *)xbar);
         FMB_LAUNCH_CHECK();
         FMB_CHECK_HIP(hipStreamSynchronize(s));
     });

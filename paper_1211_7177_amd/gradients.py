@@ -1,5 +1,7 @@
 """Scattering cross section and its gradient in the permittivity by the adjoint method.
 
+Two forms of the scattering cross section serve as the functional.  The
+surface form is
 C_sca = (Z0 / |E0|^2) oint Re(E_sca x H_sca^*) . n dA (eq. 4.2) taken over the
 scatterer's own surface, where the unknowns give the scattered fields
 directly: E_sca = Phi - E_inc and n x H_sca = (Psi - Psi_inc) / (i omega mu0),
@@ -7,6 +9,12 @@ with Psi = n x curl E (eq. 2.12).  In the units of this library
 (eps0 = mu0 = 1, omega = k0, Z0 = 1) and with (E x H^*) . n = -E . (n x H^*),
 
     C_sca = -(1/|E0|^2) sum_beta w_beta Re[ E_sca,beta . conj((Psi_beta - Psi_inc,beta) / (i k0)) ].
+
+The far-field form is C_sca = oint |F|^2 dOmega / |E0|^2 with the far-field
+amplitude F = L x of `bem_field`; its gradient in x is L^H (2 w F) / |E0|^2,
+taken by `bem_far_field_adjoint`.  It needs Phi and Psi only through the
+radiating sum, not Psi on its own, and stays accurate where the surface form
+does not (on metals with edges the discrete Psi converges slowly).
 
 For dC/d eps: A(eps) x = b gives dx = -A^{-1} (dA/deps) x deps, so with
 g = grad_x C (torch's convention: dC = Re <g, dx>) and the adjoint solution
@@ -36,6 +44,8 @@ import numpy as np
 import torch
 
 from ._abi import Plan
+from .autograd import far_field
+from .postprocess import sphere_quadrature
 from .solver import BemProblem
 
 
@@ -64,10 +74,35 @@ def scattering_cross_section(nodes, k0, x, d, pol):
     return -torch.sum(w * torch.real(torch.sum(esca * torch.conj(nh), dim=1))) / e0
 
 
+def far_field_cross_section(problem, x, pol, nt=24, nph=48):
+    """C_sca = oint |F|^2 dOmega / |E0|^2 from the far-field amplitudes of the
+    solution x [1, n, nu] (Gauss-Legendre x uniform rule on the unit sphere),
+    as a differentiable torch scalar.  Unlike the surface form of eq. 4.2 it
+    does not use Psi, whose discrete values converge slowly near edges and on
+    metals; it is positive by construction."""
+    if x.dim() == 2:
+        x = x[None]
+    dirs, wts = sphere_quadrature(nt, nph)
+    F = far_field(problem, x, dirs)
+    e0 = float(np.sum(np.abs(np.asarray(pol)) ** 2))
+    w = torch.from_numpy(wts).cuda()
+    return torch.sum(w[None, :, None] * (F.real ** 2 + F.imag ** 2)) / e0
+
+
+def _functional(kind, problem, nodes, k0, x, d, pol):
+    if kind == "surface":
+        return scattering_cross_section(nodes, k0, x, d, pol)
+    if kind == "far":
+        return far_field_cross_section(problem, x, pol)
+    raise ValueError("functional must be 'surface' or 'far'")
+
+
 def cross_section_and_eps_gradient(nodes, k0, eps, d, pol, order=16, depth=0, tol=1e-10, restart=150,
-                                   dk_rel=1e-5, mu=1.0):
+                                   dk_rel=1e-5, mu=1.0, functional="surface"):
     """(C_sca, dC/dRe eps, dC/dIm eps) for one scatterer and one plane wave, by one
-    forward solve, one adjoint solve and three FMM products of the interior plan."""
+    forward solve, one adjoint solve and three FMM products of the interior plan.
+    functional: "surface" (eq. 4.2 on the scatterer's surface) or "far" (the
+    far-field integral of `far_field_cross_section`)."""
     eps = complex(eps)
     pb = BemProblem(nodes, k0, eps, mu=mu, order=order, depth=depth)
     dep = pb.p0.info()["depth"]
@@ -75,7 +110,7 @@ def cross_section_and_eps_gradient(nodes, k0, eps, d, pol, order=16, depth=0, to
     kw = dict(tol=tol, restart=restart, maxit=4000)
     xd, _ = pb.solve(rhs, **kw)
     xg = xd.clone().requires_grad_(True)
-    C = scattering_cross_section(nodes, k0, xg, d, pol)
+    C = _functional(functional, pb, nodes, k0, xg, d, pol)
     g = torch.autograd.grad(C, xg)[0]                              # dC = Re <g, dx>
     lam, _ = pb.solve(g.contiguous(), adjoint=True, **kw)
     # (dA/deps) x: interior rows only
@@ -104,11 +139,12 @@ def cross_section_and_eps_gradient(nodes, k0, eps, d, pol, order=16, depth=0, to
 
 
 def cross_section_and_shape_gradient(nodes_at, nparams, k0, eps, d, pol, order=16, depth=0, tol=1e-10, restart=150,
-                                     h=1e-3, mu=1.0):
+                                     h=1e-3, mu=1.0, functional="surface"):
     """(C_sca, dC/dtheta f64[nparams]) at theta = 0 for the shape family
     nodes_at(theta) (a callable returning the Nystrom nodes of the moved mesh,
     node order unchanged), by one forward and one adjoint solve and, per
-    parameter, two rebuilt problems and products."""
+    parameter, two rebuilt problems and products.  functional as for
+    `cross_section_and_eps_gradient`."""
     eps = complex(eps)
     q0 = nodes_at(np.zeros(nparams))
     pb = BemProblem(q0, k0, eps, mu=mu, order=order, depth=depth)
@@ -116,7 +152,7 @@ def cross_section_and_shape_gradient(nodes_at, nparams, k0, eps, d, pol, order=1
     kw = dict(tol=tol, restart=restart, maxit=4000)
     xd, _ = pb.solve(pb.rhs_planewave(d, pol), **kw)
     xg = xd.clone().requires_grad_(True)
-    C = scattering_cross_section(q0, k0, xg, d, pol)
+    C = _functional(functional, pb, q0, k0, xg, d, pol)
     g = torch.autograd.grad(C, xg)[0]
     lam, _ = pb.solve(g.contiguous(), adjoint=True, **kw)
     pb.close()
@@ -129,7 +165,7 @@ def cross_section_and_shape_gradient(nodes_at, nparams, k0, eps, d, pol, order=1
             q = nodes_at(th)
             p = BemProblem(q, k0, eps, mu=mu, order=order, depth=dep)
             res.append(p.rhs_planewave(d, pol) - p.apply(xd))
-            fun.append(scattering_cross_section(q, k0, xd, d, pol).item())
+            fun.append(_functional(functional, p, q, k0, xd, d, pol).item())
             p.close()
         dr = (res[0] - res[1]) / (2.0 * h)
         grad[i] = (fun[0] - fun[1]) / (2.0 * h) + torch.sum(torch.conj(lam) * dr).real.item()

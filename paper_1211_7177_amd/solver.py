@@ -149,6 +149,22 @@ class BemProblem:
                                   ctypes.c_void_p(out.data_ptr()), _stream()))
         return out
 
+    def far_field_adjoint(self, G, dirs):
+        """x_bar = L^H G for far-field samples G [nrhs, nd, 3] at unit directions
+        dirs [nd, 3], L the map x -> F of field(..., far=True).  Returns
+        complex128 [nrhs, n, nu] on the GPU."""
+        G = G.contiguous()
+        if G.dtype != torch.complex128 or not G.is_cuda or G.dim() != 3:
+            raise ValueError("G must be a complex128 CUDA tensor [nrhs, nd, 3]")
+        d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+        nr, nd = G.shape[0], G.shape[1]
+        if d.shape != (nd, 3):
+            raise ValueError("dirs must be [nd, 3] matching G")
+        out = torch.empty((nr, self.n, self.nu), dtype=torch.complex128, device="cuda")
+        check(self._lib.bem_far_field_adjoint(self.h, ctypes.c_void_p(G.data_ptr()), nr, d.ctypes.data, nd,
+                                              ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
     def precond(self, v):
         out = torch.empty_like(v)
         pv, nr = self._v(v, "v")

@@ -236,3 +236,45 @@ def test_fmm_field_evaluation_matches_direct_sums(gpu):
         nn, len(P), 1e3 * times["direct"], 1e3 * times["fmm"], e), flush=True)
     assert e <= 1e-6
     pt.close()
+
+
+def test_far_field_adjoint_against_oracle_far_field(gpu):
+    """sum conj(G) . F_oracle(x) = sum conj(L^H G) . x with the oracle's far-field
+    sum on one side and the GPU adjoint on the other (dielectric and impedance
+    problems, two right-hand sides), and the autograd gradient of oint |F|^2
+    against a central difference along a random direction."""
+    from paper_1211_7177_amd import autograd as ag
+    q = nystrom3(icosphere(4))
+    n = q["points"].shape[0]
+    D, _ = _sphere_quadrature(12, 24)
+    G = complex_normal((2, D.shape[0], 3), 191)
+    Gg = torch.from_numpy(G).cuda()
+    pb = gpu.BemProblem(q, 1.2, 2.25 + 0.5j, order=12, depth=3, nrhs_max=2)
+    x = complex_normal((2, n, 6), 192)
+    xb = pb.far_field_adjoint(Gg, D).cpu().numpy()
+    for r in range(2):
+        lhs = np.sum(np.conj(G[r]) * fields.far_field(q, 1.2, x[r], D))
+        rhs = np.sum(np.conj(xb[r]) * x[r])
+        assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    xg = torch.from_numpy(x[:1]).cuda().requires_grad_(True)
+    C = torch.sum(torch.abs(ag.far_field(pb, xg, D)) ** 2)
+    g = torch.autograd.grad(C, xg)[0]
+    v = torch.from_numpy(complex_normal((1, n, 6), 193)).cuda()
+    h = 1e-4
+    Cp = torch.sum(torch.abs(pb.field(torch.from_numpy(x[:1]).cuda() + h * v, D, far=True)) ** 2)
+    Cm = torch.sum(torch.abs(pb.field(torch.from_numpy(x[:1]).cuda() - h * v, D, far=True)) ** 2)
+    fd = ((Cp - Cm) / (2 * h)).item()
+    ad = torch.sum(torch.real(torch.conj(g) * v)).item()
+    assert abs(ad - fd) <= 1e-8 * abs(fd)
+    pb.close()
+    Z = 0.2 - 0.1j
+    ib = gpu.IbcProblem(q, 1.2, Z, order=12, depth=3, nrhs_max=2)
+    x3 = complex_normal((2, n, 3), 194)
+    xb = ib.far_field_adjoint(Gg, D).cpu().numpy()
+    nrm = q["normals"]
+    for r in range(2):
+        b = (1j * 1.2 / Z) * (nrm * np.sum(nrm * x3[r], 1, keepdims=True) - x3[r])
+        lhs = np.sum(np.conj(G[r]) * fields.far_field(q, 1.2, np.concatenate([x3[r], -b], 1), D))
+        rhs = np.sum(np.conj(xb[r]) * x3[r])
+        assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    ib.close()
