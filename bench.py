@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--cpu-sample-rows", type=int, default=0,
                     help="target rows of the timed oracle apply (0: all rows, one full BEM application)")
     ap.add_argument("--skip-fp64-solve", action="store_true")
+    ap.add_argument("--skip-adjoint-solve", action="store_true")
     ap.add_argument("--translate32", choices=["fp32", "bf16x3"], default="bf16x3")
     ap.add_argument("--batch", type=int, default=8,
                     help="also time one lockstep solve of this many plane waves (0: skip)")
@@ -225,6 +226,22 @@ def main():
         log("batched", batched)
         pbb.close()
 
+    # adjoint solve A^H lam = b of the same system (the backward pass of a gradient), mixed precision with
+    # the same options, outside the timed region; one untimed solve first
+    adjoint = None
+    if not args.skip_adjoint_solve:
+        kw_adj = dict(tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=args.restart, maxit=2000,
+                      inner_reorth=args.inner_reorth, adjoint=True)
+        pb.solve(rhs, **kw_adj)
+        torch.cuda.synchronize()
+        ta0 = time.perf_counter()
+        _, ia = pb.solve(rhs, **kw_adj)
+        torch.cuda.synchronize()
+        ta = time.perf_counter() - ta0
+        adjoint = {"solves_per_s": 1.0 / ta, "ms_per_solve": 1e3 * ta, "iterations": ia["iterations"],
+                   "refinements": ia["refinements"], "residual": ia["residual"]}
+        log("adjoint solve", adjoint)
+
     # plain FP64 solve (reference path) and matvec rates, outside the timed region
     fp64 = None
     if not args.skip_fp64_solve:
@@ -356,6 +373,7 @@ def main():
         "batched": batched,
         "autotune": tuned,
         "fp64_solve": fp64,
+        "adjoint_solve": adjoint,
         "speedup_vs_fp64_solve": (solves_per_s / fp64["solves_per_s"]) if fp64 else None,
         "fmm_matvecs_per_s": rates,
         "fmm_adjoint_matvecs_per_s": adj_rates,
