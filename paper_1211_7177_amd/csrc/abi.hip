@@ -1,5 +1,6 @@
 // C entry points of the fmbem library: argument validation on the host,
 // device uploads, and dispatch to the plan / matvec steps.
+#include <algorithm>
 #include <cstring>
 
 #include "plan.h"
@@ -77,6 +78,20 @@ int fmm_plan(const double *points, const double *normals, const double *weights,
             double l2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
             FMB_REQUIRE(std::fabs(std::sqrt(l2) - 1.0) <= 1e-6, "normal " + std::to_string(i) + " is not unit length");
             FMB_REQUIRE(std::isfinite(weights[i]) && weights[i] > 0.0, "weights must be finite and positive");
+        }
+        {
+            // coincident points would meet at R = 0 in the near field: refuse them
+            std::vector<int64_t> idx(n);
+            for (int64_t i = 0; i < n; ++i) idx[i] = i;
+            std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+                return std::lexicographical_compare(points + 3 * a, points + 3 * a + 3, points + 3 * b,
+                                                    points + 3 * b + 3);
+            });
+            for (int64_t i = 1; i < n; ++i) {
+                const double *p = points + 3 * idx[i], *q = points + 3 * idx[i - 1];
+                FMB_REQUIRE(!(p[0] == q[0] && p[1] == q[1] && p[2] == q[2]),
+                            "duplicate points " + std::to_string(idx[i - 1]) + " and " + std::to_string(idx[i]));
+            }
         }
         std::vector<int32_t> tri;
         int64_t ntri = 0;

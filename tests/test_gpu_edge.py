@@ -125,3 +125,35 @@ def test_rejected_arguments(abi):
     assert lib.fmm_matvec(P.h, pa, pa, pa, 1, None) == abi.FMB_EINVAL          # y aliases a
     assert lib.fmm_matvec_adjoint(P.h, pa, pa, py, 1, None) == abi.FMB_EINVAL  # a_bar aliases y
     P.close()
+
+
+def test_field_entry_points_reject_bad_arguments(abi):
+    """bem_field with an unknown kind or a far field of the interior, far-field
+    directions that are not unit vectors (also for bem_far_field_adjoint), and an
+    FMM field target that coincides with a node are errors, reported before any
+    kernel reads the arguments; the problem stays usable afterwards."""
+    from paper_1211_7177_amd.solver import BemProblem
+    from synthetic import icosphere
+    q = nystrom3(icosphere(2))
+    n = q["points"].shape[0]
+    pb = BemProblem(q, 1.0, 2.25, order=10, depth=2)
+    x = torch.from_numpy(complex_normal((1, n, 6), 201)).cuda()
+    out = torch.empty((1, 1, 3), dtype=torch.complex128, device="cuda")
+    pts = np.array([[0.0, 0.0, 3.0]])
+    lib = abi.load()
+    import ctypes
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for kind, region in ((3, 0), (-1, 0), (1, 1), (2, 1)):
+        with pytest.raises(abi.FmbError):
+            abi.check(lib.bem_field(pb.h, ctypes.c_void_p(x.data_ptr()), 1, pts.ctypes.data, 1, region, kind,
+                                    ctypes.c_void_p(out.data_ptr()), st))
+    with pytest.raises(abi.FmbError, match="unit"):
+        pb.field(x, np.array([[0.0, 0.0, 2.0]]), far=True)
+    with pytest.raises(abi.FmbError, match="unit"):
+        pb.far_field_adjoint(torch.zeros((1, 1, 3), dtype=torch.complex128, device="cuda"), [[0.0, 0.6, 0.6]])
+    with pytest.raises(abi.FmbError):
+        pb.field(x, q["points"][:2].copy(), method="fmm")
+    E = pb.field(x, pts).cpu().numpy()
+    Ef = pb.field(x, pts, method="fmm", order=20).cpu().numpy()
+    assert np.isfinite(E).all() and _rel(Ef, E) <= 1e-6          # 3.5e-6 at p = 16 for this lone far target
+    pb.close()
