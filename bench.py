@@ -369,7 +369,7 @@ def main():
                    "inner_gram_schmidt": "two passes (DGKS)" if args.inner_reorth else "one classical pass"},
         "solve": {"iterations": last["iterations"], "refinements": last["refinements"],
                   "bem_applies_fp32": last["matvecs32"], "bem_applies_fp64": last["matvecs64"],
-                  "residual": last["residual"]},
+                  "residual": last["residual"], "fp64_fallback": last["fp64_fallback"]},
         "batched": batched,
         "autotune": tuned,
         "fp64_solve": fp64,

@@ -203,6 +203,10 @@ typedef struct {
     int32_t refinements;     /* outer FP64 refinement steps (mixed mode)                     */
     int32_t matvecs64;       /* BEM applies with the FP64 plans                               */
     int32_t matvecs32;       /* BEM applies with the FP32 plans                               */
+    int32_t fp64_fallback;   /* mixed mode: 1 if a refinement step cut the FP64 residual by    */
+                             /*    less than 2x and the solve went on in FP64 fGMRES from the  */
+                             /*    current iterate (the FP32 operator no longer contracts)     */
+    int32_t reserved;
     double residual;         /* final true relative residual |b - A x| / |b| (FP64 operator) */
     double history[256];     /* residual estimate per iteration (first 256)                  */
 } fmb_gmres_info;

@@ -49,7 +49,8 @@ class GmresOpts(ctypes.Structure):
 
 class GmresInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("refinements", ctypes.c_int32), ("matvecs64", ctypes.c_int32),
-                ("matvecs32", ctypes.c_int32), ("residual", ctypes.c_double), ("history", ctypes.c_double * 256)]
+                ("matvecs32", ctypes.c_int32), ("fp64_fallback", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("residual", ctypes.c_double), ("history", ctypes.c_double * 256)]
 
 
 EXPORTS = [

@@ -1535,6 +1535,7 @@ static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs,
     cx<double> *X = (cx<double> *)x;
     std::vector<double> relres, hist;
     int mv64 = 0, mv32 = 0, its = 0, refinements = 0;
+    bool fallback = false;
     double final_res = 0.0;
     Krylov<double> K;
     if (!op.mixed) {
@@ -1562,6 +1563,7 @@ static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs,
             FMB_CHECK_HIP(hipMemcpyAsync(rr.p, b, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
         }
         std::vector<double> bn(nrhs), rn(nrhs);
+        double prev_res = 0.0;
         norms(K, b, K.hn.as<double>(), nullptr, s);
         FMB_CHECK_HIP(hipMemcpyAsync(bn.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
         while (true) {
@@ -1575,6 +1577,13 @@ static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs,
             }
             hist.push_back(final_res);
             if (final_res <= op.tol || its >= op.maxit || refinements >= 50) break;
+            // a step that cut the residual by less than 2x: the FP32 operator (or its inner solve) no
+            // longer contracts the FP64 residual, so go on in FP64 from the current iterate
+            if (refinements >= 1 && final_res > 0.5 * prev_res) {
+                fallback = true;
+                break;
+            }
+            prev_res = final_res;
             std::vector<double> inner;
             // the last refinements only need to close the gap to tol: loosen the inner tolerance to
             // a fraction of tol/|r| when that is looser than the configured one
@@ -1590,6 +1599,14 @@ static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs,
             FMB_LAUNCH_CHECK();
             ++refinements;
         }
+        if (fallback) {
+            krylov_alloc(K, len, nrhs, op.restart);
+            std::vector<double> rel;
+            its += fgmres<double>(*pb, K, b, X, true, op.tol, std::max(1, op.maxit - its), op.precond, true, rel,
+                                  &hist, mv64, s);
+            final_res = 0.0;
+            for (double v : rel) final_res = std::max(final_res, v);
+        }
     }
     if (info) {
         std::memset(info, 0, sizeof(*info));
@@ -1597,6 +1614,7 @@ static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs,
         info->refinements = refinements;
         info->matvecs64 = mv64;
         info->matvecs32 = mv32;
+        info->fp64_fallback = fallback ? 1 : 0;
         info->residual = final_res;
         for (size_t i = 0; i < hist.size() && i < 256; ++i) info->history[i] = hist[i];
     }

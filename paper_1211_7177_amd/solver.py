@@ -28,7 +28,8 @@ def _opts(lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, seri
 
 def _info_dict(info, code):
     return {"iterations": info.iterations, "refinements": info.refinements, "matvecs64": info.matvecs64,
-            "matvecs32": info.matvecs32, "residual": info.residual, "code": code,
+            "matvecs32": info.matvecs32, "fp64_fallback": bool(info.fp64_fallback), "residual": info.residual,
+            "code": code,
             "history": list(info.history[:min(256, max(info.iterations, info.refinements + 1))])}
 
 

@@ -140,3 +140,27 @@ def test_split_ring_far_field_gradients_match_differences(ring):
         fd = (v[0] - v[1]) / (2 * hs)
         print("far shape parameter %d: adjoint %.8e differences %.8e" % (i, gs[i], fd), flush=True)
         assert abs(gs[i] - fd) <= 1e-4 * abs(fd)
+
+
+def test_full_split_ring_mixed_solve_falls_back_to_fp64():
+    """The full split ring (35,600 triangles, 106,800 nodes): its FP32 p = 5 plans
+    do not contract the FP64 residual (14 refinements stalled at 4.3e-5 without the
+    safeguard), so the mixed solve detects a step that cuts the residual by less
+    than 2x and continues in FP64 fGMRES from its iterate.  It reaches 1e-8 and
+    agrees with the plain FP64 solve; a long restart (400) avoids the stagnation
+    that restart 150 shows on this mesh (2053 FP64 iterations against 300)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1211_7177_amd.solver import BemProblem
+    from synthetic import config_mesh
+    q = nystrom3(config_mesh(4))
+    pb = BemProblem(q, K0, EPS, order=16, order32=5, translate32="bf16x3")
+    b = pb.rhs_planewave(D, POL)
+    xm, im = pb.solve(b, tol=1e-8, mixed=True, inner_tol=5e-3, restart=400, maxit=4000)
+    x6, i6 = pb.solve(b, tol=1e-8, restart=400, maxit=3000)
+    e = (torch.linalg.vector_norm(xm - x6) / torch.linalg.vector_norm(x6)).item()
+    print("mixed: %d iterations, %d refinements, fallback %s, residual %.2e; fp64: %d iterations; diff %.2e" % (
+        im["iterations"], im["refinements"], im["fp64_fallback"], im["residual"], i6["iterations"], e), flush=True)
+    assert im["fp64_fallback"] and im["residual"] <= 1e-8 and i6["residual"] <= 1e-8
+    assert e <= 1e-6
+    pb.close()
