@@ -184,7 +184,10 @@ typedef struct {
     int32_t maxit;       /* total iteration cap                                              */
     int32_t precond;     /* 0 none, 1 block A_self (6x6 per node)                            */
     int32_t x0_given;    /* 1: x holds the initial guess on entry                            */
-    int32_t mixed;       /* 1: FP32 inner solves refined by FP64 residuals (needs FP32 plans)*/
+    int32_t mixed;       /* 1: FP32 inner solves refined by FP64 residuals (needs FP32 plans);*/
+                         /* 2: nested: FP64 fGMRES preconditioned by one FP32 fGMRES cycle   */
+                         /*    of up to min(restart, inner_maxit) steps to inner_tol per     */
+                         /*    outer step (for systems whose conditioning stops refinement)  */
     double inner_tol;    /* relative tolerance of each inner FP32 solve (mixed mode)         */
     int32_t inner_maxit; /* iteration cap of each inner solve                                */
     int32_t serial;      /* 1: the k0 and k1 FMM products of each application run one after  */
@@ -199,13 +202,15 @@ typedef struct {
 } fmb_gmres_opts;
 
 typedef struct {
-    int32_t iterations;      /* Krylov iterations (all inner iterations in mixed mode)       */
-    int32_t refinements;     /* outer FP64 refinement steps (mixed mode)                     */
+    int32_t iterations;      /* Krylov iterations (all inner iterations in mixed mode; outer  */
+                             /*    plus inner in nested mode)                                 */
+    int32_t refinements;     /* outer FP64 refinement steps (mixed mode), outer FP64 fGMRES  */
+                             /*    steps (nested mode)                                        */
     int32_t matvecs64;       /* BEM applies with the FP64 plans                               */
     int32_t matvecs32;       /* BEM applies with the FP32 plans                               */
     int32_t fp64_fallback;   /* mixed mode: 1 if a refinement step cut the FP64 residual by    */
-                             /*    less than 2x and the solve went on in FP64 fGMRES from the  */
-                             /*    current iterate (the FP32 operator no longer contracts)     */
+                             /*    less than 2x and the solve went on in nested mode from the  */
+                             /*    current iterate (inner cycles of at most 100 steps)         */
     int32_t reserved;
     double residual;         /* final true relative residual |b - A x| / |b| (FP64 operator) */
     double history[256];     /* residual estimate per iteration (first 256)                  */

@@ -31,6 +31,7 @@
 #include <cstring>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "plan.h"
@@ -190,6 +191,19 @@ __global__ void k_bem_combine(const cx<T> *__restrict__ x, const double *__restr
 __global__ void k_to32(const cx<double> *__restrict__ in, cx<float> *__restrict__ out, int64_t m) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < m) out[i] = mk((float)in[i].re, (float)in[i].im);
+}
+
+// out = in for active right-hand sides, 0 for retired ones (FP64 -> FP32)
+__global__ void k_to32_active(const cx<double> *__restrict__ in, cx<float> *__restrict__ out, int64_t len, int nrhs,
+                              const int32_t *__restrict__ act) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= len * nrhs) return;
+    out[i] = act[i / len] ? mk((float)in[i].re, (float)in[i].im) : mk(0.f, 0.f);
+}
+
+__global__ void k_to64(const cx<float> *__restrict__ in, cx<double> *__restrict__ out, int64_t m) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < m) out[i] = mk((double)in[i].re, (double)in[i].im);
 }
 
 // x += d (FP32 correction into the FP64 iterate)
@@ -1366,10 +1380,24 @@ static void precond_t(fmb_problem_s &pb, const cx<T> *v, cx<T> *z, int nrhs, hip
 // the FP64 operator (T = double) or the FP32 one (T = float).  Returns the
 // iteration count; relres receives |b - A x| / |b| per rhs (computed with the
 // operator the solve used).
+// Nested mode: the preconditioner of an FP64 fGMRES is one cycle of FP32 fGMRES
+// (block-preconditioned when precond is set) on A32 z = v_j, to a relative
+// tolerance; flexible GMRES keeps every z_j, so the inexact inner solves enter
+// the FP64 minimisation and need not contract on their own.
+struct InnerSolve {
+    Krylov<float> *K;
+    cx<float> *r32, *d32;
+    double tol;
+    int maxit;
+    bool reorth;
+    int its;
+    int *matvecs;
+};
+
 template <typename T>
 static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, bool x_nonzero, double tol, int maxit,
                   int precond, bool reorth, std::vector<double> &relres, std::vector<double> *hist, int &matvecs,
-                  hipStream_t s) {
+                  hipStream_t s, InnerSolve *inner = nullptr) {
     const int nrhs = K.nrhs, m = K.m;
     const int64_t len = K.len, tot = len * nrhs;
     cx<T> *V = K.V.template as<cx<T>>(), *Z = K.Z.template as<cx<T>>(), *W = K.W.template as<cx<T>>();
@@ -1423,7 +1451,20 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
         // After the last step of a solve one masked step may have run.
         auto enqueue = [&](int j) {
             cx<T> *vj = V + (int64_t)j * tot, *zj = Z + (int64_t)j * tot;
-            if (precond) {
+            if constexpr (std::is_same<T, double>::value) {
+                if (inner) {
+                    k_to32_active<<<gridn(tot), TPB, 0, s>>>(vj, inner->r32, len, nrhs, actd);
+                    FMB_LAUNCH_CHECK();
+                    std::vector<double> rel;
+                    inner->its += fgmres<float>(pb, *inner->K, inner->r32, inner->d32, false, inner->tol, inner->maxit,
+                                                precond, inner->reorth, rel, nullptr, *inner->matvecs, s);
+                    k_to64<<<gridn(tot), TPB, 0, s>>>(inner->d32, zj, tot);
+                    FMB_LAUNCH_CHECK();
+                    bem_apply_t<T>(pb, zj, W, nrhs, s);
+                }
+            }
+            if (inner) {
+            } else if (precond) {
                 bem_apply_t<T>(pb, zj, W, nrhs, s, vj);      // z_j = M^{-1} v_j fused with the split
             } else {
                 FMB_CHECK_HIP(hipMemcpyAsync(zj, vj, tot * sizeof(cx<T>), hipMemcpyDeviceToDevice, s));
@@ -1514,7 +1555,25 @@ static void check_solve_args(fmb_problem_s *pb, const void *rhs, const void *x, 
     FMB_REQUIRE(pb && rhs && x && rhs != x, "bad arguments");
     FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
     FMB_REQUIRE(op.tol > 0 && op.restart >= 1 && op.maxit >= 1, "bad solver options");
+    FMB_REQUIRE(op.mixed >= 0 && op.mixed <= 2, "mixed must be 0, 1 or 2");
     FMB_REQUIRE(!op.mixed || pb->p032, "mixed precision needs the FP32 plans");
+}
+
+// FP64 fGMRES on the FP64 plans (basis op.restart), each step preconditioned by
+// one FP32 fGMRES cycle of at most `inner` steps to op.inner_tol; returns the
+// outer steps and adds outer plus inner steps to its.
+static int nested_fgmres(fmb_problem_s *pb, Krylov<double> &K, Krylov<float> &K32, cx<float> *r32, cx<float> *d32,
+                         const cx<double> *b, cx<double> *X, int nrhs, bool x0, int inner, int maxit,
+                         const fmb_gmres_opts &op, std::vector<double> &relres, std::vector<double> &hist, int &its,
+                         int &mv64, int &mv32, hipStream_t s) {
+    const int64_t len = pb->n * pb->nu;
+    const int mi = std::max(1, inner);
+    krylov_alloc(K, len, nrhs, op.restart);
+    krylov_alloc(K32, len, nrhs, mi);
+    InnerSolve in{&K32, r32, d32, op.inner_tol, mi, op.inner_reorth != 0, 0, &mv32};
+    const int outer = fgmres<double>(*pb, K, b, X, x0, op.tol, maxit, op.precond, true, relres, &hist, mv64, s, &in);
+    its += outer + in.its;
+    return outer;
 }
 
 // One complete solve on stream s; returns whether the tolerance was reached.
@@ -1542,6 +1601,16 @@ static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs,
         krylov_alloc(K, len, nrhs, op.restart);
         its = fgmres<double>(*pb, K, b, X, op.x0_given != 0, op.tol, op.maxit, op.precond, true, relres, &hist, mv64,
                              s);
+        for (double v : relres) final_res = std::max(final_res, v);
+    } else if (op.mixed == 2) {
+        // nested: FP64 fGMRES whose preconditioner is one FP32 fGMRES cycle
+        Krylov<float> K32;
+        DevBuf r32, d32;
+        r32.alloc(tot * sizeof(cx<float>));
+        d32.alloc(tot * sizeof(cx<float>));
+        refinements = nested_fgmres(pb, K, K32, r32.as<cx<float>>(), d32.as<cx<float>>(), b, X, nrhs,
+                                    op.x0_given != 0, std::min(op.restart, op.inner_maxit), op.maxit, op, relres, hist,
+                                    its, mv64, mv32, s);
         for (double v : relres) final_res = std::max(final_res, v);
     } else {
         // iterative refinement: FP64 residuals r = b - A64 x, inner fGMRES on
@@ -1578,7 +1647,7 @@ static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs,
             hist.push_back(final_res);
             if (final_res <= op.tol || its >= op.maxit || refinements >= 50) break;
             // a step that cut the residual by less than 2x: the FP32 operator (or its inner solve) no
-            // longer contracts the FP64 residual, so go on in FP64 from the current iterate
+            // longer contracts the FP64 residual, so go on in nested mode from the current iterate
             if (refinements >= 1 && final_res > 0.5 * prev_res) {
                 fallback = true;
                 break;
@@ -1600,10 +1669,11 @@ static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs,
             ++refinements;
         }
         if (fallback) {
-            krylov_alloc(K, len, nrhs, op.restart);
+            // go on from X in nested mode, with inner cycles of at most 100 steps
             std::vector<double> rel;
-            its += fgmres<double>(*pb, K, b, X, true, op.tol, std::max(1, op.maxit - its), op.precond, true, rel,
-                                  &hist, mv64, s);
+            nested_fgmres(pb, K, K32, r32.as<cx<float>>(), d32.as<cx<float>>(), b, X, nrhs, true,
+                          std::min({op.restart, op.inner_maxit, 100}), std::max(1, op.maxit - its), op, rel, hist, its,
+                          mv64, mv32, s);
             final_res = 0.0;
             for (double v : rel) final_res = std::max(final_res, v);
         }

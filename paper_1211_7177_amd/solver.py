@@ -17,7 +17,7 @@ def _opts(lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, seri
     opts.restart = restart
     opts.maxit = maxit
     opts.precond = 1 if precond else 0
-    opts.mixed = 1 if mixed else 0
+    opts.mixed = 2 if mixed == "nested" else (1 if mixed else 0)
     opts.inner_tol = inner_tol
     opts.inner_maxit = inner_maxit
     opts.serial = 1 if serial else 0
@@ -183,7 +183,9 @@ class BemProblem:
 
     def solve(self, rhs, tol=1e-6, restart=100, maxit=1000, precond=True, mixed=False, inner_tol=1e-3,
               inner_maxit=300, x0=None, raise_on_noconv=True, serial=False, adjoint=False, inner_reorth=False):
-        """Solve A x = rhs (or A^H x = rhs with adjoint=True) with fGMRES."""
+        """Solve A x = rhs (or A^H x = rhs with adjoint=True) with fGMRES.
+        mixed: False (FP64), True (FP32 inner solves inside FP64 refinement) or
+        "nested" (FP64 fGMRES preconditioned by one FP32 fGMRES cycle per step)."""
         opts = _opts(self._lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, serial, adjoint,
                      inner_reorth)
         x = torch.zeros_like(rhs) if x0 is None else x0.clone()

@@ -93,6 +93,28 @@ def test_mixed_precision_refinement_reaches_fp64_tolerance(gpu, small, inner_reo
     pb.close()
 
 
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_nested_mode_reaches_fp64_tolerance(gpu, small, nrhs):
+    """Nested mode (FP64 fGMRES preconditioned by FP32 fGMRES cycles) reaches the
+    FP64 tolerance, and its answer solves the oracle's system; with three waves
+    the columns retire at different steps and still match single solves."""
+    q, ob = small
+    pb = gpu.BemProblem(q, 1.0, 2.25, order=20, depth=3, order32=10, nrhs_max=3)
+    d = np.array([[0, 0, 1.0], [0.6, 0, 0.8], [0, 1.0, 0]])
+    pol = np.array([[1.0, 0, 0], [0, 1.0, 0], [0, 0, 1.0]])
+    b = pb.rhs_planewave(d[:nrhs], pol[:nrhs])
+    x, info = pb.solve(b, tol=1e-9, mixed="nested", inner_tol=1e-2, inner_maxit=30)
+    print("nested", nrhs, info["iterations"], info["refinements"], info["residual"], flush=True)
+    assert info["residual"] <= 1e-9 and not info["fp64_fallback"]
+    for r in range(nrhs):
+        xn, bn = x.cpu().numpy()[r], b.cpu().numpy()[r]
+        assert np.linalg.norm(bn - ob.apply(xn)) / np.linalg.norm(bn) <= 1e-6
+        if nrhs > 1:
+            x1, _ = pb.solve(b[r:r + 1].contiguous(), tol=1e-9, mixed="nested", inner_tol=1e-2, inner_maxit=30)
+            assert (torch.linalg.vector_norm(x1[0] - x[r]) / torch.linalg.vector_norm(x1[0])).item() <= 1e-7
+    pb.close()
+
+
 def test_batched_rhs_solve_equals_single(gpu, small):
     q, ob = small
     pb = gpu.BemProblem(q, 1.0, 2.25, order=14, depth=3, nrhs_max=3)

@@ -142,13 +142,14 @@ def test_split_ring_far_field_gradients_match_differences(ring):
         assert abs(gs[i] - fd) <= 1e-4 * abs(fd)
 
 
-def test_full_split_ring_mixed_solve_falls_back_to_fp64():
+def test_full_split_ring_mixed_and_nested_solves():
     """The full split ring (35,600 triangles, 106,800 nodes): its FP32 p = 5 plans
     do not contract the FP64 residual (14 refinements stalled at 4.3e-5 without the
     safeguard), so the mixed solve detects a step that cuts the residual by less
-    than 2x and continues in FP64 fGMRES from its iterate.  It reaches 1e-8 and
-    agrees with the plain FP64 solve; a long restart (400) avoids the stagnation
-    that restart 150 shows on this mesh (2053 FP64 iterations against 300)."""
+    than 2x and continues in nested mode from its iterate.  Nested mode from the
+    start needs no such switch.  Both reach 1e-8 and agree with the plain FP64
+    solve; a long restart (400) avoids the stagnation that restart 150 shows on
+    this mesh (2053 FP64 iterations against 300)."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1211_7177_amd.solver import BemProblem
@@ -156,11 +157,22 @@ def test_full_split_ring_mixed_solve_falls_back_to_fp64():
     q = nystrom3(config_mesh(4))
     pb = BemProblem(q, K0, EPS, order=16, order32=5, translate32="bf16x3")
     b = pb.rhs_planewave(D, POL)
-    xm, im = pb.solve(b, tol=1e-8, mixed=True, inner_tol=5e-3, restart=400, maxit=4000)
-    x6, i6 = pb.solve(b, tol=1e-8, restart=400, maxit=3000)
-    e = (torch.linalg.vector_norm(xm - x6) / torch.linalg.vector_norm(x6)).item()
-    print("mixed: %d iterations, %d refinements, fallback %s, residual %.2e; fp64: %d iterations; diff %.2e" % (
-        im["iterations"], im["refinements"], im["fp64_fallback"], im["residual"], i6["iterations"], e), flush=True)
-    assert im["fp64_fallback"] and im["residual"] <= 1e-8 and i6["residual"] <= 1e-8
-    assert e <= 1e-6
+    import time
+    res = {}
+    for name, kw in (("fp64", dict(maxit=3000)), ("mixed", dict(mixed=True, inner_tol=5e-3, maxit=4000)),
+                     ("nested", dict(mixed="nested", inner_tol=1e-2, inner_maxit=100, maxit=4000))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = pb.solve(b, tol=1e-8, restart=400, **kw)
+        torch.cuda.synchronize()
+        res[name] = (x, info, time.perf_counter() - t0)
+        print("%s: %.2f s, %d iterations, %d outer/refinements, fallback %s, residual %.2e" % (
+            name, res[name][2], info["iterations"], info["refinements"], info["fp64_fallback"], info["residual"]),
+            flush=True)
+        assert info["residual"] <= 1e-8
+    x6 = res["fp64"][0]
+    assert res["mixed"][1]["fp64_fallback"] and not res["nested"][1]["fp64_fallback"]
+    for name in ("mixed", "nested"):
+        e = (torch.linalg.vector_norm(res[name][0] - x6) / torch.linalg.vector_norm(x6)).item()
+        assert e <= 1e-6, (name, e)
     pb.close()
