@@ -73,18 +73,23 @@ def tune_matvec(nodes, k, tol, depths=(0,), orders=(4, 5, 6, 8), translates=("fp
 
 
 def tune_solve(nodes, k0, eps, rhs_dir, rhs_pol, tol=1e-6, orders32=(4, 5, 6), translates=("bf16x3", "fp32"),
-               inner_tols=(5e-3,), order64=16, depth=0, restart=150, reps=1):
+               inner_tols=(5e-3,), order64=16, depth=0, restart=150, reps=1, modes=("refine",)):
     """Fastest mixed-precision solve configuration reaching the residual `tol`.
+    modes: "refine" (FP32 inner solves inside FP64 refinement) and/or "nested"
+    (FP64 fGMRES preconditioned by FP32 fGMRES cycles of at most 100 steps).
 
-    Returns (best, table): each row holds order32, translate, inner_tol,
+    Returns (best, table): each row holds mode, order32, translate, inner_tol,
     s (seconds per solve, the mean of `reps` solves after one untimed solve),
-    iterations, refinements, residual, ok."""
+    iterations, refinements, fallback, residual, ok."""
     table = []
     for order32, tr in itertools.product(orders32, translates):
         pb = BemProblem(nodes, k0, eps, order=order64, depth=depth, order32=order32, translate32=tr)
         rhs = pb.rhs_planewave(rhs_dir, rhs_pol)
-        for itol in inner_tols:
+        for mode, itol in itertools.product(modes, inner_tols):
             def run():
+                if mode == "nested":
+                    return pb.solve(rhs, tol=tol, mixed="nested", inner_tol=itol, inner_maxit=100, restart=restart,
+                                    maxit=3000, raise_on_noconv=False)
                 return pb.solve(rhs, tol=tol, mixed=True, inner_tol=itol, restart=restart, maxit=3000,
                                 raise_on_noconv=False)
             run()
@@ -94,9 +99,10 @@ def tune_solve(nodes, k0, eps, rhs_dir, rhs_pol, tol=1e-6, orders32=(4, 5, 6), t
                 _, info = run()
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / reps
-            table.append({"order32": order32, "translate": tr, "inner_tol": itol, "s": dt,
+            table.append({"mode": mode, "order32": order32, "translate": tr, "inner_tol": itol, "s": dt,
                           "iterations": info["iterations"], "refinements": info["refinements"],
-                          "residual": info["residual"], "ok": info["residual"] <= tol})
+                          "fallback": info["fp64_fallback"], "residual": info["residual"],
+                          "ok": info["residual"] <= tol})
         pb.close()
     ok = [r for r in table if r["ok"]]
     best = min(ok, key=lambda r: r["s"]) if ok else None

@@ -61,9 +61,10 @@ def test_tune_solve_reaches_tolerance(tune, sphere):
     print("tune_solve sphere 3840 nodes", flush=True)
     best, table = tune.tune_solve(sphere, 1.0, 2.25, [0.0, 0.0, 1.0], [1.0, 0.0, 0.0], tol=1e-8,
                                   orders32=(5, 8), translates=("fp32",), inner_tols=(1e-3, 1e-2), order64=20,
-                                  depth=3)
+                                  depth=3, modes=("refine", "nested"))
     for r in table:
         print(r)
-    assert len(table) == 4 and best is not None
+    assert len(table) == 8 and best is not None
+    assert all(r["ok"] for r in table if r["mode"] == "nested")
     assert best["residual"] <= 1e-8
     assert best["s"] == min(r["s"] for r in table if r["ok"])
