@@ -98,16 +98,18 @@ def _functional(kind, problem, nodes, k0, x, d, pol):
 
 
 def cross_section_and_eps_gradient(nodes, k0, eps, d, pol, order=16, depth=0, tol=1e-10, restart=150,
-                                   dk_rel=1e-5, mu=1.0, functional="surface"):
+                                   dk_rel=1e-5, mu=1.0, functional="surface", order32=None, solve_kw=None):
     """(C_sca, dC/dRe eps, dC/dIm eps) for one scatterer and one plane wave, by one
     forward solve, one adjoint solve and three FMM products of the interior plan.
     functional: "surface" (eq. 4.2 on the scatterer's surface) or "far" (the
-    far-field integral of `far_field_cross_section`)."""
+    far-field integral of `far_field_cross_section`).  order32 builds FP32 plans
+    too, for solve_kw such as {"mixed": "nested"} (extra options of both solves)."""
     eps = complex(eps)
-    pb = BemProblem(nodes, k0, eps, mu=mu, order=order, depth=depth)
+    pb = BemProblem(nodes, k0, eps, mu=mu, order=order, depth=depth, order32=order32)
     dep = pb.p0.info()["depth"]
     rhs = pb.rhs_planewave(d, pol)
     kw = dict(tol=tol, restart=restart, maxit=4000)
+    kw.update(solve_kw or {})
     xd, _ = pb.solve(rhs, **kw)
     xg = xd.clone().requires_grad_(True)
     C = _functional(functional, pb, nodes, k0, xg, d, pol)
