@@ -62,7 +62,8 @@ __global__ void __launch_bounds__(64) k_adj_l2p(const int32_t *__restrict__ star
                                                 const double *__restrict__ spts, int64_t n, int p, double k_re,
                                                 double k_im, const double *__restrict__ inv_alpha,
                                                 const T *__restrict__ tab, const int32_t *__restrict__ gix,
-                                                int nrhs_max, const cx<T> *__restrict__ Lc, cx<T> *__restrict__ out) {
+                                                const int32_t *__restrict__ gath, int nrhs_max,
+                                                const cx<T> *__restrict__ Lc, cx<T> *__restrict__ out) {
     extern __shared__ unsigned char smem[];
     const int P2 = p * p, N = p, NN = (N + 1) * (N + 1), NS = NN + 1;
     const BasisTab<T> bt = basis_tab(tab, gix, N, P2);
@@ -73,44 +74,41 @@ __global__ void __launch_bounds__(64) k_adj_l2p(const int32_t *__restrict__ star
     const cx<T> k = mk((T)k_re, (T)k_im);
     const double X[3] = {center[3 * box], center[3 * box + 1], center[3 * box + 2]};
     const cx<T> *Lb = Lc + ((int64_t)box * nrhs_max + r) * 3 * P2;
+    const int32_t *gptr = gath, *gent = gath + NN + 1;
     for (int c = 0; c < 3; ++c) {
         __syncthreads();                                // the previous channel's evaluation is done
-        for (int t = threadIdx.x; t < 4 * NS; t += blockDim.x) D[t] = mk(T(0), T(0));
-        __syncthreads();
-        for (int t = threadIdx.x; t < P2; t += blockDim.x) {
-            int nn = 0;
-            while ((nn + 1) * (nn + 1) <= t) ++nn;
-            D[t] = (T)inv_alpha[nn] * Lb[c * P2 + t];
+        for (int t = threadIdx.x; t < NS; t += blockDim.x) {
+            cx<T> v = mk(T(0), T(0));
+            if (t < P2) {
+                int nn = 0;
+                while ((nn + 1) * (nn + 1) <= t) ++nn;
+                v = (T)inv_alpha[nn] * Lb[c * P2 + t];
+            }
+            D[t] = v;
         }
         __syncthreads();
-        if (threadIdx.x < 3) {
-            const int q = threadIdx.x;
-            cx<T> *Dq = D + (1 + q) * NS;
-            for (int idx = 0; idx < P2; ++idx) {
-                int nn = 0;
-                while ((nn + 1) * (nn + 1) <= idx) ++nn;
-                const int m = idx - nn * nn - nn;
-                const int row = nn * nn + nn - m;
-                const T *co = bt.gco + (int64_t)row * 6;
-                const int32_t *ix = bt.gix + (int64_t)row * 7;
-                const cx<T> l = k * D[idx];
-                if (q == 0) {                           // d_x = (d_+ + d_-) / 2
-                    const cx<T> h = T(0.5) * l;
-                    Dq[ix[2]] += co[2] * h;
-                    Dq[ix[3]] += co[3] * h;
-                    Dq[ix[4]] += co[4] * h;
-                    Dq[ix[5]] += co[5] * h;
-                } else if (q == 1) {                    // d_y = (d_+ - d_-) / 2i
-                    const cx<T> h = mk(T(0.5) * l.im, T(-0.5) * l.re);
-                    Dq[ix[2]] += co[2] * h;
-                    Dq[ix[3]] += co[3] * h;
-                    Dq[ix[4]] -= co[4] * h;
-                    Dq[ix[5]] -= co[5] * h;
-                } else {                                // d_z
-                    Dq[ix[0]] += co[0] * l;
-                    Dq[ix[1]] += co[1] * l;
+        // D_x, D_y, D_z: every R-table entry o gathers the gradient terms that land on it, in increasing
+        // source index (the terms of coefficient idx: slots 0-1 d_z, 2-3 d_+, 4-5 d_- of its gradient row)
+        for (int o = threadIdx.x; o < NS; o += blockDim.x) {
+            cx<T> ax = mk(T(0), T(0)), ay = mk(T(0), T(0)), az = mk(T(0), T(0));
+            if (o < NN)
+                for (int e = gptr[o]; e < gptr[o + 1]; ++e) {
+                    const int pk = gent[e];
+                    const int idx = pk & 2047, row = (pk >> 11) & 2047, slot = pk >> 22;
+                    const T co = bt.gco[(int64_t)row * 6 + slot];
+                    const cx<T> l = k * D[idx];
+                    if (slot < 2) {
+                        az += co * l;                   // d_z
+                    } else {
+                        ax += co * (T(0.5) * l);        // d_x = (d_+ + d_-) / 2
+                        const cx<T> h = mk(T(0.5) * l.im, T(-0.5) * l.re);
+                        if (slot < 4) ay += co * h;     // d_y = (d_+ - d_-) / 2i
+                        else ay -= co * h;
+                    }
                 }
-            }
+            D[NS + o] = ax;
+            D[2 * NS + o] = ay;
+            D[3 * NS + o] = az;
         }
         __syncthreads();
         for (int i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
@@ -351,8 +349,8 @@ void l2p_t(Plan &P, int nrhs, hipStream_t s) {
     const size_t sh = l2p_lds(P, threads);
     k_adj_l2p<T><<<dim3((unsigned)LL.nbox, (unsigned)nrhs), threads, sh, s>>>(
         LL.start.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(), P.n, P.order, P.k_re, P.k_im,
-        P.inv_alpha.as<double>() + (size_t)P.depth * P.order, P.btab.as<T>(), P.bgix.as<int32_t>(), P.nrhs_max,
-        LL.L.as<cx<T>>(), P.aws.as<cx<T>>());
+        P.inv_alpha.as<double>() + (size_t)P.depth * P.order, P.btab.as<T>(), P.bgix.as<int32_t>(),
+        P.agath.as<int32_t>(), P.nrhs_max, LL.L.as<cx<T>>(), P.aws.as<cx<T>>());
     FMB_LAUNCH_CHECK();
 }
 
@@ -383,6 +381,34 @@ void adjoint_prepare(Plan &P) {
     const size_t cs = P.precision == FMB_FP64 ? sizeof(cx<double>) : sizeof(cx<float>);
     const size_t need = (size_t)P.nrhs_max * P.n * 12 * cs;
     if (P.aws.bytes < need) P.aws.alloc(need);
+    if (!P.agath.p) {
+        // invert the gradient table: for every R-table entry o < (N+1)^2, the (source coefficient, its
+        // gradient row, slot) triples whose term lands on o, in increasing source coefficient
+        const int N = P.order, NN = (N + 1) * (N + 1), P2 = N * N;
+        std::vector<int32_t> gix((size_t)7 * P2);
+        FMB_CHECK_HIP(hipMemcpy(gix.data(), P.bgix.p, gix.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        std::vector<int32_t> ptr(NN + 1, 0), pos, ent;
+        std::vector<std::pair<int32_t, int32_t>> raw;
+        for (int idx = 0; idx < P2; ++idx) {
+            int nn = 0;
+            while ((nn + 1) * (nn + 1) <= idx) ++nn;
+            const int m = idx - nn * nn - nn, row = nn * nn + nn - m;
+            for (int slot = 0; slot < 6; ++slot) {
+                const int o = gix[(size_t)7 * row + slot];
+                if (o < 0 || o >= NN) continue;               // the zero entry (N+1)^2
+                raw.push_back({o, idx | (row << 11) | (slot << 22)});
+                ++ptr[o + 1];
+            }
+        }
+        for (int o = 0; o < NN; ++o) ptr[o + 1] += ptr[o];
+        pos.assign(ptr.begin(), ptr.end() - 1);
+        ent.resize(raw.size());
+        for (const auto &e : raw) ent[pos[e.first]++] = e.second;
+        std::vector<int32_t> buf(ptr);
+        buf.insert(buf.end(), ent.begin(), ent.end());
+        P.agath.alloc(buf.size() * sizeof(int32_t));
+        FMB_CHECK_HIP(hipMemcpy(P.agath.p, buf.data(), buf.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
 }
 
 void adjoint_gather(Plan &P, const void *y, int nrhs, hipStream_t s) {

@@ -98,6 +98,7 @@ struct Plan {
     DevBuf ys;        // [nrhs_max][n][3] complex, Morton order
     DevBuf ybuf;      // GEMM output slots, largest level
     DevBuf aws;       // adjoint: [nrhs_max][n][12] potentials and gradients per channel, Morton order (on first use)
+    DevBuf agath;     // adjoint: per R-table entry, the gradient terms that land on it (on first use)
     StageTimer timer;
     size_t device_bytes() const;
 };
