@@ -163,13 +163,14 @@ __global__ void __launch_bounds__(64) k_adj_l2p(const int32_t *__restrict__ star
 // slices of the sources, summed in LDS at the end in a fixed order.
 template <typename T>
 struct AdjTile {
-    double pos[ATPB][3];
+    T pos[ATPB][3];                 // relative to the target leaf's centre
     int32_t tri[ATPB];
     cx<T> q[ATPB][3];
 };
 
 template <typename T>
 __global__ void __launch_bounds__(ATPB) k_adj_p2p(const int32_t *__restrict__ start, const int32_t *__restrict__ nbr,
+                                                  const double *__restrict__ center,
                                                   const double *__restrict__ spts, const int32_t *__restrict__ stri,
                                                   const cx<T> *__restrict__ src, int64_t n, double k_re, double k_im,
                                                   cx<T> *__restrict__ out) {
@@ -196,6 +197,8 @@ __global__ void __launch_bounds__(ATPB) k_adj_p2p(const int32_t *__restrict__ st
     }
     __syncthreads();
     const int ns_total = nb_start[n_nb];
+    // coordinates relative to this leaf's centre: the differences of near pairs in T keep full precision
+    const double C[3] = {center[3 * box], center[3 * box + 1], center[3 * box + 2]};
     const T kr = (T)k_re, ki = (T)k_im;
     const T inv4pi = T(0.07957747154594766788);
     for (int tc0 = 0; tc0 < nt; tc0 += ATPB) {
@@ -204,10 +207,10 @@ __global__ void __launch_bounds__(ATPB) k_adj_p2p(const int32_t *__restrict__ st
         const int ti = threadIdx.x % ntc, sl = threadIdx.x / ntc;
         const bool active = sl < S;
         const int64_t ig = t0 + tc0 + ti;
-        double tp[3] = {0, 0, 0};
+        T tp[3] = {0, 0, 0};
         int32_t ttri = -1;
         if (active) {
-            for (int q = 0; q < 3; ++q) tp[q] = spts[3 * ig + q];
+            for (int q = 0; q < 3; ++q) tp[q] = (T)(spts[3 * ig + q] - C[q]);
             ttri = stri[ig];
         }
         cx<T> acc[12];
@@ -220,7 +223,7 @@ __global__ void __launch_bounds__(ATPB) k_adj_p2p(const int32_t *__restrict__ st
                 int b = 0;
                 while (nb_start[b + 1] <= u) ++b;
                 const int64_t sidx = start[nb_box[b]] + (u - nb_start[b]);
-                for (int q = 0; q < 3; ++q) tile.pos[j][q] = spts[3 * sidx + q];
+                for (int q = 0; q < 3; ++q) tile.pos[j][q] = (T)(spts[3 * sidx + q] - C[q]);
                 tile.tri[j] = stri[sidx];
                 const cx<T> *sr = src + ((int64_t)r * n + sidx) * 7;
                 for (int q = 0; q < 3; ++q) tile.q[j][q] = sr[3 + q];
@@ -229,8 +232,7 @@ __global__ void __launch_bounds__(ATPB) k_adj_p2p(const int32_t *__restrict__ st
             if (!active) continue;
             for (int j = sl; j < cnt; j += S) {
                 if (tile.tri[j] == ttri) continue;
-                const T dx = (T)(tp[0] - tile.pos[j][0]), dy = (T)(tp[1] - tile.pos[j][1]),
-                        dz = (T)(tp[2] - tile.pos[j][2]);
+                const T dx = tp[0] - tile.pos[j][0], dy = tp[1] - tile.pos[j][1], dz = tp[2] - tile.pos[j][2];
                 const T R2 = dx * dx + dy * dy + dz * dz;
                 const T iR = fast_rsqrt(R2);
                 const T R = R2 * iR;
@@ -358,7 +360,8 @@ template <typename T>
 void p2p_t(Plan &P, int nrhs, hipStream_t s) {
     const Level &LL = P.lv[P.depth];
     k_adj_p2p<T><<<dim3((unsigned)LL.nbox, (unsigned)nrhs), ATPB, 0, s>>>(
-        LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), P.spts.as<double>(), P.stri.as<int32_t>(), P.src.as<cx<T>>(),
+        LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(),
+        P.stri.as<int32_t>(), P.src.as<cx<T>>(),
         P.n, P.k_re, P.k_im, P.aws.as<cx<T>>());
     FMB_LAUNCH_CHECK();
 }
