@@ -44,6 +44,8 @@ def parse():
                     help="target rows of the timed oracle apply (0: all rows, one full BEM application)")
     ap.add_argument("--skip-fp64-solve", action="store_true")
     ap.add_argument("--skip-adjoint-solve", action="store_true")
+    ap.add_argument("--skip-split-ring", action="store_true",
+                    help="skip the split-ring solves and product rates reported beside the main workload")
     ap.add_argument("--translate32", choices=["fp32", "bf16x3"], default="bf16x3")
     ap.add_argument("--batch", type=int, default=8,
                     help="also time one lockstep solve of this many plane waves (0: skip)")
@@ -119,6 +121,53 @@ def measured_traffic(kernel):
         return float(meta["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def split_ring_section(log):
+    """The split-ring workload (square ring, side 1, width 0.2, thickness 0.1, gap 0.2; eps = -15 + 1i,
+    k0 = pi/2, wave along +z polarised across the gap): a nested solve, a plain FP64 solve and a nested adjoint
+    solve to 1e-8 (restart 400), and the forward and adjoint FMM product rates of its k0 plans.  Runs after the
+    timed solves of the main workload, outside their timed region."""
+    import torch
+    from synthetic import config_mesh, nystrom3
+    from paper_1211_7177_amd.solver import BemProblem
+    mesh = config_mesh(4)
+    q = nystrom3(mesh)
+    n = q["points"].shape[0]
+    pb = BemProblem(q, np.pi / 2, complex(-15.0, 1.0), order=16, order32=5, translate32="bf16x3")
+    b = pb.rhs_planewave([0.0, 0.0, 1.0], [0.0, 1.0, 0.0])
+    nested = dict(mixed="nested", inner_tol=1e-2, inner_maxit=100)
+    out = {"workload": "split_ring_%dtri_%dnodes_eps-15+1i_k0pi/2" % (len(mesh.triangles), n),
+           "depth": pb.p0.info()["depth"], "tol": 1e-8, "restart": 400}
+    for name, kw in (("nested_solve", nested), ("fp64_solve", {}), ("nested_adjoint_solve", dict(nested, adjoint=True))):
+        pb.solve(b, tol=1e-2, restart=400, maxit=4000, raise_on_noconv=False, **kw)      # allocations
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = pb.solve(b, tol=1e-8, restart=400, maxit=4000, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"s": dt, "iterations": info["iterations"], "outer": info["refinements"],
+                     "residual": info["residual"]}
+        log("split ring", name, out[name])
+    out["speedup_nested_vs_fp64"] = out["fp64_solve"]["s"] / out["nested_solve"]["s"]
+    rates = {}
+    for tag, plan, cdt in (("fp64", pb.p0, torch.complex128), ("fp32", pb.p0_32, torch.complex64)):
+        a = torch.randn(1, n, 3, dtype=cdt, device="cuda")
+        y = plan.matvec(a, a)
+        plan.matvec_adjoint(y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            plan.matvec(a, a, out=y)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(10):
+            plan.matvec_adjoint(y)
+        torch.cuda.synchronize()
+        rates[tag] = {"matvecs_per_s": 10 / (t1 - t0), "adjoint_matvecs_per_s": 10 / (time.perf_counter() - t1)}
+    out["fmm_k0_plan"] = rates
+    pb.close()
+    return out
 
 
 def main():
@@ -331,6 +380,8 @@ def main():
         log("copy calibration: 256 MiB device-to-device copy done", buf2.numel())
     log("roofline", stages_rf)
 
+    ring = None if args.skip_split_ring else split_ring_section(log)
+
     # accuracy against the oracle: FP64 direct-sum residual of the GPU solutions on sampled rows
     acc = None
     if not args.no_cpu_baseline:
@@ -374,6 +425,7 @@ def main():
         "autotune": tuned,
         "fp64_solve": fp64,
         "adjoint_solve": adjoint,
+        "split_ring": ring,
         "speedup_vs_fp64_solve": (solves_per_s / fp64["solves_per_s"]) if fp64 else None,
         "fmm_matvecs_per_s": rates,
         "fmm_adjoint_matvecs_per_s": adj_rates,
