@@ -21,7 +21,7 @@ namespace fmb {
 namespace {
 
 constexpr int GTPB = 256;
-constexpr int ATPB = 128;       // near-field block: targets on lanes, source slices on spare lanes
+constexpr int ATPB = 256;       // near-field block: targets on lanes, source slices on spare lanes (256: 8% faster than 128 in FP32)
 
 inline unsigned grid_for(int64_t m, int tpb) { return (unsigned)((m + tpb - 1) / tpb); }
 
