@@ -50,3 +50,17 @@ def test_mie_far_field_gives_mie_coefficients_and_cross_sections():
         cext = pp.extinction_from_forward(_mie_far(eps, np.array([[0.0, 0.0, 1.0]]))[0], [1.0, 0, 0], 1.0)
         assert abs(csca - qsca * np.pi) <= 1e-3 * qsca * np.pi
         assert abs(cext - qext * np.pi) <= 1e-3 * qext * np.pi
+
+
+def test_stress_tensor_force_of_mie_fields():
+    """The package's stress-tensor integral of the Mie total fields on the sphere
+    r = 2a equals Q_pr pi a^2 / 2 (B&H eq. 4.74) and the oracle's own integral of
+    the same samples (two implementations written apart)."""
+    from oracle import fields as of
+    dirs, wts = pp.sphere_quadrature(32, 64)
+    for eps in (2.25, 2.25 + 0.5j):
+        E, C = mie.fields(2.0 * dirs, 1.0, 1.0, eps, "outside")
+        F = pp.stress_tensor_force(E, C, 1.0, dirs, 4.0 * wts)
+        ref = mie.radiation_pressure(1.0, np.sqrt(eps)) * np.pi / 2.0
+        assert abs(F[2] - ref) <= 1e-9 * ref and np.abs(F[:2]).max() <= 1e-12
+        assert np.abs(F - of.stress_force(E, C, 1.0, dirs, 4.0 * wts)).max() <= 1e-13 * ref
