@@ -62,3 +62,16 @@ def test_host_validation_without_gpu():
     assert lib.fmm_matvec_adjoint(None, None, None, None, 1, None) == _abi.FMB_EINVAL
     assert b"plan" in lib.fmb_last_error()
     assert lib.gmres_solve_group(None, 1, None, None, None, None, None, None) == _abi.FMB_EINVAL
+    pts3 = pts.copy()
+    pts3[7] = pts3[2]
+    r = lib.fmm_plan(pts3.ctypes.data, nrm.ctypes.data, w.ctypes.data, 10, 1.0, 0.0, 8, None, None, ctypes.byref(h))
+    assert r == _abi.FMB_EINVAL and b"duplicate points 2 and 7" in lib.fmb_last_error()
+
+
+def test_solver_option_mapping():
+    """The Python solve options reach the C struct: mixed False/True/"nested" as 0/1/2."""
+    from paper_1211_7177_amd import _abi, solver
+    lib = _abi.load()
+    for mixed, code in ((False, 0), (True, 1), ("nested", 2)):
+        o = solver._opts(lib, 1e-6, 50, 100, True, mixed, 1e-2, 30, False)
+        assert o.mixed == code and o.restart == 50 and o.inner_maxit == 30 and o.precond == 1
