@@ -209,8 +209,9 @@ typedef struct {
     int32_t matvecs64;       /* BEM applies with the FP64 plans                               */
     int32_t matvecs32;       /* BEM applies with the FP32 plans                               */
     int32_t fp64_fallback;   /* mixed mode: 1 if a refinement step cut the FP64 residual by    */
-                             /*    less than 2x and the solve went on in nested mode from the  */
-                             /*    current iterate (inner cycles of at most 100 steps)         */
+                             /*    less than 2x, or by less than 1/20 of the reduction its     */
+                             /*    inner tolerance asked for, and the solve went on in nested  */
+                             /*    mode from the current iterate (inner cycles <= 100 steps)   */
     int32_t reserved;
     double residual;         /* final true relative residual |b - A x| / |b| (FP64 operator) */
     double history[256];     /* residual estimate per iteration (first 256)                  */

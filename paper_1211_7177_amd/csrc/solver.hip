@@ -1632,7 +1632,7 @@ static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs,
             FMB_CHECK_HIP(hipMemcpyAsync(rr.p, b, tot * sizeof(cx<double>), hipMemcpyDeviceToDevice, s));
         }
         std::vector<double> bn(nrhs), rn(nrhs);
-        double prev_res = 0.0;
+        double prev_res = 0.0, prev_itol = 0.5;
         norms(K, b, K.hn.as<double>(), nullptr, s);
         FMB_CHECK_HIP(hipMemcpyAsync(bn.data(), K.hn.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
         while (true) {
@@ -1646,9 +1646,10 @@ static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs,
             }
             hist.push_back(final_res);
             if (final_res <= op.tol || its >= op.maxit || refinements >= 50) break;
-            // a step that cut the residual by less than 2x: the FP32 operator (or its inner solve) no
-            // longer contracts the FP64 residual, so go on in nested mode from the current iterate
-            if (refinements >= 1 && final_res > 0.5 * prev_res) {
+            // a step that cut the residual by less than 2x, or by less than 1/20 of what its inner
+            // tolerance asked for: the FP32 operator (or its inner solve) no longer contracts the FP64
+            // residual, so go on in nested mode from the current iterate
+            if (refinements >= 1 && final_res > std::min(0.5, 20.0 * prev_itol) * prev_res) {
                 fallback = true;
                 break;
             }
@@ -1657,6 +1658,7 @@ static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs,
             // the last refinements only need to close the gap to tol: loosen the inner tolerance to
             // a fraction of tol/|r| when that is looser than the configured one
             const double itol = std::min(0.5, std::max(op.inner_tol, 0.3 * op.tol / std::max(final_res, 1e-300)));
+            prev_itol = itol;
             k_to32<<<gridn(tot), TPB, 0, s>>>(rr.as<cx<double>>(), r32.as<cx<float>>(), tot);
             FMB_LAUNCH_CHECK();
             its += fgmres<float>(*pb, K32, r32.as<cx<float>>(), d32.as<cx<float>>(), false, itol,
