@@ -44,6 +44,8 @@ def parse():
                     help="target rows of the timed oracle apply (0: all rows, one full BEM application)")
     ap.add_argument("--skip-fp64-solve", action="store_true")
     ap.add_argument("--skip-adjoint-solve", action="store_true")
+    ap.add_argument("--three-meshes", action="store_true",
+                    help="also solve the batched three-mesh workload (ellipsoid, torus, sphere at full size)")
     ap.add_argument("--skip-split-ring", action="store_true",
                     help="skip the split-ring solves and product rates reported beside the main workload")
     ap.add_argument("--translate32", choices=["fp32", "bf16x3"], default="bf16x3")
@@ -167,6 +169,46 @@ def split_ring_section(log):
         rates[tag] = {"matvecs_per_s": 10 / (t1 - t0), "adjoint_matvecs_per_s": 10 / (time.perf_counter() - t1)}
     out["fmm_k0_plan"] = rates
     pb.close()
+    return out
+
+
+def three_meshes_section(log, nrhs=2, rows=400):
+    """The batched workload of three uneven meshes (ellipsoid 24k nodes at k0 = 2, torus 90k at k0 = 5,
+    eps -15 + 1i, sphere 246k at k0 = 10), nrhs plane waves each, solved in one `gmres_solve_group` call to 1e-6
+    in nested mode and in plain FP64 (restart 300), with the oracle's direct-sum residual of each mesh's first
+    solution on sampled rows."""
+    import torch
+    from synthetic import CONFIGS, config_mesh, nystrom3, plane_waves, seed_for
+    from paper_1211_7177_amd.solver import BemProblem, solve_group
+    pbs, rhs, meshes = [], [], []
+    for cfg in (31, 32, 33):
+        c = CONFIGS[cfg]
+        q = nystrom3(config_mesh(cfg))
+        pb = BemProblem(q, c["k0"], c["eps"], order=16, order32=5, translate32="bf16x3", nrhs_max=nrhs)
+        d, pol = plane_waves(nrhs, seed_for(cfg, "dirs"), seed_for(cfg, "pols"))
+        pbs.append(pb)
+        rhs.append(pb.rhs_planewave(d, pol))
+        meshes.append({"name": c["name"], "nodes": q["points"].shape[0], "k0": c["k0"], "eps": str(c["eps"]),
+                       "depth": pb.p0.info()["depth"], "q": q})
+    out = {"nrhs_per_mesh": nrhs, "tol": 1e-6, "restart": 300}
+    for name, kw in (("nested", dict(mixed="nested", inner_tol=1e-2, inner_maxit=100)), ("fp64", {})):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, infos = solve_group(pbs, rhs, tol=1e-6, restart=300, maxit=4000, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = []
+        for m, x, b, info, pb in zip(meshes, xs, rhs, infos, pbs):
+            res.append({"iterations": info["iterations"], "outer": info["refinements"], "residual": info["residual"],
+                        "oracle_residual_rows": oracle_residual_rows(m["q"], float(np.real(pb.k0)), pb.eps,
+                                                                     x[0].cpu().numpy(), b[0].cpu().numpy(),
+                                                                     rows)})
+        out[name] = {"s": dt, "rhs_solves_per_s": 3 * nrhs / dt, "meshes": res}
+        log("three meshes", name, out[name])
+    out["meshes"] = [{k: v for k, v in m.items() if k != "q"} for m in meshes]
+    out["speedup_nested_vs_fp64"] = out["fp64"]["s"] / out["nested"]["s"]
+    for pb in pbs:
+        pb.close()
     return out
 
 
@@ -381,6 +423,7 @@ def main():
     log("roofline", stages_rf)
 
     ring = None if args.skip_split_ring else split_ring_section(log)
+    three = three_meshes_section(log) if args.three_meshes else None
 
     # accuracy against the oracle: FP64 direct-sum residual of the GPU solutions on sampled rows
     acc = None
@@ -426,6 +469,7 @@ def main():
         "fp64_solve": fp64,
         "adjoint_solve": adjoint,
         "split_ring": ring,
+        "three_meshes": three,
         "speedup_vs_fp64_solve": (solves_per_s / fp64["solves_per_s"]) if fp64 else None,
         "fmm_matvecs_per_s": rates,
         "fmm_adjoint_matvecs_per_s": adj_rates,
