@@ -180,11 +180,13 @@ def test_graph_replays_equal_eager(gpu, small):
     pb.close()
 
 
-def test_group_solve_uneven_meshes_equals_separate_solves(gpu):
+@pytest.mark.parametrize("mixed", [True, "nested"])
+def test_group_solve_uneven_meshes_equals_separate_solves(gpu, mixed):
     """Three meshes of uneven size, wavenumber and permittivity (an ellipsoid,
     a lossy torus, a sphere) with 2, 1 and 3 plane waves, solved by one
-    gmres_solve_group call: each answer is bit-identical to that problem's own
-    gmres_solve, and solves the oracle's system."""
+    gmres_solve_group call (refinement or nested mode): each answer is
+    bit-identical to that problem's own gmres_solve, and solves the oracle's
+    system."""
     from synthetic import geodesic_ellipsoid, torus
     meshes = [(nystrom3(geodesic_ellipsoid((1.5, 1.0, 0.75), 4)), 1.2, 2.25, 2),
               (nystrom3(torus(1.0, 0.3, 24, 8)), 1.0, -15 + 1j, 1),
@@ -200,9 +202,11 @@ def test_group_solve_uneven_meshes_equals_separate_solves(gpu):
         p /= np.linalg.norm(p, axis=1, keepdims=True)
         pbs.append(pb)
         rhs.append(pb.rhs_planewave(d, p))
-    xs, infos = gpu.solve_group(pbs, rhs, tol=1e-8, mixed=True, inner_tol=1e-3)
+    kw = dict(tol=1e-8, mixed=mixed, inner_tol=1e-3 if mixed is True else 1e-2,
+              inner_maxit=300 if mixed is True else 40)
+    xs, infos = gpu.solve_group(pbs, rhs, **kw)
     for i, (pb, b) in enumerate(zip(pbs, rhs)):
-        x1, i1 = pb.solve(b, tol=1e-8, mixed=True, inner_tol=1e-3)
+        x1, i1 = pb.solve(b, **kw)
         print("member", i, infos[i]["iterations"], i1["iterations"], infos[i]["residual"], flush=True)
         assert infos[i]["residual"] <= 1e-8
         assert infos[i]["iterations"] == i1["iterations"]
