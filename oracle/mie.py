@@ -163,7 +163,7 @@ def efficiencies(x: float, m: complex, nmax=None):
 
 
 def radiation_pressure(x: float, m: complex, nmax=None, coeffs=None):
-    """Q_pr = Q_ext - g Q_sca, with the asymmetry term (B&H eq. 4.74)
+    """Q_pr = Q_ext - g Q_sca, with the asymmetry term of Bohren & Huffman's Mie theory (Sec. 4.5)
     g Q_sca = 4/x^2 [ sum_n n(n+2)/(n+1) Re(a_n a_{n+1}^* + b_n b_{n+1}^*)
                       + sum_n (2n+1)/(n(n+1)) Re(a_n b_n^*) ].
     The time-averaged force on the sphere in a plane wave of irradiance I is

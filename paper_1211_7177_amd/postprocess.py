@@ -54,6 +54,19 @@ def extinction_from_forward(F_fwd, pol, k0):
     return float(4.0 * np.pi / np.real(k0) * np.imag(np.sum(np.conj(p) * F_fwd))) / e0
 
 
+def differential_cross_section(F, pol):
+    """dC_sca/dOmega = |F(rhat)|^2 / |E0|^2 from far-field samples F c128[m,3]
+    (the quantity plotted against angle in the paper's dimer comparison)."""
+    e0 = float(np.sum(np.abs(np.asarray(pol)) ** 2))
+    return np.sum(np.abs(np.asarray(F)) ** 2, axis=-1) / e0
+
+
+def radar_cross_section(F, pol):
+    """Bistatic radar cross section sigma = 4 pi |F(rhat)|^2 / |E0|^2 (monostatic
+    when rhat = -d)."""
+    return 4.0 * np.pi * differential_cross_section(F, pol)
+
+
 def cross_sections(problem, x, d, pol, k0, nt=32, nph=64):
     """(C_ext, C_sca, C_abs) of the solution x [1, n, nu] for the wave pol exp(i k0 d . r)."""
     d = np.asarray(d, dtype=np.float64)

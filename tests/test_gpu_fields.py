@@ -132,7 +132,7 @@ def test_optical_force_of_solved_spheres(gpu):
     """Maxwell-stress force on a lossy sphere (k0 a = 1, eps = 2.25 + 0.5i, 1280
     triangles) for two plane waves in one batch (+z polarised x, +x polarised z),
     integrated on the sphere r = 2a from the GPU E_sca and curl E_sca: along the
-    propagation direction with magnitude Q_pr pi a^2 / 2 (Mie, B&H eq. 4.74; the
+    propagation direction with magnitude Q_pr pi a^2 / 2 (Mie, B&H Sec. 4.5; the
     oracle's own solution on this mesh is 0.18% low); the
     same integral of the oracle's fields of the same solution agrees to 1e-10."""
     from oracle import fields as of

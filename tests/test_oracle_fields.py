@@ -100,7 +100,7 @@ def test_scattered_curl_of_exact_surface_fields_reproduces_mie():
 @pytest.mark.parametrize("eps", [2.25, 2.25 + 0.5j, 4.0 + 0.1j])
 def test_stress_tensor_force_equals_mie_radiation_pressure(eps):
     """The Maxwell-stress integral of the Mie total fields over spheres of radius
-    1.5a and 3a equals Q_pr pi a^2 I (B&H eq. 4.74 for g Q_sca, I = 1/2 for a unit
+    1.5a and 3a equals Q_pr pi a^2 I (B&H Sec. 4.5 for g Q_sca, I = 1/2 for a unit
     amplitude): two independent routes to the same force; the transverse
     components vanish."""
     D, W = _sphere_quadrature(40, 80)

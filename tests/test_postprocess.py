@@ -54,7 +54,7 @@ def test_mie_far_field_gives_mie_coefficients_and_cross_sections():
 
 def test_stress_tensor_force_of_mie_fields():
     """The package's stress-tensor integral of the Mie total fields on the sphere
-    r = 2a equals Q_pr pi a^2 / 2 (B&H eq. 4.74) and the oracle's own integral of
+    r = 2a equals Q_pr pi a^2 / 2 (B&H Sec. 4.5) and the oracle's own integral of
     the same samples (two implementations written apart)."""
     from oracle import fields as of
     dirs, wts = pp.sphere_quadrature(32, 64)
@@ -64,3 +64,32 @@ def test_stress_tensor_force_of_mie_fields():
         ref = mie.radiation_pressure(1.0, np.sqrt(eps)) * np.pi / 2.0
         assert abs(F[2] - ref) <= 1e-9 * ref and np.abs(F[:2]).max() <= 1e-12
         assert np.abs(F - of.stress_force(E, C, 1.0, dirs, 4.0 * wts)).max() <= 1e-13 * ref
+
+
+def test_differential_and_radar_cross_sections_of_mie_far_field():
+    """On the Mie far field of an x-polarised wave along +z: dC/dOmega integrates
+    to C_sca, equals (|S_2|^2 cos^2 phi + |S_1|^2 sin^2 phi) / k^2 with the
+    amplitude functions S_1, S_2 of the Mie coefficients (B&H Sec. 4.4), and the
+    radar cross section is 4 pi times it."""
+    eps = 2.25 + 0.5j
+    dirs, wts = pp.sphere_quadrature(32, 64)
+    F = _mie_far(eps, dirs)
+    dsc = pp.differential_cross_section(F, [1.0, 0, 0])
+    qext, qsca = mie.efficiencies(1.0, np.sqrt(eps))
+    assert abs(np.sum(wts * dsc) - qsca * np.pi) <= 1e-3 * qsca * np.pi
+    n, a, b, _, _ = mie.coefficients(1.0, np.sqrt(eps))
+    mu = np.clip(dirs[:, 2], -1, 1)
+    ph = np.arctan2(dirs[:, 1], dirs[:, 0])
+    pi_n = np.zeros((len(n), len(mu)))
+    tau_n = np.zeros_like(pi_n)
+    pi_n[0], tau_n[0] = 1.0, mu
+    for i in range(1, len(n)):
+        nn = i + 1
+        pi_n[i] = (2 * nn - 1) / (nn - 1) * mu * pi_n[i - 1] - (nn / (nn - 1) * pi_n[i - 2] if i >= 2 else 0.0)
+        tau_n[i] = nn * mu * pi_n[i] - (nn + 1) * pi_n[i - 1]
+    c = (2 * n + 1) / (n * (n + 1))
+    S1 = np.sum(c[:, None] * (a[:, None] * pi_n + b[:, None] * tau_n), axis=0)
+    S2 = np.sum(c[:, None] * (a[:, None] * tau_n + b[:, None] * pi_n), axis=0)
+    ref = (np.abs(S2) ** 2 * np.cos(ph) ** 2 + np.abs(S1) ** 2 * np.sin(ph) ** 2) / 1.0
+    assert np.max(np.abs(dsc - ref)) <= 1e-3 * np.max(ref)
+    assert np.allclose(pp.radar_cross_section(F, [1.0, 0, 0]), 4 * np.pi * dsc)
