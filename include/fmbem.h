@@ -297,10 +297,15 @@ int bem_rhs_planewave(fmb_problem_t pb, const double *dirs, const double *pols, 
 
 /*
  * gmres_solve: right-preconditioned flexible GMRES (Sec. 3.1, eq. 3.1) on
- * A x = rhs for each of nrhs right-hand sides.  rhs, x device c128
- * [nrhs][n][6].  Synchronous.  Returns FMB_ENOCONV (x holds the last
- * iterate, info filled) when maxit is reached.  info may be NULL; with
- * nrhs > 1 it describes the slowest right-hand side.
+ * A x = rhs (or A^H x = rhs with o->adjoint) for each of nrhs right-hand
+ * sides.  rhs, x device c128 [nrhs][n][nu] (nu = 6, or 3 for an impedance
+ * problem).  o->mixed selects the precision path: 0 FP64 throughout; 1 FP32
+ * inner solves inside FP64 iterative refinement, which switches to nested
+ * mode when a step stops contracting; 2 nested (FP64 fGMRES whose
+ * preconditioner is one FP32 fGMRES cycle).  The residual that stops the
+ * solve is always the FP64 one.  Synchronous.  Returns FMB_ENOCONV (x holds
+ * the last iterate, info filled) when maxit is reached.  info may be NULL;
+ * with nrhs > 1 it describes the slowest right-hand side.
  */
 int gmres_solve(fmb_problem_t pb, const void *rhs, void *x, int32_t nrhs, const fmb_gmres_opts *o,
                 fmb_gmres_info *info, void *stream);
