@@ -46,7 +46,7 @@ import torch
 from ._abi import Plan
 from .autograd import far_field
 from .postprocess import sphere_quadrature
-from .solver import BemProblem
+from .solver import BemProblem, MultiBemProblem, _nodes_of
 
 
 def _incident(nodes, k0, d, pol, dtype=torch.complex128):
@@ -172,3 +172,52 @@ def cross_section_and_shape_gradient(nodes_at, nparams, k0, eps, d, pol, order=1
         dr = (res[0] - res[1]) / (2.0 * h)
         grad[i] = (fun[0] - fun[1]) / (2.0 * h) + torch.sum(torch.conj(lam) * dr).real.item()
     return C.item(), grad
+
+
+def cross_section_and_eps_gradients_multi(nodes, region, k0, eps, d, pol, order=16, depth=0, depths=None, tol=1e-10,
+                                          restart=150, dk_rel=1e-5, mu=None, functional="far", order32=None,
+                                          solve_kw=None):
+    """(C_sca, g) for J scatterers (region[alpha] = j) under one plane wave,
+    g[j] = (dC/dRe eps_j, dC/dIm eps_j), from one forward and one adjoint solve
+    of the several-scatterer system.  Scatterer j's permittivity enters only
+    its own interior rows, through T_j and k_j, so each derivative is the
+    single-scatterer expression on scatterer j's nodes with its own plan (and
+    two plans at k_j +- delta for dOp/dk)."""
+    region = np.asarray(region)
+    J = int(region.max()) + 1
+    eps = [complex(e) for e in eps]
+    mu = [complex(m) for m in (mu if mu is not None else [1.0] * J)]
+    pb = MultiBemProblem(nodes, region, k0, eps, mu=mu, order=order, depth=depth, depths=depths, order32=order32)
+    kw = dict(tol=tol, restart=restart, maxit=4000)
+    kw.update(solve_kw or {})
+    xd, _ = pb.solve(pb.rhs_planewave(d, pol), **kw)
+    xg = xd.clone().requires_grad_(True)
+    C = _functional(functional, pb, nodes, k0, xg, d, pol)
+    g = torch.autograd.grad(C, xg)[0]
+    lam, _ = pb.solve(g.contiguous(), adjoint=True, **kw)
+    grads = np.zeros((J, 2))
+    for j in range(J):
+        idx = torch.from_numpy(np.nonzero(region == j)[0]).cuda()
+        sub = _nodes_of(nodes, region == j)
+        nrm = torch.from_numpy(sub["normals"]).cuda().to(torch.complex128)
+        phi, psi = xd[0, idx, 0:3], xd[0, idx, 3:6]
+        nphi = torch.sum(nrm * phi, dim=1, keepdim=True)
+        e = eps[j]
+        dT_phi = (-1.0 / e ** 2) * nrm * nphi
+        T_phi = phi + ((1.0 - e) / e) * nrm * nphi
+        kj = pb.kj[j]
+        delta = dk_rel * abs(kj)
+        Pj = pb.pj[j]
+        pk = dict(depth=Pj.info()["depth"], point_tri=sub["point_tri"], tri_vertices=sub["tri_vertices"])
+        Pp = Plan(sub["points"], sub["normals"], sub["weights"], kj + delta, order, **pk)
+        Pm = Plan(sub["points"], sub["normals"], sub["weights"], kj - delta, order, **pk)
+        b_int = ((-mu[j]) * psi).contiguous()
+        dOp = (Pp.matvec(T_phi.contiguous(), b_int) - Pm.matvec(T_phi.contiguous(), b_int)) / (2.0 * delta)
+        term = 0.5 * dT_phi - Pj.matvec(dT_phi.contiguous(), torch.zeros_like(phi)) - (kj / (2.0 * e)) * dOp
+        u = torch.sum(torch.conj(lam[0, idx, 3:6]) * term).item()
+        grads[j] = (-u.real, u.imag)
+        Pp.close()
+        Pm.close()
+    val = C.item()
+    pb.close()
+    return val, grads

@@ -118,3 +118,34 @@ def test_gold_dimer_force_on_one_sphere(gpu):
     assert abs(Fl[1]) <= 1e-8 * scale and abs(Fr[1]) <= 1e-8 * scale
     assert np.linalg.norm(Fl + Fr - Fb) <= 0.01 * np.linalg.norm(Fb)
     pb.close()
+
+
+def test_per_scatterer_eps_gradients_match_differences(gpu):
+    """Two lossy spheres side by side (960 nodes each, eps 2.25 + 0.5i and
+    4 + 0.3i): dC_sca/deps_j of the far-field cross section for each scatterer
+    from one forward and one adjoint solve, against h = 1e-6 central differences
+    of solves to 1e-12 in both directions of each complex eps_j."""
+    from paper_1211_7177_amd import gradients as gr
+    m, treg = union([icosphere(4), icosphere(4)], [[-1.6, 0.0, 0.0], [1.6, 0.0, 0.0]])
+    q = nystrom3(m)
+    reg = treg[q["point_tri"]]
+    eps = [2.25 + 0.5j, 4.0 + 0.3j]
+    d, p = [0.0, 0.6, 0.8], [1.0, 0.0, 0.0]
+    C, g = gr.cross_section_and_eps_gradients_multi(q, reg, 1.0, eps, d, p, order=20, depths=[3, 3], tol=1e-12,
+                                                    restart=200)
+    h = 1e-6
+    for j in range(2):
+        fd = []
+        for de in (h, -h, 1j * h, -1j * h):
+            e2 = list(eps)
+            e2[j] = e2[j] + de
+            pb = gpu.MultiBemProblem(q, reg, 1.0, e2, order=20, depths=[3, 3])
+            x, _ = pb.solve(pb.rhs_planewave(d, p), tol=1e-12, restart=200, maxit=4000)
+            fd.append(gr.far_field_cross_section(pb, x, p).item())
+            pb.close()
+        fr, fi = (fd[0] - fd[1]) / (2 * h), (fd[2] - fd[3]) / (2 * h)
+        print("scatterer %d: adjoint (%.8e, %.8e) differences (%.8e, %.8e)" % (j, g[j][0], g[j][1], fr, fi),
+              flush=True)
+        scale = max(abs(fr), abs(fi))
+        assert abs(g[j][0] - fr) <= 1e-5 * scale and abs(g[j][1] - fi) <= 1e-5 * scale
+    print("C", C)
