@@ -141,15 +141,21 @@ def cross_section_and_eps_gradient(nodes, k0, eps, d, pol, order=16, depth=0, to
 
 
 def cross_section_and_shape_gradient(nodes_at, nparams, k0, eps, d, pol, order=16, depth=0, tol=1e-10, restart=150,
-                                     h=1e-3, mu=1.0, functional="surface"):
+                                     h=1e-3, mu=1.0, functional="surface", make_problem=None):
     """(C_sca, dC/dtheta f64[nparams]) at theta = 0 for the shape family
     nodes_at(theta) (a callable returning the Nystrom nodes of the moved mesh,
     node order unchanged), by one forward and one adjoint solve and, per
     parameter, two rebuilt problems and products.  functional as for
-    `cross_section_and_eps_gradient`."""
-    eps = complex(eps)
+    `cross_section_and_eps_gradient`.  make_problem(nodes, depth), when given,
+    builds the system instead of a one-scatterer BemProblem (for instance a
+    MultiBemProblem with its region map); depth is the requested octree depth
+    of the host plan (0 first, then the depth that build chose)."""
+    eps = complex(eps) if np.isscalar(eps) else eps
+    if make_problem is None:
+        def make_problem(q, dep):
+            return BemProblem(q, k0, eps, mu=mu, order=order, depth=dep)
     q0 = nodes_at(np.zeros(nparams))
-    pb = BemProblem(q0, k0, eps, mu=mu, order=order, depth=depth)
+    pb = make_problem(q0, depth)
     dep = pb.p0.info()["depth"]
     kw = dict(tol=tol, restart=restart, maxit=4000)
     xd, _ = pb.solve(pb.rhs_planewave(d, pol), **kw)
@@ -165,7 +171,7 @@ def cross_section_and_shape_gradient(nodes_at, nparams, k0, eps, d, pol, order=1
             th = np.zeros(nparams)
             th[i] = sgn * h
             q = nodes_at(th)
-            p = BemProblem(q, k0, eps, mu=mu, order=order, depth=dep)
+            p = make_problem(q, dep)
             res.append(p.rhs_planewave(d, pol) - p.apply(xd))
             fun.append(_functional(functional, p, q, k0, xd, d, pol).item())
             p.close()

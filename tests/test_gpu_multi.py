@@ -149,3 +149,40 @@ def test_per_scatterer_eps_gradients_match_differences(gpu):
         scale = max(abs(fr), abs(fi))
         assert abs(g[j][0] - fr) <= 1e-5 * scale and abs(g[j][1] - fi) <= 1e-5 * scale
     print("C", C)
+
+
+def test_separation_gradient_of_two_spheres(gpu):
+    """The derivative of the far-field C_sca of two lossy spheres with respect to
+    moving the second one along x (their separation), by the adjoint method
+    over a shape family of the coupled system, against central differences of
+    its solves."""
+    from paper_1211_7177_amd import gradients as gr
+    from synthetic import Mesh
+    m, treg = union([icosphere(4), icosphere(4)], [[-1.6, 0.0, 0.0], [1.6, 0.0, 0.0]])
+    q0 = nystrom3(m)
+    reg = treg[q0["point_tri"]]
+    vreg = np.zeros(len(m.vertices), dtype=int)
+    vreg[m.triangles[treg == 1].ravel()] = 1
+    shift = np.zeros_like(m.vertices)
+    shift[vreg == 1, 0] = 1.0
+    eps = [2.25 + 0.5j, 4.0 + 0.3j]
+    d, p = [0.0, 0.6, 0.8], [1.0, 0.0, 0.0]
+
+    def nodes_at(th):
+        return nystrom3(Mesh(m.vertices + th[0] * shift, m.triangles))
+
+    def make(q, dep):
+        return gpu.MultiBemProblem(q, reg, 1.0, eps, order=20, depth=dep, depths=[3, 3])
+
+    C, gs = gr.cross_section_and_shape_gradient(nodes_at, 1, 1.0, eps, d, p, depth=4, tol=1e-12, restart=200,
+                                                h=1e-4, functional="far", make_problem=make)
+    h = 1e-4
+    v = []
+    for sgn in (1.0, -1.0):
+        pb = make(nodes_at(np.array([sgn * h])), 4)
+        x, _ = pb.solve(pb.rhs_planewave(d, p), tol=1e-12, restart=200, maxit=4000)
+        v.append(gr.far_field_cross_section(pb, x, p).item())
+        pb.close()
+    fd = (v[0] - v[1]) / (2 * h)
+    print("C %.6f dC/dseparation adjoint %.8e differences %.8e" % (C, gs[0], fd), flush=True)
+    assert abs(gs[0] - fd) <= 1e-5 * abs(fd)
