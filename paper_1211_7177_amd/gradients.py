@@ -46,7 +46,7 @@ import torch
 from ._abi import Plan
 from .autograd import far_field
 from .postprocess import sphere_quadrature
-from .solver import BemProblem, MultiBemProblem, _nodes_of
+from .solver import BemProblem, IbcProblem, MultiBemProblem, _nodes_of
 
 
 def _incident(nodes, k0, d, pol, dtype=torch.complex128):
@@ -227,3 +227,36 @@ def cross_section_and_eps_gradients_multi(nodes, region, k0, eps, d, pol, order=
     val = C.item()
     pb.close()
     return val, grads
+
+
+def cross_section_and_impedance_gradient(nodes, k0, Z, d, pol, order=16, depth=0, tol=1e-10, restart=150, h=1e-6):
+    """(C_sca, dC/dRe Z, dC/dIm Z) of a good conductor under the impedance
+    boundary condition (eq. 2.25), with C_sca from the far field.  The system
+    1/2 Phi + Op_k0(Phi, c n x (n x Phi)) = E_inc depends on Z only through
+    c = i k0 / Z, so (dA/dZ) x = Op_k0(0, (dc/dZ) (n (n . Phi) - Phi)) with
+    dc/dZ = -i k0 / Z^2: one product of the k0 plan beside the forward and
+    adjoint solves.  The far field depends on Z through the same b term; that
+    explicit part is the central difference of the functional at Z +- h and
+    Z +- ih with the solution held fixed."""
+    Z = complex(Z)
+    pb = IbcProblem(nodes, k0, Z, order=order, depth=depth)
+    dep = pb.p0.info()["depth"]
+    kw = dict(tol=tol, restart=restart, maxit=4000)
+    xd, _ = pb.solve(pb.rhs_planewave(d, pol), **kw)
+    xg = xd.clone().requires_grad_(True)
+    C = far_field_cross_section(pb, xg, pol)
+    g = torch.autograd.grad(C, xg)[0]
+    lam, _ = pb.solve(g.contiguous(), adjoint=True, **kw)
+    nrm = torch.from_numpy(np.ascontiguousarray(nodes["normals"])).cuda().to(torch.complex128)
+    phi = xd[0]
+    dc = -1j * complex(k0) / Z ** 2
+    bz = dc * (nrm * torch.sum(nrm * phi, dim=1, keepdim=True) - phi)
+    dAx = pb.p0.matvec(torch.zeros_like(phi), bz.contiguous())
+    u = torch.sum(torch.conj(lam[0]) * dAx).item()
+    pb.close()
+    f = []
+    for dz in (h, -h, 1j * h, -1j * h):
+        p = IbcProblem(nodes, k0, Z + dz, order=order, depth=dep)
+        f.append(far_field_cross_section(p, xd, pol).item())
+        p.close()
+    return C.item(), (f[0] - f[1]) / (2 * h) - u.real, (f[2] - f[3]) / (2 * h) + u.imag

@@ -149,3 +149,25 @@ def test_far_field_shape_gradient_of_sphere_radius_matches_mie(grad):
     print("far C %.6f (Mie %.6f) dC/da adjoint %.6f differences %.6f Mie %.6f" % (C, am(1.0), gs[0], fd, mied))
     assert abs(gs[0] - fd) <= 1e-5 * abs(fd)
     assert abs(gs[0] - mied) <= 0.03 * mied
+
+
+def test_impedance_gradient_matches_differences(grad):
+    """dC_sca/dZ of the impedance sphere (960 nodes, k0 a = 1, Z = 0.2 - 0.1i;
+    far-field cross section) by the adjoint method against h = 1e-6 central
+    differences of converged solves in both directions of the complex Z."""
+    from paper_1211_7177_amd.solver import IbcProblem
+    q = nystrom3(icosphere(4))
+    Z = 0.2 - 0.1j
+    C, gr_, gi = grad.cross_section_and_impedance_gradient(q, 1.0, Z, D, POL, order=20, depth=3, tol=1e-12,
+                                                           restart=200)
+    h = 1e-6
+    v = []
+    for dz in (h, -h, 1j * h, -1j * h):
+        pb = IbcProblem(q, 1.0, Z + dz, order=20, depth=3)
+        x, _ = pb.solve(pb.rhs_planewave(D, POL), tol=1e-12, restart=200, maxit=4000)
+        v.append(grad.far_field_cross_section(pb, x, POL).item())
+        pb.close()
+    fr, fi = (v[0] - v[1]) / (2 * h), (v[2] - v[3]) / (2 * h)
+    print("C %.6f dC/dZ adjoint (%.8e, %.8e) differences (%.8e, %.8e)" % (C, gr_, gi, fr, fi))
+    scale = max(abs(fr), abs(fi))
+    assert abs(gr_ - fr) <= 1e-5 * scale and abs(gi - fi) <= 1e-5 * scale
