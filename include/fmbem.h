@@ -351,7 +351,8 @@ int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *point
 
 /*
  * bem_far_field_adjoint: the conjugate transpose of the far-field map of
- * bem_field (region 0, far 1), x -> F: given samples G at nd unit directions it
+ * bem_field (region 0, far 1: the far-zone limit of eq. 2.5, whose power
+ * gives C_sca of eq. 4.2), x -> F: given samples G at nd unit directions it
  * returns xbar = L^H G, so that sum conj(G) . (L x) = sum conj(xbar) . x for
  * every x.  This is the backward pass of a functional of the far field (e.g.
  * C_sca = oint |F|^2 dOmega) with respect to the unknowns.  G: device c128
@@ -363,8 +364,9 @@ int bem_far_field_adjoint(fmb_problem_t pb, const void *G, int32_t nrhs, const d
                           void *stream);
 
 /*
- * bem_field_fmm: the field of bem_field's kind 0 (region 0: E_sca at host
- * points; region 1: the interior field) by the fast multipole method instead of
+ * bem_field_fmm: the field of bem_field's kind 0 (eq. 2.5 off the surface;
+ * region 0: E_sca at host points; region 1: the interior field) by the fast
+ * multipole method of eqs. 2.17-2.23 instead of
  * direct sums, for many targets.  A temporary FP64 plan of the given order is
  * built over the nodes followed by the nt targets (the targets carry zero
  * density, so only the nodes radiate); one product of it gives the sum at every
