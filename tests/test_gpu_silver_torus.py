@@ -125,3 +125,38 @@ def test_sphere_above_torus_force_signs(ring):
     print("silver", ag, "dielectric", di, flush=True)
     assert ag[355] > 0 and ag[525] < 0 and ag[525] < ag[440]
     assert all(v < 0 for v in di.values()) and di[525] < di[440] and di[525] < di[355]
+
+
+def _sphere_force(lam_nm, silver_sphere, dx):
+    from synthetic import icosphere, union
+    from paper_1211_7177_amd import materials, postprocess as pp
+    from paper_1211_7177_amd.solver import MultiBemProblem
+    c = [dx / 10.0, 0.0, 5.0]
+    m, treg = union([torus(3.5, 1.5, 72, 24), icosphere(8, 1.5)], [[0.0, 0.0, 0.0], c])
+    q = nystrom3(m)
+    reg = treg[q["point_tri"]]
+    es = complex(materials.silver_drude_lorentz(lam_nm * 1e-9))
+    k0 = float(materials.wavenumber(lam_nm * 1e-9, UNIT))
+    pb = MultiBemProblem(q, reg, k0, [es, es if silver_sphere else 2.4], order=12, order32=6)
+    x, _ = pb.solve(pb.rhs_planewave([0.0, 0.0, 1.0], [1.0, 0.0, 0.0]), tol=1e-6, restart=200, maxit=3000,
+                    mixed=True, inner_tol=1e-2)
+    F = pp.optical_force(pb, x, [0.0, 0.0, 1.0], [1.0, 0.0, 0.0], k0, 3.0, center=c, nt=24, nph=48)[0]
+    pb.close()
+    return materials.force_newtons(F, 1e9, UNIT) * 1e15
+
+
+def test_lateral_trap_near_the_papers_offset(ring):
+    """Sphere 50 nm above the torus plane at 530 nm, moved along x (Sec. 4.2,
+    Fig. 15): F_x pushes it away from the axis at small offsets (the axis is
+    not a stable point) and changes sign from + to - at an offset within 12 nm
+    of the paper's 40 nm, a stable lateral equilibrium, for the silver and the
+    dielectric sphere (measured near 48 nm for both)."""
+    for silver in (True, False):
+        xs = [20, 40, 45, 50, 55]
+        fx = [float(_sphere_force(530, silver, dx)[0]) for dx in xs]
+        print("silver" if silver else "dielectric", list(zip(xs, np.round(fx, 3))), flush=True)
+        assert fx[0] > 0
+        k = next(i for i in range(1, len(xs)) if fx[i] < 0)
+        x0 = xs[k - 1] + (xs[k] - xs[k - 1]) * fx[k - 1] / (fx[k - 1] - fx[k])
+        print("zero crossing at %.1f nm" % x0, flush=True)
+        assert fx[k - 1] > 0 and abs(x0 - 40.0) <= 12.0
