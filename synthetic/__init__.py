@@ -12,6 +12,7 @@ from .meshes import (  # noqa: F401
     icosphere,
     torus,
     split_ring,
+    split_torus,
     nystrom3,
     union,
 )

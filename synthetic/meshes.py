@@ -139,6 +139,63 @@ def torus(R: float, r: float, nu: int, nv: int) -> Mesh:
     return _orient_by_reference(mesh, core)
 
 
+def split_torus(R: float, r: float, gap: float, nu: int, nv: int, nc: int = 4) -> Mesh:
+    """Torus about the z axis (major radius R, tube radius r) with the sector
+    |phi| < gap/2 around +x removed, closed by two flat discs: nu segments along
+    the remaining angle, nv around the tube, nc rings on each disc (the outer
+    ring is the tube's end ring, so the surface is conforming)."""
+    phis = gap / 2.0 + (2.0 * np.pi - gap) * np.arange(nu + 1) / nu
+    v = 2.0 * np.pi * np.arange(nv) / nv
+    U, V = np.meshgrid(phis, v, indexing="ij")
+    pts = [np.stack([((R + r * np.cos(V)) * np.cos(U)).ravel(), ((R + r * np.cos(V)) * np.sin(U)).ravel(),
+                     (r * np.sin(V)).ravel()], axis=1)]
+    I, J = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    I, J = I.ravel(), J.ravel()
+    a, b = I * nv + J, (I + 1) * nv + J
+    c, d = (I + 1) * nv + (J + 1) % nv, I * nv + (J + 1) % nv
+    tris = [np.stack([a, b, c], 1), np.stack([a, c, d], 1)]
+    ref = []                                    # outward reference point per triangle (a point inside)
+    base = (nu + 1) * nv
+    for end, phi in ((0, phis[0]), (nu, phis[-1])):
+        cen = np.array([R * np.cos(phi), R * np.sin(phi), 0.0])
+        rings = []
+        for k in range(1, nc):                  # inner rings of the disc, then the tube's end ring
+            rr = r * k / nc
+            ring = np.stack([(R + rr * np.cos(v)) * np.cos(phi), (R + rr * np.cos(v)) * np.sin(phi), rr * np.sin(v)], 1)
+            pts.append(ring)
+            rings.append(base + np.arange(nv))
+            base += nv
+        pts.append(cen[None, :])
+        ci = base
+        base += 1
+        rings.append(end * nv + np.arange(nv))
+        jn = (np.arange(nv) + 1) % nv
+        tris.append(np.stack([np.full(nv, ci), rings[0], rings[0][jn]], 1))
+        for k in range(len(rings) - 1):
+            p0, p1 = rings[k], rings[k + 1]
+            tris.append(np.stack([p0, p1, p1[jn]], 1))
+            tris.append(np.stack([p0, p1[jn], p0[jn]], 1))
+        # the disc's outward side is away from the remaining tube, i.e. into the gap
+        t_phi = np.array([-np.sin(phi), np.cos(phi), 0.0]) * (-1.0 if end == 0 else 1.0)
+        ref.append((cen, t_phi))
+    mesh = Mesh(np.concatenate(pts), np.concatenate(tris).astype(np.int32))
+    tv = mesh.tri_vertices()
+    nrm = np.cross(tv[:, 1] - tv[:, 0], tv[:, 2] - tv[:, 0])
+    cent = tv.mean(axis=1)
+    ntube = 2 * nu * nv
+    rho = np.hypot(cent[:ntube, 0], cent[:ntube, 1])
+    core = np.stack([R * cent[:ntube, 0] / rho, R * cent[:ntube, 1] / rho, np.zeros(ntube)], 1)
+    out = np.empty_like(cent)
+    out[:ntube] = cent[:ntube] - core
+    ncap = (len(cent) - ntube) // 2
+    out[ntube:ntube + ncap] = ref[0][1]
+    out[ntube + ncap:] = ref[1][1]
+    flip = np.einsum("ij,ij->i", nrm, out) < 0
+    t = mesh.triangles.copy()
+    t[flip] = t[flip][:, [0, 2, 1]]
+    return Mesh(mesh.vertices, t.astype(np.int32))
+
+
 def split_ring(side: float = 1.0, width: float = 0.2, thickness: float = 0.1,
                gap: float = 0.2, h: float = 0.02) -> Mesh:
     """Square split ring in the xy plane, centred at the origin, the gap cut
