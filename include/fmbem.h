@@ -66,7 +66,9 @@ typedef struct {
     int64_t ntri;               /* number of triangles                                        */
     int32_t leaf_target;        /* depth 0 only: aim for about this many nodes per leaf (0=32)*/
     int32_t translate_mode;     /* FP32 plans: FMB_TRANSLATE_FP32 (default) or FMB_TRANSLATE_BF16X3 */
-    int32_t reserved[6];
+    int32_t reserved0;
+    double tol;                 /* order <= 0 only: target relative accuracy of the expansions */
+    double far_cutoff;          /* lossy k: drop interactions damped below this factor (0: default) */
 } fmb_plan_opts;
 
 /*
@@ -101,6 +103,14 @@ int fmb_plan_opts_default(fmb_plan_opts *opts);
  *   normals  host f64[n][3]   unit normals (|n| within 1e-6 of 1), outward
  *   weights  host f64[n]      Nystrom weights w_beta > 0 (eq. 2.8)
  *   order    p >= 1: degrees 0..p-1 kept at every level (eq. 2.17 cut)
+ * Lossy wavenumbers (Im k > 0, Sec. 2.1: g decays as exp(-Im k R)): the
+ * far field of level l is dropped when exp(-Im k h_l) < far_cutoff, h_l being
+ * the level's box side, the shortest distance between two boxes of its
+ * far-field lists (Appendix C).  When every level is dropped the plan is
+ * local only: no expansions are built or used, and near pairs farther apart
+ * than R_c = ln(1/far_cutoff)/Im k are dropped too.  far_cutoff = 0 selects
+ * 1e-16 for FP64 plans and 1e-8 for FP32 plans; a negative value keeps every
+ * interaction.  Real k is never cut.
  * Errors: FMB_EINVAL for n < 2, non-finite input, bad normal, w <= 0,
  * k_im < 0, depth out of range, order out of range (1..24), two nodes at
  * the same position, corr_mode > 0 without triangles or with a triangle not

@@ -26,9 +26,9 @@ radius rho_m(phi) = h_e / cos(phi) and direction rho^ = cos(phi) i_e + sin(phi) 
   The paper again keeps Taylor terms (eqs. B.4, B.5); the exact remainder is
   used here.
 
-Both angular integrals and the radial integral in H are done with
-Gauss-Legendre rules, the angular one doubled until it changes by less than
-1e-12 relative.
+The angular integrals are done with Gauss-Legendre rules, doubled until
+they change by less than 1e-12 relative; the radial integral in H is a
+series for small |k| rho_m and the exponential integral E1 otherwise.
 
 How the element integrals are shared among a triangle's nodes (the paper
 only treats the one-node centroid rule, where the node gets the whole
@@ -106,35 +106,29 @@ def static_drho_dphi(h, p1, p2):
     return np.sum(h * np.log(np.tan(np.pi / 4 + th1 / 2) / np.tan(np.pi / 4 - th2 / 2)), axis=1)
 
 
-def _H(k, rho, nr=20):
-    """H(rho) = int_0^rho [(i k u - 1) e^{i k u} + 1]/u du.
+def _H(k, rho):
+    """H(rho) = int_0^rho [(i k u - 1) e^{i k u} + 1]/u du, z = i k rho.
 
-    For |k rho| < 2 the integrand's power series integrates term by term,
-    H = sum_{n>=2} (n-1) z^n / (n n!) with z = i k rho; otherwise
-    Gauss-Legendre on 4 panels.
+    Substituting w = i k u gives H = int_0^z [(w - 1) e^w + 1]/w dw
+    = (e^z - 1) - F(z), F(z) = int_0^z (e^w - 1)/w dw = sum_{n>=1} z^n/(n n!).
+    For |z| < 2 the series H = sum_{n>=2} (n-1) z^n/(n n!) is summed term by
+    term; otherwise F(z) = -E1(-z) - ln(-z) - gamma (principal branches; -z has
+    Re >= 0 because Im k >= 0), with E1 the exponential integral.  A fixed
+    quadrature in u cannot follow the boundary layer of width 1/|k| that the
+    integrand has at u = 0 when |k| rho is large (lossy interiors).
     """
-    z0 = 1j * k * rho
-    if np.all(np.abs(z0) < 2.0):
-        out = np.zeros(rho.shape, dtype=np.complex128)
-        term = z0 * z0 / 2.0                  # z^n / n! at n = 2
-        for nn in range(2, 40):
-            out = out + (nn - 1) * term / nn
-            term = term * z0 / (nn + 1)
-        return out
-    x, w = _gl(nr)
-    out = np.zeros(rho.shape, dtype=np.complex128)
-    panels = 4
-    for pnl in range(panels):
-        a = rho * pnl / panels
-        b = rho * (pnl + 1) / panels
-        u = 0.5 * (b - a)[..., None] * (x + 1.0) + a[..., None]
-        z = 1j * k * u
-        small = np.abs(z) < 1e-3
-        f = np.where(small,
-                     (z * z / 2 + z ** 3 / 3 + z ** 4 / 8) / np.where(u > 0, u, 1.0),
-                     ((z - 1.0) * np.exp(z) + 1.0) / np.where(u > 0, u, 1.0))
-        out += 0.5 * (b - a) * np.sum(w * f, axis=-1)
-    return out
+    from scipy.special import exp1
+    z0 = 1j * k * np.asarray(rho, dtype=np.float64)
+    small = np.abs(z0) < 2.0
+    zs = np.where(small, z0, 0.0)
+    ser = np.zeros(z0.shape, dtype=np.complex128)
+    term = zs * zs / 2.0                  # z^n / n! at n = 2
+    for nn in range(2, 40):
+        ser = ser + (nn - 1) * term / nn
+        term = term * zs / (nn + 1)
+    zl = np.where(small, 1.0, z0)
+    big = np.exp(zl) - 1.0 + exp1(-zl) + np.log(-zl) + np.euler_gamma
+    return np.where(small, ser, big)
 
 
 def _angular(k, h, ie, je, p1, p2, nq):

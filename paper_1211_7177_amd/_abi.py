@@ -30,7 +30,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("precision", ctypes.c_int32), ("nrhs_max", ctypes.c_int32),
                 ("corr_mode", ctypes.c_int32), ("point_tri", ctypes.c_void_p), ("tri_vertices", ctypes.c_void_p),
                 ("ntri", ctypes.c_int64), ("leaf_target", ctypes.c_int32), ("translate_mode", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("reserved0", ctypes.c_int32), ("tol", ctypes.c_double), ("far_cutoff", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -136,7 +136,8 @@ class Plan:
     """One wavenumber's FMM operator (`fmm_plan`)."""
 
     def __init__(self, points, normals, weights, k, order, depth=0, precision="fp64", nrhs_max=1,
-                 corr="linear", point_tri=None, tri_vertices=None, leaf_target=32, translate="fp32"):
+                 corr="linear", point_tri=None, tri_vertices=None, leaf_target=32, translate="fp32", tol=0.0,
+                 far_cutoff=0.0):
         lib = load()
         self._lib = lib
         pts = _host(points, np.float64)
@@ -151,6 +152,8 @@ class Plan:
         opts.corr_mode = CORR[corr] if isinstance(corr, str) else int(corr)
         opts.leaf_target = int(leaf_target)
         opts.translate_mode = {"fp32": 1, "bf16x3": 2}[translate]
+        opts.tol = float(tol)
+        opts.far_cutoff = float(far_cutoff)
         keep = []
         if point_tri is not None:
             pt = _host(point_tri, np.int32)

@@ -2,6 +2,7 @@
 // device uploads, and dispatch to the plan / matvec steps.
 #include <algorithm>
 #include <cstring>
+#include <limits>
 
 #include "plan.h"
 
@@ -27,6 +28,26 @@ size_t Plan::device_bytes() const {
 void build_tiles(Plan &P, hipStream_t s);
 void split_operators(Plan &P, hipStream_t s);
 void alloc_workspace(Plan &P);
+
+// Far-field levels kept for a lossy wavenumber: level l is kept while the
+// damping exp(-Im k h_l) over its box side h_l (the least distance between two
+// of its far-field boxes) stays at or above the cutoff.  h_l halves per level,
+// so the kept levels are far_lmin..depth.
+static void set_far_cutoff(Plan &P, double cutoff) {
+    if (cutoff == 0.0) cutoff = P.precision == FMB_FP64 ? 1e-16 : 1e-8;
+    P.far_cutoff = cutoff;
+    P.far_lmin = 2;
+    P.rcut2 = std::numeric_limits<double>::infinity();
+    if (cutoff < 0.0 || P.k_im <= 0.0) return;
+    const double decay = std::log(1.0 / cutoff);      // exp(-decay) = cutoff
+    int l = 2;
+    while (l <= P.depth && P.k_im * (P.ext / (double)(1 << l)) > decay) ++l;
+    P.far_lmin = l;
+    if (!P.far_on()) {
+        const double rc = decay / P.k_im;
+        P.rcut2 = rc * rc;
+    }
+}
 
 static void upload(DevBuf &d, const void *h, size_t bytes, hipStream_t s) {
     d.alloc(bytes);
@@ -140,6 +161,7 @@ int fmm_plan(const double *points, const double *normals, const double *weights,
         upload(P.point_tri, tri.data(), n * sizeof(int32_t), s);
         upload(P.unrm, normals, n * 3 * sizeof(double), s);
         build_tree(P, d_pts.as<double>(), s, ntri > 0 ? tri.data() : nullptr);
+        set_far_cutoff(P, o.far_cutoff);
         gather_nodes(P, d_pts.as<double>(), d_nrm.as<double>(), d_w.as<double>(), P.point_tri.as<int32_t>(), s);
         build_operators(P, s);
         build_tiles(P, s);

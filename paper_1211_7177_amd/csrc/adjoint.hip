@@ -173,7 +173,7 @@ __global__ void __launch_bounds__(ATPB) k_adj_p2p(const int32_t *__restrict__ st
                                                   const double *__restrict__ center,
                                                   const double *__restrict__ spts, const int32_t *__restrict__ stri,
                                                   const cx<T> *__restrict__ src, int64_t n, double k_re, double k_im,
-                                                  cx<T> *__restrict__ out) {
+                                                  double rcut2, cx<T> *__restrict__ out) {
     __shared__ AdjTile<T> tile;
     __shared__ int32_t nb_start[28], nb_box[27];
     __shared__ int n_nb;
@@ -234,6 +234,7 @@ __global__ void __launch_bounds__(ATPB) k_adj_p2p(const int32_t *__restrict__ st
                 if (tile.tri[j] == ttri) continue;
                 const T dx = tp[0] - tile.pos[j][0], dy = tp[1] - tile.pos[j][1], dz = tp[2] - tile.pos[j][2];
                 const T R2 = dx * dx + dy * dy + dz * dz;
+                if (R2 > rcut2) continue;       // damped below the cutoff (local-only lossy plans)
                 const T iR = fast_rsqrt(R2);
                 const T R = R2 * iR;
                 T sn, cs;
@@ -345,7 +346,20 @@ size_t l2p_lds(const Plan &P, int threads) {
 }
 
 template <typename T>
+__global__ void k_adj_zero(cx<T> *__restrict__ x, int64_t m) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < m) x[i] = mk(T(0), T(0));
+}
+
+template <typename T>
 void l2p_t(Plan &P, int nrhs, hipStream_t s) {
+    if (!P.far_on()) {
+        // local-only plan: the near field accumulates onto zero
+        const int64_t m = (int64_t)nrhs * P.n * 12;
+        k_adj_zero<T><<<grid_for(m, GTPB), GTPB, 0, s>>>(P.aws.as<cx<T>>(), m);
+        FMB_LAUNCH_CHECK();
+        return;
+    }
     const Level &LL = P.lv[P.depth];
     const int threads = 64;
     const size_t sh = l2p_lds(P, threads);
@@ -362,7 +376,7 @@ void p2p_t(Plan &P, int nrhs, hipStream_t s) {
     k_adj_p2p<T><<<dim3((unsigned)LL.nbox, (unsigned)nrhs), ATPB, 0, s>>>(
         LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(),
         P.stri.as<int32_t>(), P.src.as<cx<T>>(),
-        P.n, P.k_re, P.k_im, P.aws.as<cx<T>>());
+        P.n, P.k_re, P.k_im, (double)(T)std::min(P.rcut2, 1e30), P.aws.as<cx<T>>());
     FMB_LAUNCH_CHECK();
 }
 

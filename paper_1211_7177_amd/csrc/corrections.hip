@@ -11,7 +11,8 @@
 //                         + (1/4pi) sum_e int rho^ H(z) dphi,
 //       CPV int_T r/r^3 dA = sum_e i_e ln[tan(pi/4 - th2/2) / tan(pi/4 + th1/2)]   (eq. B.9),
 //       H(z) = sum_{n>=2} (n-1) z^n / (n n!)   (the regular remainder; eqs. B.4-B.5
-//              keep only its leading term)
+//              keep only its leading term), summed for |z| < 4 and taken in closed
+//              form through the exponential integral E1 otherwise
 //   int_T g (s'-O) dA      = (1/4pi) sum_e int rho^ [(1 - z) e^z - 1]/k^2 dphi
 //   int_T grad'g (s'-O)^T  = (1/4pi) sum_e int rho^ rho^T [rho_m e^z - 2 (e^z - 1)/(i k)] dphi
 //
@@ -56,20 +57,29 @@ __device__ inline cx<double> H_series(cx<double> z) {
     return out;
 }
 
-__device__ inline cx<double> H_quad(cx<double> k, double rho) {
-    // int_0^rho [(i k u - 1) e^{i k u} + 1]/u du, Gauss-Legendre on 8 panels
-    cx<double> out = mk(0.0, 0.0);
-    const int panels = 8;
-    for (int pn = 0; pn < panels; ++pn) {
-        double a = rho * pn / panels, b = rho * (pn + 1) / panels;
-        for (int q = 0; q < NQ; ++q) {
-            double u = 0.5 * (b - a) * (c_glx[q] + 1.0) + a;
-            cx<double> z = mk(-k.im * u, k.re * u);
-            cx<double> f = (z - mk(1.0, 0.0)) * cexp_(z) + mk(1.0, 0.0);
-            out += (0.5 * (b - a) * c_glw[q] / u) * f;
-        }
+// E1(w), the exponential integral, for Re w >= 0 and |w| >= 2: the continued
+// fraction E1(w) = e^{-w} / (w + 1 - 1^2/(w + 3 - 2^2/(w + 5 - ...))), evaluated
+// forward by the modified Lentz method.
+__device__ inline cx<double> E1_cf(cx<double> w) {
+    cx<double> f = w + mk(1.0, 0.0), C = f, D = mk(0.0, 0.0);
+    for (int j = 1; j < 2000; ++j) {
+        const double a = -(double)j * (double)j;
+        const cx<double> b = w + mk(2.0 * j + 1.0, 0.0);
+        D = cdiv(mk(1.0, 0.0), b + a * D);
+        C = b + a * cdiv(mk(1.0, 0.0), C);
+        const cx<double> d = C * D;
+        f = f * d;
+        if (abs2(d - mk(1.0, 0.0)) < 1e-32) break;
     }
-    return out;
+    return cdiv(cexp_(-w), f);
+}
+
+__device__ inline cx<double> H_closed(cx<double> z) {
+    // H(z) = int_0^z [(u - 1) e^u + 1]/u du = e^z - 1 - F(z), F(z) = int_0^z (e^u - 1)/u du,
+    // and F(z) = -E1(-z) - ln(-z) - gamma on the principal branches (Re(-z) = Im k rho >= 0)
+    const cx<double> w = -z;
+    const cx<double> lw = mk(0.5 * log(abs2(w)), atan2(w.im, w.re));
+    return cexp_(z) - mk(1.0 - 0.57721566490153286061, 0.0) + E1_cf(w) + lw;
 }
 
 __global__ void k_tri_nodes_fill(const int32_t *__restrict__ point_tri, int64_t n, int m, int32_t *__restrict__ cnt,
@@ -151,7 +161,7 @@ __global__ void k_corr_build(const double *__restrict__ pts, const double *__res
             if (az < 1e-4) gi = rho * (mk(1.0, 0.0) + 0.5 * z + (1.0 / 6.0) * (z * z));
             else gi = cdiv(E - mk(1.0, 0.0), ik);
             G += jac * gi;
-            cx<double> Hv = az < 4.0 ? H_series(z) : H_quad(k, rho);
+            cx<double> Hv = az < 4.0 ? H_series(z) : H_closed(z);
             V[0] += (jac * rh.x) * Hv;
             V[1] += (jac * rh.y) * Hv;
             V[2] += (jac * rh.z) * Hv;

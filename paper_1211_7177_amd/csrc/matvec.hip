@@ -294,7 +294,7 @@ template <typename T>
 __global__ void __launch_bounds__(TPB) k_p2p(const int32_t *__restrict__ start, const int32_t *__restrict__ nbr,
                                              const double *__restrict__ spts, const double *__restrict__ snrm,
                                              const int32_t *__restrict__ stri, const cx<T> *__restrict__ src, int64_t n,
-                                             double k_re, double k_im, cx<T> *__restrict__ ys) {
+                                             double k_re, double k_im, double rcut2, cx<T> *__restrict__ ys) {
     __shared__ SrcTile<T> tile;
     __shared__ int32_t nb_start[28], nb_box[27];
     __shared__ int n_nb;
@@ -356,6 +356,7 @@ __global__ void __launch_bounds__(TPB) k_p2p(const int32_t *__restrict__ start, 
                 const T dx = (T)(tile.pos[j][0] - tp[0]), dy = (T)(tile.pos[j][1] - tp[1]),
                         dz = (T)(tile.pos[j][2] - tp[2]);
                 const T R2 = dx * dx + dy * dy + dz * dz;
+                if (R2 > rcut2) continue;       // damped below the cutoff (local-only lossy plans)
                 const T iR = fast_rsqrt(R2);
                 const T R = R2 * iR;
                 T sn, cs;
@@ -418,13 +419,13 @@ struct P2PTile {
     static constexpr int TS = RC == 1 ? 256 : (RC == 2 ? 128 : 64);
 };
 
-template <bool LOSSY, int RC>
+template <bool LOSSY, int RC, bool CUT = false>
 __global__ void __launch_bounds__(TPB) k_p2p32(int nleaf, int nrhs, const int32_t *__restrict__ start,
                                                const int32_t *__restrict__ nbr,
                                                const double *__restrict__ center, const double *__restrict__ spts,
                                                const double *__restrict__ snrm, const int32_t *__restrict__ stri,
                                                const cx<float> *__restrict__ src, int64_t n, double k_re,
-                                               double k_im, cx<float> *__restrict__ ys) {
+                                               double k_im, float rcut2, cx<float> *__restrict__ ys) {
     constexpr int TS = P2PTile<RC>::TS;
     __shared__ SrcHdr32 hdr[TS];
     __shared__ __attribute__((aligned(16))) cx<float> rec[TS][RC][8];   // a[3], b[3], n.a, unused
@@ -508,6 +509,7 @@ __global__ void __launch_bounds__(TPB) k_p2p32(int nleaf, int nrhs, const int32_
                 const SrcHdr32 &q = hdr[j];
                 const bool self = q.tri == ttri;
                 const float dx = q.x - tx, dy = q.y - ty, dz = q.z - tz;
+                if (CUT && dx * dx + dy * dy + dz * dz > rcut2) continue;   // damped below the cutoff
                 const float R2 = self ? 1.f : dx * dx + dy * dy + dz * dz;
                 const float iR = __builtin_amdgcn_rsqf(R2);
                 const float R = R2 * iR;
@@ -548,6 +550,16 @@ __global__ void __launch_bounds__(TPB) k_p2p32(int nleaf, int nrhs, const int32_
             }
         }
     }
+}
+
+// local-only lossy plans: pairs beyond the cutoff radius are skipped by a branch
+template <int RC>
+constexpr auto k_p2p32_cut = k_p2p32<true, RC, true>;
+
+template <typename T>
+__global__ void k_zero(cx<T> *__restrict__ x, int64_t m) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < m) x[i] = mk(T(0), T(0));
 }
 
 // ---------------------------------------------------------------- translations
@@ -1232,7 +1244,10 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
     }
     // Step 1: leaf multipoles
     Level &LL = P.lv[L];
+    const bool far = P.far_on();
+    const int lmin = std::max(2, P.far_lmin);
     if (step == k++) {
+        if (!far) return true;
         const int N = p;
         const size_t per = ((size_t)(N + 1) * (N + 2) + 1 + 7) * sizeof(cx<T>) + 6 * sizeof(T);
         // LDS: the group-reduction area (G * P2 * 3 complex when G > 1), then per node of a batch
@@ -1253,7 +1268,7 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
     for (int l = L - 1; l >= 2; --l) {
         Level &V = P.lv[l], &C = P.lv[l + 1];
         if (step != k++) continue;
-        if (V.ntiles_m2m == 0) return true;
+        if (l < lmin || V.ntiles_m2m == 0) return true;
         tm.begin(ST_M2M, s, ev);
         launch_translate<T>(V.tiles_m2m.as<Tile>(), V.ntiles_m2m, C.by_octant.as<int32_t>(), nullptr, V.m2m.as<T>(),
                             (const T *)C.M.p, (T *)yb, KR, ncol, blkR, os, s, 0, 0, bf3 ? V.m2m_hi.p : nullptr,
@@ -1269,9 +1284,10 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
     // Step 3a: S|R of every level, one run of launches; each level's slots have
     // their own region of the slot buffer (slot_base)
     if (step == k++) {
+        if (!far) return true;
         int nk = 0;
         tm.begin(ST_M2L, s, ev);
-        for (int l = 2; l <= L; ++l) {
+        for (int l = lmin; l <= L; ++l) {
             Level &V = P.lv[l];
             if (V.ntiles_m2l == 0) continue;
             launch_translate<T>(V.tiles_m2l.as<Tile>(), V.ntiles_m2l, V.ff_by_op.as<int32_t>(), V.ff_src.as<int32_t>(),
@@ -1285,18 +1301,19 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
     // Step 3b: the S|R slot sums of every level (one launch, overwriting L),
     // then R|R from the parent added into each level in turn
     if (step == k++) {
+        if (!far) return true;
         FarSumLevels fs{};
-        fs.nlev = L - 1;
+        fs.nlev = L - lmin + 1;
         int64_t tot = 0;
-        for (int l = 2; l <= L; ++l) {
+        for (int l = lmin; l <= L; ++l) {
             Level &V = P.lv[l];
-            fs.box0[l - 2] = tot;
-            fs.ff_ofs[l - 2] = V.ff_ofs.as<int32_t>();
-            fs.slot_base[l - 2] = V.slot_base;
-            fs.L[l - 2] = V.L.p;
+            fs.box0[l - lmin] = tot;
+            fs.ff_ofs[l - lmin] = V.ff_ofs.as<int32_t>();
+            fs.slot_base[l - lmin] = V.slot_base;
+            fs.L[l - lmin] = V.L.p;
             tot += V.nbox;
         }
-        fs.box0[L - 1] = tot;
+        fs.box0[L - lmin + 1] = tot;
         tm.begin(ST_SUMS, s, ev);
         k_sum_far_all<T><<<(unsigned)tot, TPB, 0, s>>>(fs, yb, blk, ncol * P2);
         FMB_LAUNCH_CHECK();
@@ -1306,7 +1323,7 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
     for (int l = 3; l <= L; ++l) {
         Level &V = P.lv[l];
         if (step != k++) continue;
-        if (V.ntiles_l2l == 0) return true;
+        if (l <= lmin || V.ntiles_l2l == 0) return true;
         Level &U = P.lv[l - 1];
         tm.begin(ST_L2L, s, ev);
         launch_translate<T>(V.tiles_l2l.as<Tile>(), V.ntiles_l2l, V.by_octant.as<int32_t>(), V.parent.as<int32_t>(),
@@ -1317,6 +1334,12 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
     }
     // Step 4: local expansions at the targets, then the near sum
     if (step == k++) {
+        if (!far) {
+            // local-only plan: the near sum accumulates onto zero
+            k_zero<T><<<gridn((int64_t)nrhs * n * 3), TPB, 0, s>>>(ys, (int64_t)nrhs * n * 3);
+            FMB_LAUNCH_CHECK();
+            return true;
+        }
         // chunk of right-hand sides per block while their local expansions fit ~24 KB of LDS
         const size_t lrhs = (size_t)3 * P2 * sizeof(cx<T>);
         const int rc = (nrhs >= 8 && 8 * lrhs <= 24576) ? 8 : ((nrhs >= 4 && 4 * lrhs <= 24576) ? 4 : 1);
@@ -1343,14 +1366,22 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
                 case 2: kern = lossy ? k_p2p32<true, 2> : k_p2p32<false, 2>; break;
                 default: kern = lossy ? k_p2p32<true, 1> : k_p2p32<false, 1>; break;
             }
+            if (!far) {
+                switch (rc) {
+                    case 8: kern = k_p2p32_cut<8>; break;
+                    case 4: kern = k_p2p32_cut<4>; break;
+                    case 2: kern = k_p2p32_cut<2>; break;
+                    default: kern = k_p2p32_cut<1>; break;
+                }
+            }
             kern<<<dim3((unsigned)LL.nbox, (unsigned)((nrhs + rc - 1) / rc)), TPB, 0, s>>>(
                 (int)LL.nbox, nrhs, LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), LL.center.as<double>(),
                 P.spts.as<double>(), P.snrm.as<double>(), P.stri.as<int32_t>(), (const cx<float> *)src, n, P.k_re,
-                P.k_im, (cx<float> *)ys);
+                P.k_im, (float)std::min(P.rcut2, 1e30), (cx<float> *)ys);
         } else {
             k_p2p<T><<<dim3((unsigned)LL.nbox, nrhs), TPB, 0, s>>>(
                 LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), P.spts.as<double>(), P.snrm.as<double>(),
-                P.stri.as<int32_t>(), src, n, P.k_re, P.k_im, ys);
+                P.stri.as<int32_t>(), src, n, P.k_re, P.k_im, P.rcut2, ys);
         }
         FMB_LAUNCH_CHECK();
         tm.end(ST_P2P, s, ev);
@@ -1403,7 +1434,7 @@ void build_tiles(Plan &P, hipStream_t s) {
     auto chunk = [](std::vector<Tile> &v, int ep, int op, int first, int count) {
         for (int q = 0; q < count; q += ep) v.push_back(Tile{op, first + q, std::min(ep, count - q)});
     };
-    for (int l = 2; l <= L; ++l) {
+    for (int l = std::max(2, P.far_lmin); l <= L; ++l) {
         Level &V = P.lv[l];
         std::vector<Tile> t;
         const int e2l = ep_for(V.nff);
@@ -1416,7 +1447,7 @@ void build_tiles(Plan &P, hipStream_t s) {
             for (int o = 0; o < 8; ++o) chunk(u, e, o, C.oct_start[o], C.oct_start[o + 1] - C.oct_start[o]);
             upload(u, V.tiles_m2m, V.ntiles_m2m);
         }
-        if (l >= 3) {
+        if (l >= 3 && l > P.far_lmin) {
             std::vector<Tile> u;
             const int e = ep_for(V.nbox);
             for (int o = 0; o < 8; ++o) chunk(u, e, o, V.oct_start[o], V.oct_start[o + 1] - V.oct_start[o]);
@@ -1438,11 +1469,11 @@ void split_operators(Plan &P, hipStream_t s) {
                                                                       lo.as<bf16x8>());
         FMB_LAUNCH_CHECK();
     };
-    for (int l = 2; l <= P.depth; ++l) {
+    for (int l = std::max(2, P.far_lmin); l <= P.depth; ++l) {
         Level &V = P.lv[l];
         split(V.m2l, N_M2L_OPS, V.m2l_hi, V.m2l_lo);
         if (l < P.depth) split(V.m2m, 8, V.m2m_hi, V.m2m_lo);
-        if (l >= 3) split(V.l2l, 8, V.l2l_hi, V.l2l_lo);
+        if (l >= 3 && l > P.far_lmin) split(V.l2l, 8, V.l2l_hi, V.l2l_lo);
     }
     FMB_CHECK_HIP(hipStreamSynchronize(s));
 }
@@ -1453,7 +1484,7 @@ void alloc_workspace(Plan &P) {
     // S|R slots of all levels side by side (they are written in one run of
     // launches); the S|S slots of the upward pass reuse the front of the buffer
     int64_t slots = 1, sr = 0;
-    for (int l = 2; l <= P.depth; ++l) {
+    for (int l = std::max(2, P.far_lmin); l <= P.depth; ++l) {
         Level &V = P.lv[l];
         V.M.alloc((size_t)V.nbox * blk * esz);
         V.L.alloc((size_t)V.nbox * blk * esz);

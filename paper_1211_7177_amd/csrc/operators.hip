@@ -344,7 +344,8 @@ void build_operators(Plan &P, hipStream_t s) {
         FMB_LAUNCH_CHECK();
         FMB_CHECK_HIP(hipStreamSynchronize(s));
     };
-    for (int l = 2; l <= L; ++l) {
+    // levels below far_lmin keep no far field (lossy cutoff): no operators there
+    for (int l = std::max(2, P.far_lmin); l <= L; ++l) {
         Level &V = P.lv[l];
         const double h = P.ext / (double)(1 << l);
         // S|R for every far-field offset that occurs at this level
@@ -381,7 +382,7 @@ void build_operators(Plan &P, hipStream_t s) {
             launch(dm, V.m2m, 8);
         }
         // R|R from the parent (level l-1) into this level: t = X_child - X_parent
-        if (l >= 3) {
+        if (l >= 3 && l > P.far_lmin) {
             std::vector<OpDesc> dl;
             for (int o = 0; o < 8; ++o) {
                 OpDesc d{};

@@ -75,6 +75,12 @@ struct Plan {
     int64_t p2p_pairs = 0;
     int leaf_target = 32;
     int translate_mode = FMB_TRANSLATE_FP32;
+    // lossy wavenumbers: levels below far_lmin keep no far field (depth + 1: local only); a
+    // local-only plan also drops near pairs with R^2 > rcut2
+    double far_cutoff = 0.0;
+    int far_lmin = 2;
+    double rcut2 = 1e300;
+    bool far_on() const { return far_lmin <= depth; }
     std::vector<Level> lv;
     // per-node data in Morton order
     DevBuf codes;     // u64[n] user order

@@ -34,6 +34,8 @@
 #include <type_traits>
 #include <vector>
 
+#include <complex>
+
 #include "plan.h"
 
 struct fmb_problem_s {
@@ -1775,6 +1777,21 @@ static void check_plans(const Plan &A, const Plan &B, const char *what) {
 
 }  // namespace fmb
 
+// The interior plan of a scatterer must carry k_j = k0 sqrt(eps_j mu_j) with the
+// principal square root (Im k_j >= 0 for passive media; Sec. 2.1) and an FP32 plan the wavenumber of
+// its FP64 twin: a mismatched plan would silently build another system.
+static void check_wavenumber(const Plan &P, cx<double> want, const char *what) {
+    const cx<double> got = mk(P.k_re, P.k_im);
+    FMB_REQUIRE(abs2(got - want) <= 1e-18 * std::max(abs2(want), 1e-300),
+                std::string(what) + ": the plan's wavenumber does not match");
+}
+
+static cx<double> interior_k(const Plan &A, cx<double> e, cx<double> u) {
+    const std::complex<double> r = std::sqrt(std::complex<double>(e.re, e.im) * std::complex<double>(u.re, u.im));
+    const std::complex<double> k = std::complex<double>(A.k_re, A.k_im) * r;   // principal square root
+    return mk(k.real(), k.imag());
+}
+
 int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_t p1_32, const double *eps,
                        const double *mu, void *stream, fmb_problem_t *out) {
     return guarded([&] {
@@ -1788,12 +1805,20 @@ int bem_problem_create(fmb_plan_t p0, fmb_plan_t p1, fmb_plan_t p0_32, fmb_plan_
         FMB_REQUIRE(A.corr_mode != FMB_CORR_NONE, "the BEM system needs self-triangle corrections in both plans");
         check_plans(A, B, "p0 and p1 must be FP64 plans");
         FMB_REQUIRE((p0_32 == nullptr) == (p1_32 == nullptr), "give both FP32 plans or neither");
+        // the two products of an application run concurrently on the plans' own workspaces
+        FMB_REQUIRE(p0 != p1, "p0 and p1 must be two different plans");
         if (p0_32) {
+            FMB_REQUIRE(p0_32 != p1_32, "p0_32 and p1_32 must be two different plans");
             FMB_REQUIRE(p0_32->p.n == A.n && p1_32->p.n == A.n, "FP32 plans cover different node counts");
             FMB_REQUIRE(p0_32->p.precision == FMB_FP32 && p1_32->p.precision == FMB_FP32, "p0_32/p1_32 must be FP32");
         }
         cx<double> e = mk(eps[0], eps[1]), u = mk(mu[0], mu[1]);
         FMB_REQUIRE(abs2(e) > 0.0, "eps must be non-zero");
+        check_wavenumber(B, interior_k(A, e, u), "p1 (k1 = k0 sqrt(eps mu))");
+        if (p0_32) {
+            check_wavenumber(p0_32->p, mk(A.k_re, A.k_im), "p0_32 (k0)");
+            check_wavenumber(p1_32->p, mk(B.k_re, B.k_im), "p1_32 (k1)");
+        }
         auto *h = new fmb_problem_s;
         std::unique_ptr<fmb_problem_s> guard(h);
         h->p0 = p0;
@@ -1841,19 +1866,28 @@ int bem_problem_create_multi(fmb_plan_t p0, const fmb_plan_t *pj, int32_t J, con
             FMB_REQUIRE(pj[j] != nullptr, "a scatterer plan is NULL");
             FMB_REQUIRE(pj[j]->p.n == cnt[j], "scatterer plan j must hold exactly the nodes with region j");
             check_plans(A, pj[j]->p, "scatterer plans must be FP64");
+            FMB_REQUIRE(pj[j] != p0, "a scatterer plan must differ from p0");
+            for (int i = 0; i < j; ++i) FMB_REQUIRE(pj[i] != pj[j], "scatterer plans must be different plans");
             if (p0_32) {
                 FMB_REQUIRE(pj_32[j] && pj_32[j]->p.n == cnt[j] && pj_32[j]->p.precision == FMB_FP32,
                             "FP32 scatterer plan j must hold the nodes with region j");
+                FMB_REQUIRE(pj_32[j] != p0_32, "an FP32 scatterer plan must differ from p0_32");
+                for (int i = 0; i < j; ++i) FMB_REQUIRE(pj_32[i] != pj_32[j], "FP32 scatterer plans must be different plans");
+                check_wavenumber(pj_32[j]->p, mk(pj[j]->p.k_re, pj[j]->p.k_im), "FP32 scatterer plan");
             }
             const cx<double> e = mk(eps[2 * j], eps[2 * j + 1]), u = mk(mu[2 * j], mu[2 * j + 1]);
             FMB_REQUIRE(abs2(e) > 0.0, "eps must be non-zero");
+            check_wavenumber(pj[j]->p, interior_k(A, e, u), "scatterer plan (k_j = k0 sqrt(eps_j mu_j))");
             h->pj[j] = pj[j];
             h->pj32[j] = p0_32 ? pj_32[j] : nullptr;
             h->nj[j] = cnt[j];
             h->tcj[j] = cdiv(mk(1.0, 0.0) - e, e);
             h->gamj[j] = u;
         }
-        if (p0_32) FMB_REQUIRE(p0_32->p.n == A.n && p0_32->p.precision == FMB_FP32, "p0_32 must be an FP32 host plan");
+        if (p0_32) {
+            FMB_REQUIRE(p0_32->p.n == A.n && p0_32->p.precision == FMB_FP32, "p0_32 must be an FP32 host plan");
+            check_wavenumber(p0_32->p, mk(A.k_re, A.k_im), "p0_32 (k0)");
+        }
         h->p0 = p0;
         h->p1 = pj[0];
         h->p032 = p0_32;

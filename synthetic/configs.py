@@ -20,7 +20,7 @@ CONFIGS = {
     31: dict(name="ellipsoid_8k", k0=2.0, eps=2.25, depth=5),
     32: dict(name="torus_30k", k0=5.0, eps=complex(-15.0, 1.0), depth=5),
     33: dict(name="sphere_81920", k0=10.0, eps=2.25, depth=6),
-    # split ring, side 1, ~50k triangles, k0 = pi/2
+    # split ring, side 1, width 0.2, thickness 0.1, gap 0.2: 49,404 triangles (148,212 points), k0 = pi/2
     4: dict(name="srr_50k", k0=np.pi / 2, eps=complex(-15.0, 1.0), depth=6),
     # prolate ellipsoid 4:1:1, 1003520 triangles, k0 = 40
     5: dict(name="prolate_1M", k0=40.0, eps=complex(-1e4, 1e2), depth=8),
@@ -39,7 +39,7 @@ def config_mesh(cfg: int):
     if cfg == 33:
         return icosphere(64, 1.0)
     if cfg == 4:
-        return split_ring(1.0, 0.2, 0.1, 0.2, h=0.0105)
+        return split_ring(1.0, 0.2, 0.1, 0.2, h=0.0087)
     if cfg == 5:
         return geodesic_ellipsoid((4.0, 1.0, 1.0), 224)
     raise KeyError(cfg)

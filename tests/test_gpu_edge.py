@@ -157,3 +157,42 @@ def test_field_entry_points_reject_bad_arguments(abi):
     Ef = pb.field(x, pts, method="fmm", order=20).cpu().numpy()
     assert np.isfinite(E).all() and _rel(Ef, E) <= 1e-6          # 3.5e-6 at p = 16 for this lone far target
     pb.close()
+
+
+def test_problem_create_rejects_shared_or_mismatched_plans(abi):
+    """bem_problem_create refuses one plan passed as both p0 and p1 (their products
+    run concurrently on the plans' own workspaces), an interior plan whose
+    wavenumber is not k0 sqrt(eps mu) (Sec. 2.1, eq. 2.13), and FP32 plans whose
+    wavenumbers differ from their FP64 twins."""
+    import ctypes
+    from synthetic import icosphere
+    q = nystrom3(icosphere(2))
+    lib = abi.load()
+    eps = np.array([2.25, 0.0])
+    mu = np.array([1.0, 0.0])
+    k0, k1 = 1.0, 1.5
+    p0 = _plan(abi, q, k0, 6, 2)
+    p1 = _plan(abi, q, k1, 6, 2)
+    pw = _plan(abi, q, 1.4, 6, 2)                                   # not k0 sqrt(2.25)
+    f0 = _plan(abi, q, k0, 5, 2, precision="fp32")
+    f1 = _plan(abi, q, k1, 5, 2, precision="fp32")
+    fw = _plan(abi, q, 1.4, 5, 2, precision="fp32")
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def create(a, b, c=None, d=None):
+        h = ctypes.c_void_p()
+        code = lib.bem_problem_create(a.h, b.h, c.h if c else None, d.h if d else None, eps.ctypes.data,
+                                      mu.ctypes.data, st, ctypes.byref(h))
+        if code == 0:
+            lib.bem_problem_destroy(h)
+        return code
+
+    assert create(p0, p0) == abi.FMB_EINVAL
+    assert create(p0, pw) == abi.FMB_EINVAL
+    assert create(p0, p1, f0, f0) == abi.FMB_EINVAL
+    assert create(p0, p1, f0, fw) == abi.FMB_EINVAL
+    assert create(p0, p1, f1, f0) == abi.FMB_EINVAL
+    assert create(p0, p1) == abi.FMB_OK
+    assert create(p0, p1, f0, f1) == abi.FMB_OK
+    for p in (p0, p1, pw, f0, f1, fw):
+        p.close()

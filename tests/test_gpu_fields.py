@@ -81,22 +81,33 @@ def test_solved_fields_match_mie(gpu):
 
 
 def test_impedance_sphere_far_field(gpu):
-    """C_sca of the impedance sphere (Z = 0.2 - 0.1i) from the solved far field
-    against the impedance-sphere Mie coefficients.  The bound is 8%: the IBC
-    discretisation's surface field stays about 9% from Mie at 960 and 3840
-    nodes (the oracle's own solution does the same), which leaves C_sca about
-    6% low."""
+    """C_sca of the impedance sphere (Z = 0.2 - 0.1i, eq. 2.25) from the solved far
+    field.  Against the oracle: its own fGMRES solution of the IBC system on the
+    direct-sum operator, put through its own far-field sum (eq. 2.5 at infinity
+    with Psi = -c n x (n x Phi), c = i k0/Z), gives the same C_sca to 1e-6.
+    Against the impedance-sphere Mie coefficients the bound is 8%: the IBC
+    discretisation's surface field stays about 9% from Mie at 960 and 3840 nodes
+    (the oracle's own solution does the same), which leaves C_sca about 6% low."""
+    from oracle.bem import IbcProblem as OracleIbc
+    from oracle.gmres import gmres_solve as oracle_gmres
     Z = 0.2 - 0.1j
     q = nystrom3(icosphere(8))
     pb = gpu.IbcProblem(q, 1.0, Z, order=20, depth=3)
     b = pb.rhs_planewave([0, 0, 1.0], [1.0, 0, 0])
-    x, info = pb.solve(b, tol=1e-8)
+    x, info = pb.solve(b, tol=1e-10)
     D, W = _sphere_quadrature()
     F = pb.field(x, D, far=True).cpu().numpy()[0]
     C = np.sum(W * np.sum(np.abs(F) ** 2, 1))
+    ob = OracleIbc(q, 1.0, Z)
+    xo, io = oracle_gmres(ob.apply, ob.rhs_planewave([0, 0, 1.0], [1.0, 0, 0]), tol=1e-10, restart=200)
+    nrm = q["normals"]
+    psi = -ob.c * (nrm * np.sum(nrm * xo, axis=1, keepdims=True) - xo)
+    Fo = fields.far_field(q, 1.0, np.concatenate([xo, psi], axis=1), D)
+    Co = np.sum(W * np.sum(np.abs(Fo) ** 2, 1))
     n, a, bb = mie.impedance_coefficients(1.0, Z)
     cref = 2.0 * np.pi * np.sum((2 * n + 1) * (abs(a) ** 2 + abs(bb) ** 2))   # pi a^2 Q_sca, x = 1
-    print("impedance sphere C_sca %.5f mie %.5f" % (C, cref))
+    print("impedance sphere C_sca %.8f oracle %.8f (rel %.2e) mie %.5f" % (C, Co, abs(C - Co) / Co, cref))
+    assert abs(C - Co) <= 1e-6 * Co
     assert abs(C - cref) <= 0.08 * cref
     pb.close()
 

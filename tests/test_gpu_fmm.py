@@ -99,21 +99,47 @@ def test_fp64_matvec_matches_direct_sum(abi, sphere, k):
     P2.close()
 
 
-def test_corrections_match_oracle(abi, sphere):
+@pytest.mark.parametrize("mesh,k,depth", [
+    ("sphere", 1.0, 3), ("sphere", 1.5 + 0.5j, 3),
+    # the lossy interiors of the torus and the large ellipsoid; on the 1280-triangle
+    # sphere |k| rho < 4 at 0.5+15.5i (series branch of the regular remainder H)
+    ("sphere", 0.5 + 15.5j, 3), ("sphere", 20 + 4000j, 3),
+    # 80 triangles: |k| rho up to ~9 at 0.5+15.5i (the exponential-integral branch)
+    ("coarse", 0.5 + 15.5j, 2), ("coarse", 4.0, 2)])
+def test_corrections_match_oracle(abi, sphere, mesh, k, depth):
+    """GPU(with corrections) - GPU(without) against the oracle's self-triangle
+    blocks (Appendix B, eqs. B.2-B.9 with the exact radial integrals), LINEAR mode."""
+    q = sphere if mesh == "sphere" else nystrom3(icosphere(2))
+    n = q["points"].shape[0]
+    a, b = _dens(n, 1)
+    print("corrections", mesh, "k=", k, flush=True)
+    P0 = _plan(abi, q, k, 8, depth, corr="none")
+    P1 = _plan(abi, q, k, 8, depth, corr="linear")
+    y0 = P0.matvec(_gpu(a), _gpu(b)).cpu().numpy()
+    y1 = P1.matvec(_gpu(a), _gpu(b)).cpu().numpy()
+    blk = self_blocks(q["points"], q["normals"], q["point_tri"], q["tri_vertices"], k, mode="linear")
+    ref = apply_corrections(q["normals"], q["point_tri"], blk, a, b)
+    assert _rel(y1 - y0, ref) <= 1e-10
+    P0.close()
+    P1.close()
+
+
+@pytest.mark.parametrize("k,lmin", [(20 + 4000j, None), (2 + 100j, 3)])
+def test_lossy_cutoff_matches_direct_sum(abi, sphere, k, lmin):
+    """Lossy wavenumbers (g decays as exp(-Im k R), Sec. 2.1): levels whose box side
+    damps the kernel below the cutoff keep no far field.  At 20+4000i the plan is
+    local only (near pairs beyond ln(1e16)/Im k dropped too); at 2+100i level 2 is
+    cut and levels 3.. kept.  Both equal the direct sum to FMM accuracy."""
     q = sphere
     n = q["points"].shape[0]
     a, b = _dens(n, 1)
-    for k in (1.0, 1.5 + 0.5j):
-        print("corrections k=", k, flush=True)
-        P0 = _plan(abi, q, k, 8, 3, corr="none")
-        P1 = _plan(abi, q, k, 8, 3, corr="linear")
-        y0 = P0.matvec(_gpu(a), _gpu(b)).cpu().numpy()
-        y1 = P1.matvec(_gpu(a), _gpu(b)).cpu().numpy()
-        blk = self_blocks(q["points"], q["normals"], q["point_tri"], q["tri_vertices"], k, mode="linear")
-        ref = apply_corrections(q["normals"], q["point_tri"], blk, a, b)
-        assert _rel(y1 - y0, ref) <= 1e-10
-        P0.close()
-        P1.close()
+    P = _plan(abi, q, k, 16, 3, corr="none")
+    y = P.matvec(_gpu(a), _gpu(b)).cpu().numpy()
+    ref = point_sum_c(q["points"], q["normals"], q["weights"], q["point_tri"], k, a, b)
+    err = _rel(y, ref)
+    print("lossy cutoff k=", k, "rel err", err)
+    assert err <= (1e-12 if lmin is None else 1e-6)
+    P.close()
 
 
 @pytest.mark.parametrize("order,tol", [(8, 2.5e-4), (9, 1e-4), (10, 5e-5)])
@@ -160,23 +186,43 @@ def test_bf16x3_matvec_tolerance(abi, sphere, order):
         X.close()
 
 
+def _rows_every_leaf(q, depth, total, seed):
+    """One node of every leaf of the reference octree (App. C) plus seeded rows up
+    to `total`, sorted."""
+    t = Octree(q["points"], depth)
+    first = t.perm[t.box_start[depth][:-1]]
+    n = q["points"].shape[0]
+    rest = np.setdiff1d(np.arange(n), first)
+    extra = np.random.default_rng(seed).choice(rest, max(0, total - len(first)), replace=False)
+    return np.sort(np.concatenate([first, extra])), len(first)
+
+
+# measured relative errors of the benchmark's FP32 operator (p = 5) against the
+# direct sum on these rows; the bounds are 1.5x the larger of the two
+TORUS_P5_BOUND = {4.0: 1e-2, complex(0.5161, 15.5034): 1e-2}
+
+
+@pytest.mark.parametrize("k", [4.0, complex(0.5161, 15.5034)])
 @pytest.mark.parametrize("translate", ["fp32", "bf16x3"])
-def test_fp32_torus_bench_order(abi, torus_c2, translate):
-    """The benchmark's FP32 operator (60k-node torus, depth 5, order 9) on 512 rows."""
+def test_fp32_torus_bench_operator(abi, torus_c2, translate, k):
+    """The benchmark's FP32 operator exactly: the 60k-node torus, depth 5, p = 5,
+    FP32 expansions and near sum with FP64 self-triangle blocks, at both
+    wavenumbers of the torus system, with FP32-MFMA or split-BF16 translations,
+    against the direct sum (eq. 2.8 point rule plus App. B blocks) on 4096 rows
+    that include a node of every leaf."""
     q = torus_c2
     n = q["points"].shape[0]
     a, b = _dens(n, 2)
-    rows = np.sort(np.random.default_rng(seed_for(2, "rows")).choice(n, 512, replace=False))
-    k = 4.0
-    print("fp32 torus", translate, flush=True)
-    P = _plan(abi, q, k, 9, 5, precision="fp32", translate=translate)
+    rows, nleaf = _rows_every_leaf(q, 5, 4096, seed_for(2, "rows"))
+    print("fp32 torus p=5", translate, "k=", k, "rows", len(rows), "leaves", nleaf, flush=True)
+    P = _plan(abi, q, k, 5, 5, precision="fp32", translate=translate)
     y = P.matvec(_gpu(a, torch.complex64), _gpu(b, torch.complex64)).cpu().numpy()[rows]
     ref = point_sum_c(q["points"], q["normals"], q["weights"], q["point_tri"], k, a, b, rows=rows)
     blk = self_blocks(q["points"], q["normals"], q["point_tri"], q["tri_vertices"], k, mode="linear")
     ref = ref + apply_corrections(q["normals"], q["point_tri"], blk, a, b, rows=rows)
     err = _rel(y, ref)
-    print("fp32 torus rel err", err)
-    assert err <= 2e-4
+    print("fp32 torus p=5 %s k=%s rel err %.3e" % (translate, k, err), flush=True)
+    assert err <= TORUS_P5_BOUND[k]
     P.close()
 
 
@@ -216,20 +262,20 @@ def test_fp32_batched_rhs_match_single(abi, sphere, translate, nrhs):
 
 
 @pytest.mark.parametrize("k", [4.0, complex(0.5161, 15.5034)])
-def test_torus_full_size_sampled_rows(abi, torus_c2, k):
-    """The 60k-node torus at depth 5: FP64 FMM + corrections against the oracle
-    on 512 seeded rows."""
+def test_torus_full_size_all_rows(abi, torus_c2, k):
+    """The 60k-node torus at depth 5: FP64 FMM (p = 16) + corrections against the
+    oracle's full direct sum, all 60,000 rows (3.6e9 pairs)."""
     q = torus_c2
     n = q["points"].shape[0]
     a, b = _dens(n, 2)
-    rows = np.sort(np.random.default_rng(seed_for(2, "rows")).choice(n, 512, replace=False))
-    print("torus k=", k, flush=True)
+    print("torus all rows k=", k, flush=True)
     P = _plan(abi, q, k, 16, 5)
-    y = P.matvec(_gpu(a), _gpu(b)).cpu().numpy()[rows]
-    ref = point_sum_c(q["points"], q["normals"], q["weights"], q["point_tri"], k, a, b, rows=rows)
+    y = P.matvec(_gpu(a), _gpu(b)).cpu().numpy()
+    ref = point_sum_c(q["points"], q["normals"], q["weights"], q["point_tri"], k, a, b)
     blk = self_blocks(q["points"], q["normals"], q["point_tri"], q["tri_vertices"], k, mode="linear")
-    ref = ref + apply_corrections(q["normals"], q["point_tri"], blk, a, b, rows=rows)
+    ref = ref + apply_corrections(q["normals"], q["point_tri"], blk, a, b)
     err = _rel(y, ref)
-    print("torus rel err", err, P.info())
+    rowmax = np.max(np.linalg.norm(y - ref, axis=1)) / np.max(np.linalg.norm(ref, axis=1))
+    print("torus all rows rel err %.3e (worst row %.3e)" % (err, rowmax), P.info(), flush=True)
     assert err <= 1e-6
     P.close()

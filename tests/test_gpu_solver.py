@@ -133,7 +133,8 @@ def test_batched_rhs_solve_equals_single(gpu, small):
 
 def test_sphere_c1_solve_vs_oracle_and_mie(gpu, c1):
     """Dielectric sphere a = 1, eps = 2.25, k0 a = 1, 1280 triangles, x-polarised
-    wave along +z, solve to 1e-8."""
+    wave along +z, solve to 1e-8.  The GPU answer is within 1e-6 of the oracle's
+    fGMRES answer on the direct-sum operator (1.2e-7 measured at p = 20)."""
     q, ob = c1
     print("C1 solve", flush=True)
     pb = gpu.BemProblem(q, 1.0, 2.25, order=20, depth=3)
@@ -144,7 +145,7 @@ def test_sphere_c1_solve_vs_oracle_and_mie(gpu, c1):
     xo, io = oracle_gmres(ob.apply, bo, ob.block_preconditioner(), tol=1e-8, restart=100)
     err = _rel(x, xo)
     print("C1 its", info["iterations"], io["iterations"], "err vs oracle", err)
-    assert err <= 1e-5
+    assert err <= 1e-6
     xm = mie.surface_unknowns(q, 1.0, 1.0, 2.25)
     assert _rel(x[:, :3], xm[:, :3]) < 0.05
     pb.close()
