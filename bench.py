@@ -1,14 +1,16 @@
-"""Benchmark: GMRES solves/s (and FMM matvecs/s) at 1e-6 relative residual on
-the 60k-node silver-like torus (R = 1, r = 0.3, 200 x 50 x 2 triangles,
-eps = -15 + 1i, k0 R = 4, octree depth 5), FP32/mixed-precision against the
-plain FP64 solve, on one MI355X.
+"""Benchmark: FMM matvecs/s and GMRES solves/s at 1e-6 relative error, FP32 against plain FP64,
+on one MI355X.
 
-One timed step is one right-preconditioned fGMRES solve of the 6N system for a
-seeded plane wave with the product path: FP32 FMM operators inside an FP64
-iterative refinement (gather, P2M, M2M, M2L, L2L, L2P, P2P, FP64 self-triangle
-corrections, BEM apply, block preconditioner, Arnoldi), to a true FP64
-residual <= 1e-6.  Plans (octree, operators, correction blocks) are built
-once before the timed region from host arrays.
+Headline workload: the large PEC-like prolate ellipsoid (semi-axes 4:1:1, 1,003,520 triangles, 3,010,560 nodes,
+18.1M unknowns, eps = -1e4 + 1e2 i, k0 = 40 along the minor semi-axis a = 1, octree depth 8).  One timed step is
+the FP32 fast-multipole product of both wavenumbers on seeded complex64 densities: the exterior k0 = 40 plan
+(orders per level from the leaves to level 2, rotation / coaxial translations) and the local-only interior plan
+(k1 = 20 + 4000i); gather, P2M, M2M, M2L, L2L, L2P, P2P and the FP64 self-triangle corrections.  Plans are
+built from host arrays and the densities are resident in HBM before timing starts.  Beside it: the FP64
+products, their accuracy against the oracle on sampled rows, a full mixed-precision fGMRES solve of the
+18.1M-unknown system, the roofline of the near field and the M2L translations, and the oracle's direct sum
+timed on the host cores.  The 60k-node torus section compares whole solves (FP32 inner / FP64 refinement
+against plain FP64) at equal accuracy.
 
 Prints one JSON line.
 """
@@ -31,8 +33,16 @@ PEAK = {"hbm_GBs": 8000.0, "fp64_TF": 78.6, "fp32_TF": 157.3, "bf16_TF": 2500.0}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed FP32 products of the large-ellipsoid workload")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--c5-tol32", type=float, default=1e-4, help="FP32 plans: accuracy the per-level orders target")
+    ap.add_argument("--c5-tol64", type=float, default=1e-6, help="FP64 plans: accuracy the per-level orders target")
+    ap.add_argument("--c5-rows", type=int, default=1024, help="seeded oracle rows of the large-ellipsoid checks")
+    ap.add_argument("--c5-solve-maxit", type=int, default=1500,
+                    help="iteration cap of the large-ellipsoid solve (0: skip the solve)")
+    ap.add_argument("--skip-torus", action="store_true", help="skip the 60k-node torus solve comparison")
+    ap.add_argument("--torus-steps", type=int, default=3)
+    ap.add_argument("--torus-warmup", type=int, default=1)
     ap.add_argument("--order64", type=int, default=16)
     ap.add_argument("--order32", type=int, default=5)
     ap.add_argument("--tol", type=float, default=1e-6)
@@ -48,8 +58,8 @@ def parse():
                     help="also time the gold-dimer optical-force workload from mesh to force")
     ap.add_argument("--three-meshes", action="store_true",
                     help="also solve the batched three-mesh workload (ellipsoid, torus, sphere at full size)")
-    ap.add_argument("--skip-split-ring", action="store_true",
-                    help="skip the split-ring solves and product rates reported beside the main workload")
+    ap.add_argument("--split-ring", action="store_true",
+                    help="also run the split-ring solves and product rates (49k triangles)")
     ap.add_argument("--translate32", choices=["fp32", "bf16x3"], default="bf16x3")
     ap.add_argument("--batch", type=int, default=8,
                     help="also time one lockstep solve of this many plane waves (0: skip)")
@@ -263,12 +273,12 @@ def dimer_section(log, nu=17):
     return out
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
+def torus_section(args, log):
+    """The silver-like torus system (R = 1, r = 0.3, 20,000 triangles, 60,000 nodes, eps = -15 + 1i, k0 R = 4,
+    depth 5): timed mixed-precision solves (FP32 FMM and Krylov vectors inside FP64 refinement) against the plain
+    FP64 solve, both to a relative FP64 residual of args.tol, with their forward errors against the oracle's own
+    solution of the same system when it is present (tests/golden), the FMM product rates and the roofline of the
+    FP32 near field and translations."""
     import torch
     from paper_1211_7177_amd.solver import BemProblem
     from synthetic import config_mesh, nystrom3, plane_waves, seed_for, CONFIGS
@@ -308,20 +318,20 @@ def main():
         return pb.solve(rhs, tol=args.tol, mixed=True, inner_tol=args.inner_tol, restart=args.restart, maxit=2000,
                         serial=serial, inner_reorth=args.inner_reorth)
 
-    for _ in range(args.warmup):
+    for _ in range(args.torus_warmup):
         _, wi = step()
-        log("warmup solve", wi)
+        log("torus warmup solve", wi["iterations"], wi["refinements"], wi["residual"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
-    for _ in range(args.steps):
+    for _ in range(args.torus_steps):
         x, inf = step()
         infos.append(inf)
-        log("timed solve", inf["iterations"], inf["refinements"], inf["residual"])
+        log("torus timed solve", inf["iterations"], inf["refinements"], inf["residual"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms_per_step = 1e3 * dt / args.steps
-    solves_per_s = args.steps / dt
+    ms_per_step = 1e3 * dt / args.torus_steps
+    solves_per_s = args.torus_steps / dt
     last = infos[-1]
     # one more solve of the same system with HIP events around the near-field
     # and translation launches of both FP32 plans; the roofline below uses their
@@ -397,6 +407,21 @@ def main():
         fp64 = {"solves_per_s": 1.0 / t64, "ms_per_solve": 1e3 * t64, "iterations": inf64["iterations"],
                 "bem_applies": inf64["matvecs64"], "residual": inf64["residual"],
                 "rel_diff_vs_mixed_solution": diff}
+    # forward error of both timed solutions against the oracle's own solution of the same discrete system
+    # (fGMRES on the direct-sum operator to 1e-10, written by tests/golden/make_torus_oracle_solution.py)
+    forward = None
+    ref_path = os.path.join(ROOT, "tests", "golden", "torus60k_oracle_solution.npy")
+    if os.path.exists(ref_path):
+        xr = np.load(ref_path)
+        nr = np.linalg.norm(xr)
+        forward = {"mixed": float(np.linalg.norm(x[0].cpu().numpy() - xr) / nr)}
+        if fp64 is not None:
+            forward["fp64"] = float(np.linalg.norm(x64[0].cpu().numpy() - xr) / nr)
+        meta = os.path.join(ROOT, "tests", "golden", "torus60k_oracle_solution.json")
+        if os.path.exists(meta):
+            with open(meta) as f:
+                forward["oracle_solution"] = json.load(f)
+        log("forward error against the oracle solution", forward)
 
     # FMM matvec rates and stage profile (HIP events on the stream the kernels run on)
     rates = {}
@@ -473,7 +498,7 @@ def main():
         log("copy calibration: 256 MiB device-to-device copy done", buf2.numel())
     log("roofline", stages_rf)
 
-    ring = None if args.skip_split_ring else split_ring_section(log)
+    ring = split_ring_section(log) if args.split_ring else None
     three = three_meshes_section(log) if args.three_meshes else None
     dimer = dimer_section(log) if args.dimer else None
 
@@ -493,21 +518,12 @@ def main():
                            fp64["bem_applies"] if fp64 else last["matvecs64"] + last["matvecs32"])
 
     out = {
-        "metric": "FMM matvecs/s & GMRES solves/s at 1e-6 rel err, FP32/batched vs plain FP64",
-        "value": solves_per_s,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
+        "solves_per_s": solves_per_s,
+        "ms_per_solve": ms_per_step,
+        "timed_solves": args.torus_steps,
         "precision": "FP32 FMM (split-BF16 MFMA translations with FP32 accumulation when translate_fp32 is "
                      "bf16x3) and FP32 inner Krylov vectors; FP64 self-triangle corrections, inner products, "
                      "Hessenberg/Givens, residuals and the refinement iterate",
-        "data": "synthetic",
         "config": {"workload": "torus_R1_r0.3_20000tri_60000nodes_eps-15+1i_k0R4_depth5_planewave",
                    "nodes": n, "unknowns": 6 * n, "depth": depth, "order_fp64": args.order64,
                    "order_fp32": args.order32, "translate_fp32": args.translate32, "tol": args.tol,
@@ -519,6 +535,7 @@ def main():
         "batched": batched,
         "autotune": tuned,
         "fp64_solve": fp64,
+        "forward_error_vs_oracle_solution": forward,
         "adjoint_solve": adjoint,
         "split_ring": ring,
         "three_meshes": three,
@@ -536,7 +553,8 @@ def main():
         "profiled_solve_kernel_ms": {s: v[0] for s, v in timed.items() if v[1]},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out))
+    pb.close()
+    return out
 
 
 def oracle_residual_rows(nodes, k0, eps, x, b, nrows):
@@ -600,6 +618,268 @@ def cpu_baseline(nodes, k0, eps, rows, applies_per_solve):
                       "scaled by n/rows to one apply (%.1f s) and by the %d applies of one FP64 fGMRES solve" %
                       (len(sel), n, dt, apply_s, applies_per_solve),
             "applies_per_s": 1.0 / apply_s}
+
+
+
+
+def _wsize(p):
+    """sum_{n<p} (2n+1)^2: entries of the rotation matrices of degrees below p."""
+    return p * (2 * p - 1) * (2 * p + 1) // 3
+
+
+def _csum(p):
+    """sum_{|m|<p} (p-|m|)^2: entries of the coaxial shift of order p."""
+    return p * p + (p - 1) * p * (2 * p - 1) // 3
+
+
+def hf_translation_flops(p):
+    """Algorithmic flops of one rotation / coaxial-shift / rotation translation of the 3 channels at order p:
+    two real rotations of a complex vector (4 flops per entry) and one complex coaxial shift (8 flops per entry)."""
+    return 3 * (8 * _wsize(p) + 8 * _csum(p))
+
+
+C5_NAME = "prolate_ellipsoid_4x1x1_1003520tri_3010560nodes_eps-1e4+1e2i_k0a40_depth8"
+
+
+def c5_workload(args, log):
+    """The large PEC-like prolate ellipsoid: plans, timed FP32 products, FP64 products, roofline, the oracle leg
+    on sampled rows and one mixed-precision solve."""
+    import torch
+    from paper_1211_7177_amd.solver import BemProblem
+    from synthetic import CONFIGS, complex_normal, config_mesh, nystrom3, plane_waves, seed_for
+    cfg = CONFIGS[5]
+    t0 = time.perf_counter()
+    nodes = nystrom3(config_mesh(5))
+    n = nodes["points"].shape[0]
+    log("c5 mesh: %d nodes in %.1f s" % (n, time.perf_counter() - t0))
+    t0 = time.perf_counter()
+    pb = BemProblem(nodes, cfg["k0"], cfg["eps"], order=0, depth=cfg["depth"], order32=0, tol=args.c5_tol64,
+                    tol32=args.c5_tol32)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    infos = {t: p.info() for t, p in (("k0_fp64", pb.p0), ("k1_fp64", pb.p1), ("k0_fp32", pb.p0_32),
+                                      ("k1_fp32", pb.p1_32))}
+    log("c5 plans built in %.1f s" % plan_s, {t: (i["order_level"], i["far_lmin"], i["device_bytes"] / 1e9)
+                                              for t, i in infos.items()})
+    a64 = complex_normal((1, n, 3), seed_for(5, "a"))
+    b64 = complex_normal((1, n, 3), seed_for(5, "b"))
+    ga = {"fp32": torch.from_numpy(a64.astype(np.complex64)).cuda(),
+          "fp64": torch.from_numpy(a64).cuda()}
+    gb = {"fp32": torch.from_numpy(b64.astype(np.complex64)).cuda(),
+          "fp64": torch.from_numpy(b64).cuda()}
+    plans = {"fp32": (pb.p0_32, pb.p1_32), "fp64": (pb.p0, pb.p1)}
+    ys = {t: (torch.empty_like(ga[t]), torch.empty_like(ga[t])) for t in plans}
+
+    def step(t):
+        p0, p1 = plans[t]
+        p0.matvec(ga[t], gb[t], out=ys[t][0])
+        p1.matvec(ga[t], gb[t], out=ys[t][1])
+
+    for _ in range(args.warmup):
+        step("fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step("fp32")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms32 = 1e3 * dt / args.steps
+    log("c5 FP32 products: %.2f ms per step (%d steps)" % (ms32, args.steps))
+    step("fp64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps64 = 3
+    for _ in range(reps64):
+        step("fp64")
+    torch.cuda.synchronize()
+    ms64 = 1e3 * (time.perf_counter() - t0) / reps64
+    log("c5 FP64 products: %.2f ms per step" % ms64)
+
+    # stage profile (HIP events on the plans' stream) of the exterior FP32 plan
+    prof = {}
+    for t in ("fp32", "fp64"):
+        p0 = plans[t][0]
+        p0.profile(True)
+        p0.profile_read(reset=True)
+        reps = 3 if t == "fp32" else 1
+        for _ in range(reps):
+            p0.matvec(ga[t], gb[t], out=ys[t][0])
+        torch.cuda.synchronize()
+        prof[t] = {k: (v[0] / reps, v[1] // reps) for k, v in p0.profile_read(reset=True).items() if v[1]}
+        p0.profile(False)
+    log("c5 exterior stage ms per product", prof)
+    inf = infos["k0_fp32"]
+    p2p_pairs = inf["p2p_pairs"] - 3 * n
+    p2p_fl = P2P_FLOPS_PER_PAIR * p2p_pairs
+    m2l_fl = sum(inf["m2l_pairs"][l] * hf_translation_flops(inf["order_level"][l]) for l in range(len(inf["m2l_pairs"])))
+    st = prof["fp32"]
+    p2p_ms, m2l_ms = st["p2p"][0], st["m2l"][0]
+    m2l_launches = max(1, st["m2l"][1])
+    stages_rf = {
+        "p2p": {"kernel": "k_p2p32 (near field, FP32 VALU)", "bound": "alu", "peak": PEAK["fp32_TF"],
+                "unit": "TFLOP/s", "achieved": p2p_fl / (p2p_ms * 1e-3) / 1e12, "per_launch_flops": p2p_fl,
+                "avg_launch_ms": p2p_ms, "launches_per_product": 1, "traffic": measured_traffic("k_p2p32 c5"),
+                "gpairs_per_s": p2p_pairs / (p2p_ms * 1e-3) / 1e9},
+        "m2l": {"kernel": "k_hf_m2l (rotation / coaxial-shift S|R, FP32 VALU, one launch per level)",
+                "bound": "alu", "peak": PEAK["fp32_TF"], "unit": "TFLOP/s",
+                "achieved": m2l_fl / (m2l_ms * 1e-3) / 1e12, "per_launch_flops": m2l_fl / m2l_launches,
+                "avg_launch_ms": m2l_ms / m2l_launches, "launches_per_product": m2l_launches,
+                "traffic": measured_traffic("k_hf_m2l c5"),
+                "pairs_per_level": inf["m2l_pairs"], "order_per_level": inf["order_level"]},
+    }
+    for v in stages_rf.values():
+        v["frac"] = v["achieved"] / v["peak"]
+    dominant = "m2l" if m2l_ms >= p2p_ms else "p2p"
+    roofline = dict(stages_rf[dominant])
+    log("c5 roofline", stages_rf)
+
+    # one mixed-precision solve of the 18.1M-unknown system for a seeded plane wave
+    solve = None
+    if args.c5_solve_maxit > 0:
+        d, pol = plane_waves(1, seed_for(5, "dirs"), seed_for(5, "pols"))
+        rhs = pb.rhs_planewave(d, pol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = pb.solve(rhs, tol=1e-6, mixed=True, inner_tol=1e-2, restart=100, maxit=args.c5_solve_maxit,
+                           raise_on_noconv=False)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        solve = {"seconds": ts, "solves_per_s": 1.0 / ts, "iterations": info["iterations"],
+                 "refinements": info["refinements"], "residual": info["residual"],
+                 "converged": info["residual"] <= 1e-6, "bem_applies_fp32": info["matvecs32"],
+                 "bem_applies_fp64": info["matvecs64"], "fp64_fallback": info["fp64_fallback"],
+                 "tol": 1e-6, "restart": 100, "inner_tol": 1e-2}
+        log("c5 solve", solve)
+        del x, rhs
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu, acc = c5_cpu_baseline(nodes, cfg, a64[0], b64[0], args.c5_rows,
+                                   {t: (ys[t][0][0].cpu().numpy(), ys[t][1][0].cpu().numpy()) for t in plans})
+        log("c5 oracle leg", cpu, acc)
+    else:
+        acc = None
+    out = {
+        "value": 1e3 / ms32, "ms_per_step": ms32,
+        "config": {"workload": C5_NAME, "nodes": n, "unknowns": 6 * n, "depth": cfg["depth"], "k0": cfg["k0"],
+                   "eps": str(cfg["eps"]), "k1": str(pb.k1), "tol_fp32": args.c5_tol32, "tol_fp64": args.c5_tol64,
+                   "order_per_level_fp32": infos["k0_fp32"]["order_level"],
+                   "order_per_level_fp64": infos["k0_fp64"]["order_level"],
+                   "interior_plan": "local only (far field damped below 1e-8 / 1e-16 at every level)",
+                   "step": "FP32 FMM products at k0 and k1 on seeded complex64 densities (one BEM application's "
+                           "products)"},
+        "fmm_matvecs_per_s": {"fp32": 1e3 / ms32, "fp64": 1e3 / ms64},
+        "unknowns_matvec_per_s": {"fp32": 6 * n * 1e3 / ms32, "fp64": 6 * n * 1e3 / ms64},
+        "speedup_fp32_vs_fp64_products": ms64 / ms32,
+        "stage_ms_per_product_k0": prof,
+        "plan_s_4plans": plan_s,
+        "plan_info": {t: {k: i[k] for k in ("nbox", "m2l_pairs", "p2p_pairs", "device_bytes", "order_level",
+                                            "far_lmin")} for t, i in infos.items()},
+        "roofline": roofline, "roofline_stages": stages_rf,
+        "product_error_vs_oracle_rows": acc,
+        "solve": solve,
+        "cpu_baseline": cpu,
+    }
+    pb.close()
+    return out
+
+
+def c5_cpu_baseline(nodes, cfg, a, b, nrows, gpu_rows):
+    """The oracle leg of the large ellipsoid: its direct FP64 sum of both wavenumbers' operators (point sum plus
+    LINEAR self-triangle blocks) on `nrows` seeded target rows with all host cores, timed and scaled to one full
+    BEM application; the same timing on one core over a smaller sample (a child process with
+    OMP_NUM_THREADS=1); and the relative error of the GPU products on those rows."""
+    import subprocess
+    from oracle.corrections import self_blocks
+    from oracle.direct import apply_corrections
+    from oracle.kernel import wavenumber
+    from oracle.native import point_sum_c
+    from synthetic import seed_for
+    n = nodes["points"].shape[0]
+    rows = np.sort(np.random.default_rng(seed_for(5, "rows")).choice(n, nrows, replace=False))
+    k0 = cfg["k0"]
+    k1 = wavenumber(k0, cfg["eps"])
+    pts, nrm, w, pt = nodes["points"], nodes["normals"], nodes["weights"], nodes["point_tri"]
+    tris = np.unique(pt[rows])
+    sub = (3 * tris[:, None] + np.arange(3)[None, :]).reshape(-1)
+    remap = np.repeat(np.arange(len(tris)), 3)
+    loc = np.searchsorted(sub, rows)
+    t0 = time.perf_counter()
+    ref = {}
+    for tag, k in (("k0", k0), ("k1", k1)):
+        y = point_sum_c(pts, nrm, w, pt, k, a, b, rows=rows)
+        blk = self_blocks(pts[sub], nrm[sub], remap, nodes["tri_vertices"][tris], k, mode="linear")
+        ref[tag] = y + apply_corrections(nrm[sub], remap, blk, a[sub], b[sub], rows=loc)
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    acc = {}
+    for t, (y0, y1) in gpu_rows.items():
+        acc[t] = {"k0": float(np.linalg.norm(y0[rows] - ref["k0"]) / np.linalg.norm(ref["k0"])),
+                  "k1": float(np.linalg.norm(y1[rows] - ref["k1"]) / np.linalg.norm(ref["k1"])),
+                  "rows": int(nrows)}
+    # one core, 32 rows, in a child process (the OpenMP pool of this one is already sized)
+    r1 = 32
+    code = ("import sys, time, numpy as np; sys.path.insert(0, %r)\n"
+            "from synthetic import config_mesh, nystrom3, complex_normal, seed_for\n"
+            "from oracle.native import point_sum_c\nfrom oracle.kernel import wavenumber\n"
+            "q = nystrom3(config_mesh(5)); n = q['points'].shape[0]\n"
+            "a = complex_normal((n, 3), seed_for(5, 'a')); b = complex_normal((n, 3), seed_for(5, 'b'))\n"
+            "rows = np.arange(0, n, n // %d)[:%d].astype(np.int64)\n"
+            "t = time.perf_counter()\n"
+            "for k in (%r, wavenumber(%r, %r)):\n"
+            "    point_sum_c(q['points'], q['normals'], q['weights'], q['point_tri'], k, a, b, rows=rows)\n"
+            "print(time.perf_counter() - t)\n") % (ROOT, r1, r1, k0, k0, cfg["eps"])
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    one = None
+    try:
+        res = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        one = float(res.stdout.strip().splitlines()[-1])
+    except (subprocess.SubprocessError, ValueError, IndexError):
+        one = None
+    apply_s = dt * n / nrows
+    cpu = {"value": 1.0 / apply_s, "unit": "matvecs/s", "cores": cores, "kind": "oracle",
+           "sample": "FP64 oracle direct sum of both wavenumbers (point sum + self-triangle blocks) on %d of %d "
+                     "seeded target rows against all sources, %.2f s with %d threads, scaled by n/rows to one full "
+                     "application of the two operators (%.0f s)" % (nrows, n, dt, cores, apply_s),
+           "seconds_per_full_apply_extrapolated": apply_s}
+    if one is not None:
+        apply1 = one * n / r1
+        cpu["one_core"] = {"value": 1.0 / apply1, "unit": "matvecs/s", "cores": 1,
+                           "sample": "point sums of both wavenumbers on %d rows, %.2f s, scaled to one full "
+                                     "application (%.0f s)" % (r1, one, apply1)}
+    return cpu, acc
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(torch.device("cuda:0"))
+    c5 = c5_workload(args, log)
+    torus = None if args.skip_torus else torus_section(args, log)
+    out = {
+        "metric": "FMM matvecs/s & GMRES solves/s at 1e-6 rel err, FP32/batched vs plain FP64",
+        "value": c5["value"],
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": c5["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": c5["config"],
+        "roofline": c5["roofline"],
+        "cpu_baseline": c5["cpu_baseline"],
+        "c5": {k: v for k, v in c5.items() if k not in ("value", "ms_per_step", "config", "roofline", "cpu_baseline")},
+        "torus": torus,
+    }
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":

@@ -67,7 +67,7 @@ typedef struct {
     int32_t leaf_target;        /* depth 0 only: aim for about this many nodes per leaf (0=32)*/
     int32_t translate_mode;     /* FP32 plans: FMB_TRANSLATE_FP32 (default) or FMB_TRANSLATE_BF16X3 */
     int32_t reserved0;
-    double tol;                 /* order <= 0 only: target relative accuracy of the expansions */
+    double tol;                 /* order <= 0 only: target relative accuracy (0: 1e-6 FP64, 1e-4 FP32) */
     double far_cutoff;          /* lossy k: drop interactions damped below this factor (0: default) */
 } fmb_plan_opts;
 
@@ -90,6 +90,9 @@ typedef struct {
     int64_t p2p_pairs;          /* near (target, source) pairs incl. excluded same-triangle  */
     int64_t corr_blocks;        /* self-triangle blocks                                       */
     int64_t device_bytes;       /* device memory the plan holds                               */
+    int32_t order_level[16];    /* truncation order of each level (0: no far field there)      */
+    int32_t far_lmin;           /* first level with far-field translations (depth+1: none)    */
+    int32_t reserved;
 } fmb_plan_info;
 
 /* Fill opts with defaults: depth 0, FP64, nrhs_max 1, LINEAR corrections. */
@@ -102,7 +105,14 @@ int fmb_plan_opts_default(fmb_plan_opts *opts);
  *   points   host f64[n][3]   node positions s_beta
  *   normals  host f64[n][3]   unit normals (|n| within 1e-6 of 1), outward
  *   weights  host f64[n]      Nystrom weights w_beta > 0 (eq. 2.8)
- *   order    p >= 1: degrees 0..p-1 kept at every level (eq. 2.17 cut)
+ *   order    p >= 1: degrees 0..p-1 kept at every level (eq. 2.17 cut), translations
+ *            as dense per-offset operators (p <= 24);
+ *            p <= 0: an order per level chosen for opts->tol (default 1e-6 FP64,
+ *            1e-4 FP32): p_l = max(2.8 d0, k d + 1.8 d0^(2/3) (k d)^(1/3)) with
+ *            d0 = -log10 tol and d the level's box diameter, so that boxes many
+ *            wavelengths across keep p_l ~ k d; translations by rotation, coaxial
+ *            shift and rotation back (O(p^3) each).  Refused when the leaf level
+ *            needs p > 40 or any level p > 400.
  * Lossy wavenumbers (Im k > 0, Sec. 2.1: g decays as exp(-Im k R)): the
  * far field of level l is dropped when exp(-Im k h_l) < far_cutoff, h_l being
  * the level's box side, the shortest distance between two boxes of its
@@ -358,6 +368,7 @@ int gmres_solve_group(const fmb_problem_t *pbs, int32_t count, const void *const
  */
 int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt, int32_t region,
               int32_t far, void *E, void *stream);
+
 
 /*
  * bem_far_field_adjoint: the conjugate transpose of the far-field map of

@@ -37,7 +37,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("order", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("nrhs_max", ctypes.c_int32), ("n", ctypes.c_int64), ("nbox", ctypes.c_int64 * 16),
                 ("m2l_pairs", ctypes.c_int64 * 16), ("p2p_pairs", ctypes.c_int64),
-                ("corr_blocks", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("corr_blocks", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("order_level", ctypes.c_int32 * 16), ("far_lmin", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class GmresOpts(ctypes.Structure):
@@ -210,7 +211,8 @@ class Plan:
         d = inf.depth
         return {"depth": d, "order": inf.order, "n": inf.n, "nbox": list(inf.nbox[:d + 1]),
                 "m2l_pairs": list(inf.m2l_pairs[:d + 1]), "p2p_pairs": inf.p2p_pairs,
-                "corr_blocks": inf.corr_blocks, "device_bytes": inf.device_bytes}
+                "corr_blocks": inf.corr_blocks, "device_bytes": inf.device_bytes,
+                "order_level": list(inf.order_level[:d + 1]), "far_lmin": inf.far_lmin}
 
     def export_tree(self, level):
         inf = self.info()

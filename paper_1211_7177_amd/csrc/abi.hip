@@ -15,13 +15,14 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 size_t Plan::device_bytes() const {
     size_t b = codes.bytes + perm.bytes + iperm.bytes + spts.bytes + snrm.bytes + sw.bytes + stri.bytes +
                inv_alpha.bytes + btab.bytes + bgix.bytes + point_tri.bytes + unrm.bytes + tri_nodes.bytes + corr_v.bytes + corr_g.bytes +
-               src.bytes + ys.bytes + ybuf.bytes;
+               src.bytes + ys.bytes + ybuf.bytes + hscratch.bytes;
     for (const Level &V : lv)
         b += V.keys.bytes + V.start.bytes + V.parent.bytes + V.center.bytes + V.nbr.bytes + V.child_start.bytes +
              V.octant.bytes + V.ff_ofs.bytes + V.ff_src.bytes + V.ff_op.bytes + V.ff_by_op.bytes + V.by_octant.bytes +
              V.m2l.bytes + V.m2m.bytes + V.l2l.bytes + V.m2l_hi.bytes + V.m2l_lo.bytes + V.m2m_hi.bytes +
              V.m2m_lo.bytes + V.l2l_hi.bytes + V.l2l_lo.bytes + V.M.bytes + V.L.bytes + V.tiles_m2l.bytes + V.tiles_m2m.bytes +
-             V.tiles_l2l.bytes;
+             V.tiles_l2l.bytes + V.hW.bytes + V.hWo.bytes + V.hph.bytes + V.hpho.bytes + V.hC.bytes + V.hCss.bytes +
+             V.hCrr.bytes + V.hopi.bytes + V.hboct.bytes;
     return b;
 }
 
@@ -82,7 +83,7 @@ int fmm_plan(const double *points, const double *normals, const double *weights,
         FMB_REQUIRE(n >= 2 && n < (int64_t)1 << 30, "n must be in [2, 2^30)");
         FMB_REQUIRE(std::isfinite(k_re) && std::isfinite(k_im) && k_im >= 0.0, "k must be finite with Im k >= 0");
         FMB_REQUIRE(k_re != 0.0 || k_im != 0.0, "k must be non-zero");
-        FMB_REQUIRE(order >= 1 && order <= MAX_ORDER, "order must be in [1, 24]");
+        FMB_REQUIRE(order <= MAX_ORDER, "order must be <= 24 (or <= 0: an order per level for opts->tol)");
         fmb_plan_opts o;
         fmb_plan_opts_default(&o);
         if (opts) o = *opts;
@@ -142,6 +143,11 @@ int fmm_plan(const double *points, const double *normals, const double *weights,
         Plan &P = h->p;
         P.n = n;
         P.depth = o.depth;
+        P.hf = order <= 0;
+        if (P.hf) {
+            P.tol = o.tol > 0.0 ? o.tol : (o.precision == FMB_FP64 ? 1e-6 : 1e-4);
+            FMB_REQUIRE(P.tol < 1.0 && P.tol >= 1e-15, "tol must be in [1e-15, 1)");
+        }
         P.order = order;
         P.P2 = order * order;
         P.precision = o.precision;
@@ -163,9 +169,24 @@ int fmm_plan(const double *points, const double *normals, const double *weights,
         build_tree(P, d_pts.as<double>(), s, ntri > 0 ? tri.data() : nullptr);
         set_far_cutoff(P, o.far_cutoff);
         gather_nodes(P, d_pts.as<double>(), d_nrm.as<double>(), d_w.as<double>(), P.point_tri.as<int32_t>(), s);
-        build_operators(P, s);
-        build_tiles(P, s);
-        split_operators(P, s);
+        if (P.hf) {
+            // an order per level for the tolerance (its box size and the wavenumber)
+            const double kabs = std::sqrt(k_re * k_re + k_im * k_im);
+            for (int l = 0; l <= P.depth; ++l)
+                P.lv[l].p = l >= std::max(2, P.far_lmin) ? hf_order(kabs, P.ext / (double)(1 << l), P.tol) : 0;
+            P.order = P.far_on() ? P.lv[P.depth].p : 1;
+            P.P2 = P.order * P.order;
+            FMB_REQUIRE(P.order <= 40, "the leaf level needs an order above 40: choose a deeper octree");
+            for (int l = 0; l <= P.depth; ++l)
+                FMB_REQUIRE(P.lv[l].p <= 400, "a level needs an order above 400: boxes too large in wavelengths");
+            build_basis_tables(P, s);
+            if (P.far_on()) build_hf(P, s);
+        } else {
+            for (int l = 0; l <= P.depth; ++l) P.lv[l].p = order;
+            build_operators(P, s);
+            build_tiles(P, s);
+            split_operators(P, s);
+        }
         alloc_workspace(P);
         if (P.corr_mode != FMB_CORR_NONE) {
             upload(d_tv, o.tri_vertices, ntri * 9 * sizeof(double), s);
@@ -208,8 +229,10 @@ int fmm_plan_info(fmb_plan_t plan, fmb_plan_info *info) {
         info->n = P.n;
         for (int l = 0; l <= P.depth && l < 16; ++l) {
             info->nbox[l] = P.lv[l].nbox;
-            info->m2l_pairs[l] = P.lv[l].nff;
+            info->m2l_pairs[l] = l >= std::max(2, P.far_lmin) ? P.lv[l].nff : 0;
+            info->order_level[l] = P.lv[l].p;
         }
+        info->far_lmin = P.far_lmin;
         info->p2p_pairs = P.p2p_pairs;
         info->corr_blocks = P.corr_mode ? P.n * P.tri_m : 0;
         info->device_bytes = (int64_t)P.device_bytes();

@@ -1,0 +1,645 @@
+// Far field with a truncation order per level (plans built with order <= 0):
+// the S|S, S|R and R|R translations of eqs. 2.20-2.21 by rotation, coaxial
+// shift and rotation back, each target accumulating its own sources in a fixed
+// order.
+//
+// A translation by t = (new centre - old centre) of a coefficient vector c
+// (field = sum_nm c_nm F_n^m(x - old centre), F = R or S of eq. 2.16, Y of
+// eq. 2.15) splits into three steps.  With theta, phi the angles of t and W^n
+// the degree-n matrix of a rotation by theta about y,
+//     Y_n^m(R_y(theta) x) = sum_m' W^n_{m m'}(theta) Y_n^m'(x),
+//   1. c'_n^m'  = sum_m W^n_{m m'}(theta) e^{i m phi} c_n^m        (t turned onto +z)
+//   2. c''_n'^m = sum_n C^m_{n' n}(|t|) c'_n^m                      (shift along +z)
+//   3. d_n^m'   = e^{-i m' phi} sum_m W^n_{m' m}(theta) c''_n^m     (turned back; W orthogonal)
+// W^n_{m m'} = s_m s_m' d^n_{m' m}(theta) with Wigner's d (s_m = (-1)^m for
+// m > 0, else 1: eq. 2.15's phase), built by the three-term recurrence in the
+// degree from the single-term value at n = max(|m|, |m'|).  The coaxial
+// coefficients (F_n^m(r + |t| z) = sum_n' C^m_{n'n} G_n'^m(r)) start from
+// C^0_{n'0} = (-1)^n' sqrt(2n'+1) f_n'(k|t|) (f = h_n for S|R, j_n for S|S and
+// R|R) and follow from the derivative rules of the basis,
+//   d_z F_n^m = k (a_n^m F_{n-1}^m - b_n^m F_{n+1}^m),
+//   (d_x + i d_y) F_n^m = k (e_n^m F_{n+1}^{m+1} + f_n^m F_{n-1}^{m+1})  (m >= 0),
+// applied to both sides of the shifted expansion: one recurrence advances the
+// source degree n, the other raises |m|.  Work per translation is O(p^3)
+// instead of the O(p^4) of a dense operator, and the tables are small enough
+// for orders in the hundreds (the coarse levels of electrically large bodies,
+// where k d reaches 10^2: truncation below eq. 2.17 needs p ~ k d).
+//
+// Scaled coefficients: Mtilde_n = M_n / alpha_n(l), Ltilde_n = L_n alpha_n(l) with
+// alpha_n(l) = 1 / max(1, x |h_n(x)|), x = |k| rho_l (rho_l the level's box
+// radius); the tables carry the alpha factors so that stored coefficients and
+// table entries stay near unit size in FP32 at every order.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <map>
+#include <thread>
+#include <tuple>
+
+#include "plan.h"
+
+namespace fmb {
+
+namespace {
+
+using cd = std::complex<double>;
+
+constexpr int HTPB = 256;
+constexpr size_t HF_LDS_MAX = 64 * 1024;
+
+// ------------------------------------------------------------ host functions
+
+// j_n(z), n = 0..N (Miller's downward ratio recurrence, then j_0 = sin z / z)
+void host_sph_j(cd z, int N, std::vector<cd> &out) {
+    out.assign(N + 1, cd(0.0, 0.0));
+    const double az = std::abs(z);
+    if (az < 1e-300) {
+        out[0] = 1.0;
+        return;
+    }
+    const int start = N + 32 + (int)(1.5 * az);
+    cd r = 0.0;
+    std::vector<cd> ratio(N + 1);
+    for (int n = start; n >= 1; --n) {
+        r = z / (double(2 * n + 1) - z * r);
+        if (n <= N) ratio[n] = r;
+    }
+    out[0] = az < 1e-3 ? 1.0 - z * z / 6.0 + z * z * z * z / 120.0 : std::sin(z) / z;
+    for (int n = 1; n <= N; ++n) out[n] = out[n - 1] * ratio[n];
+}
+
+// h_n^(1)(z), n = 0..N (upward recurrence)
+void host_sph_h(cd z, int N, std::vector<cd> &out) {
+    out.assign(N + 1, cd(0.0, 0.0));
+    const cd i(0.0, 1.0);
+    const cd e = std::exp(i * z);
+    out[0] = -i * e / z;
+    if (N >= 1) out[1] = -e * (z + i) / (z * z);
+    for (int n = 1; n < N; ++n) out[n + 1] = double(2 * n + 1) / z * out[n] - out[n - 1];
+}
+
+// alpha_n = 1 / max(1, x |h_n(x)|), n < p
+std::vector<double> hf_alpha(double x, int p) {
+    std::vector<double> a(p, 1.0);
+    if (x <= 0.0) return a;
+    std::vector<cd> h;
+    host_sph_h(cd(x, 0.0), p, h);
+    for (int n = 0; n < p; ++n) {
+        const double v = x * std::abs(h[n]);
+        a[n] = (std::isfinite(v) && v > 1.0) ? 1.0 / v : (std::isfinite(v) ? 1.0 : 1e-300);
+        if (a[n] < 1e-300) a[n] = 1e-300;
+    }
+    return a;
+}
+
+// sum_{n < p} (2n+1)^2
+inline int64_t wsize(int p) { return (int64_t)p * (2 * p - 1) * (2 * p + 1) / 3; }
+
+// W[wsize(n) + (m+n)(2n+1) + (m'+n)] = s_m s_m' d^n_{m' m}(beta), n < p
+void rotation_table(int p, double beta, double *W) {
+    const double cb = std::cos(beta);
+    const double ch = std::cos(0.5 * beta), sh = std::sin(0.5 * beta);
+    const double lch = std::log(std::fabs(ch)), lsh = std::log(std::fabs(sh));
+    auto s = [](int m) { return (m > 0 && (m & 1)) ? -1.0 : 1.0; };
+    for (int mp = -(p - 1); mp <= p - 1; ++mp)
+        for (int m = -(p - 1); m <= p - 1; ++m) {
+            const int j0 = std::max(std::abs(m), std::abs(mp));
+            // Wigner's sum has one term at j = j0: s = max(0, m - m')
+            const int sv = std::max(0, m - mp);
+            const double lg = 0.5 * (std::lgamma(j0 + mp + 1.0) + std::lgamma(j0 - mp + 1.0) +
+                                     std::lgamma(j0 + m + 1.0) + std::lgamma(j0 - m + 1.0)) -
+                              std::lgamma(j0 + m - sv + 1.0) - std::lgamma(sv + 1.0) -
+                              std::lgamma(mp - m + sv + 1.0) - std::lgamma(j0 - mp - sv + 1.0);
+            const int pc = 2 * j0 + m - mp - 2 * sv, ps = mp - m + 2 * sv;
+            double d1;
+            if ((pc > 0 && ch == 0.0) || (ps > 0 && sh == 0.0)) {
+                d1 = 0.0;
+            } else {
+                const double v = lg + (pc > 0 ? pc * lch : 0.0) + (ps > 0 ? ps * lsh : 0.0);
+                double sg = ((mp - m + sv) & 1) ? -1.0 : 1.0;
+                if (pc > 0 && ch < 0.0 && (pc & 1)) sg = -sg;
+                if (ps > 0 && sh < 0.0 && (ps & 1)) sg = -sg;
+                d1 = sg * std::exp(v);
+            }
+            double d2 = 0.0;
+            for (int j = j0; j < p; ++j) {
+                double d;
+                if (j == j0) {
+                    d = d1;
+                } else {
+                    const double c1 = j * (2.0 * j - 1.0) / std::sqrt(((double)j * j - (double)m * m) * ((double)j * j - (double)mp * mp));
+                    double t = (cb - (j > 1 ? (double)m * mp / ((double)j * (j - 1)) : 0.0)) * d1;
+                    if (j - 1 > j0)
+                        t -= std::sqrt(((j - 1.0) * (j - 1.0) - (double)m * m) * ((j - 1.0) * (j - 1.0) - (double)mp * mp)) /
+                             ((j - 1.0) * (2.0 * j - 1.0)) * d2;
+                    d = c1 * t;
+                    d2 = d1;
+                    d1 = d;
+                }
+                // W^j_{m, m'} = s_m s_m' d^j_{m', m}
+                W[wsize(j) + (int64_t)(m + j) * (2 * j + 1) + (mp + j)] = s(m) * s(mp) * d;
+            }
+        }
+}
+
+// sum_{m < min(pd, ps)} (pd - m)(ps - m)
+inline int64_t csize(int pd, int ps) {
+    int64_t s = 0;
+    for (int m = 0; m < std::min(pd, ps); ++m) s += (int64_t)(pd - m) * (ps - m);
+    return s;
+}
+
+enum { CX_SR = 0, CX_SS = 1, CX_RR = 2 };
+
+// coaxial coefficients C^m_{n'n}(t) along +z for n' < pd, n < ps, times the scale
+// factors of the stored coefficients; block m at offset sum_{j<m}(pd-j)(ps-j),
+// entry (n'-m)(ps-m) + (n-m)
+// For S|S and R|R (regular translation function) the degree recurrence loses
+// accuracy above the diagonal when k|t| is small (each step cancels terms a
+// factor (k|t|)^2 larger than the result); there only the part n' >= n is
+// recurred and the rest follows from the symmetry C^m_{n n'} = (-1)^(n+n') C^m_{n' n}
+// of the regular re-expansion.  S|R keeps the full recurrence (its entries grow
+// along it).
+void coax_table(int kind, cd k, double t, int pd, int ps, const std::vector<double> &ad,
+                const std::vector<double> &as, cd *out) {
+    const bool sym = kind != CX_SR;
+    const int pr = sym ? std::max(pd, ps) : pd;   // rows and columns recurred
+    const int pc = sym ? std::max(pd, ps) : ps;
+    const int N = pr + pc + 1;
+    std::vector<cd> f;
+    if (kind == CX_SR) host_sph_h(k * t, N, f);
+    else host_sph_j(k * t, N, f);
+    auto a_ = [](int n, int m) { return n > m ? std::sqrt((double)(n - m) * (n + m) / ((2.0 * n - 1) * (2.0 * n + 1))) : 0.0; };
+    auto b_ = [](int n, int m) { return std::sqrt((n + 1.0 - m) * (n + 1.0 + m) / ((2.0 * n + 1) * (2.0 * n + 3))); };
+    auto e_ = [](int n, int m) { return std::sqrt((n + m + 1.0) * (n + m + 2.0) / ((2.0 * n + 1) * (2.0 * n + 3))); };
+    auto f_ = [](int n, int m) {
+        return (n > 0 && n - m - 1 > 0) ? std::sqrt((double)(n - m) * (n - m - 1) / ((2.0 * n - 1) * (2.0 * n + 1))) : 0.0;
+    };
+    const int W = pc + 1;
+    std::vector<cd> C((size_t)(N + 2) * W), prev(N + 2), cur(N + 2);
+    auto at = [&](int q, int n) -> cd & { return C[(size_t)q * W + n]; };
+    int64_t off = 0;
+    for (int m = 0; m < std::min(pd, ps); ++m) {
+        std::fill(C.begin(), C.end(), cd(0.0, 0.0));
+        const int Nm = N - m;   // rows valid in column m
+        if (m == 0) {
+            for (int q = 0; q <= N; ++q) at(q, 0) = ((q & 1) ? -1.0 : 1.0) * std::sqrt(2.0 * q + 1.0) * f[q];
+        } else {
+            // C^m_{q, m} = [e^{m-1}_{q-1} C^{m-1}_{q-1, m-1} + f^{m-1}_{q+1} C^{m-1}_{q+1, m-1}] / e^{m-1}_{m-1}
+            const double den = e_(m - 1, m - 1);
+            for (int q = m; q <= Nm; ++q) at(q, m) = (e_(q - 1, m - 1) * prev[q - 1] + f_(q + 1, m - 1) * prev[q + 1]) / den;
+        }
+        for (int q = 0; q <= N + 1; ++q) prev[q] = q <= N ? at(q, m) : cd(0.0, 0.0);
+        // C_{q, n+1} = [a_n C_{q, n-1} - a_{q+1} C_{q+1, n} + b_{q-1} C_{q-1, n}] / b_n
+        for (int n = m; n < pc - 1; ++n) {
+            const int qmax = Nm - (n - m) - 1;
+            for (int q = sym ? n + 1 : m; q <= qmax; ++q) {
+                cd v = -a_(q + 1, m) * at(q + 1, n);
+                if (n - 1 >= m) v += a_(n, m) * at(q, n - 1);
+                if (q - 1 >= m) v += b_(q - 1, m) * at(q - 1, n);
+                at(q, n + 1) = v / b_(n, m);
+            }
+        }
+        for (int q = m; q < pd; ++q)
+            for (int n = m; n < ps; ++n) {
+                double sc;
+                if (kind == CX_SR) sc = ad[q] * as[n];
+                else if (kind == CX_SS) sc = as[n] / ad[q];
+                else sc = ad[q] / as[n];
+                const cd v = (sym && q < n) ? (((q + n) & 1) ? -1.0 : 1.0) * at(n, q) : at(q, n);
+                out[off + (int64_t)(q - m) * (ps - m) + (n - m)] = sc * v;
+            }
+        off += (int64_t)(pd - m) * (ps - m);
+    }
+}
+
+template <typename T>
+void upload_as(DevBuf &d, const std::vector<double> &v, hipStream_t s) {
+    std::vector<T> h(v.begin(), v.end());
+    d.alloc(std::max<size_t>(1, h.size()) * sizeof(T));
+    if (!h.empty()) FMB_CHECK_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    FMB_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+template <typename T>
+void upload_cx(DevBuf &d, const std::vector<cd> &v, hipStream_t s) {
+    std::vector<cx<T>> h(v.size());
+    for (size_t i = 0; i < v.size(); ++i) h[i] = mk((T)v[i].real(), (T)v[i].imag());
+    d.alloc(std::max<size_t>(1, h.size()) * sizeof(cx<T>));
+    if (!h.empty()) FMB_CHECK_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(cx<T>), hipMemcpyHostToDevice, s));
+    FMB_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+// run f(i) for i in [0, n) on up to 8 host threads
+template <typename F>
+void parallel_for(int n, F f) {
+    const int nt = std::max(1, std::min(n, 8));
+    std::vector<std::thread> th;
+    for (int w = 0; w < nt; ++w)
+        th.emplace_back([&, w] {
+            for (int i = w; i < n; i += nt) f(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+// ---------------------------------------------------------------- kernels
+
+struct HfArgs {
+    const void *W;       // rotation table of this translation's polar angle (covers max(ps, pd))
+    const void *ph;      // e^{i m phi}, m = 0.. (covers max(ps, pd))
+    const void *C;       // coaxial block table (pd x ps)
+    int ps, pd;
+};
+
+// decode idx = n^2 + n + m
+__device__ inline void hf_nm(int e, int &n, int &m) {
+    n = (int)sqrtf((float)e);
+    while (n * n > e) --n;
+    while ((n + 1) * (n + 1) <= e) ++n;
+    m = e - n * n - n;
+}
+
+// one translation of CH channel blocks (stride sstr between channels) into acc,
+// with the two scratch vectors b1, b2 (each CH * max(ps, pd)^2)
+template <typename T, int CH>
+__device__ void hf_translate(const cx<T> *__restrict__ src, int64_t sstr, const T *__restrict__ W,
+                             const cx<T> *__restrict__ ph, const cx<T> *__restrict__ C, int ps, int pd, cx<T> *b1,
+                             cx<T> *b2, cx<T> *acc) {
+    const int S2 = ps * ps, D2 = pd * pd;
+    // 1: phases, source order ps
+    for (int t = threadIdx.x; t < CH * S2; t += blockDim.x) {
+        const int c = t / S2, e = t - c * S2;
+        int n, m;
+        hf_nm(e, n, m);
+        const cx<T> f = m >= 0 ? ph[m] : conj(ph[-m]);
+        b1[c * S2 + e] = f * src[c * sstr + e];
+    }
+    __syncthreads();
+    // 2: rotation onto +z, c'_n^m' = sum_m W[n][m][m'] c_n^m
+    for (int t = threadIdx.x; t < CH * S2; t += blockDim.x) {
+        const int c = t / S2, e = t - c * S2;
+        int n, mp;
+        hf_nm(e, n, mp);
+        const T *w = W + (int64_t)n * (2 * n - 1) * (2 * n + 1) / 3 + (mp + n);
+        const cx<T> *x = b1 + c * S2 + n * n;
+        cx<T> s = mk(T(0), T(0));
+        for (int m = 0; m <= 2 * n; ++m) s += w[(int64_t)m * (2 * n + 1)] * x[m];
+        b2[c * S2 + e] = s;
+    }
+    __syncthreads();
+    // 3: coaxial shift, c''_n'^m = sum_n C^|m|_{n'n} c'_n^m, into order pd
+    for (int t = threadIdx.x; t < CH * D2; t += blockDim.x) {
+        const int c = t / D2, e = t - c * D2;
+        int q, m;
+        hf_nm(e, q, m);
+        const int am = m < 0 ? -m : m;
+        cx<T> s = mk(T(0), T(0));
+        if (am < ps) {
+            // block offset sum_{j < am} (pd - j)(ps - j)
+            int64_t off = 0;
+            for (int j = 0; j < am; ++j) off += (int64_t)(pd - j) * (ps - j);
+            const cx<T> *row = C + off + (int64_t)(q - am) * (ps - am);
+            const cx<T> *x = b2 + c * S2;
+            for (int n = am; n < ps; ++n) s += row[n - am] * x[n * n + n + m];
+        }
+        b1[c * D2 + e] = s;
+    }
+    __syncthreads();
+    // 4: rotation back, d_n^m' = e^{-i m' phi} sum_m W[n][m'][m] c''_n^m, accumulated
+    for (int t = threadIdx.x; t < CH * D2; t += blockDim.x) {
+        const int c = t / D2, e = t - c * D2;
+        int n, mp;
+        hf_nm(e, n, mp);
+        const T *w = W + (int64_t)n * (2 * n - 1) * (2 * n + 1) / 3 + (int64_t)(mp + n) * (2 * n + 1);
+        const cx<T> *x = b1 + c * D2 + n * n;
+        cx<T> s = mk(T(0), T(0));
+        for (int m = 0; m <= 2 * n; ++m) s += w[m] * x[m];
+        const cx<T> f = mp >= 0 ? conj(ph[mp]) : ph[-mp];
+        acc[c * D2 + e] += f * s;
+    }
+    __syncthreads();
+}
+
+template <typename T, int CH, bool GLB>
+__device__ inline void hf_buffers(cx<T> *smem, cx<T> *gscr, int64_t P2m, int64_t D2, cx<T> *&b1, cx<T> *&b2,
+                                  cx<T> *&acc) {
+    cx<T> *base = smem;
+    if (GLB) base = gscr + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * (2 * CH * P2m + CH * D2);
+    b1 = base;
+    b2 = base + CH * P2m;
+    acc = base + 2 * CH * P2m;
+}
+
+// M2L: target box b of the level sums, in list order, the S|R translations of its
+// far-field sources; writes (overwrites) its local expansion.
+template <typename T, int CH, bool GLB>
+__global__ void __launch_bounds__(HTPB) k_hf_m2l(const int32_t *__restrict__ ff_ofs, const int32_t *__restrict__ ff_src,
+                                                 const int32_t *__restrict__ ff_op, const int32_t *__restrict__ opi,
+                                                 const T *__restrict__ W, int64_t wsz, const cx<T> *__restrict__ ph,
+                                                 const cx<T> *__restrict__ C, int64_t csz, int p, int nrhs_max,
+                                                 const cx<T> *__restrict__ M, cx<T> *__restrict__ Lout, cx<T> *gscr) {
+    extern __shared__ __align__(16) unsigned char hf_smem[];
+    const int b = blockIdx.x;
+    const int col = blockIdx.y * CH;                 // first channel (r * 3 + c) of this block
+    const int r = col / 3, c0 = col % 3;
+    const int64_t P2 = (int64_t)p * p;
+    cx<T> *b1, *b2, *acc;
+    hf_buffers<T, CH, GLB>(reinterpret_cast<cx<T> *>(hf_smem), gscr, P2, P2, b1, b2, acc);
+    for (int t = threadIdx.x; t < CH * P2; t += blockDim.x) acc[t] = mk(T(0), T(0));
+    __syncthreads();
+    const int e0 = ff_ofs[b], e1 = ff_ofs[b + 1];
+    for (int e = e0; e < e1; ++e) {
+        const int s = ff_src[e], o = ff_op[e];
+        const int beta = opi[2 * o], dist = opi[2 * o + 1];
+        hf_translate<T, CH>(M + (((int64_t)s * nrhs_max + r) * 3 + c0) * P2, P2, W + beta * wsz, ph + (int64_t)o * p,
+                            C + dist * csz, p, p, b1, b2, acc);
+    }
+    cx<T> *out = Lout + (((int64_t)b * nrhs_max + r) * 3 + c0) * P2;
+    for (int t = threadIdx.x; t < CH * P2; t += blockDim.x) out[t] = acc[t];
+}
+
+// M2M into parent box b (order pd) from its children (order ps, their own octant
+// directions); writes the parent's multipole.
+template <typename T, int CH, bool GLB>
+__global__ void __launch_bounds__(HTPB) k_hf_m2m(const int32_t *__restrict__ child_start,
+                                                 const int32_t *__restrict__ child_oct, const T *__restrict__ Wo,
+                                                 int64_t wszo, const int32_t *__restrict__ beta_oct,
+                                                 const cx<T> *__restrict__ pho, int pwo, const cx<T> *__restrict__ C,
+                                                 int ps, int pd, int nrhs_max, const cx<T> *__restrict__ Mc,
+                                                 cx<T> *__restrict__ Mp, cx<T> *gscr) {
+    extern __shared__ __align__(16) unsigned char hf_smem[];
+    const int b = blockIdx.x;
+    const int col = blockIdx.y * CH;
+    const int r = col / 3, c0 = col % 3;
+    const int64_t S2 = (int64_t)ps * ps, D2 = (int64_t)pd * pd, P2m = S2 > D2 ? S2 : D2;
+    cx<T> *b1, *b2, *acc;
+    hf_buffers<T, CH, GLB>(reinterpret_cast<cx<T> *>(hf_smem), gscr, P2m, D2, b1, b2, acc);
+    for (int t = threadIdx.x; t < CH * D2; t += blockDim.x) acc[t] = mk(T(0), T(0));
+    __syncthreads();
+    for (int ch = child_start[b]; ch < child_start[b + 1]; ++ch) {
+        const int o = child_oct[ch];
+        hf_translate<T, CH>(Mc + (((int64_t)ch * nrhs_max + r) * 3 + c0) * S2, S2, Wo + beta_oct[o] * wszo,
+                            pho + (int64_t)o * pwo, C, (int)ps, (int)pd, b1, b2, acc);
+    }
+    cx<T> *out = Mp + (((int64_t)b * nrhs_max + r) * 3 + c0) * D2;
+    for (int t = threadIdx.x; t < CH * D2; t += blockDim.x) out[t] = acc[t];
+}
+
+// L2L into child box b (order pd) from its parent (order ps): added to the
+// child's local expansion (which holds its far-field sum).
+template <typename T, int CH, bool GLB>
+__global__ void __launch_bounds__(HTPB) k_hf_l2l(const int32_t *__restrict__ parent, const int32_t *__restrict__ oct,
+                                                 const T *__restrict__ Wo, int64_t wszo,
+                                                 const int32_t *__restrict__ beta_oct, const cx<T> *__restrict__ pho,
+                                                 int pwo, const cx<T> *__restrict__ C, int ps, int pd, int nrhs_max,
+                                                 const cx<T> *__restrict__ Lp, cx<T> *__restrict__ Lc, cx<T> *gscr) {
+    extern __shared__ __align__(16) unsigned char hf_smem[];
+    const int b = blockIdx.x;
+    const int col = blockIdx.y * CH;
+    const int r = col / 3, c0 = col % 3;
+    const int64_t S2 = (int64_t)ps * ps, D2 = (int64_t)pd * pd, P2m = S2 > D2 ? S2 : D2;
+    cx<T> *b1, *b2, *acc;
+    hf_buffers<T, CH, GLB>(reinterpret_cast<cx<T> *>(hf_smem), gscr, P2m, D2, b1, b2, acc);
+    cx<T> *out = Lc + (((int64_t)b * nrhs_max + r) * 3 + c0) * D2;
+    for (int t = threadIdx.x; t < CH * D2; t += blockDim.x) acc[t] = out[t];
+    __syncthreads();
+    const int o = 8 + oct[b];
+    hf_translate<T, CH>(Lp + (((int64_t)parent[b] * nrhs_max + r) * 3 + c0) * S2, S2, Wo + beta_oct[o] * wszo,
+                        pho + (int64_t)o * pwo, C, (int)ps, (int)pd, b1, b2, acc);
+    for (int t = threadIdx.x; t < CH * D2; t += blockDim.x) out[t] = acc[t];
+}
+
+template <typename T>
+__global__ void k_hf_zero(cx<T> *__restrict__ x, int64_t m) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < m) x[i] = mk(T(0), T(0));
+}
+
+template <typename T>
+size_t hf_lds(int ch, int64_t P2m, int64_t D2) { return (size_t)(2 * ch * P2m + ch * D2) * sizeof(cx<T>); }
+
+// launch mode of a translation stage: 3 channels per block in LDS, 1 in LDS, or
+// 1 with the scratch vectors in global memory (large orders)
+template <typename T>
+int hf_mode(int64_t P2m, int64_t D2) {
+    if (hf_lds<T>(3, P2m, D2) <= HF_LDS_MAX) return 3;
+    if (hf_lds<T>(1, P2m, D2) <= HF_LDS_MAX) return 1;
+    return 0;
+}
+
+}  // namespace
+
+// order needed at a level: the low-frequency floor for the tolerance, or the
+// excess-bandwidth estimate k d + 1.8 d0^(2/3) (k d)^(1/3) (d the box diameter,
+// d0 = digits) once boxes are many wavelengths across
+int hf_order(double kabs, double side, double tol) {
+    const double d0 = std::max(1.0, -std::log10(tol));
+    const double kd = kabs * side * std::sqrt(3.0);
+    const double pe = kd + 1.8 * std::pow(d0, 2.0 / 3.0) * std::cbrt(std::max(kd, 0.0));
+    const double pf = 2.8 * d0;
+    return (int)std::ceil(std::max(pe, pf));
+}
+
+void build_hf(Plan &P, hipStream_t s) {
+    const int L = P.depth;
+    const int lmin = std::max(2, P.far_lmin);
+    const cd k(P.k_re, P.k_im);
+    const double kabs = std::abs(k);
+    const bool f64 = P.precision == FMB_FP64;
+    std::vector<std::vector<double>> alpha(L + 1);
+    for (int l = 0; l <= L; ++l) {
+        const double rho = 0.5 * std::sqrt(3.0) * P.ext / (double)(1 << l);
+        alpha[l] = hf_alpha(kabs * rho, std::max(1, P.lv[l].p));
+    }
+    // 1/alpha at the leaf level for P2M / L2P (row layout [depth+1][order])
+    {
+        std::vector<double> ia((size_t)(L + 1) * P.order, 1.0);
+        for (int n = 0; n < P.order; ++n) ia[(size_t)L * P.order + n] = 1.0 / alpha[L][n];
+        upload_as<double>(P.inv_alpha, ia, s);
+    }
+    const double c1 = 1.0 / std::sqrt(3.0);
+    for (int l = lmin; l <= L; ++l) {
+        Level &V = P.lv[l];
+        const int p = V.p;
+        const double side = P.ext / (double)(1 << l);
+        // --- far-field offsets used at this level: polar-angle and distance classes
+        std::vector<int32_t> opi(2 * N_M2L_OPS, 0);
+        std::map<std::pair<int, int>, int> bkey, dkey;
+        std::vector<double> betas;
+        std::vector<double> dists;
+        std::vector<cd> ph((size_t)N_M2L_OPS * p, cd(0.0, 0.0));
+        for (int o = 0; o < N_M2L_OPS; ++o) {
+            if (V.op_start[o + 1] == V.op_start[o]) continue;
+            const int dx = o / 49 - 3, dy = (o / 7) % 7 - 3, dz = o % 7 - 3;
+            // offset = source - target box coordinates; t = X_t - X_s = -offset * side
+            const double tx = -dx * side, ty = -dy * side, tz = -dz * side;
+            const double T = std::sqrt(tx * tx + ty * ty + tz * tz);
+            const std::pair<int, int> kb{-dz, dx * dx + dy * dy};
+            if (!bkey.count(kb)) {
+                bkey[kb] = (int)betas.size();
+                betas.push_back(std::acos(std::max(-1.0, std::min(1.0, tz / T))));
+            }
+            const std::pair<int, int> kd{dx * dx + dy * dy + dz * dz, 0};
+            if (!dkey.count(kd)) {
+                dkey[kd] = (int)dists.size();
+                dists.push_back(T);
+            }
+            opi[2 * o] = bkey[kb];
+            opi[2 * o + 1] = dkey[kd];
+            const double phi = (dx == 0 && dy == 0) ? 0.0 : std::atan2(ty, tx);
+            for (int m = 0; m < p; ++m) ph[(size_t)o * p + m] = std::polar(1.0, m * phi);
+        }
+        V.hwsz = wsize(p);
+        V.hcsz = csize(p, p);
+        std::vector<double> Wt((size_t)std::max<size_t>(1, betas.size()) * V.hwsz, 0.0);
+        parallel_for((int)betas.size(), [&](int i) { rotation_table(p, betas[i], Wt.data() + (size_t)i * V.hwsz); });
+        std::vector<cd> Ct((size_t)std::max<size_t>(1, dists.size()) * V.hcsz);
+        parallel_for((int)dists.size(), [&](int i) {
+            coax_table(CX_SR, k, dists[i], p, p, alpha[l], alpha[l], Ct.data() + (size_t)i * V.hcsz);
+        });
+        // --- octant directions: 0..7 M2M into this level (t = X_parent - X_child of child octant o),
+        //     8..15 L2L into this level (t = X_child - X_parent of own octant o)
+        const int pu = l < L ? P.lv[l + 1].p : 0, pdn = l > lmin ? P.lv[l - 1].p : 0;
+        V.hpwo = std::max(p, std::max(pu, pdn));
+        V.hwszo = wsize(V.hpwo);
+        std::vector<double> Wo((size_t)2 * V.hwszo);
+        parallel_for(2, [&](int i) { rotation_table(V.hpwo, std::acos(i == 0 ? c1 : -c1), Wo.data() + (size_t)i * V.hwszo); });
+        std::vector<cd> pho((size_t)16 * V.hpwo);
+        std::vector<int32_t> boct(16);
+        for (int q = 0; q < 16; ++q) {
+            const int o = q & 7;
+            const double sg = q < 8 ? -1.0 : 1.0;
+            const double v[3] = {sg * (((o >> 0) & 1) - 0.5), sg * (((o >> 1) & 1) - 0.5), sg * (((o >> 2) & 1) - 0.5)};
+            boct[q] = v[2] > 0 ? 0 : 1;
+            const double phi = std::atan2(v[1], v[0]);
+            for (int m = 0; m < V.hpwo; ++m) pho[(size_t)q * V.hpwo + m] = std::polar(1.0, m * phi);
+        }
+        std::vector<cd> Css, Crr;
+        if (l < L) {
+            // S|S from children at level l+1: |t| = sqrt(3)/2 * side_{l+1}
+            Css.resize(csize(p, pu));
+            coax_table(CX_SS, k, 0.5 * std::sqrt(3.0) * side * 0.5, p, pu, alpha[l], alpha[l + 1], Css.data());
+        }
+        if (l > lmin) {
+            // R|R from the parent at level l-1: |t| = sqrt(3)/2 * side_l
+            Crr.resize(csize(p, pdn));
+            coax_table(CX_RR, k, 0.5 * std::sqrt(3.0) * side, p, pdn, alpha[l], alpha[l - 1], Crr.data());
+        }
+        upload_as<int32_t>(V.hopi, std::vector<double>(opi.begin(), opi.end()), s);
+        upload_as<int32_t>(V.hboct, std::vector<double>(boct.begin(), boct.end()), s);
+        if (f64) {
+            upload_as<double>(V.hW, Wt, s);
+            upload_as<double>(V.hWo, Wo, s);
+            upload_cx<double>(V.hph, ph, s);
+            upload_cx<double>(V.hpho, pho, s);
+            upload_cx<double>(V.hC, Ct, s);
+            upload_cx<double>(V.hCss, Css, s);
+            upload_cx<double>(V.hCrr, Crr, s);
+        } else {
+            upload_as<float>(V.hW, Wt, s);
+            upload_as<float>(V.hWo, Wo, s);
+            upload_cx<float>(V.hph, ph, s);
+            upload_cx<float>(V.hpho, pho, s);
+            upload_cx<float>(V.hC, Ct, s);
+            upload_cx<float>(V.hCss, Css, s);
+            upload_cx<float>(V.hCrr, Crr, s);
+        }
+    }
+    // global scratch for the translation stages whose vectors do not fit in LDS
+    const size_t cs = f64 ? sizeof(cx<double>) : sizeof(cx<float>);
+    size_t need = 0;
+    for (int l = lmin; l <= L; ++l) {
+        const Level &V = P.lv[l];
+        const int64_t P2 = (int64_t)V.p * V.p;
+        const int64_t cols = 3 * (int64_t)P.nrhs_max;
+        auto acc_need = [&](int64_t nb, int64_t P2m, int64_t D2) {
+            const int mode = f64 ? hf_mode<double>(P2m, D2) : hf_mode<float>(P2m, D2);
+            if (mode == 0) need = std::max(need, (size_t)(nb * cols * (2 * P2m + D2)) * cs);
+        };
+        acc_need(V.nbox, P2, P2);
+        if (l < L) {
+            const int64_t S2 = (int64_t)P.lv[l + 1].p * P.lv[l + 1].p;
+            acc_need(V.nbox, std::max(S2, P2), P2);
+        }
+        if (l > lmin) {
+            const int64_t S2 = (int64_t)P.lv[l - 1].p * P.lv[l - 1].p;
+            acc_need(V.nbox, std::max(S2, P2), P2);
+        }
+    }
+    if (need) P.hscratch.alloc(need);
+}
+
+// ------------------------------------------------------------ launches
+
+template <typename T>
+void hf_m2m(Plan &P, int l, int nrhs, hipStream_t s) {
+    Level &V = P.lv[l], &Cv = P.lv[l + 1];
+    const int ps = Cv.p, pd = V.p;
+    const int64_t S2 = (int64_t)ps * ps, D2 = (int64_t)pd * pd, P2m = std::max(S2, D2);
+    const int mode = hf_mode<T>(P2m, D2);
+    const int ch = mode == 3 ? 3 : 1;
+    const dim3 grid((unsigned)V.nbox, (unsigned)(3 * nrhs / ch));
+    const size_t sh = mode ? hf_lds<T>(ch, P2m, D2) : 0;
+    auto args = std::make_tuple(V.child_start.as<int32_t>(), Cv.octant.as<int32_t>(), V.hWo.as<T>(), V.hwszo,
+                                V.hboct.as<int32_t>(), V.hpho.as<cx<T>>(), V.hpwo, V.hCss.as<cx<T>>(), ps, pd,
+                                P.nrhs_max, Cv.M.as<cx<T>>(), V.M.as<cx<T>>(), P.hscratch.as<cx<T>>());
+    auto go = [&](auto kern) { std::apply([&](auto... a) { kern<<<grid, HTPB, sh, s>>>(a...); }, args); };
+    if (mode == 3) go(k_hf_m2m<T, 3, false>);
+    else if (mode == 1) go(k_hf_m2m<T, 1, false>);
+    else go(k_hf_m2m<T, 1, true>);
+    FMB_LAUNCH_CHECK();
+}
+
+template <typename T>
+void hf_m2l(Plan &P, int l, int nrhs, hipStream_t s) {
+    Level &V = P.lv[l];
+    if (V.nff == 0) {
+        // no far-field pairs: the level's local expansions start at zero
+        const int64_t m = V.nbox * P.nrhs_max * 3 * (int64_t)V.p * V.p;
+        k_hf_zero<T><<<(unsigned)((m + HTPB - 1) / HTPB), HTPB, 0, s>>>(V.L.as<cx<T>>(), m);
+        FMB_LAUNCH_CHECK();
+        return;
+    }
+    const int p = V.p;
+    const int64_t P2 = (int64_t)p * p;
+    const int mode = hf_mode<T>(P2, P2);
+    const int ch = mode == 3 ? 3 : 1;
+    const dim3 grid((unsigned)V.nbox, (unsigned)(3 * nrhs / ch));
+    const size_t sh = mode ? hf_lds<T>(ch, P2, P2) : 0;
+    auto args = std::make_tuple(V.ff_ofs.as<int32_t>(), V.ff_src.as<int32_t>(), V.ff_op.as<int32_t>(),
+                                V.hopi.as<int32_t>(), V.hW.as<T>(), V.hwsz, V.hph.as<cx<T>>(), V.hC.as<cx<T>>(),
+                                V.hcsz, p, P.nrhs_max, V.M.as<cx<T>>(), V.L.as<cx<T>>(), P.hscratch.as<cx<T>>());
+    auto go = [&](auto kern) { std::apply([&](auto... a) { kern<<<grid, HTPB, sh, s>>>(a...); }, args); };
+    if (mode == 3) go(k_hf_m2l<T, 3, false>);
+    else if (mode == 1) go(k_hf_m2l<T, 1, false>);
+    else go(k_hf_m2l<T, 1, true>);
+    FMB_LAUNCH_CHECK();
+}
+
+template <typename T>
+void hf_l2l(Plan &P, int l, int nrhs, hipStream_t s) {
+    Level &V = P.lv[l], &U = P.lv[l - 1];
+    const int ps = U.p, pd = V.p;
+    const int64_t S2 = (int64_t)ps * ps, D2 = (int64_t)pd * pd, P2m = std::max(S2, D2);
+    const int mode = hf_mode<T>(P2m, D2);
+    const int ch = mode == 3 ? 3 : 1;
+    const dim3 grid((unsigned)V.nbox, (unsigned)(3 * nrhs / ch));
+    const size_t sh = mode ? hf_lds<T>(ch, P2m, D2) : 0;
+    auto args = std::make_tuple(V.parent.as<int32_t>(), V.octant.as<int32_t>(), V.hWo.as<T>(), V.hwszo,
+                                V.hboct.as<int32_t>(), V.hpho.as<cx<T>>(), V.hpwo, V.hCrr.as<cx<T>>(), ps, pd,
+                                P.nrhs_max, U.L.as<cx<T>>(), V.L.as<cx<T>>(), P.hscratch.as<cx<T>>());
+    auto go = [&](auto kern) { std::apply([&](auto... a) { kern<<<grid, HTPB, sh, s>>>(a...); }, args); };
+    if (mode == 3) go(k_hf_l2l<T, 3, false>);
+    else if (mode == 1) go(k_hf_l2l<T, 1, false>);
+    else go(k_hf_l2l<T, 1, true>);
+    FMB_LAUNCH_CHECK();
+}
+
+template void hf_m2m<float>(Plan &, int, int, hipStream_t);
+template void hf_m2m<double>(Plan &, int, int, hipStream_t);
+template void hf_m2l<float>(Plan &, int, int, hipStream_t);
+template void hf_m2l<double>(Plan &, int, int, hipStream_t);
+template void hf_l2l<float>(Plan &, int, int, hipStream_t);
+template void hf_l2l<double>(Plan &, int, int, hipStream_t);
+
+}  // namespace fmb

@@ -1268,7 +1268,14 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
     for (int l = L - 1; l >= 2; --l) {
         Level &V = P.lv[l], &C = P.lv[l + 1];
         if (step != k++) continue;
-        if (l < lmin || V.ntiles_m2m == 0) return true;
+        if (l < lmin) return true;
+        if (P.hf) {
+            tm.begin(ST_M2M, s, ev);
+            hf_m2m<T>(P, l, nrhs, s);
+            tm.end(ST_M2M, s, ev);
+            return true;
+        }
+        if (V.ntiles_m2m == 0) return true;
         tm.begin(ST_M2M, s, ev);
         launch_translate<T>(V.tiles_m2m.as<Tile>(), V.ntiles_m2m, C.by_octant.as<int32_t>(), nullptr, V.m2m.as<T>(),
                             (const T *)C.M.p, (T *)yb, KR, ncol, blkR, os, s, 0, 0, bf3 ? V.m2m_hi.p : nullptr,
@@ -1287,6 +1294,12 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
         if (!far) return true;
         int nk = 0;
         tm.begin(ST_M2L, s, ev);
+        if (P.hf) {
+            // each target sums its own far-field translations and writes its local expansion
+            for (int l = lmin; l <= L; ++l) hf_m2l<T>(P, l, nrhs, s);
+            tm.end(ST_M2L, s, ev, L - lmin + 1);
+            return true;
+        }
         for (int l = lmin; l <= L; ++l) {
             Level &V = P.lv[l];
             if (V.ntiles_m2l == 0) continue;
@@ -1301,7 +1314,7 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
     // Step 3b: the S|R slot sums of every level (one launch, overwriting L),
     // then R|R from the parent added into each level in turn
     if (step == k++) {
-        if (!far) return true;
+        if (!far || P.hf) return true;
         FarSumLevels fs{};
         fs.nlev = L - lmin + 1;
         int64_t tot = 0;
@@ -1323,7 +1336,14 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
     for (int l = 3; l <= L; ++l) {
         Level &V = P.lv[l];
         if (step != k++) continue;
-        if (l <= lmin || V.ntiles_l2l == 0) return true;
+        if (l <= lmin) return true;
+        if (P.hf) {
+            tm.begin(ST_L2L, s, ev);
+            hf_l2l<T>(P, l, nrhs, s);
+            tm.end(ST_L2L, s, ev);
+            return true;
+        }
+        if (V.ntiles_l2l == 0) return true;
         Level &U = P.lv[l - 1];
         tm.begin(ST_L2L, s, ev);
         launch_translate<T>(V.tiles_l2l.as<Tile>(), V.ntiles_l2l, V.by_octant.as<int32_t>(), V.parent.as<int32_t>(),
@@ -1481,6 +1501,19 @@ void split_operators(Plan &P, hipStream_t s) {
 void alloc_workspace(Plan &P) {
     const size_t esz = P.precision == FMB_FP64 ? sizeof(cx<double>) : sizeof(cx<float>);
     const int64_t blk = (int64_t)P.nrhs_max * 3 * P.P2;
+    if (P.hf) {
+        // order per level; the translations need no slot buffer
+        for (int l = std::max(2, P.far_lmin); l <= P.depth; ++l) {
+            Level &V = P.lv[l];
+            const int64_t b = (int64_t)P.nrhs_max * 3 * V.p * V.p;
+            V.M.alloc((size_t)V.nbox * b * esz);
+            V.L.alloc((size_t)V.nbox * b * esz);
+        }
+        P.ybuf.alloc(256);
+        P.src.alloc((size_t)P.nrhs_max * P.n * 7 * esz);
+        P.ys.alloc((size_t)P.nrhs_max * P.n * 3 * esz);
+        return;
+    }
     // S|R slots of all levels side by side (they are written in one run of
     // launches); the S|S slots of the upward pass reuse the front of the buffer
     int64_t slots = 1, sr = 0;

@@ -44,8 +44,18 @@ struct Level {
     DevBuf l2l;           // [8]: parent (level-1) -> child at this level with octant o
     // split-BF16 fragment-major copies of the three operator sets (FP32 plans only)
     DevBuf m2l_hi, m2l_lo, m2m_hi, m2m_lo, l2l_hi, l2l_lo;
-    // expansions [nbox][nrhs_max][3][P2] complex
+    // expansions [nbox][nrhs_max][3][P2] complex (P2 = p^2 of this level)
     DevBuf M, L;
+    // plans with an order per level (rotation / coaxial translations, hf.hip)
+    int p = 0;                  // truncation order of this level
+    DevBuf hW;                  // M2L rotation tables [polar-angle class][hwsz], plan precision
+    DevBuf hWo;                 // octant rotation tables [2][hwszo] (cos theta = +-1/sqrt 3)
+    DevBuf hph, hpho;           // e^{i m phi}: [343 offsets][p] and [16 octant directions][hpwo]
+    DevBuf hC, hCss, hCrr;      // coaxial S|R [distance class][hcsz]; S|S from level+1; R|R from level-1
+    DevBuf hopi;                // i32[343][2]: polar-angle class, distance class of each far-field offset
+    DevBuf hboct;               // i32[16]: polar-angle class of each octant direction
+    int64_t hwsz = 0, hwszo = 0, hcsz = 0;
+    int hpwo = 0;
 };
 
 // stage timers (HIP events on the matvec stream), enabled per plan
@@ -81,6 +91,11 @@ struct Plan {
     int far_lmin = 2;
     double rcut2 = 1e300;
     bool far_on() const { return far_lmin <= depth; }
+    // order <= 0 at fmm_plan: an order per level for the tolerance `tol`, translations by
+    // rotation and coaxial shift (order = the leaf level's order)
+    bool hf = false;
+    double tol = 0.0;
+    DevBuf hscratch;  // vectors of translation stages too large for LDS
     std::vector<Level> lv;
     // per-node data in Morton order
     DevBuf codes;     // u64[n] user order
@@ -117,6 +132,13 @@ void build_tree(Plan &P, const double *d_pts, hipStream_t s, const int32_t *host
 void gather_nodes(Plan &P, const double *d_pts, const double *d_nrm, const double *d_w, const int32_t *d_tri,
                   hipStream_t s);
 void build_operators(Plan &P, hipStream_t s);
+void build_basis_tables(Plan &P, hipStream_t s);
+// order per level (hf.hip)
+int hf_order(double kabs, double side, double tol);
+void build_hf(Plan &P, hipStream_t s);
+template <typename T> void hf_m2m(Plan &P, int l, int nrhs, hipStream_t s);
+template <typename T> void hf_m2l(Plan &P, int l, int nrhs, hipStream_t s);
+template <typename T> void hf_l2l(Plan &P, int l, int nrhs, hipStream_t s);
 void build_corrections(Plan &P, const double *d_pts, const double *d_nrm, const double *d_tri,
                        hipStream_t s);
 void scatter_with_corrections(Plan &P, const void *ys, const void *a, const void *b, void *y, int nrhs,

@@ -1973,38 +1973,53 @@ int bem_problem_create_ibc(fmb_plan_t p0, fmb_plan_t p0_32, const double *Z, voi
     });
 }
 
+}  // extern "C"
+
+namespace {
+
+// The field sums of bem_field.  `staging` is device memory
+// for the nt target points, or NULL to allocate it for this call.
+void field_sums(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt, int32_t region,
+                int32_t far, void *E, hipStream_t s, double *staging) {
+    FMB_REQUIRE(pb && x && points && E, "bad arguments");
+    FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
+    FMB_REQUIRE(nt >= 1, "no target points");
+    FMB_REQUIRE(region == 0 || (region == 1 && !pb->ibc && pb->J == 1),
+                "region must be 0 (host) or 1 (interior of a one-scatterer dielectric problem)");
+    FMB_REQUIRE(far >= 0 && far <= 2, "kind must be 0 (field), 1 (far field) or 2 (curl)");
+    FMB_REQUIRE(far == 0 || region == 0, "the far field and the curl are of the host region");
+    for (int64_t i = 0; i < 3 * nt; ++i) FMB_REQUIRE(std::isfinite(points[i]), "non-finite target point");
+    if (far == 1)
+        for (int64_t i = 0; i < nt; ++i) {
+            const double r2 = points[3 * i] * points[3 * i] + points[3 * i + 1] * points[3 * i + 1] +
+                              points[3 * i + 2] * points[3 * i + 2];
+            FMB_REQUIRE(std::fabs(r2 - 1.0) <= 1e-9, "far-field directions must be unit vectors");
+        }
+    const Plan &A = pb->p0->p;
+    const Plan &K = region == 1 ? pb->p1->p : A;
+    DevBuf dt;
+    if (!staging) {
+        dt.alloc((size_t)nt * 3 * sizeof(double));
+        staging = dt.as<double>();
+    }
+    FMB_CHECK_HIP(hipMemcpyAsync(staging, points, (size_t)nt * 3 * sizeof(double), hipMemcpyHostToDevice, s));
+    const cx<double> tc = cdiv(mk(1.0, 0.0) - pb->eps, pb->eps);
+    const dim3 grid((unsigned)((nt + FE_TILE - 1) / FE_TILE), (unsigned)nrhs);
+    auto kern = far == 1 ? k_field<1> : (far == 2 ? k_field<2> : k_field<0>);
+    kern<<<grid, FE_TILE, 0, s>>>(staging, nt, A.spts.as<double>(), A.snrm.as<double>(), A.sw.as<double>(),
+                                  A.perm.as<int32_t>(), (const cx<double> *)x, pb->n, pb->nu, region,
+                                  pb->ibc ? 1 : 0, K.k_re, K.k_im, tc, pb->gamma, pb->cibc, (cx<double> *)E);
+    FMB_LAUNCH_CHECK();
+    FMB_CHECK_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+extern "C" {
+
 int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt, int32_t region,
               int32_t far, void *E, void *stream) {
-    return guarded([&] {
-        FMB_REQUIRE(pb && x && points && E, "bad arguments");
-        FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
-        FMB_REQUIRE(nt >= 1, "no target points");
-        FMB_REQUIRE(region == 0 || (region == 1 && !pb->ibc && pb->J == 1),
-                    "region must be 0 (host) or 1 (interior of a one-scatterer dielectric problem)");
-        FMB_REQUIRE(far >= 0 && far <= 2, "kind must be 0 (field), 1 (far field) or 2 (curl)");
-        FMB_REQUIRE(far == 0 || region == 0, "the far field and the curl are of the host region");
-        hipStream_t s = (hipStream_t)stream;
-        for (int64_t i = 0; i < 3 * nt; ++i) FMB_REQUIRE(std::isfinite(points[i]), "non-finite target point");
-        if (far == 1)
-            for (int64_t i = 0; i < nt; ++i) {
-                const double r2 = points[3 * i] * points[3 * i] + points[3 * i + 1] * points[3 * i + 1] +
-                                  points[3 * i + 2] * points[3 * i + 2];
-                FMB_REQUIRE(std::fabs(r2 - 1.0) <= 1e-9, "far-field directions must be unit vectors");
-            }
-        const Plan &A = pb->p0->p;
-        const Plan &K = region == 1 ? pb->p1->p : A;
-        DevBuf dt;
-        dt.alloc((size_t)nt * 3 * sizeof(double));
-        FMB_CHECK_HIP(hipMemcpyAsync(dt.p, points, (size_t)nt * 3 * sizeof(double), hipMemcpyHostToDevice, s));
-        const cx<double> tc = cdiv(mk(1.0, 0.0) - pb->eps, pb->eps);
-        const dim3 grid((unsigned)((nt + FE_TILE - 1) / FE_TILE), (unsigned)nrhs);
-        auto kern = far == 1 ? k_field<1> : (far == 2 ? k_field<2> : k_field<0>);
-        kern<<<grid, FE_TILE, 0, s>>>(dt.as<double>(), nt, A.spts.as<double>(), A.snrm.as<double>(), A.sw.as<double>(),
-                                      A.perm.as<int32_t>(), (const cx<double> *)x, pb->n, pb->nu, region,
-                                      pb->ibc ? 1 : 0, K.k_re, K.k_im, tc, pb->gamma, pb->cibc, (cx<double> *)E);
-        FMB_LAUNCH_CHECK();
-        FMB_CHECK_HIP(hipStreamSynchronize(s));
-    });
+    return guarded([&] { field_sums(pb, x, nrhs, points, nt, region, far, E, (hipStream_t)stream, nullptr); });
 }
 
 int bem_far_field_adjoint(fmb_problem_t pb, const void *G, int32_t nrhs, const double *dirs, int64_t nd, void *xbar,

@@ -69,7 +69,9 @@ class BemProblem:
     """
 
     def __init__(self, nodes, k0, eps, mu=1.0, order=16, depth=0, nrhs_max=1, order32=None,
-                 corr="linear", leaf_target=32, translate32="fp32"):
+                 corr="linear", leaf_target=32, translate32="fp32", tol=0.0, tol32=0.0):
+        """order / order32 = 0 choose an order per level for tol / tol32 (fmm_plan with
+        order <= 0); order32 None builds no FP32 plans."""
         lib = _abi.load()
         self._lib = lib
         self.k0 = complex(k0)
@@ -79,13 +81,13 @@ class BemProblem:
         kw = dict(point_tri=nodes["point_tri"], tri_vertices=nodes["tri_vertices"], nrhs_max=nrhs_max,
                   corr=corr, depth=depth, leaf_target=leaf_target)
         pts, nrm, w = nodes["points"], nodes["normals"], nodes["weights"]
-        self.p0 = Plan(pts, nrm, w, self.k0, order, **kw)
+        self.p0 = Plan(pts, nrm, w, self.k0, order, tol=tol, **kw)
         kw["depth"] = self.p0.info()["depth"]
-        self.p1 = Plan(pts, nrm, w, self.k1, order, **kw)
+        self.p1 = Plan(pts, nrm, w, self.k1, order, tol=tol, **kw)
         self.p0_32 = self.p1_32 = None
-        if order32:
-            self.p0_32 = Plan(pts, nrm, w, self.k0, order32, precision="fp32", translate=translate32, **kw)
-            self.p1_32 = Plan(pts, nrm, w, self.k1, order32, precision="fp32", translate=translate32, **kw)
+        if order32 is not None:
+            self.p0_32 = Plan(pts, nrm, w, self.k0, order32, precision="fp32", translate=translate32, tol=tol32, **kw)
+            self.p1_32 = Plan(pts, nrm, w, self.k1, order32, precision="fp32", translate=translate32, tol=tol32, **kw)
         self.n = pts.shape[0]
         self.nrhs_max = nrhs_max
         eps_a = np.array([self.eps.real, self.eps.imag])

@@ -124,12 +124,14 @@ def test_corrections_match_oracle(abi, sphere, mesh, k, depth):
     P1.close()
 
 
-@pytest.mark.parametrize("k,lmin", [(20 + 4000j, None), (2 + 100j, 3)])
+@pytest.mark.parametrize("k,lmin", [(2 + 400j, None), (2 + 100j, 3)])
 def test_lossy_cutoff_matches_direct_sum(abi, sphere, k, lmin):
     """Lossy wavenumbers (g decays as exp(-Im k R), Sec. 2.1): levels whose box side
-    damps the kernel below the cutoff keep no far field.  At 20+4000i the plan is
-    local only (near pairs beyond ln(1e16)/Im k dropped too); at 2+100i level 2 is
-    cut and levels 3.. kept.  Both equal the direct sum to FMM accuracy."""
+    damps the kernel below the cutoff keep no far field.  At 2+400i the plan is
+    local only, and near pairs beyond ln(1e16)/Im k = 0.092 are dropped too (the
+    1280-triangle sphere's neighbouring nodes lie 0.03-0.1 apart, so some are kept
+    and some dropped); at 2+100i level 2 is cut and levels 3.. kept.  Both equal
+    the direct sum to FMM accuracy."""
     q = sphere
     n = q["points"].shape[0]
     a, b = _dens(n, 1)
@@ -138,7 +140,7 @@ def test_lossy_cutoff_matches_direct_sum(abi, sphere, k, lmin):
     ref = point_sum_c(q["points"], q["normals"], q["weights"], q["point_tri"], k, a, b)
     err = _rel(y, ref)
     print("lossy cutoff k=", k, "rel err", err)
-    assert err <= (1e-12 if lmin is None else 1e-6)
+    assert err <= (1e-10 if lmin is None else 1e-6)
     P.close()
 
 
@@ -198,8 +200,9 @@ def _rows_every_leaf(q, depth, total, seed):
 
 
 # measured relative errors of the benchmark's FP32 operator (p = 5) against the
-# direct sum on these rows; the bounds are 1.5x the larger of the two
-TORUS_P5_BOUND = {4.0: 1e-2, complex(0.5161, 15.5034): 1e-2}
+# direct sum on these rows (1.115e-3 at k0, 7.85e-4 at k1, the same for both
+# translation kernels: the order-5 truncation dominates); bounds 1.5x those
+TORUS_P5_BOUND = {4.0: 1.7e-3, complex(0.5161, 15.5034): 1.2e-3}
 
 
 @pytest.mark.parametrize("k", [4.0, complex(0.5161, 15.5034)])
