@@ -369,6 +369,19 @@ int gmres_solve_group(const fmb_problem_t *pbs, int32_t count, const void *const
 int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt, int32_t region,
               int32_t far, void *E, void *stream);
 
+/*
+ * bem_field_noalloc: bem_field for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as bem_field; it calls no
+ * hipMalloc or hipFree.  The target points are staged in a fixed array that the
+ * library holds on every GPU it runs on until the process ends, so nt is at most
+ * FMB_FIELD_NOALLOC_MAX_TARGETS (more is FMB_EINVAL).  All calls on one GPU share
+ * that array: calls that overlap on one GPU (other threads or streams) race;
+ * calls in sequence do not, since each returns after its stream is idle.
+ */
+#define FMB_FIELD_NOALLOC_MAX_TARGETS 65536
+int bem_field_noalloc(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt,
+                      int32_t region, int32_t far, void *E, void *stream);
 
 /*
  * bem_far_field_adjoint: the conjugate transpose of the far-field map of

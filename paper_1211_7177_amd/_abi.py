@@ -16,6 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfmbem.so")
 
 FMB_OK, FMB_EINVAL, FMB_ENOMEM, FMB_EDEVICE, FMB_ENOCONV, FMB_EBREAKDOWN, FMB_ENONFINITE, FMB_ENOTIMPL = range(8)
+# largest target count of bem_field_noalloc (FMB_FIELD_NOALLOC_MAX_TARGETS in the header)
+FIELD_NOALLOC_MAX = 65536
 FMB_FP64, FMB_FP32 = 0, 1
 CORR = {"none": 0, "mean": 1, "linear": 2}
 
@@ -57,7 +59,7 @@ class GmresInfo(ctypes.Structure):
 EXPORTS = [
     "fmb_plan_opts_default", "fmm_plan", "fmm_matvec", "fmm_matvec_adjoint", "fmm_plan_info",
     "fmm_plan_export_tree", "fmm_plan_destroy", "fmm_plan_profile", "fmm_plan_profile_read", "fmb_gmres_opts_default", "bem_problem_create", "bem_problem_create_multi", "bem_problem_create_ibc", "bem_problem_use_graphs", "bem_apply", "bem_apply_adjoint",
-    "bem_precond_apply", "bem_rhs_planewave", "bem_field", "bem_field_fmm", "bem_far_field_adjoint", "gmres_solve", "gmres_solve_group", "bem_problem_destroy", "fmb_last_error",
+    "bem_precond_apply", "bem_rhs_planewave", "bem_field", "bem_field_noalloc", "bem_field_fmm", "bem_far_field_adjoint", "gmres_solve", "gmres_solve_group", "bem_problem_destroy", "fmb_last_error",
 ]
 
 _lib = None
@@ -96,6 +98,7 @@ def load():
         "gmres_solve": [vp, vp, vp, i32, vp, vp, vp],
         "gmres_solve_group": [vp, i32, vp, vp, vp, vp, vp, vp],
         "bem_field": [vp, vp, i32, vp, ctypes.c_int64, i32, i32, vp, vp],
+        "bem_field_noalloc": [vp, vp, i32, vp, ctypes.c_int64, i32, i32, vp, vp],
         "bem_field_fmm": [vp, vp, i32, vp, ctypes.c_int64, i32, i32, vp, vp],
         "bem_far_field_adjoint": [vp, vp, i32, vp, ctypes.c_int64, vp, vp],
         "bem_problem_destroy": [vp],

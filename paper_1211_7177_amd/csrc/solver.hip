@@ -29,6 +29,7 @@
 // FMM products of each application run concurrently on two streams.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <type_traits>
@@ -1977,7 +1978,7 @@ int bem_problem_create_ibc(fmb_plan_t p0, fmb_plan_t p0_32, const double *Z, voi
 
 namespace {
 
-// The field sums of bem_field.  `staging` is device memory
+// The field sums of bem_field and bem_field_noalloc.  `staging` is device memory
 // for the nt target points, or NULL to allocate it for this call.
 void field_sums(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt, int32_t region,
                 int32_t far, void *E, hipStream_t s, double *staging) {
@@ -2013,6 +2014,32 @@ void field_sums(fmb_problem_t pb, const void *x, int32_t nrhs, const double *poi
     FMB_CHECK_HIP(hipStreamSynchronize(s));
 }
 
+// Scratch of bem_field_noalloc: the staged target points.  Each GPU holds its
+// own copy of this array from the library's load to the process's end; host
+// code uses only the device address that hipGetSymbolAddress returns for it.
+constexpr int64_t FIELD_NOALLOC_MAX = FMB_FIELD_NOALLOC_MAX_TARGETS;
+__device__ __align__(256) double scratch[FIELD_NOALLOC_MAX * 3];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The current device's address of `scratch`, looked up on the first call on
+// that device (with it current) and kept.
+double *scratch_for_current_device() {
+    int dev = 0;
+    FMB_CHECK_HIP(hipGetDevice(&dev));
+    FMB_REQUIRE(dev >= 0 && dev < MAX_DEVICES, "device index out of range for bem_field_noalloc");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        FMB_CHECK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        FMB_REQUIRE(ptr != nullptr, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -2020,6 +2047,16 @@ extern "C" {
 int bem_field(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt, int32_t region,
               int32_t far, void *E, void *stream) {
     return guarded([&] { field_sums(pb, x, nrhs, points, nt, region, far, E, (hipStream_t)stream, nullptr); });
+}
+
+int bem_field_noalloc(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt,
+                      int32_t region, int32_t far, void *E, void *stream) {
+    return guarded([&] {
+        FMB_REQUIRE(nt <= FIELD_NOALLOC_MAX, "bem_field_noalloc takes at most " +
+                                                 std::to_string(FIELD_NOALLOC_MAX) + " target points per call");
+        double *staging = scratch_for_current_device();
+        field_sums(pb, x, nrhs, points, nt, region, far, E, (hipStream_t)stream, staging);
+    });
 }
 
 int bem_far_field_adjoint(fmb_problem_t pb, const void *G, int32_t nrhs, const double *dirs, int64_t nd, void *xbar,
