@@ -158,7 +158,9 @@ int fmm_matvec_adjoint(fmb_plan_t plan, const void *y, void *a_bar, void *b_bar,
 int fmm_plan_info(fmb_plan_t plan, fmb_plan_info *info);
 
 /*
- * fmm_plan_export_tree: copy the octree to host memory for inspection.
+ * fmm_plan_export_tree: copy the octree of App. C (levels, boxes, Neighbor and
+ * far-field lists FF(l, q) = Children(Neighbor(Parent)) minus Neighbor) to
+ * host memory for inspection.
  *   codes  host u64[n]   Morton code of every node (user order)
  *   perm   host i32[n]   perm[i] = user index of the i-th node in Morton order
  * and for one level l (0..depth), sized by fmm_plan_info.nbox[l] = B:
@@ -311,7 +313,19 @@ int bem_apply_adjoint(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, vo
 /* bem_precond_apply: z = M^{-1} v with M = A_self (6x6 per node, eq. 3.2). c128 [nrhs][n][6]. */
 int bem_precond_apply(fmb_problem_t pb, const void *v, void *z, int32_t nrhs, void *stream);
 
-/* bem_rhs_planewave: rhs[q] = (p_q exp(i k0 d_q . s), 0); dirs, pols host f64[nrhs][3]. */
+/*
+ * bem_rhs_planewave: the right-hand side Phi^inc of eqs. 2.9-2.12 for incident
+ * plane waves E^inc(s) = p_q exp(i k0 d_q . s) in the host medium (no incident
+ * field inside the scatterers, Sec. 2.1):
+ *   rhs[q][alpha] = (p_q exp(i k0 d_q . s_alpha), 0, 0, 0)    (6 unknowns per node)
+ *   rhs[q][alpha] = p_q exp(i k0 d_q . s_alpha)                (impedance problems)
+ *   dirs  host f64[nrhs][3]   propagation directions (used as given)
+ *   pols  host c128[nrhs][3]  complex polarisations (linear, circular or
+ *                             elliptic; interleaved re, im), used as given
+ *   rhs   device c128[nrhs][n][nu], user node order, written
+ * Synchronises `stream` before returning (dirs and pols may be freed).
+ * FMB_EINVAL for a null pointer or nrhs < 1.
+ */
 int bem_rhs_planewave(fmb_problem_t pb, const double *dirs, const double *pols, void *rhs,
                       int32_t nrhs, void *stream);
 

@@ -15,14 +15,14 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 size_t Plan::device_bytes() const {
     size_t b = codes.bytes + perm.bytes + iperm.bytes + spts.bytes + snrm.bytes + sw.bytes + stri.bytes +
                inv_alpha.bytes + btab.bytes + bgix.bytes + point_tri.bytes + unrm.bytes + tri_nodes.bytes + corr_v.bytes + corr_g.bytes +
-               src.bytes + ys.bytes + ybuf.bytes + hscratch.bytes;
+               src.bytes + ys.bytes + ybuf.bytes + hscratch.bytes + hX1.bytes + hX2.bytes;
     for (const Level &V : lv)
         b += V.keys.bytes + V.start.bytes + V.parent.bytes + V.center.bytes + V.nbr.bytes + V.child_start.bytes +
              V.octant.bytes + V.ff_ofs.bytes + V.ff_src.bytes + V.ff_op.bytes + V.ff_by_op.bytes + V.by_octant.bytes +
              V.m2l.bytes + V.m2m.bytes + V.l2l.bytes + V.m2l_hi.bytes + V.m2l_lo.bytes + V.m2m_hi.bytes +
              V.m2m_lo.bytes + V.l2l_hi.bytes + V.l2l_lo.bytes + V.M.bytes + V.L.bytes + V.tiles_m2l.bytes + V.tiles_m2m.bytes +
              V.tiles_l2l.bytes + V.hW.bytes + V.hWo.bytes + V.hph.bytes + V.hpho.bytes + V.hC.bytes + V.hCss.bytes +
-             V.hCrr.bytes + V.hopi.bytes + V.hboct.bytes;
+             V.hCrr.bytes + V.hopi.bytes + V.hboct.bytes + V.hoinfo.bytes + V.hnck.bytes + V.hmck.bytes;
     return b;
 }
 

@@ -153,7 +153,7 @@ enum { CX_SR = 0, CX_SS = 1, CX_RR = 2 };
 
 // coaxial coefficients C^m_{n'n}(t) along +z for n' < pd, n < ps, times the scale
 // factors of the stored coefficients; block m at offset sum_{j<m}(pd-j)(ps-j),
-// entry (n'-m)(ps-m) + (n-m)
+// entry (n-m)(pd-m) + (n'-m) (consecutive output degrees n' adjacent)
 // For S|S and R|R (regular translation function) the degree recurrence loses
 // accuracy above the diagonal when k|t| is small (each step cancels terms a
 // factor (k|t|)^2 larger than the result); there only the part n' >= n is
@@ -207,7 +207,7 @@ void coax_table(int kind, cd k, double t, int pd, int ps, const std::vector<doub
                 else if (kind == CX_SS) sc = as[n] / ad[q];
                 else sc = ad[q] / as[n];
                 const cd v = (sym && q < n) ? (((q + n) & 1) ? -1.0 : 1.0) * at(n, q) : at(q, n);
-                out[off + (int64_t)(q - m) * (ps - m) + (n - m)] = sc * v;
+                out[off + (int64_t)(n - m) * (pd - m) + (q - m)] = sc * v;
             }
         off += (int64_t)(pd - m) * (ps - m);
     }
@@ -298,22 +298,27 @@ __device__ void hf_translate(const cx<T> *__restrict__ src, int64_t sstr, const 
             // block offset sum_{j < am} (pd - j)(ps - j)
             int64_t off = 0;
             for (int j = 0; j < am; ++j) off += (int64_t)(pd - j) * (ps - j);
-            const cx<T> *row = C + off + (int64_t)(q - am) * (ps - am);
+            const cx<T> *col = C + off + (q - am);
             const cx<T> *x = b2 + c * S2;
-            for (int n = am; n < ps; ++n) s += row[n - am] * x[n * n + n + m];
+            for (int n = am; n < ps; ++n) s += col[(int64_t)(n - am) * (pd - am)] * x[n * n + n + m];
         }
         b1[c * D2 + e] = s;
     }
     __syncthreads();
-    // 4: rotation back, d_n^m' = e^{-i m' phi} sum_m W[n][m'][m] c''_n^m, accumulated
+    // 4: rotation back, d_n^m' = e^{-i m' phi} sum_m W[n][m'][m] c''_n^m, accumulated;
+    //    W[n][m'][m] = (-1)^(m-m') W[n][m][m'] (Wigner's d^n_{m m'} = (-1)^(m-m') d^n_{m' m}),
+    //    read along m' so that neighbouring threads read neighbouring entries
     for (int t = threadIdx.x; t < CH * D2; t += blockDim.x) {
         const int c = t / D2, e = t - c * D2;
         int n, mp;
         hf_nm(e, n, mp);
-        const T *w = W + (int64_t)n * (2 * n - 1) * (2 * n + 1) / 3 + (int64_t)(mp + n) * (2 * n + 1);
+        const T *w = W + (int64_t)n * (2 * n - 1) * (2 * n + 1) / 3 + (mp + n);
         const cx<T> *x = b1 + c * D2 + n * n;
         cx<T> s = mk(T(0), T(0));
-        for (int m = 0; m <= 2 * n; ++m) s += w[m] * x[m];
+        for (int m = 0; m <= 2 * n; ++m) {
+            const T wm = w[(int64_t)m * (2 * n + 1)];
+            s += (((m + mp + n) & 1) ? -wm : wm) * x[m];
+        }
         const cx<T> f = mp >= 0 ? conj(ph[mp]) : ph[-mp];
         acc[c * D2 + e] += f * s;
     }
@@ -427,6 +432,311 @@ int hf_mode(int64_t P2m, int64_t D2) {
     return 0;
 }
 
+// ---------------------------------------------------------------- pipeline
+// Large orders: each translation set in three launches that spread one
+// translation over many blocks.  Pairs e carry a source box, a direction d
+// (phase row, polar-angle class, distance class) and belong to a destination
+// (CSR); the forward rotation and the coaxial shift go to per-pair scratch, and
+// the back rotation walks each destination's pairs in order (deterministic).
+
+__device__ inline int64_t hf_woff(int n) { return (int64_t)n * (2 * n - 1) * (2 * n + 1) / 3; }
+
+template <typename T>
+__device__ inline cx<T> hf_phase(const cx<T> *ph, int m) { return m >= 0 ? ph[m] : conj(ph[-m]); }
+
+// position of item u within the |m|-blocks [m0, ...) of a coaxial shift to order
+// pd, items ordered (|m|, sign, n'): returns |m|, m and n'
+__device__ inline void hf_coax_item(int u, int m0, int pd, int &am, int &m, int &q) {
+    am = m0;
+    while (u >= (pd - am) * (am ? 2 : 1)) {
+        u -= (pd - am) * (am ? 2 : 1);
+        ++am;
+    }
+    const int len = pd - am;
+    m = u < len ? am : -am;
+    q = am + (u < len ? u : u - len);
+}
+
+// offset of block |m| = am in a coaxial table of orders (pd, ps): sum_{j < am} (pd - j)(ps - j)
+__device__ inline int64_t hf_coff(int am, int pd, int ps) {
+    return (int64_t)am * pd * ps - (int64_t)(pd + ps) * am * (am - 1) / 2 + (int64_t)(am - 1) * am * (2 * am - 1) / 6;
+}
+
+// X1[e][r][c][(n,m')] = sum_m W[n][m][m'] e^{i m phi} S[src][r][c][(n,m)], degrees [nck[z], nck[z+1]);
+// one thread per coefficient, all three channels (one rotation-table read serves three)
+template <typename T>
+__global__ void __launch_bounds__(HTPB) k_hf_fwd(const int32_t *__restrict__ src_idx, const int32_t *__restrict__ dir,
+                                                 int dir_add, const int32_t *__restrict__ dinfo,
+                                                 const T *__restrict__ W, int64_t wsz, const cx<T> *__restrict__ ph,
+                                                 int phs, const int32_t *__restrict__ nck, int ps, int nrhs_max,
+                                                 int nrhs, const cx<T> *__restrict__ S, cx<T> *__restrict__ X1) {
+    const int e = blockIdx.x, r = blockIdx.y, z = blockIdx.z;
+    const int n0 = nck[z], n1 = nck[z + 1];
+    const int d = dir[e] + dir_add;
+    const T *Wb = W + (int64_t)dinfo[2 * d] * wsz;
+    const cx<T> *phd = ph + (int64_t)d * phs;
+    const int64_t src = src_idx ? src_idx[e] : e;
+    const int64_t P2 = (int64_t)ps * ps;
+    const int base = n0 * n0, cnt = n1 * n1 - base;
+    const cx<T> *S0 = S + (src * nrhs_max + r) * 3 * P2;
+    cx<T> *X0 = X1 + ((int64_t)e * nrhs + r) * 3 * P2;
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+        const int ee = base + t;
+        int n, mp;
+        hf_nm(ee, n, mp);
+        const T *w = Wb + hf_woff(n) + (mp + n);
+        const cx<T> *x = S0 + n * n;
+        cx<T> a0 = mk(T(0), T(0)), a1 = a0, a2 = a0;
+        for (int m = 0; m <= 2 * n; ++m) {
+            const cx<T> g = w[(int64_t)m * (2 * n + 1)] * hf_phase(phd, m - n);
+            a0 += g * x[m];
+            a1 += g * x[P2 + m];
+            a2 += g * x[2 * P2 + m];
+        }
+        X0[ee] = a0;
+        X0[P2 + ee] = a1;
+        X0[2 * P2 + ee] = a2;
+    }
+}
+
+// X2[e][r][c][(q,m)] = sum_n C^|m|_{q n} X1[e][r][c][(n,m)], |m| in [mck[z], mck[z+1]), q < pd;
+// consecutive threads take consecutive q (adjacent table entries), all three channels
+template <typename T>
+__global__ void __launch_bounds__(HTPB) k_hf_coax(const int32_t *__restrict__ dir, int dir_add,
+                                                  const int32_t *__restrict__ dinfo, const cx<T> *__restrict__ C,
+                                                  int64_t csz, const int32_t *__restrict__ mck, int ps, int pd,
+                                                  int nrhs, const cx<T> *__restrict__ X1, cx<T> *__restrict__ X2) {
+    const int e = blockIdx.x, r = blockIdx.y, z = blockIdx.z;
+    const int m0 = mck[z], m1 = mck[z + 1];
+    const int d = dir[e] + dir_add;
+    const cx<T> *Cd = C + (int64_t)dinfo[2 * d + 1] * csz;
+    const int64_t S2 = (int64_t)ps * ps, D2 = (int64_t)pd * pd;
+    int cnt = 0;
+    for (int am = m0; am < m1; ++am) cnt += (pd - am) * (am ? 2 : 1);
+    const cx<T> *x = X1 + ((int64_t)e * nrhs + r) * 3 * S2;
+    cx<T> *y = X2 + ((int64_t)e * nrhs + r) * 3 * D2;
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+        int am, m, q;
+        hf_coax_item(t, m0, pd, am, m, q);
+        cx<T> a0 = mk(T(0), T(0)), a1 = a0, a2 = a0;
+        if (am < ps) {
+            const cx<T> *col = Cd + hf_coff(am, pd, ps) + (q - am);
+            for (int n = am; n < ps; ++n) {
+                const cx<T> cv = col[(int64_t)(n - am) * (pd - am)];
+                const int i = n * n + n + m;
+                a0 += cv * x[i];
+                a1 += cv * x[S2 + i];
+                a2 += cv * x[2 * S2 + i];
+            }
+        }
+        const int o = q * q + q + m;
+        y[o] = a0;
+        y[D2 + o] = a1;
+        y[2 * D2 + o] = a2;
+    }
+}
+
+// D[b][r][c][(n,m')] (=, or += with accumulate) sum over b's pairs e of
+// e^{-i m' phi_e} sum_m W_e[n][m'][m] X2[e][r][c][(n,m)], degrees [nck[z], nck[z+1]);
+// W[n][m'][m] = (-1)^(m-m') W[n][m][m'] (Wigner's d^n_{m m'} = (-1)^(m-m') d^n_{m' m}) is read along m'
+template <typename T>
+__global__ void __launch_bounds__(HTPB) k_hf_back(const int32_t *__restrict__ dst_ofs, const int32_t *__restrict__ dir,
+                                                  int dir_add, const int32_t *__restrict__ dinfo,
+                                                  const T *__restrict__ W, int64_t wsz, const cx<T> *__restrict__ ph,
+                                                  int phs, const int32_t *__restrict__ nck, int pd, int nrhs_max,
+                                                  int nrhs, int accumulate, const cx<T> *__restrict__ X2,
+                                                  cx<T> *__restrict__ D) {
+    const int b = blockIdx.x, r = blockIdx.y, z = blockIdx.z;
+    const int n0 = nck[z], n1 = nck[z + 1];
+    const int e0 = dst_ofs ? dst_ofs[b] : b, e1 = dst_ofs ? dst_ofs[b + 1] : b + 1;
+    const int64_t D2 = (int64_t)pd * pd;
+    const int base = n0 * n0, cnt = n1 * n1 - base;
+    cx<T> *out = D + ((int64_t)b * nrhs_max + r) * 3 * D2;
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+        const int ee = base + t;
+        int n, mp;
+        hf_nm(ee, n, mp);
+        cx<T> a0, a1, a2;
+        if (accumulate) {
+            a0 = out[ee];
+            a1 = out[D2 + ee];
+            a2 = out[2 * D2 + ee];
+        } else {
+            a0 = a1 = a2 = mk(T(0), T(0));
+        }
+        for (int e = e0; e < e1; ++e) {
+            const int d = dir[e] + dir_add;
+            const T *w = W + (int64_t)dinfo[2 * d] * wsz + hf_woff(n) + (mp + n);
+            const cx<T> *x = X2 + ((int64_t)e * nrhs + r) * 3 * D2 + n * n;
+            cx<T> s0 = mk(T(0), T(0)), s1 = s0, s2 = s0;
+            for (int m = 0; m <= 2 * n; ++m) {
+                const T wm0 = w[(int64_t)m * (2 * n + 1)];
+                const T wm = ((m + mp + n) & 1) ? -wm0 : wm0;
+                s0 += wm * x[m];
+                s1 += wm * x[D2 + m];
+                s2 += wm * x[2 * D2 + m];
+            }
+            const cx<T> f = hf_phase(ph + (int64_t)d * phs, -mp);
+            a0 += f * s0;
+            a1 += f * s1;
+            a2 += f * s2;
+        }
+        out[ee] = a0;
+        out[D2 + ee] = a1;
+        out[2 * D2 + ee] = a2;
+    }
+}
+
+// ------------------------------------------------------- small-order M2L
+// Orders up to 20 (the fine levels, most boxes): one block per (target box,
+// right-hand side), its four wavefronts translating four far-field sources at
+// a time, each in its own LDS buffers.  A lane works on all three channels of
+// a coefficient (one table read serves three).  Each lane keeps J of the
+// target's coefficients in registers (t = lane + 64 j) and adds its
+// wavefront's translations in list order; the four partial sums are added in
+// wavefront order at the end (deterministic).
+constexpr int HFW_WAVES = 4;
+
+template <typename T, int J>
+__global__ void __launch_bounds__(256) k_hf_m2l_w(const int32_t *__restrict__ ff_ofs, const int32_t *__restrict__ ff_src,
+                                                  const int32_t *__restrict__ ff_op, const int32_t *__restrict__ opi,
+                                                  const T *__restrict__ W, int64_t wsz, const cx<T> *__restrict__ ph,
+                                                  const cx<T> *__restrict__ C, int64_t csz, int p, int nrhs_max,
+                                                  const cx<T> *__restrict__ M, cx<T> *__restrict__ Lout) {
+    extern __shared__ __align__(16) unsigned char hf_smem[];
+    const int b = blockIdx.x, r = blockIdx.y;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int P2 = p * p, N3 = 3 * P2;
+    cx<T> *A = reinterpret_cast<cx<T> *>(hf_smem) + (size_t)wv * 2 * N3;
+    cx<T> *B = A + N3;
+    // tab: (n, m + n) of coefficient t; tab2: (q, m + q) of the t-th coaxial item, ordered (|m|, sign, q)
+    int32_t *tab = reinterpret_cast<int32_t *>(reinterpret_cast<cx<T> *>(hf_smem) + (size_t)HFW_WAVES * 2 * N3);
+    int32_t *tab2 = tab + P2;
+    for (int t = threadIdx.x; t < P2; t += blockDim.x) {
+        int n, m;
+        hf_nm(t, n, m);
+        tab[t] = (n << 10) | (m + n);
+        int am, q;
+        hf_coax_item(t, 0, p, am, m, q);
+        tab2[t] = (q << 10) | (m + q);
+    }
+    cx<T> acc[3 * J];
+#pragma unroll
+    for (int j = 0; j < 3 * J; ++j) acc[j] = mk(T(0), T(0));
+    const int e0 = ff_ofs[b], cnt = ff_ofs[b + 1] - e0;
+    __syncthreads();
+    for (int base = 0; base < cnt; base += HFW_WAVES) {
+        const bool act = base + wv < cnt;
+        int s = 0, o = 0;
+        if (act) {
+            s = ff_src[e0 + base + wv];
+            o = ff_op[e0 + base + wv];
+        }
+        const T *Wb = W + (int64_t)opi[2 * o] * wsz;
+        const cx<T> *Cd = C + (int64_t)opi[2 * o + 1] * csz;
+        const cx<T> *pho = ph + (int64_t)o * p;
+        if (act) {
+            // source coefficients times e^{i m phi}
+            const cx<T> *src = M + ((int64_t)s * nrhs_max + r) * 3 * P2;
+            for (int t = lane; t < P2; t += 64) {
+                const int v = tab[t], n = v >> 10, m = (v & 1023) - n;
+                const cx<T> f = hf_phase(pho, m);
+                A[t] = f * src[t];
+                A[P2 + t] = f * src[P2 + t];
+                A[2 * P2 + t] = f * src[2 * P2 + t];
+            }
+        }
+        __syncthreads();
+        if (act) {
+            // rotation onto +z: B_n^m' = sum_m W[n][m][m'] A_n^m
+            for (int t = lane; t < P2; t += 64) {
+                const int v = tab[t], n = v >> 10, mpn = v & 1023;
+                const T *w = Wb + hf_woff(n) + mpn;
+                const cx<T> *x = A + n * n;
+                cx<T> s0 = mk(T(0), T(0)), s1 = s0, s2 = s0;
+                for (int m = 0; m <= 2 * n; ++m) {
+                    const T wm = w[(int64_t)m * (2 * n + 1)];
+                    s0 += wm * x[m];
+                    s1 += wm * x[P2 + m];
+                    s2 += wm * x[2 * P2 + m];
+                }
+                B[t] = s0;
+                B[P2 + t] = s1;
+                B[2 * P2 + t] = s2;
+            }
+        }
+        __syncthreads();
+        if (act) {
+            // coaxial shift: A_q^m = sum_n C^|m|_{q n} B_n^m
+            for (int t = lane; t < P2; t += 64) {
+                const int v = tab2[t], q = v >> 10, m = (v & 1023) - q;
+                const int am = m < 0 ? -m : m;
+                const cx<T> *col = Cd + hf_coff(am, p, p) + (q - am);
+                cx<T> s0 = mk(T(0), T(0)), s1 = s0, s2 = s0;
+                for (int n = am; n < p; ++n) {
+                    const cx<T> cv = col[(int64_t)(n - am) * (p - am)];
+                    const int i = n * n + n + m;
+                    s0 += cv * B[i];
+                    s1 += cv * B[P2 + i];
+                    s2 += cv * B[2 * P2 + i];
+                }
+                const int oi = q * q + q + m;
+                A[oi] = s0;
+                A[P2 + oi] = s1;
+                A[2 * P2 + oi] = s2;
+            }
+        }
+        __syncthreads();
+        if (act) {
+            // rotation back (W[n][m'][m] = (-1)^(m-m') W[n][m][m'], read along m') and e^{-i m' phi},
+            // added to this lane's coefficients
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int t = lane + 64 * j;
+                if (t < P2) {
+                    const int v = tab[t], n = v >> 10, mpn = v & 1023;
+                    const T *w = Wb + hf_woff(n) + mpn;
+                    const cx<T> *x = A + n * n;
+                    cx<T> s0 = mk(T(0), T(0)), s1 = s0, s2 = s0;
+                    for (int m = 0; m <= 2 * n; ++m) {
+                        const T wm0 = w[(int64_t)m * (2 * n + 1)];
+                        const T wm = ((m + mpn) & 1) ? -wm0 : wm0;
+                        s0 += wm * x[m];
+                        s1 += wm * x[P2 + m];
+                        s2 += wm * x[2 * P2 + m];
+                    }
+                    const cx<T> f = hf_phase(pho, n - mpn);
+                    acc[3 * j] += f * s0;
+                    acc[3 * j + 1] += f * s1;
+                    acc[3 * j + 2] += f * s2;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // the four wavefronts' sums, added in wavefront order
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int t = lane + 64 * j;
+        if (t < P2) {
+            A[t] = acc[3 * j];
+            A[P2 + t] = acc[3 * j + 1];
+            A[2 * P2 + t] = acc[3 * j + 2];
+        }
+    }
+    __syncthreads();
+    cx<T> *out = Lout + ((int64_t)b * nrhs_max + r) * 3 * P2;
+    const cx<T> *base0 = reinterpret_cast<cx<T> *>(hf_smem);
+    for (int t = threadIdx.x; t < N3; t += blockDim.x) {
+        cx<T> v = base0[t];
+        for (int w = 1; w < HFW_WAVES; ++w) v += base0[(size_t)w * 2 * N3 + t];
+        out[t] = v;
+    }
+}
+
+template <typename T>
+size_t hfw_lds(int p) { return (size_t)HFW_WAVES * 2 * 3 * p * p * sizeof(cx<T>) + (size_t)2 * p * p * sizeof(int32_t); }
+
 }  // namespace
 
 // order needed at a level: the low-frequency floor for the tolerance, or the
@@ -438,6 +748,41 @@ int hf_order(double kabs, double side, double tol) {
     const double pe = kd + 1.8 * std::pow(d0, 2.0 / 3.0) * std::cbrt(std::max(kd, 0.0));
     const double pf = 2.8 * d0;
     return (int)std::ceil(std::max(pe, pf));
+}
+
+// translation sets whose order exceeds this run as the three-launch pipeline;
+// M2L at orders up to HFW_PMAX runs one source per wavefront
+constexpr int HF_PIPE_P = 20;
+// (and needs at most 80 KB of LDS per block, so that two blocks share a CU)
+constexpr int HFW_PMAX = 20;
+constexpr size_t HFW_LDS_MAX = 80 * 1024;
+
+// chunk boundaries: degrees n < p with about 256 coefficients per chunk, and
+// |m| < p with about 256 outputs per chunk
+static std::vector<int32_t> degree_chunks(int p) {
+    std::vector<int32_t> v{0};
+    int acc = 0;
+    for (int n = 0; n < p; ++n) {
+        acc += 2 * n + 1;
+        if (acc >= 256 || n == p - 1) {
+            v.push_back(n + 1);
+            acc = 0;
+        }
+    }
+    return v;
+}
+
+static std::vector<int32_t> m_chunks(int p) {
+    std::vector<int32_t> v{0};
+    int acc = 0;
+    for (int am = 0; am < p; ++am) {
+        acc += (p - am) * (am ? 2 : 1);
+        if (acc >= 256 || am == p - 1) {
+            v.push_back(am + 1);
+            acc = 0;
+        }
+    }
+    return v;
 }
 
 void build_hf(Plan &P, hipStream_t s) {
@@ -527,6 +872,16 @@ void build_hf(Plan &P, hipStream_t s) {
         }
         upload_as<int32_t>(V.hopi, std::vector<double>(opi.begin(), opi.end()), s);
         upload_as<int32_t>(V.hboct, std::vector<double>(boct.begin(), boct.end()), s);
+        {
+            std::vector<double> oi(32, 0.0);
+            for (int q = 0; q < 16; ++q) oi[2 * q] = boct[q];
+            upload_as<int32_t>(V.hoinfo, oi, s);
+            const std::vector<int32_t> nc = degree_chunks(p), mc = m_chunks(p);
+            V.hnnck = (int)nc.size() - 1;
+            V.hnmck = (int)mc.size() - 1;
+            upload_as<int32_t>(V.hnck, std::vector<double>(nc.begin(), nc.end()), s);
+            upload_as<int32_t>(V.hmck, std::vector<double>(mc.begin(), mc.end()), s);
+        }
         if (f64) {
             upload_as<double>(V.hW, Wt, s);
             upload_as<double>(V.hWo, Wo, s);
@@ -567,14 +922,57 @@ void build_hf(Plan &P, hipStream_t s) {
         }
     }
     if (need) P.hscratch.alloc(need);
+    // per-pair vectors of the pipelined translation sets
+    size_t xneed = 0;
+    for (int l = lmin; l <= L; ++l) {
+        const Level &V = P.lv[l];
+        auto use = [&](int64_t npairs, int ps, int pd) {
+            if (std::max(ps, pd) > HF_PIPE_P)
+                xneed = std::max(xneed, (size_t)(npairs * P.nrhs_max * 3 * (int64_t)std::max(ps * ps, pd * pd)) * cs);
+        };
+        use(V.nff, V.p, V.p);
+        if (l < L) use(P.lv[l + 1].nbox, P.lv[l + 1].p, V.p);
+        if (l > lmin) use(V.nbox, P.lv[l - 1].p, V.p);
+    }
+    if (xneed) {
+        P.hX1.alloc(xneed);
+        P.hX2.alloc(xneed);
+    }
 }
 
 // ------------------------------------------------------------ launches
+
+// three-launch translation set: npairs pairs (source box src_idx[e] or e, direction dir[e] + dir_add)
+// into ndst destinations (pairs of b: dst_ofs[b] .. dst_ofs[b+1], or e = b)
+template <typename T>
+void hf_pipe(Plan &P, int nrhs, hipStream_t s, int64_t npairs, const int32_t *src_idx, const int32_t *dir,
+             int dir_add, const int32_t *dinfo, const T *W, int64_t wsz, const cx<T> *ph, int phs, const cx<T> *C,
+             int64_t csz, const Level &Vs, const Level &Vd, int64_t ndst, const int32_t *dst_ofs, int accumulate,
+             const cx<T> *S, cx<T> *D) {
+    if (npairs == 0 || ndst == 0) return;
+    const int ps = Vs.p, pd = Vd.p;
+    cx<T> *X1 = P.hX1.as<cx<T>>(), *X2 = P.hX2.as<cx<T>>();
+    k_hf_fwd<T><<<dim3((unsigned)npairs, (unsigned)nrhs, (unsigned)Vs.hnnck), HTPB, 0, s>>>(
+        src_idx, dir, dir_add, dinfo, W, wsz, ph, phs, Vs.hnck.as<int32_t>(), ps, P.nrhs_max, nrhs, S, X1);
+    FMB_LAUNCH_CHECK();
+    k_hf_coax<T><<<dim3((unsigned)npairs, (unsigned)nrhs, (unsigned)Vd.hnmck), HTPB, 0, s>>>(
+        dir, dir_add, dinfo, C, csz, Vd.hmck.as<int32_t>(), ps, pd, nrhs, X1, X2);
+    FMB_LAUNCH_CHECK();
+    k_hf_back<T><<<dim3((unsigned)ndst, (unsigned)nrhs, (unsigned)Vd.hnnck), HTPB, 0, s>>>(
+        dst_ofs, dir, dir_add, dinfo, W, wsz, ph, phs, Vd.hnck.as<int32_t>(), pd, P.nrhs_max, nrhs, accumulate, X2, D);
+    FMB_LAUNCH_CHECK();
+}
 
 template <typename T>
 void hf_m2m(Plan &P, int l, int nrhs, hipStream_t s) {
     Level &V = P.lv[l], &Cv = P.lv[l + 1];
     const int ps = Cv.p, pd = V.p;
+    if (std::max(ps, pd) > HF_PIPE_P) {
+        hf_pipe<T>(P, nrhs, s, Cv.nbox, nullptr, Cv.octant.as<int32_t>(), 0, V.hoinfo.as<int32_t>(), V.hWo.as<T>(),
+                   V.hwszo, V.hpho.as<cx<T>>(), V.hpwo, V.hCss.as<cx<T>>(), 0, Cv, V, V.nbox,
+                   V.child_start.as<int32_t>(), 0, Cv.M.as<cx<T>>(), V.M.as<cx<T>>());
+        return;
+    }
     const int64_t S2 = (int64_t)ps * ps, D2 = (int64_t)pd * pd, P2m = std::max(S2, D2);
     const int mode = hf_mode<T>(P2m, D2);
     const int ch = mode == 3 ? 3 : 1;
@@ -601,6 +999,30 @@ void hf_m2l(Plan &P, int l, int nrhs, hipStream_t s) {
         return;
     }
     const int p = V.p;
+    if (p > HF_PIPE_P) {
+        hf_pipe<T>(P, nrhs, s, V.nff, V.ff_src.as<int32_t>(), V.ff_op.as<int32_t>(), 0, V.hopi.as<int32_t>(),
+                   V.hW.as<T>(), V.hwsz, V.hph.as<cx<T>>(), p, V.hC.as<cx<T>>(), V.hcsz, V, V, V.nbox,
+                   V.ff_ofs.as<int32_t>(), 0, V.M.as<cx<T>>(), V.L.as<cx<T>>());
+        return;
+    }
+    if (p <= HFW_PMAX && hfw_lds<T>(p) <= HFW_LDS_MAX) {
+        const int J = (p * p + 63) / 64;
+        const size_t sh = hfw_lds<T>(p);
+        auto go = [&](auto kern) {
+            if (sh > 64 * 1024)
+                FMB_CHECK_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)HFW_LDS_MAX));
+            kern<<<dim3((unsigned)V.nbox, (unsigned)nrhs), 256, sh, s>>>(
+                V.ff_ofs.as<int32_t>(), V.ff_src.as<int32_t>(), V.ff_op.as<int32_t>(), V.hopi.as<int32_t>(), V.hW.as<T>(),
+                V.hwsz, V.hph.as<cx<T>>(), V.hC.as<cx<T>>(), V.hcsz, p, P.nrhs_max, V.M.as<cx<T>>(), V.L.as<cx<T>>());
+        };
+        if (J <= 2) go(k_hf_m2l_w<T, 2>);
+        else if (J <= 3) go(k_hf_m2l_w<T, 3>);
+        else if (J <= 5) go(k_hf_m2l_w<T, 5>);
+        else go(k_hf_m2l_w<T, 7>);
+        FMB_LAUNCH_CHECK();
+        return;
+    }
     const int64_t P2 = (int64_t)p * p;
     const int mode = hf_mode<T>(P2, P2);
     const int ch = mode == 3 ? 3 : 1;
@@ -620,6 +1042,12 @@ template <typename T>
 void hf_l2l(Plan &P, int l, int nrhs, hipStream_t s) {
     Level &V = P.lv[l], &U = P.lv[l - 1];
     const int ps = U.p, pd = V.p;
+    if (std::max(ps, pd) > HF_PIPE_P) {
+        hf_pipe<T>(P, nrhs, s, V.nbox, V.parent.as<int32_t>(), V.octant.as<int32_t>(), 8, V.hoinfo.as<int32_t>(),
+                   V.hWo.as<T>(), V.hwszo, V.hpho.as<cx<T>>(), V.hpwo, V.hCrr.as<cx<T>>(), 0, U, V, V.nbox, nullptr,
+                   1, U.L.as<cx<T>>(), V.L.as<cx<T>>());
+        return;
+    }
     const int64_t S2 = (int64_t)ps * ps, D2 = (int64_t)pd * pd, P2m = std::max(S2, D2);
     const int mode = hf_mode<T>(P2m, D2);
     const int ch = mode == 3 ? 3 : 1;

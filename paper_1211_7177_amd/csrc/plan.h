@@ -56,6 +56,9 @@ struct Level {
     DevBuf hboct;               // i32[16]: polar-angle class of each octant direction
     int64_t hwsz = 0, hwszo = 0, hcsz = 0;
     int hpwo = 0;
+    DevBuf hoinfo;              // i32[16][2]: polar-angle class (and distance class 0) of each octant direction
+    DevBuf hnck, hmck;          // chunk boundaries over the degrees n < p and over |m| < p (pipeline launches)
+    int hnnck = 0, hnmck = 0;
 };
 
 // stage timers (HIP events on the matvec stream), enabled per plan
@@ -96,6 +99,7 @@ struct Plan {
     bool hf = false;
     double tol = 0.0;
     DevBuf hscratch;  // vectors of translation stages too large for LDS
+    DevBuf hX1, hX2;  // per-pair vectors of the pipelined translations (large orders)
     std::vector<Level> lv;
     // per-node data in Morton order
     DevBuf codes;     // u64[n] user order

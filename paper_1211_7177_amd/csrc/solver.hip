@@ -419,7 +419,7 @@ __global__ void k_adj_combine(const cx<T> *__restrict__ x, const double *__restr
 
 
 __global__ void k_rhs_planewave(const double *__restrict__ spts, const int32_t *__restrict__ iperm,
-                                const double *__restrict__ dirs, const double *__restrict__ pols, int64_t n, int nrhs,
+                                const double *__restrict__ dirs, const cx<double> *__restrict__ pols, int64_t n, int nrhs,
                                 double k_re, double k_im, int nu, cx<double> *__restrict__ rhs) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n * nrhs) return;
@@ -430,7 +430,8 @@ __global__ void k_rhs_planewave(const double *__restrict__ spts, const int32_t *
     double s, c;
     sincos(k_re * ph, &s, &c);
     const double e = exp(-k_im * ph);
-    for (int d = 0; d < 3; ++d) rhs[i * nu + d] = mk(pols[3 * q + d] * e * c, pols[3 * q + d] * e * s);
+    const cx<double> w = mk(e * c, e * s);
+    for (int d = 0; d < 3; ++d) rhs[i * nu + d] = pols[3 * q + d] * w;
     for (int d = 3; d < nu; ++d) rhs[i * nu + d] = mk(0.0, 0.0);
 }
 
@@ -2188,12 +2189,12 @@ int bem_rhs_planewave(fmb_problem_t pb, const double *dirs, const double *pols, 
         hipStream_t s = (hipStream_t)stream;
         DevBuf dd, dp;
         dd.alloc(nrhs * 3 * sizeof(double));
-        dp.alloc(nrhs * 3 * sizeof(double));
+        dp.alloc(nrhs * 3 * sizeof(cx<double>));
         FMB_CHECK_HIP(hipMemcpyAsync(dd.p, dirs, nrhs * 3 * sizeof(double), hipMemcpyHostToDevice, s));
-        FMB_CHECK_HIP(hipMemcpyAsync(dp.p, pols, nrhs * 3 * sizeof(double), hipMemcpyHostToDevice, s));
+        FMB_CHECK_HIP(hipMemcpyAsync(dp.p, pols, nrhs * 3 * sizeof(cx<double>), hipMemcpyHostToDevice, s));
         const Plan &A = pb->p0->p;
         k_rhs_planewave<<<gridn(pb->n * nrhs), TPB, 0, s>>>(A.spts.as<double>(), A.iperm.as<int32_t>(), dd.as<double>(),
-                                                            dp.as<double>(), pb->n, nrhs, pb->k0_re, pb->k0_im, pb->nu,
+                                                            dp.as<cx<double>>(), pb->n, nrhs, pb->k0_re, pb->k0_im, pb->nu,
                                                             (cx<double> *)rhs);
         FMB_LAUNCH_CHECK();
         FMB_CHECK_HIP(hipStreamSynchronize(s));

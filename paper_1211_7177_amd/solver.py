@@ -176,7 +176,7 @@ class BemProblem:
 
     def rhs_planewave(self, dirs, pols):
         d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
-        p = np.ascontiguousarray(np.atleast_2d(pols), dtype=np.float64)
+        p = np.ascontiguousarray(np.atleast_2d(pols), dtype=np.complex128)
         nr = d.shape[0]
         out = torch.empty((nr, self.n, self.nu), dtype=torch.complex128, device="cuda")
         check(self._lib.bem_rhs_planewave(self.h, d.ctypes.data, p.ctypes.data, ctypes.c_void_p(out.data_ptr()),
@@ -226,7 +226,7 @@ class IbcProblem(BemProblem):
     nu = 3
 
     def __init__(self, nodes, k0, Z, order=16, depth=0, nrhs_max=1, order32=None, corr="linear", leaf_target=32,
-                 translate32="fp32"):
+                 translate32="fp32", tol=0.0, tol32=0.0):
         lib = _abi.load()
         self._lib = lib
         self.k0 = complex(k0)
@@ -234,12 +234,12 @@ class IbcProblem(BemProblem):
         kw = dict(point_tri=nodes["point_tri"], tri_vertices=nodes["tri_vertices"], nrhs_max=nrhs_max,
                   corr=corr, depth=depth, leaf_target=leaf_target)
         pts, nrm, w = nodes["points"], nodes["normals"], nodes["weights"]
-        self.p0 = Plan(pts, nrm, w, self.k0, order, **kw)
+        self.p0 = Plan(pts, nrm, w, self.k0, order, tol=tol, **kw)
         kw["depth"] = self.p0.info()["depth"]
         self.p1 = self.p1_32 = None
         self.p0_32 = None
-        if order32:
-            self.p0_32 = Plan(pts, nrm, w, self.k0, order32, precision="fp32", translate=translate32, **kw)
+        if order32 is not None:
+            self.p0_32 = Plan(pts, nrm, w, self.k0, order32, precision="fp32", translate=translate32, tol=tol32, **kw)
         self.n = pts.shape[0]
         self.nrhs_max = nrhs_max
         z = np.array([self.Z.real, self.Z.imag])

@@ -53,6 +53,12 @@ def test_bem_apply_precond_rhs_match_oracle(gpu, small):
     p /= np.linalg.norm(p)
     b = pb.rhs_planewave(d, p).cpu().numpy()[0]
     assert _rel(b, ob.rhs_planewave(d, p)) <= 1e-14
+    # circular polarisation: p = (u + i v)/sqrt(2) with u, v orthonormal and normal to d
+    v = np.cross(d, p)
+    pc = (p + 1j * v) / np.sqrt(2.0)
+    bc = pb.rhs_planewave(np.stack([d, d]), np.stack([pc, np.conj(pc)])).cpu().numpy()
+    assert _rel(bc[0], ob.rhs_planewave(d, pc)) <= 1e-14
+    assert _rel(bc[1], ob.rhs_planewave(d, np.conj(pc))) <= 1e-14
     pb.close()
 
 
