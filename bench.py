@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--c5-rows", type=int, default=1024, help="seeded oracle rows of the large-ellipsoid checks")
     ap.add_argument("--c5-solve-s", type=float, default=150.0,
                     help="wall-clock budget (s) of the large-ellipsoid solve (0: skip the solve)")
-    ap.add_argument("--c5-solve-chunk", type=int, default=300,
+    ap.add_argument("--c5-solve-chunk", type=int, default=200,
                     help="Krylov iterations per call of the large-ellipsoid solve (progress line after each)")
     ap.add_argument("--skip-torus", action="store_true", help="skip the 60k-node torus solve comparison")
     ap.add_argument("--torus-steps", type=int, default=3)
@@ -112,11 +112,16 @@ def p2p_pairs(info, n):
     return info["p2p_pairs"] - 3 * n
 
 
+CSRC = os.path.join(ROOT, "paper_1211_7177_amd", "csrc")
+# kernel -> (committed FETCH_SIZE / WRITE_SIZE summary, source file the kernel is built from)
 TRAFFIC_FILES = {
-    "k_translate_bf3 S|R": os.path.join(ROOT, "profiles", "translate_bf3_sr_torus60k_p5_hbm_traffic.md"),
-    "k_p2p32": os.path.join(ROOT, "profiles", "p2p32_torus60k_hbm_traffic.md"),
+    "k_translate_bf3 S|R": (os.path.join(ROOT, "profiles", "translate_bf3_sr_torus60k_p5_hbm_traffic.md"),
+                            os.path.join(CSRC, "matvec.hip")),
+    "k_p2p32": (os.path.join(ROOT, "profiles", "p2p32_torus60k_hbm_traffic.md"), os.path.join(CSRC, "matvec.hip")),
+    "k_p2p32 c5": (os.path.join(ROOT, "profiles", "p2p32_ellipsoid1M_hbm_traffic.md"), os.path.join(CSRC, "matvec.hip")),
+    "k_hf_m2l_w c5": (os.path.join(ROOT, "profiles", "hf_m2l_w_ellipsoid1M_level8_hbm_traffic.md"),
+                      os.path.join(CSRC, "hf.hip")),
 }
-KERNEL_SRC = os.path.join(ROOT, "paper_1211_7177_amd", "csrc", "matvec.hip")
 
 
 def measured_traffic(kernel):
@@ -125,12 +130,13 @@ def measured_traffic(kernel):
     changed since the counters were taken."""
     try:
         meta = {}
-        with open(TRAFFIC_FILES[kernel]) as f:
+        summary, src = TRAFFIC_FILES[kernel]
+        with open(summary) as f:
             for line in f:
                 if ":" in line and line.startswith("    "):
                     k, v = line.strip().split(":", 1)
                     meta[k.strip()] = v.strip()
-        with open(KERNEL_SRC, "rb") as f:
+        with open(src, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
         if meta.get("kernel") != kernel or meta.get("source_sha256") != sha:
             return None
@@ -492,12 +498,6 @@ def torus_section(args, log):
     stages_rf["p2p"]["traffic"] = measured_traffic("k_p2p32")
     dominant = "p2p" if p2p_ms >= tr_ms else "translate"
     roofline = dict(stages_rf[dominant])
-    if args.copy_calibration:
-        buf = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).uniform_()
-        torch.cuda.synchronize()
-        buf2 = buf.clone()
-        torch.cuda.synchronize()
-        log("copy calibration: 256 MiB device-to-device copy done", buf2.numel())
     log("roofline", stages_rf)
 
     ring = split_ring_section(log) if args.split_ring else None
@@ -713,26 +713,34 @@ def c5_workload(args, log):
     inf = infos["k0_fp32"]
     p2p_pairs = inf["p2p_pairs"] - 3 * n
     p2p_fl = P2P_FLOPS_PER_PAIR * p2p_pairs
-    m2l_fl = sum(inf["m2l_pairs"][l] * hf_translation_flops(inf["order_level"][l]) for l in range(len(inf["m2l_pairs"])))
+    L = cfg["depth"]
+    pl = inf["order_level"]
+    m2l_fl = sum(inf["m2l_pairs"][l] * hf_translation_flops(pl[l]) for l in range(len(inf["m2l_pairs"])) if pl[l])
+    fine_fl = inf["m2l_pairs"][L] * hf_translation_flops(pl[L])
     st = prof["fp32"]
-    p2p_ms, m2l_ms = st["p2p"][0], st["m2l"][0]
-    m2l_launches = max(1, st["m2l"][1])
+    p2p_ms, m2l_ms, fine_ms = st["p2p"][0], st["m2l"][0], st["m2l_fine"][0]
     stages_rf = {
         "p2p": {"kernel": "k_p2p32 (near field, FP32 VALU)", "bound": "alu", "peak": PEAK["fp32_TF"],
                 "unit": "TFLOP/s", "achieved": p2p_fl / (p2p_ms * 1e-3) / 1e12, "per_launch_flops": p2p_fl,
-                "avg_launch_ms": p2p_ms, "launches_per_product": 1, "traffic": measured_traffic("k_p2p32 c5"),
+                "flops_per_unit": P2P_FLOPS_PER_PAIR, "unit_of_work": "(target, source) pair",
+                "units_per_launch": p2p_pairs, "avg_launch_ms": p2p_ms, "launches_per_product": 1,
+                "traffic": measured_traffic("k_p2p32 c5"),
                 "gpairs_per_s": p2p_pairs / (p2p_ms * 1e-3) / 1e9},
-        "m2l": {"kernel": "k_hf_m2l (rotation / coaxial-shift S|R, FP32 VALU, one launch per level)",
-                "bound": "alu", "peak": PEAK["fp32_TF"], "unit": "TFLOP/s",
-                "achieved": m2l_fl / (m2l_ms * 1e-3) / 1e12, "per_launch_flops": m2l_fl / m2l_launches,
-                "avg_launch_ms": m2l_ms / m2l_launches, "launches_per_product": m2l_launches,
-                "traffic": measured_traffic("k_hf_m2l c5"),
-                "pairs_per_level": inf["m2l_pairs"], "order_per_level": inf["order_level"]},
+        "m2l_fine": {"kernel": "k_hf_m2l_w (finest-level S|R by rotation / coaxial shift / rotation, FP32 VALU)",
+                     "bound": "alu", "peak": PEAK["fp32_TF"], "unit": "TFLOP/s",
+                     "achieved": fine_fl / (fine_ms * 1e-3) / 1e12, "per_launch_flops": fine_fl,
+                     "flops_per_unit": hf_translation_flops(pl[L]), "unit_of_work": "S|R translation (3 channels)",
+                     "units_per_launch": inf["m2l_pairs"][L], "order": pl[L], "avg_launch_ms": fine_ms,
+                     "launches_per_product": 1, "traffic": measured_traffic("k_hf_m2l_w c5")},
+        "m2l_all_levels": {"kernels": "k_hf_fwd / k_hf_coax / k_hf_back (orders > 20), k_hf_m2l_w (orders <= 20)",
+                           "bound": "alu", "peak": PEAK["fp32_TF"], "unit": "TFLOP/s",
+                           "achieved": m2l_fl / (m2l_ms * 1e-3) / 1e12, "flops_per_product": m2l_fl,
+                           "ms_per_product": m2l_ms, "pairs_per_level": inf["m2l_pairs"], "order_per_level": pl},
     }
     for v in stages_rf.values():
         v["frac"] = v["achieved"] / v["peak"]
-    dominant = "m2l" if m2l_ms >= p2p_ms else "p2p"
-    roofline = dict(stages_rf[dominant])
+    dominant = "m2l_fine" if fine_ms >= p2p_ms else "p2p"
+    roofline = {k: v for k, v in stages_rf[dominant].items()}
     log("c5 roofline", stages_rf)
 
     # the 18.1M-unknown system for a seeded plane wave, in nested mode (FP64 fGMRES preconditioned by FP32
@@ -875,6 +883,14 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(torch.device("cuda:0"))
+    if args.copy_calibration:
+        # a device-to-device copy of known size, for scaling the HBM byte counters of a profiled run
+        buf = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").uniform_()
+        torch.cuda.synchronize()
+        buf2 = buf.clone()
+        torch.cuda.synchronize()
+        log("copy calibration: 256 MiB device-to-device copy done", buf2.numel())
+        del buf, buf2
     c5 = c5_workload(args, log)
     torus = None if args.skip_torus else torus_section(args, log)
     out = {

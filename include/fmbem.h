@@ -186,15 +186,17 @@ int fmm_plan_destroy(fmb_plan_t plan);
  * fmm_plan_profile_read synchronises on them and returns, per stage, the
  * summed time in milliseconds and the number of kernel launches timed since
  * the last read with reset = 1 (the S|R launches of all levels run back to
- * back and share one pair of events).  Stage order (FMB_NSTAGES = 10): gather, P2M,
+ * back and share one pair of events).  Stage order (FMB_NSTAGES = 11): gather, P2M,
  * M2M (S|S translation kernel), M2L (S|R translation kernel), L2L (R|R), L2P,
  * P2P, corrections (with the return to user order, plans with corrections),
  * scatter (the return to user order, plans without corrections), sums (the
- * per-target sums of the S|S and S|R translation slots).  ms and launches: host arrays of FMB_NSTAGES entries
- * (either may be NULL).
+ * per-target sums of the S|S and S|R translation slots), and the finest level's
+ * S|R launch alone (plans with an order per level; its launch is also counted
+ * in M2L).  ms and launches: host arrays of FMB_NSTAGES entries (either may be
+ * NULL).
  */
-#define FMB_NSTAGES 10
-#define FMB_PROFILE_ALL 0x3ff
+#define FMB_NSTAGES 11
+#define FMB_PROFILE_ALL 0x7ff
 int fmm_plan_profile(fmb_plan_t plan, int32_t mask);
 int fmm_plan_profile_read(fmb_plan_t plan, double *ms, int64_t *launches, int32_t reset);
 
@@ -203,7 +205,8 @@ int fmm_plan_profile_read(fmb_plan_t plan, double *ms, int64_t *launches, int32_
 typedef struct {
     double tol;          /* stop when |b - A x| <= tol |b| (relative, 2-norm)               */
     int32_t restart;     /* Krylov basis size m                                              */
-    int32_t maxit;       /* total iteration cap                                              */
+    int32_t maxit;       /* total iteration cap (nested mode: outer plus inner steps, checked */
+                         /*    between outer steps, so one inner cycle may run past it)      */
     int32_t precond;     /* 0 none, 1 block A_self (6x6 per node)                            */
     int32_t x0_given;    /* 1: x holds the initial guess on entry                            */
     int32_t mixed;       /* 1: FP32 inner solves refined by FP64 residuals (needs FP32 plans);*/

@@ -236,7 +236,7 @@ class Plan:
         return {"codes": codes, "perm": perm, "keys": keys, "parent": parent, "start": start, "nbr": nbr,
                 "ff_ofs": ff_ofs, "ff_idx": ff_idx[:int(ff_ofs[-1])]}
 
-    STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "corr", "scatter", "sums")
+    STAGES = ("gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "corr", "scatter", "sums", "m2l_fine")
 
     def profile(self, enable=True, stages=None):
         """Time stages with HIP events on later matvecs: all of them, or only

@@ -463,13 +463,16 @@ __device__ inline int64_t hf_coff(int am, int pd, int ps) {
 }
 
 // X1[e][r][c][(n,m')] = sum_m W[n][m][m'] e^{i m phi} S[src][r][c][(n,m)], degrees [nck[z], nck[z+1]);
-// one thread per coefficient, all three channels (one rotation-table read serves three)
+// the source's coefficients of those degrees, times the phases, are staged in LDS first; then one
+// thread per coefficient, all three channels (one rotation-table read serves three)
 template <typename T>
 __global__ void __launch_bounds__(HTPB) k_hf_fwd(const int32_t *__restrict__ src_idx, const int32_t *__restrict__ dir,
                                                  int dir_add, const int32_t *__restrict__ dinfo,
                                                  const T *__restrict__ W, int64_t wsz, const cx<T> *__restrict__ ph,
                                                  int phs, const int32_t *__restrict__ nck, int ps, int nrhs_max,
                                                  int nrhs, const cx<T> *__restrict__ S, cx<T> *__restrict__ X1) {
+    extern __shared__ __align__(16) unsigned char hf_smem[];
+    cx<T> *xs = reinterpret_cast<cx<T> *>(hf_smem);
     const int e = blockIdx.x, r = blockIdx.y, z = blockIdx.z;
     const int n0 = nck[z], n1 = nck[z + 1];
     const int d = dir[e] + dir_add;
@@ -478,20 +481,29 @@ __global__ void __launch_bounds__(HTPB) k_hf_fwd(const int32_t *__restrict__ src
     const int64_t src = src_idx ? src_idx[e] : e;
     const int64_t P2 = (int64_t)ps * ps;
     const int base = n0 * n0, cnt = n1 * n1 - base;
-    const cx<T> *S0 = S + (src * nrhs_max + r) * 3 * P2;
+    const cx<T> *S0 = S + (src * nrhs_max + r) * 3 * P2 + base;
+    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+        int n, m;
+        hf_nm(base + t, n, m);
+        const cx<T> f = hf_phase(phd, m);
+        xs[t] = f * S0[t];
+        xs[cnt + t] = f * S0[P2 + t];
+        xs[2 * cnt + t] = f * S0[2 * P2 + t];
+    }
+    __syncthreads();
     cx<T> *X0 = X1 + ((int64_t)e * nrhs + r) * 3 * P2;
     for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
         const int ee = base + t;
         int n, mp;
         hf_nm(ee, n, mp);
         const T *w = Wb + hf_woff(n) + (mp + n);
-        const cx<T> *x = S0 + n * n;
+        const cx<T> *x = xs + (n * n - base);
         cx<T> a0 = mk(T(0), T(0)), a1 = a0, a2 = a0;
         for (int m = 0; m <= 2 * n; ++m) {
-            const cx<T> g = w[(int64_t)m * (2 * n + 1)] * hf_phase(phd, m - n);
-            a0 += g * x[m];
-            a1 += g * x[P2 + m];
-            a2 += g * x[2 * P2 + m];
+            const T wm = w[(int64_t)m * (2 * n + 1)];
+            a0 += wm * x[m];
+            a1 += wm * x[cnt + m];
+            a2 += wm * x[2 * cnt + m];
         }
         X0[ee] = a0;
         X0[P2 + ee] = a1;
@@ -500,33 +512,51 @@ __global__ void __launch_bounds__(HTPB) k_hf_fwd(const int32_t *__restrict__ src
 }
 
 // X2[e][r][c][(q,m)] = sum_n C^|m|_{q n} X1[e][r][c][(n,m)], |m| in [mck[z], mck[z+1]), q < pd;
-// consecutive threads take consecutive q (adjacent table entries), all three channels
+// the inputs of those |m| are staged in LDS (item order (|m|, sign, n)); consecutive threads take
+// consecutive q (adjacent table entries), all three channels
 template <typename T>
 __global__ void __launch_bounds__(HTPB) k_hf_coax(const int32_t *__restrict__ dir, int dir_add,
                                                   const int32_t *__restrict__ dinfo, const cx<T> *__restrict__ C,
                                                   int64_t csz, const int32_t *__restrict__ mck, int ps, int pd,
                                                   int nrhs, const cx<T> *__restrict__ X1, cx<T> *__restrict__ X2) {
+    extern __shared__ __align__(16) unsigned char hf_smem[];
+    cx<T> *xs = reinterpret_cast<cx<T> *>(hf_smem);
     const int e = blockIdx.x, r = blockIdx.y, z = blockIdx.z;
     const int m0 = mck[z], m1 = mck[z + 1];
     const int d = dir[e] + dir_add;
     const cx<T> *Cd = C + (int64_t)dinfo[2 * d + 1] * csz;
     const int64_t S2 = (int64_t)ps * ps, D2 = (int64_t)pd * pd;
-    int cnt = 0;
+    const int m1s = m1 < ps ? m1 : ps;
+    int cin = 0, cnt = 0;
     for (int am = m0; am < m1; ++am) cnt += (pd - am) * (am ? 2 : 1);
+    for (int am = m0; am < m1s; ++am) cin += (ps - am) * (am ? 2 : 1);
     const cx<T> *x = X1 + ((int64_t)e * nrhs + r) * 3 * S2;
+    for (int t = threadIdx.x; t < cin; t += blockDim.x) {
+        int am, m, n;
+        hf_coax_item(t, m0, ps, am, m, n);
+        const int i = n * n + n + m;
+        xs[t] = x[i];
+        xs[cin + t] = x[S2 + i];
+        xs[2 * cin + t] = x[2 * S2 + i];
+    }
+    __syncthreads();
     cx<T> *y = X2 + ((int64_t)e * nrhs + r) * 3 * D2;
     for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
         int am, m, q;
         hf_coax_item(t, m0, pd, am, m, q);
         cx<T> a0 = mk(T(0), T(0)), a1 = a0, a2 = a0;
         if (am < ps) {
+            // this |m|'s staged inputs: items of the blocks before it, then the sign
+            int at = 0;
+            for (int j = m0; j < am; ++j) at += (ps - j) * (j ? 2 : 1);
+            if (m < 0) at += ps - am;
             const cx<T> *col = Cd + hf_coff(am, pd, ps) + (q - am);
+            const cx<T> *xi = xs + at;
             for (int n = am; n < ps; ++n) {
                 const cx<T> cv = col[(int64_t)(n - am) * (pd - am)];
-                const int i = n * n + n + m;
-                a0 += cv * x[i];
-                a1 += cv * x[S2 + i];
-                a2 += cv * x[2 * S2 + i];
+                a0 += cv * xi[n - am];
+                a1 += cv * xi[cin + n - am];
+                a2 += cv * xi[2 * cin + n - am];
             }
         }
         const int o = q * q + q + m;
@@ -538,7 +568,8 @@ __global__ void __launch_bounds__(HTPB) k_hf_coax(const int32_t *__restrict__ di
 
 // D[b][r][c][(n,m')] (=, or += with accumulate) sum over b's pairs e of
 // e^{-i m' phi_e} sum_m W_e[n][m'][m] X2[e][r][c][(n,m)], degrees [nck[z], nck[z+1]);
-// W[n][m'][m] = (-1)^(m-m') W[n][m][m'] (Wigner's d^n_{m m'} = (-1)^(m-m') d^n_{m' m}) is read along m'
+// W[n][m'][m] = (-1)^(m-m') W[n][m][m'] (Wigner's d^n_{m m'} = (-1)^(m-m') d^n_{m' m}) is read along m';
+// each pair's inputs of those degrees are staged in LDS
 template <typename T>
 __global__ void __launch_bounds__(HTPB) k_hf_back(const int32_t *__restrict__ dst_ofs, const int32_t *__restrict__ dir,
                                                   int dir_add, const int32_t *__restrict__ dinfo,
@@ -546,44 +577,65 @@ __global__ void __launch_bounds__(HTPB) k_hf_back(const int32_t *__restrict__ ds
                                                   int phs, const int32_t *__restrict__ nck, int pd, int nrhs_max,
                                                   int nrhs, int accumulate, const cx<T> *__restrict__ X2,
                                                   cx<T> *__restrict__ D) {
+    extern __shared__ __align__(16) unsigned char hf_smem[];
+    cx<T> *xs = reinterpret_cast<cx<T> *>(hf_smem);
     const int b = blockIdx.x, r = blockIdx.y, z = blockIdx.z;
     const int n0 = nck[z], n1 = nck[z + 1];
     const int e0 = dst_ofs ? dst_ofs[b] : b, e1 = dst_ofs ? dst_ofs[b + 1] : b + 1;
     const int64_t D2 = (int64_t)pd * pd;
     const int base = n0 * n0, cnt = n1 * n1 - base;
     cx<T> *out = D + ((int64_t)b * nrhs_max + r) * 3 * D2;
-    for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
-        const int ee = base + t;
-        int n, mp;
-        hf_nm(ee, n, mp);
-        cx<T> a0, a1, a2;
-        if (accumulate) {
-            a0 = out[ee];
-            a1 = out[D2 + ee];
-            a2 = out[2 * D2 + ee];
-        } else {
-            a0 = a1 = a2 = mk(T(0), T(0));
+    // each thread owns coefficients t = threadIdx.x + HTPB i; at most 4 per thread (chunks hold < 4 HTPB)
+    cx<T> acc[4][3];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int t = threadIdx.x + HTPB * i;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            acc[i][c] = (accumulate && t < cnt) ? out[c * D2 + base + t] : mk(T(0), T(0));
+    }
+    for (int e = e0; e < e1; ++e) {
+        const int d = dir[e] + dir_add;
+        const cx<T> *x = X2 + ((int64_t)e * nrhs + r) * 3 * D2 + base;
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            xs[t] = x[t];
+            xs[cnt + t] = x[D2 + t];
+            xs[2 * cnt + t] = x[2 * D2 + t];
         }
-        for (int e = e0; e < e1; ++e) {
-            const int d = dir[e] + dir_add;
-            const T *w = W + (int64_t)dinfo[2 * d] * wsz + hf_woff(n) + (mp + n);
-            const cx<T> *x = X2 + ((int64_t)e * nrhs + r) * 3 * D2 + n * n;
-            cx<T> s0 = mk(T(0), T(0)), s1 = s0, s2 = s0;
-            for (int m = 0; m <= 2 * n; ++m) {
-                const T wm0 = w[(int64_t)m * (2 * n + 1)];
-                const T wm = ((m + mp + n) & 1) ? -wm0 : wm0;
-                s0 += wm * x[m];
-                s1 += wm * x[D2 + m];
-                s2 += wm * x[2 * D2 + m];
+        __syncthreads();
+        const T *Wd = W + (int64_t)dinfo[2 * d] * wsz;
+        const cx<T> *phd = ph + (int64_t)d * phs;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int t = threadIdx.x + HTPB * i;
+            if (t < cnt) {
+                int n, mp;
+                hf_nm(base + t, n, mp);
+                const T *w = Wd + hf_woff(n) + (mp + n);
+                const cx<T> *xi = xs + (n * n - base);
+                cx<T> s0 = mk(T(0), T(0)), s1 = s0, s2 = s0;
+                for (int m = 0; m <= 2 * n; ++m) {
+                    const T wm0 = w[(int64_t)m * (2 * n + 1)];
+                    const T wm = ((m + mp + n) & 1) ? -wm0 : wm0;
+                    s0 += wm * xi[m];
+                    s1 += wm * xi[cnt + m];
+                    s2 += wm * xi[2 * cnt + m];
+                }
+                const cx<T> f = hf_phase(phd, -mp);
+                acc[i][0] += f * s0;
+                acc[i][1] += f * s1;
+                acc[i][2] += f * s2;
             }
-            const cx<T> f = hf_phase(ph + (int64_t)d * phs, -mp);
-            a0 += f * s0;
-            a1 += f * s1;
-            a2 += f * s2;
         }
-        out[ee] = a0;
-        out[D2 + ee] = a1;
-        out[2 * D2 + ee] = a2;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int t = threadIdx.x + HTPB * i;
+        if (t < cnt) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) out[c * D2 + base + t] = acc[i][c];
+        }
     }
 }
 
@@ -607,6 +659,7 @@ __global__ void __launch_bounds__(256) k_hf_m2l_w(const int32_t *__restrict__ ff
     const int b = blockIdx.x, r = blockIdx.y;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int P2 = p * p, N3 = 3 * P2;
+    // per wavefront two vectors of p^2 coefficients x 3 channels, channel-interleaved ([coefficient][3])
     cx<T> *A = reinterpret_cast<cx<T> *>(hf_smem) + (size_t)wv * 2 * N3;
     cx<T> *B = A + N3;
     // tab: (n, m + n) of coefficient t; tab2: (q, m + q) of the t-th coaxial item, ordered (|m|, sign, q)
@@ -641,9 +694,9 @@ __global__ void __launch_bounds__(256) k_hf_m2l_w(const int32_t *__restrict__ ff
             for (int t = lane; t < P2; t += 64) {
                 const int v = tab[t], n = v >> 10, m = (v & 1023) - n;
                 const cx<T> f = hf_phase(pho, m);
-                A[t] = f * src[t];
-                A[P2 + t] = f * src[P2 + t];
-                A[2 * P2 + t] = f * src[2 * P2 + t];
+                A[3 * t] = f * src[t];
+                A[3 * t + 1] = f * src[P2 + t];
+                A[3 * t + 2] = f * src[2 * P2 + t];
             }
         }
         __syncthreads();
@@ -651,18 +704,20 @@ __global__ void __launch_bounds__(256) k_hf_m2l_w(const int32_t *__restrict__ ff
             // rotation onto +z: B_n^m' = sum_m W[n][m][m'] A_n^m
             for (int t = lane; t < P2; t += 64) {
                 const int v = tab[t], n = v >> 10, mpn = v & 1023;
+                const int st = 2 * n + 1;
                 const T *w = Wb + hf_woff(n) + mpn;
-                const cx<T> *x = A + n * n;
+                const cx<T> *x = A + 3 * n * n;
                 cx<T> s0 = mk(T(0), T(0)), s1 = s0, s2 = s0;
-                for (int m = 0; m <= 2 * n; ++m) {
-                    const T wm = w[(int64_t)m * (2 * n + 1)];
-                    s0 += wm * x[m];
-                    s1 += wm * x[P2 + m];
-                    s2 += wm * x[2 * P2 + m];
+#pragma unroll 4
+                for (int m = 0; m < st; ++m) {
+                    const T wm = w[m * st];
+                    s0 += wm * x[3 * m];
+                    s1 += wm * x[3 * m + 1];
+                    s2 += wm * x[3 * m + 2];
                 }
-                B[t] = s0;
-                B[P2 + t] = s1;
-                B[2 * P2 + t] = s2;
+                B[3 * t] = s0;
+                B[3 * t + 1] = s1;
+                B[3 * t + 2] = s2;
             }
         }
         __syncthreads();
@@ -671,44 +726,63 @@ __global__ void __launch_bounds__(256) k_hf_m2l_w(const int32_t *__restrict__ ff
             for (int t = lane; t < P2; t += 64) {
                 const int v = tab2[t], q = v >> 10, m = (v & 1023) - q;
                 const int am = m < 0 ? -m : m;
+                const int cs = p - am;
                 const cx<T> *col = Cd + hf_coff(am, p, p) + (q - am);
+                const cx<T> *x = B + 3 * (am * am + am + m);
                 cx<T> s0 = mk(T(0), T(0)), s1 = s0, s2 = s0;
+                // input n sits at 3 (n^2 + n + m); successive n are 3 (2n + 2) entries apart
+                int off = 0;
+#pragma unroll 2
                 for (int n = am; n < p; ++n) {
-                    const cx<T> cv = col[(int64_t)(n - am) * (p - am)];
-                    const int i = n * n + n + m;
-                    s0 += cv * B[i];
-                    s1 += cv * B[P2 + i];
-                    s2 += cv * B[2 * P2 + i];
+                    const cx<T> cv = col[(n - am) * cs];
+                    s0 += cv * x[off];
+                    s1 += cv * x[off + 1];
+                    s2 += cv * x[off + 2];
+                    off += 6 * n + 6;
                 }
-                const int oi = q * q + q + m;
-                A[oi] = s0;
-                A[P2 + oi] = s1;
-                A[2 * P2 + oi] = s2;
+                A[3 * (q * q + q + m)] = s0;
+                A[3 * (q * q + q + m) + 1] = s1;
+                A[3 * (q * q + q + m) + 2] = s2;
             }
         }
         __syncthreads();
         if (act) {
-            // rotation back (W[n][m'][m] = (-1)^(m-m') W[n][m][m'], read along m') and e^{-i m' phi},
-            // added to this lane's coefficients
+            // rotation back, d_n^m' = e^{-i m' phi} sum_m W[n][m'][m] c_n^m with W[n][m'][m] =
+            // (-1)^(m-m') W[n][m][m'] read along m': the even-m and odd-m terms are summed apart and
+            // combined with their signs at the end; added to this lane's coefficients
 #pragma unroll
             for (int j = 0; j < J; ++j) {
                 const int t = lane + 64 * j;
                 if (t < P2) {
                     const int v = tab[t], n = v >> 10, mpn = v & 1023;
+                    const int st = 2 * n + 1;
                     const T *w = Wb + hf_woff(n) + mpn;
-                    const cx<T> *x = A + n * n;
-                    cx<T> s0 = mk(T(0), T(0)), s1 = s0, s2 = s0;
-                    for (int m = 0; m <= 2 * n; ++m) {
-                        const T wm0 = w[(int64_t)m * (2 * n + 1)];
-                        const T wm = ((m + mpn) & 1) ? -wm0 : wm0;
-                        s0 += wm * x[m];
-                        s1 += wm * x[P2 + m];
-                        s2 += wm * x[2 * P2 + m];
+                    const cx<T> *x = A + 3 * n * n;
+                    cx<T> e0_ = mk(T(0), T(0)), e1_ = e0_, e2_ = e0_, o0 = e0_, o1 = e0_, o2 = e0_;
+                    int m = 0;
+#pragma unroll 2
+                    for (; m + 1 < st; m += 2) {
+                        const T we = w[m * st], wo = w[(m + 1) * st];
+                        e0_ += we * x[3 * m];
+                        e1_ += we * x[3 * m + 1];
+                        e2_ += we * x[3 * m + 2];
+                        o0 += wo * x[3 * m + 3];
+                        o1 += wo * x[3 * m + 4];
+                        o2 += wo * x[3 * m + 5];
                     }
+                    {
+                        const T we = w[m * st];           // m = 2n, even
+                        e0_ += we * x[3 * m];
+                        e1_ += we * x[3 * m + 1];
+                        e2_ += we * x[3 * m + 2];
+                    }
+                    // (-1)^(m - m') = (-1)^(m + mpn) for m the index 0..2n
+                    const T sg = (mpn & 1) ? T(-1) : T(1);
                     const cx<T> f = hf_phase(pho, n - mpn);
-                    acc[3 * j] += f * s0;
-                    acc[3 * j + 1] += f * s1;
-                    acc[3 * j + 2] += f * s2;
+                    const cx<T> fs = sg * f;
+                    acc[3 * j] += fs * (e0_ - o0);
+                    acc[3 * j + 1] += fs * (e1_ - o1);
+                    acc[3 * j + 2] += fs * (e2_ - o2);
                 }
             }
         }
@@ -719,17 +793,18 @@ __global__ void __launch_bounds__(256) k_hf_m2l_w(const int32_t *__restrict__ ff
     for (int j = 0; j < J; ++j) {
         const int t = lane + 64 * j;
         if (t < P2) {
-            A[t] = acc[3 * j];
-            A[P2 + t] = acc[3 * j + 1];
-            A[2 * P2 + t] = acc[3 * j + 2];
+            A[3 * t] = acc[3 * j];
+            A[3 * t + 1] = acc[3 * j + 1];
+            A[3 * t + 2] = acc[3 * j + 2];
         }
     }
     __syncthreads();
     cx<T> *out = Lout + ((int64_t)b * nrhs_max + r) * 3 * P2;
     const cx<T> *base0 = reinterpret_cast<cx<T> *>(hf_smem);
     for (int t = threadIdx.x; t < N3; t += blockDim.x) {
-        cx<T> v = base0[t];
-        for (int w = 1; w < HFW_WAVES; ++w) v += base0[(size_t)w * 2 * N3 + t];
+        const int c = t / P2, i = t - c * P2;
+        cx<T> v = base0[3 * i + c];
+        for (int w = 1; w < HFW_WAVES; ++w) v += base0[(size_t)w * 2 * N3 + 3 * i + c];
         out[t] = v;
     }
 }
@@ -753,32 +828,53 @@ int hf_order(double kabs, double side, double tol) {
 // translation sets whose order exceeds this run as the three-launch pipeline;
 // M2L at orders up to HFW_PMAX runs one source per wavefront
 constexpr int HF_PIPE_P = 20;
-// (and needs at most 80 KB of LDS per block, so that two blocks share a CU)
+// (its LDS, up to 157 KB per block for FP64 at order 20, fits the CU's 160 KB)
 constexpr int HFW_PMAX = 20;
-constexpr size_t HFW_LDS_MAX = 80 * 1024;
+constexpr size_t HFW_LDS_MAX = 160 * 1024;
 
-// chunk boundaries: degrees n < p with about 256 coefficients per chunk, and
-// |m| < p with about 256 outputs per chunk
-static std::vector<int32_t> degree_chunks(int p) {
+// chunk boundaries of the pipelined launches (one block per pair and chunk): about
+// 256 coefficients per chunk and never more than HF_CHUNK_MAX, which is what the
+// kernels' LDS staging and per-thread registers hold.  Degrees n < p:
+constexpr int HF_CHUNK_MAX = 4 * HTPB;
+
+static std::vector<int32_t> degree_chunks(int p, int &maxc) {
     std::vector<int32_t> v{0};
     int acc = 0;
+    maxc = 0;
     for (int n = 0; n < p; ++n) {
-        acc += 2 * n + 1;
+        const int w = 2 * n + 1;
+        if (acc > 0 && acc + w > HF_CHUNK_MAX) {
+            v.push_back(n);
+            maxc = std::max(maxc, acc);
+            acc = 0;
+        }
+        acc += w;
         if (acc >= 256 || n == p - 1) {
             v.push_back(n + 1);
+            maxc = std::max(maxc, acc);
             acc = 0;
         }
     }
     return v;
 }
 
-static std::vector<int32_t> m_chunks(int p) {
+// |m| < pd for a coaxial shift from order ps to order pd: a block |m| holds
+// (pd - |m|) outputs and (ps - |m|) inputs per sign, and both counts stay within a chunk
+static std::vector<int32_t> m_chunks(int pd, int ps, int &maxc) {
     std::vector<int32_t> v{0};
     int acc = 0;
-    for (int am = 0; am < p; ++am) {
-        acc += (p - am) * (am ? 2 : 1);
-        if (acc >= 256 || am == p - 1) {
+    maxc = 0;
+    for (int am = 0; am < pd; ++am) {
+        const int w = std::max(pd - am, std::max(ps - am, 0)) * (am ? 2 : 1);
+        if (acc > 0 && acc + w > HF_CHUNK_MAX) {
+            v.push_back(am);
+            maxc = std::max(maxc, acc);
+            acc = 0;
+        }
+        acc += w;
+        if (acc >= 256 || am == pd - 1) {
             v.push_back(am + 1);
+            maxc = std::max(maxc, acc);
             acc = 0;
         }
     }
@@ -876,11 +972,16 @@ void build_hf(Plan &P, hipStream_t s) {
             std::vector<double> oi(32, 0.0);
             for (int q = 0; q < 16; ++q) oi[2 * q] = boct[q];
             upload_as<int32_t>(V.hoinfo, oi, s);
-            const std::vector<int32_t> nc = degree_chunks(p), mc = m_chunks(p);
+            const std::vector<int32_t> nc = degree_chunks(p, V.hnck_max), mc = m_chunks(p, p, V.hmck_max),
+                                       mss = m_chunks(p, pu, V.hmck_ss_max), mrr = m_chunks(p, pdn, V.hmck_rr_max);
             V.hnnck = (int)nc.size() - 1;
             V.hnmck = (int)mc.size() - 1;
+            V.hnmck_ss = (int)mss.size() - 1;
+            V.hnmck_rr = (int)mrr.size() - 1;
             upload_as<int32_t>(V.hnck, std::vector<double>(nc.begin(), nc.end()), s);
             upload_as<int32_t>(V.hmck, std::vector<double>(mc.begin(), mc.end()), s);
+            upload_as<int32_t>(V.hmck_ss, std::vector<double>(mss.begin(), mss.end()), s);
+            upload_as<int32_t>(V.hmck_rr, std::vector<double>(mrr.begin(), mrr.end()), s);
         }
         if (f64) {
             upload_as<double>(V.hW, Wt, s);
@@ -943,23 +1044,29 @@ void build_hf(Plan &P, hipStream_t s) {
 // ------------------------------------------------------------ launches
 
 // three-launch translation set: npairs pairs (source box src_idx[e] or e, direction dir[e] + dir_add)
-// into ndst destinations (pairs of b: dst_ofs[b] .. dst_ofs[b+1], or e = b)
+// into ndst destinations (pairs of b: dst_ofs[b] .. dst_ofs[b+1], or e = b); mck / nmck / mck_max: the
+// |m| chunks of this coaxial shift
 template <typename T>
 void hf_pipe(Plan &P, int nrhs, hipStream_t s, int64_t npairs, const int32_t *src_idx, const int32_t *dir,
              int dir_add, const int32_t *dinfo, const T *W, int64_t wsz, const cx<T> *ph, int phs, const cx<T> *C,
-             int64_t csz, const Level &Vs, const Level &Vd, int64_t ndst, const int32_t *dst_ofs, int accumulate,
-             const cx<T> *S, cx<T> *D) {
+             int64_t csz, const Level &Vs, const Level &Vd, const DevBuf &mck, int nmck, int mck_max, int64_t ndst,
+             const int32_t *dst_ofs, int accumulate, const cx<T> *S, cx<T> *D) {
     if (npairs == 0 || ndst == 0) return;
     const int ps = Vs.p, pd = Vd.p;
+    if (Vs.hnck_max > HF_CHUNK_MAX || Vd.hnck_max > HF_CHUNK_MAX || mck_max > HF_CHUNK_MAX)
+        throw Status{FMB_EINVAL, "translation chunk larger than the kernels hold"};
     cx<T> *X1 = P.hX1.as<cx<T>>(), *X2 = P.hX2.as<cx<T>>();
-    k_hf_fwd<T><<<dim3((unsigned)npairs, (unsigned)nrhs, (unsigned)Vs.hnnck), HTPB, 0, s>>>(
-        src_idx, dir, dir_add, dinfo, W, wsz, ph, phs, Vs.hnck.as<int32_t>(), ps, P.nrhs_max, nrhs, S, X1);
+    k_hf_fwd<T><<<dim3((unsigned)npairs, (unsigned)nrhs, (unsigned)Vs.hnnck), HTPB,
+                  3 * (size_t)Vs.hnck_max * sizeof(cx<T>), s>>>(src_idx, dir, dir_add, dinfo, W, wsz, ph, phs,
+                                                                Vs.hnck.as<int32_t>(), ps, P.nrhs_max, nrhs, S, X1);
     FMB_LAUNCH_CHECK();
-    k_hf_coax<T><<<dim3((unsigned)npairs, (unsigned)nrhs, (unsigned)Vd.hnmck), HTPB, 0, s>>>(
-        dir, dir_add, dinfo, C, csz, Vd.hmck.as<int32_t>(), ps, pd, nrhs, X1, X2);
+    k_hf_coax<T><<<dim3((unsigned)npairs, (unsigned)nrhs, (unsigned)nmck), HTPB, 3 * (size_t)mck_max * sizeof(cx<T>),
+                   s>>>(dir, dir_add, dinfo, C, csz, mck.as<int32_t>(), ps, pd, nrhs, X1, X2);
     FMB_LAUNCH_CHECK();
-    k_hf_back<T><<<dim3((unsigned)ndst, (unsigned)nrhs, (unsigned)Vd.hnnck), HTPB, 0, s>>>(
-        dst_ofs, dir, dir_add, dinfo, W, wsz, ph, phs, Vd.hnck.as<int32_t>(), pd, P.nrhs_max, nrhs, accumulate, X2, D);
+    k_hf_back<T><<<dim3((unsigned)ndst, (unsigned)nrhs, (unsigned)Vd.hnnck), HTPB,
+                   3 * (size_t)Vd.hnck_max * sizeof(cx<T>), s>>>(dst_ofs, dir, dir_add, dinfo, W, wsz, ph, phs,
+                                                                 Vd.hnck.as<int32_t>(), pd, P.nrhs_max, nrhs,
+                                                                 accumulate, X2, D);
     FMB_LAUNCH_CHECK();
 }
 
@@ -969,8 +1076,8 @@ void hf_m2m(Plan &P, int l, int nrhs, hipStream_t s) {
     const int ps = Cv.p, pd = V.p;
     if (std::max(ps, pd) > HF_PIPE_P) {
         hf_pipe<T>(P, nrhs, s, Cv.nbox, nullptr, Cv.octant.as<int32_t>(), 0, V.hoinfo.as<int32_t>(), V.hWo.as<T>(),
-                   V.hwszo, V.hpho.as<cx<T>>(), V.hpwo, V.hCss.as<cx<T>>(), 0, Cv, V, V.nbox,
-                   V.child_start.as<int32_t>(), 0, Cv.M.as<cx<T>>(), V.M.as<cx<T>>());
+                   V.hwszo, V.hpho.as<cx<T>>(), V.hpwo, V.hCss.as<cx<T>>(), 0, Cv, V, V.hmck_ss, V.hnmck_ss,
+                   V.hmck_ss_max, V.nbox, V.child_start.as<int32_t>(), 0, Cv.M.as<cx<T>>(), V.M.as<cx<T>>());
         return;
     }
     const int64_t S2 = (int64_t)ps * ps, D2 = (int64_t)pd * pd, P2m = std::max(S2, D2);
@@ -1001,8 +1108,8 @@ void hf_m2l(Plan &P, int l, int nrhs, hipStream_t s) {
     const int p = V.p;
     if (p > HF_PIPE_P) {
         hf_pipe<T>(P, nrhs, s, V.nff, V.ff_src.as<int32_t>(), V.ff_op.as<int32_t>(), 0, V.hopi.as<int32_t>(),
-                   V.hW.as<T>(), V.hwsz, V.hph.as<cx<T>>(), p, V.hC.as<cx<T>>(), V.hcsz, V, V, V.nbox,
-                   V.ff_ofs.as<int32_t>(), 0, V.M.as<cx<T>>(), V.L.as<cx<T>>());
+                   V.hW.as<T>(), V.hwsz, V.hph.as<cx<T>>(), p, V.hC.as<cx<T>>(), V.hcsz, V, V, V.hmck, V.hnmck,
+                   V.hmck_max, V.nbox, V.ff_ofs.as<int32_t>(), 0, V.M.as<cx<T>>(), V.L.as<cx<T>>());
         return;
     }
     if (p <= HFW_PMAX && hfw_lds<T>(p) <= HFW_LDS_MAX) {
@@ -1044,8 +1151,8 @@ void hf_l2l(Plan &P, int l, int nrhs, hipStream_t s) {
     const int ps = U.p, pd = V.p;
     if (std::max(ps, pd) > HF_PIPE_P) {
         hf_pipe<T>(P, nrhs, s, V.nbox, V.parent.as<int32_t>(), V.octant.as<int32_t>(), 8, V.hoinfo.as<int32_t>(),
-                   V.hWo.as<T>(), V.hwszo, V.hpho.as<cx<T>>(), V.hpwo, V.hCrr.as<cx<T>>(), 0, U, V, V.nbox, nullptr,
-                   1, U.L.as<cx<T>>(), V.L.as<cx<T>>());
+                   V.hWo.as<T>(), V.hwszo, V.hpho.as<cx<T>>(), V.hpwo, V.hCrr.as<cx<T>>(), 0, U, V, V.hmck_rr,
+                   V.hnmck_rr, V.hmck_rr_max, V.nbox, nullptr, 1, U.L.as<cx<T>>(), V.L.as<cx<T>>());
         return;
     }
     const int64_t S2 = (int64_t)ps * ps, D2 = (int64_t)pd * pd, P2m = std::max(S2, D2);

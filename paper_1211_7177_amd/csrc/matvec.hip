@@ -1296,7 +1296,11 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
         tm.begin(ST_M2L, s, ev);
         if (P.hf) {
             // each target sums its own far-field translations and writes its local expansion
-            for (int l = lmin; l <= L; ++l) hf_m2l<T>(P, l, nrhs, s);
+            for (int l = lmin; l < L; ++l) hf_m2l<T>(P, l, nrhs, s);
+            hipEvent_t ev2 = nullptr;
+            tm.begin(ST_M2L_FINE, s, ev2);
+            hf_m2l<T>(P, L, nrhs, s);
+            tm.end(ST_M2L_FINE, s, ev2, 1);
             tm.end(ST_M2L, s, ev, L - lmin + 1);
             return true;
         }

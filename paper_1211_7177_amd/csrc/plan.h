@@ -57,12 +57,15 @@ struct Level {
     int64_t hwsz = 0, hwszo = 0, hcsz = 0;
     int hpwo = 0;
     DevBuf hoinfo;              // i32[16][2]: polar-angle class (and distance class 0) of each octant direction
-    DevBuf hnck, hmck;          // chunk boundaries over the degrees n < p and over |m| < p (pipeline launches)
-    int hnnck = 0, hnmck = 0;
+    // chunk boundaries of the pipelined launches: degrees n < p, and |m| < p for the
+    // coaxial shifts of the S|R set, of the S|S set into this level and of the R|R set into it
+    DevBuf hnck, hmck, hmck_ss, hmck_rr;
+    int hnnck = 0, hnmck = 0, hnmck_ss = 0, hnmck_rr = 0;
+    int hnck_max = 0, hmck_max = 0, hmck_ss_max = 0, hmck_rr_max = 0;   // largest chunk (coefficients)
 };
 
 // stage timers (HIP events on the matvec stream), enabled per plan
-enum Stage { ST_GATHER = 0, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_L2P, ST_P2P, ST_CORR, ST_SCATTER, ST_SUMS, ST_COUNT };
+enum Stage { ST_GATHER = 0, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_L2P, ST_P2P, ST_CORR, ST_SCATTER, ST_SUMS, ST_M2L_FINE, ST_COUNT };
 
 struct StageTimer {
     uint32_t mask = 0;                   // stages (bit 1 << stage) that record events

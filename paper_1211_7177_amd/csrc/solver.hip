@@ -1427,6 +1427,9 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
         FMB_CHECK_HIP(hipMemcpyAsync(R, b, tot * sizeof(cx<T>), hipMemcpyDeviceToDevice, s));
     }
     int its = 0;
+    // iterations spent: this solve's steps plus, in nested mode, the inner steps
+    // (maxit caps the total; the cap is checked between outer steps)
+    auto spent = [&]() { return its + (inner ? inner->its : 0); };
     relres.assign(nrhs, 0.0);
     while (true) {
         norms(K, R, K.hn.template as<double>(), K.hninv.template as<double>(), s);
@@ -1439,7 +1442,7 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
             act[r] = (beta[r] > tol * bn[r]) ? 1 : 0;
             any = any || act[r];
         }
-        if (!any || its >= maxit) break;
+        if (!any || spent() >= maxit) break;
         FMB_CHECK_HIP(hipMemcpyAsync(actd, act.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
         k_scale_into<T><<<gridn(tot), TPB, 0, s>>>(R, K.hninv.template as<double>(), V, len, nrhs, actd);
         FMB_LAUNCH_CHECK();
@@ -1500,12 +1503,12 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
             FMB_CHECK_HIP(hipEventRecord(K.ev[sl], s));
         };
         int queued = -1;
-        for (int j = 0; j < m && its < maxit; ++j) {
+        for (int j = 0; j < m && spent() < maxit; ++j) {
             if (queued < j) {
                 enqueue(j);
                 queued = j;
             }
-            if (j + 1 < m && its + 1 < maxit) {
+            if (j + 1 < m && spent() + 1 < maxit) {
                 enqueue(j + 1);
                 queued = j + 1;
             }
