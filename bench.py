@@ -38,9 +38,9 @@ def parse():
     ap.add_argument("--c5-tol32", type=float, default=1e-4, help="FP32 plans: accuracy the per-level orders target")
     ap.add_argument("--c5-tol64", type=float, default=1e-6, help="FP64 plans: accuracy the per-level orders target")
     ap.add_argument("--c5-rows", type=int, default=1024, help="seeded oracle rows of the large-ellipsoid checks")
-    ap.add_argument("--c5-solve-s", type=float, default=150.0,
+    ap.add_argument("--c5-solve-s", type=float, default=60.0,
                     help="wall-clock budget (s) of the large-ellipsoid solve (0: skip the solve)")
-    ap.add_argument("--c5-solve-chunk", type=int, default=200,
+    ap.add_argument("--c5-solve-chunk", type=int, default=1000,
                     help="Krylov iterations per call of the large-ellipsoid solve (progress line after each)")
     ap.add_argument("--skip-torus", action="store_true", help="skip the 60k-node torus solve comparison")
     ap.add_argument("--torus-steps", type=int, default=3)
