@@ -38,16 +38,20 @@ def parse():
     ap.add_argument("--c5-tol32", type=float, default=1e-4, help="FP32 plans: accuracy the per-level orders target")
     ap.add_argument("--c5-tol64", type=float, default=1e-6, help="FP64 plans: accuracy the per-level orders target")
     ap.add_argument("--c5-rows", type=int, default=1024, help="seeded oracle rows of the large-ellipsoid checks")
-    ap.add_argument("--c5-solve-s", type=float, default=60.0,
+    ap.add_argument("--c5-solve-s", type=float, default=45.0,
                     help="wall-clock budget (s) of the large-ellipsoid solve (0: skip the solve)")
     ap.add_argument("--c5-solve-chunk", type=int, default=1000,
                     help="Krylov iterations per call of the large-ellipsoid solve (progress line after each)")
     ap.add_argument("--skip-torus", action="store_true", help="skip the 60k-node torus solve comparison")
     ap.add_argument("--torus-steps", type=int, default=3)
     ap.add_argument("--torus-warmup", type=int, default=1)
-    ap.add_argument("--order64", type=int, default=16)
+    ap.add_argument("--order64", type=int, default=0,
+                    help="torus FP64 plans: fixed order (> 0) or orders per level for --tol64 (<= 0)")
+    ap.add_argument("--tol64", type=float, default=1e-8, help="torus FP64 plans with orders per level: accuracy")
     ap.add_argument("--order32", type=int, default=5)
-    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--tol", type=float, default=1e-8,
+                    help="torus solves: relative FP64 residual (1e-8 with the 1e-8 FP64 operator puts both timed "
+                         "solutions within 1e-6 of the converged discrete solution)")
     ap.add_argument("--inner-tol", type=float, default=5e-3)
     ap.add_argument("--restart", type=int, default=150, help="Krylov basis size (inner solves and the FP64 solve)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -311,7 +315,7 @@ def torus_section(args, log):
         if best is not None:
             args.order32, args.translate32 = best["order32"], best["translate"]
     t0 = time.perf_counter()
-    pb = BemProblem(nodes, k0, eps, order=args.order64, depth=depth, order32=args.order32,
+    pb = BemProblem(nodes, k0, eps, order=args.order64, depth=depth, order32=args.order32, tol=args.tol64,
                     translate32=args.translate32)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
@@ -368,7 +372,7 @@ def torus_section(args, log):
     # args.batch seeded plane waves through plans built for that many columns
     batched = None
     if args.batch > 1:
-        pbb = BemProblem(nodes, k0, eps, order=args.order64, depth=depth, order32=args.order32,
+        pbb = BemProblem(nodes, k0, eps, order=args.order64, depth=depth, order32=args.order32, tol=args.tol64,
                          translate32=args.translate32, nrhs_max=args.batch)
         db, pob = plane_waves(args.batch, seed_for(2, "dirs"), seed_for(2, "pols"))
         rb = pbb.rhs_planewave(db, pob)
@@ -527,7 +531,8 @@ def torus_section(args, log):
                      "bf16x3) and FP32 inner Krylov vectors; FP64 self-triangle corrections, inner products, "
                      "Hessenberg/Givens, residuals and the refinement iterate",
         "config": {"workload": "torus_R1_r0.3_20000tri_60000nodes_eps-15+1i_k0R4_depth5_planewave",
-                   "nodes": n, "unknowns": 6 * n, "depth": depth, "order_fp64": args.order64,
+                   "nodes": n, "unknowns": 6 * n, "depth": depth,
+                   "order_fp64": info64["order_level"] if args.order64 <= 0 else args.order64, "tol_fp64": args.tol64,
                    "order_fp32": args.order32, "translate_fp32": args.translate32, "tol": args.tol,
                    "restart": args.restart, "inner_tol": args.inner_tol,
                    "inner_gram_schmidt": "two passes (DGKS)" if args.inner_reorth else "one classical pass"},
