@@ -677,10 +677,17 @@ def c5_workload(args, log):
     plans = {"fp32": (pb.p0_32, pb.p1_32), "fp64": (pb.p0, pb.p1)}
     ys = {t: (torch.empty_like(ga[t]), torch.empty_like(ga[t])) for t in plans}
 
+    # one step = one application of the 6N operator (eqs. 2.9-2.13): split, the k0 and k1 FMM products
+    # (their near fields in one launch in FP32), corrections, combine; x = (a, b) as (Phi, Psi)
+    xs = {"fp32": torch.cat([ga["fp32"], gb["fp32"]], dim=2).contiguous(),
+          "fp64": torch.cat([ga["fp64"], gb["fp64"]], dim=2).contiguous()}
+    rs = {t: torch.empty_like(xs[t]) for t in xs}
+
     def step(t):
-        p0, p1 = plans[t]
-        p0.matvec(ga[t], gb[t], out=ys[t][0])
-        p1.matvec(ga[t], gb[t], out=ys[t][1])
+        if t == "fp32":
+            pb.apply32(xs[t], out=rs[t])
+        else:
+            rs[t] = pb.apply(xs[t])
 
     for _ in range(args.warmup):
         step("fp32")
@@ -691,7 +698,16 @@ def c5_workload(args, log):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms32 = 1e3 * dt / args.steps
-    log("c5 FP32 products: %.2f ms per step (%d steps)" % (ms32, args.steps))
+    log("c5 FP32 applications: %.2f ms per step (%d steps)" % (ms32, args.steps))
+    # per-step spread (each step synchronised on its own; outside the timed loop)
+    per = []
+    for _ in range(args.steps):
+        t1 = time.perf_counter()
+        step("fp32")
+        torch.cuda.synchronize()
+        per.append(1e3 * (time.perf_counter() - t1))
+    spread = {"p10_ms": float(np.percentile(per, 10)), "median_ms": float(np.median(per)),
+              "p90_ms": float(np.percentile(per, 90))}
     step("fp64")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -700,7 +716,12 @@ def c5_workload(args, log):
         step("fp64")
     torch.cuda.synchronize()
     ms64 = 1e3 * (time.perf_counter() - t0) / reps64
-    log("c5 FP64 products: %.2f ms per step" % ms64)
+    log("c5 FP64 applications: %.2f ms per step" % ms64, "FP32 spread", spread)
+    # the plans' own products on (a, b), for the oracle check of each wavenumber's operator
+    for t, (p0, p1) in plans.items():
+        p0.matvec(ga[t], gb[t], out=ys[t][0])
+        p1.matvec(ga[t], gb[t], out=ys[t][1])
+    torch.cuda.synchronize()
 
     # stage profile (HIP events on the plans' stream) of the exterior FP32 plan
     prof = {}
@@ -790,17 +811,18 @@ def c5_workload(args, log):
     else:
         acc = None
     out = {
-        "value": 1e3 / ms32, "ms_per_step": ms32,
+        "value": 1e3 / ms32, "ms_per_step": ms32, "step_spread_fp32": spread,
         "config": {"workload": C5_NAME, "nodes": n, "unknowns": 6 * n, "depth": cfg["depth"], "k0": cfg["k0"],
                    "eps": str(cfg["eps"]), "k1": str(pb.k1), "tol_fp32": args.c5_tol32, "tol_fp64": args.c5_tol64,
                    "order_per_level_fp32": infos["k0_fp32"]["order_level"],
                    "order_per_level_fp64": infos["k0_fp64"]["order_level"],
                    "interior_plan": "local only (far field damped below 1e-8 / 1e-16 at every level)",
-                   "step": "FP32 FMM products at k0 and k1 on seeded complex64 densities (one BEM application's "
-                           "products)"},
-        "fmm_matvecs_per_s": {"fp32": 1e3 / ms32, "fp64": 1e3 / ms64},
+                   "step": "one application of the 6N operator with the FP32 plans (bem_apply32: split, FMM "
+                           "products at k0 and k1 with one fused near-field launch, FP64-built self-triangle "
+                           "blocks, combine) on a seeded complex64 vector"},
+        "bem_matvecs_per_s": {"fp32": 1e3 / ms32, "fp64": 1e3 / ms64},
         "unknowns_matvec_per_s": {"fp32": 6 * n * 1e3 / ms32, "fp64": 6 * n * 1e3 / ms64},
-        "speedup_fp32_vs_fp64_products": ms64 / ms32,
+        "speedup_fp32_vs_fp64": ms64 / ms32,
         "stage_ms_per_product_k0": prof,
         "plan_s_4plans": plan_s,
         "plan_info": {t: {k: i[k] for k in ("nbox", "m2l_pairs", "p2p_pairs", "device_bytes", "order_level",

@@ -305,6 +305,17 @@ int bem_problem_use_graphs(fmb_problem_t pb, int32_t enable);
 int bem_apply(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, void *stream);
 
 /*
+ * bem_apply32: r = A x with the problem's FP32 plans, the operator the inner solves of the
+ * mixed modes apply (eqs. 2.9-2.13; FP32 products, FP64 self-triangle blocks rounded to FP32
+ * in the return to user order).  x and r device c64 [nrhs][n][nu] (nu = 6, or 3 for
+ * impedance problems), not aliased.  When both FP32 plans share their nodes and octree, k0
+ * is real and the interior plan is local only (strongly lossy k1), the two near fields run as
+ * one launch.  FMB_EINVAL without FP32 plans or for nrhs
+ * out of range.  Asynchronous on `stream`.
+ */
+int bem_apply32(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, void *stream);
+
+/*
  * bem_apply_adjoint: r = A^H x, the conjugate transpose of bem_apply's
  * operator, x and r device c128 [nrhs][n][6].  With (a_j, b_j) = Op_kj^H x_j
  * (fmm_matvec_adjoint) for x_0 = x[0:3], x_1 = x[3:6]:

@@ -58,7 +58,7 @@ class GmresInfo(ctypes.Structure):
 
 EXPORTS = [
     "fmb_plan_opts_default", "fmm_plan", "fmm_matvec", "fmm_matvec_adjoint", "fmm_plan_info",
-    "fmm_plan_export_tree", "fmm_plan_destroy", "fmm_plan_profile", "fmm_plan_profile_read", "fmb_gmres_opts_default", "bem_problem_create", "bem_problem_create_multi", "bem_problem_create_ibc", "bem_problem_use_graphs", "bem_apply", "bem_apply_adjoint",
+    "fmm_plan_export_tree", "fmm_plan_destroy", "fmm_plan_profile", "fmm_plan_profile_read", "fmb_gmres_opts_default", "bem_problem_create", "bem_problem_create_multi", "bem_problem_create_ibc", "bem_problem_use_graphs", "bem_apply", "bem_apply32", "bem_apply_adjoint",
     "bem_precond_apply", "bem_rhs_planewave", "bem_field", "bem_field_noalloc", "bem_field_fmm", "bem_far_field_adjoint", "gmres_solve", "gmres_solve_group", "bem_problem_destroy", "fmb_last_error",
 ]
 
@@ -93,6 +93,7 @@ def load():
         "bem_problem_use_graphs": [vp, i32],
         "bem_apply_adjoint": [vp, vp, vp, i32, vp],
         "bem_apply": [vp, vp, vp, i32, vp],
+        "bem_apply32": [vp, vp, vp, i32, vp],
         "bem_precond_apply": [vp, vp, vp, i32, vp],
         "bem_rhs_planewave": [vp, vp, vp, vp, i32, vp],
         "gmres_solve": [vp, vp, vp, i32, vp, vp, vp],

@@ -15,6 +15,9 @@
 //   d_z R_n^m        = k [ -A_n^m R_{n+1}^m     + B_n^m R_{n-1}^m ]
 //   (d_x + i d_y) R  = k [ -C_n^m R_{n+1}^{m+1} + D_n^m R_{n-1}^{m+1} ]
 //   (d_x - i d_y) R  = k [ -E_n^m R_{n+1}^{m-1} + F_n^m R_{n-1}^{m-1} ]
+#include <array>
+#include <map>
+
 #include "basis.h"
 #include "plan.h"
 
@@ -556,6 +559,157 @@ __global__ void __launch_bounds__(TPB) k_p2p32(int nleaf, int nrhs, const int32_
 template <int RC>
 constexpr auto k_p2p32_cut = k_p2p32<true, RC, true>;
 
+// The near fields of the two plans of one BEM application at once, when the interior
+// plan is local only (same nodes and octree; k0 real, k1 strongly lossy; one
+// right-hand side per block row): the pair geometry, the LDS staging of the source
+// headers and the reciprocal square root are shared, and each pair adds k0's terms
+// and, within k1's cutoff radius, k1's.  Same layout and reduction as k_p2p32.
+__global__ void __launch_bounds__(TPB) k_p2p32_pair(int nleaf, int nrhs, const int32_t *__restrict__ start,
+                                                    const int32_t *__restrict__ nbr,
+                                                    const double *__restrict__ center,
+                                                    const double *__restrict__ spts, const double *__restrict__ snrm,
+                                                    const int32_t *__restrict__ stri,
+                                                    const cx<float> *__restrict__ src0,
+                                                    const cx<float> *__restrict__ src1, int64_t n, double k0,
+                                                    double k1_re, double k1_im, float rcut2_1,
+                                                    cx<float> *__restrict__ ys0, cx<float> *__restrict__ ys1) {
+    constexpr int TS = 128;
+    __shared__ SrcHdr32 hdr[TS];
+    __shared__ __attribute__((aligned(16))) cx<float> rec[2][TS][8];   // a[3], b[3], n.a, unused per plan
+    __shared__ int32_t sid[TS];
+    __shared__ int32_t nb_start[28], nb_box[27];
+    __shared__ int n_nb;
+    __shared__ cx<float> red[TPB][3];
+    const int box = blockIdx.x, r = blockIdx.y;
+    if (box >= nleaf || r >= nrhs) return;
+    const int t0 = start[box], t1 = start[box + 1];
+    const int nt = t1 - t0;
+    const double c0x = center[3 * box], c0y = center[3 * box + 1], c0z = center[3 * box + 2];
+    if (threadIdx.x == 0) {
+        int c = 0, tot = 0;
+        for (int q = 0; q < 27; ++q) {
+            const int b = nbr[box * 27 + q];
+            if (b >= 0) {
+                nb_box[c] = b;
+                nb_start[c] = tot;
+                tot += start[b + 1] - start[b];
+                ++c;
+            }
+        }
+        nb_start[c] = tot;
+        n_nb = c;
+    }
+    __syncthreads();
+    const int ns_total = nb_start[n_nb];
+    const float krev0 = (float)(k0 * 0.15915494309189533577), kr0 = (float)k0;
+    const float krev1 = (float)(k1_re * 0.15915494309189533577);
+    const float kexp1 = (float)(-k1_im * 1.44269504088896340736);
+    const float kr1 = (float)k1_re, ki1 = (float)k1_im;
+    const float inv4pi = 0.07957747154594766788f;
+    for (int tc0 = 0; tc0 < nt; tc0 += TPB) {
+        const int ntc = min(TPB, nt - tc0);
+        const int S = TPB / ntc;
+        const int ti = threadIdx.x % ntc, sl = threadIdx.x / ntc;
+        const bool active = sl < S;
+        const int64_t ig = t0 + tc0 + ti;
+        float tx = 0.f, ty = 0.f, tz = 0.f;
+        int32_t ttri = -1;
+        if (active) {
+            tx = (float)(spts[3 * ig] - c0x);
+            ty = (float)(spts[3 * ig + 1] - c0y);
+            tz = (float)(spts[3 * ig + 2] - c0z);
+            ttri = stri[ig];
+        }
+        cx<float> acc0[3] = {mk(0.f, 0.f), mk(0.f, 0.f), mk(0.f, 0.f)};
+        cx<float> acc1[3] = {mk(0.f, 0.f), mk(0.f, 0.f), mk(0.f, 0.f)};
+        for (int base = 0; base < ns_total; base += TS) {
+            const int cnt = min(TS, ns_total - base);
+            __syncthreads();
+            for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
+                const int u = base + j;
+                int b = 0;
+                while (nb_start[b + 1] <= u) ++b;
+                const int64_t sidx = start[nb_box[b]] + (u - nb_start[b]);
+                SrcHdr32 q;
+                q.x = (float)(spts[3 * sidx] - c0x);
+                q.y = (float)(spts[3 * sidx + 1] - c0y);
+                q.z = (float)(spts[3 * sidx + 2] - c0z);
+                q.tri = stri[sidx];
+                q.nx = (float)snrm[3 * sidx];
+                q.ny = (float)snrm[3 * sidx + 1];
+                q.nz = (float)snrm[3 * sidx + 2];
+                q.pad = 0.f;
+                hdr[j] = q;
+                sid[j] = (int32_t)sidx;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < cnt * 16; e += blockDim.x) {
+                const int w = e % 8, pl = (e / 8) % 2, j = e / 16;
+                const cx<float> *sp = pl ? src1 : src0;
+                rec[pl][j][w] = w < 7 ? sp[((int64_t)r * n + sid[j]) * 7 + w] : mk(0.f, 0.f);
+            }
+            __syncthreads();
+            if (!active) continue;
+            for (int j = sl; j < cnt; j += S) {
+                const SrcHdr32 &q = hdr[j];
+                const bool self = q.tri == ttri;
+                const float dx = q.x - tx, dy = q.y - ty, dz = q.z - tz;
+                const float R2r = dx * dx + dy * dy + dz * dz;
+                const float R2 = self ? 1.f : R2r;
+                const float iR = __builtin_amdgcn_rsqf(R2);
+                const float R = R2 * iR;
+                const float iR2 = iR * iR;
+                const float v = q.nx * dx + q.ny * dy + q.nz * dz;
+                {
+                    // k0 (real): g = e^{i k0 R} / (4 pi R), f = (i k0 R - 1) g / R^2
+                    const float sn = __builtin_amdgcn_sinf(krev0 * R), cs = __builtin_amdgcn_cosf(krev0 * R);
+                    const float sc = self ? 0.f : inv4pi * iR;
+                    const cx<float> g = mk(sc * cs, sc * sn);
+                    const cx<float> f = mk(iR2 * (-g.re - kr0 * R * g.im), iR2 * (-g.im + kr0 * R * g.re));
+                    const cx<float> *qr = rec[0][j];
+                    const cx<float> u = dx * qr[0] + dy * qr[1] + dz * qr[2];
+                    const cx<float> wx = q.nx * u - v * qr[0] - dx * qr[6];
+                    const cx<float> wy = q.ny * u - v * qr[1] - dy * qr[6];
+                    const cx<float> wz = q.nz * u - v * qr[2] - dz * qr[6];
+                    acc0[0] += f * wx + g * qr[3];
+                    acc0[1] += f * wy + g * qr[4];
+                    acc0[2] += f * wz + g * qr[5];
+                }
+                if (R2r <= rcut2_1) {
+                    // k1 (lossy): the same with the decay e^{-Im k1 R}
+                    const float sn = __builtin_amdgcn_sinf(krev1 * R), cs = __builtin_amdgcn_cosf(krev1 * R);
+                    const float ex = __builtin_amdgcn_exp2f(kexp1 * R);
+                    const float sc = self ? 0.f : inv4pi * iR * ex;
+                    const cx<float> g = mk(sc * cs, sc * sn);
+                    const cx<float> f = mk(iR2 * ((-ki1 * R - 1.f) * g.re - kr1 * R * g.im),
+                                           iR2 * ((-ki1 * R - 1.f) * g.im + kr1 * R * g.re));
+                    const cx<float> *qr = rec[1][j];
+                    const cx<float> u = dx * qr[0] + dy * qr[1] + dz * qr[2];
+                    const cx<float> wx = q.nx * u - v * qr[0] - dx * qr[6];
+                    const cx<float> wy = q.ny * u - v * qr[1] - dy * qr[6];
+                    const cx<float> wz = q.nz * u - v * qr[2] - dz * qr[6];
+                    acc1[0] += f * wx + g * qr[3];
+                    acc1[1] += f * wy + g * qr[4];
+                    acc1[2] += f * wz + g * qr[5];
+                }
+            }
+        }
+        // sum the source slices, one plan at a time
+        for (int pl = 0; pl < 2; ++pl) {
+            __syncthreads();
+            for (int c = 0; c < 3; ++c) red[threadIdx.x][c] = pl ? acc1[c] : acc0[c];
+            __syncthreads();
+            if (threadIdx.x < ntc) {
+                cx<float> sm[3] = {mk(0.f, 0.f), mk(0.f, 0.f), mk(0.f, 0.f)};
+                for (int q = 0; q < S; ++q)
+                    for (int c = 0; c < 3; ++c) sm[c] += red[q * ntc + threadIdx.x][c];
+                cx<float> *o = (pl ? ys1 : ys0) + ((int64_t)r * n + t0 + tc0 + threadIdx.x) * 3;
+                for (int c = 0; c < 3; ++c) o[c] += sm[c];
+            }
+        }
+    }
+}
+
 template <typename T>
 __global__ void k_zero(cx<T> *__restrict__ x, int64_t m) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -913,14 +1067,21 @@ inline bool use_big(int precision, int KR) {
 inline int bf3_job_cols(int p) { return p <= 5 ? 96 : (p <= 8 ? 64 : 32); }
 
 inline bool use_bf3(const Plan &P) {
-    return P.precision == FMB_FP32 && P.translate_mode == FMB_TRANSLATE_BF16X3 && P.order >= 2 && P.order <= 9 &&
-           3 * P.nrhs_max <= bf3_job_cols(P.order);
+    return P.precision == FMB_FP32 && P.translate_mode == FMB_TRANSLATE_BF16X3 && P.order >= 2 && P.order <= 9;
 }
 
 // the operator-stationary kernel applies to FP32 operators of order 2 <= p <= 9
-// whose column blocks (3 nrhs columns per entry) fit one job
 inline bool use_os(int precision, int p, int nrhs_max) {
-    return precision == FMB_FP32 && p >= 2 && p <= 9 && 3 * nrhs_max <= OS_MAXCOLS;
+    (void)nrhs_max;
+    return precision == FMB_FP32 && p >= 2 && p <= 9;
+}
+
+// right-hand sides per translation launch: a job holds whole entries of 3 x (this many)
+// columns, so wider batches run as several launches over slices of the right-hand sides
+inline int translate_rhs_chunk(const Plan &P) {
+    if (use_bf3(P)) return std::min(P.nrhs_max, bf3_job_cols(P.order) / 3);
+    if (use_os(P.precision, P.order, P.nrhs_max)) return std::min(P.nrhs_max, OS_MAXCOLS / 3);
+    return P.nrhs_max;
 }
 
 // Split-BF16 variant of the operator-stationary kernel (FP32 plans, p <= 9).
@@ -1228,6 +1389,10 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
     const int64_t blkR = 2 * blk;
     const bool os = use_os(P.precision, p, P.nrhs_max);
     const bool bf3 = use_bf3(P);
+    // translations run over slices of at most cw right-hand sides; roff(r0) is the
+    // offset (in reals) of right-hand side r0 inside a box's or slot's block
+    const int cw = translate_rhs_chunk(P);
+    auto roff = [&](int r0) { return (int64_t)r0 * 3 * KR; };
     cx<T> *src = P.src.as<cx<T>>();
     cx<T> *ys = P.ys.as<cx<T>>();
     cx<T> *yb = P.ybuf.as<cx<T>>();
@@ -1253,7 +1418,11 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
         // LDS: the group-reduction area (G * P2 * 3 complex when G > 1), then per node of a batch
         const int G = P2 <= TPB ? TPB / P2 : 1;
         const size_t redb = G > 1 ? (size_t)G * P2 * 3 * sizeof(cx<T>) : 0;
-        const int batch = (int)std::max<size_t>(1, std::min<size_t>(64, (60000 - redb) / per));
+        // node batches sized so that the block's LDS stays near 24 KB (several blocks share a CU), with at
+        // least 8 nodes per batch while 60 KB allow it
+        const size_t fit = (60000 - redb) / per;
+        const size_t want = std::max<size_t>(8, (redb < 24000 ? 24000 - redb : 0) / per);
+        const int batch = (int)std::max<size_t>(1, std::min<size_t>({(size_t)64, fit, want}));
         const size_t sh = redb + (size_t)batch * per;
         tm.begin(ST_P2M, s, ev);
         k_p2m<T><<<(unsigned)LL.nbox, TPB, sh, s>>>(
@@ -1277,10 +1446,11 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
         }
         if (V.ntiles_m2m == 0) return true;
         tm.begin(ST_M2M, s, ev);
-        launch_translate<T>(V.tiles_m2m.as<Tile>(), V.ntiles_m2m, C.by_octant.as<int32_t>(), nullptr, V.m2m.as<T>(),
-                            (const T *)C.M.p, (T *)yb, KR, ncol, blkR, os, s, 0, 0, bf3 ? V.m2m_hi.p : nullptr,
-                            V.m2m_lo.p);
-        tm.end(ST_M2M, s, ev);
+        for (int r0 = 0; r0 < nrhs; r0 += cw)
+            launch_translate<T>(V.tiles_m2m.as<Tile>(), V.ntiles_m2m, C.by_octant.as<int32_t>(), nullptr, V.m2m.as<T>(),
+                                (const T *)C.M.p + roff(r0), (T *)yb + roff(r0), KR, 3 * std::min(cw, nrhs - r0), blkR,
+                                os, s, 0, 0, bf3 ? V.m2m_hi.p : nullptr, V.m2m_lo.p);
+        tm.end(ST_M2M, s, ev, (nrhs + cw - 1) / cw);
         tm.begin(ST_SUMS, s, ev);
         k_sum_children<T><<<(unsigned)V.nbox, TPB, 0, s>>>(V.child_start.as<int32_t>(), V.nbox, yb, V.M.as<cx<T>>(), blk,
                                                            ncol * P2);
@@ -1307,10 +1477,13 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
         for (int l = lmin; l <= L; ++l) {
             Level &V = P.lv[l];
             if (V.ntiles_m2l == 0) continue;
-            launch_translate<T>(V.tiles_m2l.as<Tile>(), V.ntiles_m2l, V.ff_by_op.as<int32_t>(), V.ff_src.as<int32_t>(),
-                                V.m2l.as<T>(), (const T *)V.M.p, (T *)(yb + V.slot_base * blk), KR, ncol, blkR, os, s,
-                                1, 0, bf3 ? V.m2l_hi.p : nullptr, V.m2l_lo.p);
-            ++nk;
+            for (int r0 = 0; r0 < nrhs; r0 += cw) {
+                launch_translate<T>(V.tiles_m2l.as<Tile>(), V.ntiles_m2l, V.ff_by_op.as<int32_t>(),
+                                    V.ff_src.as<int32_t>(), V.m2l.as<T>(), (const T *)V.M.p + roff(r0),
+                                    (T *)(yb + V.slot_base * blk) + roff(r0), KR, 3 * std::min(cw, nrhs - r0), blkR,
+                                    os, s, 1, 0, bf3 ? V.m2l_hi.p : nullptr, V.m2l_lo.p);
+                ++nk;
+            }
         }
         tm.end(ST_M2L, s, ev, nk);
         return true;
@@ -1350,10 +1523,12 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
         if (V.ntiles_l2l == 0) return true;
         Level &U = P.lv[l - 1];
         tm.begin(ST_L2L, s, ev);
-        launch_translate<T>(V.tiles_l2l.as<Tile>(), V.ntiles_l2l, V.by_octant.as<int32_t>(), V.parent.as<int32_t>(),
-                            V.l2l.as<T>(), (const T *)U.L.p, (T *)V.L.p, KR, ncol, blkR, os, s, 2, 1,
-                            bf3 ? V.l2l_hi.p : nullptr, V.l2l_lo.p);
-        tm.end(ST_L2L, s, ev);
+        for (int r0 = 0; r0 < nrhs; r0 += cw)
+            launch_translate<T>(V.tiles_l2l.as<Tile>(), V.ntiles_l2l, V.by_octant.as<int32_t>(), V.parent.as<int32_t>(),
+                                V.l2l.as<T>(), (const T *)U.L.p + roff(r0), (T *)V.L.p + roff(r0), KR,
+                                3 * std::min(cw, nrhs - r0), blkR, os, s, 2, 1, bf3 ? V.l2l_hi.p : nullptr,
+                                V.l2l_lo.p);
+        tm.end(ST_L2L, s, ev, (nrhs + cw - 1) / cw);
         return true;
     }
     // Step 4: local expansions at the targets, then the near sum
@@ -1379,6 +1554,7 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
         return true;
     }
     if (step == k++) {
+        if (P.fuse_p2p) return true;           // the two-product runner launches both near fields at once
         tm.begin(ST_P2P, s, ev);
         if (sizeof(T) == sizeof(float)) {
             const bool lossy = P.k_im != 0.0;
@@ -1449,8 +1625,9 @@ void build_tiles(Plan &P, hipStream_t s) {
                                       : (use_big(P.precision, 2 * P.P2)
                                              ? (P.precision == FMB_FP64 ? big_n<double>() : big_n<float>())
                                              : TN));
-    const int ep_max = std::max(1, cols / (3 * P.nrhs_max));
-    const int ep_min = os ? std::max(1, OS_COLS / (3 * P.nrhs_max)) : ep_max;
+    const int cw = translate_rhs_chunk(P);
+    const int ep_max = std::max(1, cols / (3 * cw));
+    const int ep_min = os ? std::max(1, OS_COLS / (3 * cw)) : ep_max;
     auto ep_for = [&](int64_t total) {
         int64_t e = total / EP_BLOCKS;
         return (int)std::max<int64_t>(ep_min, std::min<int64_t>(ep_max, e));
@@ -1650,12 +1827,74 @@ void run_matvec_adjoint(Plan &P, const void *y, void *abar, void *bbar, int nrhs
     }
 }
 
+// the two plans of one BEM application share their nodes and octree when both are
+// FP32 over the same points at the same depth.  When the interior plan is local only
+// (its product is a cut near field and little else), both near fields run as one
+// launch.  When both plans have far fields, their products overlap on two streams,
+// and joining them around one near-field launch measured slower (the 60k-node torus:
+// 316 against 303 ms per mixed solve), so they stay apart.
+static bool p2p_fusable(const Plan &P0, const Plan &P1) {
+    return P0.precision == FMB_FP32 && P1.precision == FMB_FP32 && &P0 != &P1 && P0.n == P1.n &&
+           P0.depth == P1.depth && P0.lv[P0.depth].nbox == P1.lv[P1.depth].nbox && P0.k_im == 0.0 &&
+           P1.k_im > 0.0 && P0.far_on() && !P1.far_on() && P0.lo[0] == P1.lo[0] && P0.lo[1] == P1.lo[1] &&
+           P0.lo[2] == P1.lo[2] && P0.ext == P1.ext;
+}
+
+// two events per device and host thread for the join around the fused near field
+static hipEvent_t *pair_events() {
+    static thread_local std::map<int, std::array<hipEvent_t, 2>> evs;
+    int dev = 0;
+    FMB_CHECK_HIP(hipGetDevice(&dev));
+    auto it = evs.find(dev);
+    if (it == evs.end()) {
+        std::array<hipEvent_t, 2> e{};
+        for (auto &x : e) FMB_CHECK_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+        it = evs.emplace(dev, e).first;
+    }
+    return it->second.data();
+}
+
+static void launch_p2p_pair(Plan &P0, Plan &P1, int nrhs, hipStream_t s) {
+    Level &LL = P0.lv[P0.depth];
+    hipEvent_t ev = nullptr;
+    P0.timer.begin(ST_P2P, s, ev);
+    k_p2p32_pair<<<dim3((unsigned)LL.nbox, (unsigned)nrhs), TPB, 0, s>>>(
+        (int)LL.nbox, nrhs, LL.start.as<int32_t>(), LL.nbr.as<int32_t>(), LL.center.as<double>(),
+        P0.spts.as<double>(), P0.snrm.as<double>(), P0.stri.as<int32_t>(), P0.src.as<cx<float>>(),
+        P1.src.as<cx<float>>(), P0.n, P0.k_re, P1.k_re, P1.k_im, (float)std::min(P1.rcut2, 1e30),
+        P0.ys.as<cx<float>>(), P1.ys.as<cx<float>>());
+    FMB_LAUNCH_CHECK();
+    P0.timer.end(ST_P2P, s, ev);
+}
+
 void run_matvec_pair(Plan &P0, const void *a0, const void *b0, void *y0, hipStream_t s0, Plan &P1, const void *a1,
                      const void *b1, void *y1, hipStream_t s1, int nrhs) {
+    // the near-field step (the same index in both plans: gather, P2M, the S|S levels, S|R, its sums,
+    // the R|R levels, L2P, then P2P)
+    const bool fuse = p2p_fusable(P0, P1);
+    const int p2p_step = 2 * P0.depth + 1;
+    P0.fuse_p2p = P1.fuse_p2p = fuse;
+    struct Reset {
+        Plan &a, &b;
+        ~Reset() { a.fuse_p2p = b.fuse_p2p = false; }
+    } reset{P0, P1};
     bool more0 = true, more1 = true;
     for (int st = 0; more0 || more1; ++st) {
         if (more0) more0 = run_step(P0, a0, b0, y0, nrhs, s0, st);
         if (more1) more1 = run_step(P1, a1, b1, y1, nrhs, s1, st);
+        if (fuse && st == p2p_step) {
+            // s0 waits for s1's L2P, runs both near fields, and s1 waits for that
+            hipEvent_t *ev = pair_events();
+            if (s0 != s1) {
+                FMB_CHECK_HIP(hipEventRecord(ev[0], s1));
+                FMB_CHECK_HIP(hipStreamWaitEvent(s0, ev[0], 0));
+            }
+            launch_p2p_pair(P0, P1, nrhs, s0);
+            if (s0 != s1) {
+                FMB_CHECK_HIP(hipEventRecord(ev[1], s0));
+                FMB_CHECK_HIP(hipStreamWaitEvent(s1, ev[1], 0));
+            }
+        }
     }
 }
 

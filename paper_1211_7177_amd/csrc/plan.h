@@ -83,6 +83,7 @@ struct StageTimer {
 };
 
 struct Plan {
+    bool fuse_p2p = false;      // set by the two-product runner: the P2P step is left to its fused launch
     int64_t n = 0;
     int depth = 0, order = 0, P2 = 0, precision = FMB_FP64, nrhs_max = 1, corr_mode = 0;
     double k_re = 0, k_im = 0;

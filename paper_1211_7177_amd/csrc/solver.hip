@@ -2168,6 +2168,15 @@ int bem_apply(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, void *stre
     });
 }
 
+int bem_apply32(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, void *stream) {
+    return guarded([&] {
+        FMB_REQUIRE(pb && x && r && x != r, "bad arguments");
+        FMB_REQUIRE(pb->p032 != nullptr, "bem_apply32 needs the FP32 plans");
+        FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
+        bem_apply_t<float>(*pb, (const cx<float> *)x, (cx<float> *)r, nrhs, (hipStream_t)stream);
+    });
+}
+
 int bem_apply_adjoint(fmb_problem_t pb, const void *x, void *r, int32_t nrhs, void *stream) {
     return guarded([&] {
         FMB_REQUIRE(pb && x && r && x != r, "bad arguments");

@@ -117,6 +117,16 @@ class BemProblem:
         check(self._lib.bem_apply(self.h, px, ctypes.c_void_p(out.data_ptr()), nr, _stream()))
         return out
 
+    def apply32(self, x, out=None):
+        """A x with the FP32 plans (the inner solves' operator), x complex64 [nrhs, n, nu] on the GPU."""
+        if x.dim() == 2:
+            x = x.unsqueeze(0)
+        px = _abi._dev(x, torch.complex64, (self.n, self.nu), "x")
+        out = torch.empty_like(x) if out is None else out
+        _abi._dev(out, torch.complex64, (self.n, self.nu), "out")
+        check(self._lib.bem_apply32(self.h, px, ctypes.c_void_p(out.data_ptr()), x.shape[0], _stream()))
+        return out
+
     def apply_adjoint(self, v):
         """A^H v, v complex128 [nrhs, n, 6] (or [n, 6]) on the GPU."""
         out = torch.empty_like(v)

@@ -243,12 +243,14 @@ def test_batched_rhs_and_determinism(abi, sphere):
     P.close()
 
 
-@pytest.mark.parametrize("translate,nrhs", [("fp32", 5), ("bf16x3", 8)])
+@pytest.mark.parametrize("translate,nrhs", [("fp32", 5), ("bf16x3", 8), ("bf16x3", 45), ("fp32", 100)])
 def test_fp32_batched_rhs_match_single(abi, sphere, translate, nrhs):
     """FP32 plans with several right-hand sides (the near field shares the pair
     geometry across a chunk of them; 5 = a chunk of 4 and a ragged chunk of 1):
     each column equals its single-RHS product to FP32 rounding, and both match
-    the direct sum."""
+    the direct sum.  45 and 100 right-hand sides exceed one translation job
+    (21 at order 8 for split-BF16, 96 for FP32), so the translations run over
+    slices of the batch."""
     q = sphere
     n = q["points"].shape[0]
     a, b = _dens(n, 1, nrhs=nrhs)

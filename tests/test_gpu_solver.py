@@ -62,6 +62,40 @@ def test_bem_apply_precond_rhs_match_oracle(gpu, small):
     pb.close()
 
 
+@pytest.mark.parametrize("eps", [complex(2.25, 0.5), complex(-1e4, 1e2)])
+def test_fp32_apply_with_fused_near_fields(gpu, eps):
+    """bem_apply32 (the FP32 operator of the mixed solves, whose two near fields run as one
+    launch when k0 is real and the k1 plan local only) on the 3840-node sphere: equal to the same
+    application assembled from the two FP32 plans' separate products (eqs. 2.9-2.13 with
+    T = I + (1 - eps)/eps n n, gamma = 1) to FP32 rounding, and within the FP32 plans'
+    accuracy of the oracle's application.  eps = -1e4 + 1e2i makes k1 = 0.5 + 100i, whose
+    FP32 plan is local only (its near field cut at ln(1e8)/Im k1 inside the fused launch);
+    eps = 2.25 + 0.5i keeps both far fields, and the two products run apart."""
+    q = nystrom3(icosphere(8))
+    n = q["points"].shape[0]
+    k0 = 1.0
+    print("fused near fields, eps", eps, flush=True)
+    pb = gpu.BemProblem(q, k0, eps, order=20, depth=3, order32=0, tol32=1e-5)
+    x = complex_normal((n, 6), seed_for(1, "a"))
+    r32 = pb.apply32(torch.from_numpy(x.astype(np.complex64)).cuda()).cpu().numpy()[0].astype(np.complex128)
+    # the same application from the FP32 plans' separate products
+    nrm = q["normals"]
+    phi, psi = x[:, :3], x[:, 3:]
+    tphi = phi + ((1 - eps) / eps) * nrm * np.sum(nrm * phi, axis=1, keepdims=True)
+    c64 = lambda v: torch.from_numpy(np.ascontiguousarray(v).astype(np.complex64)).cuda()
+    y0 = pb.p0_32.matvec(c64(phi), c64(-psi)).cpu().numpy().astype(np.complex128)
+    y1 = pb.p1_32.matvec(c64(tphi), c64(-psi)).cpu().numpy().astype(np.complex128)
+    sep = np.concatenate([0.5 * phi + y0, 0.5 * tphi - y1], axis=1)
+    e_sep = _rel(r32, sep)
+    ob = OracleBem(q, k0, eps)
+    e_or = _rel(r32, ob.apply(x))
+    print("bem_apply32 eps %s: vs separate FP32 products %.2e, vs oracle %.2e, k1 plan far_lmin %d" % (
+        eps, e_sep, e_or, pb.p1_32.info()["far_lmin"]), flush=True)
+    assert e_sep <= 2e-6
+    assert e_or <= 2e-4
+    pb.close()
+
+
 def test_fp64_solve_matches_oracle_solve(gpu, small):
     q, ob = small
     print("fp64 solve small sphere", flush=True)
