@@ -825,6 +825,9 @@ int hf_order(double kabs, double side, double tol) {
     return (int)std::ceil(std::max(pe, pf));
 }
 
+// per-pair scratch of the pipeline: right-hand sides beyond what fits run in slices
+constexpr size_t HF_PIPE_BYTES = (size_t)2 << 30;
+
 // translation sets whose order exceeds this run as the three-launch pipeline;
 // M2L at orders up to HFW_PMAX runs one source per wavefront
 constexpr int HF_PIPE_P = 20;
@@ -1023,13 +1026,16 @@ void build_hf(Plan &P, hipStream_t s) {
         }
     }
     if (need) P.hscratch.alloc(need);
-    // per-pair vectors of the pipelined translation sets
+    // per-pair vectors of the pipelined translation sets: room for as many right-hand sides as fit
+    // HF_PIPE_BYTES (at least one); wider batches run the pipeline over slices of them
     size_t xneed = 0;
     for (int l = lmin; l <= L; ++l) {
         const Level &V = P.lv[l];
         auto use = [&](int64_t npairs, int ps, int pd) {
-            if (std::max(ps, pd) > HF_PIPE_P)
-                xneed = std::max(xneed, (size_t)(npairs * P.nrhs_max * 3 * (int64_t)std::max(ps * ps, pd * pd)) * cs);
+            if (std::max(ps, pd) <= HF_PIPE_P) return;
+            const size_t per = (size_t)(npairs * 3 * (int64_t)std::max(ps * ps, pd * pd)) * cs;
+            const int64_t rc = std::max<int64_t>(1, std::min<int64_t>(P.nrhs_max, (int64_t)(HF_PIPE_BYTES / per)));
+            xneed = std::max(xneed, per * (size_t)rc);
         };
         use(V.nff, V.p, V.p);
         if (l < L) use(P.lv[l + 1].nbox, P.lv[l + 1].p, V.p);
@@ -1056,18 +1062,31 @@ void hf_pipe(Plan &P, int nrhs, hipStream_t s, int64_t npairs, const int32_t *sr
     if (Vs.hnck_max > HF_CHUNK_MAX || Vd.hnck_max > HF_CHUNK_MAX || mck_max > HF_CHUNK_MAX)
         throw Status{FMB_EINVAL, "translation chunk larger than the kernels hold"};
     cx<T> *X1 = P.hX1.as<cx<T>>(), *X2 = P.hX2.as<cx<T>>();
-    k_hf_fwd<T><<<dim3((unsigned)npairs, (unsigned)nrhs, (unsigned)Vs.hnnck), HTPB,
-                  3 * (size_t)Vs.hnck_max * sizeof(cx<T>), s>>>(src_idx, dir, dir_add, dinfo, W, wsz, ph, phs,
-                                                                Vs.hnck.as<int32_t>(), ps, P.nrhs_max, nrhs, S, X1);
-    FMB_LAUNCH_CHECK();
-    k_hf_coax<T><<<dim3((unsigned)npairs, (unsigned)nrhs, (unsigned)nmck), HTPB, 3 * (size_t)mck_max * sizeof(cx<T>),
-                   s>>>(dir, dir_add, dinfo, C, csz, mck.as<int32_t>(), ps, pd, nrhs, X1, X2);
-    FMB_LAUNCH_CHECK();
-    k_hf_back<T><<<dim3((unsigned)ndst, (unsigned)nrhs, (unsigned)Vd.hnnck), HTPB,
-                   3 * (size_t)Vd.hnck_max * sizeof(cx<T>), s>>>(dst_ofs, dir, dir_add, dinfo, W, wsz, ph, phs,
-                                                                 Vd.hnck.as<int32_t>(), pd, P.nrhs_max, nrhs,
-                                                                 accumulate, X2, D);
-    FMB_LAUNCH_CHECK();
+    // right-hand sides per slice: what the scratch holds for this set
+    const size_t per = (size_t)npairs * 3 * (size_t)std::max(ps * ps, pd * pd) * sizeof(cx<T>);
+    const int rc = (int)std::max<size_t>(1, std::min<size_t>((size_t)nrhs, std::min(P.hX1.bytes, P.hX2.bytes) / per));
+    if ((size_t)rc * per > std::min(P.hX1.bytes, P.hX2.bytes))
+        throw Status{FMB_EINVAL, "pipeline scratch smaller than one right-hand side"};
+    const int64_t S2 = (int64_t)ps * ps, D2 = (int64_t)pd * pd;
+    for (int r0 = 0; r0 < nrhs; r0 += rc) {
+        const int nr = std::min(rc, nrhs - r0);
+        // right-hand side r0 of every box starts r0 * 3 p^2 into the box's block
+        const cx<T> *Sr = S + (int64_t)r0 * 3 * S2;
+        cx<T> *Dr = D + (int64_t)r0 * 3 * D2;
+        k_hf_fwd<T><<<dim3((unsigned)npairs, (unsigned)nr, (unsigned)Vs.hnnck), HTPB,
+                      3 * (size_t)Vs.hnck_max * sizeof(cx<T>), s>>>(src_idx, dir, dir_add, dinfo, W, wsz, ph, phs,
+                                                                    Vs.hnck.as<int32_t>(), ps, P.nrhs_max, nr, Sr, X1);
+        FMB_LAUNCH_CHECK();
+        k_hf_coax<T><<<dim3((unsigned)npairs, (unsigned)nr, (unsigned)nmck), HTPB,
+                       3 * (size_t)mck_max * sizeof(cx<T>), s>>>(dir, dir_add, dinfo, C, csz, mck.as<int32_t>(), ps,
+                                                                  pd, nr, X1, X2);
+        FMB_LAUNCH_CHECK();
+        k_hf_back<T><<<dim3((unsigned)ndst, (unsigned)nr, (unsigned)Vd.hnnck), HTPB,
+                       3 * (size_t)Vd.hnck_max * sizeof(cx<T>), s>>>(dst_ofs, dir, dir_add, dinfo, W, wsz, ph, phs,
+                                                                     Vd.hnck.as<int32_t>(), pd, P.nrhs_max, nr,
+                                                                     accumulate, X2, Dr);
+        FMB_LAUNCH_CHECK();
+    }
 }
 
 template <typename T>
