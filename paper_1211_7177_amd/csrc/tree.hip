@@ -360,13 +360,6 @@ __global__ void k_gather_nodes(const double *__restrict__ pts, const double *__r
     stri[i] = tri[u];
 }
 
-__global__ void k_dup_check(const double *__restrict__ spts, int64_t n, int32_t *__restrict__ flag) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i == 0 || i >= n) return;
-    if (spts[3 * i] == spts[3 * i - 3] && spts[3 * i + 1] == spts[3 * i - 2] && spts[3 * i + 2] == spts[3 * i - 1])
-        atomicOr(flag, 1);
-}
-
 __global__ void k_p2p_pairs(const int32_t *__restrict__ start, const int32_t *__restrict__ nbr, int64_t nbox,
                             unsigned long long *__restrict__ total) {
     int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -645,15 +638,7 @@ void gather_nodes(Plan &P, const double *d_pts, const double *d_nrm, const doubl
                                                 P.snrm.as<double>(), P.sw.as<double>(), P.stri.as<int32_t>(),
                                                 P.iperm.as<int32_t>());
     FMB_LAUNCH_CHECK();
-    DevBuf flag;
-    flag.alloc(sizeof(int32_t));
-    FMB_CHECK_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
-    k_dup_check<<<grid_for(n), TPB, 0, s>>>(P.spts.as<double>(), n, flag.as<int32_t>());
-    FMB_LAUNCH_CHECK();
-    int32_t h = 0;
-    FMB_CHECK_HIP(hipMemcpyAsync(&h, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    FMB_CHECK_HIP(hipStreamSynchronize(s));
-    FMB_REQUIRE(h == 0, "two nodes have identical coordinates");
+    // coincident nodes are refused on the host before the plan is built (a full sort of the coordinates)
 }
 
 }  // namespace fmb
