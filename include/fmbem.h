@@ -444,6 +444,53 @@ int bem_far_field_adjoint(fmb_problem_t pb, const void *G, int32_t nrhs, const d
 int bem_field_fmm(fmb_problem_t pb, const void *x, int32_t nrhs, const double *points, int64_t nt, int32_t region,
                   int32_t order, void *E, void *stream);
 
+/*
+ * bem_shape_pairs: derivatives of one wavenumber's point sum with respect to
+ * the nodes, the part of a shape gradient (eq. 4.2 differentiated through the
+ * system of eqs. 2.8 and 2.12) that couples distinct triangles.  For fixed
+ * densities (a, b) and adjoint weights lam, the bilinear form
+ *   B = sum_alpha conj(lam_alpha) . PS_k(a, b)_alpha
+ * of the point sum PS_k (fmm_matvec's operator without the self-triangle
+ * blocks, pairs inside one triangle excluded) is differentiated with respect
+ * to every node's position, normal and weight; a node's position derivative
+ * sums its source and target roles.  With u = conj(lam_alpha), d = s_beta - s_alpha,
+ * g of eq. 2.4, grad'g = f d, f = (ikR - 1) g / R^2, f'/R = (3 - 3ikR - k^2 R^2) g / R^4,
+ * c = (u . n_beta) a_beta - (u . a_beta) n_beta - (n_beta . a_beta) u, e = u . b_beta:
+ *   ds[beta]  = sum_alpha w_beta [ f c + ((f'/R)(d . c) + f e) d ] - sum_gamma (the same with beta as target)
+ *   dn[beta]  = sum_alpha w_beta f [ (d . a_beta) u - (u . a_beta) d - (d . u) a_beta ]
+ *   dw[beta]  = sum_alpha [ f (d . c) + g e ]
+ * (holomorphic derivatives of the complex B; a real functional takes Re).
+ *   points, normals  device f64[n][3];  weights device f64[n];  point_tri device i32[n]
+ *                    (triangle of each node; values are compared, not indexed)
+ *   lam, a, b        device c128[n][3], user node order
+ *   ds, dn           device c128[n][3], written;  dw device c128[n], written
+ * Direct FP64 sums, two passes of n^2 pairs; asynchronous on `stream`.  A pair
+ * of nodes of different triangles at the same position contributes nothing.
+ * FMB_EINVAL for n < 1, a NULL pointer, k_im < 0 or an output aliasing an input.
+ */
+int bem_shape_pairs(const double *points, const double *normals, const double *weights, const int32_t *point_tri,
+                    int64_t n, double k_re, double k_im, const void *lam, const void *a, const void *b, void *ds,
+                    void *dn, void *dw, void *stream);
+
+/*
+ * bem_self_blocks: the self-triangle correction blocks of Appendix B for a
+ * given geometry, as fmm_plan builds them (mode FMB_CORR_MEAN or
+ * FMB_CORR_LINEAR), without a plan: the local part of a shape gradient
+ * differentiates them numerically.  Node alpha's row gets, for the j-th node
+ * beta of its triangle (the triangle's nodes in ascending index order),
+ *   y_alpha += n_beta (dV . a_beta) - (n_beta . dV) a_beta - dV (n_beta . a_beta) + dG b_beta,
+ *   dV = dv[alpha][j] (c128[3]),  dG = dg[alpha][j].
+ *   points, normals  host f64[n][3] (unit normals);  point_tri host i32[n] in [0, ntri)
+ *   tri_vertices     host f64[ntri][3][3];  every triangle holds n / ntri in {1, 3} nodes
+ *   dv               device c128[n][m][3], dg device c128[n][m], m = n / ntri, written
+ * Allocates temporary device memory; synchronous.  FMB_EINVAL for bad sizes,
+ * non-finite input, non-unit normals, out-of-range point_tri, a triangle not
+ * holding exactly m nodes, or LINEAR with m = 1.
+ */
+int bem_self_blocks(const double *points, const double *normals, const int32_t *point_tri, const double *tri_vertices,
+                    int64_t n, int64_t ntri, int32_t mode, double k_re, double k_im, void *dv, void *dg,
+                    void *stream);
+
 int bem_problem_destroy(fmb_problem_t pb);
 
 /* Thread-local message for the last non-zero status returned on this thread. */

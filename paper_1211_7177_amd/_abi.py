@@ -59,7 +59,7 @@ class GmresInfo(ctypes.Structure):
 EXPORTS = [
     "fmb_plan_opts_default", "fmm_plan", "fmm_matvec", "fmm_matvec_adjoint", "fmm_plan_info",
     "fmm_plan_export_tree", "fmm_plan_destroy", "fmm_plan_profile", "fmm_plan_profile_read", "fmb_gmres_opts_default", "bem_problem_create", "bem_problem_create_multi", "bem_problem_create_ibc", "bem_problem_use_graphs", "bem_apply", "bem_apply32", "bem_apply_adjoint",
-    "bem_precond_apply", "bem_rhs_planewave", "bem_field", "bem_field_noalloc", "bem_field_fmm", "bem_far_field_adjoint", "gmres_solve", "gmres_solve_group", "bem_problem_destroy", "fmb_last_error",
+    "bem_precond_apply", "bem_rhs_planewave", "bem_field", "bem_field_noalloc", "bem_field_fmm", "bem_far_field_adjoint", "bem_shape_pairs", "bem_self_blocks", "gmres_solve", "gmres_solve_group", "bem_problem_destroy", "fmb_last_error",
 ]
 
 _lib = None
@@ -102,6 +102,8 @@ def load():
         "bem_field_noalloc": [vp, vp, i32, vp, ctypes.c_int64, i32, i32, vp, vp],
         "bem_field_fmm": [vp, vp, i32, vp, ctypes.c_int64, i32, i32, vp, vp],
         "bem_far_field_adjoint": [vp, vp, i32, vp, ctypes.c_int64, vp, vp],
+        "bem_shape_pairs": [vp, vp, vp, vp, i64, f64, f64, vp, vp, vp, vp, vp, vp, vp],
+        "bem_self_blocks": [vp, vp, vp, vp, i64, i64, i32, f64, f64, vp, vp, vp],
         "bem_problem_destroy": [vp],
     }
     for name, args in sig.items():
@@ -135,6 +137,44 @@ def _dev(t, dtype, shape_tail, name):
     if tuple(t.shape[-len(shape_tail):]) != tuple(shape_tail):
         raise ValueError("%s has shape %s, expected [..., %s]" % (name, tuple(t.shape), shape_tail))
     return ctypes.c_void_p(t.data_ptr())
+
+
+def shape_pairs(points, normals, weights, point_tri, k, lam, a, b):
+    """(ds, dn, dw): derivatives of B = sum conj(lam) . PS_k(a, b) with respect to
+    the node positions, normals and weights (`bem_shape_pairs`).  points,
+    normals f64 [n, 3], weights f64 [n], point_tri i32 [n], lam, a, b c128
+    [n, 3], all on the GPU; returns c128 [n, 3], [n, 3], [n]."""
+    lib = load()
+    n = points.shape[0]
+    args = [_dev(points, torch.float64, (n, 3), "points"), _dev(normals, torch.float64, (n, 3), "normals"),
+            _dev(weights, torch.float64, (n,), "weights"), _dev(point_tri, torch.int32, (n,), "point_tri")]
+    args += [_dev(t, torch.complex128, (n, 3), nm) for t, nm in ((lam, "lam"), (a, "a"), (b, "b"))]
+    ds = torch.empty((n, 3), dtype=torch.complex128, device=points.device)
+    dn = torch.empty_like(ds)
+    dw = torch.empty((n,), dtype=torch.complex128, device=points.device)
+    k = complex(k)
+    check(lib.bem_shape_pairs(*args[:4], n, k.real, k.imag, *args[4:], ctypes.c_void_p(ds.data_ptr()),
+                              ctypes.c_void_p(dn.data_ptr()), ctypes.c_void_p(dw.data_ptr()), _stream()))
+    return ds, dn, dw
+
+
+def self_blocks(points, normals, point_tri, tri_vertices, k, mode="linear", device="cuda"):
+    """(dV c128 [n, m, 3], dG c128 [n, m]) on the GPU: the self-triangle blocks of
+    the given geometry (`bem_self_blocks`; host inputs, m = n / ntri)."""
+    lib = load()
+    pts = _host(points, np.float64)
+    nrm = _host(normals, np.float64)
+    pt = _host(point_tri, np.int32)
+    tv = _host(tri_vertices, np.float64)
+    n, ntri = pts.shape[0], tv.shape[0]
+    m = n // ntri
+    dv = torch.empty((n, m, 3), dtype=torch.complex128, device=device)
+    dg = torch.empty((n, m), dtype=torch.complex128, device=device)
+    k = complex(k)
+    check(lib.bem_self_blocks(pts.ctypes.data, nrm.ctypes.data, pt.ctypes.data, tv.ctypes.data, n, ntri,
+                              CORR[mode] if isinstance(mode, str) else int(mode), k.real, k.imag,
+                              ctypes.c_void_p(dv.data_ptr()), ctypes.c_void_p(dg.data_ptr()), _stream()))
+    return dv, dg
 
 
 class Plan:

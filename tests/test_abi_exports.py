@@ -67,6 +67,28 @@ def test_host_validation_without_gpu():
     r = lib.fmm_plan(pts3.ctypes.data, nrm.ctypes.data, w.ctypes.data, 10, 1.0, 0.0, 8, None, None, ctypes.byref(h))
     assert r == _abi.FMB_EINVAL and b"duplicate points 2 and 7" in lib.fmb_last_error()
 
+    # shape-derivative entry points: every check happens on the host
+    assert lib.bem_shape_pairs(None, None, None, None, 10, 1.0, 0.0, None, None, None, None, None, None,
+                               None) == _abi.FMB_EINVAL
+    assert b"pointer" in lib.fmb_last_error()
+    out, out2 = ctypes.c_void_p(16), ctypes.c_void_p(32)
+    ids, tv10 = np.arange(10, dtype=np.int32), np.zeros((10, 3, 3))
+    for n_, ntri_, mode, want in ((10, 5, 2, b"1 or 3 nodes"), (10, 10, 2, b"3 nodes per triangle"),
+                                  (10, 10, 7, b"mode")):
+        r = lib.bem_self_blocks(pts.ctypes.data, nrm.ctypes.data, ids.ctypes.data, tv10.ctypes.data, n_, ntri_,
+                                mode, 1.0, 0.0, out, out2, None)
+        assert r == _abi.FMB_EINVAL and want in lib.fmb_last_error(), lib.fmb_last_error()
+    pts9, bad9, nrm9, tv3 = pts[:9].copy(), bad[:9].copy(), nrm[:9].copy(), np.zeros((3, 3, 3))
+    tri9 = np.arange(9, dtype=np.int32) // 3
+    r = lib.bem_self_blocks(pts9.ctypes.data, bad9.ctypes.data, tri9.ctypes.data, tv3.ctypes.data, 9, 3, 2, 1.0,
+                            0.0, out, out2, None)
+    assert r == _abi.FMB_EINVAL and b"unit" in lib.fmb_last_error()
+    badtri = tri9.copy()
+    badtri[4] = 3
+    r = lib.bem_self_blocks(pts9.ctypes.data, nrm9.ctypes.data, badtri.ctypes.data, tv3.ctypes.data, 9, 3, 2, 1.0,
+                            0.0, out, out2, None)
+    assert r == _abi.FMB_EINVAL and b"point_tri" in lib.fmb_last_error()
+
 
 def test_solver_option_mapping():
     """The Python solve options reach the C struct: mixed False/True/"nested" as 0/1/2."""
