@@ -198,12 +198,23 @@ def _surface_explicit(k0, x, d, pol, s, n, w):
 
 def cross_section_and_vertex_gradient(vertices, triangles, k0, eps, d, pol, order=16, depth=0, tol=1e-10,
                                       restart=150, mu=1.0, functional="far", order32=None, solve_kw=None,
-                                      fd_rel=1e-5, plan_tol=0.0):
+                                      fd_rel=1e-5, plan_tol=0.0, stats=None):
     """(C_sca, dC/dv f64[nv, 3], dC/d(delta_v) f64[nv]) for one scatterer of
     permittivity eps under the plane wave pol exp(i k0 d . s), delta_v being the
     displacement of vertex v along its vertex normal.  functional: "far"
     (oint |F|^2 dOmega) or "surface" (eq. 4.2 on the scatterer's surface).
-    order / plan_tol / order32 / solve_kw as for `BemProblem` and its solve."""
+    order / plan_tol / order32 / solve_kw as for `BemProblem` and its solve.
+    stats: a dict to receive the seconds of each phase (device-synchronised)
+    and the solves' iteration counts."""
+    import time
+
+    def mark(key, t0):
+        if stats is not None:
+            torch.cuda.synchronize()
+            stats[key] = time.perf_counter() - t0
+        return time.perf_counter()
+
+    t0 = time.perf_counter()
     V = np.ascontiguousarray(vertices, dtype=np.float64)
     F = np.ascontiguousarray(triangles, dtype=np.int64)
     q = nodes_of_mesh(V, F)
@@ -213,11 +224,18 @@ def cross_section_and_vertex_gradient(vertices, triangles, k0, eps, d, pol, orde
     kw = dict(tol=tol, restart=restart, maxit=4000)
     kw.update(solve_kw or {})
     try:
-        xd, _ = pb.solve(pb.rhs_planewave(d, pol), **kw)
+        t0 = mark("setup_s", t0)
+        xd, inf = pb.solve(pb.rhs_planewave(d, pol), **kw)
+        t0 = mark("solve_s", t0)
         xg = xd.clone().requires_grad_(True)
         C = _functional(functional, pb, q, k0, xg, d, pol)
         g = torch.autograd.grad(C, xg)[0]
-        lam, _ = pb.solve(g.contiguous(), adjoint=True, **kw)
+        t0 = mark("functional_s", t0)
+        lam, inf_adj = pb.solve(g.contiguous(), adjoint=True, **kw)
+        t0 = mark("adjoint_solve_s", t0)
+        if stats is not None:
+            stats["iterations"] = inf["iterations"]
+            stats["adjoint_iterations"] = inf_adj["iterations"]
         x, lam = xd[0], lam[0]
         phi, psi = x[:, 0:3].contiguous(), x[:, 3:6].contiguous()
         lam0, lam1 = lam[:, 0:3].contiguous(), lam[:, 3:6].contiguous()
@@ -225,6 +243,7 @@ def cross_section_and_vertex_gradient(vertices, triangles, k0, eps, d, pol, orde
         k1, gamma = pb.k1, pb.mu
     finally:
         pb.close()
+    t0 = mark("adjoint_product_s", t0)
     dev = x.device
     Vt = torch.from_numpy(V).to(dev).requires_grad_(True)
     Ft = torch.from_numpy(F).to(dev)
@@ -236,6 +255,7 @@ def cross_section_and_vertex_gradient(vertices, triangles, k0, eps, d, pol, orde
     # point sums: sum conj(lam) . A x holds +B_k0(lam0; Phi, -Psi) - B_k1(lam1; T Phi, -gamma Psi)
     ds0, dn0, dw0 = shape_pairs(s0, n0, w0, tri, k0, lam0, phi, b0)
     ds1, dn1, dw1 = shape_pairs(s0, n0, w0, tri, k1, lam1, tphi, b1)
+    t0 = mark("pairs_s", t0)
     GS = -(ds0 - ds1).real
     GN = -(dn0 - dn1).real
     GW = -(dw0 - dw1).real
@@ -258,6 +278,8 @@ def cross_section_and_vertex_gradient(vertices, triangles, k0, eps, d, pol, orde
     GS, GN = GS + ls, GN + ln
     # carry the node derivatives to the vertices
     gV = torch.autograd.grad(torch.sum(GS * s) + torch.sum(GN * n) + torch.sum(GW * w), Vt)[0].cpu().numpy()
+    t0 = mark("explicit_s", t0)
     # self-triangle blocks: -Re d/dv [ S_k0(lam0; Phi, -Psi) - S_k1(lam1; T Phi, -gamma Psi) ]
     gV -= self_triangle_vertex_derivative(V, F, [(k0, 1.0, lam0, phi, b0), (k1, -1.0, lam1, tphi, b1)], fd_rel)
+    mark("self_blocks_s", t0)
     return float(C.item()), gV, np.sum(gV * vertex_normals(V, F), axis=1)
