@@ -67,7 +67,7 @@ def parse():
                     "(the configuration's 64: about 200 GB and many minutes for the sphere)")
     ap.add_argument("--c3-fp64-rhs", type=int, default=2, help="waves per mesh of the plain FP64 comparison")
     ap.add_argument("--split-ring", action="store_true",
-                    help="also run the split-ring solves and product rates (49k triangles)")
+                    help="also run the split-ring solves, product rates and vertex gradient (49k triangles)")
     ap.add_argument("--translate32", choices=["fp32", "bf16x3"], default="bf16x3")
     ap.add_argument("--batch", type=int, default=8,
                     help="also time one lockstep solve of this many plane waves (0: skip)")
@@ -154,8 +154,9 @@ def measured_traffic(kernel):
 def split_ring_section(log):
     """The split-ring workload (square ring, side 1, width 0.2, thickness 0.1, gap 0.2; eps = -15 + 1i,
     k0 = pi/2, wave along +z polarised across the gap): a nested solve, a plain FP64 solve and a nested adjoint
-    solve to 1e-8 (restart 400), and the forward and adjoint FMM product rates of its k0 plans.  Runs after the
-    timed solves of the main workload, outside their timed region."""
+    solve to 1e-8 (restart 400), the forward and adjoint FMM product rates of its k0 plans, and the gradient of
+    the far-field C_sca at every vertex.  Runs after the timed solves of the main workload, outside their timed
+    region."""
     import torch
     from synthetic import config_mesh, nystrom3
     from paper_1211_7177_amd.solver import BemProblem
@@ -195,6 +196,22 @@ def split_ring_section(log):
         rates[tag] = {"matvecs_per_s": 10 / (t1 - t0), "adjoint_matvecs_per_s": 10 / (time.perf_counter() - t1)}
     out["fmm_k0_plan"] = rates
     pb.close()
+    # dC_sca/dv at every vertex (far-field form): one forward and one adjoint solve (nested, 1e-12), the
+    # point-sum derivative passes at k0 and k1, the explicit terms and the self-triangle block differences
+    from paper_1211_7177_amd.shape import cross_section_and_vertex_gradient
+    stats = {}
+    t0 = time.perf_counter()
+    C, gV, _ = cross_section_and_vertex_gradient(mesh.vertices, mesh.triangles, np.pi / 2, complex(-15.0, 1.0),
+                                                 [0.0, 0.0, 1.0], [0.0, 1.0, 0.0], order=16, order32=5, tol=1e-12,
+                                                 restart=400, functional="far", solve_kw=nested, stats=stats)
+    dt = time.perf_counter() - t0
+    out["vertex_gradient"] = {
+        "vertices": int(len(mesh.vertices)), "C_sca_far": C, "s": dt, "phases_s": stats,
+        "translation_residual": float(np.linalg.norm(gV.sum(axis=0)) / np.abs(gV).sum()),
+        # two passes (target role, source role) over all n^2 node pairs at each of k0 and k1
+        "pair_evaluations_per_s": 4.0 * n * n / stats["pairs_s"],
+    }
+    log("split ring vertex gradient", out["vertex_gradient"])
     return out
 
 

@@ -13,6 +13,7 @@ Contents (each module cites the passage of the paper it follows):
   bem.py          the 6N system for one scatterer and the block preconditioner (eqs. 2.6-2.13, 3.1-3.2)
   gmres.py        right-preconditioned flexible GMRES (Sec. 3.1)
   mie.py          Mie series for a sphere (the external check of Sec. 3.2)
+  shape.py        shape derivatives of the point sum; the two forms of C_sca (eq. 4.2)
 
 Every function is pinned by tests/test_oracle_*.py against closed forms,
 brute force, identities or textbook results.

@@ -38,6 +38,8 @@ again with lambda = A^{-H} g, so one forward and one adjoint solve serve every
 parameter; each parameter adds the central difference of b - A x and of f at
 theta +- h e_i (two problem builds and two products on the octree depth of the
 unperturbed shape, with x held fixed).
+The derivative in every mesh vertex at once, with no rebuilt problem per
+parameter, is `shape.cross_section_and_vertex_gradient`.
 """
 
 import numpy as np
