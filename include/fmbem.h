@@ -207,7 +207,12 @@ typedef struct {
     int32_t restart;     /* Krylov basis size m                                              */
     int32_t maxit;       /* total iteration cap (nested mode: outer plus inner steps, checked */
                          /*    between outer steps, so one inner cycle may run past it)      */
-    int32_t precond;     /* 0 none, 1 block A_self (6x6 per node)                            */
+    int32_t precond;     /* 0 none; 1 block A_self (6x6 per node, 3x3 for ibc), each block    */
+                         /*    inverted exactly; 2 the paper's form (Sec. 3.1): an inner     */
+                         /*    GMRES on the same block-diagonal A_self, at most 10 steps, to */
+                         /*    a relative residual of 1e-2 per right-hand side (it keeps     */
+                         /*    M = A_self and rebuilds it from the stored inverses at the    */
+                         /*    first such solve: n nu^2 more complex entries per precision)  */
     int32_t x0_given;    /* 1: x holds the initial guess on entry                            */
     int32_t mixed;       /* 1: FP32 inner solves refined by FP64 residuals (needs FP32 plans);*/
                          /* 2: nested: FP64 fGMRES preconditioned by one FP32 fGMRES cycle   */

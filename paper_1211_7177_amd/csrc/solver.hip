@@ -29,6 +29,7 @@
 // FMM products of each application run concurrently on two streams.
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -61,6 +62,11 @@ struct fmb_problem_s {
     fmb::cx<double> tcj[8] = {}, gamj[8] = {};
     fmb::DevBuf minv;          // c128[n][6][6] (c128[n][3][3] for ibc)
     fmb::DevBuf minv32;        // c64[n][6][6], FP32 copy for the inner solves (FP32 plans only)
+    // the blocks M themselves (the inverse of minv) and their FP32 copy, built at
+    // the first solve that asks for the inner-GMRES preconditioner (precond = 2),
+    // and that preconditioner's Krylov workspaces (FP64, FP32)
+    fmb::DevBuf mfwd, mfwd32;
+    std::shared_ptr<void> pg64, pg32;
     fmb::DevBuf upts;          // f64[n][3] user order
     // matvec staging [nrhs][n][3] for the two plans (FP64) and their FP32 copies
     fmb::DevBuf a0, b0, a1, b1, y0, y1;
@@ -317,6 +323,64 @@ __global__ void k_precond_apply(const cx<T> *__restrict__ minv, const cx<T> *__r
         cx<T> s = mk(T(0), T(0));
         for (int q = 0; q < 6; ++q) s += M[r * 6 + q] * in[q];
         z[i * 6 + r] = s;
+    }
+}
+
+// Inverse of every nb x nb block (nb = 3 or 6), Gauss-Jordan with partial
+// pivoting in FP64: turns the stored M^{-1} back into M for the inner GMRES.
+template <int NB>
+__global__ void k_block_invert(const cx<double> *__restrict__ in, cx<double> *__restrict__ out, int64_t n,
+                               int32_t *__restrict__ bad) {
+    int64_t a = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    cx<double> A[NB][2 * NB];
+    for (int i = 0; i < NB; ++i)
+        for (int j = 0; j < NB; ++j) {
+            A[i][j] = in[(a * NB + i) * NB + j];
+            A[i][NB + j] = mk(i == j ? 1.0 : 0.0, 0.0);
+        }
+    for (int c = 0; c < NB; ++c) {
+        int piv = c;
+        double best = abs2(A[c][c]);
+        for (int r = c + 1; r < NB; ++r)
+            if (abs2(A[r][c]) > best) {
+                best = abs2(A[r][c]);
+                piv = r;
+            }
+        if (!(best > 0.0)) {
+            atomicOr(bad, 1);
+            return;
+        }
+        if (piv != c)
+            for (int j = 0; j < 2 * NB; ++j) {
+                const cx<double> t = A[c][j];
+                A[c][j] = A[piv][j];
+                A[piv][j] = t;
+            }
+        const cx<double> inv = cdiv(mk(1.0, 0.0), A[c][c]);
+        for (int j = 0; j < 2 * NB; ++j) A[c][j] = A[c][j] * inv;
+        for (int r = 0; r < NB; ++r) {
+            if (r == c) continue;
+            const cx<double> f = A[r][c];
+            for (int j = 0; j < 2 * NB; ++j) A[r][j] -= f * A[c][j];
+        }
+    }
+    for (int i = 0; i < NB; ++i)
+        for (int j = 0; j < NB; ++j) out[(a * NB + i) * NB + j] = A[i][NB + j];
+}
+
+// out = M v per node (herm = 1: M^H v) for [nrhs][n][nb] vectors
+template <typename T>
+__global__ void k_block_mul(const cx<T> *__restrict__ blk, int nb, int herm, const cx<T> *__restrict__ v,
+                            cx<T> *__restrict__ out, int64_t n, int nrhs) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n * nrhs) return;
+    const cx<T> *M = blk + (i % n) * nb * nb;
+    const cx<T> *vi = v + i * nb;
+    for (int r = 0; r < nb; ++r) {
+        cx<T> acc = mk(T(0), T(0));
+        for (int q = 0; q < nb; ++q) acc += (herm ? conj(M[q * nb + r]) : M[r * nb + q]) * vi[q];
+        out[i * nb + r] = acc;
     }
 }
 
@@ -1380,6 +1444,156 @@ static void precond_t(fmb_problem_s &pb, const cx<T> *v, cx<T> *z, int nrhs, hip
     FMB_LAUNCH_CHECK();
 }
 
+// The preconditioner in the paper's form (Sec. 3.1): z ~ M^{-1} v (M^{-H} v in
+// adjoint mode) by an inner GMRES on the block-diagonal M = A_self, at most
+// PG_MAXIT steps, each right-hand side stopping at the first step whose residual
+// estimate is at most PG_TOL |v|.  Classical Gram-Schmidt applied twice; the small
+// least-squares problems (Givens rotations, back substitution) are solved on the
+// host, with one synchronisation per step.  fGMRES keeps every z, so the inexact
+// inner solve is allowed to change from step to step.
+constexpr int PG_MAXIT = 10;
+constexpr double PG_TOL = 1e-2;
+
+// M (and its FP32 copy when the problem has FP32 plans), from the stored inverses
+static void ensure_forward_blocks(fmb_problem_s &pb, hipStream_t s) {
+    if (pb.mfwd.p) return;
+    const int nb = pb.nu;
+    const int64_t cnt = pb.n * nb * nb;
+    pb.mfwd.alloc((size_t)cnt * sizeof(cx<double>));
+    DevBuf bad;
+    bad.alloc(sizeof(int32_t));
+    FMB_CHECK_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+    if (nb == 6)
+        k_block_invert<6><<<gridn(pb.n), TPB, 0, s>>>(pb.minv.as<cx<double>>(), pb.mfwd.as<cx<double>>(), pb.n,
+                                                      bad.as<int32_t>());
+    else
+        k_block_invert<3><<<gridn(pb.n), TPB, 0, s>>>(pb.minv.as<cx<double>>(), pb.mfwd.as<cx<double>>(), pb.n,
+                                                      bad.as<int32_t>());
+    FMB_LAUNCH_CHECK();
+    if (pb.minv32.p) {
+        pb.mfwd32.alloc((size_t)cnt * sizeof(cx<float>));
+        k_to32<<<gridn(cnt), TPB, 0, s>>>(pb.mfwd.as<cx<double>>(), pb.mfwd32.as<cx<float>>(), cnt);
+        FMB_LAUNCH_CHECK();
+    }
+    int32_t hb = 0;
+    FMB_CHECK_HIP(hipMemcpyAsync(&hb, bad.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    FMB_CHECK_HIP(hipStreamSynchronize(s));
+    if (hb) {
+        pb.mfwd.release();
+        pb.mfwd32.release();
+        throw Status{FMB_EINVAL, "a preconditioner block is singular"};
+    }
+}
+
+template <typename T>
+static Krylov<T> &pg_workspace(fmb_problem_s &pb) {
+    std::shared_ptr<void> &slot = sizeof(T) == sizeof(float) ? pb.pg32 : pb.pg64;
+    if (!slot) slot = std::shared_ptr<void>(new Krylov<T>(), [](void *p) { delete static_cast<Krylov<T> *>(p); });
+    return *static_cast<Krylov<T> *>(slot.get());
+}
+
+template <typename T>
+static void precond_gmres(fmb_problem_s &pb, const cx<T> *v, cx<T> *z, int nrhs, hipStream_t s) {
+    const bool f32 = sizeof(T) == sizeof(float);
+    const int nb = pb.nu, m = PG_MAXIT;
+    const int64_t len = pb.n * nb, tot = len * nrhs;
+    const cx<T> *blk = (f32 ? pb.mfwd32 : pb.mfwd).template as<cx<T>>();
+    FMB_REQUIRE(blk != nullptr, "the inner-GMRES preconditioner's blocks were not built");
+    Krylov<T> &K = pg_workspace<T>(pb);
+    krylov_alloc(K, len, nrhs, m);
+    cx<T> *U = K.V.template as<cx<T>>(), *W = K.W.template as<cx<T>>();
+    int32_t *act = K.act.template as<int32_t>();
+    double *hn = K.hn.template as<double>(), *hninv = K.hninv.template as<double>();
+    cx<double> *h = K.h.template as<cx<double>>(), *h2 = K.h2.template as<cx<double>>();
+    std::vector<int32_t> on(nrhs, 1);
+    FMB_CHECK_HIP(hipMemcpyAsync(act, on.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    norms(K, v, hn, hninv, s);
+    k_scale_into<T><<<gridn(tot), TPB, 0, s>>>(v, hninv, U, len, nrhs, act);
+    FMB_LAUNCH_CHECK();
+    std::vector<double> beta(nrhs), hnh(nrhs), cs((size_t)nrhs * m, 1.0);
+    std::vector<cx<double>> sn((size_t)nrhs * m, mk(0.0, 0.0)), Rm((size_t)nrhs * m * m, mk(0.0, 0.0)),
+        g((size_t)nrhs * (m + 1), mk(0.0, 0.0)), hh((size_t)(m + 1) * nrhs), hh2((size_t)(m + 1) * nrhs);
+    std::vector<int> kr(nrhs, -1);
+    FMB_CHECK_HIP(hipMemcpyAsync(beta.data(), hn, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    FMB_CHECK_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < nrhs; ++r) {
+        g[(size_t)r * (m + 1)] = mk(beta[r], 0.0);
+        if (!(beta[r] > 0.0)) kr[r] = 0;
+    }
+    int steps = 0;
+    for (int j = 0; j < m; ++j) {
+        bool all = true;
+        for (int r = 0; r < nrhs; ++r) all = all && kr[r] >= 0;
+        if (all) break;
+        k_block_mul<T><<<gridn(pb.n * nrhs), TPB, 0, s>>>(blk, nb, pb.adjoint ? 1 : 0, U + (int64_t)j * tot, W, pb.n,
+                                                          nrhs);
+        FMB_LAUNCH_CHECK();
+        dots(K, (const cx<T> *)U, j + 1, (const cx<T> *)nullptr, (const cx<T> *)W, (const int32_t *)nullptr, h, s);
+        combine(K, (const cx<T> *)U, j + 1, h, -1.0, W, act, (const int32_t *)nullptr, (double *)nullptr, s);
+        dots(K, (const cx<T> *)U, j + 1, (const cx<T> *)nullptr, (const cx<T> *)W, (const int32_t *)nullptr, h2, s);
+        combine(K, (const cx<T> *)U, j + 1, h2, -1.0, W, act, (const int32_t *)nullptr, (double *)nullptr, s);
+        norms(K, W, hn, hninv, s);
+        k_scale_into<T><<<gridn(tot), TPB, 0, s>>>(W, hninv, U + (int64_t)(j + 1) * tot, len, nrhs, act);
+        FMB_LAUNCH_CHECK();
+        const size_t cnt = (size_t)(j + 1) * nrhs;
+        FMB_CHECK_HIP(hipMemcpyAsync(hh.data(), h, cnt * sizeof(cx<double>), hipMemcpyDeviceToHost, s));
+        FMB_CHECK_HIP(hipMemcpyAsync(hh2.data(), h2, cnt * sizeof(cx<double>), hipMemcpyDeviceToHost, s));
+        FMB_CHECK_HIP(hipMemcpyAsync(hnh.data(), hn, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        FMB_CHECK_HIP(hipStreamSynchronize(s));
+        steps = j + 1;
+        for (int r = 0; r < nrhs; ++r) {
+            if (kr[r] >= 0) continue;
+            std::vector<cx<double>> col(j + 2);
+            for (int i = 0; i <= j; ++i) col[i] = hh[(size_t)i * nrhs + r] + hh2[(size_t)i * nrhs + r];
+            col[j + 1] = mk(hnh[r], 0.0);
+            double *c = &cs[(size_t)r * m];
+            cx<double> *sv = &sn[(size_t)r * m], *gr = &g[(size_t)r * (m + 1)];
+            for (int i = 0; i < j; ++i) {
+                const cx<double> t = c[i] * col[i] + sv[i] * col[i + 1];
+                col[i + 1] = c[i] * col[i + 1] - conj(sv[i]) * col[i];
+                col[i] = t;
+            }
+            // rotation zeroing col[j + 1]: c = |a| / rho, s = (a / |a|) conj(b) / rho
+            const cx<double> a = col[j], b = col[j + 1];
+            const double aa = std::sqrt(abs2(a)), rho = std::sqrt(abs2(a) + abs2(b));
+            if (rho == 0.0) {
+                c[j] = 1.0;
+                sv[j] = mk(0.0, 0.0);
+            } else if (aa == 0.0) {
+                c[j] = 0.0;
+                sv[j] = mk(1.0, 0.0);
+            } else {
+                c[j] = aa / rho;
+                sv[j] = (1.0 / (aa * rho)) * (a * conj(b));
+            }
+            col[j] = c[j] * a + sv[j] * b;
+            gr[j + 1] = -(conj(sv[j]) * gr[j]);
+            gr[j] = c[j] * gr[j];
+            for (int i = 0; i <= j; ++i) Rm[((size_t)r * m + i) * m + j] = col[i];
+            if (std::sqrt(abs2(gr[j + 1])) <= PG_TOL * beta[r]) kr[r] = j + 1;
+        }
+    }
+    // y from R y = g per rhs (steps taken: kr, or all steps), z = U y
+    std::vector<cx<double>> y((size_t)(m + 1) * nrhs, mk(0.0, 0.0));
+    for (int r = 0; r < nrhs; ++r) {
+        const int k = kr[r] >= 0 ? kr[r] : steps;
+        std::vector<cx<double>> yr(k, mk(0.0, 0.0));
+        for (int i = k - 1; i >= 0; --i) {
+            cx<double> t = g[(size_t)r * (m + 1) + i];
+            for (int q = i + 1; q < k; ++q) t -= Rm[((size_t)r * m + i) * m + q] * yr[q];
+            const cx<double> d = Rm[((size_t)r * m + i) * m + i];
+            yr[i] = abs2(d) > 0.0 ? cdiv(t, d) : mk(0.0, 0.0);
+        }
+        for (int i = 0; i < k; ++i) y[(size_t)i * nrhs + r] = yr[i];
+    }
+    cx<double> *yd = K.y.template as<cx<double>>();
+    FMB_CHECK_HIP(hipMemcpyAsync(yd, y.data(), y.size() * sizeof(cx<double>), hipMemcpyHostToDevice, s));
+    FMB_CHECK_HIP(hipMemsetAsync(z, 0, tot * sizeof(cx<T>), s));
+    combine(K, (const cx<T> *)U, std::max(steps, 1), yd, 1.0, z, act, (const int32_t *)nullptr, (double *)nullptr, s);
+    // the host vectors above are read by the copies before the stream is left
+    FMB_CHECK_HIP(hipStreamSynchronize(s));
+}
+
 // One right-preconditioned fGMRES solve of A x = b, x updated in place, with
 // the FP64 operator (T = double) or the FP32 one (T = float).  Returns the
 // iteration count; relres receives |b - A x| / |b| per rhs (computed with the
@@ -1471,6 +1685,9 @@ static int fgmres(fmb_problem_s &pb, Krylov<T> &K, const cx<T> *b, cx<T> *x, boo
                 }
             }
             if (inner) {
+            } else if (precond == 2) {
+                precond_gmres<T>(pb, vj, zj, nrhs, s);       // z_j ~ M^{-1} v_j by the inner GMRES
+                bem_apply_t<T>(pb, zj, W, nrhs, s);
             } else if (precond) {
                 bem_apply_t<T>(pb, zj, W, nrhs, s, vj);      // z_j = M^{-1} v_j fused with the split
             } else {
@@ -1563,6 +1780,7 @@ static void check_solve_args(fmb_problem_s *pb, const void *rhs, const void *x, 
     FMB_REQUIRE(nrhs >= 1 && nrhs <= pb->nrhs_max, "nrhs out of range");
     FMB_REQUIRE(op.tol > 0 && op.restart >= 1 && op.maxit >= 1, "bad solver options");
     FMB_REQUIRE(op.mixed >= 0 && op.mixed <= 2, "mixed must be 0, 1 or 2");
+    FMB_REQUIRE(op.precond >= 0 && op.precond <= 2, "precond must be 0, 1 or 2");
     FMB_REQUIRE(!op.mixed || pb->p032, "mixed precision needs the FP32 plans");
 }
 
@@ -1587,6 +1805,7 @@ static int nested_fgmres(fmb_problem_s *pb, Krylov<double> &K, Krylov<float> &K3
 static bool solve_one(fmb_problem_s *pb, const void *rhs, void *x, int32_t nrhs, const fmb_gmres_opts &op,
                       fmb_gmres_info *info, hipStream_t s) {
     check_solve_args(pb, rhs, x, nrhs, op);
+    if (op.precond == 2) ensure_forward_blocks(*pb, s);
     pb->serial = op.serial != 0;
     pb->adjoint = op.adjoint != 0;
     struct ModeReset {

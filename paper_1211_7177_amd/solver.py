@@ -16,7 +16,9 @@ def _opts(lib, tol, restart, maxit, precond, mixed, inner_tol, inner_maxit, seri
     opts.tol = tol
     opts.restart = restart
     opts.maxit = maxit
-    opts.precond = 1 if precond else 0
+    # precond: False (none), True or "block" (exact 6x6 block inverse), "gmres" (the paper's inner
+    # GMRES of at most 10 steps on the same blocks)
+    opts.precond = 2 if precond == "gmres" else (1 if precond else 0)
     opts.mixed = 2 if mixed == "nested" else (1 if mixed else 0)
     opts.inner_tol = inner_tol
     opts.inner_maxit = inner_maxit

@@ -97,3 +97,5 @@ def test_solver_option_mapping():
     for mixed, code in ((False, 0), (True, 1), ("nested", 2)):
         o = solver._opts(lib, 1e-6, 50, 100, True, mixed, 1e-2, 30, False)
         assert o.mixed == code and o.restart == 50 and o.inner_maxit == 30 and o.precond == 1
+    for precond, code in ((False, 0), (True, 1), ("block", 1), ("gmres", 2)):
+        assert solver._opts(lib, 1e-6, 50, 100, precond, False, 1e-2, 30, False).precond == code

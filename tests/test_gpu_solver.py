@@ -266,18 +266,92 @@ def test_preconditioner_effect_of_the_papers_spheres(gpu):
     7040 and 28,160), restart 100, tolerance 1e-6.  At ka = 1.67 both converge,
     the preconditioned solve in under a quarter of the iterations (51 against
     387 measured); at ka = 5.57 the preconditioned solve converges (185) and the
-    unpreconditioned one does not within 1500 iterations, as the paper reports."""
+    unpreconditioned one does not within 1500 iterations, as the paper reports.
+    The paper's own form of the preconditioner (an inner GMRES of at most 10
+    steps on A_self, precond = "gmres") converges in both cases too."""
     for nu, ka, converges_without in ((19, 1.67, True), (38, 5.57, False)):
         q = nystrom3(icosphere(nu))
         pb = gpu.BemProblem(q, ka / 1.33, 1.33 ** 2, order=16)
         b = pb.rhs_planewave([0, 0, 1.0], [1.0, 0, 0])
         _, ip = pb.solve(b, tol=1e-6, restart=100, maxit=1500)
+        _, ig = pb.solve(b, tol=1e-6, restart=100, maxit=1500, precond="gmres")
         _, iu = pb.solve(b, tol=1e-6, restart=100, maxit=1500, precond=False, raise_on_noconv=False)
-        print("ka %.2f: preconditioned %d iterations, without %d (residual %.2e)" % (
-            ka, ip["iterations"], iu["iterations"], iu["residual"]), flush=True)
-        assert ip["residual"] <= 1e-6
+        print("ka %.2f: preconditioned %d iterations (inner-GMRES form %d), without %d (residual %.2e)" % (
+            ka, ip["iterations"], ig["iterations"], iu["iterations"], iu["residual"]), flush=True)
+        assert ip["residual"] <= 1e-6 and ig["residual"] <= 1e-6
+        if converges_without:
+            assert 2 * ig["iterations"] <= iu["iterations"]
         if converges_without:
             assert iu["residual"] <= 1e-6 and 4 * ip["iterations"] <= iu["iterations"]
         else:
             assert iu["residual"] > 1e-6 and iu["iterations"] >= 1500
         pb.close()
+
+
+def _oracle_inner_gmres_precond(ob, adjoint=False):
+    """The paper's preconditioner on the oracle side: GMRES on the block-diagonal
+    M = A_self (M^H for the adjoint system), at most 10 steps, to 1e-2."""
+    M = ob.precond_blocks()
+    if adjoint:
+        M = np.conj(np.transpose(M, (0, 2, 1)))
+
+    def Mop(v):
+        return np.einsum("nij,nj->ni", M, v)
+
+    def P(v):
+        return oracle_gmres(Mop, v, None, tol=1e-2, restart=10, maxit=10)[0]
+    return P
+
+
+def test_paper_form_preconditioner_matches_oracle(gpu, small):
+    """precond = "gmres" (Sec. 3.1: an inner GMRES of at most 10 steps on A_self,
+    here to 1e-2) against the oracle's fGMRES with the same inner GMRES: the same
+    solution (1e-6) and iteration count (+-3), forward and adjoint; the solution
+    equals the exact-block-inverse solve's."""
+    q, ob = small
+    print("paper-form preconditioner, small sphere", flush=True)
+    b = ob.rhs_planewave([0, 0, 1.0], [1.0, 0, 0])
+    pb = gpu.BemProblem(q, 1.0, 2.25, order=22, depth=3)
+    bg = torch.from_numpy(b).cuda().unsqueeze(0)
+    for adjoint in (False, True):
+        A = ob.apply_adjoint if adjoint else ob.apply
+        xo, io = oracle_gmres(A, b, _oracle_inner_gmres_precond(ob, adjoint), tol=1e-10, restart=100)
+        x, info = pb.solve(bg, tol=1e-10, restart=100, maxit=400, precond="gmres", adjoint=adjoint)
+        xb, ib = pb.solve(bg, tol=1e-10, restart=100, maxit=400, adjoint=adjoint)
+        x, xb = x.cpu().numpy()[0], xb.cpu().numpy()[0]
+        print("adjoint %s: gpu %d iterations, oracle %d, block inverse %d; err %.2e vs block %.2e" % (
+            adjoint, info["iterations"], io["iterations"], ib["iterations"], _rel(x, xo), _rel(x, xb)), flush=True)
+        assert info["residual"] <= 1e-10
+        assert _rel(x, xo) <= 1e-6 and _rel(x, xb) <= 1e-7
+        assert abs(info["iterations"] - io["iterations"]) <= 3
+    pb.close()
+
+
+@pytest.mark.parametrize("mixed", [True, "nested"])
+def test_paper_form_preconditioner_in_mixed_modes(gpu, small, mixed):
+    """The inner-GMRES preconditioner inside the FP32 inner solves (its FP32
+    blocks): refinement and nested mode reach the FP64 tolerance and the
+    exact-block solution."""
+    q, ob = small
+    print("paper-form preconditioner, mixed", mixed, flush=True)
+    pb = gpu.BemProblem(q, 1.0, 2.25, order=20, depth=3, order32=10)
+    b = pb.rhs_planewave([0, 0, 1.0], [1.0, 0, 0])
+    x, info = pb.solve(b, tol=1e-9, mixed=mixed, inner_tol=1e-2, precond="gmres")
+    xb, _ = pb.solve(b, tol=1e-9, mixed=mixed, inner_tol=1e-2)
+    print(info, flush=True)
+    assert info["residual"] <= 1e-9
+    assert _rel(x.cpu().numpy(), xb.cpu().numpy()) <= 1e-7
+    pb.close()
+
+
+def test_paper_form_preconditioner_impedance_problem(gpu, small):
+    """The inner GMRES on the 3x3 blocks of an impedance problem (eq. 2.25)."""
+    q, _ = small
+    pb = gpu.IbcProblem(q, 1.0, 0.05 - 0.05j, order=20, depth=3)
+    b = pb.rhs_planewave([0, 0, 1.0], [1.0, 0, 0])
+    x, info = pb.solve(b, tol=1e-10, restart=100, maxit=400, precond="gmres")
+    xb, ib = pb.solve(b, tol=1e-10, restart=100, maxit=400)
+    print("ibc: inner-GMRES form %d iterations, block inverse %d" % (info["iterations"], ib["iterations"]), flush=True)
+    assert info["residual"] <= 1e-10
+    assert _rel(x.cpu().numpy(), xb.cpu().numpy()) <= 1e-7
+    pb.close()
