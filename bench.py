@@ -66,8 +66,8 @@ def parse():
     ap.add_argument("--c3-rhs", type=int, default=4, help="plane waves per mesh of the three-mesh section "
                     "(the configuration's 64: about 200 GB and many minutes for the sphere)")
     ap.add_argument("--c3-fp64-rhs", type=int, default=2, help="waves per mesh of the plain FP64 comparison")
-    ap.add_argument("--split-ring", action="store_true",
-                    help="also run the split-ring solves, product rates and vertex gradient (49k triangles)")
+    ap.add_argument("--split-ring", action=argparse.BooleanOptionalAction, default=True,
+                    help="the split-ring solves, product rates and vertex gradient (49k triangles; about 30 s)")
     ap.add_argument("--translate32", choices=["fp32", "bf16x3"], default="bf16x3")
     ap.add_argument("--batch", type=int, default=8,
                     help="also time one lockstep solve of this many plane waves (0: skip)")

@@ -164,12 +164,19 @@ def _far_explicit(k0, x, pol, s, n, w, nt=24, nph=48, chunk=64):
     for lo in range(0, len(dirs), chunk):
         r = torch.from_numpy(dirs[lo:lo + chunk]).to(s.device)
         W = torch.from_numpy(wts[lo:lo + chunk]).to(s.device)
+        # sums over the nodes as elementwise products and reductions (a product with K = n and
+        # N = 3 runs far below the library GEMM's speed)
         ph = wl[None, :] * torch.exp(-1j * k0 * (r @ sl.T))                # [nd, n]
         nc = nl.to(torch.complex128)
-        ra = (r.to(torch.complex128) @ a.T)                                  # [nd, n]  r . a
-        nr = (r @ nl.T).to(torch.complex128)                                 # [nd, n]  n . r
+        rc = r.to(torch.complex128)
+        ra = torch.sum(rc[:, None, :] * a[None], dim=2)                      # [nd, n]  r . a
+        nr = torch.sum(r[:, None, :] * nl[None], dim=2).to(torch.complex128)  # [nd, n]  n . r
         na = torch.sum(nc * a, dim=1)                                        # [n]
-        term = (-1j * k0) * ((ph * ra) @ nc - (ph * nr) @ a - r.to(torch.complex128) * (ph @ na)[:, None]) + ph @ b
+        s1 = torch.sum((ph * ra)[:, :, None] * nc[None], dim=1)              # [nd, 3]
+        s2 = torch.sum((ph * nr)[:, :, None] * a[None], dim=1)
+        s3 = torch.sum(ph * na[None], dim=1)
+        s4 = torch.sum(ph[:, :, None] * b[None], dim=1)
+        term = (-1j * k0) * (s1 - s2 - rc * s3[:, None]) + s4
         Fk = -(1.0 / (4.0 * np.pi)) * term
         Ck = torch.sum(W[:, None] * (Fk.real ** 2 + Fk.imag ** 2)) / e0
         g = torch.autograd.grad(Ck, (sl, nl, wl))

@@ -288,3 +288,36 @@ def test_full_split_ring_vertex_gradient():
     print("  bump field (%d vertices): vertex gradient %.8e differences %.8e (two solves in %.1f s)" % (
         np.count_nonzero(fld[:, 2]), an, fd, time.perf_counter() - t0), flush=True)
     assert abs(an - fd) <= 1e-4 * np.sum(np.abs(gV * fld))
+
+
+def test_split_ring_shape_derivatives_match_oracle(ring):
+    """On the 2.4k-triangle copy (7206 nodes), at k0 and at the metal's k1: the
+    point-sum derivatives of `bem_shape_pairs` against the oracle's direct
+    formula, and the self-triangle blocks of `bem_self_blocks` against the
+    oracle's, entry by entry."""
+    from oracle.corrections import self_blocks as oracle_blocks
+    from oracle.kernel import wavenumber
+    from oracle.shape import pair_derivatives
+    from paper_1211_7177_amd import _abi
+    q = nystrom3(ring)
+    n = q["points"].shape[0]
+    lam, a, b = (complex_normal((n, 3), 300 + i) for i in range(3))
+
+    def g(x):
+        return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+    for k in (K0, wavenumber(K0, EPS)):
+        print("ring shape derivatives k=", k, flush=True)
+        got = _abi.shape_pairs(g(q["points"]), g(q["normals"]), g(q["weights"]), g(q["point_tri"]), k, g(lam),
+                               g(a), g(b))
+        ref = pair_derivatives(q["points"], q["normals"], q["weights"], q["point_tri"], k, lam, a, b)
+        for gg, r in zip(got, ref):
+            err = np.max(np.abs(gg.cpu().numpy() - r)) / np.max(np.abs(r))
+            print("  pairs max rel %.2e" % err, flush=True)
+            assert err <= 1e-12
+        dv, dg = _abi.self_blocks(q["points"], q["normals"], q["point_tri"], q["tri_vertices"], k)
+        _, rv, rg = oracle_blocks(q["points"], q["normals"], q["point_tri"], q["tri_vertices"], k)
+        ev = np.max(np.abs(dv.cpu().numpy() - rv)) / np.max(np.abs(rv))
+        eg = np.max(np.abs(dg.cpu().numpy() - rg)) / np.max(np.abs(rg))
+        print("  blocks dV %.2e dG %.2e" % (ev, eg), flush=True)
+        assert ev <= 1e-11 and eg <= 1e-11
