@@ -469,8 +469,10 @@ int bem_field_fmm(fmb_problem_t pb, const void *x, int32_t nrhs, const double *p
  *                    (triangle of each node; values are compared, not indexed)
  *   lam, a, b        device c128[n][3], user node order
  *   ds, dn           device c128[n][3], written;  dw device c128[n], written
- * Direct FP64 sums, two passes of n^2 pairs; asynchronous on `stream`.  A pair
- * of nodes of different triangles at the same position contributes nothing.
+ * Direct FP64 sums, two passes of n^2 pairs, each split over chunks of the
+ * other side whose partial sums (a temporary device buffer of at most
+ * 64 n x 10 complex) are added in a fixed order; synchronous.  A pair of nodes
+ * of different triangles at the same position contributes nothing.
  * FMB_EINVAL for n < 1, a NULL pointer, k_im < 0 or an output aliasing an input.
  */
 int bem_shape_pairs(const double *points, const double *normals, const double *weights, const int32_t *point_tri,

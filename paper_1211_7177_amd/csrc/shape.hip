@@ -13,8 +13,13 @@
 //   dB/dn_beta  = sum_alpha w_beta f [ (d . a_beta) u - (u . a_beta) d - (d . u) a_beta ]
 //   dB/dw_beta  = sum_alpha [ f (d . c) + g e ].
 // Two direct O(n^2) FP64 passes, one thread per output node and the other side
-// staged through LDS in tiles: first every node as a target (its share of
-// dB/ds), then every node as a source (dB/ds added, dB/dn, dB/dw).
+// staged through LDS in tiles: every node as a target (its share of dB/ds), and
+// every node as a source (dB/ds, dB/dn, dB/dw).  The other side is split into
+// chunks (grid.y) so that a launch holds enough wavefronts to hide the latency
+// of the per-pair sincos and exp; each chunk writes partial sums, which a last
+// pass adds in chunk order (the result does not depend on scheduling).
+#include <algorithm>
+
 #include "plan.h"
 
 namespace fmb {
@@ -22,6 +27,8 @@ namespace fmb {
 namespace {
 
 constexpr int SP_TILE = 128;
+constexpr int SP_WAVES = 8192;       // wavefronts a launch aims at (about 8 per SIMD)
+constexpr int SP_MAX_CHUNKS = 64;
 
 struct SrcTile {
     double pos[SP_TILE][3];
@@ -54,10 +61,11 @@ __global__ void __launch_bounds__(SP_TILE) k_shape_tgt(const double *__restrict_
                                                        const double *__restrict__ wts, const int32_t *__restrict__ tri,
                                                        const cx<double> *__restrict__ lam,
                                                        const cx<double> *__restrict__ a,
-                                                       const cx<double> *__restrict__ b, int64_t n, double k_re,
-                                                       double k_im, cx<double> *__restrict__ ds) {
+                                                       const cx<double> *__restrict__ b, int64_t n, int64_t chunk,
+                                                       double k_re, double k_im, cx<double> *__restrict__ ds) {
     __shared__ SrcTile S;
     const int64_t al = blockIdx.x * (int64_t)SP_TILE + threadIdx.x;
+    const int64_t lo = blockIdx.y * chunk, hi = min(n, lo + chunk);
     const bool active = al < n;
     double p[3] = {0, 0, 0};
     cx<double> u[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
@@ -70,8 +78,8 @@ __global__ void __launch_bounds__(SP_TILE) k_shape_tgt(const double *__restrict_
         ta = tri[al];
     }
     cx<double> acc[3] = {mk(0.0, 0.0), mk(0.0, 0.0), mk(0.0, 0.0)};
-    for (int64_t base = 0; base < n; base += SP_TILE) {
-        const int cnt = (int)min((int64_t)SP_TILE, n - base);
+    for (int64_t base = lo; base < hi; base += SP_TILE) {
+        const int cnt = (int)min((int64_t)SP_TILE, hi - base);
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
             const int j = threadIdx.x;
@@ -109,7 +117,8 @@ __global__ void __launch_bounds__(SP_TILE) k_shape_tgt(const double *__restrict_
         }
     }
     if (!active) return;
-    for (int q = 0; q < 3; ++q) ds[3 * al + q] = acc[q];
+    cx<double> *o = ds + 3 * ((int64_t)blockIdx.y * n + al);
+    for (int q = 0; q < 3; ++q) o[q] = acc[q];
 }
 
 // every node as a source: ds[beta] += w_beta sum_alpha [ f c + ((f'/R)(d . c) + f e) d ],
@@ -118,11 +127,12 @@ __global__ void __launch_bounds__(SP_TILE) k_shape_src(const double *__restrict_
                                                        const double *__restrict__ wts, const int32_t *__restrict__ tri,
                                                        const cx<double> *__restrict__ lam,
                                                        const cx<double> *__restrict__ a,
-                                                       const cx<double> *__restrict__ b, int64_t n, double k_re,
-                                                       double k_im, cx<double> *__restrict__ ds,
+                                                       const cx<double> *__restrict__ b, int64_t n, int64_t chunk,
+                                                       double k_re, double k_im, cx<double> *__restrict__ ds,
                                                        cx<double> *__restrict__ dn, cx<double> *__restrict__ dw) {
     __shared__ TgtTile S;
     const int64_t be = blockIdx.x * (int64_t)SP_TILE + threadIdx.x;
+    const int64_t lo = blockIdx.y * chunk, hi = min(n, lo + chunk);
     const bool active = be < n;
     double p[3] = {0, 0, 0}, nb[3] = {0, 0, 0}, w = 0.0;
     cx<double> ab[3], bb[3];
@@ -141,8 +151,8 @@ __global__ void __launch_bounds__(SP_TILE) k_shape_src(const double *__restrict_
     const cx<double> na = nb[0] * ab[0] + nb[1] * ab[1] + nb[2] * ab[2];
     cx<double> as[3], an[3], aw = mk(0.0, 0.0);
     for (int q = 0; q < 3; ++q) as[q] = an[q] = mk(0.0, 0.0);
-    for (int64_t base = 0; base < n; base += SP_TILE) {
-        const int cnt = (int)min((int64_t)SP_TILE, n - base);
+    for (int64_t base = lo; base < hi; base += SP_TILE) {
+        const int cnt = (int)min((int64_t)SP_TILE, hi - base);
         __syncthreads();
         if ((int)threadIdx.x < cnt) {
             const int j = threadIdx.x;
@@ -180,11 +190,37 @@ __global__ void __launch_bounds__(SP_TILE) k_shape_src(const double *__restrict_
         }
     }
     if (!active) return;
+    const int64_t e = (int64_t)blockIdx.y * n + be;
     for (int q = 0; q < 3; ++q) {
-        ds[3 * be + q] += w * as[q];
-        dn[3 * be + q] = w * an[q];
+        ds[3 * e + q] = w * as[q];
+        dn[3 * e + q] = w * an[q];
     }
-    dw[be] = aw;
+    dw[e] = aw;
+}
+
+// the partial sums of the chunks, added in chunk order: ds from both passes, dn, dw
+__global__ void k_shape_sum(const cx<double> *__restrict__ pt, const cx<double> *__restrict__ ps,
+                            const cx<double> *__restrict__ pn, const cx<double> *__restrict__ pw, int64_t n,
+                            int chunks, cx<double> *__restrict__ ds, cx<double> *__restrict__ dn,
+                            cx<double> *__restrict__ dw) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cx<double> s[3], t[3], u[3], v = mk(0.0, 0.0);
+    for (int q = 0; q < 3; ++q) s[q] = t[q] = u[q] = mk(0.0, 0.0);
+    for (int c = 0; c < chunks; ++c) {
+        const int64_t e = (int64_t)c * n + i;
+        for (int q = 0; q < 3; ++q) {
+            s[q] += pt[3 * e + q];
+            t[q] += ps[3 * e + q];
+            u[q] += pn[3 * e + q];
+        }
+        v += pw[e];
+    }
+    for (int q = 0; q < 3; ++q) {
+        ds[3 * i + q] = s[q] + t[q];
+        dn[3 * i + q] = u[q];
+    }
+    dw[i] = v;
 }
 
 }  // namespace
@@ -210,15 +246,28 @@ int bem_shape_pairs(const double *points, const double *normals, const double *w
             for (const void *i : ins) FMB_REQUIRE(o != i, "outputs must not alias inputs");
         FMB_REQUIRE(ds != dn && ds != dw && dn != dw, "ds, dn and dw must be distinct");
         hipStream_t s = (hipStream_t)stream;
-        const unsigned grid = (unsigned)((n + SP_TILE - 1) / SP_TILE);
+        const int64_t tiles = (n + SP_TILE - 1) / SP_TILE;
+        // chunks of whole tiles of the other side: about SP_WAVES wavefronts per launch
+        int64_t want = (SP_WAVES + 2 * tiles - 1) / (2 * tiles);
+        want = std::max<int64_t>(1, std::min<int64_t>({want, tiles, (int64_t)SP_MAX_CHUNKS}));
+        const int64_t chunk = ((tiles + want - 1) / want) * SP_TILE;
+        const int chunks = (int)((n + chunk - 1) / chunk);
+        DevBuf part;
+        part.alloc((size_t)chunks * n * 10 * sizeof(cx<double>));
+        cx<double> *pt = part.as<cx<double>>(), *ps = pt + (size_t)chunks * n * 3, *pn = ps + (size_t)chunks * n * 3,
+                   *pw = pn + (size_t)chunks * n * 3;
+        const dim3 grid((unsigned)tiles, (unsigned)chunks);
         k_shape_tgt<<<grid, SP_TILE, 0, s>>>(points, normals, weights, point_tri, (const cx<double> *)lam,
-                                             (const cx<double> *)a, (const cx<double> *)b, n, k_re, k_im,
-                                             (cx<double> *)ds);
+                                             (const cx<double> *)a, (const cx<double> *)b, n, chunk, k_re, k_im, pt);
         FMB_LAUNCH_CHECK();
         k_shape_src<<<grid, SP_TILE, 0, s>>>(points, normals, weights, point_tri, (const cx<double> *)lam,
-                                             (const cx<double> *)a, (const cx<double> *)b, n, k_re, k_im,
-                                             (cx<double> *)ds, (cx<double> *)dn, (cx<double> *)dw);
+                                             (const cx<double> *)a, (const cx<double> *)b, n, chunk, k_re, k_im, ps,
+                                             pn, pw);
         FMB_LAUNCH_CHECK();
+        k_shape_sum<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(pt, ps, pn, pw, n, chunks, (cx<double> *)ds,
+                                                                (cx<double> *)dn, (cx<double> *)dw);
+        FMB_LAUNCH_CHECK();
+        FMB_CHECK_HIP(hipStreamSynchronize(s));    // the partial sums are freed on return
     });
 }
 
