@@ -16,7 +16,9 @@ lambda = A^{-H} grad_x f gives
     dC/dv = df/dv |_x + Re d/dv [ sum conj(lambda) . (b - A x) ] |_{x, lambda}.
 
 The rows of A x are (1/2 Phi + Op_k0(Phi, -Psi), 1/2 T Phi - Op_k1(T Phi, -gamma Psi))
-with T = I + (1 - eps)/eps n n^T.  The geometry enters through
+with T = I + (1 - eps)/eps n n^T (eq. 2.13); with several scatterers (Fig. 1) the
+host rows run over every node and scatterer j's interior rows over its own
+nodes with its own k_j, T_j and gamma_j.  The geometry enters through
 * the incident field E_inc(s) in b and T(n) in the interior jump term:
   torch autograd on the node positions and normals;
 * T(n) Phi as the interior operator's density: its derivative is
@@ -81,12 +83,6 @@ def vertex_normals(vertices, triangles):
     for j in range(3):
         np.add.at(N, F[:, j], cr)
     return N / np.linalg.norm(N, axis=1, keepdims=True)
-
-
-def _tphi(nrm, phi, eps):
-    """T Phi = Phi + (1 - eps)/eps n (n . Phi) (eq. 2.13)."""
-    nc = nrm.to(torch.complex128)
-    return phi + ((1.0 - eps) / eps) * nc * torch.sum(nc * phi, dim=1, keepdim=True)
 
 
 def apply_self_blocks(nrm, point_tri, dv, dg, a, b):
@@ -205,15 +201,20 @@ def _surface_explicit(k0, x, d, pol, s, n, w):
 
 def cross_section_and_vertex_gradient(vertices, triangles, k0, eps, d, pol, order=16, depth=0, tol=1e-10,
                                       restart=150, mu=1.0, functional="far", order32=None, solve_kw=None,
-                                      fd_rel=1e-5, plan_tol=0.0, stats=None):
-    """(C_sca, dC/dv f64[nv, 3], dC/d(delta_v) f64[nv]) for one scatterer of
-    permittivity eps under the plane wave pol exp(i k0 d . s), delta_v being the
-    displacement of vertex v along its vertex normal.  functional: "far"
-    (oint |F|^2 dOmega) or "surface" (eq. 4.2 on the scatterer's surface).
-    order / plan_tol / order32 / solve_kw as for `BemProblem` and its solve.
-    stats: a dict to receive the seconds of each phase (device-synchronised)
-    and the solves' iteration counts."""
+                                      fd_rel=1e-5, plan_tol=0.0, stats=None, tri_region=None):
+    """(C_sca, dC/dv f64[nv, 3], dC/d(delta_v) f64[nv]) under the plane wave
+    pol exp(i k0 d . s), delta_v being the displacement of vertex v along its
+    vertex normal.  One scatterer of permittivity eps (and permeability mu), or,
+    with tri_region (the scatterer of every triangle, 0..J-1), J scatterers with
+    eps[j] and mu[j] (scalars apply to all): the host rows use every node at k0,
+    scatterer j's interior rows its own nodes at k_j (Fig. 1).  functional: "far"
+    (oint |F|^2 dOmega) or "surface" (eq. 4.2 on the scatterers' surfaces).
+    order / plan_tol / order32 / solve_kw as for `BemProblem` and its solve
+    (plan_tol applies to one scatterer only).  stats: a dict to receive the
+    seconds of each phase (device-synchronised) and the solves' iteration counts."""
     import time
+
+    from .solver import MultiBemProblem
 
     def mark(key, t0):
         if stats is not None:
@@ -225,9 +226,19 @@ def cross_section_and_vertex_gradient(vertices, triangles, k0, eps, d, pol, orde
     V = np.ascontiguousarray(vertices, dtype=np.float64)
     F = np.ascontiguousarray(triangles, dtype=np.int64)
     q = nodes_of_mesh(V, F)
-    eps = complex(eps)
-    mu = complex(mu)
-    pb = BemProblem(q, k0, eps, mu=mu, order=order, depth=depth, order32=order32, tol=plan_tol)
+    if tri_region is None:
+        J, region = 1, np.zeros(len(q["points"]), dtype=np.int32)
+        eps_l, mu_l = [complex(eps)], [complex(mu)]
+        pb = BemProblem(q, k0, eps_l[0], mu=mu_l[0], order=order, depth=depth, order32=order32, tol=plan_tol)
+    else:
+        region = np.repeat(np.asarray(tri_region, dtype=np.int32), 3)
+        J = int(region.max()) + 1
+        eps_l = [complex(e) for e in np.broadcast_to(np.asarray(eps, dtype=np.complex128), (J,))]
+        mu_l = [complex(m) for m in np.broadcast_to(np.asarray(mu, dtype=np.complex128), (J,))]
+        pb = MultiBemProblem(q, region, k0, eps_l, mu=mu_l, order=order, depth=depth, order32=order32)
+    plans = pb.pj if J > 1 else [pb.p1]
+    kj = list(pb.kj) if J > 1 else [pb.k1]
+    idx = [np.nonzero(region == j)[0] for j in range(J)]
     kw = dict(tol=tol, restart=restart, maxit=4000)
     kw.update(solve_kw or {})
     try:
@@ -244,28 +255,45 @@ def cross_section_and_vertex_gradient(vertices, triangles, k0, eps, d, pol, orde
             stats["iterations"] = inf["iterations"]
             stats["adjoint_iterations"] = inf_adj["iterations"]
         x, lam = xd[0], lam[0]
+        dev = x.device
+        idx_t = [torch.from_numpy(i).to(dev) for i in idx]
         phi, psi = x[:, 0:3].contiguous(), x[:, 3:6].contiguous()
         lam0, lam1 = lam[:, 0:3].contiguous(), lam[:, 3:6].contiguous()
-        abar1, _ = pb.p1.matvec_adjoint(lam1)
-        k1, gamma = pb.k1, pb.mu
+        # abar_1 = (Op_kj^H lambda_1)_a of each scatterer's plan, over its own nodes
+        abar1 = torch.zeros_like(lam1)
+        for j in range(J):
+            abar1[idx_t[j]] = plans[j].matvec_adjoint(lam1[idx_t[j]].contiguous())[0]
     finally:
         pb.close()
     t0 = mark("adjoint_product_s", t0)
-    dev = x.device
+    # per-node T coefficient (1 - eps)/eps and gamma = mu of the node's scatterer
+    reg_t = torch.from_numpy(region.astype(np.int64)).to(dev)
+    tcoef = torch.tensor([(1.0 - e) / e for e in eps_l], dtype=torch.complex128, device=dev)[reg_t][:, None]
+    gam = torch.tensor(mu_l, dtype=torch.complex128, device=dev)[reg_t][:, None]
+
+    def tmul(nrm):
+        nc = nrm.to(torch.complex128)
+        return phi + tcoef * nc * torch.sum(nc * phi, dim=1, keepdim=True)
+
     Vt = torch.from_numpy(V).to(dev).requires_grad_(True)
     Ft = torch.from_numpy(F).to(dev)
     s, n, w = nodes_of_triangles(Vt[Ft])
     s0, n0, w0 = s.detach().contiguous(), n.detach().contiguous(), w.detach().contiguous()
     tri = torch.from_numpy(q["point_tri"]).to(dev)
-    tphi = _tphi(n0, phi, eps).contiguous()
-    b0, b1 = (-psi).contiguous(), (-gamma * psi).contiguous()
-    # point sums: sum conj(lam) . A x holds +B_k0(lam0; Phi, -Psi) - B_k1(lam1; T Phi, -gamma Psi)
-    ds0, dn0, dw0 = shape_pairs(s0, n0, w0, tri, k0, lam0, phi, b0)
-    ds1, dn1, dw1 = shape_pairs(s0, n0, w0, tri, k1, lam1, tphi, b1)
+    tphi = tmul(n0).contiguous()
+    b0, b1 = (-psi).contiguous(), (-gam * psi).contiguous()
+    # point sums: sum conj(lam) . A x holds +B_k0(lam0; Phi, -Psi) over all nodes and
+    # -B_kj(lam1; T Phi, -gamma Psi) over each scatterer's own nodes
+    ds, dn, dw = shape_pairs(s0, n0, w0, tri, k0, lam0, phi, b0)
+    for j in range(J):
+        i = idx_t[j]
+        dsj, dnj, dwj = shape_pairs(s0[i].contiguous(), n0[i].contiguous(), w0[i].contiguous(), tri[i].contiguous(),
+                                    kj[j], lam1[i].contiguous(), tphi[i].contiguous(), b1[i].contiguous())
+        ds[i] -= dsj
+        dn[i] -= dnj
+        dw[i] -= dwj
     t0 = mark("pairs_s", t0)
-    GS = -(ds0 - ds1).real
-    GN = -(dn0 - dn1).real
-    GW = -(dw0 - dw1).real
+    GS, GN, GW = -ds.real, -dn.real, -dw.real
     # explicit dependence of the functional
     if functional == "far":
         es, en, ew = _far_explicit(k0, x, pol, s0, n0, w0)
@@ -278,7 +306,7 @@ def cross_section_and_vertex_gradient(vertices, triangles, k0, eps, d, pol, orde
     dd = torch.tensor(np.asarray(d, dtype=np.float64), device=dev)
     p = torch.tensor(np.asarray(pol, dtype=np.complex128), device=dev)
     Einc = torch.exp(1j * complex(k0) * (sl @ dd))[:, None] * p[None, :]
-    tp = _tphi(nl, phi, eps)
+    tp = tmul(nl)
     L = (torch.sum(torch.conj(lam0) * Einc).real
          - torch.sum(torch.conj(lam1) * (0.5 * tp) - torch.conj(abar1) * tp).real)
     ls, ln = torch.autograd.grad(L, (sl, nl))
@@ -286,7 +314,12 @@ def cross_section_and_vertex_gradient(vertices, triangles, k0, eps, d, pol, orde
     # carry the node derivatives to the vertices
     gV = torch.autograd.grad(torch.sum(GS * s) + torch.sum(GN * n) + torch.sum(GW * w), Vt)[0].cpu().numpy()
     t0 = mark("explicit_s", t0)
-    # self-triangle blocks: -Re d/dv [ S_k0(lam0; Phi, -Psi) - S_k1(lam1; T Phi, -gamma Psi) ]
-    gV -= self_triangle_vertex_derivative(V, F, [(k0, 1.0, lam0, phi, b0), (k1, -1.0, lam1, tphi, b1)], fd_rel)
+    # self-triangle blocks: -Re d/dv [ S_k0(lam0; Phi, -Psi) - S_kj(lam1; T Phi, -gamma Psi) on scatterer j ]
+    terms = [(k0, 1.0, lam0, phi, b0)]
+    for j in range(J):
+        lj = torch.zeros_like(lam1)
+        lj[idx_t[j]] = lam1[idx_t[j]]
+        terms.append((kj[j], -1.0, lj, tphi, b1))
+    gV -= self_triangle_vertex_derivative(V, F, terms, fd_rel)
     mark("self_blocks_s", t0)
     return float(C.item()), gV, np.sum(gV * vertex_normals(V, F), axis=1)
