@@ -145,21 +145,22 @@ def self_triangle_vertex_derivative(vertices, triangles, terms, fd_rel=1e-5):
     return out
 
 
-def _far_explicit(k0, x, pol, s, n, w, nt=24, nph=48, chunk=64):
+def _far_explicit(k0, a, b_of_n, pol, s, n, w, nt=24, nph=48, chunk=64):
     """d/d(s, n, w) of C = sum W |F|^2 / |E0|^2 with F the far-field amplitude of
-    the unknowns x [n, 6] held fixed (the same sum `bem_field` evaluates:
-    F(r) = -(1/4pi) sum w e^{-ik0 r.s} [ -ik0 (n (r.a) - (n.r) a - r (n.a)) + b ], a = Phi, b = -Psi),
+    the densities held fixed (the same sum `bem_field` evaluates:
+    F(r) = -(1/4pi) sum w e^{-ik0 r.s} [ -ik0 (n (r.a) - (n.r) a - r (n.a)) + b ], a = Phi,
+    b = b_of_n(n): -Psi for dielectrics, c n x (n x Phi) under the impedance condition),
     with the Gauss-Legendre x uniform rule of `far_field_cross_section`."""
     from .postprocess import sphere_quadrature
     dirs, wts = sphere_quadrature(nt, nph)
     e0 = float(np.sum(np.abs(np.asarray(pol)) ** 2))
-    a, b = x[:, 0:3], -x[:, 3:6]
     sl, nl, wl = (t.detach().clone().requires_grad_(True) for t in (s, n, w))
     gs, gn, gw = torch.zeros_like(s), torch.zeros_like(n), torch.zeros_like(w)
     k0 = complex(k0)
     for lo in range(0, len(dirs), chunk):
         r = torch.from_numpy(dirs[lo:lo + chunk]).to(s.device)
         W = torch.from_numpy(wts[lo:lo + chunk]).to(s.device)
+        b = b_of_n(nl)
         # sums over the nodes as elementwise products and reductions (a product with K = n and
         # N = 3 runs far below the library GEMM's speed)
         ph = wl[None, :] * torch.exp(-1j * k0 * (r @ sl.T))                # [nd, n]
@@ -296,7 +297,7 @@ def cross_section_and_vertex_gradient(vertices, triangles, k0, eps, d, pol, orde
     GS, GN, GW = -ds.real, -dn.real, -dw.real
     # explicit dependence of the functional
     if functional == "far":
-        es, en, ew = _far_explicit(k0, x, pol, s0, n0, w0)
+        es, en, ew = _far_explicit(k0, phi, lambda nl: b0, pol, s0, n0, w0)
     else:
         es, en, ew = _surface_explicit(k0, x, d, pol, s0, n0, w0)
     GS, GN, GW = GS + es, GN + en, GW + ew
@@ -322,4 +323,57 @@ def cross_section_and_vertex_gradient(vertices, triangles, k0, eps, d, pol, orde
         terms.append((kj[j], -1.0, lj, tphi, b1))
     gV -= self_triangle_vertex_derivative(V, F, terms, fd_rel)
     mark("self_blocks_s", t0)
+    return float(C.item()), gV, np.sum(gV * vertex_normals(V, F), axis=1)
+
+
+def impedance_cross_section_and_vertex_gradient(vertices, triangles, k0, Z, d, pol, order=16, depth=0, tol=1e-10,
+                                                restart=150, order32=None, solve_kw=None, fd_rel=1e-5, plan_tol=0.0):
+    """(C_sca, dC/dv f64[nv, 3], dC/d(delta_v) f64[nv]) of a good conductor under
+    the impedance boundary condition (eqs. 2.24-2.25), C_sca from the far field:
+    A Phi = 1/2 Phi + Op_k0(Phi, b(n)), b = c n x (n x Phi), c = i k0 / Z.  Besides
+    the point sum's and the self blocks' geometry, the normal enters through b
+    (its derivative is conj(bbar) . db, bbar = (Op_k0^H lambda)_b) and the far field."""
+    from .gradients import far_field_cross_section
+    from .solver import IbcProblem
+    V = np.ascontiguousarray(vertices, dtype=np.float64)
+    F = np.ascontiguousarray(triangles, dtype=np.int64)
+    q = nodes_of_mesh(V, F)
+    pb = IbcProblem(q, k0, Z, order=order, depth=depth, order32=order32, tol=plan_tol)
+    kw = dict(tol=tol, restart=restart, maxit=4000)
+    kw.update(solve_kw or {})
+    try:
+        xd, _ = pb.solve(pb.rhs_planewave(d, pol), **kw)
+        xg = xd.clone().requires_grad_(True)
+        C = far_field_cross_section(pb, xg, pol)
+        g = torch.autograd.grad(C, xg)[0]
+        lam, _ = pb.solve(g.contiguous(), adjoint=True, **kw)
+        phi, lam = xd[0].contiguous(), lam[0].contiguous()
+        _, bbar = pb.p0.matvec_adjoint(lam)
+    finally:
+        pb.close()
+    dev = phi.device
+    c = 1j * complex(k0) / complex(Z)
+
+    def b_of(nrm):
+        nc = nrm.to(torch.complex128)
+        return c * (nc * torch.sum(nc * phi, dim=1, keepdim=True) - phi)
+
+    Vt = torch.from_numpy(V).to(dev).requires_grad_(True)
+    s, n, w = nodes_of_triangles(Vt[torch.from_numpy(F).to(dev)])
+    s0, n0, w0 = s.detach().contiguous(), n.detach().contiguous(), w.detach().contiguous()
+    tri = torch.from_numpy(q["point_tri"]).to(dev)
+    b0 = b_of(n0).contiguous()
+    ds, dn, dw = shape_pairs(s0, n0, w0, tri, k0, lam, phi, b0)
+    es, en, ew = _far_explicit(k0, phi, b_of, pol, s0, n0, w0)
+    GS, GN, GW = es - ds.real, en - dn.real, ew - dw.real
+    # Re sum conj(lam) . E_inc(s) - Re sum conj(bbar) . b(n)
+    sl, nl = s0.clone().requires_grad_(True), n0.clone().requires_grad_(True)
+    dd = torch.tensor(np.asarray(d, dtype=np.float64), device=dev)
+    p = torch.tensor(np.asarray(pol, dtype=np.complex128), device=dev)
+    Einc = torch.exp(1j * complex(k0) * (sl @ dd))[:, None] * p[None, :]
+    L = torch.sum(torch.conj(lam) * Einc).real - torch.sum(torch.conj(bbar) * b_of(nl)).real
+    ls, ln = torch.autograd.grad(L, (sl, nl))
+    GS, GN = GS + ls, GN + ln
+    gV = torch.autograd.grad(torch.sum(GS * s) + torch.sum(GN * n) + torch.sum(GW * w), Vt)[0].cpu().numpy()
+    gV -= self_triangle_vertex_derivative(V, F, [(k0, 1.0, lam, phi, b0)], fd_rel)
     return float(C.item()), gV, np.sum(gV * vertex_normals(V, F), axis=1)

@@ -264,3 +264,44 @@ def test_vertex_gradient_two_scatterers(abi):
             fun, C, an, fd, scale, np.linalg.norm(gV.sum(axis=0))), flush=True)
         assert abs(an - fd) <= 2e-6 * scale
         assert np.linalg.norm(gV.sum(axis=0)) <= 1e-7 * np.abs(gV).sum()
+
+
+def test_impedance_vertex_gradient(abi):
+    """A good conductor under the impedance condition (eq. 2.25; Z = 0.1 - 0.2i,
+    k0 = 1.2, far-field C_sca) on a 120-triangle torus: dC/dv along a seeded
+    normal field against central differences (h = 1e-4) of GPU solves and of the
+    oracle's own solves; it sums to zero under translation."""
+    from oracle.bem import IbcProblem as OracleIbc
+    from paper_1211_7177_amd.gradients import far_field_cross_section
+    from paper_1211_7177_amd.shape import impedance_cross_section_and_vertex_gradient, nodes_of_mesh
+    from paper_1211_7177_amd.solver import IbcProblem
+    from synthetic.meshes import Mesh
+    m = torus(1.0, 0.35, 10, 6)
+    V, F = m.vertices.copy(), m.triangles.copy()
+    k0, Z = 1.2, 0.1 - 0.2j
+    print("impedance vertex gradient", flush=True)
+    C, gV, _ = impedance_cross_section_and_vertex_gradient(V, F, k0, Z, D, POL, order=20, depth=2, tol=1e-12,
+                                                           restart=200)
+    W = _direction(V, F, 4)
+
+    def gpu_C(Vx):
+        pb = IbcProblem(nodes_of_mesh(Vx, F), k0, Z, order=20, depth=2)
+        x, _ = pb.solve(pb.rhs_planewave(D, POL), tol=1e-12, restart=200, maxit=4000)
+        c = far_field_cross_section(pb, x, POL).item()
+        pb.close()
+        return c
+
+    def oracle_C(Vx):
+        q = nystrom3(Mesh(Vx, F.astype(np.int32)))
+        ob = OracleIbc(q, k0, Z)
+        x, _ = oracle_gmres(ob.apply, ob.rhs_planewave(D, POL), ob.block_preconditioner(), tol=1e-13, restart=300)
+        return cross_section_far(q, k0, np.concatenate([x, -ob.c * ob.nnx(x)], axis=1), POL)
+
+    an = np.sum(gV * W)
+    fd_gpu = (gpu_C(V + 1e-4 * W) - gpu_C(V - 1e-4 * W)) / 2e-4
+    fd_or = (oracle_C(V + 1e-4 * W) - oracle_C(V - 1e-4 * W)) / 2e-4
+    scale = np.sum(np.abs(gV * W))
+    print("ibc C %.8f (oracle %.8f): adjoint %.10e, GPU differences %.10e, oracle differences %.10e" % (
+        C, oracle_C(V), an, fd_gpu, fd_or), flush=True)
+    assert abs(an - fd_gpu) <= 2e-6 * scale and abs(an - fd_or) <= 2e-6 * scale
+    assert np.linalg.norm(gV.sum(axis=0)) <= 1e-7 * np.abs(gV).sum()
