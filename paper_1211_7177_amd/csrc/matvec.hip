@@ -86,9 +86,10 @@ __device__ inline int xcd_tile(int i, int ntiles) {
 //   grad = ((d_+ + d_-) / 2, (d_+ - d_-) / 2i, d_z),
 // with coefficients and indices from the plan's table; k multiplies the whole
 // gradient part once per coefficient after the node loop.
-constexpr int P2M_SLOTS = 3;     // coefficients per thread when p^2 > blockDim
+constexpr int P2M_SLOTS = 3;     // coefficients per thread when p^2 > blockDim (orders up to 27)
+constexpr int P2M_SLOTS_MAX = 7; // leaf orders 28..40 (7 x 256 >= 40^2)
 
-template <typename T>
+template <typename T, int SLOTS>
 __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, const double *__restrict__ center,
                                              const double *__restrict__ spts, const double *__restrict__ snrm,
                                              const cx<T> *__restrict__ src, int64_t n, int p, double k_re, double k_im,
@@ -116,8 +117,8 @@ __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, 
     // a leaf that fits one batch builds its tables once for all right-hand sides
     const bool one = s1 - s0 <= batch;
     for (int r = 0; r < nrhs; ++r) {
-        cx<T> accb[P2M_SLOTS][3], accg[P2M_SLOTS][3];
-        for (int u = 0; u < P2M_SLOTS; ++u)
+        cx<T> accb[SLOTS][3], accg[SLOTS][3];
+        for (int u = 0; u < SLOTS; ++u)
             for (int c = 0; c < 3; ++c) accb[u][c] = accg[u][c] = mk(T(0), T(0));
         for (int b0 = s0; b0 < s1; b0 += batch) {
             const int nb = min(batch, s1 - b0);
@@ -146,7 +147,7 @@ __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, 
             for (int t = threadIdx.x; t < nb * 7; t += blockDim.x)
                 sv[t] = src[((int64_t)r * n + b0) * 7 + t];
             __syncthreads();
-            for (int u = 0; u < P2M_SLOTS; ++u) {
+            for (int u = 0; u < SLOTS; ++u) {
                 const int idx = (G > 1) ? ((int)threadIdx.x % P2) : (int)threadIdx.x + u * (int)blockDim.x;
                 if (idx >= P2 || grp >= G || (G > 1 && u > 0)) break;
                 int ix[7];
@@ -172,8 +173,8 @@ __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, 
                 }
             }
         }
-        cx<T> acc[P2M_SLOTS][3];
-        for (int u = 0; u < P2M_SLOTS; ++u)
+        cx<T> acc[SLOTS][3];
+        for (int u = 0; u < SLOTS; ++u)
             for (int c = 0; c < 3; ++c) acc[u][c] = accb[u][c] + k * accg[u][c];
         cx<T> *Mo = M + ((int64_t)box * nrhs_max + r) * 3 * P2;
         if (G > 1) {
@@ -194,7 +195,7 @@ __global__ void __launch_bounds__(TPB) k_p2m(const int32_t *__restrict__ start, 
                 }
             }
         } else {
-            for (int u = 0; u < P2M_SLOTS; ++u) {
+            for (int u = 0; u < SLOTS; ++u) {
                 const int idx = threadIdx.x + u * blockDim.x;
                 if (idx >= P2) break;
                 int nn = 0;
@@ -1424,8 +1425,10 @@ bool matvec_step(Plan &P, const cx<T> *a, const cx<T> *b, cx<T> *y, int nrhs, hi
         const size_t want = std::max<size_t>(8, (redb < 24000 ? 24000 - redb : 0) / per);
         const int batch = (int)std::max<size_t>(1, std::min<size_t>({(size_t)64, fit, want}));
         const size_t sh = redb + (size_t)batch * per;
+        FMB_REQUIRE(P2 <= P2M_SLOTS_MAX * TPB, "leaf order too large for the multipole kernel");
+        auto kern = P2 <= P2M_SLOTS * TPB ? k_p2m<T, P2M_SLOTS> : k_p2m<T, P2M_SLOTS_MAX>;
         tm.begin(ST_P2M, s, ev);
-        k_p2m<T><<<(unsigned)LL.nbox, TPB, sh, s>>>(
+        kern<<<(unsigned)LL.nbox, TPB, sh, s>>>(
             LL.start.as<int32_t>(), LL.center.as<double>(), P.spts.as<double>(), P.snrm.as<double>(), src, n, p, P.k_re,
             P.k_im, P.inv_alpha.as<double>() + (size_t)L * p, P.btab.as<T>(), P.bgix.as<int32_t>(), nrhs, P.nrhs_max,
             batch, LL.M.as<cx<T>>());

@@ -50,7 +50,8 @@ def _rel(y, ref):
 
 @pytest.mark.parametrize("k,tol,bound", [(1.0, 1e-6, 1e-6), (1.5, 1e-8, 1e-8), (2 + 1.5j, 1e-6, 1e-6),
                                          (4.0, 1e-10, 2e-10), (1.5, 1e-4, 1e-4), (1.5, 0.1, 0.1), (1.5, 1e-3, 1e-3),
-                                         (1.5, 1e-5, 1e-5), (1.5, 4e-7, 4e-7), (1.5, 7e-8, 7e-8)])
+                                         (1.5, 1e-5, 1e-5), (1.5, 4e-7, 4e-7), (1.5, 7e-8, 7e-8),
+                                         (4.0, 1e-11, 3e-11)])
 def test_fp64_per_level_order_matches_direct_sum(abi, sphere, k, tol, bound):
     """FP64 plans whose orders are chosen per level for `tol` (eq. 2.17 truncation;
     S|S, S|R, R|R of eqs. 2.20-2.21 by rotation and coaxial shift) against the
@@ -58,7 +59,10 @@ def test_fp64_per_level_order_matches_direct_sum(abi, sphere, k, tol, bound):
     reach about `tol` (measured 1.8e-7, 3.3e-9, 1.8e-7, 1.4e-10).  Orders above 20
     run the three-launch pipeline, orders up to 20 the wavefront-per-source M2L;
     tol 0.1, 1e-3, 1e-4, 1e-5, 4e-7 and 7e-8 give leaf orders 3, 9, 12, 14, 18
-    and 21 (measured 1.0e-2, 5.4e-5, 5.4e-6, 1.3e-6, 9.0e-8, 1.2e-8)."""
+    and 21 (measured 1.0e-2, 5.4e-5, 5.4e-6, 1.3e-6, 9.0e-8, 1.2e-8).  k = 4 at
+    tol 1e-10 and 1e-11 puts orders 28 and 31 at the leaves, whose multipoles
+    hold more coefficients than the multipole kernel's threads take in three
+    passes."""
     q = sphere
     n = q["points"].shape[0]
     a, b = _dens(n, 1)
