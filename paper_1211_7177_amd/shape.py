@@ -145,14 +145,17 @@ def self_triangle_vertex_derivative(vertices, triangles, terms, fd_rel=1e-5):
     return out
 
 
-def _far_explicit(k0, a, b_of_n, pol, s, n, w, nt=24, nph=48, chunk=64):
+def _far_explicit(k0, a, b_of_n, pol, s, n, w, nt=24, nph=48, chunk_bytes=5e8):
     """d/d(s, n, w) of C = sum W |F|^2 / |E0|^2 with F the far-field amplitude of
     the densities held fixed (the same sum `bem_field` evaluates:
     F(r) = -(1/4pi) sum w e^{-ik0 r.s} [ -ik0 (n (r.a) - (n.r) a - r (n.a)) + b ], a = Phi,
     b = b_of_n(n): -Psi for dielectrics, c n x (n x Phi) under the impedance condition),
-    with the Gauss-Legendre x uniform rule of `far_field_cross_section`."""
+    with the Gauss-Legendre x uniform rule of `far_field_cross_section`.  Directions
+    are taken in chunks whose [chunk, n, 3] complex intermediates stay near
+    chunk_bytes."""
     from .postprocess import sphere_quadrature
     dirs, wts = sphere_quadrature(nt, nph)
+    chunk = int(max(1, min(64, chunk_bytes // (48 * s.shape[0]))))
     e0 = float(np.sum(np.abs(np.asarray(pol)) ** 2))
     sl, nl, wl = (t.detach().clone().requires_grad_(True) for t in (s, n, w))
     gs, gn, gw = torch.zeros_like(s), torch.zeros_like(n), torch.zeros_like(w)
