@@ -110,7 +110,7 @@ def _per_triangle(vals, point_tri_l, ntri):
 
 def self_triangle_vertex_derivative(vertices, triangles, terms, fd_rel=1e-5):
     """d/dv Re[ sum_i c_i sum_alpha conj(lam_i,alpha) . S_{k_i}(a_i, b_i)_alpha ] for
-    terms = [(k_i, c_i, lam_i, a_i, b_i), ...] (torch [n, 3] on the GPU), S_k the
+    terms = [(k_i, c_i, lam_i, a_i, b_i), ...] (torch [n, 3], on the device the blocks are built for), S_k the
     self-triangle terms of `bem_self_blocks` (LINEAR blocks), with the densities
     held fixed: central differences in each triangle corner coordinate, step
     fd_rel times the triangle's longest edge.  Returns f64[nv, 3]."""
