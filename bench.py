@@ -969,7 +969,7 @@ def c5_cpu_baseline(nodes, cfg, a, b, nrows, gpu_rows):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (this build has no multi-GPU path); got --gpus %d" % args.gpus,
+        print("bench.py runs on one GPU only (the library has no multi-GPU path); got --gpus %d" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
