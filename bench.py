@@ -76,7 +76,8 @@ def parse():
     ap.add_argument("--serial", action="store_true",
                     help="run the k0 and k1 FMM products of each application one after the other (one stream)")
     ap.add_argument("--autotune", action="store_true",
-                    help="pick the FP32 order and translation kernel by timing whole solves first (autotune.tune_solve)")
+                    help="pick the octree depth, FP32 order and translation kernel by timing whole solves first "
+                         "(autotune.tune_solve)")
     ap.add_argument("--graphs", action="store_true",
                     help="replay the two FMM products from a captured HIP graph (default: eager launches)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -375,11 +376,11 @@ def torus_section(args, log):
         from paper_1211_7177_amd.autotune import tune_solve
         best, table = tune_solve(nodes, k0, eps, d, pol, tol=args.tol, orders32=(4, 5, 6),
                                  translates=("bf16x3", "fp32"), inner_tols=(args.inner_tol,), order64=args.order64,
-                                 depth=depth, restart=args.restart)
+                                 depths=(depth - 1, depth, depth + 1), restart=args.restart)
         tuned = {"chosen": best, "table": table}
         log("autotune", best)
         if best is not None:
-            args.order32, args.translate32 = best["order32"], best["translate"]
+            args.order32, args.translate32, depth = best["order32"], best["translate"], best["depth"]
     t0 = time.perf_counter()
     pb = BemProblem(nodes, k0, eps, order=args.order64, depth=depth, order32=args.order32, tol=args.tol64,
                     translate32=args.translate32)

@@ -7,9 +7,10 @@ Two levels, both timing real launches on the current device through the C ABI
   order, translation kernel) by time per product, keeping those whose product
   on a seeded density stays within `tol` (relative 2-norm) of an FP64
   reference plan of high order.
-* `tune_solve` ranks whole mixed-precision solves of one scatterer (FP32
-  order, translation kernel, inner tolerance) by time to the FP64 residual
-  `tol`, since a cheaper but coarser inner operator can cost refinement steps.
+* `tune_solve` ranks whole mixed-precision solves of one scatterer (octree
+  depth, FP32 order, translation kernel, inner tolerance) by time to the FP64
+  residual `tol`, since a cheaper but coarser inner operator can cost
+  refinement steps.
 
 Each returns the winning candidate and the full table.
 """
@@ -73,17 +74,21 @@ def tune_matvec(nodes, k, tol, depths=(0,), orders=(4, 5, 6, 8), translates=("fp
 
 
 def tune_solve(nodes, k0, eps, rhs_dir, rhs_pol, tol=1e-6, orders32=(4, 5, 6), translates=("bf16x3", "fp32"),
-               inner_tols=(5e-3,), order64=16, depth=0, restart=150, reps=1, modes=("refine",)):
+               inner_tols=(5e-3,), order64=16, depth=0, restart=150, reps=1, modes=("refine",), depths=None):
     """Fastest mixed-precision solve configuration reaching the residual `tol`.
     modes: "refine" (FP32 inner solves inside FP64 refinement) and/or "nested"
     (FP64 fGMRES preconditioned by FP32 fGMRES cycles of at most 100 steps).
+    depths: octree depths to try (0 picks one from the node count); default
+    the single `depth`.
 
-    Returns (best, table): each row holds mode, order32, translate, inner_tol,
-    s (seconds per solve, the mean of `reps` solves after one untimed solve),
-    iterations, refinements, fallback, residual, ok."""
+    Returns (best, table): each row holds depth (the plans' actual depth),
+    mode, order32, translate, inner_tol, s (seconds per solve, the mean of
+    `reps` solves after one untimed solve), iterations, refinements, fallback,
+    residual, ok."""
     table = []
-    for order32, tr in itertools.product(orders32, translates):
-        pb = BemProblem(nodes, k0, eps, order=order64, depth=depth, order32=order32, translate32=tr)
+    for dep, order32, tr in itertools.product(depths if depths is not None else (depth,), orders32, translates):
+        pb = BemProblem(nodes, k0, eps, order=order64, depth=dep, order32=order32, translate32=tr)
+        actual = pb.p0.info()["depth"]
         rhs = pb.rhs_planewave(rhs_dir, rhs_pol)
         for mode, itol in itertools.product(modes, inner_tols):
             def run():
@@ -99,7 +104,8 @@ def tune_solve(nodes, k0, eps, rhs_dir, rhs_pol, tol=1e-6, orders32=(4, 5, 6), t
                 _, info = run()
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / reps
-            table.append({"mode": mode, "order32": order32, "translate": tr, "inner_tol": itol, "s": dt,
+            table.append({"depth": actual, "mode": mode, "order32": order32, "translate": tr, "inner_tol": itol,
+                          "s": dt,
                           "iterations": info["iterations"], "refinements": info["refinements"],
                           "fallback": info["fp64_fallback"], "residual": info["residual"],
                           "ok": info["residual"] <= tol})

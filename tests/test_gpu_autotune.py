@@ -68,3 +68,16 @@ def test_tune_solve_reaches_tolerance(tune, sphere):
     assert all(r["ok"] for r in table if r["mode"] == "nested")
     assert best["residual"] <= 1e-8
     assert best["s"] == min(r["s"] for r in table if r["ok"])
+
+
+def test_tune_solve_over_depths(tune, sphere):
+    """The depth dimension: depths 2 and 3 of the 3840-node sphere, each row
+    carrying the plans' actual depth, both reaching the tolerance, the winner
+    the fastest."""
+    print("tune_solve over depths", flush=True)
+    best, table = tune.tune_solve(sphere, 1.0, 2.25, [0.0, 0.0, 1.0], [1.0, 0.0, 0.0], tol=1e-8, orders32=(5,),
+                                  translates=("fp32",), inner_tols=(1e-2,), order64=20, depths=(2, 3))
+    for r in table:
+        print(r)
+    assert [r["depth"] for r in table] == [2, 3]
+    assert all(r["ok"] for r in table) and best["s"] == min(r["s"] for r in table)
